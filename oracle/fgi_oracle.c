@@ -1,0 +1,827 @@
+/*
+ * fgi_oracle.c -- plain, slow, FP64 CPU oracle for the force-gradient HMC
+ * hot path of Kennedy, Clark and Silva, "Force Gradient Integrators"
+ * (arXiv:0910.2950).
+ *
+ * THIS IS TEST INFRASTRUCTURE.  It exists only so that tests, the smoke
+ * check and the CPU-baseline leg of the benchmark can check the GPU library
+ * against an independent implementation.  The GPU library never calls it,
+ * links it or includes anything from it, and it includes nothing of the GPU
+ * library.
+ *
+ * Everything is double precision, lexicographic, array-of-structures, full
+ * lattice.  Even/odd structure appears only as a parity test on a site.
+ * Reductions are sequential sums over per-site arrays in lexicographic order
+ * (deterministic regardless of the OpenMP thread count).
+ *
+ * Conventions (the paper fixes none of these; each is a reading):
+ *  - site index i = x + Lx*(y + Ly*(z + Lz*t)); parity(i) = (x+y+z+t) mod 2.
+ *  - links U[mu][i][a][b] complex; momenta P[mu][i][8] real components p_a of
+ *    the anti-Hermitian matrix P = sum_a p_a T^a with T^a = i*lambda^a/2
+ *    (Gell-Mann lambda), so Tr(T^a T^b) = -delta_ab/2 and T(p) = 1/2 sum p_a^2.
+ *  - component of an anti-Hermitian traceless X:  x_a = -2 Tr(T^a X).
+ *  - e_a f(U) = d/dt f(exp(t T^a) U_l) at t=0 for one link l (the paper's
+ *    left-invariant operators of Section 4, e_i(U) = -T_i U, up to the sign
+ *    of the generator, which cancels in every quantity computed here).
+ *  - force F_a = -e_a S (the S-hat flow of Section 2: p' = p + h F),
+ *    link flow (T-hat): U' = exp(h P) U.
+ *  - gauge action S_G = beta * sum_{x, mu<nu} (1 - Re Tr U_{mu nu}(x) / 3).
+ *  - Wilson operator M = 1 - kappa D, with
+ *      D psi(x) = sum_mu [(1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^+ psi(x-mu)],
+ *    DeGrand-Rossi gamma matrices, antiperiodic in t, periodic in space.
+ *  - even-odd Schur operator on even sites: Mhat = 1 - kappa^2 D_eo D_oe,
+ *    Mhat^+ = g5 Mhat g5.  Pseudofermion action S_F = phi^+ (Mhat^+ Mhat)^-1 phi,
+ *    phi = Mhat^+ eta, so S_F at the start equals eta^+ eta (Section 4: the
+ *    generic pseudofermion action with kernel Mhat^+ Mhat).
+ *  - even-site vectors are stored compactly: the k-th even site in
+ *    lexicographic order is entry k.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------ */
+/* lattice geometry                                                    */
+/* ------------------------------------------------------------------ */
+
+static long lat_volume(const int L[4]) { return (long)L[0] * L[1] * L[2] * L[3]; }
+
+static void lat_coords(const int L[4], long i, int c[4]) {
+    c[0] = (int)(i % L[0]); i /= L[0];
+    c[1] = (int)(i % L[1]); i /= L[1];
+    c[2] = (int)(i % L[2]); i /= L[2];
+    c[3] = (int)i;
+}
+
+static long lat_index(const int L[4], const int c[4]) {
+    return c[0] + (long)L[0] * (c[1] + (long)L[1] * (c[2] + (long)L[2] * c[3]));
+}
+
+static int lat_parity(const int L[4], long i) {
+    int c[4];
+    lat_coords(L, i, c);
+    return (c[0] + c[1] + c[2] + c[3]) & 1;
+}
+
+/* neighbour of site i one step in direction mu, forward (s=+1) or backward */
+static long lat_step(const int L[4], long i, int mu, int s) {
+    int c[4];
+    lat_coords(L, i, c);
+    c[mu] = (c[mu] + s + L[mu]) % L[mu];
+    return lat_index(L, c);
+}
+
+/* fermion boundary sign of the hop from x to x+mu (s=+1) or x-mu (s=-1):
+ * -1 when the hop wraps around the time direction. */
+static double lat_bc(const int L[4], long i, int mu, int s) {
+    int c[4];
+    if (mu != 3) return 1.0;
+    lat_coords(L, i, c);
+    if (s > 0 && c[3] == L[3] - 1) return -1.0;
+    if (s < 0 && c[3] == 0) return -1.0;
+    return 1.0;
+}
+
+/* ------------------------------------------------------------------ */
+/* 3x3 complex matrices                                                */
+/* ------------------------------------------------------------------ */
+
+typedef struct { cplx m[3][3]; } mat3;
+
+static mat3 m_zero(void) { mat3 r; memset(&r, 0, sizeof r); return r; }
+static mat3 m_unit(void) { mat3 r = m_zero(); r.m[0][0] = r.m[1][1] = r.m[2][2] = 1.0; return r; }
+
+static mat3 m_mul(mat3 a, mat3 b) {
+    mat3 r;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            cplx s = 0;
+            for (int k = 0; k < 3; k++) s += a.m[i][k] * b.m[k][j];
+            r.m[i][j] = s;
+        }
+    return r;
+}
+
+static mat3 m_dag(mat3 a) {
+    mat3 r;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) r.m[i][j] = conj(a.m[j][i]);
+    return r;
+}
+
+static mat3 m_add(mat3 a, mat3 b) {
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) a.m[i][j] += b.m[i][j];
+    return a;
+}
+
+static mat3 m_scale(mat3 a, cplx s) {
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) a.m[i][j] *= s;
+    return a;
+}
+
+static cplx m_trace(mat3 a) { return a.m[0][0] + a.m[1][1] + a.m[2][2]; }
+
+static mat3 link_get(const cplx *U, long V, int mu, long i) {
+    mat3 r;
+    memcpy(&r, U + ((long)mu * V + i) * 9, sizeof r);
+    return r;
+}
+
+static void link_put(cplx *U, long V, int mu, long i, mat3 a) {
+    memcpy(U + ((long)mu * V + i) * 9, &a, sizeof a);
+}
+
+/* ------------------------------------------------------------------ */
+/* su(3) basis: T^a = i lambda^a / 2                                   */
+/* ------------------------------------------------------------------ */
+
+static mat3 gen_T(int a) {
+    mat3 l = m_zero();
+    const double r3 = 1.0 / sqrt(3.0);
+    switch (a) {
+    case 0: l.m[0][1] = 1; l.m[1][0] = 1; break;
+    case 1: l.m[0][1] = -I; l.m[1][0] = I; break;
+    case 2: l.m[0][0] = 1; l.m[1][1] = -1; break;
+    case 3: l.m[0][2] = 1; l.m[2][0] = 1; break;
+    case 4: l.m[0][2] = -I; l.m[2][0] = I; break;
+    case 5: l.m[1][2] = 1; l.m[2][1] = 1; break;
+    case 6: l.m[1][2] = -I; l.m[2][1] = I; break;
+    case 7: l.m[0][0] = r3; l.m[1][1] = r3; l.m[2][2] = -2 * r3; break;
+    }
+    return m_scale(l, 0.5 * I);
+}
+
+/* X = sum_a p_a T^a */
+static mat3 alg_from_components(const double p[8]) {
+    mat3 r = m_zero();
+    for (int a = 0; a < 8; a++) r = m_add(r, m_scale(gen_T(a), p[a]));
+    return r;
+}
+
+/* x_a = -2 Tr(T^a X), exact for traceless anti-Hermitian X */
+static void alg_components(mat3 X, double x[8]) {
+    for (int a = 0; a < 8; a++) x[a] = creal(-2.0 * m_trace(m_mul(gen_T(a), X)));
+}
+
+/* traceless anti-Hermitian part: (W - W^+)/2 - Tr(W - W^+)/6 */
+static mat3 traceless_antiherm(mat3 W) {
+    mat3 A = m_scale(m_add(W, m_scale(m_dag(W), -1.0)), 0.5);
+    cplx t = m_trace(A) / 3.0;
+    for (int i = 0; i < 3; i++) A.m[i][i] -= t;
+    return A;
+}
+
+/* exp(X) by Taylor series with scaling and squaring.  X is scaled by 2^-s so
+ * that its Frobenius norm is below 1/8, the series is summed to 24 terms
+ * (remainder far below one ulp), and the result squared s times. */
+static mat3 mat_exp(mat3 X) {
+    double nrm = 0;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) nrm += creal(X.m[i][j] * conj(X.m[i][j]));
+    nrm = sqrt(nrm);
+    int s = 0;
+    while (nrm > 0.125) { nrm *= 0.5; s++; }
+    mat3 Y = m_scale(X, ldexp(1.0, -s));
+    mat3 term = m_unit(), sum = m_unit();
+    for (int k = 1; k <= 24; k++) {
+        term = m_scale(m_mul(term, Y), 1.0 / k);
+        sum = m_add(sum, term);
+    }
+    for (int k = 0; k < s; k++) sum = m_mul(sum, sum);
+    return sum;
+}
+
+/* ------------------------------------------------------------------ */
+/* gauge action and force                                              */
+/* ------------------------------------------------------------------ */
+
+static mat3 plaquette(const int L[4], const cplx *U, long i, int mu, int nu) {
+    long V = lat_volume(L);
+    long ip = lat_step(L, i, mu, +1), in = lat_step(L, i, nu, +1);
+    mat3 a = link_get(U, V, mu, i), b = link_get(U, V, nu, ip);
+    mat3 c = link_get(U, V, mu, in), d = link_get(U, V, nu, i);
+    return m_mul(m_mul(a, b), m_mul(m_dag(c), m_dag(d)));
+}
+
+/* per-site gauge action density h_G(x) = beta sum_{mu<nu} (1 - ReTr U_mn / 3) */
+static void gauge_density(const int L[4], double beta, const cplx *U, double *h) {
+    long V = lat_volume(L);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < V; i++) {
+        double s = 0;
+        for (int mu = 0; mu < 4; mu++)
+            for (int nu = mu + 1; nu < 4; nu++)
+                s += 1.0 - creal(m_trace(plaquette(L, U, i, mu, nu))) / 3.0;
+        h[i] = beta * s;
+    }
+}
+
+double oracle_gauge_action(const int L[4], double beta, const cplx *U) {
+    long V = lat_volume(L);
+    double *h = malloc(sizeof(double) * V), s = 0;
+    gauge_density(L, beta, U, h);
+    for (long i = 0; i < V; i++) s += h[i];
+    free(h);
+    return s;
+}
+
+/* average plaquette ReTr U_P / 3 over all 6V plaquettes */
+double oracle_plaquette(const int L[4], const cplx *U) {
+    long V = lat_volume(L);
+    return 1.0 - oracle_gauge_action(L, 1.0, U) / (6.0 * V);
+}
+
+/* sum of the 6 staples attached to link (mu, x):
+ * A = sum_{nu != mu} [U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+ *                     + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)]
+ * so that the part of S_G containing U_mu(x) is -beta/3 ReTr(U_mu(x) A). */
+static mat3 staple_sum(const int L[4], const cplx *U, long i, int mu) {
+    long V = lat_volume(L);
+    mat3 A = m_zero();
+    long ipm = lat_step(L, i, mu, +1);
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == mu) continue;
+        long ipn = lat_step(L, i, nu, +1), imn = lat_step(L, i, nu, -1);
+        long ipm_mn = lat_step(L, ipm, nu, -1);
+        mat3 up = m_mul(m_mul(link_get(U, V, nu, ipm), m_dag(link_get(U, V, mu, ipn))),
+                        m_dag(link_get(U, V, nu, i)));
+        mat3 dn = m_mul(m_mul(m_dag(link_get(U, V, nu, ipm_mn)), m_dag(link_get(U, V, mu, imn))),
+                        link_get(U, V, nu, imn));
+        A = m_add(A, m_add(up, dn));
+    }
+    return A;
+}
+
+/* F_a(mu,x) = -e_a S_G = -(beta/6) [TA(U_mu(x) A_mu(x))]_a
+ * (e_a of -beta/3 ReTr(U A) is -beta/3 ReTr(T^a U A) = +beta/6 [TA(UA)]_a) */
+void oracle_gauge_force(const int L[4], double beta, const cplx *U, double *F) {
+    long V = lat_volume(L);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int mu = 0; mu < 4; mu++)
+        for (long i = 0; i < V; i++) {
+            mat3 W = m_mul(link_get(U, V, mu, i), staple_sum(L, U, i, mu));
+            double x[8];
+            alg_components(traceless_antiherm(W), x);
+            for (int a = 0; a < 8; a++) F[((long)mu * V + i) * 8 + a] = -beta / 6.0 * x[a];
+        }
+}
+
+/* Directional derivative of the gauge force along a field of algebra
+ * elements V_l (components v[mu][i][8]):
+ *   J_V[F_G](l) = d/dt F_G(exp(t V) U) at t = 0,
+ * written out with the product rule on U_mu(x) A_mu(x), using
+ * d U_l = V_l U_l and d U_l^+ = -U_l^+ V_l for every link l. */
+void oracle_gauge_force_tangent(const int L[4], double beta, const cplx *U, const double *v,
+                                double *J) {
+    long V = lat_volume(L);
+    mat3 *Vm = malloc(sizeof(mat3) * 4 * V);
+    for (long l = 0; l < 4 * V; l++) Vm[l] = alg_from_components(v + l * 8);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int mu = 0; mu < 4; mu++)
+        for (long i = 0; i < V; i++) {
+            mat3 u = link_get(U, V, mu, i);
+            mat3 du = m_mul(Vm[(long)mu * V + i], u);
+            mat3 A = m_zero(), dA = m_zero();
+            long ipm = lat_step(L, i, mu, +1);
+            for (int nu = 0; nu < 4; nu++) {
+                if (nu == mu) continue;
+                long ipn = lat_step(L, i, nu, +1), imn = lat_step(L, i, nu, -1);
+                long ipm_mn = lat_step(L, ipm, nu, -1);
+                /* upper staple a b^+ c^+ with a = U_nu(x+mu), b = U_mu(x+nu), c = U_nu(x) */
+                mat3 a = link_get(U, V, nu, ipm), b = link_get(U, V, mu, ipn), c = link_get(U, V, nu, i);
+                mat3 da = m_mul(Vm[(long)nu * V + ipm], a);
+                mat3 dbd = m_scale(m_mul(m_dag(b), Vm[(long)mu * V + ipn]), -1.0); /* d(b^+) */
+                mat3 dcd = m_scale(m_mul(m_dag(c), Vm[(long)nu * V + i]), -1.0);  /* d(c^+) */
+                A = m_add(A, m_mul(m_mul(a, m_dag(b)), m_dag(c)));
+                dA = m_add(dA, m_mul(m_mul(da, m_dag(b)), m_dag(c)));
+                dA = m_add(dA, m_mul(m_mul(a, dbd), m_dag(c)));
+                dA = m_add(dA, m_mul(m_mul(a, m_dag(b)), dcd));
+                /* lower staple d^+ e^+ f with d = U_nu(x+mu-nu), e = U_mu(x-nu), f = U_nu(x-nu) */
+                mat3 d = link_get(U, V, nu, ipm_mn), e = link_get(U, V, mu, imn), f = link_get(U, V, nu, imn);
+                mat3 ddd = m_scale(m_mul(m_dag(d), Vm[(long)nu * V + ipm_mn]), -1.0);
+                mat3 ded = m_scale(m_mul(m_dag(e), Vm[(long)mu * V + imn]), -1.0);
+                mat3 df = m_mul(Vm[(long)nu * V + imn], f);
+                A = m_add(A, m_mul(m_mul(m_dag(d), m_dag(e)), f));
+                dA = m_add(dA, m_mul(m_mul(ddd, m_dag(e)), f));
+                dA = m_add(dA, m_mul(m_mul(m_dag(d), ded), f));
+                dA = m_add(dA, m_mul(m_mul(m_dag(d), m_dag(e)), df));
+            }
+            mat3 dW = m_add(m_mul(du, A), m_mul(u, dA));
+            double x[8];
+            alg_components(traceless_antiherm(dW), x);
+            for (int k = 0; k < 8; k++) J[((long)mu * V + i) * 8 + k] = -beta / 6.0 * x[k];
+        }
+    free(Vm);
+}
+
+/* ------------------------------------------------------------------ */
+/* momenta and link updates                                            */
+/* ------------------------------------------------------------------ */
+
+static void kinetic_density(const int L[4], const double *P, double *h) {
+    long V = lat_volume(L);
+    for (long i = 0; i < V; i++) {
+        double s = 0;
+        for (int mu = 0; mu < 4; mu++)
+            for (int a = 0; a < 8; a++) {
+                double p = P[((long)mu * V + i) * 8 + a];
+                s += p * p;
+            }
+        h[i] = 0.5 * s;
+    }
+}
+
+double oracle_kinetic(const int L[4], const double *P) {
+    long V = lat_volume(L);
+    double *h = malloc(sizeof(double) * V), s = 0;
+    kinetic_density(L, P, h);
+    for (long i = 0; i < V; i++) s += h[i];
+    free(h);
+    return s;
+}
+
+/* exp(h X) with X = sum_a p_a T^a; out is 3x3 row-major complex */
+void oracle_exp_su3(const double p[8], double h, cplx *out) {
+    double q[8];
+    for (int a = 0; a < 8; a++) q[a] = h * p[a];
+    mat3 E = mat_exp(alg_from_components(q));
+    memcpy(out, &E, sizeof E);
+}
+
+/* T-hat flow for time h: U_l <- exp(h P_l) U_l on every link */
+void oracle_link_update(const int L[4], double h, const double *P, cplx *U) {
+    long V = lat_volume(L);
+#pragma omp parallel for schedule(static)
+    for (long l = 0; l < 4 * V; l++) {
+        double q[8];
+        for (int a = 0; a < 8; a++) q[a] = h * P[l * 8 + a];
+        mat3 E = mat_exp(alg_from_components(q));
+        mat3 u;
+        memcpy(&u, U + l * 9, sizeof u);
+        u = m_mul(E, u);
+        memcpy(U + l * 9, &u, sizeof u);
+    }
+}
+
+/* Gram-Schmidt on rows 0 and 1, row 2 = conj(row0 x row1): the closest
+ * special-unitary matrix in the usual lattice sense. */
+void oracle_reunitarize(const int L[4], cplx *U) {
+    long V = lat_volume(L);
+#pragma omp parallel for schedule(static)
+    for (long l = 0; l < 4 * V; l++) {
+        cplx *u = U + l * 9;
+        double n0 = 0;
+        for (int j = 0; j < 3; j++) n0 += creal(u[j] * conj(u[j]));
+        n0 = 1.0 / sqrt(n0);
+        for (int j = 0; j < 3; j++) u[j] *= n0;
+        cplx d = 0;
+        for (int j = 0; j < 3; j++) d += conj(u[j]) * u[3 + j];
+        for (int j = 0; j < 3; j++) u[3 + j] -= d * u[j];
+        double n1 = 0;
+        for (int j = 0; j < 3; j++) n1 += creal(u[3 + j] * conj(u[3 + j]));
+        n1 = 1.0 / sqrt(n1);
+        for (int j = 0; j < 3; j++) u[3 + j] *= n1;
+        u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+        u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+        u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Wilson-Dirac operator                                               */
+/* ------------------------------------------------------------------ */
+
+/* DeGrand-Rossi gamma matrices, g[0..3] = gamma_1..gamma_4 (x, y, z, t) */
+static cplx GAM[4][4][4];
+static int gam_ready = 0;
+
+static void gamma_init(void) {
+    if (gam_ready) return;
+    memset(GAM, 0, sizeof GAM);
+    GAM[0][0][3] = I;  GAM[0][1][2] = I;  GAM[0][2][1] = -I; GAM[0][3][0] = -I;
+    GAM[1][0][3] = -1; GAM[1][1][2] = 1;  GAM[1][2][1] = 1;  GAM[1][3][0] = -1;
+    GAM[2][0][2] = I;  GAM[2][1][3] = -I; GAM[2][2][0] = -I; GAM[2][3][1] = I;
+    GAM[3][0][2] = 1;  GAM[3][1][3] = 1;  GAM[3][2][0] = 1;  GAM[3][3][1] = 1;
+    gam_ready = 1;
+}
+
+/* for tests: copy gamma_{mu+1} (mu = 0..3) as a 4x4 row-major complex matrix */
+void oracle_gamma(int mu, cplx *out) {
+    gamma_init();
+    memcpy(out, GAM[mu], sizeof GAM[mu]);
+}
+
+/* out(s) = (1 + sign*gamma_mu) in(s), for one 4x3 spinor */
+static void spin_proj(int mu, double sign, const cplx *in, cplx *out) {
+    for (int s = 0; s < 4; s++)
+        for (int c = 0; c < 3; c++) {
+            cplx v = in[s * 3 + c];
+            for (int t = 0; t < 4; t++) v += sign * GAM[mu][s][t] * in[t * 3 + c];
+            out[s * 3 + c] = v;
+        }
+}
+
+/* out = u * in on the colour index of each spin component */
+static void colour_mul(mat3 u, const cplx *in, cplx *out) {
+    for (int s = 0; s < 4; s++)
+        for (int a = 0; a < 3; a++) {
+            cplx v = 0;
+            for (int b = 0; b < 3; b++) v += u.m[a][b] * in[s * 3 + b];
+            out[s * 3 + a] = v;
+        }
+}
+
+/* full-lattice hopping term out = D in (in, out: [V][4][3]) */
+void oracle_dhop(const int L[4], const cplx *U, const cplx *in, cplx *out) {
+    long V = lat_volume(L);
+    gamma_init();
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < V; i++) {
+        cplx acc[12] = {0}, t1[12], t2[12];
+        for (int mu = 0; mu < 4; mu++) {
+            long f = lat_step(L, i, mu, +1), b = lat_step(L, i, mu, -1);
+            double sf = lat_bc(L, i, mu, +1), sb = lat_bc(L, i, mu, -1);
+            colour_mul(link_get(U, V, mu, i), in + f * 12, t1);
+            spin_proj(mu, -1.0, t1, t2);
+            for (int k = 0; k < 12; k++) acc[k] += sf * t2[k];
+            colour_mul(m_dag(link_get(U, V, mu, b)), in + b * 12, t1);
+            spin_proj(mu, +1.0, t1, t2);
+            for (int k = 0; k < 12; k++) acc[k] += sb * t2[k];
+        }
+        memcpy(out + i * 12, acc, sizeof acc);
+    }
+}
+
+/* out = (1 - kappa D) in, full lattice */
+void oracle_wilson(const int L[4], double kappa, const cplx *U, const cplx *in, cplx *out) {
+    long V = lat_volume(L);
+    oracle_dhop(L, U, in, out);
+    for (long k = 0; k < V * 12; k++) out[k] = in[k] - kappa * out[k];
+}
+
+/* compact even-site vector <-> full-lattice vector (odd sites zero) */
+static void even_to_full(const int L[4], const cplx *e, cplx *full) {
+    long V = lat_volume(L), k = 0;
+    for (long i = 0; i < V; i++) {
+        if (lat_parity(L, i) == 0) { memcpy(full + i * 12, e + k * 12, 12 * sizeof(cplx)); k++; }
+        else memset(full + i * 12, 0, 12 * sizeof(cplx));
+    }
+}
+
+static void full_to_even(const int L[4], const cplx *full, cplx *e) {
+    long V = lat_volume(L), k = 0;
+    for (long i = 0; i < V; i++)
+        if (lat_parity(L, i) == 0) { memcpy(e + k * 12, full + i * 12, 12 * sizeof(cplx)); k++; }
+}
+
+static void zero_parity(const int L[4], cplx *full, int par) {
+    long V = lat_volume(L);
+    for (long i = 0; i < V; i++)
+        if (lat_parity(L, i) == par) memset(full + i * 12, 0, 12 * sizeof(cplx));
+}
+
+static void apply_g5(long nsites, cplx *v) {
+    for (long i = 0; i < nsites; i++)
+        for (int k = 6; k < 12; k++) v[i * 12 + k] = -v[i * 12 + k];
+}
+
+/* Mhat psi_e = psi_e - kappa^2 D_eo D_oe psi_e on compact even vectors;
+ * dagger != 0 applies Mhat^+ = g5 Mhat g5. */
+void oracle_mhat(const int L[4], double kappa, const cplx *U, const cplx *in, cplx *out, int dagger) {
+    long V = lat_volume(L), Vh = V / 2;
+    cplx *f = malloc(sizeof(cplx) * 12 * V), *g = malloc(sizeof(cplx) * 12 * V);
+    cplx *tmp = malloc(sizeof(cplx) * 12 * Vh);
+    memcpy(tmp, in, sizeof(cplx) * 12 * Vh);
+    if (dagger) apply_g5(Vh, tmp);
+    even_to_full(L, tmp, f);
+    oracle_dhop(L, U, f, g);   /* odd part of g = D_oe psi_e */
+    zero_parity(L, g, 0);
+    oracle_dhop(L, U, g, f);   /* even part of f = D_eo D_oe psi_e */
+    full_to_even(L, f, out);
+    for (long k = 0; k < Vh * 12; k++) out[k] = tmp[k] - kappa * kappa * out[k];
+    if (dagger) apply_g5(Vh, out);
+    free(f); free(g); free(tmp);
+}
+
+static double vdot_re(long n, const cplx *a, const cplx *b) {
+    double s = 0;
+    for (long k = 0; k < n; k++) s += creal(conj(a[k]) * b[k]);
+    return s;
+}
+
+/* A = Mhat^+ Mhat */
+static void normal_op(const int L[4], double kappa, const cplx *U, const cplx *in, cplx *out,
+                      cplx *tmp) {
+    oracle_mhat(L, kappa, U, in, tmp, 0);
+    oracle_mhat(L, kappa, U, tmp, out, 1);
+}
+
+/* Conjugate gradient on A = Mhat^+ Mhat from a zero start.  Stops when the
+ * true residual |phi - A x| <= tol |phi| (when the recursive residual first
+ * passes the target the true residual is formed; if it has not passed, CG
+ * restarts from it).  Returns the iteration count, or -1 on maxiter. */
+int oracle_cg(const int L[4], double kappa, const cplx *U, const cplx *phi, cplx *x, double tol,
+              int maxiter, double *rel_resid) {
+    long n = (lat_volume(L) / 2) * 12;
+    cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n);
+    cplx *Ap = malloc(sizeof(cplx) * n), *tmp = malloc(sizeof(cplx) * n);
+    double bb = vdot_re(n, phi, phi), target = tol * tol * bb;
+    memset(x, 0, sizeof(cplx) * n);
+    memcpy(r, phi, sizeof(cplx) * n);
+    memcpy(p, r, sizeof(cplx) * n);
+    double rr = bb;
+    int it = 0, status = -1;
+    if (bb == 0.0) { status = 0; goto done; }
+    while (it < maxiter) {
+        normal_op(L, kappa, U, p, Ap, tmp);
+        double alpha = rr / vdot_re(n, p, Ap);
+        for (long k = 0; k < n; k++) { x[k] += alpha * p[k]; r[k] -= alpha * Ap[k]; }
+        double rr_new = vdot_re(n, r, r);
+        it++;
+        if (rr_new <= target) {
+            normal_op(L, kappa, U, x, Ap, tmp);
+            for (long k = 0; k < n; k++) r[k] = phi[k] - Ap[k];
+            rr_new = vdot_re(n, r, r);
+            if (rr_new <= target) { status = it; break; }
+            memcpy(p, r, sizeof(cplx) * n);
+            rr = rr_new;
+            continue;
+        }
+        double beta = rr_new / rr;
+        for (long k = 0; k < n; k++) p[k] = r[k] + beta * p[k];
+        rr = rr_new;
+    }
+done:
+    if (rel_resid) {
+        normal_op(L, kappa, U, x, Ap, tmp);
+        for (long k = 0; k < n; k++) r[k] = phi[k] - Ap[k];
+        *rel_resid = bb > 0 ? sqrt(vdot_re(n, r, r) / bb) : 0.0;
+    }
+    free(r); free(p); free(Ap); free(tmp);
+    return status;
+}
+
+/* heatbath: phi = Mhat^+ eta */
+void oracle_pf_heatbath(const int L[4], double kappa, const cplx *U, const cplx *eta, cplx *phi) {
+    oracle_mhat(L, kappa, U, eta, phi, 1);
+}
+
+/* per even site: Re phi(x)^+ X(x), compact even order */
+static void pf_density(long Vh, const cplx *phi, const cplx *X, double *h) {
+    for (long k = 0; k < Vh; k++) h[k] = vdot_re(12, phi + k * 12, X + k * 12);
+}
+
+/* S_F = Re phi^+ X with X = (Mhat^+ Mhat)^-1 phi (zero-start CG) */
+double oracle_pf_action(const int L[4], double kappa, const cplx *U, const cplx *phi, double tol,
+                        int maxiter, int *iters) {
+    long Vh = lat_volume(L) / 2;
+    cplx *X = malloc(sizeof(cplx) * 12 * Vh);
+    double *h = malloc(sizeof(double) * Vh), s = 0;
+    int it = oracle_cg(L, kappa, U, phi, X, tol, maxiter, NULL);
+    if (iters) *iters = it;
+    pf_density(Vh, phi, X, h);
+    for (long k = 0; k < Vh; k++) s += h[k];
+    free(X); free(h);
+    return s;
+}
+
+/* Pseudofermion force for S = phi^+ (Mhat^+ Mhat)^-1 phi given the solution
+ * X_e.  From the Section 4 relation e_a(S) = -X^+ e_a(M) X applied to the
+ * kernel Mhat^+ Mhat:
+ *     e_a S = 2 kappa^2 Re[ Y^+ (e_a D) X ]
+ * with full-lattice X = (X_e, D_oe X_e), Y = (Mhat X_e, D_eo^+ Mhat X_e)
+ * and D_eo^+ = g5 D_oe g5.  For the link (mu, x) this is
+ *     Re Tr[T^a W] * bc,  W = sum_s [U X(x+mu)]_s [(1-g_mu) Y(x)]_s^+
+ *                             + sum_s [U (1+g_mu) Y(x+mu)]_s [X(x)]_s^+,
+ * and Re Tr[T^a W] = -[TA(W)]_a / 2, so F_a = -e_a S = kappa^2 bc [TA W]_a.
+ * The result is ADDED to F (scaled by `scale`). */
+void oracle_fermion_force_add(const int L[4], double kappa, const cplx *U, const cplx *Xe,
+                              double scale, double *F) {
+    long V = lat_volume(L), Vh = V / 2;
+    gamma_init();
+    cplx *X = malloc(sizeof(cplx) * 12 * V), *Y = malloc(sizeof(cplx) * 12 * V);
+    cplx *t = malloc(sizeof(cplx) * 12 * V), *ye = malloc(sizeof(cplx) * 12 * Vh);
+    /* X = (X_e, D_oe X_e) */
+    even_to_full(L, Xe, X);
+    oracle_dhop(L, U, X, t);
+    for (long i = 0; i < V; i++)
+        if (lat_parity(L, i) == 1) memcpy(X + i * 12, t + i * 12, 12 * sizeof(cplx));
+    /* Y = (Mhat X_e, g5 D_oe g5 Mhat X_e) */
+    oracle_mhat(L, kappa, U, Xe, ye, 0);
+    apply_g5(Vh, ye);
+    even_to_full(L, ye, Y);
+    oracle_dhop(L, U, Y, t);
+    apply_g5(V, t);
+    apply_g5(Vh, ye);
+    even_to_full(L, ye, Y);
+    for (long i = 0; i < V; i++)
+        if (lat_parity(L, i) == 1) memcpy(Y + i * 12, t + i * 12, 12 * sizeof(cplx));
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int mu = 0; mu < 4; mu++)
+        for (long i = 0; i < V; i++) {
+            long f = lat_step(L, i, mu, +1);
+            double bc = lat_bc(L, i, mu, +1);
+            mat3 u = link_get(U, V, mu, i);
+            cplx a1[12], b1[12], a2[12], b2[12];
+            colour_mul(u, X + f * 12, a1);
+            spin_proj(mu, -1.0, Y + i * 12, b1);
+            spin_proj(mu, +1.0, Y + f * 12, b2);
+            colour_mul(u, b2, a2);
+            const cplx *x0 = X + i * 12;
+            mat3 W = m_zero();
+            for (int s = 0; s < 4; s++)
+                for (int p = 0; p < 3; p++)
+                    for (int q = 0; q < 3; q++)
+                        W.m[p][q] += a1[s * 3 + p] * conj(b1[s * 3 + q]) + a2[s * 3 + p] * conj(x0[s * 3 + q]);
+            double x[8];
+            alg_components(traceless_antiherm(W), x);
+            for (int a = 0; a < 8; a++) F[((long)mu * V + i) * 8 + a] += scale * kappa * kappa * bc * x[a];
+        }
+    free(X); free(Y); free(t); free(ye);
+}
+
+/* ------------------------------------------------------------------ */
+/* total force and integrator                                          */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double beta, kappa, cg_tol;
+    int cg_maxiter;
+    int fermions;    /* 0: pure gauge */
+    int fg_exact;    /* G stages: 0 displacement form, 1 exact gauge form */
+} oracle_action;
+
+typedef struct {
+    long solves, cg_iters, cg_fail;
+} oracle_stats;
+
+/* F = F_G + F_F at U (F_F needs one CG solve) */
+static void total_force(const int L[4], const oracle_action *act, const cplx *U, const cplx *phi,
+                        double *F, oracle_stats *st) {
+    oracle_gauge_force(L, act->beta, U, F);
+    if (!act->fermions) return;
+    long Vh = lat_volume(L) / 2;
+    cplx *X = malloc(sizeof(cplx) * 12 * Vh);
+    int it = oracle_cg(L, act->kappa, U, phi, X, act->cg_tol, act->cg_maxiter, NULL);
+    st->solves++;
+    if (it < 0) { st->cg_fail++; st->cg_iters += act->cg_maxiter; }
+    else st->cg_iters += it;
+    oracle_fermion_force_add(L, act->kappa, U, X, 1.0, F);
+    free(X);
+}
+
+void oracle_force(const int L[4], double beta, double kappa, int fermions, double cg_tol,
+                  int cg_maxiter, const cplx *U, const cplx *phi, double *F, long *stats3) {
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 0};
+    oracle_stats st = {0, 0, 0};
+    total_force(L, &act, U, phi, F, &st);
+    if (stats3) { stats3[0] = st.solves; stats3[1] = st.cg_iters; stats3[2] = st.cg_fail; }
+}
+
+/* One HMC molecular-dynamics trajectory of nsteps steps of size dt = tau/nsteps.
+ * The step is given as a table of stages, each (kind, w, xi):
+ *   'P': p += w dt F(U)                                      (S-hat flow)
+ *   'Q': U <- exp(w dt P) U                                  (T-hat flow)
+ *   'G': the combined S-hat and force-gradient flow of Table 1's last row,
+ *        exp(w dt S-hat - xi dt^3 C-hat) with C = {S,{S,T}}.  Since C depends
+ *        on U only, its flow is a momentum kick by -(-xi dt^3) grad C, which
+ *        for C = sum_a (e_a S)^2 is 2 xi dt^3 J_F[F] with
+ *        J_F[F] = d/dt F(exp(tF) U); the whole stage is
+ *          exact form:        p += w dt F + 2 xi dt^3 J_F[F]
+ *          displacement form: U' = exp((2 xi / w) dt^2 F(U)) U,
+ *                             p += w dt F(U')   (same to O(dt^5)).
+ * Consecutive P stages (the last of one step and the first of the next) are
+ * merged into one, so every P stage costs one force evaluation.
+ * eta (compact even sites) is the pseudofermion heatbath noise:
+ * phi = Mhat^+ eta is formed first and S_F(start) = eta^+ eta.  When
+ * phi_in is given instead (eta NULL), phi = phi_in and S_F(start) is measured
+ * with a CG solve (used to run a trajectory backwards on the same phi).
+ * dH = H(end) - H(start) summed as per-site differences.
+ * Returns 0, or -3 when some CG solve hit maxiter. */
+int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, double cg_tol,
+                      int cg_maxiter, int fg_exact, int nstages, const char *kinds,
+                      const double *ws, const double *xis, double tau, int nsteps, cplx *U,
+                      double *P, const cplx *eta, const cplx *phi_in, double *dH, long *stats3) {
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, fg_exact};
+    oracle_stats st = {0, 0, 0};
+    long V = lat_volume(L), Vh = V / 2;
+    double dt = tau / nsteps;
+
+    /* expand the step table over all steps and merge neighbouring P stages */
+    int nmax = nstages * nsteps, n = 0;
+    char *K = malloc(nmax);
+    double *W = malloc(sizeof(double) * nmax), *XI = malloc(sizeof(double) * nmax);
+    for (int s = 0; s < nsteps; s++)
+        for (int k = 0; k < nstages; k++) {
+            if (kinds[k] == 'P' && n > 0 && K[n - 1] == 'P') { W[n - 1] += ws[k]; continue; }
+            K[n] = kinds[k]; W[n] = ws[k]; XI[n] = xis ? xis[k] : 0.0; n++;
+        }
+
+    cplx *phi = NULL;
+    double *h0 = malloc(sizeof(double) * V), *h1 = malloc(sizeof(double) * V);
+    double *tmp = malloc(sizeof(double) * V);
+    double *F = malloc(sizeof(double) * 4 * V * 8), *F2 = malloc(sizeof(double) * 4 * V * 8);
+    cplx *Ud = malloc(sizeof(cplx) * 4 * V * 9);
+    double *hf0 = NULL, *hf1 = NULL;
+
+    /* start Hamiltonian, per site */
+    gauge_density(L, beta, U, h0);
+    kinetic_density(L, P, tmp);
+    for (long i = 0; i < V; i++) h0[i] += tmp[i];
+    if (fermions) {
+        phi = malloc(sizeof(cplx) * 12 * Vh);
+        hf0 = malloc(sizeof(double) * Vh);
+        hf1 = malloc(sizeof(double) * Vh);
+        if (eta) {
+            oracle_pf_heatbath(L, kappa, U, eta, phi);
+            for (long k = 0; k < Vh; k++) hf0[k] = vdot_re(12, eta + k * 12, eta + k * 12);
+        } else {
+            cplx *X0 = malloc(sizeof(cplx) * 12 * Vh);
+            memcpy(phi, phi_in, sizeof(cplx) * 12 * Vh);
+            int it = oracle_cg(L, kappa, U, phi, X0, cg_tol, cg_maxiter, NULL);
+            st.solves++;
+            if (it < 0) { st.cg_fail++; st.cg_iters += cg_maxiter; } else st.cg_iters += it;
+            pf_density(Vh, phi, X0, hf0);
+            free(X0);
+        }
+    }
+
+    for (int s = 0; s < n; s++) {
+        double w = W[s];
+        if (K[s] == 'P') {
+            total_force(L, &act, U, phi, F, &st);
+            for (long k = 0; k < 4 * V * 8; k++) P[k] += w * dt * F[k];
+        } else if (K[s] == 'Q') {
+            oracle_link_update(L, w * dt, P, U);
+        } else if (K[s] == 'G') {
+            total_force(L, &act, U, phi, F, &st);
+            if (fg_exact) {
+                oracle_gauge_force_tangent(L, beta, U, F, F2);
+                for (long k = 0; k < 4 * V * 8; k++)
+                    P[k] += w * dt * F[k] + 2.0 * XI[s] * dt * dt * dt * F2[k];
+            } else {
+                memcpy(Ud, U, sizeof(cplx) * 4 * V * 9);
+                oracle_link_update(L, 2.0 * XI[s] / w * dt * dt, F, Ud);
+                total_force(L, &act, Ud, phi, F2, &st);
+                for (long k = 0; k < 4 * V * 8; k++) P[k] += w * dt * F2[k];
+            }
+        }
+    }
+
+    gauge_density(L, beta, U, h1);
+    kinetic_density(L, P, tmp);
+    for (long i = 0; i < V; i++) h1[i] += tmp[i];
+    double d = 0;
+    for (long i = 0; i < V; i++) d += h1[i] - h0[i];
+    int status = 0;
+    if (fermions) {
+        cplx *X = malloc(sizeof(cplx) * 12 * Vh);
+        int it = oracle_cg(L, kappa, U, phi, X, cg_tol, cg_maxiter, NULL);
+        st.solves++;
+        if (it < 0) { st.cg_fail++; st.cg_iters += cg_maxiter; } else st.cg_iters += it;
+        pf_density(Vh, phi, X, hf1);
+        for (long k = 0; k < Vh; k++) d += hf1[k] - hf0[k];
+        free(X);
+    }
+    *dH = d;
+    if (st.cg_fail) status = -3;
+    if (stats3) { stats3[0] = st.solves; stats3[1] = st.cg_iters; stats3[2] = st.cg_fail; }
+    free(K); free(W); free(XI); free(h0); free(h1); free(tmp); free(F); free(F2); free(Ud);
+    free(phi); free(hf0); free(hf1);
+    return status;
+}
+
+/* Poisson brackets of Section 3 at (U, P):
+ *   SST = {S,{S,T}} = sum_{links,a} (e_a S)^2 = sum F_a^2            (Section 4)
+ *   TST = {T,{S,T}} = d/dt <p, F(exp(tP) U)> at t = 0, by a central
+ *         difference with step h (needs two force evaluations).         */
+void oracle_brackets(const int L[4], double beta, double kappa, int fermions, double cg_tol,
+                     int cg_maxiter, const cplx *U, const double *P, const cplx *phi, double h,
+                     double *SST, double *TST) {
+    long V = lat_volume(L), n = 4 * V * 8;
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 0};
+    oracle_stats st = {0, 0, 0};
+    double *F = malloc(sizeof(double) * n);
+    cplx *Ud = malloc(sizeof(cplx) * 4 * V * 9);
+    total_force(L, &act, U, phi, F, &st);
+    double s = 0;
+    for (long k = 0; k < n; k++) s += F[k] * F[k];
+    *SST = s;
+    double fp = 0, fm = 0;
+    memcpy(Ud, U, sizeof(cplx) * 4 * V * 9);
+    oracle_link_update(L, h, P, Ud);
+    total_force(L, &act, Ud, phi, F, &st);
+    for (long k = 0; k < n; k++) fp += P[k] * F[k];
+    memcpy(Ud, U, sizeof(cplx) * 4 * V * 9);
+    oracle_link_update(L, -h, P, Ud);
+    total_force(L, &act, Ud, phi, F, &st);
+    for (long k = 0; k < n; k++) fm += P[k] * F[k];
+    *TST = (fp - fm) / (2.0 * h);
+    free(F); free(Ud);
+}

@@ -1,0 +1,288 @@
+"""ctypes wrapper of the FP64 CPU oracle (fgi_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py.  The GPU library never imports it.
+
+Array conventions (numpy, C order, lexicographic site i = x + Lx(y + Ly(z + Lz t))):
+  U    complex128 (4, V, 3, 3)   links U_mu(x)
+  P    float64    (4, V, 8)      momentum components p_a, P = sum p_a T^a, T^a = i lambda^a / 2
+  eta, phi, X  complex128 (V/2, 4, 3)  even-site spinors, k-th even site in lexicographic order
+  full spinors complex128 (V, 4, 3)
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fgi_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force=True):
+    """Compile the oracle with gcc (plain C99 + OpenMP, -O2, no fast-math)."""
+    cmd = ["gcc", "-std=gnu99", "-O2", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
+           "-ffp-contract=off", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    if force or not os.path.exists(_LIB):
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_lp = ctypes.POINTER(ctypes.c_long)
+_vp = ctypes.c_void_p
+_d = ctypes.c_double
+_i = ctypes.c_int
+
+
+def _declare(L):
+    L.oracle_gauge_action.argtypes = [_ip, _d, _vp]
+    L.oracle_gauge_action.restype = _d
+    L.oracle_plaquette.argtypes = [_ip, _vp]
+    L.oracle_plaquette.restype = _d
+    L.oracle_gauge_force.argtypes = [_ip, _d, _vp, _vp]
+    L.oracle_gauge_force_tangent.argtypes = [_ip, _d, _vp, _vp, _vp]
+    L.oracle_kinetic.argtypes = [_ip, _vp]
+    L.oracle_kinetic.restype = _d
+    L.oracle_exp_su3.argtypes = [_vp, _d, _vp]
+    L.oracle_link_update.argtypes = [_ip, _d, _vp, _vp]
+    L.oracle_reunitarize.argtypes = [_ip, _vp]
+    L.oracle_gamma.argtypes = [_i, _vp]
+    L.oracle_dhop.argtypes = [_ip, _vp, _vp, _vp]
+    L.oracle_wilson.argtypes = [_ip, _d, _vp, _vp, _vp]
+    L.oracle_mhat.argtypes = [_ip, _d, _vp, _vp, _vp, _i]
+    L.oracle_cg.argtypes = [_ip, _d, _vp, _vp, _vp, _d, _i, _dp]
+    L.oracle_cg.restype = _i
+    L.oracle_pf_heatbath.argtypes = [_ip, _d, _vp, _vp, _vp]
+    L.oracle_pf_action.argtypes = [_ip, _d, _vp, _vp, _d, _i, _ip]
+    L.oracle_pf_action.restype = _d
+    L.oracle_fermion_force_add.argtypes = [_ip, _d, _vp, _vp, _d, _vp]
+    L.oracle_force.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _lp]
+    L.oracle_trajectory.argtypes = [_ip, _d, _d, _i, _d, _i, _i, _i, ctypes.c_char_p, _vp, _vp,
+                                    _d, _i, _vp, _vp, _vp, _vp, _dp, _lp]
+    L.oracle_trajectory.restype = _i
+    L.oracle_brackets.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _d, _dp, _dp]
+
+
+def _dims(dims):
+    return (ctypes.c_int * 4)(*[int(d) for d in dims])
+
+
+def _c(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def volume(dims):
+    return int(np.prod(dims))
+
+
+def gauge_action(dims, beta, U):
+    U = _c(U, np.complex128)
+    return lib().oracle_gauge_action(_dims(dims), beta, _ptr(U))
+
+
+def plaquette(dims, U):
+    U = _c(U, np.complex128)
+    return lib().oracle_plaquette(_dims(dims), _ptr(U))
+
+
+def gauge_force(dims, beta, U):
+    U = _c(U, np.complex128)
+    F = np.zeros((4, volume(dims), 8))
+    lib().oracle_gauge_force(_dims(dims), beta, _ptr(U), _ptr(F))
+    return F
+
+
+def gauge_force_tangent(dims, beta, U, Vdir):
+    """J_V[F_G] = d/dt F_G(exp(t V) U) at t = 0."""
+    U = _c(U, np.complex128)
+    Vdir = _c(Vdir, np.float64)
+    J = np.zeros((4, volume(dims), 8))
+    lib().oracle_gauge_force_tangent(_dims(dims), beta, _ptr(U), _ptr(Vdir), _ptr(J))
+    return J
+
+
+def kinetic(dims, P):
+    P = _c(P, np.float64)
+    return lib().oracle_kinetic(_dims(dims), _ptr(P))
+
+
+def exp_su3(p, h=1.0):
+    p = _c(p, np.float64)
+    out = np.zeros((3, 3), np.complex128)
+    lib().oracle_exp_su3(_ptr(p), h, _ptr(out))
+    return out
+
+
+def link_update(dims, h, P, U):
+    """returns exp(h P) U (U not modified)"""
+    U = np.array(U, dtype=np.complex128, copy=True, order="C")
+    P = _c(P, np.float64)
+    lib().oracle_link_update(_dims(dims), h, _ptr(P), _ptr(U))
+    return U
+
+
+def reunitarize(dims, U):
+    U = np.array(U, dtype=np.complex128, copy=True, order="C")
+    lib().oracle_reunitarize(_dims(dims), _ptr(U))
+    return U
+
+
+def gamma(mu):
+    out = np.zeros((4, 4), np.complex128)
+    lib().oracle_gamma(mu, _ptr(out))
+    return out
+
+
+def dhop(dims, U, psi):
+    U = _c(U, np.complex128)
+    psi = _c(psi, np.complex128)
+    out = np.zeros_like(psi)
+    lib().oracle_dhop(_dims(dims), _ptr(U), _ptr(psi), _ptr(out))
+    return out
+
+
+def wilson(dims, kappa, U, psi):
+    U = _c(U, np.complex128)
+    psi = _c(psi, np.complex128)
+    out = np.zeros_like(psi)
+    lib().oracle_wilson(_dims(dims), kappa, _ptr(U), _ptr(psi), _ptr(out))
+    return out
+
+
+def mhat(dims, kappa, U, psi_e, dagger=False):
+    U = _c(U, np.complex128)
+    psi_e = _c(psi_e, np.complex128)
+    out = np.zeros_like(psi_e)
+    lib().oracle_mhat(_dims(dims), kappa, _ptr(U), _ptr(psi_e), _ptr(out), int(bool(dagger)))
+    return out
+
+
+def cg(dims, kappa, U, phi, tol=1e-14, maxiter=10000):
+    """returns (X, iterations or -1, true relative residual)"""
+    U = _c(U, np.complex128)
+    phi = _c(phi, np.complex128)
+    X = np.zeros_like(phi)
+    rr = ctypes.c_double(0)
+    it = lib().oracle_cg(_dims(dims), kappa, _ptr(U), _ptr(phi), _ptr(X), tol, maxiter,
+                         ctypes.byref(rr))
+    return X, it, rr.value
+
+
+def pf_heatbath(dims, kappa, U, eta):
+    U = _c(U, np.complex128)
+    eta = _c(eta, np.complex128)
+    phi = np.zeros_like(eta)
+    lib().oracle_pf_heatbath(_dims(dims), kappa, _ptr(U), _ptr(eta), _ptr(phi))
+    return phi
+
+
+def pf_action(dims, kappa, U, phi, tol=1e-14, maxiter=10000):
+    U = _c(U, np.complex128)
+    phi = _c(phi, np.complex128)
+    it = ctypes.c_int(0)
+    s = lib().oracle_pf_action(_dims(dims), kappa, _ptr(U), _ptr(phi), tol, maxiter,
+                               ctypes.byref(it))
+    return s, it.value
+
+
+def fermion_force(dims, kappa, U, Xe):
+    U = _c(U, np.complex128)
+    Xe = _c(Xe, np.complex128)
+    F = np.zeros((4, volume(dims), 8))
+    lib().oracle_fermion_force_add(_dims(dims), kappa, _ptr(U), _ptr(Xe), 1.0, _ptr(F))
+    return F
+
+
+def force(dims, beta, U, kappa=0.0, phi=None, tol=1e-14, maxiter=10000):
+    """total force F = F_G (+ F_F when phi is given); returns (F, stats)"""
+    U = _c(U, np.complex128)
+    F = np.zeros((4, volume(dims), 8))
+    st = (ctypes.c_long * 3)()
+    ferm = phi is not None
+    phi_a = _c(phi, np.complex128) if ferm else None
+    lib().oracle_force(_dims(dims), beta, kappa, int(ferm), tol, maxiter, _ptr(U),
+                       _ptr(phi_a) if ferm else None, _ptr(F), st)
+    return F, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2])
+
+
+def trajectory(dims, beta, stages, tau, nsteps, U, P, kappa=0.0, eta=None, tol=1e-14,
+               maxiter=10000, fg_exact=False, phi=None):
+    """One MD trajectory.  stages: list of (kind, w, xi) with kind in 'PQG'.
+    Fermions: give eta (phi = Mhat^+ eta) or phi itself.
+    Returns (U_final, P_final, dH, stats, status)."""
+    U = np.array(U, dtype=np.complex128, copy=True, order="C")
+    P = np.array(P, dtype=np.float64, copy=True, order="C")
+    kinds = "".join(s[0] for s in stages).encode()
+    ws = np.array([s[1] for s in stages], np.float64)
+    xis = np.array([s[2] if len(s) > 2 else 0.0 for s in stages], np.float64)
+    ferm = eta is not None or phi is not None
+    eta_a = _c(eta, np.complex128) if eta is not None else None
+    phi_a = _c(phi, np.complex128) if phi is not None else None
+    dH = ctypes.c_double(0)
+    st = (ctypes.c_long * 3)()
+    status = lib().oracle_trajectory(_dims(dims), beta, kappa, int(ferm), tol, maxiter,
+                                     int(bool(fg_exact)), len(stages), kinds, _ptr(ws), _ptr(xis),
+                                     tau, nsteps, _ptr(U), _ptr(P),
+                                     _ptr(eta_a) if eta_a is not None else None,
+                                     _ptr(phi_a) if phi_a is not None else None,
+                                     ctypes.byref(dH), st)
+    return U, P, dH.value, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2]), status
+
+
+def brackets(dims, beta, U, P, kappa=0.0, phi=None, h=1e-4, tol=1e-14, maxiter=10000):
+    """(SST, TST) = ({S,{S,T}}, {T,{S,T}}) at (U, P); TST by central difference."""
+    U = _c(U, np.complex128)
+    P = _c(P, np.float64)
+    ferm = phi is not None
+    phi_a = _c(phi, np.complex128) if ferm else None
+    sst = ctypes.c_double(0)
+    tst = ctypes.c_double(0)
+    lib().oracle_brackets(_dims(dims), beta, kappa, int(ferm), tol, maxiter, _ptr(U), _ptr(P),
+                          _ptr(phi_a) if ferm else None, h, ctypes.byref(sst), ctypes.byref(tst))
+    return sst.value, tst.value
+
+
+# ---------------------------------------------------------------------------
+# integrator tables (Table 1), written as step stage lists (kind, w, xi)
+# ---------------------------------------------------------------------------
+
+def table(name, alpha=0.1932):
+    """Stage table of one step for the integrators of Table 1."""
+    if name == "PQP":
+        return [("P", 0.5, 0.0), ("Q", 1.0, 0.0), ("P", 0.5, 0.0)]
+    if name == "QPQ":
+        return [("Q", 0.5, 0.0), ("P", 1.0, 0.0), ("Q", 0.5, 0.0)]
+    if name == "PQPQP":
+        return [("P", alpha, 0.0), ("Q", 0.5, 0.0), ("P", 1.0 - 2.0 * alpha, 0.0),
+                ("Q", 0.5, 0.0), ("P", alpha, 0.0)]
+    if name == "FG":
+        return [("P", 1.0 / 6.0, 0.0), ("Q", 0.5, 0.0), ("G", 2.0 / 3.0, 1.0 / 72.0),
+                ("Q", 0.5, 0.0), ("P", 1.0 / 6.0, 0.0)]
+    if name == "CAMPOSTRINI":
+        c = 2.0 ** (1.0 / 3.0)
+        w1 = 1.0 / (2.0 - c)
+        w0 = -c / (2.0 - c)
+        return [("Q", w1 / 2, 0.0), ("P", w1, 0.0), ("Q", (w1 + w0) / 2, 0.0), ("P", w0, 0.0),
+                ("Q", (w1 + w0) / 2, 0.0), ("P", w1, 0.0), ("Q", w1 / 2, 0.0)]
+    raise ValueError(name)

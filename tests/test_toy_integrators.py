@@ -1,0 +1,213 @@
+"""Pins of the integrator stage tables (Table 1) on a flat toy model whose
+Poisson brackets are known in closed form.
+
+Model: q, p in R^n on a ring, S(q) = sum(q_i^2/2 + lam q_i^4/4) + c sum q_i q_{i+1},
+T = p^2/2.  With {A,B} = dA/dq . dB/dp - dA/dp . dB/dq, g = grad S, H = Hess S,
+K, L the 3rd and 4th derivative tensors (diagonal here):
+  {S,{S,T}} = g.g,              {T,{S,T}} = -p.H.p,
+  {{S,T},{S,{S,T}}} = -2 g.H.g, {{S,T},{T,{S,T}}} = -2|Hp|^2 + K[g,p,p],
+  {T,{T,{S,{S,T}}}} = 2K[p,p,g] + 2|Hp|^2,  {T,{T,{T,{S,T}}}} = -L[p,p,p,p],
+and the two brackets that start {S,{S,{S,..}}} / {T,{S,{S,..}}} vanish.
+The shadow Hamiltonians of Table 1 then predict dH over a trajectory; the
+residual after subtracting the prediction must drop one order faster
+(x16 per halving of dt for the dt^2 rows, x64 for the dt^4 rows).
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import table
+
+LAM, C = 0.7, 0.3
+N = 6
+
+
+def grad(q):
+    return q + LAM * q ** 3 + C * (np.roll(q, 1) + np.roll(q, -1))
+
+
+def hess_vec(q, v):
+    return (1 + 3 * LAM * q ** 2) * v + C * (np.roll(v, 1) + np.roll(v, -1))
+
+
+def action(q):
+    return np.sum(q ** 2 / 2 + LAM * q ** 4 / 4) + C * np.sum(q * np.roll(q, -1))
+
+
+def ham(q, p):
+    return action(q) + 0.5 * p @ p
+
+
+def brackets(q, p):
+    g = grad(q)
+    Hp = hess_vec(q, p)
+    Hg = hess_vec(q, g)
+    K = 6 * LAM * q      # K_iii
+    Lt = 6 * LAM         # L_iiii
+    return dict(
+        SST=g @ g,
+        TST=-p @ Hp,
+        STSST=-2 * g @ Hg,
+        STTST=-2 * Hp @ Hp + np.sum(K * g * p * p),
+        TTSST=2 * np.sum(K * p * p * g) + 2 * Hp @ Hp,
+        TTTST=-Lt * np.sum(p ** 4),
+    )
+
+
+def integrate(q, p, stages, tau, n, fg_exact=True):
+    """Flat-space version of the stage semantics used by the lattice code:
+    P: p += w dt F, Q: q += w dt p, G: exact p += w dt F + 2 xi dt^3 J_F[F]
+    (J_F[F] = d/dt F(q + t F) = H g) or displacement p += w dt F(q + (2xi/w) dt^2 F)."""
+    q, p = q.copy(), p.copy()
+    dt = tau / n
+    for _ in range(n):
+        for kind, w, xi in stages:
+            if kind == "P":
+                p -= w * dt * grad(q)
+            elif kind == "Q":
+                q += w * dt * p
+            elif kind == "G":
+                F = -grad(q)
+                if fg_exact:
+                    p += w * dt * F + 2 * xi * dt ** 3 * hess_vec(q, grad(q))
+                else:
+                    p += w * dt * (-grad(q + 2 * xi / w * dt ** 2 * F))
+    return q, p
+
+
+@pytest.fixture(scope="module")
+def start():
+    g = np.random.Generator(np.random.PCG64(0x09102950))
+    return g.standard_normal(N), g.standard_normal(N)
+
+
+def dt2_coeffs(name, alpha=None):
+    """Table 1 / Section 3 coefficients (a, b) of dt^2 ({S,{S,T}}, {T,{S,T}})."""
+    if name == "PQP":
+        return -1 / 24, -2 / 24
+    if name == "QPQ":
+        return 2 / 24, 1 / 24
+    if name == "PQPQP":
+        return (6 * alpha ** 2 - 6 * alpha + 1) / 12, (1 - 6 * alpha) / 24
+    raise ValueError(name)
+
+
+@pytest.mark.parametrize("name,alpha", [("PQP", None), ("QPQ", None), ("PQPQP", 1 / 6),
+                                        ("PQPQP", 0.5 * (1 - 1 / np.sqrt(3))),
+                                        ("PQPQP", 0.1932)])
+def test_dt2_shadow_rows(start, name, alpha):
+    q0, p0 = start
+    st = table(name, alpha) if alpha is not None else table(name)
+    a, b = dt2_coeffs(name, alpha)
+    b0 = brackets(q0, p0)
+    res = []
+    for n in (8, 16, 32, 64):
+        dt = 1.0 / n
+        q1, p1 = integrate(q0, p0, st, 1.0, n)
+        b1 = brackets(q1, p1)
+        dH = ham(q1, p1) - ham(q0, p0)
+        pred = -dt ** 2 * (a * (b1["SST"] - b0["SST"]) + b * (b1["TST"] - b0["TST"]))
+        res.append(abs(dH - pred))
+    ratios = [res[i] / res[i + 1] for i in range(len(res) - 1)]
+    # residual is O(dt^4): factor 16 per halving
+    assert all(12 < r < 20 for r in ratios[1:]), (name, alpha, res, ratios)
+
+
+def test_table1_special_alphas_cancel_terms():
+    # alpha = 1/6 kills the {T,{S,T}} term; alpha = (1-1/sqrt3)/2 kills {S,{S,T}}
+    a, b = dt2_coeffs("PQPQP", 1 / 6)
+    assert abs(b) < 1e-16 and abs(a - 1 / 72) < 1e-16
+    a, b = dt2_coeffs("PQPQP", 0.5 * (1 - 1 / np.sqrt(3)))
+    assert abs(a) < 1e-15 and abs(b - (np.sqrt(3) - 2) / 24) < 1e-15
+
+
+def fg_dt4(b):
+    return (36 * b["STSST"] + 72 * b["STTST"] + 126 * b["TTSST"] + 54 * b["TTTST"]) / 155520
+
+
+def camp_dt4(b):
+    c2, c4 = 2 ** (1 / 3), 4 ** (1 / 3)
+    return ((180 * c4 + 240 * c2 + 312) * b["STSST"] + (60 * c4 + 80 * c2 + 104) * b["STTST"]
+            + (20 * c2 + 32) * b["TTSST"] + (5 * c2 + 8) * b["TTTST"]) / 34560
+
+
+def test_fg_exact_dt4_row(start):
+    """Table 1 last row: H~ = H - dt^4/155520 (...); the dt^2 term is gone."""
+    q0, p0 = start
+    st = table("FG")
+    b0 = brackets(q0, p0)
+    res, raw = [], []
+    for n in (4, 8, 16, 32):
+        dt = 1.0 / n
+        q1, p1 = integrate(q0, p0, st, 1.0, n, fg_exact=True)
+        b1 = brackets(q1, p1)
+        dH = ham(q1, p1) - ham(q0, p0)
+        pred = dt ** 4 * (fg_dt4(b1) - fg_dt4(b0))
+        raw.append(abs(dH))
+        res.append(abs(dH - pred))
+    r_raw = [raw[i] / raw[i + 1] for i in range(3)]
+    r_res = [res[i] / res[i + 1] for i in range(3)]
+    assert all(12 < r < 20 for r in r_raw[1:]), raw          # dH ~ dt^4
+    assert all(48 < r < 80 for r in r_res[1:]), (res, r_res)  # residual ~ dt^6
+
+
+def test_campostrini_dt4_row(start):
+    q0, p0 = start
+    st = table("CAMPOSTRINI")
+    b0 = brackets(q0, p0)
+    res = []
+    for n in (8, 16, 32, 64):
+        dt = 1.0 / n
+        q1, p1 = integrate(q0, p0, st, 1.0, n)
+        b1 = brackets(q1, p1)
+        dH = ham(q1, p1) - ham(q0, p0)
+        pred = -dt ** 4 * (camp_dt4(b1) - camp_dt4(b0))
+        res.append(abs(dH - pred))
+    r = [res[i] / res[i + 1] for i in range(3)]
+    assert all(48 < x < 80 for x in r[1:]), (res, r)
+
+
+def test_fg_displacement_is_fourth_order(start):
+    """Displacement form U' = exp(c dt^2 F) U with c = 2 xi / w = 1/24 keeps dH ~ dt^4."""
+    q0, p0 = start
+    st = table("FG")
+    raw = []
+    for n in (8, 16, 32, 64):
+        q1, p1 = integrate(q0, p0, st, 1.0, n, fg_exact=False)
+        raw.append(abs(ham(q1, p1) - ham(q0, p0)))
+    r = [raw[i] / raw[i + 1] for i in range(3)]
+    assert all(12 < x < 20 for x in r[1:]), (raw, r)
+
+
+def test_fg_displacement_vs_exact_one_stage(start):
+    """One G stage: |p_disp - p_exact| ~ dt^5 (x32 per halving)."""
+    q0, p0 = start
+    errs = []
+    for dt in (0.2, 0.1, 0.05, 0.025):
+        w, xi = 2 / 3, 1 / 72
+        F = -grad(q0)
+        pe = p0 + w * dt * F + 2 * xi * dt ** 3 * hess_vec(q0, grad(q0))
+        pd = p0 - w * dt * grad(q0 + 2 * xi / w * dt ** 2 * F)
+        errs.append(np.max(np.abs(pe - pd)))
+    r = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(26 < x < 38 for x in r), (errs, r)
+
+
+def test_wrong_fg_factor_fails(start):
+    """The reading of the force-gradient factor matters: with the flow taken as
+    p += w dt F + xi dt^3 J_F[F] (no factor 2) the dt^2 error does not cancel."""
+    q0, p0 = start
+    raw = []
+    for n in (8, 16, 32):
+        dt = 1.0 / n
+        q, p = q0.copy(), p0.copy()
+        for _ in range(n):
+            for kind, w, xi in table("FG"):
+                if kind == "P":
+                    p -= w * dt * grad(q)
+                elif kind == "Q":
+                    q += w * dt * p
+                else:
+                    p += -w * dt * grad(q) + xi * dt ** 3 * hess_vec(q, grad(q))
+        raw.append(abs(ham(q, p) - ham(q0, p0)))
+    r = [raw[i] / raw[i + 1] for i in range(2)]
+    assert r[-1] < 6, (raw, r)  # only second order
