@@ -1,0 +1,227 @@
+/*
+ * fgi.h -- C ABI of the MI355X force-gradient HMC library (libfgi.so).
+ *
+ * The library implements the molecular-dynamics hot path of Kennedy, Clark
+ * and Silva, "Force Gradient Integrators" (LAT2009, arXiv:0910.2950):
+ * Hamiltonian H(U, p) = S(U) + T(p) (Section 2), integrators built as
+ * products of the exactly integrable flows of S, T and of the force-gradient
+ * bracket {S,{S,T}} (Section 3, Table 1), the gauge force gradient and the
+ * pseudofermion force of Section 4, and the change dH over one trajectory
+ * (Section 5, Figure 1).  All of it runs on one GPU in hand-written HIP.
+ *
+ * Conventions fixed by this library (the paper leaves them open):
+ *   - site index i = x + Lx*(y + Ly*(z + Lz*t)); every extent even and >= 2;
+ *     parity of a site = (x+y+z+t) mod 2; time direction antiperiodic for the
+ *     fermions, everything else periodic.
+ *   - su(3) basis T^a = i lambda^a / 2 (Gell-Mann lambda); a momentum or force
+ *     is stored as its 8 real components, P = sum_a p_a T^a, T(p) = 1/2 sum p_a^2.
+ *   - link update (the T-hat flow of Section 2): U <- exp(h P) U;
+ *     momentum update (S-hat flow): p <- p + h F with F_a = -d/dt S(exp(t T^a) U)
+ *     at t = 0 on each link.
+ *   - gauge action S_G = beta sum_{x, mu<nu} (1 - Re Tr U_{mu nu}(x) / 3).
+ *   - Wilson operator M = 1 - kappa D,
+ *       D psi(x) = sum_mu [(1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu)],
+ *     DeGrand-Rossi gamma matrices; even-odd Schur operator on even sites
+ *     Mhat = 1 - kappa^2 D_eo D_oe; pseudofermion action (Section 4 with the
+ *     kernel Mhat^+ Mhat)  S_F = phi^+ (Mhat^+ Mhat)^-1 phi,  phi = Mhat^+ eta.
+ *
+ * User layouts (all DEVICE pointers, caller-owned, C-contiguous):
+ *   links      complex128 [4][V][3][3]     U_mu(x), row-major colour matrix
+ *   momenta    float64    [4][V][8]        components p_a (also forces)
+ *   even field complex128 [V/2][4][3]      entry k = k-th even site in
+ *                                          lexicographic order (spin, colour)
+ *   odd field  complex128 [V/2][4][3]      same for odd sites
+ * Links and momenta must be 16- resp. 8-byte aligned.
+ *
+ * Streams: every call takes a hipStream_t (as void*, NULL = legacy default
+ * stream); all device work is ordered on it.  Calls that return host
+ * scalars (actions, dH, statistics) synchronise that stream before returning.
+ * A context is not thread-safe: one host thread per context at a time.
+ *
+ * Errors: every call returns FGI_OK (0) or a negative code; the text of the
+ * last failure of the calling thread is in fgi_last_error().  Arguments are
+ * checked on the host before any launch (FGI_EINVAL leaves outputs untouched).
+ * No C++ exception crosses this boundary.
+ */
+#ifndef FGI_H
+#define FGI_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FGI_OK 0
+#define FGI_EINVAL (-1)     /* bad geometry, null/misaligned pointer, bad option */
+#define FGI_EHIP (-2)       /* HIP runtime failure (text in fgi_last_error) */
+#define FGI_ENOCONV (-3)    /* a CG solve reached cg_maxiter; outputs are written */
+#define FGI_ENONFINITE (-4) /* NaN/Inf in a residual or in dH */
+
+#define FGI_FP64 0 /* everything FP64 */
+#define FGI_MP32 1 /* CG inner iterations FP32 (links and vectors), FP64 reliable updates */
+#define FGI_MP16 2 /* CG inner iterations with FP16 12-real links and FP16 vectors
+                      (per-site scale), FP32 accumulation, FP64 reliable updates */
+
+typedef struct fgi_ctx fgi_ctx;
+
+typedef struct {
+    int dims[4]; /* Lx, Ly, Lz, Lt */
+} fgi_geom;
+
+typedef struct {
+    double beta;        /* Wilson gauge coupling */
+    double kappa;       /* Wilson hopping parameter; 0 = pure gauge (no fermions) */
+    double kappa_hasen; /* Hasenbusch mass-preconditioning kappa' (< kappa); 0 = off */
+    double cg_tol;      /* CG stop: |phi - A x| <= cg_tol |phi| (true residual) */
+    int cg_maxiter;     /* CG iteration cap */
+    int prec;           /* FGI_FP64 | FGI_MP32 | FGI_MP16 (CG inner precision) */
+    int link_recon;     /* 18 or 12: storage of the FP32 sloppy links (FP16 uses 12) */
+    int fg_exact;       /* G stages: 0 = displacement form, 1 = exact gauge force
+                           gradient (pure gauge only) */
+} fgi_action;
+
+/* One stage of an integrator step (Table 1), coefficients multiply the step h:
+ *   kind 'P': p += w h F                       (flow of S)
+ *   kind 'Q': U <- exp(w h P) U                (flow of T); on an outer level
+ *             of a nested scheme it runs the next level for time w h instead
+ *   kind 'G': the stage exp(w h S-hat - xi h^3 C-hat), C = {S,{S,T}}:
+ *             exact form        p += w h F + 2 xi h^3 J_F[F],
+ *                               J_F[F] = d/dt F(exp(t F) U) at t = 0
+ *             displacement form U' = exp((2 xi / w) h^2 F(U)) U, p += w h F(U')
+ * Neighbouring P stages of consecutive steps are merged into one. */
+#define FGI_MAX_STAGES 16
+#define FGI_MAX_LEVELS 4
+typedef struct {
+    int kind; /* 'P', 'Q' or 'G' */
+    int pad;
+    double w;
+    double xi;
+} fgi_stage;
+
+#define FGI_TERM_GAUGE 1     /* S_G */
+#define FGI_TERM_FERMION 2   /* S_F (or the heavy Hasenbusch term S_1) */
+#define FGI_TERM_HASEN 4     /* Hasenbusch ratio term S_2 */
+
+typedef struct {
+    int nstages;
+    int terms;    /* FGI_TERM_* mask: action terms whose force this level applies */
+    int nsub;     /* steps of this level per Q stage of the level above (>= 1) */
+    int pad;
+    fgi_stage st[FGI_MAX_STAGES];
+} fgi_level;
+
+typedef struct {
+    int nlevels;  /* level 0 is the outermost time scale */
+    int pad;
+    fgi_level lev[FGI_MAX_LEVELS];
+} fgi_integrator;
+
+typedef struct {
+    long solves;           /* CG solves (the cost unit of Section 5) */
+    long cg_iters;         /* CG iterations summed over solves */
+    int cg_iters_max;      /* largest single solve */
+    int reliable_updates;  /* FP64 residual replacements summed over solves */
+    double max_rel_resid;  /* largest final true relative residual */
+    long force_evals;      /* force evaluations (gauge + fermion counted once) */
+    double seconds;        /* host wall time of the call */
+} fgi_stats;
+
+#define FGI_PQP 0          /* leapfrog, P first (Table 1 row 1) */
+#define FGI_QPQ 1          /* leapfrog, Q first (row 2) */
+#define FGI_PQPQP 2        /* Omelyan PQPQP with parameter alpha (Section 3) */
+#define FGI_CAMPOSTRINI 3  /* 4th order, 7 stages, Q first (row 5) */
+#define FGI_FG 4           /* force-gradient PQPQP (row 6) */
+
+/* ---------------------------------------------------------------- context */
+/* Create a context on HIP device `device` (owns scratch memory only). */
+int fgi_create(fgi_ctx** out, int device);
+/* Free all scratch of the context; the context pointer is invalid afterwards. */
+int fgi_destroy(fgi_ctx* ctx);
+/* Text of the calling thread's last failure ("" if none). */
+const char* fgi_last_error(void);
+/* Tuning/diagnostic options: "cg_batch" (CG iterations between host polls),
+ * "ru_delta" (reliable-update residual drop), "profile" (1: time every bare
+ * Dslash launch with HIP events), "profile_reset". */
+int fgi_set_option(fgi_ctx* ctx, const char* name, double value);
+/* Accumulated Dslash profile since the last reset: total kernel ms, number of
+ * timed launches and output sites summed over them. */
+int fgi_get_profile(fgi_ctx* ctx, double* ms, long* launches, long* sites);
+
+/* ------------------------------------------------ Hamiltonian (Section 2) */
+/* *S = S_G(U) (FP64). */
+int fgi_gauge_action(fgi_ctx* ctx, const fgi_geom* g, double beta, const void* U, double* S, void* stream);
+/* *T = 1/2 sum p_a^2 over all links (FP64). */
+int fgi_kinetic(fgi_ctx* ctx, const fgi_geom* g, const void* P, double* T, void* stream);
+
+/* ------------------------------------------- forces (Sections 2 and 4) */
+/* F = gauge force -e_a S_G on every link (momentum layout). */
+int fgi_gauge_force(fgi_ctx* ctx, const fgi_geom* g, double beta, const void* U, void* F, void* stream);
+/* J = d/dt F_G(exp(t V) U) at t = 0 for a field V of su(3) components
+ * (momentum layout).  With V = F_G this is the gauge force gradient of
+ * Section 4 that enters the Table 1 force-gradient stage. */
+int fgi_force_gradient(fgi_ctx* ctx, const fgi_geom* g, double beta, const void* U, const void* V, void* J,
+                       void* stream);
+/* F = F_G + F_F, the total force of S_G + S_F at U for pseudofermion phi
+ * (even field; NULL or act->kappa == 0 for pure gauge).  One CG solve. */
+int fgi_force(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* phi, void* F,
+              fgi_stats* st, void* stream);
+/* F = F_F(X): the pseudofermion force of Section 4, e_a S = -X^+ e_a(A) X
+ * for A = Mhat^+ Mhat, given the solution X = A^-1 phi (even field). */
+int fgi_fermion_force(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* X,
+                      void* F, void* stream);
+
+/* ------------------------------------------- Wilson operator and solver */
+/* out = D_{p,1-p} in: the hopping term from the other parity to parity
+ * `out_parity` (in: field of parity 1-out_parity, out: parity out_parity),
+ * evaluated in storage precision `prec` (FGI_FP64/MP32/MP16, links as in act). */
+int fgi_dslash(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* in, void* out,
+               int out_parity, int prec, void* stream);
+/* out = Mhat in (dagger = 0) or Mhat^+ in (dagger = 1), even fields, FP64. */
+int fgi_mhat(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* in, void* out,
+             int dagger, void* stream);
+/* X = (Mhat^+ Mhat)^-1 phi by CG from a zero start in act->prec with FP64
+ * reliable updates, to act->cg_tol.  FGI_ENOCONV when act->cg_maxiter is hit
+ * (X holds the last iterate). */
+int fgi_cg_solve(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* phi, void* X,
+                 fgi_stats* st, void* stream);
+/* phi = Mhat^+ eta (pseudofermion heatbath for Gaussian eta, P ~ exp(-eta^+ eta)). */
+int fgi_pf_heatbath(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* eta,
+                    void* phi, void* stream);
+/* *SF = Re phi^+ (Mhat^+ Mhat)^-1 phi (one CG solve). */
+int fgi_pf_action(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* phi,
+                  double* SF, fgi_stats* st, void* stream);
+
+/* ------------------------------------------ Poisson brackets (Section 3) */
+/* *SST = {S,{S,T}} = sum |F|^2 and *TST = {T,{S,T}} = d/dt <p, F(exp(tP) U)>
+ * at t = 0, the latter by a central difference of step h (two more force
+ * evaluations).  phi may be NULL for pure gauge. */
+int fgi_poisson_brackets(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* P,
+                         const void* phi, double h, double* SST, double* TST, fgi_stats* st, void* stream);
+
+/* ----------------------------------------------- integrators (Table 1) */
+/* Fill a one-level integrator for a Table 1 scheme (alpha used by PQPQP). */
+int fgi_integrator_builtin(int which, double alpha, fgi_integrator* out);
+
+/* One molecular-dynamics trajectory of length tau in nsteps outer steps.
+ * U, P (user layout) are updated in place.  Fermions (act->kappa != 0):
+ * eta1 is the heatbath noise of the pseudofermion (phi = Mhat^+ eta1, S_F at
+ * the start = eta1^+ eta1), or phi itself when pf_is_phi = 1 (S_F at the
+ * start then costs one solve); eta2 is the noise of the Hasenbusch ratio
+ * term (act->kappa_hasen != 0), else NULL.  *dH = H(end) - H(start), summed
+ * as per-site differences.  Synchronises the stream. */
+int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const fgi_integrator* integ, double tau,
+                   int nsteps, void* U, void* P, const void* eta1, const void* eta2, int pf_is_phi, double* dH,
+                   fgi_stats* st, void* stream);
+
+/* --------------------------------------------------------- utilities */
+/* U <- exp(h P) U on every link (exact su(3) exponential). */
+int fgi_link_update(fgi_ctx* ctx, const fgi_geom* g, double h, const void* P, void* U, void* stream);
+/* Project every link back onto SU(3) (Gram-Schmidt of rows 0, 1; row 2 = conj(row0 x row1)). */
+int fgi_reunitarize(fgi_ctx* ctx, const fgi_geom* g, void* U, void* stream);
+/* out[k] = exp(h sum_a p[k][a] T^a) for n elements (p: float64 [n][8],
+ * out: complex128 [n][3][3], device pointers). */
+int fgi_exp_su3(fgi_ctx* ctx, int n, const void* p, double h, void* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FGI_H */

@@ -1,0 +1,828 @@
+// C-ABI entry points, context and the integrator driver (host side).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "../../include/fgi.h"
+#include "fgi_internal.h"
+
+struct fgi_ctx {
+    fgi::Ctx c;
+};
+
+namespace fgi {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& m) { g_last_error = m; }
+
+void* DevBuf::get(size_t n) {
+    if (n > bytes) {
+        if (p) {
+            hipFree(p);
+            p = nullptr;
+            bytes = 0;
+        }
+        FGI_HIP(hipMalloc(&p, n));
+        bytes = n;
+    }
+    return p;
+}
+
+void DevBuf::release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+Geom make_geom(const int dims[4]) {
+    Geom g;
+    long V = 1;
+    for (int m = 0; m < 4; m++) {
+        if (dims[m] < 2 || (dims[m] & 1)) throw Error(FGI_EINVAL, "every lattice extent must be even and >= 2");
+        g.L[m] = dims[m];
+        V *= dims[m];
+    }
+    if (V > (1L << 30)) throw Error(FGI_EINVAL, "lattice volume too large");
+    g.Lxh = dims[0] / 2;
+    g.V = (int)V;
+    g.Vh = (int)(V / 2);
+    return g;
+}
+
+}  // namespace fgi
+
+using namespace fgi;
+
+namespace {
+
+template <typename F>
+int guarded(F&& f) {
+    try {
+        f();
+        return FGI_OK;
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return FGI_EHIP;
+    } catch (...) {
+        set_last_error("unknown failure");
+        return FGI_EHIP;
+    }
+}
+
+void need(const void* p, const char* what, size_t align) {
+    if (!p) throw Error(FGI_EINVAL, std::string("null pointer: ") + what);
+    if (((uintptr_t)p) % align) throw Error(FGI_EINVAL, std::string("misaligned pointer: ") + what);
+}
+
+Ctx& ctx_of(fgi_ctx* c) {
+    if (!c) throw Error(FGI_EINVAL, "null context");
+    FGI_HIP(hipSetDevice(c->c.device));
+    return c->c;
+}
+
+struct StreamScope {
+    Ctx& c;
+    StreamScope(Ctx& cc, void* s) : c(cc) { c.stream = (hipStream_t)s; }
+    ~StreamScope() { c.stream = nullptr; }
+};
+
+size_t gauge_bytes(const Geom& g) { return sizeof(d2) * 9 * 4 * (size_t)g.V; }
+size_t mom_bytes(const Geom& g) { return sizeof(double) * 8 * 4 * (size_t)g.V; }
+size_t spinor_bytes(const Geom& g) { return sizeof(d2) * 12 * (size_t)g.Vh; }
+size_t sloppy_bytes(const Geom& g) { return sizeof(float) * 18 * 4 * (size_t)g.V; }
+
+double sync_scalar(Ctx& c, const double* dev, int slot) {
+    FGI_HIP(hipMemcpyAsync(c.host_scal + slot, dev, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    FGI_HIP(hipStreamSynchronize(c.stream));
+    return c.host_scal[slot];
+}
+
+void check_action(const fgi_action* a) {
+    if (!a) throw Error(FGI_EINVAL, "null action");
+    if (a->prec < FGI_FP64 || a->prec > FGI_MP16) throw Error(FGI_EINVAL, "bad precision");
+    if (a->link_recon != 18 && a->link_recon != 12) throw Error(FGI_EINVAL, "link_recon must be 18 or 12");
+    if (a->kappa != 0 && (a->cg_tol <= 0 || a->cg_maxiter <= 0)) throw Error(FGI_EINVAL, "bad CG settings");
+    if (a->kappa_hasen != 0 && (a->kappa == 0 || a->kappa_hasen >= a->kappa))
+        throw Error(FGI_EINVAL, "Hasenbusch kappa' must satisfy 0 < kappa' < kappa");
+}
+
+int sloppy_prec(const fgi_action* a) { return a->prec == FGI_FP64 ? P64 : (a->prec == FGI_MP32 ? P32 : P16); }
+int sloppy_recon(const fgi_action* a) { return a->prec == FGI_MP16 ? 12 : a->link_recon; }
+
+void accumulate_stats(fgi_stats* st, const CGResult& r) {
+    if (!st) return;
+    st->solves++;
+    st->cg_iters += r.iters;
+    if (r.iters > st->cg_iters_max) st->cg_iters_max = r.iters;
+    st->reliable_updates += r.reliable_updates;
+    if (r.rel_resid > st->max_rel_resid) st->max_rel_resid = r.rel_resid;
+}
+
+// --------------------------------------------------------------------------
+// The state of one trajectory (or one single call) in internal layouts.
+// --------------------------------------------------------------------------
+struct Fields {
+    Ctx& c;
+    Geom g;
+    fgi_action act;
+    d2* U = nullptr;      // FP64 master links
+    void* Us = nullptr;   // sloppy links (MP modes)
+    d2* Ud = nullptr;     // displaced links of an FG stage
+    void* Uds = nullptr;
+    double* P = nullptr;
+    double* F = nullptr;  // force scratch
+    d2* phi[2] = {nullptr, nullptr};
+    d2* X = nullptr;
+    d2* W = nullptr;      // second solution vector (Hasenbusch)
+    int sp, rc;
+    bool nonconv = false;
+    fgi_stats* st = nullptr;
+
+    Fields(Ctx& cc, const Geom& gg, const fgi_action& a) : c(cc), g(gg), act(a) {
+        sp = sloppy_prec(&act);
+        rc = sloppy_recon(&act);
+    }
+
+    FermionOp op64(const d2* u, double kappa) const { return FermionOp{&g, kappa, u, P64, 18}; }
+    FermionOp ops(const d2* u, const void* us, double kappa) const {
+        if (sp == P64) return op64(u, kappa);
+        return FermionOp{&g, kappa, us, sp, rc};
+    }
+
+    CGResult solve(const d2* u, const void* us, double kappa, const d2* rhs, d2* x) {
+        CGResult r = cg_solve(c, op64(u, kappa), ops(u, us, kappa), sp, rhs, x, act.cg_tol, act.cg_maxiter);
+        accumulate_stats(st, r);
+        if (!r.converged) nonconv = true;
+        return r;
+    }
+
+    // out (+)= coef * F_terms(u)
+    void force(const d2* u, const void* us, int terms, double* out, double coef, bool accumulate) {
+        bool have = accumulate;
+        if (st) st->force_evals++;
+        if (terms & FGI_TERM_GAUGE) {
+            gauge_force(c, g, act.beta, u, out, coef, have ? 1 : 0);
+            have = true;
+        }
+        bool ferm = act.kappa != 0.0 && (terms & (FGI_TERM_FERMION | FGI_TERM_HASEN));
+        if (!ferm) {
+            if (!have) zero_mom(out);
+            return;
+        }
+        if (!have) zero_mom(out);
+        if (act.kappa_hasen == 0.0) {
+            if (terms & FGI_TERM_FERMION) {
+                solve(u, us, act.kappa, phi[0], X);
+                fermion_force(c, op64(u, act.kappa), X, out, coef);
+            }
+        } else {
+            throw Error(FGI_EINVAL, "Hasenbusch terms are not available in this build");
+        }
+    }
+
+    void zero_mom(double* out) { zero_doubles(c, out, mom_bytes(g) / sizeof(double)); }
+};
+
+}  // namespace
+
+// ==========================================================================
+extern "C" {
+
+const char* fgi_last_error(void) { return fgi::g_last_error.c_str(); }
+
+int fgi_create(fgi_ctx** out, int device) {
+    return guarded([&] {
+        if (!out) throw Error(FGI_EINVAL, "null output");
+        int n = 0;
+        FGI_HIP(hipGetDeviceCount(&n));
+        if (device < 0 || device >= n) throw Error(FGI_EINVAL, "bad device index");
+        FGI_HIP(hipSetDevice(device));
+        fgi_ctx* c = new fgi_ctx();
+        c->c.device = device;
+        FGI_HIP(hipHostMalloc((void**)&c->c.host_scal, 64 * sizeof(double), hipHostMallocDefault));
+        FGI_HIP(hipHostMalloc((void**)&c->c.host_state, sizeof(CGState), hipHostMallocDefault));
+        void* st = c->c.state.get(sizeof(CGState));
+        FGI_HIP(hipMemset(st, 0, sizeof(CGState)));
+        FGI_HIP(hipDeviceSynchronize());
+        *out = c;
+    });
+}
+
+int fgi_destroy(fgi_ctx* ctx) {
+    return guarded([&] {
+        if (!ctx) throw Error(FGI_EINVAL, "null context");
+        Ctx& c = ctx->c;
+        FGI_HIP(hipSetDevice(c.device));
+        FGI_HIP(hipDeviceSynchronize());
+        DevBuf* bufs[] = {&c.gauge, &c.gauge_disp, &c.sloppy, &c.sloppy_disp, &c.mom, &c.force, &c.force2,
+                          &c.scratch_mom, &c.eta, &c.phi, &c.X, &c.Xo, &c.Ye, &c.Yo, &c.tmp_e, &c.tmp_o,
+                          &c.cg_r, &c.cg_p, &c.cg_q, &c.s_x, &c.s_r, &c.s_p, &c.s_q, &c.s_t, &c.s_norms,
+                          &c.h0, &c.hf0, &c.partial, &c.scal, &c.state, &c.phi2, &c.eta2, &c.user_tmp};
+        for (DevBuf* b : bufs) b->release();
+        for (hipEvent_t e : c.ev_pool) hipEventDestroy(e);
+        if (c.host_scal) hipHostFree(c.host_scal);
+        if (c.host_state) hipHostFree(c.host_state);
+        delete ctx;
+    });
+}
+
+int fgi_set_option(fgi_ctx* ctx, const char* name, double value) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!name) throw Error(FGI_EINVAL, "null option name");
+        std::string n(name);
+        if (n == "cg_batch") {
+            if (value < 1 || value > 1024) throw Error(FGI_EINVAL, "cg_batch out of range");
+            c.cg_batch = (int)value;
+        } else if (n == "ru_delta") {
+            if (!(value > 0 && value < 1)) throw Error(FGI_EINVAL, "ru_delta must be in (0,1)");
+            c.ru_delta = value;
+        } else if (n == "profile") {
+            c.profile = value != 0;
+        } else if (n == "profile_reset") {
+            c.dslash_ms = 0;
+            c.dslash_launches = 0;
+            c.dslash_sites = 0;
+            c.ev_used = 0;
+        } else {
+            throw Error(FGI_EINVAL, "unknown option " + n);
+        }
+    });
+}
+
+int fgi_get_profile(fgi_ctx* ctx, double* ms, long* launches, long* sites) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        prof_collect(c);
+        if (ms) *ms = c.dslash_ms;
+        if (launches) *launches = c.dslash_launches;
+        if (sites) *sites = c.dslash_sites;
+    });
+}
+
+int fgi_gauge_action(fgi_ctx* ctx, const fgi_geom* gg, double beta, const void* U, double* S, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg || !S) throw Error(FGI_EINVAL, "null argument");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        StreamScope ss(c, stream);
+        d2* u = (d2*)c.gauge.get(gauge_bytes(g));
+        pack_gauge(c, g, U, u);
+        double* h = (double*)c.h0.get(sizeof(double) * g.V);
+        ham_density(c, g, beta, u, nullptr, h);
+        double* part = (double*)c.partial.get(sizeof(double) * 65536);
+        double* scal = (double*)c.scal.get(sizeof(double) * 64);
+        int nb = diff_partials(c, g.V, h, nullptr, part);
+        final_sum(c, part, nb, scal);
+        *S = sync_scalar(c, scal, 0);
+    });
+}
+
+int fgi_kinetic(fgi_ctx* ctx, const fgi_geom* gg, const void* P, double* T, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg || !T) throw Error(FGI_EINVAL, "null argument");
+        Geom g = make_geom(gg->dims);
+        need(P, "P", 8);
+        StreamScope ss(c, stream);
+        double* pm = (double*)c.mom.get(mom_bytes(g));
+        pack_mom(c, g, (const double*)P, pm);
+        double* h = (double*)c.h0.get(sizeof(double) * g.V);
+        ham_density(c, g, 0.0, nullptr, pm, h);
+        double* part = (double*)c.partial.get(sizeof(double) * 65536);
+        double* scal = (double*)c.scal.get(sizeof(double) * 64);
+        int nb = diff_partials(c, g.V, h, nullptr, part);
+        final_sum(c, part, nb, scal);
+        *T = sync_scalar(c, scal, 0);
+    });
+}
+
+int fgi_gauge_force(fgi_ctx* ctx, const fgi_geom* gg, double beta, const void* U, void* F, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(F, "F", 8);
+        StreamScope ss(c, stream);
+        d2* u = (d2*)c.gauge.get(gauge_bytes(g));
+        double* f = (double*)c.force.get(mom_bytes(g));
+        pack_gauge(c, g, U, u);
+        gauge_force(c, g, beta, u, f, 1.0, 0);
+        unpack_mom(c, g, f, (double*)F);
+    });
+}
+
+int fgi_force_gradient(fgi_ctx* ctx, const fgi_geom* gg, double beta, const void* U, const void* Vd, void* J,
+                       void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(Vd, "V", 8);
+        need(J, "J", 8);
+        StreamScope ss(c, stream);
+        d2* u = (d2*)c.gauge.get(gauge_bytes(g));
+        double* v = (double*)c.force2.get(mom_bytes(g));
+        double* j = (double*)c.force.get(mom_bytes(g));
+        pack_gauge(c, g, U, u);
+        pack_mom(c, g, (const double*)Vd, v);
+        gauge_force_tangent(c, g, beta, u, v, j, 1.0, 0);
+        unpack_mom(c, g, j, (double*)J);
+    });
+}
+
+int fgi_link_update(fgi_ctx* ctx, const fgi_geom* gg, double h, const void* P, void* U, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(P, "P", 8);
+        StreamScope ss(c, stream);
+        d2* u = (d2*)c.gauge.get(gauge_bytes(g));
+        double* pm = (double*)c.mom.get(mom_bytes(g));
+        pack_gauge(c, g, U, u);
+        pack_mom(c, g, (const double*)P, pm);
+        link_update(c, g, h, pm, u, u, nullptr, P64, 18);
+        unpack_gauge(c, g, u, U);
+    });
+}
+
+int fgi_reunitarize(fgi_ctx* ctx, const fgi_geom* gg, void* U, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        StreamScope ss(c, stream);
+        d2* u = (d2*)c.gauge.get(gauge_bytes(g));
+        pack_gauge(c, g, U, u);
+        reunitarize(c, g, u);
+        unpack_gauge(c, g, u, U);
+    });
+}
+
+int fgi_exp_su3(fgi_ctx* ctx, int n, const void* p, double h, void* out, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (n < 0) throw Error(FGI_EINVAL, "negative count");
+        if (n == 0) return;
+        need(p, "p", 8);
+        need(out, "out", 16);
+        StreamScope ss(c, stream);
+        exp_su3_batch(c, n, (const double*)p, h, out);
+    });
+}
+
+int fgi_dslash(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* in, void* out,
+               int out_parity, int prec, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        check_action(act);
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(in, "in", 16);
+        need(out, "out", 16);
+        if (out_parity != 0 && out_parity != 1) throw Error(FGI_EINVAL, "parity must be 0 or 1");
+        if (prec < FGI_FP64 || prec > FGI_MP16) throw Error(FGI_EINVAL, "bad precision");
+        StreamScope ss(c, stream);
+        fgi_action a = *act;
+        a.prec = prec;
+        Fields f(c, g, a);
+        d2* u = (d2*)c.gauge.get(gauge_bytes(g));
+        pack_gauge(c, g, U, u);
+        d2* vin = (d2*)c.tmp_e.get(spinor_bytes(g));
+        d2* vout = (d2*)c.X.get(spinor_bytes(g));
+        pack_even_spinor(c, g, in, vin);  // same layout for either parity
+        FermionOp op = f.op64(u, a.kappa);
+        if (f.sp == P64) {
+            dslash(c, op, out_parity, P64, SpinorPtr{vin, nullptr}, P64, SpinorPtr{vout, nullptr});
+        } else {
+            void* us = c.sloppy.get(sloppy_bytes(g));
+            make_sloppy(c, g, u, us, f.sp, f.rc);
+            FermionOp os = f.ops(u, us, a.kappa);
+            size_t nb = sizeof(float) * 24 * (size_t)g.Vh;
+            float* norms = (float*)c.s_norms.get(sizeof(float) * 3 * (size_t)g.Vh);
+            SpinorPtr si{c.s_p.get(nb), norms}, so{c.s_q.get(nb), norms + g.Vh};
+            convert_spinor(c, g, P64, SpinorPtr{vin, nullptr}, f.sp, si);
+            dslash(c, os, out_parity, f.sp, si, f.sp, so);
+            convert_spinor(c, g, f.sp, so, P64, SpinorPtr{vout, nullptr});
+        }
+        unpack_even_spinor(c, g, vout, out);
+    });
+}
+
+int fgi_mhat(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* in, void* out,
+             int dagger, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        check_action(act);
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(in, "in", 16);
+        need(out, "out", 16);
+        StreamScope ss(c, stream);
+        d2* u = (d2*)c.gauge.get(gauge_bytes(g));
+        pack_gauge(c, g, U, u);
+        d2* vin = (d2*)c.tmp_e.get(spinor_bytes(g));
+        d2* vout = (d2*)c.X.get(spinor_bytes(g));
+        d2* t = (d2*)c.Xo.get(spinor_bytes(g));
+        pack_even_spinor(c, g, in, vin);
+        FermionOp op{&g, act->kappa, u, P64, 18};
+        mhat(c, op, P64, SpinorPtr{vin, nullptr}, SpinorPtr{t, nullptr}, SpinorPtr{vout, nullptr}, dagger ? 1 : 0);
+        unpack_even_spinor(c, g, vout, out);
+    });
+}
+
+int fgi_pf_heatbath(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* eta,
+                    void* phi, void* stream) {
+    return fgi_mhat(ctx, gg, act, U, eta, phi, 1, stream);
+}
+
+int fgi_cg_solve(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* phi, void* X,
+                 fgi_stats* st, void* stream) {
+    int rc = guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        check_action(act);
+        if (act->kappa == 0) throw Error(FGI_EINVAL, "kappa must be nonzero");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(phi, "phi", 16);
+        need(X, "X", 16);
+        auto t0 = std::chrono::steady_clock::now();
+        StreamScope ss(c, stream);
+        Fields f(c, g, *act);
+        f.st = st;
+        f.U = (d2*)c.gauge.get(gauge_bytes(g));
+        pack_gauge(c, g, U, f.U);
+        if (f.sp != P64) {
+            f.Us = c.sloppy.get(sloppy_bytes(g));
+            make_sloppy(c, g, f.U, f.Us, f.sp, f.rc);
+        }
+        d2* ph = (d2*)c.phi.get(spinor_bytes(g));
+        d2* x = (d2*)c.X.get(spinor_bytes(g));
+        pack_even_spinor(c, g, phi, ph);
+        f.solve(f.U, f.Us, act->kappa, ph, x);
+        unpack_even_spinor(c, g, x, X);
+        FGI_HIP(hipStreamSynchronize(c.stream));
+        if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (f.nonconv) throw Error(FGI_ENOCONV, "CG reached cg_maxiter");
+    });
+    return rc;
+}
+
+int fgi_pf_action(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* phi,
+                  double* SF, fgi_stats* st, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg || !SF) throw Error(FGI_EINVAL, "null argument");
+        check_action(act);
+        if (act->kappa == 0) throw Error(FGI_EINVAL, "kappa must be nonzero");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(phi, "phi", 16);
+        StreamScope ss(c, stream);
+        Fields f(c, g, *act);
+        f.st = st;
+        f.U = (d2*)c.gauge.get(gauge_bytes(g));
+        pack_gauge(c, g, U, f.U);
+        if (f.sp != P64) {
+            f.Us = c.sloppy.get(sloppy_bytes(g));
+            make_sloppy(c, g, f.U, f.Us, f.sp, f.rc);
+        }
+        d2* ph = (d2*)c.phi.get(spinor_bytes(g));
+        d2* x = (d2*)c.X.get(spinor_bytes(g));
+        pack_even_spinor(c, g, phi, ph);
+        f.solve(f.U, f.Us, act->kappa, ph, x);
+        double* part = (double*)c.partial.get(sizeof(double) * 65536);
+        double* scal = (double*)c.scal.get(sizeof(double) * 64);
+        int nb = pf_density_partials(c, g, ph, x, nullptr, part);
+        final_sum(c, part, nb, scal);
+        *SF = sync_scalar(c, scal, 0);
+        if (f.nonconv) throw Error(FGI_ENOCONV, "CG reached cg_maxiter");
+    });
+}
+
+int fgi_force(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* phi, void* F,
+              fgi_stats* st, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        check_action(act);
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(F, "F", 8);
+        bool ferm = act->kappa != 0 && phi;
+        if (ferm) need(phi, "phi", 16);
+        StreamScope ss(c, stream);
+        fgi_action a = *act;
+        if (!ferm) a.kappa = 0;
+        Fields f(c, g, a);
+        f.st = st;
+        f.U = (d2*)c.gauge.get(gauge_bytes(g));
+        pack_gauge(c, g, U, f.U);
+        if (ferm && f.sp != P64) {
+            f.Us = c.sloppy.get(sloppy_bytes(g));
+            make_sloppy(c, g, f.U, f.Us, f.sp, f.rc);
+        }
+        if (ferm) {
+            f.phi[0] = (d2*)c.phi.get(spinor_bytes(g));
+            pack_even_spinor(c, g, phi, f.phi[0]);
+            f.X = (d2*)c.X.get(spinor_bytes(g));
+        }
+        double* fm = (double*)c.force.get(mom_bytes(g));
+        f.force(f.U, f.Us, FGI_TERM_GAUGE | FGI_TERM_FERMION, fm, 1.0, false);
+        unpack_mom(c, g, fm, (double*)F);
+        FGI_HIP(hipStreamSynchronize(c.stream));
+        if (f.nonconv) throw Error(FGI_ENOCONV, "CG reached cg_maxiter");
+    });
+}
+
+int fgi_fermion_force(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* X,
+                      void* F, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        check_action(act);
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(X, "X", 16);
+        need(F, "F", 8);
+        StreamScope ss(c, stream);
+        d2* u = (d2*)c.gauge.get(gauge_bytes(g));
+        pack_gauge(c, g, U, u);
+        d2* x = (d2*)c.X.get(spinor_bytes(g));
+        pack_even_spinor(c, g, X, x);
+        double* fm = (double*)c.force.get(mom_bytes(g));
+        zero_doubles(c, fm, mom_bytes(g) / sizeof(double));
+        fermion_force(c, FermionOp{&g, act->kappa, u, P64, 18}, x, fm, 1.0);
+        unpack_mom(c, g, fm, (double*)F);
+    });
+}
+
+int fgi_poisson_brackets(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* P,
+                         const void* phi, double h, double* SST, double* TST, fgi_stats* st, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg || !SST || !TST) throw Error(FGI_EINVAL, "null argument");
+        check_action(act);
+        if (!(h > 0)) throw Error(FGI_EINVAL, "h must be positive");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(P, "P", 8);
+        bool ferm = act->kappa != 0 && phi;
+        StreamScope ss(c, stream);
+        fgi_action a = *act;
+        if (!ferm) a.kappa = 0;
+        Fields f(c, g, a);
+        f.st = st;
+        f.U = (d2*)c.gauge.get(gauge_bytes(g));
+        f.Ud = (d2*)c.gauge_disp.get(gauge_bytes(g));
+        pack_gauge(c, g, U, f.U);
+        double* pm = (double*)c.mom.get(mom_bytes(g));
+        pack_mom(c, g, (const double*)P, pm);
+        if (ferm) {
+            f.phi[0] = (d2*)c.phi.get(spinor_bytes(g));
+            pack_even_spinor(c, g, phi, f.phi[0]);
+            f.X = (d2*)c.X.get(spinor_bytes(g));
+            if (f.sp != P64) {
+                f.Us = c.sloppy.get(sloppy_bytes(g));
+                f.Uds = c.sloppy_disp.get(sloppy_bytes(g));
+                make_sloppy(c, g, f.U, f.Us, f.sp, f.rc);
+            }
+        }
+        double* fm = (double*)c.force.get(mom_bytes(g));
+        double* part = (double*)c.partial.get(sizeof(double) * 65536);
+        double* scal = (double*)c.scal.get(sizeof(double) * 64);
+        const int terms = FGI_TERM_GAUGE | FGI_TERM_FERMION;
+        // SST = sum F^2
+        f.force(f.U, f.Us, terms, fm, 1.0, false);
+        int nb = dot_partials(c, 4L * 2 * 8 * g.Vh, fm, fm, part);
+        final_sum(c, part, nb, scal);
+        double sst = sync_scalar(c, scal, 0);
+        // TST = d/dt <p, F(exp(tP) U)> by central difference
+        double v[2];
+        for (int k = 0; k < 2; k++) {
+            double hh = k == 0 ? h : -h;
+            link_update(c, g, hh, pm, f.U, f.Ud, f.Uds, f.sp, f.rc);
+            f.force(f.Ud, f.Uds, terms, fm, 1.0, false);
+            nb = dot_partials(c, 4L * 2 * 8 * g.Vh, pm, fm, part);
+            final_sum(c, part, nb, scal + 1 + k);
+            v[k] = sync_scalar(c, scal + 1 + k, 1 + k);
+        }
+        *SST = sst;
+        *TST = (v[0] - v[1]) / (2.0 * h);
+        if (f.nonconv) throw Error(FGI_ENOCONV, "CG reached cg_maxiter");
+    });
+}
+
+int fgi_integrator_builtin(int which, double alpha, fgi_integrator* out) {
+    return guarded([&] {
+        if (!out) throw Error(FGI_EINVAL, "null output");
+        std::memset(out, 0, sizeof(*out));
+        out->nlevels = 1;
+        fgi_level& L = out->lev[0];
+        L.terms = FGI_TERM_GAUGE | FGI_TERM_FERMION | FGI_TERM_HASEN;
+        L.nsub = 1;
+        auto add = [&](int kind, double w, double xi) {
+            fgi_stage& s = L.st[L.nstages++];
+            s.kind = kind;
+            s.w = w;
+            s.xi = xi;
+        };
+        switch (which) {
+        case FGI_PQP:
+            add('P', 0.5, 0); add('Q', 1.0, 0); add('P', 0.5, 0);
+            break;
+        case FGI_QPQ:
+            add('Q', 0.5, 0); add('P', 1.0, 0); add('Q', 0.5, 0);
+            break;
+        case FGI_PQPQP:
+            if (!(alpha > 0 && alpha < 0.5)) throw Error(FGI_EINVAL, "alpha must be in (0, 1/2)");
+            add('P', alpha, 0); add('Q', 0.5, 0); add('P', 1 - 2 * alpha, 0); add('Q', 0.5, 0); add('P', alpha, 0);
+            break;
+        case FGI_CAMPOSTRINI: {
+            // Table 1 row 5: coefficients a cbrt4 + b cbrt2 + c over 12, 6, 12, 3
+            const double c2 = std::cbrt(2.0), c4 = std::cbrt(4.0);
+            const double q1 = (c4 + 2 * c2 + 4) / 12, p1 = (c4 + 2 * c2 + 4) / 6;
+            const double q2 = (-c4 - 2 * c2 + 2) / 12, p2 = -(c4 + 2 * c2 + 1) / 3;
+            add('Q', q1, 0); add('P', p1, 0); add('Q', q2, 0); add('P', p2, 0);
+            add('Q', q2, 0); add('P', p1, 0); add('Q', q1, 0);
+            break;
+        }
+        case FGI_FG:
+            add('P', 1.0 / 6, 0); add('Q', 0.5, 0); add('G', 2.0 / 3, 1.0 / 72); add('Q', 0.5, 0); add('P', 1.0 / 6, 0);
+            break;
+        default:
+            throw Error(FGI_EINVAL, "unknown integrator");
+        }
+    });
+}
+
+}  // extern "C"
+
+// ==========================================================================
+// trajectory driver
+// ==========================================================================
+namespace {
+
+void check_integrator(const fgi_integrator* I) {
+    if (!I) throw Error(FGI_EINVAL, "null integrator");
+    if (I->nlevels < 1 || I->nlevels > FGI_MAX_LEVELS) throw Error(FGI_EINVAL, "bad number of levels");
+    for (int l = 0; l < I->nlevels; l++) {
+        const fgi_level& L = I->lev[l];
+        if (L.nstages < 1 || L.nstages > FGI_MAX_STAGES) throw Error(FGI_EINVAL, "bad number of stages");
+        if (l > 0 && L.nsub < 1) throw Error(FGI_EINVAL, "nsub must be >= 1");
+        for (int k = 0; k < L.nstages; k++) {
+            int kd = L.st[k].kind;
+            if (kd != 'P' && kd != 'Q' && kd != 'G') throw Error(FGI_EINVAL, "stage kind must be P, Q or G");
+            if (kd == 'G' && L.st[k].w == 0) throw Error(FGI_EINVAL, "G stage needs w != 0");
+        }
+    }
+}
+
+struct Driver {
+    Fields& f;
+    const fgi_integrator& I;
+    Driver(Fields& ff, const fgi_integrator& ii) : f(ff), I(ii) {}
+
+    // run level l for n steps of size h (P stages merged across steps)
+    void run(int l, int n, double h) {
+        const fgi_level& L = I.lev[l];
+        double pending = 0.0;  // P weight waiting to be applied
+        for (int step = 0; step < n; step++) {
+            for (int k = 0; k < L.nstages; k++) {
+                const fgi_stage& s = L.st[k];
+                if (s.kind == 'P') {
+                    pending += s.w;
+                    continue;
+                }
+                flush(l, pending, h);
+                pending = 0.0;
+                if (s.kind == 'Q') {
+                    if (l + 1 < I.nlevels) {
+                        int ns = I.lev[l + 1].nsub;
+                        run(l + 1, ns, s.w * h / ns);
+                    } else {
+                        link_update(f.c, f.g, s.w * h, f.P, f.U, f.U, f.Us, f.sp, f.rc);
+                    }
+                } else {
+                    fg_stage(l, s.w, s.xi, h);
+                }
+            }
+        }
+        flush(l, pending, h);
+    }
+
+    void flush(int l, double w, double h) {
+        if (w == 0.0) return;
+        f.force(f.U, f.Us, I.lev[l].terms, f.P, w * h, true);
+    }
+
+    void fg_stage(int l, double w, double xi, double h) {
+        int terms = I.lev[l].terms;
+        if (f.act.fg_exact) {
+            if (f.act.kappa != 0.0 && (terms & (FGI_TERM_FERMION | FGI_TERM_HASEN)))
+                throw Error(FGI_EINVAL, "exact force gradient is available for the gauge action only");
+            f.force(f.U, f.Us, terms, f.F, 1.0, false);
+            mom_axpy(f.c, f.g, w * h, f.F, f.P);
+            gauge_force_tangent(f.c, f.g, f.act.beta, f.U, f.F, f.P, 2.0 * xi * h * h * h, 1);
+            return;
+        }
+        f.force(f.U, f.Us, terms, f.F, 1.0, false);
+        link_update(f.c, f.g, 2.0 * xi / w * h * h, f.F, f.U, f.Ud, f.Uds, f.sp, f.rc);
+        f.force(f.Ud, f.Uds, terms, f.P, w * h, true);
+    }
+};
+
+}  // namespace
+
+extern "C" int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const fgi_integrator* integ,
+                              double tau, int nsteps, void* U, void* P, const void* eta1, const void* eta2,
+                              int pf_is_phi, double* dH, fgi_stats* st, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg || !dH) throw Error(FGI_EINVAL, "null argument");
+        check_action(act);
+        check_integrator(integ);
+        if (nsteps < 1) throw Error(FGI_EINVAL, "nsteps must be >= 1");
+        if (!std::isfinite(tau)) throw Error(FGI_EINVAL, "tau must be finite");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(P, "P", 8);
+        const bool ferm = act->kappa != 0.0;
+        if (ferm) need(eta1, "eta1", 16);
+        if (act->kappa_hasen != 0.0) throw Error(FGI_EINVAL, "Hasenbusch terms are not available in this build");
+        auto t0 = std::chrono::steady_clock::now();
+        StreamScope ss(c, stream);
+        Fields f(c, g, *act);
+        f.st = st;
+        f.U = (d2*)c.gauge.get(gauge_bytes(g));
+        f.Ud = (d2*)c.gauge_disp.get(gauge_bytes(g));
+        f.P = (double*)c.mom.get(mom_bytes(g));
+        f.F = (double*)c.force.get(mom_bytes(g));
+        pack_gauge(c, g, U, f.U);
+        pack_mom(c, g, (const double*)P, f.P);
+        if (ferm && f.sp != P64) {
+            f.Us = c.sloppy.get(sloppy_bytes(g));
+            f.Uds = c.sloppy_disp.get(sloppy_bytes(g));
+            make_sloppy(c, g, f.U, f.Us, f.sp, f.rc);
+        }
+        double* h0 = (double*)c.h0.get(sizeof(double) * g.V);
+        double* h1 = (double*)c.hf0.get(sizeof(double) * g.V);
+        double* part = (double*)c.partial.get(sizeof(double) * 65536);
+        double* scal = (double*)c.scal.get(sizeof(double) * 64);
+        d2* eta = nullptr;
+        double sf0 = 0.0;
+        if (ferm) {
+            f.phi[0] = (d2*)c.phi.get(spinor_bytes(g));
+            f.X = (d2*)c.X.get(spinor_bytes(g));
+            if (pf_is_phi) {
+                pack_even_spinor(c, g, eta1, f.phi[0]);
+                f.solve(f.U, f.Us, act->kappa, f.phi[0], f.X);
+                int nb = pf_density_partials(c, g, f.phi[0], f.X, nullptr, part);
+                final_sum(c, part, nb, scal + 2);
+                sf0 = sync_scalar(c, scal + 2, 2);
+            } else {
+                eta = (d2*)c.eta.get(spinor_bytes(g));
+                pack_even_spinor(c, g, eta1, eta);
+                pf_heatbath(c, f.op64(f.U, act->kappa), eta, f.phi[0]);
+            }
+        }
+        ham_density(c, g, act->beta, f.U, f.P, h0);
+
+        Driver d(f, *integ);
+        d.run(0, nsteps, tau / nsteps);
+
+        ham_density(c, g, act->beta, f.U, f.P, h1);
+        int nb = diff_partials(c, g.V, h1, h0, part);
+        final_sum(c, part, nb, scal);
+        double dh = sync_scalar(c, scal, 0);
+        if (ferm) {
+            f.solve(f.U, f.Us, act->kappa, f.phi[0], f.X);
+            nb = pf_density_partials(c, g, f.phi[0], f.X, eta, part);
+            final_sum(c, part, nb, scal + 1);
+            dh += sync_scalar(c, scal + 1, 1) - sf0;
+        }
+        unpack_gauge(c, g, f.U, U);
+        unpack_mom(c, g, f.P, (double*)P);
+        FGI_HIP(hipStreamSynchronize(c.stream));
+        *dH = dh;
+        if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (!std::isfinite(dh)) throw Error(FGI_ENONFINITE, "dH is not finite");
+        if (f.nonconv) throw Error(FGI_ENOCONV, "a CG solve reached cg_maxiter");
+    });
+}

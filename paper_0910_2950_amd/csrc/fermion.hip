@@ -1,0 +1,685 @@
+// Fermion-side kernels: the even/odd Wilson hopping term (Dslash) with fused
+// Schur-complement and conjugate-gradient epilogues, the reliable-update CG
+// driver, the pseudofermion heatbath and the pseudofermion force.
+//
+// Wilson operator M = 1 - kappa D, D psi(x) = sum_mu [(1 - g_mu) U_mu(x) psi(x+mu)
+// + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu)], antiperiodic in t; even/odd Schur
+// operator Mhat = 1 - kappa^2 D_eo D_oe on even sites, Mhat^+ = g5 Mhat g5, so
+//   Mhat v   : t = D_oe v,      out = v - kappa^2 D_eo t
+//   Mhat^+ v : t = D_oe g5 v,   out = v - kappa^2 g5 D_eo t.
+// Every Dslash-shaped kernel computes acc = D_{p_out, 1-p_out} [g5] in and the
+// epilogue  out = center - kappa^2 [g5] acc  (or out = [g5] acc for a bare hop).
+#include <algorithm>
+#include <climits>
+#include <cmath>
+
+#include "fgi_internal.h"
+
+namespace fgi {
+
+static const int DBS = 256;  // threads per block of every Dslash-shaped kernel
+static inline int nblk(long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+// --------------------------------------------------------------- hop sum ---
+template <typename R> __device__ __forceinline__ void flip_lower(cx<R> v[4][3]) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) { v[2][k] = -v[2][k]; v[3][k] = -v[3][k]; }
+}
+
+template <int MU, int PIN, int PL, int RECON, int G5IN, typename R>
+__device__ __forceinline__ void hop_dir(const Geom& g, int p, int s, const Coord& c, const void* links,
+                                        const SpinorPtr& in, cx<R> acc[4][3]) {
+    cx<R> psi[4][3], h[2][3], uh[2][3];
+    {   // forward hop: (1 - g_mu) U_mu(x) psi(x + mu)
+        int sn = cb_neighbour(g, c, MU, +1);
+        SpinorIO<PIN, R>::load(in, sn, g.Vh, psi);
+        if (G5IN) flip_lower(psi);
+        spin_proj<MU, -1>(psi, h);
+        M3<R> u = LinkIO<PL, RECON, R>::load(links, MU, p, s, g.Vh);
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int a = 0; a < 3; a++) uh[j][a] = u.e[a][0] * h[j][0] + u.e[a][1] * h[j][1] + u.e[a][2] * h[j][2];
+        R bc = (MU == 3 && c.c[3] == g.L[3] - 1) ? R(-1) : R(1);
+        spin_recon_acc<MU, -1>(acc, uh, bc);
+    }
+    {   // backward hop: (1 + g_mu) U_mu(x - mu)^+ psi(x - mu)
+        int sn = cb_neighbour(g, c, MU, -1);
+        SpinorIO<PIN, R>::load(in, sn, g.Vh, psi);
+        if (G5IN) flip_lower(psi);
+        spin_proj<MU, +1>(psi, h);
+        M3<R> u = LinkIO<PL, RECON, R>::load(links, MU, 1 - p, sn, g.Vh);
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+                uh[j][a] = cmul(u.e[0][a], h[j][0]) + cmul(u.e[1][a], h[j][1]) + cmul(u.e[2][a], h[j][2]);
+        R bc = (MU == 3 && c.c[3] == 0) ? R(-1) : R(1);
+        spin_recon_acc<MU, +1>(acc, uh, bc);
+    }
+}
+
+template <int PIN, int PL, int RECON, int G5IN, typename R>
+__device__ __forceinline__ void hop_sum(const Geom& g, int p, int s, const void* links, const SpinorPtr& in,
+                                        cx<R> acc[4][3]) {
+    Coord c = cb_coords(g, p, s);
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) acc[i][k] = {R(0), R(0)};
+    hop_dir<0, PIN, PL, RECON, G5IN>(g, p, s, c, links, in, acc);
+    hop_dir<1, PIN, PL, RECON, G5IN>(g, p, s, c, links, in, acc);
+    hop_dir<2, PIN, PL, RECON, G5IN>(g, p, s, c, links, in, acc);
+    hop_dir<3, PIN, PL, RECON, G5IN>(g, p, s, c, links, in, acc);
+}
+
+// ------------------------------------------------ last-block reductions ---
+// Every block writes its partial; the last block to arrive (atomic counter)
+// sums all partials in a fixed order and publishes the scalar, so the value
+// does not depend on block scheduling.  Returns true in the last block.
+__device__ __forceinline__ bool last_block_sum(double v, double* partial, unsigned* counter, double* lds,
+                                               double* total) {
+    __shared__ int is_last;
+    double a[1] = {v};
+    block_sum<1>(a, lds);
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(partial + blockIdx.x, a[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        unsigned prev = atomicAdd(counter, 1u);
+        is_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    double t = 0.0;
+    for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) t += __hip_atomic_load(partial + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double b[1] = {t};
+    block_sum<1>(b, lds);
+    *total = b[0];
+    if (threadIdx.x == 0) *counter = 0u;
+    return true;
+}
+
+// ---------------------------------------------------------- the kernel ---
+enum Mode {
+    M_HOP = 0,    // out = [g5] acc
+    M_SCHUR = 1,  // out = center - kappa^2 [g5] acc          [|out|^2 -> *result]
+    M_CGQ = 2,    // CG: q = p - kappa^2 acc, pAp = |q|^2 (= <p, Mhat^+ Mhat p>)
+    M_CGX = 3,    // CG: Ap = q - kappa^2 g5 acc; x += alpha p; r -= alpha Ap; |r|^2
+    M_RESID = 4   // r = aux - (center - kappa^2 g5 acc), |r|^2 -> *result
+};
+
+struct DArgs {
+    Geom g;
+    int p_out;
+    double kappa2;
+    const void* links;
+    SpinorPtr in, center, out, aux, x, r;
+    double* partial;
+    unsigned* counter;
+    double* result;
+    CGState* st;
+    int iter;
+    int g5out;
+};
+
+template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN>
+__global__ void __launch_bounds__(DBS) k_dslash(DArgs A) {
+    typedef typename Real<PIN == P64 ? P64 : P32>::T R;
+    __shared__ double lds[DBS / 64];
+    const Geom& g = A.g;
+    if (A.st && A.st->stop_at <= A.iter) return;  // solve converged: the whole grid no-ops
+    int b = xcd_block(blockIdx.x, gridDim.x);
+    int s = b * DBS + threadIdx.x;
+    double nrm = 0.0;
+    if (s < g.Vh) {
+        cx<R> acc[4][3];
+        hop_sum<PIN, PL, RECON, G5IN, R>(g, A.p_out, s, A.links, A.in, acc);
+        if (A.g5out) flip_lower(acc);
+        if (MODE == M_HOP) {
+            SpinorIO<POUT, R>::store(A.out, s, g.Vh, acc);
+        } else {
+            cx<R> cen[4][3];
+            SpinorIO<PC, R>::load(A.center, s, g.Vh, cen);
+            const R k2 = R(A.kappa2);
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int k = 0; k < 3; k++) acc[i][k] = cen[i][k] - k2 * acc[i][k];
+            if (MODE == M_SCHUR || MODE == M_CGQ) {
+                SpinorIO<POUT, R>::store(A.out, s, g.Vh, acc);
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+#pragma unroll
+                    for (int k = 0; k < 3; k++)
+                        nrm += double(acc[i][k].re) * double(acc[i][k].re) + double(acc[i][k].im) * double(acc[i][k].im);
+            } else if (MODE == M_RESID) {
+                cx<R> ph[4][3];
+                SpinorIO<PC, R>::load(A.aux, s, g.Vh, ph);
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        acc[i][k] = ph[i][k] - acc[i][k];
+                        nrm += double(acc[i][k].re) * double(acc[i][k].re) + double(acc[i][k].im) * double(acc[i][k].im);
+                    }
+                SpinorIO<POUT, R>::store(A.out, s, g.Vh, acc);
+            } else if (MODE == M_CGX) {
+                typedef typename Real<PX>::T RX;
+                const RX al = RX(A.st->rr[A.iter & 1] / A.st->pAp);
+                cx<RX> pv[4][3], xv[4][3], rv[4][3];
+                SpinorIO<PC, RX>::load(A.aux, s, g.Vh, pv);  // p has the precision of q
+                SpinorIO<PX, RX>::load(A.x, s, g.Vh, xv);
+                SpinorIO<PX, RX>::load(A.r, s, g.Vh, rv);
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        cx<RX> ap = {RX(acc[i][k].re), RX(acc[i][k].im)};
+                        xv[i][k] = xv[i][k] + al * pv[i][k];
+                        rv[i][k] = rv[i][k] - al * ap;
+                        nrm += double(rv[i][k].re) * double(rv[i][k].re) + double(rv[i][k].im) * double(rv[i][k].im);
+                    }
+                SpinorIO<PX, RX>::store(A.x, s, g.Vh, xv);
+                SpinorIO<PX, RX>::store(A.r, s, g.Vh, rv);
+            }
+        }
+    }
+    if (MODE == M_HOP) return;
+    if (MODE == M_SCHUR && !A.result) return;
+    double total;
+    bool last = last_block_sum(nrm, A.partial, A.counter, lds, &total);
+    if (!last || threadIdx.x != 0) return;
+    if (MODE == M_CGQ) {
+        A.st->pAp = total;
+    } else if (MODE == M_CGX) {
+        A.st->rr[(A.iter + 1) & 1] = total;
+        A.st->iters = A.iter + 1;
+        if (total <= A.st->rr_stop) A.st->stop_at = A.iter + 1;
+    } else {
+        *A.result = total;
+    }
+}
+
+// p = r + beta p, beta = rr_{k+1} / rr_k  (skipped once converged)
+template <int PP, int PX>
+__global__ void __launch_bounds__(DBS) k_cg_p(Geom g, SpinorPtr r, SpinorPtr pv, CGState* st, int iter) {
+    if (st->stop_at <= iter + 1) return;
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.Vh) return;
+    typedef typename Real<PX>::T RX;
+    const RX beta = RX(st->rr[(iter + 1) & 1] / st->rr[iter & 1]);
+    cx<RX> a[4][3], b[4][3];
+    SpinorIO<PX, RX>::load(r, s, g.Vh, a);
+    SpinorIO<PP, RX>::load(pv, s, g.Vh, b);
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) b[i][k] = a[i][k] + beta * b[i][k];
+    SpinorIO<PP, RX>::store(pv, s, g.Vh, b);
+}
+
+// conversion between storage precisions (through FP64 registers)
+template <int PA, int PB>
+__global__ void k_convert(int Vh, SpinorPtr a, SpinorPtr b) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= Vh) return;
+    cx<double> v[4][3];
+    SpinorIO<PA, double>::load(a, s, Vh, v);
+    SpinorIO<PB, double>::store(b, s, Vh, v);
+}
+
+// y(FP64) += x(PX)
+template <int PX>
+__global__ void k_add_to64(int Vh, SpinorPtr x, SpinorPtr y) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= Vh) return;
+    cx<double> a[4][3], b[4][3];
+    SpinorIO<PX, double>::load(x, s, Vh, a);
+    SpinorIO<P64, double>::load(y, s, Vh, b);
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) b[i][k] = b[i][k] + a[i][k];
+    SpinorIO<P64, double>::store(y, s, Vh, b);
+}
+
+__global__ void k_set_state(CGState* st, CGState v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *st = v;
+}
+
+__global__ void k_zero(size_t n, double* p) {
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0.0;
+}
+
+__global__ void k_norm2_partials(int Vh, const d2* __restrict__ v, double* partial) {
+    __shared__ double lds[DBS / 64];
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    double a[1] = {0.0};
+    if (s < Vh) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            d2 e = v[(size_t)k * Vh + s];
+            a[0] += e.x * e.x + e.y * e.y;
+        }
+    }
+    block_sum<1>(a, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = a[0];
+}
+
+// Re phi^+ X - |eta|^2 per even site, block partials
+__global__ void k_pf_density(int Vh, const d2* __restrict__ phi, const d2* __restrict__ X, const d2* __restrict__ eta,
+                             double* partial) {
+    __shared__ double lds[DBS / 64];
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    double a[1] = {0.0};
+    if (s < Vh) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            d2 f = phi[(size_t)k * Vh + s], x = X[(size_t)k * Vh + s];
+            a[0] += f.x * x.x + f.y * x.y;
+            if (eta) {
+                d2 e = eta[(size_t)k * Vh + s];
+                a[0] -= e.x * e.x + e.y * e.y;
+            }
+        }
+    }
+    block_sum<1>(a, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = a[0];
+}
+
+// ----------------------------------------------------- fermion force ------
+// For S = phi^+ (Mhat^+ Mhat)^-1 phi and full-lattice X = (X_e, D_oe X_e),
+// Y = (Mhat X_e, g5 D_oe g5 Mhat X_e):  F_mu(x) = kappa^2 bc TA(U_mu(x) C) with
+//   C = sum_k h-_k(X(x+mu)) h-_k(Y(x))^+ + h+_k(Y(x+mu)) h+_k(X(x))^+,
+// h-/h+ the two independent spin components of (1 -/+ g_mu) (colour vectors),
+// bc = -1 on the time boundary link.
+template <int MU>
+__device__ __forceinline__ void ff_link(const Geom& g, int p, int s, const Coord& c, const d2* U,
+                                        const SpinorPtr X[2], const SpinorPtr Y[2], double coef, double* F) {
+    int sn = cb_neighbour(g, c, MU, +1);
+    cx<double> a[4][3], h1[2][3], h2[2][3], h3[2][3], h4[2][3];
+    SpinorIO<P64, double>::load(X[1 - p], sn, g.Vh, a);
+    spin_proj<MU, -1>(a, h1);
+    SpinorIO<P64, double>::load(Y[p], s, g.Vh, a);
+    spin_proj<MU, -1>(a, h2);
+    SpinorIO<P64, double>::load(Y[1 - p], sn, g.Vh, a);
+    spin_proj<MU, +1>(a, h3);
+    SpinorIO<P64, double>::load(X[p], s, g.Vh, a);
+    spin_proj<MU, +1>(a, h4);
+    M3<double> C;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            C.e[i][j] = mulc(h1[0][i], h2[0][j]) + mulc(h1[1][i], h2[1][j]) + mulc(h3[0][i], h4[0][j]) +
+                        mulc(h3[1][i], h4[1][j]);
+    M3<double> W = m3_mul(gauge_load(U, MU, p, s, g.Vh), C);
+    double x[8];
+    ta_components(W, x);
+    double f = coef * ((MU == 3 && c.c[3] == g.L[3] - 1) ? -1.0 : 1.0);
+    double* o = F + (size_t)((MU * 2 + p) * 8) * g.Vh + s;
+#pragma unroll
+    for (int k = 0; k < 8; k++) o[(size_t)k * g.Vh] += f * x[k];
+}
+
+__global__ void __launch_bounds__(256) k_fermion_force(Geom g, const d2* __restrict__ U, SpinorPtr Xe, SpinorPtr Xo,
+                                                      SpinorPtr Ye, SpinorPtr Yo, double coef, double* __restrict__ F) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.V) return;
+    int p = t / g.Vh, s = t % g.Vh;
+    Coord c = cb_coords(g, p, s);
+    SpinorPtr X[2] = {Xe, Xo}, Y[2] = {Ye, Yo};
+    ff_link<0>(g, p, s, c, U, X, Y, coef, F);
+    ff_link<1>(g, p, s, c, U, X, Y, coef, F);
+    ff_link<2>(g, p, s, c, U, X, Y, coef, F);
+    ff_link<3>(g, p, s, c, U, X, Y, coef, F);
+}
+
+// ------------------------------------------------------- host launchers ---
+static SpinorPtr sp(const void* v, float* norm = nullptr) { return SpinorPtr{(void*)v, norm}; }
+
+template <int MODE, int PIN, int PC, int POUT, int PX, int G5IN>
+static void launch_dslash(Ctx& c, const FermionOp& op, DArgs& a) {
+    int nb = nblk(a.g.Vh, DBS);
+    bool prof = c.profile && (MODE == M_HOP);
+    if (prof) prof_begin(c);
+    if constexpr (PIN == P64) {
+        if (op.prec != P64) throw Error(-1, "FP64 spinors need FP64 links");
+        hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, P64, 18, G5IN>), dim3(nb), dim3(DBS), 0, c.stream, a);
+    } else {
+        if (op.prec == P32 && op.recon == 18)
+            hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, P32, 18, G5IN>), dim3(nb), dim3(DBS), 0, c.stream, a);
+        else if (op.prec == P32)
+            hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, P32, 12, G5IN>), dim3(nb), dim3(DBS), 0, c.stream, a);
+        else if (op.prec == P16)
+            hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, P16, 12, G5IN>), dim3(nb), dim3(DBS), 0, c.stream, a);
+        else
+            throw Error(-1, "sloppy spinors need sloppy links");
+    }
+    FGI_LAUNCH_CHECK();
+    if (prof) prof_end(c, a.g.Vh);
+}
+
+static DArgs base_args(const FermionOp& op, int p_out) {
+    DArgs a{};
+    a.g = *op.g;
+    a.p_out = p_out;
+    a.kappa2 = op.kappa * op.kappa;
+    a.links = op.links;
+    return a;
+}
+
+static CGState* dev_state(Ctx& c) { return (CGState*)c.state.get(sizeof(CGState)); }
+static unsigned* dev_counter(Ctx& c) { return (unsigned*)((char*)c.state.get(sizeof(CGState)) + offsetof(CGState, counter)); }
+
+void dslash(Ctx& c, const FermionOp& op, int out_parity, int prec_in, SpinorPtr in, int prec_out, SpinorPtr out) {
+    DArgs a = base_args(op, out_parity);
+    a.in = in;
+    a.out = out;
+    if (prec_in == P64 && prec_out == P64) launch_dslash<M_HOP, P64, P64, P64, P64, 0>(c, op, a);
+    else if (prec_in == P32 && prec_out == P32) launch_dslash<M_HOP, P32, P32, P32, P32, 0>(c, op, a);
+    else if (prec_in == P16 && prec_out == P16) launch_dslash<M_HOP, P16, P16, P16, P32, 0>(c, op, a);
+    else throw Error(-1, "dslash: unsupported precision pair");
+}
+
+void mhat(Ctx& c, const FermionOp& op, int prec, SpinorPtr in_e, SpinorPtr tmp_o, SpinorPtr out_e, int dagger) {
+    if (prec != P64) throw Error(-1, "mhat: FP64 only");
+    DArgs a = base_args(op, 1);
+    a.in = in_e;
+    a.out = tmp_o;
+    if (dagger) launch_dslash<M_HOP, P64, P64, P64, P64, 1>(c, op, a);
+    else launch_dslash<M_HOP, P64, P64, P64, P64, 0>(c, op, a);
+    DArgs b = base_args(op, 0);
+    b.in = tmp_o;
+    b.center = in_e;
+    b.out = out_e;
+    b.g5out = dagger;
+    launch_dslash<M_SCHUR, P64, P64, P64, P64, 0>(c, op, b);
+}
+
+void pf_heatbath(Ctx& c, const FermionOp& op64, const d2* eta, d2* phi) {
+    d2* t = (d2*)c.tmp_o.get(sizeof(d2) * 12 * (size_t)op64.g->Vh);
+    mhat(c, op64, P64, sp(eta), sp(t), sp(phi), 1);
+}
+
+void spinor_copy(Ctx& c, const Geom& g, const d2* src, d2* dst) {
+    FGI_HIP(hipMemcpyAsync(dst, src, sizeof(d2) * 12 * (size_t)g.Vh, hipMemcpyDeviceToDevice, c.stream));
+}
+
+int pf_density_partials(Ctx& c, const Geom& g, const d2* phi, const d2* X, const d2* eta, double* partial) {
+    int nb = nblk(g.Vh, DBS);
+    hipLaunchKernelGGL(k_pf_density, dim3(nb), dim3(DBS), 0, c.stream, g.Vh, phi, X, eta, partial);
+    FGI_LAUNCH_CHECK();
+    return nb;
+}
+
+void fermion_force(Ctx& c, const FermionOp& op64, const d2* Xe, double* F, double coef) {
+    const Geom& g = *op64.g;
+    size_t n = sizeof(d2) * 12 * (size_t)g.Vh;
+    d2* Xo = (d2*)c.Xo.get(n);
+    d2* Ye = (d2*)c.Ye.get(n);
+    d2* Yo = (d2*)c.Yo.get(n);
+    d2* t = (d2*)c.tmp_o.get(n);
+    dslash(c, op64, 1, P64, sp(Xe), P64, sp(Xo));          // X_o = D_oe X_e
+    mhat(c, op64, P64, sp(Xe), sp(t), sp(Ye), 0);          // Y_e = Mhat X_e
+    {                                                       // Y_o = g5 D_oe g5 Y_e
+        DArgs a = base_args(op64, 1);
+        a.in = sp(Ye);
+        a.out = sp(Yo);
+        a.g5out = 1;
+        launch_dslash<M_HOP, P64, P64, P64, P64, 1>(c, op64, a);
+    }
+    hipLaunchKernelGGL(k_fermion_force, dim3(nblk(g.V, 256)), dim3(256), 0, c.stream, g, (const d2*)op64.links, sp(Xe),
+                       sp(Xo), sp(Ye), sp(Yo), coef * op64.kappa * op64.kappa, F);
+    FGI_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- CG ------
+static double norm2_sync(Ctx& c, const Geom& g, const d2* v) {
+    double* part = (double*)c.partial.get(sizeof(double) * 65536);
+    double* scal = (double*)c.scal.get(sizeof(double) * 64);
+    int nb = nblk(g.Vh, DBS);
+    hipLaunchKernelGGL(k_norm2_partials, dim3(nb), dim3(DBS), 0, c.stream, g.Vh, v, part);
+    FGI_LAUNCH_CHECK();
+    final_sum(c, part, nb, scal);
+    FGI_HIP(hipMemcpyAsync(c.host_scal, scal, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    FGI_HIP(hipStreamSynchronize(c.stream));
+    return c.host_scal[0];
+}
+
+// r64 = phi - Mhat^+ Mhat X (FP64), returns |r64|^2
+static double true_residual(Ctx& c, const FermionOp& op64, const d2* phi, const d2* X, d2* r64) {
+    const Geom& g = *op64.g;
+    size_t n = sizeof(d2) * 12 * (size_t)g.Vh;
+    d2* t = (d2*)c.tmp_o.get(n);
+    d2* q = (d2*)c.cg_q.get(n);
+    double* scal = (double*)c.scal.get(sizeof(double) * 64);
+    mhat(c, op64, P64, sp(X), sp(t), sp(q), 0);  // q = Mhat X
+    DArgs a = base_args(op64, 1);                // t = D_oe g5 q
+    a.in = sp(q);
+    a.out = sp(t);
+    launch_dslash<M_HOP, P64, P64, P64, P64, 1>(c, op64, a);
+    DArgs b = base_args(op64, 0);                // r = phi - (q - k^2 g5 D_eo t)
+    b.in = sp(t);
+    b.center = sp(q);
+    b.aux = sp(phi);
+    b.out = sp(r64);
+    b.g5out = 1;
+    b.partial = (double*)c.partial.get(sizeof(double) * 65536);
+    b.counter = dev_counter(c);
+    b.result = scal + 1;
+    launch_dslash<M_RESID, P64, P64, P64, P64, 0>(c, op64, b);
+    FGI_HIP(hipMemcpyAsync(c.host_scal + 1, scal + 1, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    FGI_HIP(hipStreamSynchronize(c.stream));
+    return c.host_scal[1];
+}
+
+struct CGVecs {
+    SpinorPtr x, r, p, q, t;  // x, r in PX; p, q, t in PP
+};
+
+template <int PP, int PX>
+static void cg_iteration(Ctx& c, const FermionOp& ops, const CGVecs& v, int k) {
+    CGState* st = dev_state(c);
+    double* part = (double*)c.partial.get(sizeof(double) * 65536);
+    unsigned* cnt = dev_counter(c);
+    const Geom& g = *ops.g;
+    {   // t = D_oe p
+        DArgs a = base_args(ops, 1);
+        a.in = v.p;
+        a.out = v.t;
+        a.st = st;
+        a.iter = k;
+        launch_dslash<M_HOP, PP, PP, PP, PX, 0>(c, ops, a);
+    }
+    {   // q = p - k^2 D_eo t ; pAp = |q|^2
+        DArgs a = base_args(ops, 0);
+        a.in = v.t;
+        a.center = v.p;
+        a.out = v.q;
+        a.partial = part;
+        a.counter = cnt;
+        a.st = st;
+        a.iter = k;
+        launch_dslash<M_CGQ, PP, PP, PP, PX, 0>(c, ops, a);
+    }
+    {   // t = D_oe g5 q
+        DArgs a = base_args(ops, 1);
+        a.in = v.q;
+        a.out = v.t;
+        a.st = st;
+        a.iter = k;
+        launch_dslash<M_HOP, PP, PP, PP, PX, 1>(c, ops, a);
+    }
+    {   // Ap = q - k^2 g5 D_eo t; x += alpha p; r -= alpha Ap; rr'
+        DArgs a = base_args(ops, 0);
+        a.in = v.t;
+        a.center = v.q;
+        a.aux = v.p;
+        a.x = v.x;
+        a.r = v.r;
+        a.g5out = 1;
+        a.partial = part;
+        a.counter = cnt;
+        a.st = st;
+        a.iter = k;
+        launch_dslash<M_CGX, PP, PP, PP, PX, 0>(c, ops, a);
+    }
+    hipLaunchKernelGGL((k_cg_p<PP, PX>), dim3(nblk(g.Vh, DBS)), dim3(DBS), 0, c.stream, g, v.r, v.p, st, k);
+    FGI_LAUNCH_CHECK();
+}
+
+template <int PA, int PB>
+static void convert(Ctx& c, const Geom& g, SpinorPtr a, SpinorPtr b) {
+    hipLaunchKernelGGL((k_convert<PA, PB>), dim3(nblk(g.Vh, DBS)), dim3(DBS), 0, c.stream, g.Vh, a, b);
+    FGI_LAUNCH_CHECK();
+}
+
+void convert_spinor(Ctx& c, const Geom& g, int pa, SpinorPtr a, int pb, SpinorPtr b) {
+    if (pa == P64 && pb == P32) convert<P64, P32>(c, g, a, b);
+    else if (pa == P64 && pb == P16) convert<P64, P16>(c, g, a, b);
+    else if (pa == P32 && pb == P64) convert<P32, P64>(c, g, a, b);
+    else if (pa == P16 && pb == P64) convert<P16, P64>(c, g, a, b);
+    else if (pa == P64 && pb == P64) convert<P64, P64>(c, g, a, b);
+    else throw Error(-1, "convert_spinor: unsupported pair");
+}
+
+static void zero_spinor(Ctx& c, const Geom& g, void* v, int prec) {
+    size_t n = prec == P64 ? 24 * (size_t)g.Vh : (prec == P32 ? 12 * (size_t)g.Vh : 0);
+    if (prec == P16) throw Error(-1, "zero_spinor: FP16");
+    hipLaunchKernelGGL(k_zero, dim3(nblk((long)n, 256)), dim3(256), 0, c.stream, n, (double*)v);
+    FGI_LAUNCH_CHECK();
+}
+
+template <int PP, int PX>
+static CGResult cg_run(Ctx& c, const FermionOp& op64, const FermionOp& ops, const d2* phi, d2* X, double tol,
+                       int maxiter) {
+    const Geom& g = *op64.g;
+    const size_t n64 = sizeof(d2) * 12 * (size_t)g.Vh;
+    CGResult res{0, 0, 0.0, 0};
+    double bb = norm2_sync(c, g, phi);
+    zero_spinor(c, g, X, P64);
+    if (bb == 0.0) {
+        res.converged = 1;
+        return res;
+    }
+    const double target = tol * tol * bb;
+    d2* r64 = (d2*)c.cg_r.get(n64);
+    CGVecs v;
+    float* norms = (float*)c.s_norms.get(sizeof(float) * 3 * (size_t)g.Vh);
+    if (PX == P64) {
+        spinor_copy(c, g, phi, r64);
+        v.x = sp(X);
+        v.r = sp(r64);
+        v.p = sp(c.cg_p.get(n64));
+        v.q = sp(c.cg_q.get(n64));
+        v.t = sp(c.s_t.get(n64));
+        spinor_copy(c, g, phi, (d2*)v.p.v);
+    } else {
+        size_t nx = sizeof(float) * 24 * (size_t)g.Vh;
+        size_t np = PP == P32 ? nx : sizeof(_Float16) * 24 * (size_t)g.Vh;
+        v.x = sp(c.s_x.get(nx));
+        v.r = sp(c.s_r.get(nx));
+        v.p = sp(c.s_p.get(np), norms);
+        v.q = sp(c.s_q.get(np), norms + g.Vh);
+        v.t = sp(c.s_t.get(np), norms + 2 * (size_t)g.Vh);
+        zero_spinor(c, g, v.x.v, P32);
+        convert<P64, PX>(c, g, sp(phi), v.r);
+        convert<P64, PP>(c, g, sp(phi), v.p);
+    }
+    CGState* st = dev_state(c);
+    CGState h{};
+    h.rr[0] = bb;
+    h.rr_stop = (PX == P64) ? target : std::max(c.ru_delta * c.ru_delta * bb, target);
+    h.stop_at = INT_MAX;
+    h.counter = 0;
+    hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, c.stream, st, h);
+    FGI_LAUNCH_CHECK();
+    int k = 0;
+    for (;;) {
+        int nb = std::min(c.cg_batch, maxiter - k);
+        for (int j = 0; j < nb; j++) cg_iteration<PP, PX>(c, ops, v, k + j);
+        FGI_HIP(hipMemcpyAsync(c.host_state, st, sizeof(CGState), hipMemcpyDeviceToHost, c.stream));
+        FGI_HIP(hipStreamSynchronize(c.stream));
+        const CGState hs = *c.host_state;
+        bool inner_done = hs.stop_at <= k + nb;
+        int kend = inner_done ? hs.stop_at : k + nb;
+        if (inner_done || kend >= maxiter) {
+            if (PX != P64) {
+                hipLaunchKernelGGL((k_add_to64<PX>), dim3(nblk(g.Vh, DBS)), dim3(DBS), 0, c.stream, g.Vh, v.x, sp(X));
+                FGI_LAUNCH_CHECK();
+            }
+            double rr = true_residual(c, op64, phi, X, r64);
+            res.iters = kend;
+            res.rel_resid = std::sqrt(rr / bb);
+            if (!std::isfinite(rr)) throw Error(-4, "CG: non-finite residual");
+            if (rr <= target) {
+                res.converged = 1;
+                break;
+            }
+            if (kend >= maxiter) break;
+            // reliable update: continue from the true residual, keep the direction
+            res.reliable_updates++;
+            if (PX != P64) {
+                convert<P64, PX>(c, g, sp(r64), v.r);
+                zero_spinor(c, g, v.x.v, P32);
+            }
+            CGState u = hs;
+            u.rr[kend & 1] = rr;
+            u.stop_at = INT_MAX;
+            u.rr_stop = (PX == P64) ? target : std::max(c.ru_delta * c.ru_delta * rr, target);
+            u.counter = 0;
+            hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, c.stream, st, u);
+            FGI_LAUNCH_CHECK();
+            // p = r + beta p with beta = |r_true|^2 / rr_{kend-1}
+            hipLaunchKernelGGL((k_cg_p<PP, PX>), dim3(nblk(g.Vh, DBS)), dim3(DBS), 0, c.stream, g, v.r, v.p, st, kend - 1);
+            FGI_LAUNCH_CHECK();
+            k = kend;
+        } else {
+            k = kend;
+        }
+    }
+    if (c.profile) prof_collect(c);
+    return res;
+}
+
+CGResult cg_solve(Ctx& c, const FermionOp& op64, const FermionOp& ops, int sprec, const d2* phi, d2* X, double tol,
+                  int maxiter) {
+    if (sprec == P64) return cg_run<P64, P64>(c, op64, op64, phi, X, tol, maxiter);
+    if (sprec == P32) return cg_run<P32, P32>(c, op64, ops, phi, X, tol, maxiter);
+    return cg_run<P16, P32>(c, op64, ops, phi, X, tol, maxiter);
+}
+
+// ---------------------------------------------------------- profiling -----
+void prof_begin(Ctx& c) {
+    if (c.ev_used + 2 > c.ev_pool.size()) {
+        for (int i = 0; i < 64; i++) {
+            hipEvent_t e;
+            FGI_HIP(hipEventCreate(&e));
+            c.ev_pool.push_back(e);
+        }
+    }
+    FGI_HIP(hipEventRecord(c.ev_pool[c.ev_used], c.stream));
+}
+
+void prof_end(Ctx& c, int sites) {
+    FGI_HIP(hipEventRecord(c.ev_pool[c.ev_used + 1], c.stream));
+    c.ev_used += 2;
+    c.dslash_launches++;
+    c.dslash_sites += sites;
+}
+
+void prof_collect(Ctx& c) {
+    if (c.ev_used == 0) return;
+    FGI_HIP(hipEventSynchronize(c.ev_pool[c.ev_used - 1]));
+    for (size_t i = 0; i < c.ev_used; i += 2) {
+        float ms = 0.f;
+        FGI_HIP(hipEventElapsedTime(&ms, c.ev_pool[i], c.ev_pool[i + 1]));
+        c.dslash_ms += ms;
+    }
+    c.ev_used = 0;
+}
+
+}  // namespace fgi

@@ -1,0 +1,569 @@
+// Device-side building blocks of the force-gradient HMC library for gfx950:
+// lattice geometry on the even/odd checkerboard, the structure-of-arrays field
+// layouts, SU(3)/su(3) algebra, Wilson spin projectors, storage precisions and
+// deterministic wave64 block reductions.
+//
+// Internal layouts (all per parity p in {0 even, 1 odd}, checkerboard index s
+// in [0, Vh), Vh = V/2; a "chunk" is one 16- or 8-byte vector, consecutive s
+// consecutive in memory so a wave's 64 lanes read one contiguous span):
+//   gauge FP64        double2 [4 mu][2 p][9 elem][Vh]      (row-major 3x3)
+//   gauge FP32 / 18   float2  [4][2][9][Vh]
+//   gauge FP32 / 12   float4  [4][2][3][Vh]    rows 0,1 (row 2 rebuilt)
+//   gauge FP16 / 12   half4   [4][2][3][Vh]    rows 0,1
+//   momentum / force  double  [4][2][8][Vh]    su(3) components p_a
+//   spinor FP64       double2 [12][Vh]         (spin*3 + colour)
+//   spinor FP32       float4  [6][Vh]          two complex per chunk
+//   spinor FP16       half8   [3][Vh] + float norm[Vh]   (values / norm)
+// The site with checkerboard index s and parity p is the lexicographic site
+// i = 2 s + ((y + z + t + p) & 1), i = x + Lx (y + Ly (z + Lz t)).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fgi {
+
+// --------------------------------------------------------------------------
+// geometry
+// --------------------------------------------------------------------------
+struct Geom {
+    int L[4];   // extents x, y, z, t (all even)
+    int Lxh;    // L[0] / 2
+    int V, Vh;  // volume, half volume
+};
+
+struct Coord { int c[4]; };
+
+__device__ __forceinline__ Coord cb_coords(const Geom& g, int p, int s) {
+    Coord r;
+    int xh = s % g.Lxh;
+    int q = s / g.Lxh;
+    r.c[1] = q % g.L[1]; q /= g.L[1];
+    r.c[2] = q % g.L[2];
+    r.c[3] = q / g.L[2];
+    r.c[0] = 2 * xh + ((r.c[1] + r.c[2] + r.c[3] + p) & 1);
+    return r;
+}
+
+__device__ __forceinline__ int cb_index(const Geom& g, const Coord& c) {
+    int i = c.c[0] + g.L[0] * (c.c[1] + g.L[1] * (c.c[2] + g.L[2] * c.c[3]));
+    return i >> 1;
+}
+
+// checkerboard index of the neighbour x +/- mu (it has the other parity)
+__device__ __forceinline__ int cb_neighbour(const Geom& g, Coord c, int mu, int dir) {
+    int v = c.c[mu] + dir;
+    v = v < 0 ? v + g.L[mu] : (v >= g.L[mu] ? v - g.L[mu] : v);
+    c.c[mu] = v;
+    return cb_index(g, c);
+}
+
+// XCD-aware block order: the hardware hands consecutive workgroups to the 8
+// XCDs round-robin; remap so each XCD walks one contiguous slab of sites and
+// neighbour reads stay in its own L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int nx = 8;
+    int q = nb / nx, r = nb % nx;
+    int x = b % nx, k = b / nx;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// --------------------------------------------------------------------------
+// complex numbers and 3x3 matrices, templated on the real type
+// --------------------------------------------------------------------------
+template <typename R> struct cx { R re, im; };
+
+template <typename R> __device__ __forceinline__ cx<R> mk(R a, R b) { return cx<R>{a, b}; }
+template <typename R> __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R> __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R> __device__ __forceinline__ cx<R> operator-(cx<R> a) { return {-a.re, -a.im}; }
+template <typename R> __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R> __device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R> __device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
+template <typename R> __device__ __forceinline__ cx<R> times_i(cx<R> a) { return {-a.im, a.re}; }
+template <typename R> __device__ __forceinline__ cx<R> times_mi(cx<R> a) { return {a.im, -a.re}; }
+// a * conj(b)
+template <typename R> __device__ __forceinline__ cx<R> mulc(cx<R> a, cx<R> b) {
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+// conj(a) * b
+template <typename R> __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+
+template <typename R> struct M3 { cx<R> e[3][3]; };
+
+template <typename R> __device__ __forceinline__ M3<R> m3_zero() {
+    M3<R> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) r.e[i][j] = {R(0), R(0)};
+    return r;
+}
+
+template <typename R> __device__ __forceinline__ M3<R> m3_mul(const M3<R>& a, const M3<R>& b) {
+    M3<R> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) r.e[i][j] = a.e[i][0] * b.e[0][j] + a.e[i][1] * b.e[1][j] + a.e[i][2] * b.e[2][j];
+    return r;
+}
+
+// a * b^+
+template <typename R> __device__ __forceinline__ M3<R> m3_mul_nd(const M3<R>& a, const M3<R>& b) {
+    M3<R> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            r.e[i][j] = mulc(a.e[i][0], b.e[j][0]) + mulc(a.e[i][1], b.e[j][1]) + mulc(a.e[i][2], b.e[j][2]);
+    return r;
+}
+
+// a^+ * b
+template <typename R> __device__ __forceinline__ M3<R> m3_mul_dn(const M3<R>& a, const M3<R>& b) {
+    M3<R> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            r.e[i][j] = cmul(a.e[0][i], b.e[0][j]) + cmul(a.e[1][i], b.e[1][j]) + cmul(a.e[2][i], b.e[2][j]);
+    return r;
+}
+
+template <typename R> __device__ __forceinline__ M3<R> m3_dag(const M3<R>& a) {
+    M3<R> r;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) r.e[i][j] = conj(a.e[j][i]);
+    return r;
+}
+
+template <typename R> __device__ __forceinline__ void m3_acc(M3<R>& a, const M3<R>& b) {
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) a.e[i][j] = a.e[i][j] + b.e[i][j];
+}
+
+template <typename R> __device__ __forceinline__ void m3_scale(M3<R>& a, R s) {
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) a.e[i][j] = s * a.e[i][j];
+}
+
+// --------------------------------------------------------------------------
+// su(3) <-> components.  Basis T^a = i lambda^a / 2 (Gell-Mann lambda),
+// Tr(T^a T^b) = -delta_ab / 2; X = sum_a x_a T^a; x_a = -2 Tr(T^a X).
+// Written out element by element.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ M3<double> alg_matrix(const double x[8]) {
+    const double r3 = 0.57735026918962576451;  // 1/sqrt(3)
+    M3<double> X;
+    // diagonal: i/2 (x3 + x8/sqrt3), i/2 (-x3 + x8/sqrt3), i/2 (-2 x8/sqrt3)
+    X.e[0][0] = {0.0, 0.5 * (x[2] + r3 * x[7])};
+    X.e[1][1] = {0.0, 0.5 * (-x[2] + r3 * x[7])};
+    X.e[2][2] = {0.0, -r3 * x[7]};
+    // (0,1): i/2 (x1 - i x2) = (x2/2, x1/2); (1,0): i/2 (x1 + i x2) = (-x2/2, x1/2)
+    X.e[0][1] = {0.5 * x[1], 0.5 * x[0]};
+    X.e[1][0] = {-0.5 * x[1], 0.5 * x[0]};
+    X.e[0][2] = {0.5 * x[4], 0.5 * x[3]};
+    X.e[2][0] = {-0.5 * x[4], 0.5 * x[3]};
+    X.e[1][2] = {0.5 * x[6], 0.5 * x[5]};
+    X.e[2][1] = {-0.5 * x[6], 0.5 * x[5]};
+    return X;
+}
+
+// components of the traceless anti-Hermitian part TA(W) = (W - W^+)/2 - Tr(W - W^+)/6,
+// i.e. x_a = -2 Tr(T^a TA(W)) = Im-parts combined as below.
+template <typename R> __device__ __forceinline__ void ta_components(const M3<R>& W, R x[8]) {
+    const R r3 = R(0.57735026918962576451);
+    // A = (W - W^+)/2: A01 = (W01 - conj W10)/2 etc.; A has diagonal i*Im(W_kk)
+    // -2 Tr(T^a A) for the off-diagonal generators:
+    //   a=1: Im(W01 + W10)          a=2: Re(W01 - W10)
+    //   a=4: Im(W02 + W20)          a=5: Re(W02 - W20)
+    //   a=6: Im(W12 + W21)          a=7: Re(W12 - W21)
+    //   a=3: Im(W00) - Im(W11)      a=8: (Im W00 + Im W11 - 2 Im W22)/sqrt3
+    x[0] = W.e[0][1].im + W.e[1][0].im;
+    x[1] = W.e[0][1].re - W.e[1][0].re;
+    x[2] = W.e[0][0].im - W.e[1][1].im;
+    x[3] = W.e[0][2].im + W.e[2][0].im;
+    x[4] = W.e[0][2].re - W.e[2][0].re;
+    x[5] = W.e[1][2].im + W.e[2][1].im;
+    x[6] = W.e[1][2].re - W.e[2][1].re;
+    x[7] = r3 * (W.e[0][0].im + W.e[1][1].im - R(2) * W.e[2][2].im);
+}
+
+// --------------------------------------------------------------------------
+// su(3) exponential: exp(X) for traceless anti-Hermitian X, by the
+// Cayley-Hamilton closed form of Morningstar and Peardon (Phys. Rev. D 69
+// (2004) 054501): with Q = -i X Hermitian traceless, exp(iQ) = f0 + f1 Q + f2 Q^2,
+// where f_j follow from c0 = det Q, c1 = Tr Q^2 / 2.  Negative c0 is mapped
+// to positive c0 with f_j(-c0) = (-1)^j conj(f_j(c0)).  Tiny Q uses a Taylor
+// series instead (the closed form divides by a quantity of order c1).
+// --------------------------------------------------------------------------
+__device__ inline M3<double> su3_exp(const M3<double>& X) {
+    M3<double> Q;  // Q = -i X
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) Q.e[i][j] = times_mi(X.e[i][j]);
+    M3<double> Q2 = m3_mul(Q, Q);
+    double c1 = 0.5 * (Q2.e[0][0].re + Q2.e[1][1].re + Q2.e[2][2].re);
+    M3<double> r;
+    if (c1 < 1e-6) {
+        // exp(X) = sum_k X^k / k!, |X|^2 ~ 2 c1 < 2e-6: 9 terms leave < 1e-30
+        M3<double> term, sum;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                term.e[i][j] = {i == j ? 1.0 : 0.0, 0.0};
+                sum.e[i][j] = term.e[i][j];
+            }
+        for (int k = 1; k <= 9; k++) {
+            term = m3_mul(term, X);
+            m3_scale(term, 1.0 / k);
+            m3_acc(sum, term);
+        }
+        return sum;
+    }
+    // c0 = det Q = Tr Q^3 / 3 (real for Hermitian traceless Q)
+    M3<double> Q3 = m3_mul(Q2, Q);
+    double c0 = (Q3.e[0][0].re + Q3.e[1][1].re + Q3.e[2][2].re) / 3.0;
+    bool neg = c0 < 0;
+    c0 = fabs(c0);
+    double c0max = 2.0 * pow(c1 / 3.0, 1.5);
+    double ratio = c0 / c0max;
+    ratio = ratio > 1.0 ? 1.0 : ratio;
+    double theta = acos(ratio);
+    double u = sqrt(c1 / 3.0) * cos(theta / 3.0);
+    double w = sqrt(c1) * sin(theta / 3.0);
+    double u2 = u * u, w2 = w * w;
+    double xi0 = (fabs(w) < 0.05) ? 1.0 - w2 / 6.0 * (1.0 - w2 / 20.0 * (1.0 - w2 / 42.0 * (1.0 - w2 / 72.0)))
+                                  : sin(w) / w;
+    double cw = cos(w);
+    double s2u, c2u, su, cu;
+    sincos(2.0 * u, &s2u, &c2u);
+    sincos(u, &su, &cu);
+    cx<double> e2iu = {c2u, s2u};
+    cx<double> emiu = {cu, -su};
+    // h0 = (u^2 - w^2) e^{2iu} + e^{-iu} (8 u^2 cos w + 2 i u (3u^2 + w^2) xi0)
+    cx<double> h0 = (u2 - w2) * e2iu + emiu * mk(8.0 * u2 * cw, 2.0 * u * (3.0 * u2 + w2) * xi0);
+    // h1 = 2u e^{2iu} - e^{-iu} (2u cos w - i (3u^2 - w^2) xi0)
+    cx<double> h1 = (2.0 * u) * e2iu - emiu * mk(2.0 * u * cw, -(3.0 * u2 - w2) * xi0);
+    // h2 = e^{2iu} - e^{-iu} (cos w + 3 i u xi0)
+    cx<double> h2 = e2iu - emiu * mk(cw, 3.0 * u * xi0);
+    double den = 1.0 / (9.0 * u2 - w2);
+    cx<double> f0 = den * h0, f1 = den * h1, f2 = den * h2;
+    if (neg) {
+        f0 = conj(f0);
+        f1 = -conj(f1);
+        f2 = conj(f2);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            cx<double> v = f1 * Q.e[i][j] + f2 * Q2.e[i][j];
+            if (i == j) v = v + f0;
+            r.e[i][j] = v;
+        }
+    return r;
+}
+
+// --------------------------------------------------------------------------
+// Wilson spin projectors in the DeGrand-Rossi basis (gamma_1..4 for x,y,z,t).
+// proj<MU, SIGN> returns the two independent spin components h0, h1 of
+// (1 + SIGN gamma_MU) psi; recon<MU, SIGN> rebuilds the full 4-spinor (as an
+// accumulation) from h0, h1 (already multiplied by a link).
+//   (1 - g1): h = (p0 - i p3, p1 - i p2), full = (h0, h1,  i h1,  i h0)
+//   (1 + g1): h = (p0 + i p3, p1 + i p2), full = (h0, h1, -i h1, -i h0)
+//   (1 - g2): h = (p0 + p3,   p1 - p2),   full = (h0, h1, -h1,  h0)
+//   (1 + g2): h = (p0 - p3,   p1 + p2),   full = (h0, h1,  h1, -h0)
+//   (1 - g3): h = (p0 - i p2, p1 + i p3), full = (h0, h1,  i h0, -i h1)
+//   (1 + g3): h = (p0 + i p2, p1 - i p3), full = (h0, h1, -i h0,  i h1)
+//   (1 - g4): h = (p0 - p2,   p1 - p3),   full = (h0, h1, -h0, -h1)
+//   (1 + g4): h = (p0 + p2,   p1 + p3),   full = (h0, h1,  h0,  h1)
+// --------------------------------------------------------------------------
+template <int MU, int SIGN, typename R>
+__device__ __forceinline__ void spin_proj(const cx<R> p[4][3], cx<R> h[2][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if (MU == 0) {
+            if (SIGN < 0) { h[0][c] = p[0][c] + times_mi(p[3][c]); h[1][c] = p[1][c] + times_mi(p[2][c]); }
+            else          { h[0][c] = p[0][c] + times_i(p[3][c]);  h[1][c] = p[1][c] + times_i(p[2][c]); }
+        } else if (MU == 1) {
+            if (SIGN < 0) { h[0][c] = p[0][c] + p[3][c]; h[1][c] = p[1][c] - p[2][c]; }
+            else          { h[0][c] = p[0][c] - p[3][c]; h[1][c] = p[1][c] + p[2][c]; }
+        } else if (MU == 2) {
+            if (SIGN < 0) { h[0][c] = p[0][c] + times_mi(p[2][c]); h[1][c] = p[1][c] + times_i(p[3][c]); }
+            else          { h[0][c] = p[0][c] + times_i(p[2][c]);  h[1][c] = p[1][c] + times_mi(p[3][c]); }
+        } else {
+            if (SIGN < 0) { h[0][c] = p[0][c] - p[2][c]; h[1][c] = p[1][c] - p[3][c]; }
+            else          { h[0][c] = p[0][c] + p[2][c]; h[1][c] = p[1][c] + p[3][c]; }
+        }
+    }
+}
+
+// acc += s * reconstruct(h), s = +/-1 boundary sign
+template <int MU, int SIGN, typename R>
+__device__ __forceinline__ void spin_recon_acc(cx<R> acc[4][3], const cx<R> h[2][3], R s) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        cx<R> a = s * h[0][c], b = s * h[1][c];
+        acc[0][c] = acc[0][c] + a;
+        acc[1][c] = acc[1][c] + b;
+        if (MU == 0) {
+            if (SIGN < 0) { acc[2][c] = acc[2][c] + times_i(b);  acc[3][c] = acc[3][c] + times_i(a); }
+            else          { acc[2][c] = acc[2][c] + times_mi(b); acc[3][c] = acc[3][c] + times_mi(a); }
+        } else if (MU == 1) {
+            if (SIGN < 0) { acc[2][c] = acc[2][c] - b; acc[3][c] = acc[3][c] + a; }
+            else          { acc[2][c] = acc[2][c] + b; acc[3][c] = acc[3][c] - a; }
+        } else if (MU == 2) {
+            if (SIGN < 0) { acc[2][c] = acc[2][c] + times_i(a);  acc[3][c] = acc[3][c] + times_mi(b); }
+            else          { acc[2][c] = acc[2][c] + times_mi(a); acc[3][c] = acc[3][c] + times_i(b); }
+        } else {
+            if (SIGN < 0) { acc[2][c] = acc[2][c] - a; acc[3][c] = acc[3][c] - b; }
+            else          { acc[2][c] = acc[2][c] + a; acc[3][c] = acc[3][c] + b; }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// storage precisions
+// --------------------------------------------------------------------------
+enum Prec { P64 = 0, P32 = 1, P16 = 2 };
+
+template <int P> struct Real { typedef float T; };
+template <> struct Real<P64> { typedef double T; };
+
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// spinor field view: base pointer of one parity field + norm array (FP16)
+struct SpinorPtr {
+    void* v;
+    float* norm;
+};
+
+template <int P, typename R> struct SpinorIO;
+
+template <typename R> struct SpinorIO<P64, R> {
+    static __device__ __forceinline__ void load(const SpinorPtr& f, int s, int Vh, cx<R> p[4][3]) {
+        const d2* b = (const d2*)f.v;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            d2 v = b[(size_t)k * Vh + s];
+            p[k / 3][k % 3] = {R(v.x), R(v.y)};
+        }
+    }
+    static __device__ __forceinline__ void store(const SpinorPtr& f, int s, int Vh, const cx<R> p[4][3]) {
+        d2* b = (d2*)f.v;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            d2 v = {double(p[k / 3][k % 3].re), double(p[k / 3][k % 3].im)};
+            b[(size_t)k * Vh + s] = v;
+        }
+    }
+};
+
+template <typename R> struct SpinorIO<P32, R> {
+    static __device__ __forceinline__ void load(const SpinorPtr& f, int s, int Vh, cx<R> p[4][3]) {
+        const f4* b = (const f4*)f.v;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            f4 v = b[(size_t)k * Vh + s];
+            p[(2 * k) / 3][(2 * k) % 3] = {R(v.x), R(v.y)};
+            p[(2 * k + 1) / 3][(2 * k + 1) % 3] = {R(v.z), R(v.w)};
+        }
+    }
+    static __device__ __forceinline__ void store(const SpinorPtr& f, int s, int Vh, const cx<R> p[4][3]) {
+        f4* b = (f4*)f.v;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const cx<R>& a = p[(2 * k) / 3][(2 * k) % 3];
+            const cx<R>& c = p[(2 * k + 1) / 3][(2 * k + 1) % 3];
+            f4 v = {float(a.re), float(a.im), float(c.re), float(c.im)};
+            b[(size_t)k * Vh + s] = v;
+        }
+    }
+};
+
+template <typename R> struct SpinorIO<P16, R> {
+    static __device__ __forceinline__ void load(const SpinorPtr& f, int s, int Vh, cx<R> p[4][3]) {
+        const h8* b = (const h8*)f.v;
+        float nrm = f.norm[s];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            h8 v = b[(size_t)k * Vh + s];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                int e = 4 * k + j;
+                p[e / 3][e % 3] = {R(float(v[2 * j]) * nrm), R(float(v[2 * j + 1]) * nrm)};
+            }
+        }
+    }
+    static __device__ __forceinline__ void store(const SpinorPtr& f, int s, int Vh, const cx<R> p[4][3]) {
+        h8* b = (h8*)f.v;
+        float m = 0.f;
+#pragma unroll
+        for (int e = 0; e < 12; e++) {
+            m = fmaxf(m, fabsf(float(p[e / 3][e % 3].re)));
+            m = fmaxf(m, fabsf(float(p[e / 3][e % 3].im)));
+        }
+        float inv = m > 0.f ? 1.0f / m : 0.f;
+        f.norm[s] = m;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            h8 v;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                int e = 4 * k + j;
+                v[2 * j] = (_Float16)(float(p[e / 3][e % 3].re) * inv);
+                v[2 * j + 1] = (_Float16)(float(p[e / 3][e % 3].im) * inv);
+            }
+            b[(size_t)k * Vh + s] = v;
+        }
+    }
+};
+
+// link field loads: base points at the whole gauge field; (mu, p, s) selects a link
+template <int P, int RECON, typename R> struct LinkIO;
+
+template <typename R> struct LinkIO<P64, 18, R> {
+    static __device__ __forceinline__ M3<R> load(const void* base, int mu, int p, int s, int Vh) {
+        const d2* b = (const d2*)base + (size_t)((mu * 2 + p) * 9) * Vh + s;
+        M3<R> u;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            d2 v = b[(size_t)k * Vh];
+            u.e[k / 3][k % 3] = {R(v.x), R(v.y)};
+        }
+        return u;
+    }
+};
+
+template <typename R> struct LinkIO<P32, 18, R> {
+    static __device__ __forceinline__ M3<R> load(const void* base, int mu, int p, int s, int Vh) {
+        const f2* b = (const f2*)base + (size_t)((mu * 2 + p) * 9) * Vh + s;
+        M3<R> u;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            f2 v = b[(size_t)k * Vh];
+            u.e[k / 3][k % 3] = {R(v.x), R(v.y)};
+        }
+        return u;
+    }
+};
+
+// third row of an SU(3) matrix from the first two: row2 = conj(row0 x row1)
+template <typename R> __device__ __forceinline__ void recon_row2(M3<R>& u) {
+    u.e[2][0] = conj(u.e[0][1] * u.e[1][2] - u.e[0][2] * u.e[1][1]);
+    u.e[2][1] = conj(u.e[0][2] * u.e[1][0] - u.e[0][0] * u.e[1][2]);
+    u.e[2][2] = conj(u.e[0][0] * u.e[1][1] - u.e[0][1] * u.e[1][0]);
+}
+
+template <typename R> struct LinkIO<P32, 12, R> {
+    static __device__ __forceinline__ M3<R> load(const void* base, int mu, int p, int s, int Vh) {
+        const f4* b = (const f4*)base + (size_t)((mu * 2 + p) * 3) * Vh + s;
+        M3<R> u;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            f4 v = b[(size_t)k * Vh];
+            int e0 = 2 * k, e1 = 2 * k + 1;
+            u.e[e0 / 3][e0 % 3] = {R(v.x), R(v.y)};
+            u.e[e1 / 3][e1 % 3] = {R(v.z), R(v.w)};
+        }
+        recon_row2(u);
+        return u;
+    }
+};
+
+template <typename R> struct LinkIO<P16, 12, R> {
+    static __device__ __forceinline__ M3<R> load(const void* base, int mu, int p, int s, int Vh) {
+        const h4* b = (const h4*)base + (size_t)((mu * 2 + p) * 3) * Vh + s;
+        M3<R> u;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            h4 v = b[(size_t)k * Vh];
+            int e0 = 2 * k, e1 = 2 * k + 1;
+            u.e[e0 / 3][e0 % 3] = {R(float(v.x)), R(float(v.y))};
+            u.e[e1 / 3][e1 % 3] = {R(float(v.z)), R(float(v.w))};
+        }
+        recon_row2(u);
+        return u;
+    }
+};
+
+// FP64 master gauge field access (double2 chunks)
+__device__ __forceinline__ M3<double> gauge_load(const d2* U, int mu, int p, int s, int Vh) {
+    return LinkIO<P64, 18, double>::load(U, mu, p, s, Vh);
+}
+
+__device__ __forceinline__ void gauge_store(d2* U, int mu, int p, int s, int Vh, const M3<double>& u) {
+    d2* b = U + (size_t)((mu * 2 + p) * 9) * Vh + s;
+#pragma unroll
+    for (int k = 0; k < 9; k++) b[(size_t)k * Vh] = d2{u.e[k / 3][k % 3].re, u.e[k / 3][k % 3].im};
+}
+
+__device__ __forceinline__ void mom_load(const double* P, int mu, int p, int s, int Vh, double x[8]) {
+    const double* b = P + (size_t)((mu * 2 + p) * 8) * Vh + s;
+#pragma unroll
+    for (int a = 0; a < 8; a++) x[a] = b[(size_t)a * Vh];
+}
+
+__device__ __forceinline__ void mom_store(double* P, int mu, int p, int s, int Vh, const double x[8]) {
+    double* b = P + (size_t)((mu * 2 + p) * 8) * Vh + s;
+#pragma unroll
+    for (int a = 0; a < 8; a++) b[(size_t)a * Vh] = x[a];
+}
+
+// --------------------------------------------------------------------------
+// deterministic block reductions (fixed shuffle tree, fixed wave order)
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// sum over the block of NV values per thread; result valid in every thread.
+// lds must hold NV * (blockDim.x / 64) doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum(double v[NV], double* lds) {
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; k++) v[k] = wave_sum(v[k]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; k++) lds[k * nw + wid] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        double s = 0;
+        for (int w = 0; w < nw; w++) s += lds[k * nw + w];
+        v[k] = s;
+    }
+}
+
+// sum of n partial values (written by an earlier kernel), computed the same
+// way in every block that asks: thread t takes t, t + bs, ... then block_sum.
+__device__ __forceinline__ double sum_partials(const double* part, int n, double* lds) {
+    double v[1] = {0.0};
+    for (int k = threadIdx.x; k < n; k += blockDim.x) v[0] += part[k];
+    block_sum<1>(v, lds);
+    return v[0];
+}
+
+}  // namespace fgi

@@ -1,0 +1,154 @@
+// Host-side internals of the force-gradient HMC library: the context that owns
+// scratch memory, the kernel launchers of each translation unit, and error
+// plumbing.  Nothing here crosses the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "fgi_device.h"
+
+namespace fgi {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+
+#define FGI_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            throw ::fgi::Error(-2, std::string(#call) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+#define FGI_LAUNCH_CHECK() FGI_HIP(hipGetLastError())
+
+Geom make_geom(const int dims[4]);
+
+// grow-only device buffer owned by the context
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void* get(size_t n);
+    void release();
+};
+
+// Device-resident reduction/iteration state of one CG solve.  Written by the
+// solver kernels, copied to pinned host memory when the host polls.
+struct CGState {
+    double rr[2];      // |r|^2 of the iteration vectors, slot k & 1 holds iteration k's
+    double pAp;        // <p, A p> of the current iteration
+    double rr_stop;    // inner stopping target
+    int stop_at;       // first iteration index that must not run (INT_MAX while running)
+    int iters;         // iterations completed
+    unsigned counter;  // arrival counter of the last-block reductions (0 between kernels)
+    int pad;
+};
+
+// field pointers of one gauge configuration in every storage the solver needs
+struct GaugeSet {
+    d2* u64;          // FP64 master
+    void* sloppy;     // FP32/18, FP32/12 or FP16/12 copy (nullptr in FP64 mode)
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // persistent trajectory / call scratch
+    DevBuf gauge, gauge_disp, sloppy, sloppy_disp, mom, force, force2, scratch_mom;
+    DevBuf eta, phi, X, Xo, Ye, Yo, tmp_e, tmp_o, cg_r, cg_p, cg_q;
+    DevBuf s_x, s_r, s_p, s_q, s_t, s_norms;
+    DevBuf h0, hf0, partial, scal, state;
+    DevBuf phi2, eta2, user_tmp;
+    double* host_scal = nullptr;   // pinned, 64 doubles
+    CGState* host_state = nullptr; // pinned
+    // profiling of the Dslash launches (events bracket each launch when on)
+    bool profile = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double dslash_ms = 0.0;
+    long dslash_launches = 0;
+    long dslash_sites = 0;     // output sites summed over profiled launches
+    int dslash_bytes_per_site = 0;
+    // solver tuning
+    int cg_batch = 8;          // iterations launched between host polls
+    int dslash_split = 0;      // 0 = automatic
+    double ru_delta = 0.1;     // reliable-update trigger |r| drop
+};
+
+// ---------------- gauge.hip ----------------
+void pack_gauge(Ctx&, const Geom&, const void* user, d2* internal);
+void unpack_gauge(Ctx&, const Geom&, const d2* internal, void* user);
+void pack_mom(Ctx&, const Geom&, const double* user, double* internal);
+void unpack_mom(Ctx&, const Geom&, const double* internal, double* user);
+void pack_even_spinor(Ctx&, const Geom&, const void* user, d2* internal);
+void unpack_even_spinor(Ctx&, const Geom&, const d2* internal, void* user);
+void make_sloppy(Ctx&, const Geom&, const d2* u64, void* sloppy, int prec, int recon);
+// per-site h = beta * sum_{mu<nu}(1 - ReTr U_P/3) [when U != null] + kinetic of P [when P != null]
+void ham_density(Ctx&, const Geom&, double beta, const d2* U, const double* P, double* h);
+// partial[b] = sum over block b of (h1 - h0) [or h1 when h0 == null]; returns nblocks
+int diff_partials(Ctx&, int n, const double* h1, const double* h0, double* partial);
+void final_sum(Ctx&, const double* partial, int n, double* out);
+// F_G into F: mode 0: F = c * F_G; 1: F += c * F_G
+void gauge_force(Ctx&, const Geom&, double beta, const d2* U, double* F, double c, int accumulate);
+// J = c * d/dt F_G(exp(t V) U) (+ J when accumulate)
+void gauge_force_tangent(Ctx&, const Geom&, double beta, const d2* U, const double* Vd, double* J,
+                         double c, int accumulate);
+// dst = exp(h X) src on every link; sloppy copy of dst written when sloppy != null
+void link_update(Ctx&, const Geom&, double h, const double* X, const d2* src, d2* dst, void* sloppy,
+                 int prec, int recon);
+// y += a x over the 4 * 2 * 8 * Vh momentum components
+void mom_axpy(Ctx&, const Geom&, double a, const double* x, double* y);
+void reunitarize(Ctx&, const Geom&, d2* U);
+// partial[b] = sum over block b of x[k] y[k], k < n; returns nblocks
+int dot_partials(Ctx&, long n, const double* x, const double* y, double* partial);
+// p[0..n) = 0 (a kernel, not a memset, so it can sit in a captured graph)
+void zero_doubles(Ctx&, double* p, size_t n);
+// exp of one su(3) element (test hook of the device exponential)
+void exp_su3_batch(Ctx&, int n, const double* p, double h, void* out);
+
+// ---------------- fermion.hip ----------------
+struct FermionOp {
+    const Geom* g;
+    double kappa;
+    const void* links;   // gauge storage for this operator
+    int prec, recon;     // link storage precision / reconstruction
+};
+// out_{1-p} = D_{(1-p) p} in_p  (hopping term between parities)
+void dslash(Ctx&, const FermionOp&, int out_parity, int prec_in, SpinorPtr in, int prec_out,
+            SpinorPtr out);
+// out_e = [g5] (in_e - kappa^2 D_eo t_o)  where t_o = D_oe in_e is computed too
+void mhat(Ctx&, const FermionOp&, int prec, SpinorPtr in_e, SpinorPtr tmp_o, SpinorPtr out_e,
+          int dagger);
+struct CGResult {
+    int iters;
+    int converged;
+    double rel_resid;
+    int reliable_updates;
+};
+// X = (Mhat^+ Mhat)^-1 phi from a zero start; FP64 op64 for the true residual,
+// sloppy op for the inner iterations (same op for FP64 mode)
+CGResult cg_solve(Ctx&, const FermionOp& op64, const FermionOp& ops, int sprec, const d2* phi, d2* X,
+                  double tol, int maxiter);
+// phi = Mhat^+ eta
+void pf_heatbath(Ctx&, const FermionOp& op64, const d2* eta, d2* phi);
+// F += c * F_F(X_e) (pseudofermion force given the solution X_e)
+void fermion_force(Ctx&, const FermionOp& op64, const d2* Xe, double* F, double c);
+// partials of Re phi^+ X - |eta|^2 (eta may be null) per even site; returns nblocks
+int pf_density_partials(Ctx&, const Geom&, const d2* phi, const d2* X, const d2* eta, double* partial);
+// for the Hasenbusch pair: out = Mhat(kappa2)^+ in etc. use mhat with another op
+void spinor_copy(Ctx&, const Geom&, const d2* src, d2* dst);
+// b = a with storage conversion (P64/P32/P16 -> P64/P32/P16)
+void convert_spinor(Ctx&, const Geom&, int prec_a, SpinorPtr a, int prec_b, SpinorPtr b);
+
+// profiling helpers for Dslash launches
+void prof_begin(Ctx&);
+void prof_end(Ctx&, int sites);
+void prof_collect(Ctx&);
+
+}  // namespace fgi

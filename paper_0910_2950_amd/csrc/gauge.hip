@@ -1,0 +1,435 @@
+// Gauge-side kernels: layout conversion, Hamiltonian densities, the Wilson
+// gauge (staple) force and its tangent (the force gradient along a field),
+// the exact su(3) link update and reunitarisation.  FP64 throughout.
+#include "fgi_internal.h"
+
+namespace fgi {
+
+static inline int nblocks(long n, int bs) { return (int)((n + bs - 1) / bs); }
+static const int BS = 256;
+
+// lexicographic index of checkerboard site (p, s)
+__device__ __forceinline__ int lex_index(const Geom& g, int p, int s) {
+    Coord c = cb_coords(g, p, s);
+    return c.c[0] + g.L[0] * (c.c[1] + g.L[1] * (c.c[2] + g.L[2] * c.c[3]));
+}
+
+// ---------------------------------------------------------------- layout ---
+__global__ void k_pack_gauge(Geom g, const d2* __restrict__ user, d2* __restrict__ U, int to_internal) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * g.V) return;
+    int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
+    int i = lex_index(g, p, s);
+    d2* in = U + (size_t)((mu * 2 + p) * 9) * g.Vh + s;
+    const size_t ub = ((size_t)mu * g.V + i) * 9;
+    if (to_internal) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) in[(size_t)k * g.Vh] = user[ub + k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 9; k++) ((d2*)user)[ub + k] = in[(size_t)k * g.Vh];
+    }
+}
+
+__global__ void k_pack_mom(Geom g, const double* __restrict__ user, double* __restrict__ P, int to_internal) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * g.V) return;
+    int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
+    int i = lex_index(g, p, s);
+    double* in = P + (size_t)((mu * 2 + p) * 8) * g.Vh + s;
+    const size_t ub = ((size_t)mu * g.V + i) * 8;
+    if (to_internal) {
+#pragma unroll
+        for (int a = 0; a < 8; a++) in[(size_t)a * g.Vh] = user[ub + a];
+    } else {
+#pragma unroll
+        for (int a = 0; a < 8; a++) ((double*)user)[ub + a] = in[(size_t)a * g.Vh];
+    }
+}
+
+// user even spinor: entry k (= checkerboard index of the k-th even site) holds [4][3] complex
+__global__ void k_pack_even(Geom g, const d2* __restrict__ user, d2* __restrict__ X, int to_internal) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.Vh) return;
+    if (to_internal) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) X[(size_t)k * g.Vh + s] = user[(size_t)s * 12 + k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; k++) ((d2*)user)[(size_t)s * 12 + k] = X[(size_t)k * g.Vh + s];
+    }
+}
+
+void pack_gauge(Ctx& c, const Geom& g, const void* user, d2* U) {
+    hipLaunchKernelGGL(k_pack_gauge, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, (const d2*)user, U, 1);
+    FGI_LAUNCH_CHECK();
+}
+void unpack_gauge(Ctx& c, const Geom& g, const d2* U, void* user) {
+    hipLaunchKernelGGL(k_pack_gauge, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, (const d2*)user, (d2*)U, 0);
+    FGI_LAUNCH_CHECK();
+}
+void pack_mom(Ctx& c, const Geom& g, const double* user, double* P) {
+    hipLaunchKernelGGL(k_pack_mom, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, user, P, 1);
+    FGI_LAUNCH_CHECK();
+}
+void unpack_mom(Ctx& c, const Geom& g, const double* P, double* user) {
+    hipLaunchKernelGGL(k_pack_mom, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, (const double*)user, (double*)P, 0);
+    FGI_LAUNCH_CHECK();
+}
+void pack_even_spinor(Ctx& c, const Geom& g, const void* user, d2* X) {
+    hipLaunchKernelGGL(k_pack_even, dim3(nblocks(g.Vh, BS)), dim3(BS), 0, c.stream, g, (const d2*)user, X, 1);
+    FGI_LAUNCH_CHECK();
+}
+void unpack_even_spinor(Ctx& c, const Geom& g, const d2* X, void* user) {
+    hipLaunchKernelGGL(k_pack_even, dim3(nblocks(g.Vh, BS)), dim3(BS), 0, c.stream, g, (const d2*)user, (d2*)X, 0);
+    FGI_LAUNCH_CHECK();
+}
+
+// sloppy copies of the FP64 master gauge field
+__global__ void k_make_sloppy(Geom g, const d2* __restrict__ U, void* __restrict__ out, int prec, int recon) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * g.V) return;
+    int s = t % g.Vh, r = t / g.Vh;  // r = mu * 2 + p
+    const d2* in = U + (size_t)(r * 9) * g.Vh + s;
+    d2 e[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) e[k] = in[(size_t)k * g.Vh];
+    if (prec == P32 && recon == 18) {
+        f2* o = (f2*)out + (size_t)(r * 9) * g.Vh + s;
+#pragma unroll
+        for (int k = 0; k < 9; k++) o[(size_t)k * g.Vh] = f2{(float)e[k].x, (float)e[k].y};
+    } else if (prec == P32) {
+        f4* o = (f4*)out + (size_t)(r * 3) * g.Vh + s;
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+            o[(size_t)k * g.Vh] = f4{(float)e[2 * k].x, (float)e[2 * k].y, (float)e[2 * k + 1].x, (float)e[2 * k + 1].y};
+    } else {
+        h4* o = (h4*)out + (size_t)(r * 3) * g.Vh + s;
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+            o[(size_t)k * g.Vh] = h4{(_Float16)e[2 * k].x, (_Float16)e[2 * k].y, (_Float16)e[2 * k + 1].x,
+                                     (_Float16)e[2 * k + 1].y};
+    }
+}
+
+void make_sloppy(Ctx& c, const Geom& g, const d2* U, void* sloppy, int prec, int recon) {
+    hipLaunchKernelGGL(k_make_sloppy, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, U, sloppy, prec, recon);
+    FGI_LAUNCH_CHECK();
+}
+
+// ----------------------------------------------------------- densities ---
+// h(x) = beta sum_{mu<nu} (1 - ReTr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+]/3)
+//        + 1/2 sum_mu |p_mu(x)|^2
+__global__ void k_ham_density(Geom g, double beta, const d2* __restrict__ U, const double* __restrict__ P,
+                              double* __restrict__ h) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.V) return;
+    int p = t / g.Vh, s = t % g.Vh;
+    Coord c = cb_coords(g, p, s);
+    double acc = 0.0;
+#pragma unroll 1
+    for (int mu = 0; mu < (U ? 4 : 0); mu++) {
+        M3<double> umu = gauge_load(U, mu, p, s, g.Vh);
+        int smu = cb_neighbour(g, c, mu, +1);
+#pragma unroll 1
+        for (int nu = mu + 1; nu < 4; nu++) {
+            int snu = cb_neighbour(g, c, nu, +1);
+            M3<double> a = m3_mul(umu, gauge_load(U, nu, 1 - p, smu, g.Vh));
+            M3<double> b = m3_mul(gauge_load(U, nu, p, s, g.Vh), gauge_load(U, mu, 1 - p, snu, g.Vh));
+            double tr = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) tr += a.e[i][j].re * b.e[i][j].re + a.e[i][j].im * b.e[i][j].im;
+            acc += 1.0 - tr / 3.0;
+        }
+    }
+    acc *= beta;
+    if (P) {
+        double kin = 0.0;
+        for (int mu = 0; mu < 4; mu++) {
+            double x[8];
+            mom_load(P, mu, p, s, g.Vh, x);
+#pragma unroll
+            for (int a = 0; a < 8; a++) kin += x[a] * x[a];
+        }
+        acc += 0.5 * kin;
+    }
+    h[t] = acc;
+}
+
+void ham_density(Ctx& c, const Geom& g, double beta, const d2* U, const double* P, double* h) {
+    hipLaunchKernelGGL(k_ham_density, dim3(nblocks(g.V, BS)), dim3(BS), 0, c.stream, g, beta, U, P, h);
+    FGI_LAUNCH_CHECK();
+}
+
+__global__ void k_diff_partials(int n, const double* __restrict__ h1, const double* __restrict__ h0,
+                                double* __restrict__ partial) {
+    __shared__ double lds[16];
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[1] = {0.0};
+    if (t < n) v[0] = h0 ? h1[t] - h0[t] : h1[t];
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
+int diff_partials(Ctx& c, int n, const double* h1, const double* h0, double* partial) {
+    int nb = nblocks(n, BS);
+    hipLaunchKernelGGL(k_diff_partials, dim3(nb), dim3(BS), 0, c.stream, n, h1, h0, partial);
+    FGI_LAUNCH_CHECK();
+    return nb;
+}
+
+__global__ void k_final_sum(const double* __restrict__ partial, int n, double* __restrict__ out) {
+    __shared__ double lds[16];
+    double s = sum_partials(partial, n, lds);
+    if (threadIdx.x == 0) *out = s;
+}
+
+void final_sum(Ctx& c, const double* partial, int n, double* out) {
+    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(BS), 0, c.stream, partial, n, out);
+    FGI_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------- force -----
+// Staple sum A_mu(x) = sum_{nu != mu} [U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+//                                     + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)];
+// the part of S_G holding U_mu(x) is -beta/3 ReTr(U_mu(x) A_mu(x)), so
+// F_mu(x) = -e S = -(beta/6) TA(U_mu(x) A_mu(x)).
+__global__ void __launch_bounds__(256) k_gauge_force(Geom g, double beta, const d2* __restrict__ U,
+                                                    double* __restrict__ F, double coef, int accumulate) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * g.V) return;
+    int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
+    Coord c = cb_coords(g, p, s);
+    int s_pmu = cb_neighbour(g, c, mu, +1);
+    Coord cpm = c;
+    cpm.c[mu] = (c.c[mu] + 1) % g.L[mu];
+    M3<double> A = m3_zero<double>();
+#pragma unroll 1
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == mu) continue;
+        int s_pnu = cb_neighbour(g, c, nu, +1);
+        int s_mnu = cb_neighbour(g, c, nu, -1);
+        int s_pmu_mnu = cb_neighbour(g, cpm, nu, -1);
+        // upper: U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+        M3<double> up = m3_mul_nd(m3_mul_nd(gauge_load(U, nu, 1 - p, s_pmu, g.Vh), gauge_load(U, mu, 1 - p, s_pnu, g.Vh)),
+                                  gauge_load(U, nu, p, s, g.Vh));
+        m3_acc(A, up);
+        // lower: (U_mu(x-nu) U_nu(x+mu-nu))^+ U_nu(x-nu)
+        M3<double> ed = m3_mul(gauge_load(U, mu, 1 - p, s_mnu, g.Vh), gauge_load(U, nu, p, s_pmu_mnu, g.Vh));
+        m3_acc(A, m3_mul_dn(ed, gauge_load(U, nu, 1 - p, s_mnu, g.Vh)));
+    }
+    M3<double> W = m3_mul(gauge_load(U, mu, p, s, g.Vh), A);
+    double x[8];
+    ta_components(W, x);
+    double* o = F + (size_t)(r * 8) * g.Vh + s;
+    double f = -beta / 6.0 * coef;
+#pragma unroll
+    for (int a = 0; a < 8; a++) {
+        double v = f * x[a];
+        o[(size_t)a * g.Vh] = accumulate ? o[(size_t)a * g.Vh] + v : v;
+    }
+}
+
+void gauge_force(Ctx& c, const Geom& g, double beta, const d2* U, double* F, double coef, int accumulate) {
+    hipLaunchKernelGGL(k_gauge_force, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, beta, U, F, coef, accumulate);
+    FGI_LAUNCH_CHECK();
+}
+
+// Tangent of the gauge force along a field of su(3) elements V:
+// d/dt F_G(exp(tV) U) at t = 0.  Each link moves as dU = V U, dU^+ = -U^+ V;
+// the product rule is applied factor by factor to U_mu(x) A_mu(x).
+__device__ __forceinline__ M3<double> valg(const double* Vd, int mu, int p, int s, int Vh) {
+    double x[8];
+    mom_load(Vd, mu, p, s, Vh, x);
+    return alg_matrix(x);
+}
+
+__global__ void __launch_bounds__(256) k_gauge_tangent(Geom g, double beta, const d2* __restrict__ U,
+                                                      const double* __restrict__ Vd, double* __restrict__ J,
+                                                      double coef, int accumulate) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * g.V) return;
+    int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
+    Coord c = cb_coords(g, p, s);
+    int s_pmu = cb_neighbour(g, c, mu, +1);
+    Coord cpm = c;
+    cpm.c[mu] = (c.c[mu] + 1) % g.L[mu];
+    M3<double> A = m3_zero<double>(), dA = m3_zero<double>();
+#pragma unroll 1
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == mu) continue;
+        int s_pnu = cb_neighbour(g, c, nu, +1);
+        int s_mnu = cb_neighbour(g, c, nu, -1);
+        int s_pmu_mnu = cb_neighbour(g, cpm, nu, -1);
+        {   // upper staple a b^+ c^+
+            M3<double> a = gauge_load(U, nu, 1 - p, s_pmu, g.Vh);
+            M3<double> b = gauge_load(U, mu, 1 - p, s_pnu, g.Vh);
+            M3<double> cc = gauge_load(U, nu, p, s, g.Vh);
+            M3<double> da = m3_mul(valg(Vd, nu, 1 - p, s_pmu, g.Vh), a);
+            M3<double> db = m3_mul(valg(Vd, mu, 1 - p, s_pnu, g.Vh), b);
+            M3<double> dc = m3_mul(valg(Vd, nu, p, s, g.Vh), cc);
+            M3<double> bc = m3_mul_nd(m3_dag(b), cc);  // b^+ c^+
+            m3_acc(A, m3_mul(a, bc));
+            m3_acc(dA, m3_mul(da, bc));
+            m3_acc(dA, m3_mul_nd(m3_mul_nd(a, db), cc));
+            m3_acc(dA, m3_mul_nd(m3_mul_nd(a, b), dc));
+        }
+        {   // lower staple d^+ e^+ f
+            M3<double> d = gauge_load(U, nu, p, s_pmu_mnu, g.Vh);
+            M3<double> e = gauge_load(U, mu, 1 - p, s_mnu, g.Vh);
+            M3<double> f = gauge_load(U, nu, 1 - p, s_mnu, g.Vh);
+            M3<double> dd = m3_mul(valg(Vd, nu, p, s_pmu_mnu, g.Vh), d);
+            M3<double> de = m3_mul(valg(Vd, mu, 1 - p, s_mnu, g.Vh), e);
+            M3<double> df = m3_mul(valg(Vd, nu, 1 - p, s_mnu, g.Vh), f);
+            M3<double> ed = m3_mul(e, d);  // (d^+ e^+)^+
+            m3_acc(A, m3_mul_dn(ed, f));
+            m3_acc(dA, m3_mul_dn(m3_mul(e, dd), f));
+            m3_acc(dA, m3_mul_dn(m3_mul(de, d), f));
+            m3_acc(dA, m3_mul_dn(ed, df));
+        }
+    }
+    M3<double> u = gauge_load(U, mu, p, s, g.Vh);
+    M3<double> du = m3_mul(valg(Vd, mu, p, s, g.Vh), u);
+    M3<double> dW = m3_mul(du, A);
+    m3_acc(dW, m3_mul(u, dA));
+    double x[8];
+    ta_components(dW, x);
+    double* o = J + (size_t)(r * 8) * g.Vh + s;
+    double f = -beta / 6.0 * coef;
+#pragma unroll
+    for (int a = 0; a < 8; a++) {
+        double v = f * x[a];
+        o[(size_t)a * g.Vh] = accumulate ? o[(size_t)a * g.Vh] + v : v;
+    }
+}
+
+void gauge_force_tangent(Ctx& c, const Geom& g, double beta, const d2* U, const double* Vd, double* J, double coef,
+                         int accumulate) {
+    hipLaunchKernelGGL(k_gauge_tangent, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, beta, U, Vd, J, coef,
+                       accumulate);
+    FGI_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------ updates ----
+__global__ void k_link_update(Geom g, double h, const double* __restrict__ X, const d2* __restrict__ src,
+                              d2* __restrict__ dst, void* __restrict__ sloppy, int prec, int recon) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * g.V) return;
+    int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
+    double x[8];
+    mom_load(X, mu, p, s, g.Vh, x);
+#pragma unroll
+    for (int a = 0; a < 8; a++) x[a] *= h;
+    M3<double> E = su3_exp(alg_matrix(x));
+    M3<double> u = m3_mul(E, gauge_load(src, mu, p, s, g.Vh));
+    gauge_store(dst, mu, p, s, g.Vh, u);
+    if (sloppy) {
+        if (prec == P32 && recon == 18) {
+            f2* o = (f2*)sloppy + (size_t)(r * 9) * g.Vh + s;
+#pragma unroll
+            for (int k = 0; k < 9; k++) o[(size_t)k * g.Vh] = f2{(float)u.e[k / 3][k % 3].re, (float)u.e[k / 3][k % 3].im};
+        } else if (prec == P32) {
+            f4* o = (f4*)sloppy + (size_t)(r * 3) * g.Vh + s;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                cx<double> a = u.e[(2 * k) / 3][(2 * k) % 3], b = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3];
+                o[(size_t)k * g.Vh] = f4{(float)a.re, (float)a.im, (float)b.re, (float)b.im};
+            }
+        } else {
+            h4* o = (h4*)sloppy + (size_t)(r * 3) * g.Vh + s;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                cx<double> a = u.e[(2 * k) / 3][(2 * k) % 3], b = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3];
+                o[(size_t)k * g.Vh] = h4{(_Float16)a.re, (_Float16)a.im, (_Float16)b.re, (_Float16)b.im};
+            }
+        }
+    }
+}
+
+void link_update(Ctx& c, const Geom& g, double h, const double* X, const d2* src, d2* dst, void* sloppy, int prec,
+                 int recon) {
+    hipLaunchKernelGGL(k_link_update, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, h, X, src, dst, sloppy,
+                       prec, recon);
+    FGI_LAUNCH_CHECK();
+}
+
+__global__ void k_axpy(long n, double a, const double* __restrict__ x, double* __restrict__ y) {
+    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] += a * x[t];
+}
+
+void mom_axpy(Ctx& c, const Geom& g, double a, const double* x, double* y) {
+    long n = 4L * 2 * 8 * g.Vh;
+    hipLaunchKernelGGL(k_axpy, dim3(nblocks(n, BS)), dim3(BS), 0, c.stream, n, a, x, y);
+    FGI_LAUNCH_CHECK();
+}
+
+__global__ void k_dot_partials(long n, const double* __restrict__ x, const double* __restrict__ y,
+                               double* __restrict__ partial) {
+    __shared__ double lds[16];
+    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[1] = {t < n ? x[t] * y[t] : 0.0};
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
+int dot_partials(Ctx& c, long n, const double* x, const double* y, double* partial) {
+    int nb = nblocks(n, BS);
+    hipLaunchKernelGGL(k_dot_partials, dim3(nb), dim3(BS), 0, c.stream, n, x, y, partial);
+    FGI_LAUNCH_CHECK();
+    return nb;
+}
+
+__global__ void k_zero_d(size_t n, double* __restrict__ p) {
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0.0;
+}
+
+void zero_doubles(Ctx& c, double* p, size_t n) {
+    hipLaunchKernelGGL(k_zero_d, dim3(nblocks((long)n, BS)), dim3(BS), 0, c.stream, n, p);
+    FGI_LAUNCH_CHECK();
+}
+
+// Gram-Schmidt on rows 0 and 1, row 2 = conj(row0 x row1)
+__global__ void k_reunitarize(Geom g, d2* __restrict__ U) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * g.V) return;
+    int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
+    M3<double> u = gauge_load(U, mu, p, s, g.Vh);
+    double n0 = 0;
+    for (int j = 0; j < 3; j++) n0 += u.e[0][j].re * u.e[0][j].re + u.e[0][j].im * u.e[0][j].im;
+    n0 = 1.0 / sqrt(n0);
+    for (int j = 0; j < 3; j++) u.e[0][j] = n0 * u.e[0][j];
+    cx<double> d = {0, 0};
+    for (int j = 0; j < 3; j++) d = d + cmul(u.e[0][j], u.e[1][j]);
+    for (int j = 0; j < 3; j++) u.e[1][j] = u.e[1][j] - d * u.e[0][j];
+    double n1 = 0;
+    for (int j = 0; j < 3; j++) n1 += u.e[1][j].re * u.e[1][j].re + u.e[1][j].im * u.e[1][j].im;
+    n1 = 1.0 / sqrt(n1);
+    for (int j = 0; j < 3; j++) u.e[1][j] = n1 * u.e[1][j];
+    recon_row2(u);
+    gauge_store(U, mu, p, s, g.Vh, u);
+}
+
+void reunitarize(Ctx& c, const Geom& g, d2* U) {
+    hipLaunchKernelGGL(k_reunitarize, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, U);
+    FGI_LAUNCH_CHECK();
+}
+
+__global__ void k_exp_batch(int n, const double* __restrict__ p, double h, d2* __restrict__ out) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double x[8];
+    for (int a = 0; a < 8; a++) x[a] = h * p[(size_t)t * 8 + a];
+    M3<double> E = su3_exp(alg_matrix(x));
+    for (int k = 0; k < 9; k++) out[(size_t)t * 9 + k] = d2{E.e[k / 3][k % 3].re, E.e[k / 3][k % 3].im};
+}
+
+void exp_su3_batch(Ctx& c, int n, const double* p, double h, void* out) {
+    hipLaunchKernelGGL(k_exp_batch, dim3(nblocks(n, BS)), dim3(BS), 0, c.stream, n, p, h, (d2*)out);
+    FGI_LAUNCH_CHECK();
+}
+
+}  // namespace fgi

@@ -1,0 +1,363 @@
+"""Python binding of libfgi.so (include/fgi.h): argument marshalling only.
+
+Every C entry point fgi_<name> is exposed as Context.<name> (or a module
+function for the context-free ones) with the same arguments, taking torch
+tensors that already live on the GPU.  All arithmetic happens in the HIP
+library; if libfgi.so is missing this module raises instead of falling back.
+
+Tensor layouts (C-contiguous, on the context's device):
+  U    complex128 (4, V, 3, 3)    links, site i = x + Lx(y + Ly(z + Lz t))
+  P    float64    (4, V, 8)       momentum / force components
+  even/odd fields complex128 (V/2, 4, 3)
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch  # noqa: F401  (loads the HIP runtime torch uses before libfgi)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfgi.so")
+
+FGI_OK, FGI_EINVAL, FGI_EHIP, FGI_ENOCONV, FGI_ENONFINITE = 0, -1, -2, -3, -4
+PREC = {"fp64": 0, "mp32": 1, "mp16": 2}
+INTEGRATORS = {"PQP": 0, "QPQ": 1, "PQPQP": 2, "CAMPOSTRINI": 3, "FG": 4}
+TERM_GAUGE, TERM_FERMION, TERM_HASEN = 1, 2, 4
+MAX_STAGES, MAX_LEVELS = 16, 4
+
+
+class FgiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("fgi error %d: %s" % (code, msg))
+        self.code = code
+
+
+class fgi_geom(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4)]
+
+
+class fgi_action(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("kappa", ctypes.c_double), ("kappa_hasen", ctypes.c_double),
+                ("cg_tol", ctypes.c_double), ("cg_maxiter", ctypes.c_int), ("prec", ctypes.c_int),
+                ("link_recon", ctypes.c_int), ("fg_exact", ctypes.c_int)]
+
+
+class fgi_stage(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("pad", ctypes.c_int), ("w", ctypes.c_double), ("xi", ctypes.c_double)]
+
+
+class fgi_level(ctypes.Structure):
+    _fields_ = [("nstages", ctypes.c_int), ("terms", ctypes.c_int), ("nsub", ctypes.c_int), ("pad", ctypes.c_int),
+                ("st", fgi_stage * MAX_STAGES)]
+
+
+class fgi_integrator(ctypes.Structure):
+    _fields_ = [("nlevels", ctypes.c_int), ("pad", ctypes.c_int), ("lev", fgi_level * MAX_LEVELS)]
+
+
+class fgi_stats(ctypes.Structure):
+    _fields_ = [("solves", ctypes.c_long), ("cg_iters", ctypes.c_long), ("cg_iters_max", ctypes.c_int),
+                ("reliable_updates", ctypes.c_int), ("max_rel_resid", ctypes.c_double),
+                ("force_evals", ctypes.c_long), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_vp, _d, _i = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
+_P = ctypes.POINTER
+
+SIGNATURES = {
+    "fgi_create": (_i, [_P(_vp), _i]),
+    "fgi_destroy": (_i, [_vp]),
+    "fgi_last_error": (ctypes.c_char_p, []),
+    "fgi_set_option": (_i, [_vp, ctypes.c_char_p, _d]),
+    "fgi_get_profile": (_i, [_vp, _P(_d), _P(ctypes.c_long), _P(ctypes.c_long)]),
+    "fgi_gauge_action": (_i, [_vp, _P(fgi_geom), _d, _vp, _P(_d), _vp]),
+    "fgi_kinetic": (_i, [_vp, _P(fgi_geom), _vp, _P(_d), _vp]),
+    "fgi_gauge_force": (_i, [_vp, _P(fgi_geom), _d, _vp, _vp, _vp]),
+    "fgi_force_gradient": (_i, [_vp, _P(fgi_geom), _d, _vp, _vp, _vp, _vp]),
+    "fgi_force": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _P(fgi_stats), _vp]),
+    "fgi_fermion_force": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _vp]),
+    "fgi_dslash": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _i, _i, _vp]),
+    "fgi_mhat": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _i, _vp]),
+    "fgi_cg_solve": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _P(fgi_stats), _vp]),
+    "fgi_pf_heatbath": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _vp]),
+    "fgi_pf_action": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _P(_d), _P(fgi_stats), _vp]),
+    "fgi_poisson_brackets": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _d, _P(_d), _P(_d),
+                                  _P(fgi_stats), _vp]),
+    "fgi_integrator_builtin": (_i, [_i, _d, _P(fgi_integrator)]),
+    "fgi_trajectory": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _P(fgi_integrator), _d, _i, _vp, _vp, _vp, _vp,
+                            _i, _P(_d), _P(fgi_stats), _vp]),
+    "fgi_link_update": (_i, [_vp, _P(fgi_geom), _d, _vp, _vp, _vp]),
+    "fgi_reunitarize": (_i, [_vp, _P(fgi_geom), _vp, _vp]),
+    "fgi_exp_su3": (_i, [_vp, _i, _vp, _d, _vp, _vp]),
+}
+
+
+def lib():
+    """Load libfgi.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FgiError(FGI_EINVAL, "libfgi.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, allow=()):
+    if rc != FGI_OK and rc not in allow:
+        raise FgiError(rc, lib().fgi_last_error().decode())
+    return rc
+
+
+def _geom(dims):
+    return fgi_geom((ctypes.c_int * 4)(*[int(d) for d in dims]))
+
+
+@dataclass
+class Action:
+    beta: float
+    kappa: float = 0.0
+    kappa_hasen: float = 0.0
+    cg_tol: float = 1e-10
+    cg_maxiter: int = 20000
+    prec: str = "fp64"
+    link_recon: int = 18
+    fg_exact: bool = False
+
+    def c(self):
+        return fgi_action(self.beta, self.kappa, self.kappa_hasen, self.cg_tol, int(self.cg_maxiter),
+                          PREC[self.prec], int(self.link_recon), int(bool(self.fg_exact)))
+
+
+def integrator_builtin(which, alpha=0.1932):
+    out = fgi_integrator()
+    _check(lib().fgi_integrator_builtin(INTEGRATORS[which] if isinstance(which, str) else int(which),
+                                        float(alpha), ctypes.byref(out)))
+    return out
+
+
+def integrator_from_levels(levels):
+    """levels: list of (stages, terms, nsub), stages a list of (kind, w, xi); level 0 outermost."""
+    I = fgi_integrator()
+    I.nlevels = len(levels)
+    for l, (stages, terms, nsub) in enumerate(levels):
+        L = I.lev[l]
+        L.nstages = len(stages)
+        L.terms = terms
+        L.nsub = nsub
+        for k, s in enumerate(stages):
+            L.st[k].kind = ord(s[0])
+            L.st[k].w = s[1]
+            L.st[k].xi = s[2] if len(s) > 2 else 0.0
+    return I
+
+
+def _ptr(t, dtype, shape=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise FgiError(FGI_EINVAL, "%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise FgiError(FGI_EINVAL, "%s must have dtype %s" % (name, dtype))
+    if not t.is_contiguous():
+        raise FgiError(FGI_EINVAL, "%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise FgiError(FGI_EINVAL, "%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _vol(dims):
+    v = 1
+    for d in dims:
+        v *= int(d)
+    return v
+
+
+class Context:
+    """One fgi_ctx on a HIP device (owns the library's scratch memory)."""
+
+    def __init__(self, device=0):
+        self.device = device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            _check(lib().fgi_create(ctypes.byref(h), int(device)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fgi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- options / profile
+    def set_option(self, name, value):
+        _check(lib().fgi_set_option(self.h, name.encode(), float(value)))
+
+    def get_profile(self):
+        ms, n, s = ctypes.c_double(), ctypes.c_long(), ctypes.c_long()
+        _check(lib().fgi_get_profile(self.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(s)))
+        return ms.value, n.value, s.value
+
+    # ---- shapes
+    @staticmethod
+    def _shapes(dims):
+        V = _vol(dims)
+        return (4, V, 3, 3), (4, V, 8), (V // 2, 4, 3)
+
+    # ---- Hamiltonian
+    def gauge_action(self, dims, beta, U):
+        su, _, _ = self._shapes(dims)
+        S = ctypes.c_double()
+        _check(lib().fgi_gauge_action(self.h, _geom(dims), beta, _ptr(U, torch.complex128, su, "U"),
+                                      ctypes.byref(S), _stream()))
+        return S.value
+
+    def kinetic(self, dims, P):
+        _, sp, _ = self._shapes(dims)
+        T = ctypes.c_double()
+        _check(lib().fgi_kinetic(self.h, _geom(dims), _ptr(P, torch.float64, sp, "P"), ctypes.byref(T), _stream()))
+        return T.value
+
+    # ---- forces
+    def gauge_force(self, dims, beta, U, F=None):
+        su, sp, _ = self._shapes(dims)
+        F = torch.empty(sp, dtype=torch.float64, device=U.device) if F is None else F
+        _check(lib().fgi_gauge_force(self.h, _geom(dims), beta, _ptr(U, torch.complex128, su, "U"),
+                                     _ptr(F, torch.float64, sp, "F"), _stream()))
+        return F
+
+    def force_gradient(self, dims, beta, U, V, J=None):
+        su, sp, _ = self._shapes(dims)
+        J = torch.empty(sp, dtype=torch.float64, device=U.device) if J is None else J
+        _check(lib().fgi_force_gradient(self.h, _geom(dims), beta, _ptr(U, torch.complex128, su, "U"),
+                                        _ptr(V, torch.float64, sp, "V"), _ptr(J, torch.float64, sp, "J"),
+                                        _stream()))
+        return J
+
+    def force(self, dims, act, U, phi=None, F=None, allow_noconv=False):
+        su, sp, se = self._shapes(dims)
+        F = torch.empty(sp, dtype=torch.float64, device=U.device) if F is None else F
+        st = fgi_stats()
+        _check(lib().fgi_force(self.h, _geom(dims), ctypes.byref(act.c()), _ptr(U, torch.complex128, su, "U"),
+                               _ptr(phi, torch.complex128, se, "phi"), _ptr(F, torch.float64, sp, "F"),
+                               ctypes.byref(st), _stream()), (FGI_ENOCONV,) if allow_noconv else ())
+        return F, st.as_dict()
+
+    def fermion_force(self, dims, act, U, X, F=None):
+        su, sp, se = self._shapes(dims)
+        F = torch.empty(sp, dtype=torch.float64, device=U.device) if F is None else F
+        _check(lib().fgi_fermion_force(self.h, _geom(dims), ctypes.byref(act.c()),
+                                       _ptr(U, torch.complex128, su, "U"), _ptr(X, torch.complex128, se, "X"),
+                                       _ptr(F, torch.float64, sp, "F"), _stream()))
+        return F
+
+    # ---- Wilson operator / solver
+    def dslash(self, dims, act, U, inp, out_parity, prec="fp64", out=None):
+        su, _, se = self._shapes(dims)
+        out = torch.empty(se, dtype=torch.complex128, device=U.device) if out is None else out
+        _check(lib().fgi_dslash(self.h, _geom(dims), ctypes.byref(act.c()), _ptr(U, torch.complex128, su, "U"),
+                                _ptr(inp, torch.complex128, se, "in"), _ptr(out, torch.complex128, se, "out"),
+                                int(out_parity), PREC[prec], _stream()))
+        return out
+
+    def mhat(self, dims, act, U, inp, dagger=False, out=None):
+        su, _, se = self._shapes(dims)
+        out = torch.empty(se, dtype=torch.complex128, device=U.device) if out is None else out
+        _check(lib().fgi_mhat(self.h, _geom(dims), ctypes.byref(act.c()), _ptr(U, torch.complex128, su, "U"),
+                              _ptr(inp, torch.complex128, se, "in"), _ptr(out, torch.complex128, se, "out"),
+                              int(bool(dagger)), _stream()))
+        return out
+
+    def cg_solve(self, dims, act, U, phi, X=None, allow_noconv=False):
+        su, _, se = self._shapes(dims)
+        X = torch.empty(se, dtype=torch.complex128, device=U.device) if X is None else X
+        st = fgi_stats()
+        rc = _check(lib().fgi_cg_solve(self.h, _geom(dims), ctypes.byref(act.c()),
+                                       _ptr(U, torch.complex128, su, "U"), _ptr(phi, torch.complex128, se, "phi"),
+                                       _ptr(X, torch.complex128, se, "X"), ctypes.byref(st), _stream()),
+                    (FGI_ENOCONV,) if allow_noconv else ())
+        d = st.as_dict()
+        d["status"] = rc
+        return X, d
+
+    def pf_heatbath(self, dims, act, U, eta, phi=None):
+        su, _, se = self._shapes(dims)
+        phi = torch.empty(se, dtype=torch.complex128, device=U.device) if phi is None else phi
+        _check(lib().fgi_pf_heatbath(self.h, _geom(dims), ctypes.byref(act.c()), _ptr(U, torch.complex128, su, "U"),
+                                     _ptr(eta, torch.complex128, se, "eta"), _ptr(phi, torch.complex128, se, "phi"),
+                                     _stream()))
+        return phi
+
+    def pf_action(self, dims, act, U, phi):
+        su, _, se = self._shapes(dims)
+        S = ctypes.c_double()
+        st = fgi_stats()
+        _check(lib().fgi_pf_action(self.h, _geom(dims), ctypes.byref(act.c()), _ptr(U, torch.complex128, su, "U"),
+                                   _ptr(phi, torch.complex128, se, "phi"), ctypes.byref(S), ctypes.byref(st),
+                                   _stream()))
+        return S.value, st.as_dict()
+
+    def poisson_brackets(self, dims, act, U, P, phi=None, h=1e-4):
+        su, sp, se = self._shapes(dims)
+        a, b = ctypes.c_double(), ctypes.c_double()
+        st = fgi_stats()
+        _check(lib().fgi_poisson_brackets(self.h, _geom(dims), ctypes.byref(act.c()),
+                                          _ptr(U, torch.complex128, su, "U"), _ptr(P, torch.float64, sp, "P"),
+                                          _ptr(phi, torch.complex128, se, "phi"), h, ctypes.byref(a),
+                                          ctypes.byref(b), ctypes.byref(st), _stream()))
+        return a.value, b.value
+
+    # ---- trajectory
+    def trajectory(self, dims, act, integ, tau, nsteps, U, P, eta1=None, eta2=None, pf_is_phi=False,
+                   allow_noconv=False):
+        """Updates U, P in place; returns (dH, stats)."""
+        su, sp, se = self._shapes(dims)
+        if isinstance(integ, str):
+            integ = integrator_builtin(integ)
+        dH = ctypes.c_double()
+        st = fgi_stats()
+        rc = _check(lib().fgi_trajectory(self.h, _geom(dims), ctypes.byref(act.c()), ctypes.byref(integ),
+                                         float(tau), int(nsteps), _ptr(U, torch.complex128, su, "U"),
+                                         _ptr(P, torch.float64, sp, "P"), _ptr(eta1, torch.complex128, se, "eta1"),
+                                         _ptr(eta2, torch.complex128, se, "eta2"), int(bool(pf_is_phi)),
+                                         ctypes.byref(dH), ctypes.byref(st), _stream()),
+                    (FGI_ENOCONV,) if allow_noconv else ())
+        d = st.as_dict()
+        d["status"] = rc
+        return dH.value, d
+
+    # ---- utilities
+    def link_update(self, dims, h, P, U):
+        su, sp, _ = self._shapes(dims)
+        _check(lib().fgi_link_update(self.h, _geom(dims), float(h), _ptr(P, torch.float64, sp, "P"),
+                                     _ptr(U, torch.complex128, su, "U"), _stream()))
+        return U
+
+    def reunitarize(self, dims, U):
+        su, _, _ = self._shapes(dims)
+        _check(lib().fgi_reunitarize(self.h, _geom(dims), _ptr(U, torch.complex128, su, "U"), _stream()))
+        return U
+
+    def exp_su3(self, p, h=1.0):
+        n = p.shape[0]
+        out = torch.empty((n, 3, 3), dtype=torch.complex128, device=p.device)
+        _check(lib().fgi_exp_su3(self.h, int(n), _ptr(p, torch.float64, (n, 8), "p"), float(h),
+                                 _ptr(out, torch.complex128, (n, 3, 3), "out"), _stream()))
+        return out

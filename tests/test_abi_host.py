@@ -1,0 +1,86 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point include/fgi.h declares, validates arguments before touching
+a device, and its built-in Table 1 stage tables agree with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_0910_2950_amd import fgi
+from oracle.oracle import table
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "fgi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fgi_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    assert "fgi_trajectory" in syms and "fgi_force" in syms and len(syms) >= 20
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fgi.lib()
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+    # the binding declares a signature for each of them
+    assert set(declared_symbols()) == set(fgi.SIGNATURES), set(declared_symbols()) ^ set(fgi.SIGNATURES)
+
+
+def test_struct_layouts_match_c_sizes():
+    # sizes fixed by include/fgi.h (LP64): stage 24, level 16 + 16*24, integrator 8 + 4*level
+    assert ctypes.sizeof(fgi.fgi_stage) == 24
+    assert ctypes.sizeof(fgi.fgi_level) == 16 + 16 * 24
+    assert ctypes.sizeof(fgi.fgi_integrator) == 8 + 4 * ctypes.sizeof(fgi.fgi_level)
+    assert ctypes.sizeof(fgi.fgi_action) == 4 * 8 + 4 * 4
+
+
+@pytest.mark.parametrize("name", ["PQP", "QPQ", "PQPQP", "CAMPOSTRINI", "FG"])
+def test_builtin_tables_match_oracle(name):
+    I = fgi.integrator_builtin(name, 0.1932)
+    assert I.nlevels == 1
+    L = I.lev[0]
+    got = [(chr(L.st[k].kind), L.st[k].w, L.st[k].xi) for k in range(L.nstages)]
+    ref = table(name, 0.1932)
+    assert len(got) == len(ref)
+    for (k1, w1, x1), (k2, w2, x2) in zip(got, ref):
+        assert k1 == k2 and abs(w1 - w2) < 1e-15 and abs(x1 - x2) < 1e-15
+
+
+def test_campostrini_weights_sum_to_one():
+    L = fgi.integrator_builtin("CAMPOSTRINI").lev[0]
+    q = sum(L.st[k].w for k in range(L.nstages) if chr(L.st[k].kind) == "Q")
+    p = sum(L.st[k].w for k in range(L.nstages) if chr(L.st[k].kind) == "P")
+    assert abs(q - 1) < 1e-15 and abs(p - 1) < 1e-15
+
+
+def test_builtin_rejects_bad_arguments():
+    with pytest.raises(fgi.FgiError) as e:
+        fgi.integrator_builtin(17)
+    assert e.value.code == fgi.FGI_EINVAL
+    with pytest.raises(fgi.FgiError):
+        fgi.integrator_builtin("PQPQP", 0.7)
+
+
+def test_null_context_is_rejected_without_device_work():
+    lib = fgi.lib()
+    S = ctypes.c_double()
+    rc = lib.fgi_gauge_action(None, fgi._geom((4, 4, 4, 4)), 6.0, None, ctypes.byref(S), None)
+    assert rc == fgi.FGI_EINVAL
+    assert b"context" in lib.fgi_last_error()
+
+
+def test_create_without_device_reports_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    rc = fgi.lib().fgi_create(ctypes.byref(h), 0)
+    assert rc in (fgi.FGI_EHIP, fgi.FGI_EINVAL)
+    assert fgi.lib().fgi_last_error() != b""
