@@ -1,0 +1,343 @@
+#!/usr/bin/env python3
+"""Benchmark of the force-gradient HMC hot path on one MI355X.
+
+Workload: Nf=2 Wilson fermions + Wilson gauge action on a 16^3 x 32 lattice,
+beta = 5.6, kappa = 0.1575, even-odd preconditioned; links thermalised from a
+seeded hot start by 20 FP64 HMC trajectories (Omelyan PQPQP, alpha = 0.1932,
+Metropolis off for the first half); every measured trajectory starts from
+that field with fresh seeded Gaussian momenta and pseudofermion noise.
+
+One step = one trajectory (tau = 1) of the mixed-precision force-gradient
+integrator (Table 1, last row, displacement form) at the step count n_FG at
+which <dH^2> reaches the 80 % acceptance level; the FP64 leapfrog (PQP) leg is
+timed the same way at its own matched step count and reported beside it.
+All inputs (links, momenta, noise) are resident in HBM before timing starts.
+
+Prints one JSON line (see the keys below).  --calibrate runs the step-size
+sweep that fixes the matched step counts instead.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "s/trajectory at fixed <δH²> (FG vs leapfrog), 16^3x32 Nf=2; Dslash HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+# target <dH^2> for 80 % acceptance: <P_acc> = erfc(sqrt(<dH>)/2), <dH^2> ~ 2 <dH>
+DH2_TARGET = 0.257
+# matched step counts from the calibration sweep (bench.py --calibrate)
+N_FG_DEFAULT = 12
+N_LF_DEFAULT = 103
+# compulsory bytes per output site of one bare Dslash (8 links + input + output spinor)
+DSLASH_BYTES = {("mp16", 12): 8 * 24 + 2 * (48 + 4), ("mp32", 12): 8 * 48 + 2 * 96,
+                ("mp32", 18): 8 * 72 + 2 * 96, ("fp64", 18): 8 * 144 + 2 * 192}
+PREC_ID = {"fp64": 0, "mp32": 1, "mp16": 2}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6, help="timed FG trajectories")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dims", default="16,16,16,32")
+    ap.add_argument("--beta", type=float, default=5.6)
+    ap.add_argument("--kappa", type=float, default=0.1575)
+    ap.add_argument("--therm", type=int, default=20, help="FP64 HMC trajectories from the hot start")
+    ap.add_argument("--therm-tau", type=float, default=6.0, help="trajectory length of the thermalisation runs")
+    ap.add_argument("--therm-steps", type=int, default=72)
+    ap.add_argument("--n-fg", type=int, default=N_FG_DEFAULT)
+    ap.add_argument("--n-lf", type=int, default=N_LF_DEFAULT)
+    ap.add_argument("--lf-steps", type=int, default=3, help="timed FP64 leapfrog trajectories (0: skip)")
+    ap.add_argument("--prec", default="mp16", choices=["fp64", "mp32", "mp16"])
+    ap.add_argument("--recon", type=int, default=12)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--cg-batch", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=12, help="oracle CG iterations timed for the CPU baseline")
+    ap.add_argument("--calibrate", action="store_true", help="step-size sweep for the matched step counts")
+    ap.add_argument("--cal-traj", type=int, default=6)
+    ap.add_argument("--seed", type=int, default=0x09102950 + 2)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also run one device copy of MIB MiB (a known-size kernel that calibrates "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    return ap.parse_args()
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for f in ("fermion.hip", "fgi_device.h"):
+        with open(os.path.join(ROOT, "paper_0910_2950_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_key):
+    """HBM bytes per launch of the profiled Dslash from the committed rocprofv3
+    counter summary, or None when it is absent or the kernel source changed."""
+    path = os.path.join(ROOT, "profiles", "dslash_hbm_traffic_16x16x16x32.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != source_digest() or kv.get("kernel_key") != kernel_key:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+class Runner:
+    def __init__(self, args):
+        import torch
+
+        from paper_0910_2950_amd import fgi, synth
+        self.torch, self.fgi, self.synth = torch, fgi, synth
+        self.args = args
+        self.dims = tuple(int(x) for x in args.dims.split(","))
+        self.dev = torch.device("cuda:0")
+        self.ctx = fgi.Context(0)
+        self.ctx.set_option("cg_batch", args.cg_batch)
+
+    def action(self, prec, recon=18):
+        return self.fgi.Action(beta=self.args.beta, kappa=self.args.kappa, cg_tol=self.args.tol,
+                               cg_maxiter=50000, prec=prec, link_recon=recon)
+
+    def to_dev(self, a):
+        return self.torch.from_numpy(np.ascontiguousarray(a)).to(self.dev)
+
+    def thermalise(self):
+        a = self.args
+        synth = self.synth
+        U0, _, _, _ = synth.hot_start(self.dims, a.seed, fermions=False)
+        U = self.to_dev(U0)
+        act = self.action("fp64")
+        integ = self.fgi.integrator_builtin("PQPQP", 0.1932)
+        u = synth.rng(a.seed + 999).random(max(a.therm, 1))
+        plaq = 1.0 - self.ctx.gauge_action(self.dims, 1.0, U) / (6.0 * np.prod(self.dims))
+        for k in range(a.therm):
+            P, eta = synth.refresh(self.dims, a.seed + 1000 * (k + 1))
+            Ut = U.clone()
+            dH, st = self.ctx.trajectory(self.dims, act, integ, a.therm_tau, a.therm_steps, Ut, self.to_dev(P),
+                                         self.to_dev(eta))
+            acc = (k < a.therm // 2) or (u[k] < math.exp(-dH) if dH > -700 else True)
+            if acc:
+                U = Ut
+            self.ctx.reunitarize(self.dims, U)
+            plaq = 1.0 - self.ctx.gauge_action(self.dims, 1.0, U) / (6.0 * np.prod(self.dims))
+            log("therm %2d dH=%+.4e acc=%d plaq=%.5f cg_iters=%d solves=%d %.2fs" %
+                (k, dH, acc, plaq, st["cg_iters"], st["solves"], st["seconds"]))
+        return U, plaq
+
+    def fresh_inputs(self, n, base):
+        out = []
+        for k in range(n):
+            P, eta = self.synth.refresh(self.dims, base + k)
+            out.append((self.to_dev(P), self.to_dev(eta)))
+        return out
+
+    def run_leg(self, U_therm, act, name, nsteps, inputs, profile=False):
+        """Trajectories from U_therm with the given (P, eta) sets; returns per-trajectory records."""
+        torch = self.torch
+        integ = self.fgi.integrator_builtin(name, 0.1932)
+        U = torch.empty_like(U_therm)
+        P = torch.empty_like(inputs[0][0])
+        if profile:
+            self.ctx.set_option("profile_prec", PREC_ID[act.prec] if act.prec != "mp32" else 1)
+            self.ctx.set_option("profile_reset", 1)
+            self.ctx.set_option("profile", 1)
+        recs = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for (P0, eta) in inputs:
+            U.copy_(U_therm)
+            P.copy_(P0)
+            dH, st = self.ctx.trajectory(self.dims, act, integ, 1.0, nsteps, U, P, eta)
+            recs.append(dict(dH=dH, **st))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = None
+        if profile:
+            self.ctx.set_option("profile", 0)
+            prof = self.ctx.get_profile()
+        return recs, t1 - t0, prof
+
+
+def summarise(recs):
+    dh = np.array([r["dH"] for r in recs])
+    return dict(mean_dH=float(dh.mean()), mean_dH2=float((dh ** 2).mean()),
+                acceptance=float(np.mean(np.minimum(1.0, np.exp(-dh)))),
+                exp_minus_dH=float(np.mean(np.exp(-dh))),
+                solves_per_traj=float(np.mean([r["solves"] for r in recs])),
+                cg_iters_per_traj=float(np.mean([r["cg_iters"] for r in recs])),
+                cg_iters_max=int(max(r["cg_iters_max"] for r in recs)),
+                max_rel_resid=float(max(r["max_rel_resid"] for r in recs)))
+
+
+def cpu_baseline(args, dims, iters_per_traj, force_evals_per_traj, links_updates_per_traj):
+    """Oracle as it stands, on a bounded sample: time oracle CG iterations, one
+    gauge force, one fermion force and one link update at the full size on a
+    synthetic hot-start field; scale by the trajectory's own counts."""
+    from oracle import oracle as orc
+    from paper_0910_2950_amd import synth
+    U, _, eta, _ = synth.hot_start(dims, args.seed + 77, fermions=True)
+    P = synth.gaussian_momenta(synth.rng(args.seed + 78), dims)
+    orc.lib()
+    t = time.perf_counter()
+    phi = orc.pf_heatbath(dims, args.kappa, U, eta)
+    t_heat = time.perf_counter() - t
+    t = time.perf_counter()
+    orc.cg(dims, args.kappa, U, phi, tol=1e-30, maxiter=args.cpu_iters)
+    t_it = (time.perf_counter() - t) / args.cpu_iters
+    t = time.perf_counter()
+    orc.gauge_force(dims, args.beta, U)
+    t_gf = time.perf_counter() - t
+    t = time.perf_counter()
+    orc.fermion_force(dims, args.kappa, U, phi)
+    t_ff = time.perf_counter() - t
+    t = time.perf_counter()
+    orc.link_update(dims, 0.1, P, U)
+    t_lu = time.perf_counter() - t
+    est = iters_per_traj * t_it + force_evals_per_traj * (t_gf + t_ff) + links_updates_per_traj * t_lu + t_heat
+    sample = ("oracle at %s: %d CG iterations (%.3f s each), 1 gauge force (%.2f s), 1 fermion force (%.2f s), "
+              "1 link update (%.2f s), 1 heatbath (%.2f s); scaled to one FG trajectory with the GPU run's "
+              "counts (%.0f CG iterations, %.0f force evaluations, %d link updates)"
+              % ("x".join(map(str, dims)), args.cpu_iters, t_it, t_gf, t_ff, t_lu, t_heat, iters_per_traj,
+                 force_evals_per_traj, links_updates_per_traj))
+    return dict(value=est, unit="s/trajectory", cores=orc.threads(), kind="oracle", sample=sample)
+
+
+def calibrate(args):
+    R = Runner(args)
+    U, plaq = R.thermalise()
+    legs = [("FG", args.prec, args.recon, [10, 12, 14, 16, 20]), ("FG", "fp64", 18, [12, 16]),
+            ("PQP", "fp64", 18, [64, 96, 128]), ("PQPQP", "fp64", 18, [24, 32, 40])]
+    out = {}
+    for name, prec, recon, ns in legs:
+        act = R.action(prec, recon)
+        pts = []
+        for n in ns:
+            inputs = R.fresh_inputs(args.cal_traj, args.seed + 500000 + 1000 * n)
+            recs, sec, _ = R.run_leg(U, act, name, n, inputs)
+            s = summarise(recs)
+            s.update(n=n, s_per_traj=sec / len(recs))
+            pts.append(s)
+            log("cal %-6s %s n=%2d <dH^2>=%.4e acc=%.3f s/traj=%.3f solves=%.0f iters=%.0f" %
+                (name, prec, n, s["mean_dH2"], s["acceptance"], s["s_per_traj"], s["solves_per_traj"],
+                 s["cg_iters_per_traj"]))
+        # fit log <dH^2> = c + q log dt over the points in the asymptotic regime
+        # (<dH^2> < 10); n* = the smallest measured n whose <dH^2> meets the target
+        fit_pts = [p for p in pts if p["mean_dH2"] < 10.0]
+        q = c = n_fit = None
+        if len(fit_pts) >= 2:
+            x = np.log(1.0 / np.array([p["n"] for p in fit_pts]))
+            y = np.log(np.array([max(p["mean_dH2"], 1e-30) for p in fit_pts]))
+            q, c = np.polyfit(x, y, 1)
+            n_fit = float(math.exp((c - math.log(DH2_TARGET)) / q))
+        ok = [p["n"] for p in pts if p["mean_dH2"] <= DH2_TARGET]
+        n_star = min(ok) if ok else None
+        out[name + "-" + prec] = dict(points=pts, slope=q, n_fit=n_fit, n_star=n_star)
+        log("fit %s-%s: <dH^2> ~ dt^%s  n_fit=%s n*=%s" % (name, prec, q, n_fit, n_star))
+    print(json.dumps(dict(calibration=out, plaquette=plaq, dims=args.dims, target_dH2=DH2_TARGET)))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (--gpus %d requested)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate:
+        calibrate(args)
+        return
+    R = Runner(args)
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        x = R.torch.ones(n, dtype=R.torch.float32, device=R.dev)
+        y = R.torch.empty_like(x)
+        y.copy_(x)
+        R.torch.cuda.synchronize()
+        log("copy probe: %d bytes read, %d bytes written" % (4 * n, 4 * n))
+        del x, y
+    t_setup = time.perf_counter()
+    U, plaq = R.thermalise()
+    act_fg = R.action(args.prec, args.recon)
+    inputs = R.fresh_inputs(args.warmup + args.steps, args.seed + 100000)
+    log("setup (thermalisation + inputs) %.1fs" % (time.perf_counter() - t_setup))
+
+    # warmup (untimed)
+    if args.warmup:
+        R.run_leg(U, act_fg, "FG", args.n_fg, inputs[:args.warmup])
+    # timed FG leg with live Dslash event timing
+    recs, sec, prof = R.run_leg(U, act_fg, "FG", args.n_fg, inputs[args.warmup:], profile=True)
+    fg = summarise(recs)
+    s_per_traj = sec / args.steps
+    log("FG-%s n=%d: %.4f s/traj  <dH^2>=%.4e acc=%.3f solves=%.1f iters=%.0f" %
+        (args.prec, args.n_fg, s_per_traj, fg["mean_dH2"], fg["acceptance"], fg["solves_per_traj"],
+         fg["cg_iters_per_traj"]))
+
+    # FP64 leapfrog leg at its matched step count
+    lf = None
+    if args.lf_steps > 0:
+        lf_inputs = R.fresh_inputs(args.lf_steps, args.seed + 200000)
+        recs_lf, sec_lf, _ = R.run_leg(U, R.action("fp64"), "PQP", args.n_lf, lf_inputs)
+        lf = summarise(recs_lf)
+        lf.update(n=args.n_lf, s_per_traj=sec_lf / args.lf_steps, trajectories=args.lf_steps)
+        log("LF-fp64 n=%d: %.4f s/traj  <dH^2>=%.4e acc=%.3f iters=%.0f" %
+            (args.n_lf, lf["s_per_traj"], lf["mean_dH2"], lf["acceptance"], lf["cg_iters_per_traj"]))
+
+    # roofline of the dominant kernel: the bare sloppy Dslash hop inside CG
+    ms, launches, sites = prof
+    V = int(np.prod(R.dims))
+    bps = DSLASH_BYTES[(args.prec, 12 if args.prec == "mp16" else args.recon)]
+    key = "%s/%d" % (args.prec, 12 if args.prec == "mp16" else args.recon)
+    roof = None
+    if launches:
+        avg_s = ms / 1e3 / launches
+        bytes_per_launch = sites / launches * bps
+        achieved = bytes_per_launch / avg_s / 1e9
+        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=read_traffic(key),
+                    kernel="bare even-odd Dslash hop (%s storage), %d output sites per launch" % (key, V // 2),
+                    algorithmic_bytes_per_launch=bytes_per_launch, avg_launch_us=round(avg_s * 1e6, 3),
+                    launches_timed=launches)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        iters_fp64 = (lf["cg_iters_per_traj"] / lf["solves_per_traj"] * fg["solves_per_traj"]) if lf else \
+            fg["cg_iters_per_traj"]
+        cpu = cpu_baseline(args, R.dims, iters_fp64, fg["solves_per_traj"], 2 * args.n_fg + args.n_fg)
+        log("cpu baseline %.1f s/traj on %d threads" % (cpu["value"], cpu["cores"]))
+
+    out = dict(metric=METRIC, value=round(s_per_traj, 5), unit="s/trajectory", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(s_per_traj * 1e3, 3), higher_is_better=False,
+               scaling="weak", vs_baseline=None, dtype="f32 arithmetic, f16 storage, f64 reliable updates/"
+               "Hamiltonian" if args.prec == "mp16" else args.prec, data="synthetic",
+               config=dict(workload="Nf=2 Wilson %s beta=%.2f kappa=%.4f, thermalised by %d FP64 HMC "
+                                    "trajectories from a seeded hot start; FG (%s, displacement form) at n=%d, "
+                                    "tau=1, CG tol %.0e" % ("x".join(map(str, R.dims)), args.beta, args.kappa,
+                                                            args.therm, args.prec, args.n_fg, args.tol),
+                           lattice=list(R.dims), integrator="FG", n_steps=args.n_fg, plaquette=round(plaq, 6)),
+               fg=fg, lf_fp64=lf,
+               speedup_vs_lf_fp64=(round(lf["s_per_traj"] / s_per_traj, 3) if lf else None),
+               roofline=roof, cpu_baseline=cpu)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -140,7 +140,8 @@ int fgi_destroy(fgi_ctx* ctx);
 const char* fgi_last_error(void);
 /* Tuning/diagnostic options: "cg_batch" (CG iterations between host polls),
  * "ru_delta" (reliable-update residual drop), "profile" (1: time every bare
- * Dslash launch with HIP events), "profile_reset". */
+ * Dslash launch with HIP events), "profile_prec" (time only launches whose
+ * input spinor precision is 0 FP64 / 1 FP32 / 2 FP16; -1 all), "profile_reset". */
 int fgi_set_option(fgi_ctx* ctx, const char* name, double value);
 /* Accumulated Dslash profile since the last reset: total kernel ms, number of
  * timed launches and output sites summed over them. */

@@ -38,11 +38,15 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 typedef double complex cplx;
+
+/* number of OpenMP threads the oracle's parallel loops use */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ */
 /* lattice geometry                                                    */

@@ -51,6 +51,8 @@ _i = ctypes.c_int
 
 
 def _declare(L):
+    L.oracle_threads.argtypes = []
+    L.oracle_threads.restype = _i
     L.oracle_gauge_action.argtypes = [_ip, _d, _vp]
     L.oracle_gauge_action.restype = _d
     L.oracle_plaquette.argtypes = [_ip, _vp]
@@ -90,6 +92,10 @@ def _c(a, dtype):
 
 def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def threads():
+    return lib().oracle_threads()
 
 
 def volume(dims):

@@ -246,6 +246,9 @@ int fgi_set_option(fgi_ctx* ctx, const char* name, double value) {
             c.ru_delta = value;
         } else if (n == "profile") {
             c.profile = value != 0;
+        } else if (n == "profile_prec") {
+            if (value < -1 || value > 2) throw Error(FGI_EINVAL, "profile_prec must be -1, 0, 1 or 2");
+            c.profile_prec = (int)value;
         } else if (n == "profile_reset") {
             c.dslash_ms = 0;
             c.dslash_launches = 0;

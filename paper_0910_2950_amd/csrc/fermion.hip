@@ -343,7 +343,7 @@ static SpinorPtr sp(const void* v, float* norm = nullptr) { return SpinorPtr{(vo
 template <int MODE, int PIN, int PC, int POUT, int PX, int G5IN>
 static void launch_dslash(Ctx& c, const FermionOp& op, DArgs& a) {
     int nb = nblk(a.g.Vh, DBS);
-    bool prof = c.profile && (MODE == M_HOP);
+    bool prof = c.profile && (MODE == M_HOP) && (c.profile_prec < 0 || c.profile_prec == PIN);
     if (prof) prof_begin(c);
     if constexpr (PIN == P64) {
         if (op.prec != P64) throw Error(-1, "FP64 spinors need FP64 links");

@@ -69,6 +69,7 @@ struct Ctx {
     CGState* host_state = nullptr; // pinned
     // profiling of the Dslash launches (events bracket each launch when on)
     bool profile = false;
+    int profile_prec = -1;     // time only bare Dslash launches with this input precision (-1: all)
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     double dslash_ms = 0.0;
