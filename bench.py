@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--recon", type=int, default=12)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--cg-batch", type=int, default=16)
+    ap.add_argument("--graphs", type=int, default=1, help="replay CG batches as HIP graphs (0: eager launches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle CG iterations timed for the CPU baseline")
     ap.add_argument("--calibrate", action="store_true", help="step-size sweep for the matched step counts")
@@ -113,6 +114,7 @@ class Runner:
         self.dev = torch.device("cuda:0")
         self.ctx = fgi.Context(0)
         self.ctx.set_option("cg_batch", args.cg_batch)
+        self.ctx.set_option("graphs", args.graphs)
 
     def action(self, prec, recon=18):
         return self.fgi.Action(beta=self.args.beta, kappa=self.args.kappa, cg_tol=self.args.tol,
@@ -313,7 +315,8 @@ def main():
         achieved = bytes_per_launch / avg_s / 1e9
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=read_traffic(key),
-                    kernel="bare even-odd Dslash hop (%s storage), %d output sites per launch" % (key, V // 2),
+                    kernel="bare even-odd Dslash hop t = D_oe g5 q of the CG (%s storage), %d output sites "
+                           "per launch; HIP events around 16 back-to-back launches after every solve" % (key, V // 2),
                     algorithmic_bytes_per_launch=bytes_per_launch, avg_launch_us=round(avg_s * 1e6, 3),
                     launches_timed=launches)
 

@@ -208,6 +208,7 @@ int fgi_create(fgi_ctx** out, int device) {
         c->c.device = device;
         FGI_HIP(hipHostMalloc((void**)&c->c.host_scal, 64 * sizeof(double), hipHostMallocDefault));
         FGI_HIP(hipHostMalloc((void**)&c->c.host_state, sizeof(CGState), hipHostMallocDefault));
+        FGI_HIP(hipHostMalloc((void**)&c->c.host_aux, 64, hipHostMallocDefault));
         void* st = c->c.state.get(sizeof(CGState));
         FGI_HIP(hipMemset(st, 0, sizeof(CGState)));
         FGI_HIP(hipDeviceSynchronize());
@@ -224,11 +225,14 @@ int fgi_destroy(fgi_ctx* ctx) {
         DevBuf* bufs[] = {&c.gauge, &c.gauge_disp, &c.sloppy, &c.sloppy_disp, &c.mom, &c.force, &c.force2,
                           &c.scratch_mom, &c.eta, &c.phi, &c.X, &c.Xo, &c.Ye, &c.Yo, &c.tmp_e, &c.tmp_o,
                           &c.cg_r, &c.cg_p, &c.cg_q, &c.s_x, &c.s_r, &c.s_p, &c.s_q, &c.s_t, &c.s_norms,
-                          &c.h0, &c.hf0, &c.partial, &c.scal, &c.state, &c.phi2, &c.eta2, &c.user_tmp};
+                          &c.h0, &c.hf0, &c.partial, &c.scal, &c.state, &c.phi2, &c.eta2, &c.user_tmp, &c.aux};
         for (DevBuf* b : bufs) b->release();
         for (hipEvent_t e : c.ev_pool) hipEventDestroy(e);
+        for (GraphEntry& e : c.graphs) hipGraphExecDestroy(e.exec);
+        if (c.cap_stream) hipStreamDestroy(c.cap_stream);
         if (c.host_scal) hipHostFree(c.host_scal);
         if (c.host_state) hipHostFree(c.host_state);
+        if (c.host_aux) hipHostFree(c.host_aux);
         delete ctx;
     });
 }
@@ -244,6 +248,10 @@ int fgi_set_option(fgi_ctx* ctx, const char* name, double value) {
         } else if (n == "ru_delta") {
             if (!(value > 0 && value < 1)) throw Error(FGI_EINVAL, "ru_delta must be in (0,1)");
             c.ru_delta = value;
+        } else if (n == "persistent") {
+            c.use_persistent = value != 0;
+        } else if (n == "graphs") {
+            c.use_graphs = value != 0;
         } else if (n == "profile") {
             c.profile = value != 0;
         } else if (n == "profile_prec") {
@@ -253,7 +261,6 @@ int fgi_set_option(fgi_ctx* ctx, const char* name, double value) {
             c.dslash_ms = 0;
             c.dslash_launches = 0;
             c.dslash_sites = 0;
-            c.ev_used = 0;
         } else {
             throw Error(FGI_EINVAL, "unknown option " + n);
         }
@@ -263,7 +270,6 @@ int fgi_set_option(fgi_ctx* ctx, const char* name, double value) {
 int fgi_get_profile(fgi_ctx* ctx, double* ms, long* launches, long* sites) {
     return guarded([&] {
         Ctx& c = ctx_of(ctx);
-        prof_collect(c);
         if (ms) *ms = c.dslash_ms;
         if (launches) *launches = c.dslash_launches;
         if (sites) *sites = c.dslash_sites;

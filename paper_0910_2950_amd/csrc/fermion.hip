@@ -26,14 +26,65 @@ template <typename R> __device__ __forceinline__ void flip_lower(cx<R> v[4][3]) 
     for (int k = 0; k < 3; k++) { v[2][k] = -v[2][k]; v[3][k] = -v[3][k]; }
 }
 
-template <int MU, int PIN, int PL, int RECON, int G5IN, typename R>
-__device__ __forceinline__ void hop_dir(const Geom& g, int p, int s, const Coord& c, const void* links,
-                                        const SpinorPtr& in, cx<R> acc[4][3]) {
+// Round a spinor to FP16 storage with the per-site scale exactly as
+// SpinorIO<P16>::store followed by ::load does, in registers.
+template <typename R> __device__ __forceinline__ void quantize16(cx<R> v[4][3]) {
+    float m = 0.f;
+#pragma unroll
+    for (int e = 0; e < 12; e++) {
+        m = fmaxf(m, fabsf(float(v[e / 3][e % 3].re)));
+        m = fmaxf(m, fabsf(float(v[e / 3][e % 3].im)));
+    }
+    float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+    for (int e = 0; e < 12; e++) {
+        cx<R>& a = v[e / 3][e % 3];
+        a.re = R(float((_Float16)(float(a.re) * inv)) * m);
+        a.im = R(float((_Float16)(float(a.im) * inv)) * m);
+    }
+}
+
+// p_new = r + beta p_old (explicit FMAs so every kernel rounds identically)
+template <typename R>
+__device__ __forceinline__ void p_update(const cx<R> r[4][3], cx<R> p[4][3], R beta) {
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            p[i][k].re = fma(beta, p[i][k].re, r[i][k].re);
+            p[i][k].im = fma(beta, p[i][k].im, r[i][k].im);
+        }
+}
+
+// neighbour spinor loaders used by the hop sum
+template <int PIN, int G5IN, typename R> struct LoadPlain {
+    SpinorPtr in;
+    __device__ __forceinline__ void operator()(int s, int Vh, cx<R> psi[4][3]) const {
+        SpinorIO<PIN, R>::load(in, s, Vh, psi);
+        if (G5IN) flip_lower(psi);
+    }
+};
+
+// CG direction formed on the fly: p_new = r + beta p_old, rounded to p's storage
+template <int PP, int PX, typename R> struct LoadPNew {
+    SpinorPtr p, r;
+    R beta;
+    __device__ __forceinline__ void operator()(int s, int Vh, cx<R> v[4][3]) const {
+        cx<R> a[4][3];
+        SpinorIO<PX, R>::load(r, s, Vh, a);
+        SpinorIO<PP, R>::load(p, s, Vh, v);
+        p_update(a, v, beta);
+        if (PP == P16) quantize16(v);
+    }
+};
+
+template <int MU, int PL, int RECON, typename R, typename L>
+__device__ __forceinline__ void hop_dir(const Geom& g, int p, int s, const Coord& c, const void* links, const L& load,
+                                        cx<R> acc[4][3]) {
     cx<R> psi[4][3], h[2][3], uh[2][3];
     {   // forward hop: (1 - g_mu) U_mu(x) psi(x + mu)
         int sn = cb_neighbour(g, c, MU, +1);
-        SpinorIO<PIN, R>::load(in, sn, g.Vh, psi);
-        if (G5IN) flip_lower(psi);
+        load(sn, g.Vh, psi);
         spin_proj<MU, -1>(psi, h);
         M3<R> u = LinkIO<PL, RECON, R>::load(links, MU, p, s, g.Vh);
 #pragma unroll
@@ -45,8 +96,7 @@ __device__ __forceinline__ void hop_dir(const Geom& g, int p, int s, const Coord
     }
     {   // backward hop: (1 + g_mu) U_mu(x - mu)^+ psi(x - mu)
         int sn = cb_neighbour(g, c, MU, -1);
-        SpinorIO<PIN, R>::load(in, sn, g.Vh, psi);
-        if (G5IN) flip_lower(psi);
+        load(sn, g.Vh, psi);
         spin_proj<MU, +1>(psi, h);
         M3<R> u = LinkIO<PL, RECON, R>::load(links, MU, 1 - p, sn, g.Vh);
 #pragma unroll
@@ -59,18 +109,18 @@ __device__ __forceinline__ void hop_dir(const Geom& g, int p, int s, const Coord
     }
 }
 
-template <int PIN, int PL, int RECON, int G5IN, typename R>
-__device__ __forceinline__ void hop_sum(const Geom& g, int p, int s, const void* links, const SpinorPtr& in,
+template <int PL, int RECON, typename R, typename L>
+__device__ __forceinline__ void hop_sum(const Geom& g, int p, int s, const void* links, const L& load,
                                         cx<R> acc[4][3]) {
     Coord c = cb_coords(g, p, s);
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
         for (int k = 0; k < 3; k++) acc[i][k] = {R(0), R(0)};
-    hop_dir<0, PIN, PL, RECON, G5IN>(g, p, s, c, links, in, acc);
-    hop_dir<1, PIN, PL, RECON, G5IN>(g, p, s, c, links, in, acc);
-    hop_dir<2, PIN, PL, RECON, G5IN>(g, p, s, c, links, in, acc);
-    hop_dir<3, PIN, PL, RECON, G5IN>(g, p, s, c, links, in, acc);
+    hop_dir<0, PL, RECON>(g, p, s, c, links, load, acc);
+    hop_dir<1, PL, RECON>(g, p, s, c, links, load, acc);
+    hop_dir<2, PL, RECON>(g, p, s, c, links, load, acc);
+    hop_dir<3, PL, RECON>(g, p, s, c, links, load, acc);
 }
 
 // ------------------------------------------------ last-block reductions ---
@@ -104,9 +154,10 @@ __device__ __forceinline__ bool last_block_sum(double v, double* partial, unsign
 enum Mode {
     M_HOP = 0,    // out = [g5] acc
     M_SCHUR = 1,  // out = center - kappa^2 [g5] acc          [|out|^2 -> *result]
-    M_CGQ = 2,    // CG: q = p - kappa^2 acc, pAp = |q|^2 (= <p, Mhat^+ Mhat p>)
-    M_CGX = 3,    // CG: Ap = q - kappa^2 g5 acc; x += alpha p; r -= alpha Ap; |r|^2
-    M_RESID = 4   // r = aux - (center - kappa^2 g5 acc), |r|^2 -> *result
+    M_CGQ = 2,    // CG: p = r + beta p (stored), q = p - kappa^2 acc, pAp = |q|^2 (= <p, Mhat^+ Mhat p>)
+    M_CGX = 3,    // CG: Ap = q - kappa^2 g5 acc; x += alpha p; r -= alpha Ap; |r|^2, next beta
+    M_RESID = 4,  // r = aux - (center - kappa^2 g5 acc), |r|^2 -> *result
+    M_HOPP = 5    // CG: out = D (r + beta p_old), the new direction formed per neighbour
 };
 
 struct DArgs {
@@ -119,7 +170,7 @@ struct DArgs {
     unsigned* counter;
     double* result;
     CGState* st;
-    int iter;
+    int iter;   // absolute index, or the offset from st->base inside a CG batch
     int g5out;
 };
 
@@ -128,19 +179,34 @@ __global__ void __launch_bounds__(DBS) k_dslash(DArgs A) {
     typedef typename Real<PIN == P64 ? P64 : P32>::T R;
     __shared__ double lds[DBS / 64];
     const Geom& g = A.g;
-    if (A.st && A.st->stop_at <= A.iter) return;  // solve converged: the whole grid no-ops
+    const int iter = A.st ? A.st->base + A.iter : A.iter;
+    if (A.st && A.st->stop_at <= iter) return;  // solve converged: the whole grid no-ops
     int b = xcd_block(blockIdx.x, gridDim.x);
     int s = b * DBS + threadIdx.x;
     double nrm = 0.0;
     if (s < g.Vh) {
         cx<R> acc[4][3];
-        hop_sum<PIN, PL, RECON, G5IN, R>(g, A.p_out, s, A.links, A.in, acc);
+        if constexpr (MODE == M_HOPP) {
+            LoadPNew<PIN, PX, R> ld{A.in, A.r, R(A.st->beta)};
+            hop_sum<PL, RECON, R>(g, A.p_out, s, A.links, ld, acc);
+        } else {
+            LoadPlain<PIN, G5IN, R> ld{A.in};
+            hop_sum<PL, RECON, R>(g, A.p_out, s, A.links, ld, acc);
+        }
         if (A.g5out) flip_lower(acc);
-        if (MODE == M_HOP) {
+        if (MODE == M_HOP || MODE == M_HOPP) {
             SpinorIO<POUT, R>::store(A.out, s, g.Vh, acc);
         } else {
             cx<R> cen[4][3];
             SpinorIO<PC, R>::load(A.center, s, g.Vh, cen);
+            if constexpr (MODE == M_CGQ) {
+                // the new search direction at this site, stored in place of p_old
+                cx<R> rr[4][3];
+                SpinorIO<PX, R>::load(A.r, s, g.Vh, rr);
+                p_update(rr, cen, R(A.st->beta));
+                SpinorIO<PC, R>::store(A.center, s, g.Vh, cen);
+                if (PC == P16) quantize16(cen);
+            }
             const R k2 = R(A.kappa2);
 #pragma unroll
             for (int i = 0; i < 4; i++)
@@ -166,7 +232,7 @@ __global__ void __launch_bounds__(DBS) k_dslash(DArgs A) {
                 SpinorIO<POUT, R>::store(A.out, s, g.Vh, acc);
             } else if (MODE == M_CGX) {
                 typedef typename Real<PX>::T RX;
-                const RX al = RX(A.st->rr[A.iter & 1] / A.st->pAp);
+                const RX al = RX(A.st->rr[iter & 1] / A.st->pAp);
                 cx<RX> pv[4][3], xv[4][3], rv[4][3];
                 SpinorIO<PC, RX>::load(A.aux, s, g.Vh, pv);  // p has the precision of q
                 SpinorIO<PX, RX>::load(A.x, s, g.Vh, xv);
@@ -185,7 +251,7 @@ __global__ void __launch_bounds__(DBS) k_dslash(DArgs A) {
             }
         }
     }
-    if (MODE == M_HOP) return;
+    if (MODE == M_HOP || MODE == M_HOPP) return;
     if (MODE == M_SCHUR && !A.result) return;
     double total;
     bool last = last_block_sum(nrm, A.partial, A.counter, lds, &total);
@@ -193,30 +259,217 @@ __global__ void __launch_bounds__(DBS) k_dslash(DArgs A) {
     if (MODE == M_CGQ) {
         A.st->pAp = total;
     } else if (MODE == M_CGX) {
-        A.st->rr[(A.iter + 1) & 1] = total;
-        A.st->iters = A.iter + 1;
-        if (total <= A.st->rr_stop) A.st->stop_at = A.iter + 1;
+        A.st->beta = total / A.st->rr[iter & 1];
+        A.st->rr[(iter + 1) & 1] = total;
+        A.st->iters = iter + 1;
+        if (total <= A.st->rr_stop) A.st->stop_at = iter + 1;
     } else {
         *A.result = total;
     }
 }
 
-// p = r + beta p, beta = rr_{k+1} / rr_k  (skipped once converged)
-template <int PP, int PX>
-__global__ void __launch_bounds__(DBS) k_cg_p(Geom g, SpinorPtr r, SpinorPtr pv, CGState* st, int iter) {
-    if (st->stop_at <= iter + 1) return;
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= g.Vh) return;
+// advance the batch base (last node of a CG batch)
+__global__ void k_advance(CGState* st, int n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->base += n;
+}
+
+// --------------------------------------------------- persistent CG kernel ---
+// All iterations of one inner CG run in a single cooperative launch: the four
+// Dslash-shaped phases of an iteration are separated by grid barriers.  Every
+// block owns one contiguous chunk of even and odd checkerboard sites (XCD-aware
+// block order) in every phase, so its links and spinors stay in its XCD's L2.
+// The scalar recurrences (alpha, beta, |r|^2) are identical in every block: a
+// barrier's last arriving block sums the block partials in a fixed order and
+// publishes the total with the release of the barrier.
+struct PArgs {
+    Geom g;
+    double kappa2;
+    const void* links;
+    SpinorPtr x, r, p, q, t;
+    double* part;        // [gridDim] block partials
+    double* total;       // [2] published reduction results
+    unsigned* bar;       // [0] arrivals, [1] generation
+    CGState* st;
+    int* err;            // set to 1 when a barrier wait exceeds its spin limit
+    int max_iters;       // iterations allowed in this launch (>= 1)
+    int chunk;           // sites per block (multiple of the block size)
+};
+
+// Grid barrier with an optional fixed-order reduction of part[0..nb) into
+// *total by the last arriving block.  Waits are bounded: after 2^26 polls
+// (about a second) the block flags *err; every block checks *err after each
+// barrier and leaves the iteration loop, so the kernel always terminates.
+__device__ __forceinline__ double grid_barrier(unsigned* bar, double* part, double* total, bool reduce, int* err,
+                                               double* lds, bool* abort) {
+    __shared__ double result;
+    __shared__ int last;
+    __shared__ int aborted;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned gen = __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        unsigned arrived = atomicAdd(bar, 1u);
+        last = (arrived == gridDim.x - 1);
+        if (!last) {
+            long spins = 0;
+            while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (++spins > (1L << 26)) {
+                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __threadfence();
+        aborted = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    *abort = aborted != 0;
+    if (last) {
+        if (reduce) {
+            double t = 0.0;
+            for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x)
+                t += __hip_atomic_load(part + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            double v[1] = {t};
+            block_sum<1>(v, lds);
+            if (threadIdx.x == 0) {
+                __hip_atomic_store(total, v[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                result = v[0];
+            }
+        }
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        return reduce ? result : 0.0;
+    }
+    if (reduce) {
+        if (threadIdx.x == 0) result = __hip_atomic_load(total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        return result;
+    }
+    return 0.0;
+}
+
+template <int PP, int PX, int PL, int RECON>
+__global__ void __launch_bounds__(DBS) k_cg_persistent(PArgs A) {
+    typedef typename Real<PP == P64 ? P64 : P32>::T R;
     typedef typename Real<PX>::T RX;
-    const RX beta = RX(st->rr[(iter + 1) & 1] / st->rr[iter & 1]);
-    cx<RX> a[4][3], b[4][3];
-    SpinorIO<PX, RX>::load(r, s, g.Vh, a);
-    SpinorIO<PP, RX>::load(pv, s, g.Vh, b);
+    __shared__ double lds[DBS / 64];
+    const Geom& g = A.g;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int s0 = b * A.chunk, s1 = min(s0 + A.chunk, g.Vh);
+    const R k2 = R(A.kappa2);
+    // every block reads the state before the first barrier; block 0 rewrites it
+    // only after the last one
+    const CGState S = *A.st;
+    int iter = S.base;
+    if (S.stop_at <= iter) return;
+    double rr = S.rr[iter & 1];
+    double rr_prev = S.rr[(iter + 1) & 1];
+    double beta = S.beta;
+    bool stopped = false, abort = false;
+    for (int j = 0; j < A.max_iters; j++) {
+        // t = D_oe (r + beta p)
+        for (int s = s0 + (int)threadIdx.x; s < s1; s += DBS) {
+            cx<R> acc[4][3];
+            LoadPNew<PP, PX, R> ld{A.p, A.r, R(beta)};
+            hop_sum<PL, RECON, R>(g, 1, s, A.links, ld, acc);
+            SpinorIO<PP, R>::store(A.t, s, g.Vh, acc);
+        }
+        grid_barrier(A.bar, A.part, A.total, false, A.err, lds, &abort);
+        if (abort) break;
+        // p = r + beta p; q = p - k^2 D_eo t; pAp = |q|^2
+        double nq = 0.0;
+        for (int s = s0 + (int)threadIdx.x; s < s1; s += DBS) {
+            cx<R> acc[4][3], cen[4][3], rv[4][3];
+            LoadPlain<PP, 0, R> ld{A.t};
+            hop_sum<PL, RECON, R>(g, 0, s, A.links, ld, acc);
+            SpinorIO<PX, R>::load(A.r, s, g.Vh, rv);
+            SpinorIO<PP, R>::load(A.p, s, g.Vh, cen);
+            p_update(rv, cen, R(beta));
+            SpinorIO<PP, R>::store(A.p, s, g.Vh, cen);
+            if (PP == P16) quantize16(cen);
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+            for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int k = 0; k < 3; k++) b[i][k] = a[i][k] + beta * b[i][k];
-    SpinorIO<PP, RX>::store(pv, s, g.Vh, b);
+                for (int k = 0; k < 3; k++) {
+                    acc[i][k] = cen[i][k] - k2 * acc[i][k];
+                    nq += double(acc[i][k].re) * double(acc[i][k].re) + double(acc[i][k].im) * double(acc[i][k].im);
+                }
+            SpinorIO<PP, R>::store(A.q, s, g.Vh, acc);
+        }
+        {
+            double v[1] = {nq};
+            block_sum<1>(v, lds);
+            if (threadIdx.x == 0) __hip_atomic_store(A.part + blockIdx.x, v[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const double pAp = grid_barrier(A.bar, A.part, A.total, true, A.err, lds, &abort);
+        if (abort) break;
+        const double alpha = rr / pAp;
+        // t = D_oe g5 q
+        for (int s = s0 + (int)threadIdx.x; s < s1; s += DBS) {
+            cx<R> acc[4][3];
+            LoadPlain<PP, 1, R> ld{A.q};
+            hop_sum<PL, RECON, R>(g, 1, s, A.links, ld, acc);
+            SpinorIO<PP, R>::store(A.t, s, g.Vh, acc);
+        }
+        grid_barrier(A.bar, A.part, A.total, false, A.err, lds, &abort);
+        if (abort) break;
+        // Ap = q - k^2 g5 D_eo t; x += alpha p; r -= alpha Ap
+        double nr = 0.0;
+        for (int s = s0 + (int)threadIdx.x; s < s1; s += DBS) {
+            cx<R> acc[4][3], cen[4][3];
+            LoadPlain<PP, 0, R> ld{A.t};
+            hop_sum<PL, RECON, R>(g, 0, s, A.links, ld, acc);
+            flip_lower(acc);
+            SpinorIO<PP, R>::load(A.q, s, g.Vh, cen);
+            cx<RX> pv[4][3], xv[4][3], rv[4][3];
+            SpinorIO<PP, RX>::load(A.p, s, g.Vh, pv);
+            SpinorIO<PX, RX>::load(A.x, s, g.Vh, xv);
+            SpinorIO<PX, RX>::load(A.r, s, g.Vh, rv);
+            const RX al = RX(alpha);
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    cx<R> a = cen[i][k] - k2 * acc[i][k];
+                    cx<RX> ap = {RX(a.re), RX(a.im)};
+                    xv[i][k] = xv[i][k] + al * pv[i][k];
+                    rv[i][k] = rv[i][k] - al * ap;
+                    nr += double(rv[i][k].re) * double(rv[i][k].re) + double(rv[i][k].im) * double(rv[i][k].im);
+                }
+            SpinorIO<PX, RX>::store(A.x, s, g.Vh, xv);
+            SpinorIO<PX, RX>::store(A.r, s, g.Vh, rv);
+        }
+        {
+            double v[1] = {nr};
+            block_sum<1>(v, lds);
+            if (threadIdx.x == 0) __hip_atomic_store(A.part + blockIdx.x, v[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const double rr_new = grid_barrier(A.bar, A.part, A.total + 1, true, A.err, lds, &abort);
+        if (abort) break;
+        beta = rr_new / rr;
+        rr_prev = rr;
+        rr = rr_new;
+        iter++;
+        if (rr_new <= S.rr_stop) {
+            stopped = true;
+            break;
+        }
+    }
+    if (b == 0 && threadIdx.x == 0 && !abort) {
+        CGState o = S;
+        o.rr[iter & 1] = rr;            // |r|^2 after the last iteration
+        o.rr[(iter + 1) & 1] = rr_prev; // and before it (a restart needs both)
+        o.beta = beta;
+        o.base = iter;
+        o.iters = iter;
+        o.stop_at = stopped ? iter : INT_MAX;
+        *A.st = o;
+    }
 }
 
 // conversion between storage precisions (through FP64 registers)
@@ -343,8 +596,6 @@ static SpinorPtr sp(const void* v, float* norm = nullptr) { return SpinorPtr{(vo
 template <int MODE, int PIN, int PC, int POUT, int PX, int G5IN>
 static void launch_dslash(Ctx& c, const FermionOp& op, DArgs& a) {
     int nb = nblk(a.g.Vh, DBS);
-    bool prof = c.profile && (MODE == M_HOP) && (c.profile_prec < 0 || c.profile_prec == PIN);
-    if (prof) prof_begin(c);
     if constexpr (PIN == P64) {
         if (op.prec != P64) throw Error(-1, "FP64 spinors need FP64 links");
         hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, P64, 18, G5IN>), dim3(nb), dim3(DBS), 0, c.stream, a);
@@ -359,7 +610,6 @@ static void launch_dslash(Ctx& c, const FermionOp& op, DArgs& a) {
             throw Error(-1, "sloppy spinors need sloppy links");
     }
     FGI_LAUNCH_CHECK();
-    if (prof) prof_end(c, a.g.Vh);
 }
 
 static DArgs base_args(const FermionOp& op, int p_out) {
@@ -480,40 +730,47 @@ struct CGVecs {
     SpinorPtr x, r, p, q, t;  // x, r in PX; p, q, t in PP
 };
 
+// One CG iteration on A = Mhat^+ Mhat in four Dslash-shaped kernels; the
+// iteration index is st->base + j so a captured batch can be replayed.
+//   t = D_oe (r + beta p)            [p formed per neighbour]
+//   p = r + beta p; q = p - k^2 D_eo t; pAp = |q|^2
+//   t = D_oe g5 q                    [bare hop: the profiled kernel]
+//   Ap = q - k^2 g5 D_eo t; x += alpha p; r -= alpha Ap; rr, beta
 template <int PP, int PX>
-static void cg_iteration(Ctx& c, const FermionOp& ops, const CGVecs& v, int k) {
+static void cg_iteration(Ctx& c, const FermionOp& ops, const CGVecs& v, int j) {
     CGState* st = dev_state(c);
     double* part = (double*)c.partial.get(sizeof(double) * 65536);
     unsigned* cnt = dev_counter(c);
-    const Geom& g = *ops.g;
-    {   // t = D_oe p
+    {
         DArgs a = base_args(ops, 1);
         a.in = v.p;
+        a.r = v.r;
         a.out = v.t;
         a.st = st;
-        a.iter = k;
-        launch_dslash<M_HOP, PP, PP, PP, PX, 0>(c, ops, a);
+        a.iter = j;
+        launch_dslash<M_HOPP, PP, PP, PP, PX, 0>(c, ops, a);
     }
-    {   // q = p - k^2 D_eo t ; pAp = |q|^2
+    {
         DArgs a = base_args(ops, 0);
         a.in = v.t;
         a.center = v.p;
+        a.r = v.r;
         a.out = v.q;
         a.partial = part;
         a.counter = cnt;
         a.st = st;
-        a.iter = k;
+        a.iter = j;
         launch_dslash<M_CGQ, PP, PP, PP, PX, 0>(c, ops, a);
     }
-    {   // t = D_oe g5 q
+    {
         DArgs a = base_args(ops, 1);
         a.in = v.q;
         a.out = v.t;
         a.st = st;
-        a.iter = k;
+        a.iter = j;
         launch_dslash<M_HOP, PP, PP, PP, PX, 1>(c, ops, a);
     }
-    {   // Ap = q - k^2 g5 D_eo t; x += alpha p; r -= alpha Ap; rr'
+    {
         DArgs a = base_args(ops, 0);
         a.in = v.t;
         a.center = v.q;
@@ -524,11 +781,71 @@ static void cg_iteration(Ctx& c, const FermionOp& ops, const CGVecs& v, int k) {
         a.partial = part;
         a.counter = cnt;
         a.st = st;
-        a.iter = k;
+        a.iter = j;
         launch_dslash<M_CGX, PP, PP, PP, PX, 0>(c, ops, a);
     }
-    hipLaunchKernelGGL((k_cg_p<PP, PX>), dim3(nblk(g.Vh, DBS)), dim3(DBS), 0, c.stream, g, v.r, v.p, st, k);
+}
+
+// B iterations then base += B, on c.stream
+template <int PP, int PX>
+static void cg_batch_eager(Ctx& c, const FermionOp& ops, const CGVecs& v, int B) {
+    for (int j = 0; j < B; j++) cg_iteration<PP, PX>(c, ops, v, j);
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c.stream, dev_state(c), B);
     FGI_LAUNCH_CHECK();
+}
+
+// N bare hops t = D_oe g5 q on the solve's live operator and vectors (the
+// sample that times the Dslash kernel; t is scratch, q is only read)
+template <int PP, int PX>
+static void hop_sample_eager(Ctx& c, const FermionOp& ops, const CGVecs& v, int N) {
+    for (int j = 0; j < N; j++) {
+        DArgs a = base_args(ops, 1);
+        a.in = v.q;
+        a.out = v.t;
+        launch_dslash<M_HOP, PP, PP, PP, PX, 1>(c, ops, a);
+    }
+}
+
+// Capture `body` on the private capture stream into an instantiated graph,
+// cached under `key`.
+template <typename Body>
+static GraphEntry& cached_graph(Ctx& c, const std::string& key, Body body) {
+    for (auto& e : c.graphs)
+        if (e.key == key) return e;
+    if (!c.cap_stream) FGI_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+    if (c.graphs.size() >= 24) {
+        hipGraphExecDestroy(c.graphs.front().exec);
+        c.graphs.erase(c.graphs.begin());
+    }
+    GraphEntry e;
+    e.key = key;
+    hipStream_t saved = c.stream;
+    c.stream = c.cap_stream;
+    hipGraph_t graph = nullptr;
+    try {
+        FGI_HIP(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeRelaxed));
+        body();
+        FGI_HIP(hipStreamEndCapture(c.cap_stream, &graph));
+        FGI_HIP(hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0));
+        FGI_HIP(hipGraphDestroy(graph));
+    } catch (...) {
+        c.stream = saved;
+        hipStreamEndCapture(c.cap_stream, &graph);
+        if (graph) hipGraphDestroy(graph);
+        throw;
+    }
+    c.stream = saved;
+    c.graphs.push_back(e);
+    return c.graphs.back();
+}
+
+template <int PP, int PX>
+static std::string graph_key(const char* what, Ctx& c, const FermionOp& ops, const CGVecs& v, int n) {
+    char key[512];
+    snprintf(key, sizeof key, "%s/%d/%d/%p/%.17g/%d/%d/%d/%d/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%d", what, PP, PX,
+             ops.links, ops.kappa, ops.prec, ops.recon, ops.g->L[0], ops.g->L[1], ops.g->L[2], ops.g->L[3],
+             ops.g->Vh, v.x.v, v.r.v, v.p.v, v.q.v, v.t.v, (void*)v.p.norm, (void*)dev_state(c), c.partial.p, n);
+    return key;
 }
 
 template <int PA, int PB>
@@ -551,6 +868,66 @@ static void zero_spinor(Ctx& c, const Geom& g, void* v, int prec) {
     if (prec == P16) throw Error(-1, "zero_spinor: FP16");
     hipLaunchKernelGGL(k_zero, dim3(nblk((long)n, 256)), dim3(256), 0, c.stream, n, (double*)v);
     FGI_LAUNCH_CHECK();
+}
+
+// Resources of the persistent solver: barrier words, error flag, totals.
+struct PersistentAux {
+    unsigned bar[2];
+    int err;
+    int pad;
+    double total[2];
+};
+
+__global__ void k_reset_aux(PersistentAux* a) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        a->bar[0] = 0;
+        a->bar[1] = 0;
+        a->err = 0;
+    }
+}
+
+template <int PP, int PX, int PL, int RC>
+static void launch_persistent_t(Ctx& c, PArgs& a) {
+    const void* f = (const void*)k_cg_persistent<PP, PX, PL, RC>;
+    int per_cu = 0;
+    FGI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, DBS, 0));
+    int dev = 0, ncu = 0;
+    FGI_HIP(hipGetDevice(&dev));
+    FGI_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    int need = nblk(a.g.Vh, DBS);
+    int nb = std::min(need, std::max(1, per_cu) * ncu);
+    a.chunk = nblk(nblk(a.g.Vh, nb), DBS) * DBS;
+    nb = nblk(a.g.Vh, a.chunk);
+    void* args[] = {&a};
+    FGI_HIP(hipLaunchCooperativeKernel(f, dim3(nb), dim3(DBS), args, 0, c.stream));
+}
+
+template <int PP, int PX>
+static void launch_persistent(Ctx& c, const FermionOp& ops, const CGVecs& v, int max_iters, PersistentAux* aux) {
+    PArgs a{};
+    a.g = *ops.g;
+    a.kappa2 = ops.kappa * ops.kappa;
+    a.links = ops.links;
+    a.x = v.x;
+    a.r = v.r;
+    a.p = v.p;
+    a.q = v.q;
+    a.t = v.t;
+    a.part = (double*)c.partial.get(sizeof(double) * 65536);
+    a.total = aux->total;
+    a.bar = aux->bar;
+    a.err = &aux->err;
+    a.st = dev_state(c);
+    a.max_iters = max_iters;
+    hipLaunchKernelGGL(k_reset_aux, dim3(1), dim3(64), 0, c.stream, aux);
+    FGI_LAUNCH_CHECK();
+    if constexpr (PP == P64) {
+        launch_persistent_t<PP, PX, P64, 18>(c, a);
+    } else {
+        if (ops.prec == P32 && ops.recon == 18) launch_persistent_t<PP, PX, P32, 18>(c, a);
+        else if (ops.prec == P32) launch_persistent_t<PP, PX, P32, 12>(c, a);
+        else launch_persistent_t<PP, PX, P16, 12>(c, a);
+    }
 }
 
 template <int PP, int PX>
@@ -589,23 +966,45 @@ static CGResult cg_run(Ctx& c, const FermionOp& op64, const FermionOp& ops, cons
         convert<P64, PX>(c, g, sp(phi), v.r);
         convert<P64, PP>(c, g, sp(phi), v.p);
     }
+    c.partial.get(sizeof(double) * 65536);  // allocate before any capture
     CGState* st = dev_state(c);
     CGState h{};
     h.rr[0] = bb;
     h.rr_stop = (PX == P64) ? target : std::max(c.ru_delta * c.ru_delta * bb, target);
+    h.beta = 0.0;
     h.stop_at = INT_MAX;
+    h.base = 0;
     h.counter = 0;
     hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, c.stream, st, h);
     FGI_LAUNCH_CHECK();
-    int k = 0;
+    const bool prof = c.profile && (c.profile_prec < 0 || c.profile_prec == PP);
+    const int B = c.cg_batch;
+    const bool persistent = c.use_persistent;
+    PersistentAux* aux = (PersistentAux*)c.aux.get(sizeof(PersistentAux));
+    GraphEntry* ge = nullptr;
+    if (c.use_graphs && !persistent)
+        ge = &cached_graph(c, graph_key<PP, PX>("cg", c, ops, v, B), [&] { cg_batch_eager<PP, PX>(c, ops, v, B); });
+    int k = 0;  // iteration index of the next batch
     for (;;) {
-        int nb = std::min(c.cg_batch, maxiter - k);
-        for (int j = 0; j < nb; j++) cg_iteration<PP, PX>(c, ops, v, k + j);
-        FGI_HIP(hipMemcpyAsync(c.host_state, st, sizeof(CGState), hipMemcpyDeviceToHost, c.stream));
-        FGI_HIP(hipStreamSynchronize(c.stream));
-        const CGState hs = *c.host_state;
-        bool inner_done = hs.stop_at <= k + nb;
-        int kend = inner_done ? hs.stop_at : k + nb;
+        int kend;
+        CGState hs;
+        if (persistent) {
+            launch_persistent<PP, PX>(c, ops, v, maxiter - k, aux);
+            FGI_HIP(hipMemcpyAsync(c.host_state, st, sizeof(CGState), hipMemcpyDeviceToHost, c.stream));
+            FGI_HIP(hipMemcpyAsync(c.host_aux, &aux->err, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+            FGI_HIP(hipStreamSynchronize(c.stream));
+            if (*c.host_aux) throw Error(-2, "CG: grid barrier wait exceeded its limit");
+            hs = *c.host_state;
+            kend = hs.base;
+        } else {
+            if (ge) FGI_HIP(hipGraphLaunch(ge->exec, c.stream));
+            else cg_batch_eager<PP, PX>(c, ops, v, B);
+            FGI_HIP(hipMemcpyAsync(c.host_state, st, sizeof(CGState), hipMemcpyDeviceToHost, c.stream));
+            FGI_HIP(hipStreamSynchronize(c.stream));
+            hs = *c.host_state;
+            kend = hs.stop_at <= k + B ? hs.stop_at : k + B;
+        }
+        bool inner_done = hs.stop_at <= kend;
         if (inner_done || kend >= maxiter) {
             if (PX != P64) {
                 hipLaunchKernelGGL((k_add_to64<PX>), dim3(nblk(g.Vh, DBS)), dim3(DBS), 0, c.stream, g.Vh, v.x, sp(X));
@@ -627,21 +1026,43 @@ static CGResult cg_run(Ctx& c, const FermionOp& op64, const FermionOp& ops, cons
                 zero_spinor(c, g, v.x.v, P32);
             }
             CGState u = hs;
+            u.beta = rr / hs.rr[(kend - 1) & 1];
             u.rr[kend & 1] = rr;
             u.stop_at = INT_MAX;
+            u.base = kend;
             u.rr_stop = (PX == P64) ? target : std::max(c.ru_delta * c.ru_delta * rr, target);
             u.counter = 0;
             hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, c.stream, st, u);
-            FGI_LAUNCH_CHECK();
-            // p = r + beta p with beta = |r_true|^2 / rr_{kend-1}
-            hipLaunchKernelGGL((k_cg_p<PP, PX>), dim3(nblk(g.Vh, DBS)), dim3(DBS), 0, c.stream, g, v.r, v.p, st, kend - 1);
             FGI_LAUNCH_CHECK();
             k = kend;
         } else {
             k = kend;
         }
     }
-    if (c.profile) prof_collect(c);
+    if (prof) {
+        // live sample of the bare hop: N back-to-back launches between two events
+        const int N = 16;
+        if (c.ev_pool.empty()) {
+            for (int i = 0; i < 2; i++) {
+                hipEvent_t e;
+                FGI_HIP(hipEventCreate(&e));
+                c.ev_pool.push_back(e);
+            }
+        }
+        GraphEntry* hg = nullptr;
+        if (c.use_graphs)
+            hg = &cached_graph(c, graph_key<PP, PX>("hop", c, ops, v, N), [&] { hop_sample_eager<PP, PX>(c, ops, v, N); });
+        FGI_HIP(hipEventRecord(c.ev_pool[0], c.stream));
+        if (hg) FGI_HIP(hipGraphLaunch(hg->exec, c.stream));
+        else hop_sample_eager<PP, PX>(c, ops, v, N);
+        FGI_HIP(hipEventRecord(c.ev_pool[1], c.stream));
+        FGI_HIP(hipEventSynchronize(c.ev_pool[1]));
+        float ms = 0.f;
+        FGI_HIP(hipEventElapsedTime(&ms, c.ev_pool[0], c.ev_pool[1]));
+        c.dslash_ms += ms;
+        c.dslash_launches += N;
+        c.dslash_sites += (long)N * g.Vh;
+    }
     return res;
 }
 
@@ -650,36 +1071,6 @@ CGResult cg_solve(Ctx& c, const FermionOp& op64, const FermionOp& ops, int sprec
     if (sprec == P64) return cg_run<P64, P64>(c, op64, op64, phi, X, tol, maxiter);
     if (sprec == P32) return cg_run<P32, P32>(c, op64, ops, phi, X, tol, maxiter);
     return cg_run<P16, P32>(c, op64, ops, phi, X, tol, maxiter);
-}
-
-// ---------------------------------------------------------- profiling -----
-void prof_begin(Ctx& c) {
-    if (c.ev_used + 2 > c.ev_pool.size()) {
-        for (int i = 0; i < 64; i++) {
-            hipEvent_t e;
-            FGI_HIP(hipEventCreate(&e));
-            c.ev_pool.push_back(e);
-        }
-    }
-    FGI_HIP(hipEventRecord(c.ev_pool[c.ev_used], c.stream));
-}
-
-void prof_end(Ctx& c, int sites) {
-    FGI_HIP(hipEventRecord(c.ev_pool[c.ev_used + 1], c.stream));
-    c.ev_used += 2;
-    c.dslash_launches++;
-    c.dslash_sites += sites;
-}
-
-void prof_collect(Ctx& c) {
-    if (c.ev_used == 0) return;
-    FGI_HIP(hipEventSynchronize(c.ev_pool[c.ev_used - 1]));
-    for (size_t i = 0; i < c.ev_used; i += 2) {
-        float ms = 0.f;
-        FGI_HIP(hipEventElapsedTime(&ms, c.ev_pool[i], c.ev_pool[i + 1]));
-        c.dslash_ms += ms;
-    }
-    c.ev_used = 0;
 }
 
 }  // namespace fgi

@@ -44,10 +44,17 @@ struct CGState {
     double rr[2];      // |r|^2 of the iteration vectors, slot k & 1 holds iteration k's
     double pAp;        // <p, A p> of the current iteration
     double rr_stop;    // inner stopping target
+    double beta;       // p_k = r_k + beta p_{k-1} (0 at a start)
     int stop_at;       // first iteration index that must not run (INT_MAX while running)
     int iters;         // iterations completed
+    int base;          // iteration index of the first iteration of the current batch
     unsigned counter;  // arrival counter of the last-block reductions (0 between kernels)
-    int pad;
+};
+
+// one instantiated CG batch graph, keyed by everything its kernels capture
+struct GraphEntry {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
 };
 
 // field pointers of one gauge configuration in every storage the solver needs
@@ -64,18 +71,28 @@ struct Ctx {
     DevBuf eta, phi, X, Xo, Ye, Yo, tmp_e, tmp_o, cg_r, cg_p, cg_q;
     DevBuf s_x, s_r, s_p, s_q, s_t, s_norms;
     DevBuf h0, hf0, partial, scal, state;
-    DevBuf phi2, eta2, user_tmp;
+    DevBuf phi2, eta2, user_tmp, aux;
     double* host_scal = nullptr;   // pinned, 64 doubles
     CGState* host_state = nullptr; // pinned
-    // profiling of the Dslash launches (events bracket each launch when on)
+    int* host_aux = nullptr;       // pinned (persistent-solver error flag)
+    // Live profile of the bare Dslash hop inside CG: when on, after every solve
+    // 16 back-to-back launches of t = D_oe g5 q (the solve's operator and
+    // vectors, one captured graph) are bracketed by HIP events on the solve's
+    // stream and their time accumulated.
     bool profile = false;
-    int profile_prec = -1;     // time only bare Dslash launches with this input precision (-1: all)
+    int profile_prec = -1;     // only solves whose inner precision is this (-1: all)
     std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
     double dslash_ms = 0.0;
     long dslash_launches = 0;
     long dslash_sites = 0;     // output sites summed over profiled launches
-    int dslash_bytes_per_site = 0;
+    // inner CG: batches of per-phase kernels replayed as HIP graphs (default)
+    // or launched eagerly, or one persistent cooperative launch per inner run
+    // (slower on this part: its grid barriers need agent-scope fences, which
+    // write back and invalidate the XCD L2 caches four times per iteration)
+    bool use_persistent = false;
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    std::vector<GraphEntry> graphs;
     // solver tuning
     int cg_batch = 8;          // iterations launched between host polls
     int dslash_split = 0;      // 0 = automatic
@@ -147,9 +164,5 @@ void spinor_copy(Ctx&, const Geom&, const d2* src, d2* dst);
 // b = a with storage conversion (P64/P32/P16 -> P64/P32/P16)
 void convert_spinor(Ctx&, const Geom&, int prec_a, SpinorPtr a, int prec_b, SpinorPtr b);
 
-// profiling helpers for Dslash launches
-void prof_begin(Ctx&);
-void prof_end(Ctx&, int sites);
-void prof_collect(Ctx&);
 
 }  // namespace fgi

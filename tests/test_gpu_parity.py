@@ -283,3 +283,48 @@ def test_trajectory_mixed_precision_close_to_fp64(ctx, orc, prec):
     assert relmax(host(P), Po) < 1e-7
     assert abs(dH - dHo) < 1e-6, (dH, dHo)
     assert st["max_rel_resid"] <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mp32", "mp16"])
+def test_cg_graph_replays_match_eager(ctx, prec):
+    """CG batches replayed from a captured HIP graph give bitwise the same
+    solution as the same kernels launched one by one, on every replay (three
+    solves in a row with other eager work between them)."""
+    dims = (8, 8, 8, 8)
+    U = dev(links(dims, 40))
+    act = Action(beta=5.6, kappa=0.155, cg_tol=1e-10, prec=prec, link_recon=12 if prec != "fp64" else 18)
+    phis = [dev(spinor(dims, 41 + k)) for k in range(3)]
+    try:
+        ctx.set_option("graphs", 0)
+        ref = [host(ctx.cg_solve(dims, act, U, ph)[0]) for ph in phis]
+        ctx.set_option("graphs", 1)
+        for k, ph in enumerate(phis):
+            X, st = ctx.cg_solve(dims, act, U, ph)
+            ctx.gauge_force(dims, 5.6, U)  # eager work between replays
+            assert np.array_equal(host(X), ref[k]), (prec, k)
+            assert st["max_rel_resid"] <= 1e-10
+    finally:
+        ctx.set_option("graphs", 1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mp32", "mp16"])
+@pytest.mark.parametrize("dims", [(6, 4, 4, 6), (8, 8, 8, 8), (16, 16, 16, 32)])
+def test_cg_persistent_matches_per_phase(ctx, prec, dims):
+    """The persistent cooperative solver and the per-phase kernels solve the
+    same system to the same tolerance (launch shapes differ, so rounding of the
+    reductions may differ); repeated persistent solves are bitwise repeatable."""
+    U = dev(links(dims, 50))
+    phi = dev(spinor(dims, 51))
+    tol = 1e-12 if prec == "fp64" else 1e-10
+    act = Action(beta=5.6, kappa=0.155, cg_tol=tol, prec=prec, link_recon=12 if prec != "fp64" else 18)
+    ctx.set_option("persistent", 1)
+    try:
+        X1, st1 = ctx.cg_solve(dims, act, U, phi)
+        X2, st2 = ctx.cg_solve(dims, act, U, phi)
+    finally:
+        ctx.set_option("persistent", 0)
+    assert np.array_equal(host(X1), host(X2))
+    X3, st3 = ctx.cg_solve(dims, act, U, phi)
+    assert st1["max_rel_resid"] <= tol and st3["max_rel_resid"] <= tol
+    assert relmax(host(X1), host(X3)) < 100 * tol
+
