@@ -167,6 +167,14 @@ int fgi_gauge_force(fgi_ctx* ctx, const fgi_geom* g, double beta, const void* U,
  * Section 4 that enters the Table 1 force-gradient stage. */
 int fgi_force_gradient(fgi_ctx* ctx, const fgi_geom* g, double beta, const void* U, const void* V, void* J,
                        void* stream);
+/* HV = H V with H the Hessian of S_G(exp(omega) U) in the chart omega (su(3)
+ * components per link) at omega = 0, i.e. the symmetrised second derivative
+ * (e_a e_b + e_b e_a) S_G / 2.  Per link HV = -J_V[F_G] + [V, F_G] / 2 with
+ * J_V as in fgi_force_gradient; along V = F_G the commutator vanishes and HV is
+ * minus the Section 4 force gradient.  (Backs the double backward of the
+ * PyTorch autograd wrapper.) */
+int fgi_gauge_hvp(fgi_ctx* ctx, const fgi_geom* g, double beta, const void* U, const void* V, void* HV,
+                  void* stream);
 /* F = F_G + F_F, the total force of S_G + S_F at U for pseudofermion phi
  * (even field; NULL or act->kappa == 0 for pure gauge).  One CG solve. */
 int fgi_force(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* phi, void* F,
@@ -196,6 +204,22 @@ int fgi_pf_heatbath(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, cons
 /* *SF = Re phi^+ (Mhat^+ Mhat)^-1 phi (one CG solve). */
 int fgi_pf_action(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* phi,
                   double* SF, fgi_stats* st, void* stream);
+
+/* ------------------------- Hasenbusch mass preconditioning (two pseudofermions)
+ * With act->kappa_hasen = kappa2 (< kappa) the pseudofermion action is split
+ * S_F = S_1 + S_2, S_1 = phi1^+ (Mhat2^+ Mhat2)^-1 phi1 (Mhat2 at kappa2) and
+ * S_2 = chi^+ (Mhat^+ Mhat)^-1 chi, chi = Mhat2^+ phi2, each with the Section 4
+ * force; the integrator's term masks put them on separate time scales. */
+/* phi2 = Mhat2 (Mhat2^+ Mhat2)^-1 Mhat^+ eta2, so that S_2 = eta2^+ eta2 (one solve). */
+int fgi_hasen_heatbath(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* eta2,
+                       void* phi2, fgi_stats* st, void* stream);
+/* *S2 = Re chi^+ (Mhat^+ Mhat)^-1 chi with chi = Mhat2^+ phi2 (one solve). */
+int fgi_hasen_action(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* phi2,
+                     double* S2, fgi_stats* st, void* stream);
+/* F = sum of the forces of the FGI_TERM_* terms selected by `terms` at U
+ * (phi1: S_F or S_1 pseudofermion, phi2: S_2's; NULL when not selected). */
+int fgi_force_terms(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* phi1,
+                    const void* phi2, int terms, void* F, fgi_stats* st, void* stream);
 
 /* ------------------------------------------ Poisson brackets (Section 3) */
 /* *SST = {S,{S,T}} = sum |F|^2 and *TST = {T,{S,T}} = d/dt <p, F(exp(tP) U)>

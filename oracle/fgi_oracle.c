@@ -595,35 +595,28 @@ double oracle_pf_action(const int L[4], double kappa, const cplx *U, const cplx 
     return s;
 }
 
-/* Pseudofermion force for S = phi^+ (Mhat^+ Mhat)^-1 phi given the solution
- * X_e.  From the Section 4 relation e_a(S) = -X^+ e_a(M) X applied to the
- * kernel Mhat^+ Mhat:
- *     e_a S = 2 kappa^2 Re[ Y^+ (e_a D) X ]
- * with full-lattice X = (X_e, D_oe X_e), Y = (Mhat X_e, D_eo^+ Mhat X_e)
- * and D_eo^+ = g5 D_oe g5.  For the link (mu, x) this is
- *     Re Tr[T^a W] * bc,  W = sum_s [U X(x+mu)]_s [(1-g_mu) Y(x)]_s^+
+/* Generic bilinear force.  For full-lattice X = (X_e, D_oe X_e) and
+ * Y = (Y_e, g5 D_oe g5 Y_e) (so that Y_o = D_eo^+ Y_e) the derivative of
+ * 2 Re[Y^+ D X] along link (mu, x) is
+ *     2 Re Tr[T^a W] * bc,  W = sum_s [U X(x+mu)]_s [(1-g_mu) Y(x)]_s^+
  *                             + sum_s [U (1+g_mu) Y(x+mu)]_s [X(x)]_s^+,
- * and Re Tr[T^a W] = -[TA(W)]_a / 2, so F_a = -e_a S = kappa^2 bc [TA W]_a.
- * The result is ADDED to F (scaled by `scale`). */
-void oracle_fermion_force_add(const int L[4], double kappa, const cplx *U, const cplx *Xe,
-                              double scale, double *F) {
-    long V = lat_volume(L), Vh = V / 2;
+ * with Re Tr[T^a W] = -[TA(W)]_a / 2; this adds coef * bc * [TA W]_a to F. */
+static void force_xy_add(const int L[4], const cplx *U, const cplx *Xe, const cplx *Ye, double coef, double *F) {
+    long V = lat_volume(L);
     gamma_init();
     cplx *X = malloc(sizeof(cplx) * 12 * V), *Y = malloc(sizeof(cplx) * 12 * V);
-    cplx *t = malloc(sizeof(cplx) * 12 * V), *ye = malloc(sizeof(cplx) * 12 * Vh);
+    cplx *t = malloc(sizeof(cplx) * 12 * V);
     /* X = (X_e, D_oe X_e) */
     even_to_full(L, Xe, X);
     oracle_dhop(L, U, X, t);
     for (long i = 0; i < V; i++)
         if (lat_parity(L, i) == 1) memcpy(X + i * 12, t + i * 12, 12 * sizeof(cplx));
-    /* Y = (Mhat X_e, g5 D_oe g5 Mhat X_e) */
-    oracle_mhat(L, kappa, U, Xe, ye, 0);
-    apply_g5(Vh, ye);
-    even_to_full(L, ye, Y);
+    /* Y = (Y_e, g5 D_oe g5 Y_e) */
+    even_to_full(L, Ye, Y);
+    apply_g5(V, Y);
     oracle_dhop(L, U, Y, t);
     apply_g5(V, t);
-    apply_g5(Vh, ye);
-    even_to_full(L, ye, Y);
+    even_to_full(L, Ye, Y);
     for (long i = 0; i < V; i++)
         if (lat_parity(L, i) == 1) memcpy(Y + i * 12, t + i * 12, 12 * sizeof(cplx));
 #pragma omp parallel for collapse(2) schedule(static)
@@ -645,9 +638,67 @@ void oracle_fermion_force_add(const int L[4], double kappa, const cplx *U, const
                         W.m[p][q] += a1[s * 3 + p] * conj(b1[s * 3 + q]) + a2[s * 3 + p] * conj(x0[s * 3 + q]);
             double x[8];
             alg_components(traceless_antiherm(W), x);
-            for (int a = 0; a < 8; a++) F[((long)mu * V + i) * 8 + a] += scale * kappa * kappa * bc * x[a];
+            for (int a = 0; a < 8; a++) F[((long)mu * V + i) * 8 + a] += coef * bc * x[a];
         }
-    free(X); free(Y); free(t); free(ye);
+    free(X); free(Y); free(t);
+}
+
+/* Pseudofermion force for S = phi^+ (Mhat^+ Mhat)^-1 phi given the solution
+ * X_e.  From the Section 4 relation e_a(S) = -X^+ e_a(M) X applied to the
+ * kernel Mhat^+ Mhat, with dMhat = -kappa^2 (dD_eo D_oe + D_eo dD_oe):
+ *     e_a S = 2 kappa^2 Re[ Y^+ (e_a D) X ],  Y_e = Mhat X_e,
+ * so F_a = -e_a S = kappa^2 bc [TA W]_a (force_xy_add with coef kappa^2).
+ * The result is ADDED to F (scaled by `scale`). */
+void oracle_fermion_force_add(const int L[4], double kappa, const cplx *U, const cplx *Xe,
+                              double scale, double *F) {
+    long Vh = lat_volume(L) / 2;
+    cplx *ye = malloc(sizeof(cplx) * 12 * Vh);
+    oracle_mhat(L, kappa, U, Xe, ye, 0);
+    force_xy_add(L, U, Xe, ye, scale * kappa * kappa, F);
+    free(ye);
+}
+
+/* Hasenbusch mass preconditioning: S_F = S_1 + S_2 with a heavier kappa2,
+ *   S_1 = phi1^+ (Mhat2^+ Mhat2)^-1 phi1                      (Mhat2 at kappa2)
+ *   S_2 = chi^+ (Mhat^+ Mhat)^-1 chi,  chi = Mhat2^+ phi2.
+ * Heatbath: phi1 = Mhat2^+ eta1, phi2 = Mhat2 (Mhat2^+ Mhat2)^-1 Mhat^+ eta2, so
+ * S_1 = eta1^+ eta1 and S_2 = eta2^+ eta2 at the start. */
+int oracle_hasen_heatbath(const int L[4], double kappa, double kappa2, const cplx *U, const cplx *eta2,
+                          cplx *phi2, double tol, int maxiter) {
+    long Vh = lat_volume(L) / 2;
+    cplx *a = malloc(sizeof(cplx) * 12 * Vh), *x = malloc(sizeof(cplx) * 12 * Vh);
+    oracle_mhat(L, kappa, U, eta2, a, 1);
+    int it = oracle_cg(L, kappa2, U, a, x, tol, maxiter, NULL);
+    oracle_mhat(L, kappa2, U, x, phi2, 0);
+    free(a); free(x);
+    return it;
+}
+
+/* S_2 value: Re chi^+ X2, X2 = (Mhat^+ Mhat)^-1 chi (returns X2 when asked) */
+double oracle_hasen_action(const int L[4], double kappa, double kappa2, const cplx *U, const cplx *phi2,
+                           double tol, int maxiter, cplx *X2out, int *iters) {
+    long Vh = lat_volume(L) / 2;
+    cplx *chi = malloc(sizeof(cplx) * 12 * Vh), *x = malloc(sizeof(cplx) * 12 * Vh);
+    oracle_mhat(L, kappa2, U, phi2, chi, 1);
+    int it = oracle_cg(L, kappa, U, chi, x, tol, maxiter, NULL);
+    if (iters) *iters = it;
+    double s = 0;
+    for (long k = 0; k < Vh; k++) s += vdot_re(12, chi + k * 12, x + k * 12);
+    if (X2out) memcpy(X2out, x, sizeof(cplx) * 12 * Vh);
+    free(chi); free(x);
+    return s;
+}
+
+/* Force of S_2 given X2 = (Mhat^+ Mhat)^-1 Mhat2^+ phi2:
+ *   dS_2 = 2 Re[(dMhat2^+ phi2)^+ X2] - X2^+ d(Mhat^+ Mhat) X2
+ * The second term is the ordinary pseudofermion force of X2 at kappa; the
+ * first is 2 Re[phi2^+ dMhat2 X2] = -2 kappa2^2 Re[Z^+ dD W] with W built from
+ * X2 and Z from phi2, i.e. force_xy_add(X2, phi2) with coef -kappa2^2.
+ * Added to F, scaled by `scale`. */
+void oracle_hasen_force_add(const int L[4], double kappa, double kappa2, const cplx *U, const cplx *phi2,
+                            const cplx *X2, double scale, double *F) {
+    oracle_fermion_force_add(L, kappa, U, X2, scale, F);
+    force_xy_add(L, U, X2, phi2, -scale * kappa2 * kappa2, F);
 }
 
 /* ------------------------------------------------------------------ */
@@ -799,6 +850,151 @@ int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, d
     free(K); free(W); free(XI); free(h0); free(h1); free(tmp); free(F); free(F2); free(Ud);
     free(phi); free(hf0); free(hf1);
     return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* nested (multi time scale) integrator with Hasenbusch terms          */
+/* ------------------------------------------------------------------ */
+
+#define TERM_GAUGE 1
+#define TERM_FERM 2   /* S_F, or S_1 when kappa2 != 0 */
+#define TERM_HASEN 4  /* S_2 */
+
+typedef struct {
+    const int *L;
+    double beta, kappa, kappa2, tol;
+    int maxiter, nlevels;
+    const int *nstages, *terms, *nsub;
+    const char *const *kinds;
+    const double *const *ws, *const *xis;
+    const cplx *phi1, *phi2;
+    cplx *U;
+    double *P;
+    oracle_stats st;
+} nested_run;
+
+static void count_solve(nested_run *r, int it) {
+    r->st.solves++;
+    if (it < 0) { r->st.cg_fail++; r->st.cg_iters += r->maxiter; } else r->st.cg_iters += it;
+}
+
+/* F = sum of the forces of the selected terms at links W */
+static void terms_force(nested_run *r, const cplx *W, int terms, double *F) {
+    const int *L = r->L;
+    long V = lat_volume(L), Vh = V / 2;
+    memset(F, 0, sizeof(double) * 4 * V * 8);
+    if (terms & TERM_GAUGE) {
+        double *g = malloc(sizeof(double) * 4 * V * 8);
+        oracle_gauge_force(L, r->beta, W, g);
+        for (long k = 0; k < 4 * V * 8; k++) F[k] += g[k];
+        free(g);
+    }
+    if (r->kappa == 0.0) return;
+    cplx *x = malloc(sizeof(cplx) * 12 * Vh);
+    if (terms & TERM_FERM) {
+        double k1 = r->kappa2 != 0.0 ? r->kappa2 : r->kappa;
+        count_solve(r, oracle_cg(L, k1, W, r->phi1, x, r->tol, r->maxiter, NULL));
+        oracle_fermion_force_add(L, k1, W, x, 1.0, F);
+    }
+    if ((terms & TERM_HASEN) && r->kappa2 != 0.0) {
+        int it;
+        oracle_hasen_action(L, r->kappa, r->kappa2, W, r->phi2, r->tol, r->maxiter, x, &it);
+        count_solve(r, it);
+        oracle_hasen_force_add(L, r->kappa, r->kappa2, W, r->phi2, x, 1.0, F);
+    }
+    free(x);
+}
+
+/* run level l for n steps of size h: the step table repeated n times with
+ * neighbouring P stages merged; a Q stage of an outer level runs the next
+ * level for w*h in nsub[l+1] steps; the innermost Q stage updates the links */
+static void run_level(nested_run *r, int l, int n, double h) {
+    const int *L = r->L;
+    long V = lat_volume(L);
+    int ns = r->nstages[l], tot = ns * n, m = 0;
+    char *K = malloc(tot);
+    double *Wt = malloc(sizeof(double) * tot), *XI = malloc(sizeof(double) * tot);
+    for (int s = 0; s < n; s++)
+        for (int k = 0; k < ns; k++) {
+            if (r->kinds[l][k] == 'P' && m > 0 && K[m - 1] == 'P') { Wt[m - 1] += r->ws[l][k]; continue; }
+            K[m] = r->kinds[l][k]; Wt[m] = r->ws[l][k]; XI[m] = r->xis[l][k]; m++;
+        }
+    double *F = malloc(sizeof(double) * 4 * V * 8);
+    cplx *Ud = malloc(sizeof(cplx) * 4 * V * 9);
+    for (int s = 0; s < m; s++) {
+        double w = Wt[s];
+        if (K[s] == 'P') {
+            terms_force(r, r->U, r->terms[l], F);
+            for (long k = 0; k < 4 * V * 8; k++) r->P[k] += w * h * F[k];
+        } else if (K[s] == 'Q') {
+            if (l + 1 < r->nlevels) run_level(r, l + 1, r->nsub[l + 1], w * h / r->nsub[l + 1]);
+            else oracle_link_update(L, w * h, r->P, r->U);
+        } else {
+            terms_force(r, r->U, r->terms[l], F);
+            memcpy(Ud, r->U, sizeof(cplx) * 4 * V * 9);
+            oracle_link_update(L, 2.0 * XI[s] / w * h * h, F, Ud);
+            terms_force(r, Ud, r->terms[l], F);
+            for (long k = 0; k < 4 * V * 8; k++) r->P[k] += w * h * F[k];
+        }
+    }
+    free(K); free(Wt); free(XI); free(F); free(Ud);
+}
+
+/* Nested trajectory (level 0 outermost, stage tables concatenated in `kinds`,
+ * `ws`, `xis` with nstages[l] entries per level).  Fermions: eta1 (S_F or
+ * S_1) and eta2 (S_2, when kappa2 != 0) are heatbath noises.  dH as a sum of
+ * per-site differences plus the fermion action differences. */
+int oracle_trajectory_nested(const int L[4], double beta, double kappa, double kappa2, double cg_tol,
+                             int cg_maxiter, int nlevels, const int *nstages, const int *terms, const int *nsub,
+                             const char *kinds, const double *ws, const double *xis, double tau, int nsteps,
+                             cplx *U, double *P, const cplx *eta1, const cplx *eta2, double *dH, long *stats3) {
+    long V = lat_volume(L), Vh = V / 2;
+    const char *kp[8];
+    const double *wp[8], *xp[8];
+    int off = 0;
+    for (int l = 0; l < nlevels && l < 8; l++) {
+        kp[l] = kinds + off; wp[l] = ws + off; xp[l] = xis + off;
+        off += nstages[l];
+    }
+    nested_run r = {L, beta, kappa, kappa2, cg_tol, cg_maxiter, nlevels, nstages, terms, nsub, kp, wp, xp,
+                    NULL, NULL, U, P, {0, 0, 0}};
+    cplx *phi1 = NULL, *phi2 = NULL;
+    double *h0 = malloc(sizeof(double) * V), *h1 = malloc(sizeof(double) * V), *tmp = malloc(sizeof(double) * V);
+    gauge_density(L, beta, U, h0);
+    kinetic_density(L, P, tmp);
+    for (long i = 0; i < V; i++) h0[i] += tmp[i];
+    double sf0 = 0.0;
+    if (kappa != 0.0) {
+        phi1 = malloc(sizeof(cplx) * 12 * Vh);
+        oracle_pf_heatbath(L, kappa2 != 0.0 ? kappa2 : kappa, U, eta1, phi1);
+        sf0 += vdot_re(12 * Vh, eta1, eta1);
+        if (kappa2 != 0.0) {
+            phi2 = malloc(sizeof(cplx) * 12 * Vh);
+            count_solve(&r, oracle_hasen_heatbath(L, kappa, kappa2, U, eta2, phi2, cg_tol, cg_maxiter));
+            sf0 += vdot_re(12 * Vh, eta2, eta2);
+        }
+    }
+    r.phi1 = phi1;
+    r.phi2 = phi2;
+    run_level(&r, 0, nsteps, tau / nsteps);
+    gauge_density(L, beta, U, h1);
+    kinetic_density(L, P, tmp);
+    double d = 0;
+    for (long i = 0; i < V; i++) d += (h1[i] + tmp[i]) - h0[i];
+    if (kappa != 0.0) {
+        int it;
+        double s1 = oracle_pf_action(L, kappa2 != 0.0 ? kappa2 : kappa, U, phi1, cg_tol, cg_maxiter, &it);
+        count_solve(&r, it);
+        if (kappa2 != 0.0) {
+            s1 += oracle_hasen_action(L, kappa, kappa2, U, phi2, cg_tol, cg_maxiter, NULL, &it);
+            count_solve(&r, it);
+        }
+        d += s1 - sf0;
+    }
+    *dH = d;
+    if (stats3) { stats3[0] = r.st.solves; stats3[1] = r.st.cg_iters; stats3[2] = r.st.cg_fail; }
+    free(phi1); free(phi2); free(h0); free(h1); free(tmp);
+    return r.st.cg_fail ? -3 : 0;
 }
 
 /* Poisson brackets of Section 3 at (U, P):

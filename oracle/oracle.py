@@ -79,6 +79,14 @@ def _declare(L):
                                     _d, _i, _vp, _vp, _vp, _vp, _dp, _lp]
     L.oracle_trajectory.restype = _i
     L.oracle_brackets.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _d, _dp, _dp]
+    L.oracle_hasen_heatbath.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _d, _i]
+    L.oracle_hasen_heatbath.restype = _i
+    L.oracle_hasen_action.argtypes = [_ip, _d, _d, _vp, _vp, _d, _i, _vp, _ip]
+    L.oracle_hasen_action.restype = _d
+    L.oracle_hasen_force_add.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _d, _vp]
+    L.oracle_trajectory_nested.argtypes = [_ip, _d, _d, _d, _d, _i, _i, _vp, _vp, _vp, ctypes.c_char_p, _vp, _vp,
+                                           _d, _i, _vp, _vp, _vp, _vp, _dp, _lp]
+    L.oracle_trajectory_nested.restype = _i
 
 
 def _dims(dims):
@@ -267,6 +275,57 @@ def brackets(dims, beta, U, P, kappa=0.0, phi=None, h=1e-4, tol=1e-14, maxiter=1
     lib().oracle_brackets(_dims(dims), beta, kappa, int(ferm), tol, maxiter, _ptr(U), _ptr(P),
                           _ptr(phi_a) if ferm else None, h, ctypes.byref(sst), ctypes.byref(tst))
     return sst.value, tst.value
+
+
+def hasen_heatbath(dims, kappa, kappa2, U, eta2, tol=1e-14, maxiter=10000):
+    """phi2 = Mhat2 (Mhat2^+ Mhat2)^-1 Mhat^+ eta2 (Mhat2 at kappa2)"""
+    U = _c(U, np.complex128)
+    eta2 = _c(eta2, np.complex128)
+    phi2 = np.zeros_like(eta2)
+    lib().oracle_hasen_heatbath(_dims(dims), kappa, kappa2, _ptr(U), _ptr(eta2), _ptr(phi2), tol, maxiter)
+    return phi2
+
+
+def hasen_action(dims, kappa, kappa2, U, phi2, tol=1e-14, maxiter=10000):
+    """(S_2, X2) with S_2 = chi^+ (Mhat^+ Mhat)^-1 chi, chi = Mhat2^+ phi2"""
+    U = _c(U, np.complex128)
+    phi2 = _c(phi2, np.complex128)
+    X2 = np.zeros_like(phi2)
+    it = ctypes.c_int(0)
+    s = lib().oracle_hasen_action(_dims(dims), kappa, kappa2, _ptr(U), _ptr(phi2), tol, maxiter, _ptr(X2),
+                                  ctypes.byref(it))
+    return s, X2
+
+
+def hasen_force(dims, kappa, kappa2, U, phi2, X2):
+    U = _c(U, np.complex128)
+    F = np.zeros((4, volume(dims), 8))
+    lib().oracle_hasen_force_add(_dims(dims), kappa, kappa2, _ptr(U), _ptr(_c(phi2, np.complex128)),
+                                 _ptr(_c(X2, np.complex128)), 1.0, _ptr(F))
+    return F
+
+
+def trajectory_nested(dims, beta, levels, tau, nsteps, U, P, kappa=0.0, kappa2=0.0, eta1=None, eta2=None,
+                      tol=1e-14, maxiter=10000):
+    """levels: list of (stages, terms, nsub), level 0 outermost; terms bit 1 gauge,
+    2 S_F (or S_1 with Hasenbusch), 4 S_2.  Returns (U, P, dH, stats, status)."""
+    U = np.array(U, dtype=np.complex128, copy=True, order="C")
+    P = np.array(P, dtype=np.float64, copy=True, order="C")
+    ns = np.array([len(l[0]) for l in levels], np.int32)
+    terms = np.array([l[1] for l in levels], np.int32)
+    nsub = np.array([l[2] for l in levels], np.int32)
+    kinds = "".join(s[0] for l in levels for s in l[0]).encode()
+    ws = np.array([s[1] for l in levels for s in l[0]], np.float64)
+    xis = np.array([s[2] if len(s) > 2 else 0.0 for l in levels for s in l[0]], np.float64)
+    dH = ctypes.c_double(0)
+    st = (ctypes.c_long * 3)()
+    e1 = _c(eta1, np.complex128) if eta1 is not None else None
+    e2 = _c(eta2, np.complex128) if eta2 is not None else None
+    status = lib().oracle_trajectory_nested(_dims(dims), beta, kappa, kappa2, tol, maxiter, len(levels), _ptr(ns),
+                                            _ptr(terms), _ptr(nsub), kinds, _ptr(ws), _ptr(xis), tau, nsteps,
+                                            _ptr(U), _ptr(P), _ptr(e1) if e1 is not None else None,
+                                            _ptr(e2) if e2 is not None else None, ctypes.byref(dH), st)
+    return U, P, dH.value, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2]), status
 
 
 # ---------------------------------------------------------------------------

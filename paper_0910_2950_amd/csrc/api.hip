@@ -138,9 +138,10 @@ struct Fields {
     void* Uds = nullptr;
     double* P = nullptr;
     double* F = nullptr;  // force scratch
-    d2* phi[2] = {nullptr, nullptr};
-    d2* X = nullptr;
-    d2* W = nullptr;      // second solution vector (Hasenbusch)
+    d2* phi[2] = {nullptr, nullptr};  // S_F (or S_1) and the Hasenbusch ratio term S_2
+    d2* X = nullptr;      // solution of the S_F / S_1 solve
+    d2* X2 = nullptr;     // solution of the S_2 solve
+    d2* chi = nullptr;    // Mhat2^+ phi2
     int sp, rc;
     bool nonconv = false;
     fgi_stats* st = nullptr;
@@ -177,14 +178,54 @@ struct Fields {
             return;
         }
         if (!have) zero_mom(out);
-        if (act.kappa_hasen == 0.0) {
-            if (terms & FGI_TERM_FERMION) {
-                solve(u, us, act.kappa, phi[0], X);
-                fermion_force(c, op64(u, act.kappa), X, out, coef);
-            }
-        } else {
-            throw Error(FGI_EINVAL, "Hasenbusch terms are not available in this build");
+        const double k1 = act.kappa_hasen != 0.0 ? act.kappa_hasen : act.kappa;
+        if (terms & FGI_TERM_FERMION) {
+            solve(u, us, k1, phi[0], X);
+            fermion_force(c, op64(u, k1), X, out, coef);
         }
+        if ((terms & FGI_TERM_HASEN) && act.kappa_hasen != 0.0) {
+            // S_2 = chi^+ (Mhat^+ Mhat)^-1 chi, chi = Mhat2^+ phi2: the ordinary force
+            // of X2 at kappa plus -kappa2^2 TA(U C(X2, phi2)) from the U dependence of chi
+            hasen_solve(u, us);
+            fermion_force(c, op64(u, act.kappa), X2, out, coef);
+            fermion_force_xy(c, op64(u, act.kappa_hasen), X2, phi[1], out,
+                             -coef * act.kappa_hasen * act.kappa_hasen);
+        }
+    }
+
+    // chi = Mhat2^+ phi2 at u; X2 = (Mhat^+ Mhat)^-1 chi
+    void hasen_solve(const d2* u, const void* us) {
+        d2* t = (d2*)c.tmp_o.get(spinor_bytes(g));
+        mhat(c, op64(u, act.kappa_hasen), P64, SpinorPtr{phi[1], nullptr}, SpinorPtr{t, nullptr},
+             SpinorPtr{chi, nullptr}, 1);
+        solve(u, us, act.kappa, chi, X2);
+    }
+
+    // phi2 = Mhat2 (Mhat2^+ Mhat2)^-1 Mhat^+ eta2 at u (one solve at kappa2)
+    void hasen_heatbath(const d2* u, const void* us, const d2* eta2) {
+        d2* t = (d2*)c.tmp_o.get(spinor_bytes(g));
+        mhat(c, op64(u, act.kappa), P64, SpinorPtr{(void*)eta2, nullptr}, SpinorPtr{t, nullptr},
+             SpinorPtr{chi, nullptr}, 1);
+        solve(u, us, act.kappa_hasen, chi, X2);
+        mhat(c, op64(u, act.kappa_hasen), P64, SpinorPtr{X2, nullptr}, SpinorPtr{t, nullptr},
+             SpinorPtr{phi[1], nullptr}, 0);
+    }
+
+    // sum over the pseudofermion terms of Re phi^+ X - |eta|^2 (eta may be null):
+    // the fermion part of H at u minus its heatbath value
+    double pf_energy(const d2* u, const void* us, const d2* eta1, const d2* eta2, double* part, double* scal) {
+        const double k1 = act.kappa_hasen != 0.0 ? act.kappa_hasen : act.kappa;
+        solve(u, us, k1, phi[0], X);
+        int nb = pf_density_partials(c, g, phi[0], X, eta1, part);
+        final_sum(c, part, nb, scal + 4);
+        double e = sync_scalar(c, scal + 4, 4);
+        if (act.kappa_hasen != 0.0) {
+            hasen_solve(u, us);
+            nb = pf_density_partials(c, g, chi, X2, eta2, part);
+            final_sum(c, part, nb, scal + 5);
+            e += sync_scalar(c, scal + 5, 5);
+        }
+        return e;
     }
 
     void zero_mom(double* out) { zero_doubles(c, out, mom_bytes(g) / sizeof(double)); }
@@ -347,6 +388,26 @@ int fgi_force_gradient(fgi_ctx* ctx, const fgi_geom* gg, double beta, const void
         pack_mom(c, g, (const double*)Vd, v);
         gauge_force_tangent(c, g, beta, u, v, j, 1.0, 0);
         unpack_mom(c, g, j, (double*)J);
+    });
+}
+
+int fgi_gauge_hvp(fgi_ctx* ctx, const fgi_geom* gg, double beta, const void* U, const void* Vd, void* HV,
+                  void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(Vd, "V", 8);
+        need(HV, "HV", 8);
+        StreamScope ss(c, stream);
+        d2* u = (d2*)c.gauge.get(gauge_bytes(g));
+        double* v = (double*)c.force2.get(mom_bytes(g));
+        double* j = (double*)c.force.get(mom_bytes(g));
+        pack_gauge(c, g, U, u);
+        pack_mom(c, g, (const double*)Vd, v);
+        gauge_force_tangent(c, g, beta, u, v, j, 1.0, 0, 1);
+        unpack_mom(c, g, j, (double*)HV);
     });
 }
 
@@ -582,6 +643,100 @@ int fgi_fermion_force(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, c
     });
 }
 
+// prepare a Fields object with packed links (and sloppy copy) for the fermion entry points
+namespace {
+void setup_fermion_fields(Ctx& c, Fields& f, const Geom& g, const void* U) {
+    f.U = (d2*)c.gauge.get(gauge_bytes(g));
+    pack_gauge(c, g, U, f.U);
+    if (f.sp != P64) {
+        f.Us = c.sloppy.get(sloppy_bytes(g));
+        make_sloppy(c, g, f.U, f.Us, f.sp, f.rc);
+    }
+    f.phi[0] = (d2*)c.phi.get(spinor_bytes(g));
+    f.phi[1] = (d2*)c.phi2.get(spinor_bytes(g));
+    f.X = (d2*)c.X.get(spinor_bytes(g));
+    f.X2 = (d2*)c.X2.get(spinor_bytes(g));
+    f.chi = (d2*)c.chi.get(spinor_bytes(g));
+}
+void check_hasen(const fgi_action* act) {
+    check_action(act);
+    if (act->kappa == 0 || act->kappa_hasen == 0) throw Error(FGI_EINVAL, "needs kappa and kappa_hasen");
+}
+}  // namespace
+
+int fgi_hasen_heatbath(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* eta2,
+                       void* phi2, fgi_stats* st, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        check_hasen(act);
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(eta2, "eta2", 16);
+        need(phi2, "phi2", 16);
+        StreamScope ss(c, stream);
+        Fields f(c, g, *act);
+        f.st = st;
+        setup_fermion_fields(c, f, g, U);
+        d2* e = (d2*)c.eta2.get(spinor_bytes(g));
+        pack_even_spinor(c, g, eta2, e);
+        f.hasen_heatbath(f.U, f.Us, e);
+        unpack_even_spinor(c, g, f.phi[1], phi2);
+        FGI_HIP(hipStreamSynchronize(c.stream));
+        if (f.nonconv) throw Error(FGI_ENOCONV, "CG reached cg_maxiter");
+    });
+}
+
+int fgi_hasen_action(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* phi2,
+                     double* S2, fgi_stats* st, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg || !S2) throw Error(FGI_EINVAL, "null argument");
+        check_hasen(act);
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(phi2, "phi2", 16);
+        StreamScope ss(c, stream);
+        Fields f(c, g, *act);
+        f.st = st;
+        setup_fermion_fields(c, f, g, U);
+        pack_even_spinor(c, g, phi2, f.phi[1]);
+        f.hasen_solve(f.U, f.Us);
+        double* part = (double*)c.partial.get(sizeof(double) * 65536);
+        double* scal = (double*)c.scal.get(sizeof(double) * 64);
+        int nb = pf_density_partials(c, g, f.chi, f.X2, nullptr, part);
+        final_sum(c, part, nb, scal);
+        *S2 = sync_scalar(c, scal, 0);
+        if (f.nonconv) throw Error(FGI_ENOCONV, "CG reached cg_maxiter");
+    });
+}
+
+int fgi_force_terms(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* phi1,
+                    const void* phi2, int terms, void* F, fgi_stats* st, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        check_action(act);
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(F, "F", 8);
+        if (terms & ~(FGI_TERM_GAUGE | FGI_TERM_FERMION | FGI_TERM_HASEN)) throw Error(FGI_EINVAL, "bad term mask");
+        if (act->kappa != 0 && (terms & FGI_TERM_FERMION)) need(phi1, "phi1", 16);
+        if (act->kappa_hasen != 0 && (terms & FGI_TERM_HASEN)) need(phi2, "phi2", 16);
+        StreamScope ss(c, stream);
+        Fields f(c, g, *act);
+        f.st = st;
+        setup_fermion_fields(c, f, g, U);
+        if (phi1) pack_even_spinor(c, g, phi1, f.phi[0]);
+        if (phi2) pack_even_spinor(c, g, phi2, f.phi[1]);
+        double* fm = (double*)c.force.get(mom_bytes(g));
+        f.force(f.U, f.Us, terms, fm, 1.0, false);
+        unpack_mom(c, g, fm, (double*)F);
+        FGI_HIP(hipStreamSynchronize(c.stream));
+        if (f.nonconv) throw Error(FGI_ENOCONV, "CG reached cg_maxiter");
+    });
+}
+
 int fgi_poisson_brackets(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* P,
                          const void* phi, double h, double* SST, double* TST, fgi_stats* st, void* stream) {
     return guarded([&] {
@@ -773,8 +928,9 @@ extern "C" int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action
         need(U, "U", 16);
         need(P, "P", 8);
         const bool ferm = act->kappa != 0.0;
+        const bool hasen = act->kappa_hasen != 0.0;
         if (ferm) need(eta1, "eta1", 16);
-        if (act->kappa_hasen != 0.0) throw Error(FGI_EINVAL, "Hasenbusch terms are not available in this build");
+        if (hasen) need(eta2, "eta2", 16);
         auto t0 = std::chrono::steady_clock::now();
         StreamScope ss(c, stream);
         Fields f(c, g, *act);
@@ -794,21 +950,30 @@ extern "C" int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action
         double* h1 = (double*)c.hf0.get(sizeof(double) * g.V);
         double* part = (double*)c.partial.get(sizeof(double) * 65536);
         double* scal = (double*)c.scal.get(sizeof(double) * 64);
-        d2* eta = nullptr;
+        d2 *eta = nullptr, *eta_2 = nullptr;
         double sf0 = 0.0;
         if (ferm) {
             f.phi[0] = (d2*)c.phi.get(spinor_bytes(g));
             f.X = (d2*)c.X.get(spinor_bytes(g));
+            if (hasen) {
+                f.phi[1] = (d2*)c.phi2.get(spinor_bytes(g));
+                f.X2 = (d2*)c.X2.get(spinor_bytes(g));
+                f.chi = (d2*)c.chi.get(spinor_bytes(g));
+            }
+            const double k1 = hasen ? act->kappa_hasen : act->kappa;
             if (pf_is_phi) {
                 pack_even_spinor(c, g, eta1, f.phi[0]);
-                f.solve(f.U, f.Us, act->kappa, f.phi[0], f.X);
-                int nb = pf_density_partials(c, g, f.phi[0], f.X, nullptr, part);
-                final_sum(c, part, nb, scal + 2);
-                sf0 = sync_scalar(c, scal + 2, 2);
+                if (hasen) pack_even_spinor(c, g, eta2, f.phi[1]);
+                sf0 = f.pf_energy(f.U, f.Us, nullptr, nullptr, part, scal);
             } else {
                 eta = (d2*)c.eta.get(spinor_bytes(g));
                 pack_even_spinor(c, g, eta1, eta);
-                pf_heatbath(c, f.op64(f.U, act->kappa), eta, f.phi[0]);
+                pf_heatbath(c, f.op64(f.U, k1), eta, f.phi[0]);
+                if (hasen) {
+                    eta_2 = (d2*)c.eta2.get(spinor_bytes(g));
+                    pack_even_spinor(c, g, eta2, eta_2);
+                    f.hasen_heatbath(f.U, f.Us, eta_2);
+                }
             }
         }
         ham_density(c, g, act->beta, f.U, f.P, h0);
@@ -820,12 +985,7 @@ extern "C" int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action
         int nb = diff_partials(c, g.V, h1, h0, part);
         final_sum(c, part, nb, scal);
         double dh = sync_scalar(c, scal, 0);
-        if (ferm) {
-            f.solve(f.U, f.Us, act->kappa, f.phi[0], f.X);
-            nb = pf_density_partials(c, g, f.phi[0], f.X, eta, part);
-            final_sum(c, part, nb, scal + 1);
-            dh += sync_scalar(c, scal + 1, 1) - sf0;
-        }
+        if (ferm) dh += f.pf_energy(f.U, f.Us, eta, eta_2, part, scal) - sf0;
         unpack_gauge(c, g, f.U, U);
         unpack_mom(c, g, f.P, (double*)P);
         FGI_HIP(hipStreamSynchronize(c.stream));

@@ -665,15 +665,14 @@ int pf_density_partials(Ctx& c, const Geom& g, const d2* phi, const d2* X, const
     return nb;
 }
 
-void fermion_force(Ctx& c, const FermionOp& op64, const d2* Xe, double* F, double coef) {
+// F += coef * TA(U C(X, Y)) with X = (X_e, D_oe X_e), Y = (Y_e, g5 D_oe g5 Y_e):
+// the derivative -d/dt of 2 Re[Y^+ D X] / 2 per link (coef carries the kappas)
+void fermion_force_xy(Ctx& c, const FermionOp& op64, const d2* Xe, const d2* Ye, double* F, double coef) {
     const Geom& g = *op64.g;
     size_t n = sizeof(d2) * 12 * (size_t)g.Vh;
     d2* Xo = (d2*)c.Xo.get(n);
-    d2* Ye = (d2*)c.Ye.get(n);
     d2* Yo = (d2*)c.Yo.get(n);
-    d2* t = (d2*)c.tmp_o.get(n);
     dslash(c, op64, 1, P64, sp(Xe), P64, sp(Xo));          // X_o = D_oe X_e
-    mhat(c, op64, P64, sp(Xe), sp(t), sp(Ye), 0);          // Y_e = Mhat X_e
     {                                                       // Y_o = g5 D_oe g5 Y_e
         DArgs a = base_args(op64, 1);
         a.in = sp(Ye);
@@ -682,8 +681,18 @@ void fermion_force(Ctx& c, const FermionOp& op64, const d2* Xe, double* F, doubl
         launch_dslash<M_HOP, P64, P64, P64, P64, 1>(c, op64, a);
     }
     hipLaunchKernelGGL(k_fermion_force, dim3(nblk(g.V, 256)), dim3(256), 0, c.stream, g, (const d2*)op64.links, sp(Xe),
-                       sp(Xo), sp(Ye), sp(Yo), coef * op64.kappa * op64.kappa, F);
+                       sp(Xo), sp(Ye), sp(Yo), coef, F);
     FGI_LAUNCH_CHECK();
+}
+
+// pseudofermion force of phi^+ (Mhat^+ Mhat)^-1 phi at op64.kappa: Y_e = Mhat X_e
+void fermion_force(Ctx& c, const FermionOp& op64, const d2* Xe, double* F, double coef) {
+    const Geom& g = *op64.g;
+    size_t n = sizeof(d2) * 12 * (size_t)g.Vh;
+    d2* Ye = (d2*)c.Ye.get(n);
+    d2* t = (d2*)c.tmp_o.get(n);
+    mhat(c, op64, P64, sp(Xe), sp(t), sp(Ye), 0);
+    fermion_force_xy(c, op64, Xe, Ye, F, coef * op64.kappa * op64.kappa);
 }
 
 // ---------------------------------------------------------------- CG ------

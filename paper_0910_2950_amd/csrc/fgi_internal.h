@@ -71,7 +71,7 @@ struct Ctx {
     DevBuf eta, phi, X, Xo, Ye, Yo, tmp_e, tmp_o, cg_r, cg_p, cg_q;
     DevBuf s_x, s_r, s_p, s_q, s_t, s_norms;
     DevBuf h0, hf0, partial, scal, state;
-    DevBuf phi2, eta2, user_tmp, aux;
+    DevBuf phi2, eta2, user_tmp, aux, chi, X2;
     double* host_scal = nullptr;   // pinned, 64 doubles
     CGState* host_state = nullptr; // pinned
     int* host_aux = nullptr;       // pinned (persistent-solver error flag)
@@ -114,9 +114,10 @@ int diff_partials(Ctx&, int n, const double* h1, const double* h0, double* parti
 void final_sum(Ctx&, const double* partial, int n, double* out);
 // F_G into F: mode 0: F = c * F_G; 1: F += c * F_G
 void gauge_force(Ctx&, const Geom&, double beta, const d2* U, double* F, double c, int accumulate);
-// J = c * d/dt F_G(exp(t V) U) (+ J when accumulate)
+// mode 0: J = c * d/dt F_G(exp(t V) U); mode 1: J = c * (-J_V[F_G] + [V, F_G]/2),
+// the Hessian of S_G in the chart exp(omega) U at omega = 0 applied to V (+ J when accumulate)
 void gauge_force_tangent(Ctx&, const Geom&, double beta, const d2* U, const double* Vd, double* J,
-                         double c, int accumulate);
+                         double c, int accumulate, int mode = 0);
 // dst = exp(h X) src on every link; sloppy copy of dst written when sloppy != null
 void link_update(Ctx&, const Geom&, double h, const double* X, const d2* src, d2* dst, void* sloppy,
                  int prec, int recon);
@@ -157,6 +158,8 @@ CGResult cg_solve(Ctx&, const FermionOp& op64, const FermionOp& ops, int sprec, 
 void pf_heatbath(Ctx&, const FermionOp& op64, const d2* eta, d2* phi);
 // F += c * F_F(X_e) (pseudofermion force given the solution X_e)
 void fermion_force(Ctx&, const FermionOp& op64, const d2* Xe, double* F, double c);
+// F += coef * TA(U C(X, Y)), X = (X_e, D_oe X_e), Y = (Y_e, g5 D_oe g5 Y_e)
+void fermion_force_xy(Ctx&, const FermionOp& op64, const d2* Xe, const d2* Ye, double* F, double coef);
 // partials of Re phi^+ X - |eta|^2 (eta may be null) per even site; returns nblocks
 int pf_density_partials(Ctx&, const Geom&, const d2* phi, const d2* X, const d2* eta, double* partial);
 // for the Hasenbusch pair: out = Mhat(kappa2)^+ in etc. use mhat with another op

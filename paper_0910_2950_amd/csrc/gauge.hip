@@ -246,9 +246,12 @@ __device__ __forceinline__ M3<double> valg(const double* Vd, int mu, int p, int 
     return alg_matrix(x);
 }
 
+// mode 0: J = coef * d/dt F_G(exp(tV) U)
+// mode 1: J = coef * (Hessian of S_G in the chart exp(omega) U at omega = 0) V
+//         = coef * (-J_V[F_G] + [V, F_G] / 2)   (per link commutator)
 __global__ void __launch_bounds__(256) k_gauge_tangent(Geom g, double beta, const d2* __restrict__ U,
                                                       const double* __restrict__ Vd, double* __restrict__ J,
-                                                      double coef, int accumulate) {
+                                                      double coef, int accumulate, int mode) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 4 * g.V) return;
     int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
@@ -291,24 +294,46 @@ __global__ void __launch_bounds__(256) k_gauge_tangent(Geom g, double beta, cons
         }
     }
     M3<double> u = gauge_load(U, mu, p, s, g.Vh);
-    M3<double> du = m3_mul(valg(Vd, mu, p, s, g.Vh), u);
+    M3<double> vl = valg(Vd, mu, p, s, g.Vh);
+    M3<double> du = m3_mul(vl, u);
     M3<double> dW = m3_mul(du, A);
     m3_acc(dW, m3_mul(u, dA));
     double x[8];
     ta_components(dW, x);
     double* o = J + (size_t)(r * 8) * g.Vh + s;
-    double f = -beta / 6.0 * coef;
+    const double f = -beta / 6.0;
+    if (mode == 1) {
+        // F = f TA(U A) as a matrix; [V, F] components
+        double fx[8];
+        ta_components(m3_mul(u, A), fx);
+#pragma unroll
+        for (int a = 0; a < 8; a++) fx[a] *= f;
+        M3<double> Fm = alg_matrix(fx);
+        M3<double> C = m3_mul(vl, Fm);
+        M3<double> D = m3_mul(Fm, vl);
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) C.e[i][j] = C.e[i][j] - D.e[i][j];
+        double cx8[8];
+        ta_components(C, cx8);
+#pragma unroll
+        for (int a = 0; a < 8; a++) x[a] = -f * x[a] + 0.5 * cx8[a];
+    } else {
+#pragma unroll
+        for (int a = 0; a < 8; a++) x[a] = f * x[a];
+    }
 #pragma unroll
     for (int a = 0; a < 8; a++) {
-        double v = f * x[a];
+        double v = coef * x[a];
         o[(size_t)a * g.Vh] = accumulate ? o[(size_t)a * g.Vh] + v : v;
     }
 }
 
 void gauge_force_tangent(Ctx& c, const Geom& g, double beta, const d2* U, const double* Vd, double* J, double coef,
-                         int accumulate) {
+                         int accumulate, int mode) {
     hipLaunchKernelGGL(k_gauge_tangent, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, beta, U, Vd, J, coef,
-                       accumulate);
+                       accumulate, mode);
     FGI_LAUNCH_CHECK();
 }
 

@@ -78,6 +78,10 @@ SIGNATURES = {
     "fgi_kinetic": (_i, [_vp, _P(fgi_geom), _vp, _P(_d), _vp]),
     "fgi_gauge_force": (_i, [_vp, _P(fgi_geom), _d, _vp, _vp, _vp]),
     "fgi_force_gradient": (_i, [_vp, _P(fgi_geom), _d, _vp, _vp, _vp, _vp]),
+    "fgi_gauge_hvp": (_i, [_vp, _P(fgi_geom), _d, _vp, _vp, _vp, _vp]),
+    "fgi_hasen_heatbath": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _P(fgi_stats), _vp]),
+    "fgi_hasen_action": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _P(_d), _P(fgi_stats), _vp]),
+    "fgi_force_terms": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _i, _vp, _P(fgi_stats), _vp]),
     "fgi_force": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _P(fgi_stats), _vp]),
     "fgi_fermion_force": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _vp]),
     "fgi_dslash": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _i, _i, _vp]),
@@ -251,6 +255,13 @@ class Context:
                                         _stream()))
         return J
 
+    def gauge_hvp(self, dims, beta, U, V, HV=None):
+        su, sp, _ = self._shapes(dims)
+        HV = torch.empty(sp, dtype=torch.float64, device=U.device) if HV is None else HV
+        _check(lib().fgi_gauge_hvp(self.h, _geom(dims), beta, _ptr(U, torch.complex128, su, "U"),
+                                   _ptr(V, torch.float64, sp, "V"), _ptr(HV, torch.float64, sp, "HV"), _stream()))
+        return HV
+
     def force(self, dims, act, U, phi=None, F=None, allow_noconv=False):
         su, sp, se = self._shapes(dims)
         F = torch.empty(sp, dtype=torch.float64, device=U.device) if F is None else F
@@ -258,6 +269,33 @@ class Context:
         _check(lib().fgi_force(self.h, _geom(dims), ctypes.byref(act.c()), _ptr(U, torch.complex128, su, "U"),
                                _ptr(phi, torch.complex128, se, "phi"), _ptr(F, torch.float64, sp, "F"),
                                ctypes.byref(st), _stream()), (FGI_ENOCONV,) if allow_noconv else ())
+        return F, st.as_dict()
+
+    def hasen_heatbath(self, dims, act, U, eta2):
+        su, _, se = self._shapes(dims)
+        phi2 = torch.empty(se, dtype=torch.complex128, device=U.device)
+        st = fgi_stats()
+        _check(lib().fgi_hasen_heatbath(self.h, _geom(dims), ctypes.byref(act.c()), _ptr(U, torch.complex128, su, "U"),
+                                        _ptr(eta2, torch.complex128, se, "eta2"), _ptr(phi2, torch.complex128, se, "phi2"),
+                                        ctypes.byref(st), _stream()))
+        return phi2
+
+    def hasen_action(self, dims, act, U, phi2):
+        su, _, se = self._shapes(dims)
+        S = ctypes.c_double()
+        st = fgi_stats()
+        _check(lib().fgi_hasen_action(self.h, _geom(dims), ctypes.byref(act.c()), _ptr(U, torch.complex128, su, "U"),
+                                      _ptr(phi2, torch.complex128, se, "phi2"), ctypes.byref(S), ctypes.byref(st),
+                                      _stream()))
+        return S.value
+
+    def force_terms(self, dims, act, U, phi1, phi2, terms):
+        su, sp, se = self._shapes(dims)
+        F = torch.empty(sp, dtype=torch.float64, device=U.device)
+        st = fgi_stats()
+        _check(lib().fgi_force_terms(self.h, _geom(dims), ctypes.byref(act.c()), _ptr(U, torch.complex128, su, "U"),
+                                     _ptr(phi1, torch.complex128, se, "phi1"), _ptr(phi2, torch.complex128, se, "phi2"),
+                                     int(terms), _ptr(F, torch.float64, sp, "F"), ctypes.byref(st), _stream()))
         return F, st.as_dict()
 
     def fermion_force(self, dims, act, U, X, F=None):
