@@ -243,6 +243,30 @@ int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const
                    int nsteps, void* U, void* P, const void* eta1, const void* eta2, int pf_is_phi, double* dH,
                    fgi_stats* st, void* stream);
 
+/* ------------------------------------------------ batched chains
+ * Many independent chains of different lattice sizes and couplings advanced
+ * together: every MD sub-step is one set of kernel launches covering all
+ * chains (each chain keeps its own geometry, beta, kappa and CG state, and
+ * stops its solves on its own).  Chain buffers are caller-owned device
+ * memory in the user layouts above.  The action supplies the precision and
+ * CG settings (its beta and kappa are ignored); either every chain has
+ * fermions (kappa != 0) or none; one pseudofermion per chain. */
+typedef struct {
+    int dims[4];
+    int pad;
+    double beta;
+    double kappa;
+    void* U;          /* links, updated in place */
+    void* P;          /* momenta, updated in place */
+    const void* eta;  /* pseudofermion heatbath noise (even sites) */
+} fgi_chain;
+
+/* One trajectory of every chain with the same integrator, tau and nsteps;
+ * dH[i] = H_i(end) - H_i(start).  Synchronises the stream. */
+int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain* chains, const fgi_action* act,
+                           const fgi_integrator* integ, double tau, int nsteps, double* dH, fgi_stats* st,
+                           void* stream);
+
 /* --------------------------------------------------------- utilities */
 /* U <- exp(h P) U on every link (exact su(3) exponential). */
 int fgi_link_update(fgi_ctx* ctx, const fgi_geom* g, double h, const void* P, void* U, void* stream);

@@ -266,7 +266,8 @@ int fgi_destroy(fgi_ctx* ctx) {
         DevBuf* bufs[] = {&c.gauge, &c.gauge_disp, &c.sloppy, &c.sloppy_disp, &c.mom, &c.force, &c.force2,
                           &c.scratch_mom, &c.eta, &c.phi, &c.X, &c.Xo, &c.Ye, &c.Yo, &c.tmp_e, &c.tmp_o,
                           &c.cg_r, &c.cg_p, &c.cg_q, &c.s_x, &c.s_r, &c.s_p, &c.s_q, &c.s_t, &c.s_norms,
-                          &c.h0, &c.hf0, &c.partial, &c.scal, &c.state, &c.phi2, &c.eta2, &c.user_tmp, &c.aux};
+                          &c.h0, &c.hf0, &c.partial, &c.scal, &c.state, &c.phi2, &c.eta2, &c.user_tmp, &c.aux,
+                          &c.chi, &c.X2, &c.cdesc, &c.bstate, &c.bscal, &c.bh0, &c.bh1, &c.bres};
         for (DevBuf* b : bufs) b->release();
         for (hipEvent_t e : c.ev_pool) hipEventDestroy(e);
         for (GraphEntry& e : c.graphs) hipGraphExecDestroy(e.exec);
@@ -274,6 +275,8 @@ int fgi_destroy(fgi_ctx* ctx) {
         if (c.host_scal) hipHostFree(c.host_scal);
         if (c.host_state) hipHostFree(c.host_state);
         if (c.host_aux) hipHostFree(c.host_aux);
+        if (c.host_bstates) hipHostFree(c.host_bstates);
+        if (c.host_bscal) hipHostFree(c.host_bscal);
         delete ctx;
     });
 }
@@ -992,6 +995,189 @@ extern "C" int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action
         *dH = dh;
         if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (!std::isfinite(dh)) throw Error(FGI_ENONFINITE, "dH is not finite");
+        if (f.nonconv) throw Error(FGI_ENOCONV, "a CG solve reached cg_maxiter");
+    });
+}
+
+// ==========================================================================
+// batched independent chains
+// ==========================================================================
+namespace {
+
+struct BFields {
+    Ctx& c;
+    Batch B;
+    fgi_action act;
+    int sp, rc;
+    d2 *U = nullptr, *Ud = nullptr;
+    void *Us = nullptr, *Uds = nullptr;
+    double *P = nullptr, *F = nullptr;
+    d2 *phi = nullptr, *X = nullptr;
+    bool fermions = false, nonconv = false;
+    fgi_stats* st = nullptr;
+
+    BFields(Ctx& cc, const fgi_action& a) : c(cc), act(a) {
+        sp = sloppy_prec(&act);
+        rc = sloppy_recon(&act);
+    }
+    FermionOp op64(const d2* u) const { return FermionOp{nullptr, 0.0, u, P64, 18}; }
+    FermionOp ops(const d2* u, const void* us) const {
+        if (sp == P64) return op64(u);
+        return FermionOp{nullptr, 0.0, us, sp, rc};
+    }
+    void solve(const d2* u, const void* us, const d2* rhs, d2* x) {
+        std::vector<CGResult> r = cg_solve_b(c, B, op64(u), ops(u, us), sp, rhs, x, act.cg_tol, act.cg_maxiter);
+        for (const CGResult& q : r) {
+            accumulate_stats(st, q);
+            if (!q.converged) nonconv = true;
+        }
+    }
+    void force(const d2* u, const void* us, int terms, double* out, double coef, bool accumulate) {
+        bool have = accumulate;
+        if (st) st->force_evals++;
+        if (terms & FGI_TERM_GAUGE) {
+            gauge_force_b(c, B, u, out, coef, have ? 1 : 0);
+            have = true;
+        }
+        if (!have) zero_doubles(c, out, 8 * (size_t)B.links);
+        if (fermions && (terms & FGI_TERM_FERMION)) {
+            solve(u, us, phi, X);
+            fermion_force_b(c, B, op64(u), X, out, coef);
+        }
+    }
+};
+
+struct BDriver {
+    BFields& f;
+    const fgi_integrator& I;
+    void run(int l, int n, double h) {
+        const fgi_level& L = I.lev[l];
+        double pending = 0.0;
+        for (int step = 0; step < n; step++) {
+            for (int k = 0; k < L.nstages; k++) {
+                const fgi_stage& s = L.st[k];
+                if (s.kind == 'P') {
+                    pending += s.w;
+                    continue;
+                }
+                if (pending != 0.0) f.force(f.U, f.Us, L.terms, f.P, pending * h, true);
+                pending = 0.0;
+                if (s.kind == 'Q') {
+                    if (l + 1 < I.nlevels) run(l + 1, I.lev[l + 1].nsub, s.w * h / I.lev[l + 1].nsub);
+                    else link_update_b(f.c, f.B, s.w * h, f.P, f.U, f.U, f.Us, f.sp, f.rc);
+                } else {
+                    f.force(f.U, f.Us, L.terms, f.F, 1.0, false);
+                    link_update_b(f.c, f.B, 2.0 * s.xi / s.w * h * h, f.F, f.U, f.Ud, f.Uds, f.sp, f.rc);
+                    f.force(f.Ud, f.Uds, L.terms, f.P, s.w * h, true);
+                }
+            }
+        }
+        if (pending != 0.0) f.force(f.U, f.Us, L.terms, f.P, pending * h, true);
+    }
+};
+
+}  // namespace
+
+extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain* chains, const fgi_action* act,
+                                      const fgi_integrator* integ, double tau, int nsteps, double* dH, fgi_stats* st,
+                                      void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (nchains < 1 || !chains || !dH) throw Error(FGI_EINVAL, "need chains and a dH array");
+        check_action(act);
+        check_integrator(integ);
+        if (nsteps < 1 || !std::isfinite(tau)) throw Error(FGI_EINVAL, "bad tau / nsteps");
+        if (act->kappa_hasen != 0.0) throw Error(FGI_EINVAL, "batched chains take one pseudofermion");
+        if (act->fg_exact) throw Error(FGI_EINVAL, "batched chains use the displacement force-gradient form");
+        const bool ferm = chains[0].kappa != 0.0;
+        std::vector<ChainDesc> cd(nchains);
+        Batch B;
+        B.nc = nchains;
+        for (int i = 0; i < nchains; i++) {
+            const fgi_chain& ch = chains[i];
+            if ((ch.kappa != 0.0) != ferm) throw Error(FGI_EINVAL, "all chains need fermions or none");
+            need(ch.U, "chain U", 16);
+            need(ch.P, "chain P", 8);
+            if (ferm) need(ch.eta, "chain eta", 16);
+            ChainDesc& d = cd[i];
+            d.g = make_geom(ch.dims);
+            d.site0 = B.sites;
+            d.vol0 = B.vol;
+            d.link0 = B.links;
+            d.beta = ch.beta;
+            d.kappa = ch.kappa;
+            const long n[3] = {d.g.Vh, d.g.V, 4L * d.g.V};
+            for (int k = 0; k < 3; k++) {
+                d.blk0[k] = B.nblk[k];
+                d.nblk[k] = (int)((n[k] + 255) / 256);
+                B.nblk[k] += d.nblk[k];
+            }
+            d.user_U = ch.U;
+            d.user_P = ch.P;
+            d.user_eta = ch.eta;
+            B.sites += d.g.Vh;
+            B.vol += d.g.V;
+            B.links += 4L * d.g.V;
+        }
+        if (B.nblk[GRID_VH] > 65536 || B.nblk[GRID_V] > 65536) throw Error(FGI_EINVAL, "batch too large");
+        auto t0 = std::chrono::steady_clock::now();
+        StreamScope ss(c, stream);
+        ChainDesc* dcd = (ChainDesc*)c.cdesc.get(sizeof(ChainDesc) * nchains);
+        FGI_HIP(hipMemcpyAsync(dcd, cd.data(), sizeof(ChainDesc) * nchains, hipMemcpyHostToDevice, c.stream));
+        B.cd = dcd;
+        BFields f(c, *act);
+        f.B = B;
+        f.st = st;
+        f.fermions = ferm;
+        const size_t gb = sizeof(d2) * 9 * (size_t)B.links, mb = sizeof(double) * 8 * (size_t)B.links;
+        const size_t sb = sizeof(d2) * 12 * (size_t)B.sites, slb = sizeof(float) * 18 * (size_t)B.links;
+        f.U = (d2*)c.gauge.get(gb);
+        f.Ud = (d2*)c.gauge_disp.get(gb);
+        f.P = (double*)c.mom.get(mb);
+        f.F = (double*)c.force.get(mb);
+        pack_b(c, B, f.U, 0, 1);
+        pack_b(c, B, f.P, 1, 1);
+        d2* eta = nullptr;
+        if (ferm) {
+            f.phi = (d2*)c.phi.get(sb);
+            f.X = (d2*)c.X.get(sb);
+            eta = (d2*)c.eta.get(sb);
+            pack_b(c, B, eta, 2, 1);
+            if (f.sp != P64) {
+                f.Us = c.sloppy.get(slb);
+                f.Uds = c.sloppy_disp.get(slb);
+                make_sloppy_b(c, B, f.U, f.Us, f.sp, f.rc);
+            }
+            pf_heatbath_b(c, B, f.op64(f.U), eta, f.phi);
+        }
+        double* h0 = (double*)c.bh0.get(sizeof(double) * B.vol);
+        double* h1 = (double*)c.bh1.get(sizeof(double) * B.vol);
+        double* part = (double*)c.partial.get(sizeof(double) * 65536);
+        double* res = (double*)c.bres.get(sizeof(double) * 2 * nchains);  // not shared with the solver's scalars
+        ham_density_b(c, B, f.U, f.P, h0);
+
+        BDriver d{f, *integ};
+        d.run(0, nsteps, tau / nsteps);
+
+        ham_density_b(c, B, f.U, f.P, h1);
+        diff_sums_b(c, B, h1, h0, part, res);
+        if (ferm) {
+            f.solve(f.U, f.Us, f.phi, f.X);
+            pf_density_b(c, B, f.phi, f.X, eta, part, res + nchains);
+        }
+        std::vector<double> out(2 * nchains, 0.0);
+        FGI_HIP(hipMemcpyAsync(out.data(), res, sizeof(double) * (ferm ? 2 : 1) * nchains, hipMemcpyDeviceToHost,
+                               c.stream));
+        pack_b(c, B, f.U, 0, 0);
+        pack_b(c, B, f.P, 1, 0);
+        FGI_HIP(hipStreamSynchronize(c.stream));
+        bool finite = true;
+        for (int i = 0; i < nchains; i++) {
+            dH[i] = out[i] + (ferm ? out[nchains + i] : 0.0);
+            finite = finite && std::isfinite(dH[i]);
+        }
+        if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (!finite) throw Error(FGI_ENONFINITE, "dH is not finite");
         if (f.nonconv) throw Error(FGI_ENOCONV, "a CG solve reached cg_maxiter");
     });
 }

@@ -127,25 +127,28 @@ __device__ __forceinline__ void hop_sum(const Geom& g, int p, int s, const void*
 // Every block writes its partial; the last block to arrive (atomic counter)
 // sums all partials in a fixed order and publishes the scalar, so the value
 // does not depend on block scheduling.  Returns true in the last block.
+// b, nb: the block's logical index and the number of blocks taking part
+// (the chain's blocks in a batched launch); partials are stored by logical
+// index, so a chain reduces identically alone or inside a batch.
 __device__ __forceinline__ bool last_block_sum(double v, double* partial, unsigned* counter, double* lds,
-                                               double* total) {
+                                               double* total, int b, int nb) {
     __shared__ int is_last;
     double a[1] = {v};
     block_sum<1>(a, lds);
     if (threadIdx.x == 0) {
-        __hip_atomic_store(partial + blockIdx.x, a[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(partial + b, a[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
         unsigned prev = atomicAdd(counter, 1u);
-        is_last = (prev == gridDim.x - 1);
+        is_last = (prev == (unsigned)nb - 1);
     }
     __syncthreads();
     if (!is_last) return false;
     __threadfence();
     double t = 0.0;
-    for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) t += __hip_atomic_load(partial + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    double b[1] = {t};
-    block_sum<1>(b, lds);
-    *total = b[0];
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) t += __hip_atomic_load(partial + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double tt[1] = {t};
+    block_sum<1>(tt, lds);
+    *total = tt[0];
     if (threadIdx.x == 0) *counter = 0u;
     return true;
 }
@@ -172,16 +175,17 @@ struct DArgs {
     CGState* st;
     int iter;   // absolute index, or the offset from st->base inside a CG batch
     int g5out;
+    int gate;   // with st: 0 skip once st->stop_at <= iteration, 1 skip unless st->act
 };
 
 template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN>
-__global__ void __launch_bounds__(DBS) k_dslash(DArgs A) {
+__device__ __forceinline__ void dslash_body(const DArgs& A, int b, int nb, double* lds) {
     typedef typename Real<PIN == P64 ? P64 : P32>::T R;
-    __shared__ double lds[DBS / 64];
     const Geom& g = A.g;
     const int iter = A.st ? A.st->base + A.iter : A.iter;
-    if (A.st && A.st->stop_at <= iter) return;  // solve converged: the whole grid no-ops
-    int b = xcd_block(blockIdx.x, gridDim.x);
+    if (A.st) {  // uniform over the chain's blocks: converged / masked chains no-op
+        if (A.gate ? !A.st->act : A.st->stop_at <= iter) return;
+    }
     int s = b * DBS + threadIdx.x;
     double nrm = 0.0;
     if (s < g.Vh) {
@@ -254,7 +258,7 @@ __global__ void __launch_bounds__(DBS) k_dslash(DArgs A) {
     if (MODE == M_HOP || MODE == M_HOPP) return;
     if (MODE == M_SCHUR && !A.result) return;
     double total;
-    bool last = last_block_sum(nrm, A.partial, A.counter, lds, &total);
+    bool last = last_block_sum(nrm, A.partial, A.counter, lds, &total, b, nb);
     if (!last || threadIdx.x != 0) return;
     if (MODE == M_CGQ) {
         A.st->pAp = total;
@@ -268,9 +272,65 @@ __global__ void __launch_bounds__(DBS) k_dslash(DArgs A) {
     }
 }
 
+template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN>
+__global__ void __launch_bounds__(DBS) k_dslash(DArgs A) {
+    __shared__ double lds[DBS / 64];
+    dslash_body<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN>(A, xcd_block(blockIdx.x, gridDim.x), gridDim.x, lds);
+}
+
+// one chain's part of a concatenated spinor field / link field
+template <int P> __device__ __forceinline__ SpinorPtr spin_off(SpinorPtr p, const ChainDesc& d) {
+    if (!p.v) return p;
+    SpinorPtr q = p;
+    if (P == P64) q.v = (d2*)p.v + 12 * (size_t)d.site0;
+    else if (P == P32) q.v = (f4*)p.v + 6 * (size_t)d.site0;
+    else {
+        q.v = (h8*)p.v + 3 * (size_t)d.site0;
+        q.norm = p.norm + d.site0;
+    }
+    return q;
+}
+
+template <int PL, int RECON> __device__ __forceinline__ size_t link_byte_off(const ChainDesc& d) {
+    if (PL == P64) return 9 * (size_t)d.link0 * sizeof(d2);
+    if (PL == P32 && RECON == 18) return 9 * (size_t)d.link0 * sizeof(f2);
+    if (PL == P32) return 3 * (size_t)d.link0 * sizeof(f4);
+    return 3 * (size_t)d.link0 * sizeof(h4);
+}
+
+// batched launch: every chain of the batch with its own geometry, kappa,
+// solver state (base.st[c]) and result slot (base.result[c])
+template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN>
+__global__ void __launch_bounds__(DBS) k_dslash_b(DArgs base, const ChainDesc* __restrict__ cd, int nc) {
+    __shared__ double lds[DBS / 64];
+    const int gb = xcd_block(blockIdx.x, gridDim.x);
+    const int c = find_chain(cd, nc, gb, GRID_VH);
+    const ChainDesc& d = cd[c];
+    DArgs A = base;
+    A.g = d.g;
+    A.kappa2 = d.kappa * d.kappa;
+    A.links = (const char*)base.links + link_byte_off<PL, RECON>(d);
+    A.in = spin_off<PIN>(base.in, d);
+    A.center = spin_off<PC>(base.center, d);
+    A.aux = spin_off<PC>(base.aux, d);
+    A.out = spin_off<POUT>(base.out, d);
+    A.x = spin_off<PX>(base.x, d);
+    A.r = spin_off<PX>(base.r, d);
+    A.partial = base.partial ? base.partial + d.blk0[GRID_VH] : nullptr;
+    A.st = base.st ? base.st + c : nullptr;
+    A.counter = A.st ? &A.st->counter : nullptr;
+    A.result = base.result ? base.result + c : nullptr;
+    dslash_body<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN>(A, gb - d.blk0[GRID_VH], d.nblk[GRID_VH], lds);
+}
+
 // advance the batch base (last node of a CG batch)
 __global__ void k_advance(CGState* st, int n) {
     if (threadIdx.x == 0 && blockIdx.x == 0) st->base += n;
+}
+
+__global__ void k_advance_b(CGState* st, int nc, int n) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nc) st[c].base += n;
 }
 
 // --------------------------------------------------- persistent CG kernel ---
@@ -588,6 +648,111 @@ __global__ void __launch_bounds__(256) k_fermion_force(Geom g, const d2* __restr
     ff_link<1>(g, p, s, c, U, X, Y, coef, F);
     ff_link<2>(g, p, s, c, U, X, Y, coef, F);
     ff_link<3>(g, p, s, c, U, X, Y, coef, F);
+}
+
+// ------------------------------------------------- batched small kernels ---
+// chain of the calling block in a Vh-sized batched grid and its local site
+#define FGI_CHAIN_SITE(cd, nc)                                             \
+    const int c_ = find_chain(cd, nc, blockIdx.x, GRID_VH);                \
+    const ChainDesc& d = cd[c_];                                           \
+    const int s = (blockIdx.x - d.blk0[GRID_VH]) * blockDim.x + threadIdx.x
+
+template <int PA, int PB>
+__global__ void k_convert_b(const ChainDesc* __restrict__ cd, int nc, const CGState* st, SpinorPtr a, SpinorPtr b) {
+    FGI_CHAIN_SITE(cd, nc);
+    if (s >= d.g.Vh || (st && !st[c_].act)) return;
+    cx<double> v[4][3];
+    SpinorIO<PA, double>::load(spin_off<PA>(a, d), s, d.g.Vh, v);
+    SpinorIO<PB, double>::store(spin_off<PB>(b, d), s, d.g.Vh, v);
+}
+
+template <int PX>
+__global__ void k_add_to64_b(const ChainDesc* __restrict__ cd, int nc, const CGState* st, SpinorPtr x, SpinorPtr y) {
+    FGI_CHAIN_SITE(cd, nc);
+    if (s >= d.g.Vh || !st[c_].act) return;
+    cx<double> a[4][3], b[4][3];
+    SpinorIO<PX, double>::load(spin_off<PX>(x, d), s, d.g.Vh, a);
+    SpinorPtr yy = spin_off<P64>(y, d);
+    SpinorIO<P64, double>::load(yy, s, d.g.Vh, b);
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) b[i][k] = b[i][k] + a[i][k];
+    SpinorIO<P64, double>::store(yy, s, d.g.Vh, b);
+}
+
+// zero a chain's FP32 / FP64 spinor (only chains with act set when st is given)
+template <int P>
+__global__ void k_zero_spinor_b(const ChainDesc* __restrict__ cd, int nc, const CGState* st, SpinorPtr v) {
+    FGI_CHAIN_SITE(cd, nc);
+    if (s >= d.g.Vh || (st && !st[c_].act)) return;
+    cx<double> z[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) z[i][k] = {0.0, 0.0};
+    SpinorIO<P, double>::store(spin_off<P>(v, d), s, d.g.Vh, z);
+}
+
+__global__ void k_norm2_partials_b(const ChainDesc* __restrict__ cd, int nc, const d2* __restrict__ v,
+                                   double* __restrict__ partial) {
+    __shared__ double lds[DBS / 64];
+    FGI_CHAIN_SITE(cd, nc);
+    const d2* w = v + 12 * (size_t)d.site0;
+    double a[1] = {0.0};
+    if (s < d.g.Vh) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            d2 e = w[(size_t)k * d.g.Vh + s];
+            a[0] += e.x * e.x + e.y * e.y;
+        }
+    }
+    block_sum<1>(a, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = a[0];
+}
+
+__global__ void k_pf_density_b(const ChainDesc* __restrict__ cd, int nc, const d2* __restrict__ phi,
+                               const d2* __restrict__ X, const d2* __restrict__ eta, double* __restrict__ partial) {
+    __shared__ double lds[DBS / 64];
+    FGI_CHAIN_SITE(cd, nc);
+    const size_t o = 12 * (size_t)d.site0;
+    const int Vh = d.g.Vh;
+    double a[1] = {0.0};
+    if (s < Vh) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            d2 f = phi[o + (size_t)k * Vh + s], x = X[o + (size_t)k * Vh + s];
+            a[0] += f.x * x.x + f.y * x.y;
+            if (eta) {
+                d2 e = eta[o + (size_t)k * Vh + s];
+                a[0] -= e.x * e.x + e.y * e.y;
+            }
+        }
+    }
+    block_sum<1>(a, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = a[0];
+}
+
+// batched fermion force: coef times kappa_c^2 for chain c (Y_e = Mhat X_e form)
+__global__ void __launch_bounds__(256) k_fermion_force_b(const ChainDesc* __restrict__ cd, int nc,
+                                                        const d2* __restrict__ U, SpinorPtr Xe, SpinorPtr Xo,
+                                                        SpinorPtr Ye, SpinorPtr Yo, double coef,
+                                                        double* __restrict__ F) {
+    const int c_ = find_chain(cd, nc, blockIdx.x, GRID_V);
+    const ChainDesc& d = cd[c_];
+    const Geom& g = d.g;
+    const int t = (blockIdx.x - d.blk0[GRID_V]) * blockDim.x + threadIdx.x;
+    if (t >= g.V) return;
+    int p = t / g.Vh, s = t % g.Vh;
+    Coord c = cb_coords(g, p, s);
+    SpinorPtr X[2] = {spin_off<P64>(Xe, d), spin_off<P64>(Xo, d)}, Y[2] = {spin_off<P64>(Ye, d), spin_off<P64>(Yo, d)};
+    const d2* u = U + 9 * d.link0;
+    double* f = F + 8 * d.link0;
+    const double cf = coef * d.kappa * d.kappa;
+    ff_link<0>(g, p, s, c, u, X, Y, cf, f);
+    ff_link<1>(g, p, s, c, u, X, Y, cf, f);
+    ff_link<2>(g, p, s, c, u, X, Y, cf, f);
+    ff_link<3>(g, p, s, c, u, X, Y, cf, f);
 }
 
 // ------------------------------------------------------- host launchers ---
@@ -1073,6 +1238,329 @@ static CGResult cg_run(Ctx& c, const FermionOp& op64, const FermionOp& ops, cons
         c.dslash_sites += (long)N * g.Vh;
     }
     return res;
+}
+
+// ====================================================== batched chains ======
+template <int MODE, int PIN, int PC, int POUT, int PX, int G5IN>
+static void launch_dslash_b(Ctx& c, const Batch& B, const FermionOp& op, DArgs& a) {
+    const int nb = B.nblk[GRID_VH];
+    if constexpr (PIN == P64) {
+        hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P64, 18, G5IN>), dim3(nb), dim3(DBS), 0, c.stream, a,
+                           B.cd, B.nc);
+    } else {
+        if (op.prec == P32 && op.recon == 18)
+            hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P32, 18, G5IN>), dim3(nb), dim3(DBS), 0, c.stream,
+                               a, B.cd, B.nc);
+        else if (op.prec == P32)
+            hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P32, 12, G5IN>), dim3(nb), dim3(DBS), 0, c.stream,
+                               a, B.cd, B.nc);
+        else
+            hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P16, 12, G5IN>), dim3(nb), dim3(DBS), 0, c.stream,
+                               a, B.cd, B.nc);
+    }
+    FGI_LAUNCH_CHECK();
+}
+
+static DArgs base_args_b(const FermionOp& op, int p_out) {
+    DArgs a{};
+    a.p_out = p_out;
+    a.links = op.links;
+    return a;
+}
+
+#define FGI_B_LAUNCH(kernel, grid) \
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(DBS), 0, c.stream
+
+// out = Mhat in (dagger: Mhat^+) for every chain (gated by st[c].act when st given)
+static void mhat_b(Ctx& c, const Batch& B, const FermionOp& op64, const d2* in, d2* tmp, d2* out, int dagger,
+                   CGState* st) {
+    DArgs a = base_args_b(op64, 1);
+    a.in = sp(in);
+    a.out = sp(tmp);
+    a.st = st;
+    a.gate = 1;
+    if (dagger) launch_dslash_b<M_HOP, P64, P64, P64, P64, 1>(c, B, op64, a);
+    else launch_dslash_b<M_HOP, P64, P64, P64, P64, 0>(c, B, op64, a);
+    DArgs b = base_args_b(op64, 0);
+    b.in = sp(tmp);
+    b.center = sp(in);
+    b.out = sp(out);
+    b.g5out = dagger;
+    b.st = st;
+    b.gate = 1;
+    launch_dslash_b<M_SCHUR, P64, P64, P64, P64, 0>(c, B, op64, b);
+}
+
+void pf_heatbath_b(Ctx& c, const Batch& B, const FermionOp& op64, const d2* eta, d2* phi) {
+    d2* t = (d2*)c.tmp_o.get(sizeof(d2) * 12 * (size_t)B.sites);
+    mhat_b(c, B, op64, eta, t, phi, 1, nullptr);
+}
+
+void fermion_force_b(Ctx& c, const Batch& B, const FermionOp& op64, const d2* Xe, double* F, double coef) {
+    size_t n = sizeof(d2) * 12 * (size_t)B.sites;
+    d2* Xo = (d2*)c.Xo.get(n);
+    d2* Ye = (d2*)c.Ye.get(n);
+    d2* Yo = (d2*)c.Yo.get(n);
+    d2* t = (d2*)c.tmp_o.get(n);
+    {
+        DArgs a = base_args_b(op64, 1);
+        a.in = sp(Xe);
+        a.out = sp(Xo);
+        launch_dslash_b<M_HOP, P64, P64, P64, P64, 0>(c, B, op64, a);
+    }
+    mhat_b(c, B, op64, Xe, t, Ye, 0, nullptr);
+    {
+        DArgs a = base_args_b(op64, 1);
+        a.in = sp(Ye);
+        a.out = sp(Yo);
+        a.g5out = 1;
+        launch_dslash_b<M_HOP, P64, P64, P64, P64, 1>(c, B, op64, a);
+    }
+    hipLaunchKernelGGL(k_fermion_force_b, dim3(B.nblk[GRID_V]), dim3(256), 0, c.stream, B.cd, B.nc,
+                       (const d2*)op64.links, sp(Xe), sp(Xo), sp(Ye), sp(Yo), coef, F);
+    FGI_LAUNCH_CHECK();
+}
+
+void pf_density_b(Ctx& c, const Batch& B, const d2* phi, const d2* X, const d2* eta, double* partial, double* out) {
+    hipLaunchKernelGGL(k_pf_density_b, dim3(B.nblk[GRID_VH]), dim3(DBS), 0, c.stream, B.cd, B.nc, phi, X, eta, partial);
+    FGI_LAUNCH_CHECK();
+    final_sums_b(c, B, partial, GRID_VH, out);
+}
+
+// r = phi - Mhat^+ Mhat X and |r|^2 -> res[c] for the chains with act set
+static void true_residual_b(Ctx& c, const Batch& B, const FermionOp& op64, const d2* phi, const d2* X, d2* r64,
+                            CGState* st, double* res) {
+    size_t n = sizeof(d2) * 12 * (size_t)B.sites;
+    d2* t = (d2*)c.tmp_o.get(n);
+    d2* q = (d2*)c.cg_q.get(n);
+    mhat_b(c, B, op64, X, t, q, 0, st);
+    DArgs a = base_args_b(op64, 1);
+    a.in = sp(q);
+    a.out = sp(t);
+    a.st = st;
+    a.gate = 1;
+    launch_dslash_b<M_HOP, P64, P64, P64, P64, 1>(c, B, op64, a);
+    DArgs b = base_args_b(op64, 0);
+    b.in = sp(t);
+    b.center = sp(q);
+    b.aux = sp(phi);
+    b.out = sp(r64);
+    b.g5out = 1;
+    b.partial = (double*)c.partial.get(sizeof(double) * 65536);
+    b.st = st;
+    b.gate = 1;
+    b.result = res;
+    launch_dslash_b<M_RESID, P64, P64, P64, P64, 0>(c, B, op64, b);
+}
+
+template <int PP, int PX>
+static void cg_iteration_b(Ctx& c, const Batch& B, const FermionOp& ops, const CGVecs& v, int j, CGState* st) {
+    double* part = (double*)c.partial.get(sizeof(double) * 65536);
+    {
+        DArgs a = base_args_b(ops, 1);
+        a.in = v.p;
+        a.r = v.r;
+        a.out = v.t;
+        a.st = st;
+        a.iter = j;
+        launch_dslash_b<M_HOPP, PP, PP, PP, PX, 0>(c, B, ops, a);
+    }
+    {
+        DArgs a = base_args_b(ops, 0);
+        a.in = v.t;
+        a.center = v.p;
+        a.r = v.r;
+        a.out = v.q;
+        a.partial = part;
+        a.st = st;
+        a.iter = j;
+        launch_dslash_b<M_CGQ, PP, PP, PP, PX, 0>(c, B, ops, a);
+    }
+    {
+        DArgs a = base_args_b(ops, 1);
+        a.in = v.q;
+        a.out = v.t;
+        a.st = st;
+        a.iter = j;
+        launch_dslash_b<M_HOP, PP, PP, PP, PX, 1>(c, B, ops, a);
+    }
+    {
+        DArgs a = base_args_b(ops, 0);
+        a.in = v.t;
+        a.center = v.q;
+        a.aux = v.p;
+        a.x = v.x;
+        a.r = v.r;
+        a.g5out = 1;
+        a.partial = part;
+        a.st = st;
+        a.iter = j;
+        launch_dslash_b<M_CGX, PP, PP, PP, PX, 0>(c, B, ops, a);
+    }
+}
+
+template <int PP, int PX>
+static void cg_batch_b(Ctx& c, const Batch& B, const FermionOp& ops, const CGVecs& v, int nit, CGState* st) {
+    for (int j = 0; j < nit; j++) cg_iteration_b<PP, PX>(c, B, ops, v, j, st);
+    hipLaunchKernelGGL(k_advance_b, dim3(nblk(B.nc, 64)), dim3(64), 0, c.stream, st, B.nc, nit);
+    FGI_LAUNCH_CHECK();
+}
+
+static void upload_states(Ctx& c, CGState* dev, const std::vector<CGState>& h) {
+    std::copy(h.begin(), h.end(), c.host_bstates);
+    FGI_HIP(hipMemcpyAsync(dev, c.host_bstates, sizeof(CGState) * h.size(), hipMemcpyHostToDevice, c.stream));
+}
+
+static void download_states(Ctx& c, const CGState* dev, std::vector<CGState>& h) {
+    FGI_HIP(hipMemcpyAsync(c.host_bstates, dev, sizeof(CGState) * h.size(), hipMemcpyDeviceToHost, c.stream));
+    FGI_HIP(hipStreamSynchronize(c.stream));
+    std::copy(c.host_bstates, c.host_bstates + h.size(), h.begin());
+}
+
+static void download_doubles(Ctx& c, const double* dev, int n) {
+    FGI_HIP(hipMemcpyAsync(c.host_bscal, dev, sizeof(double) * n, hipMemcpyDeviceToHost, c.stream));
+    FGI_HIP(hipStreamSynchronize(c.stream));
+}
+
+// All chains of the batch solved together: every kernel covers every chain,
+// each chain with its own CG state; chains stop on their own and take their
+// reliable updates in masked steps.
+template <int PP, int PX>
+static std::vector<CGResult> cg_run_b(Ctx& c, const Batch& B, const FermionOp& op64, const FermionOp& ops,
+                                      const d2* phi, d2* X, double tol, int maxiter) {
+    const int nc = B.nc;
+    const size_t n64 = sizeof(d2) * 12 * (size_t)B.sites;
+    std::vector<CGResult> res(nc, CGResult{0, 0, 0.0, 0});
+    double* part = (double*)c.partial.get(sizeof(double) * 65536);
+    double* dres = (double*)c.bscal.get(sizeof(double) * nc);
+    CGState* st = (CGState*)c.bstate.get(sizeof(CGState) * nc);
+    hipLaunchKernelGGL(k_norm2_partials_b, dim3(B.nblk[GRID_VH]), dim3(DBS), 0, c.stream, B.cd, nc, phi, part);
+    FGI_LAUNCH_CHECK();
+    final_sums_b(c, B, part, GRID_VH, dres);
+    download_doubles(c, dres, nc);
+    std::vector<double> bb(c.host_bscal, c.host_bscal + nc), target(nc);
+    zero_doubles(c, (double*)X, 24 * (size_t)B.sites);
+    d2* r64 = (d2*)c.cg_r.get(n64);
+    CGVecs v;
+    float* norms = (float*)c.s_norms.get(sizeof(float) * 3 * (size_t)B.sites);
+    if (PX == P64) {
+        FGI_HIP(hipMemcpyAsync(r64, phi, n64, hipMemcpyDeviceToDevice, c.stream));
+        v.x = sp(X);
+        v.r = sp(r64);
+        v.p = sp(c.cg_p.get(n64));
+        v.q = sp(c.cg_q.get(n64));
+        v.t = sp(c.s_t.get(n64));
+        FGI_HIP(hipMemcpyAsync(v.p.v, phi, n64, hipMemcpyDeviceToDevice, c.stream));
+    } else {
+        size_t nx = sizeof(float) * 24 * (size_t)B.sites;
+        size_t np = PP == P32 ? nx : sizeof(_Float16) * 24 * (size_t)B.sites;
+        v.x = sp(c.s_x.get(nx));
+        v.r = sp(c.s_r.get(nx));
+        v.p = sp(c.s_p.get(np), norms);
+        v.q = sp(c.s_q.get(np), norms + B.sites);
+        v.t = sp(c.s_t.get(np), norms + 2 * (size_t)B.sites);
+        zero_doubles(c, (double*)v.x.v, 12 * (size_t)B.sites);
+        FGI_B_LAUNCH((k_convert_b<P64, PX>), B.nblk[GRID_VH]), B.cd, nc, nullptr, sp(phi), v.r);
+        FGI_B_LAUNCH((k_convert_b<P64, PP>), B.nblk[GRID_VH]), B.cd, nc, nullptr, sp(phi), v.p);
+        FGI_LAUNCH_CHECK();
+    }
+    std::vector<CGState> hs(nc);
+    std::vector<int> done(nc, 0);
+    for (int i = 0; i < nc; i++) {
+        target[i] = tol * tol * bb[i];
+        CGState& h = hs[i];
+        h = CGState{};
+        h.rr[0] = bb[i];
+        h.rr_stop = (PX == P64) ? target[i] : std::max(c.ru_delta * c.ru_delta * bb[i], target[i]);
+        h.stop_at = bb[i] == 0.0 ? 0 : INT_MAX;
+        if (bb[i] == 0.0) {
+            done[i] = 1;
+            res[i].converged = 1;
+        }
+    }
+    upload_states(c, st, hs);
+    const int Bi = c.cg_batch;
+    GraphEntry* ge = nullptr;
+    if (c.use_graphs) {
+        char key[256];
+        snprintf(key, sizeof key, "bcg/%d/%d/%p/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%d", PP, PX, ops.links, ops.prec,
+                 ops.recon, nc, (void*)B.cd, v.x.v, v.r.v, v.p.v, v.q.v, v.t.v, (void*)st, (void*)part, Bi);
+        ge = &cached_graph(c, key, [&] { cg_batch_b<PP, PX>(c, B, ops, v, Bi, st); });
+    }
+    int left = 0;
+    for (int i = 0; i < nc; i++) left += !done[i];
+    while (left > 0) {
+        if (ge) FGI_HIP(hipGraphLaunch(ge->exec, c.stream));
+        else cg_batch_b<PP, PX>(c, B, ops, v, Bi, st);
+        download_states(c, st, hs);
+        bool any = false;
+        std::vector<int> kend(nc, 0);
+        for (int i = 0; i < nc; i++) {
+            hs[i].act = 0;
+            if (done[i]) continue;
+            bool inner = hs[i].stop_at <= hs[i].base;
+            kend[i] = inner ? hs[i].stop_at : hs[i].base;
+            if (inner || kend[i] >= maxiter) {
+                hs[i].act = 1;
+                any = true;
+            }
+        }
+        if (!any) continue;
+        upload_states(c, st, hs);
+        if (PX != P64) {
+            FGI_B_LAUNCH((k_add_to64_b<PX>), B.nblk[GRID_VH]), B.cd, nc, st, v.x, sp(X));
+            FGI_LAUNCH_CHECK();
+        }
+        true_residual_b(c, B, op64, phi, X, r64, st, dres);
+        download_doubles(c, dres, nc);
+        bool restart = false;
+        for (int i = 0; i < nc; i++) {
+            if (!hs[i].act) continue;
+            double rr = c.host_bscal[i];
+            if (!std::isfinite(rr)) throw Error(-4, "batched CG: non-finite residual");
+            res[i].iters = kend[i];
+            res[i].rel_resid = bb[i] > 0 ? std::sqrt(rr / bb[i]) : 0.0;
+            if (rr <= target[i] || kend[i] >= maxiter) {
+                res[i].converged = rr <= target[i];
+                done[i] = 1;
+                left--;
+                hs[i].act = 0;
+                hs[i].stop_at = hs[i].base;  // no-op from now on
+                continue;
+            }
+            res[i].reliable_updates++;
+            restart = true;
+            hs[i].beta = rr / hs[i].rr[(kend[i] - 1) & 1];
+            hs[i].rr[kend[i] & 1] = rr;
+            hs[i].stop_at = INT_MAX;
+            hs[i].base = kend[i];
+            hs[i].rr_stop = (PX == P64) ? target[i] : std::max(c.ru_delta * c.ru_delta * rr, target[i]);
+            hs[i].counter = 0;
+        }
+        upload_states(c, st, hs);  // act still set for the restarting chains
+        if (restart && PX != P64) {
+            FGI_B_LAUNCH((k_convert_b<P64, PX>), B.nblk[GRID_VH]), B.cd, nc, st, sp(r64), v.r);
+            FGI_B_LAUNCH((k_zero_spinor_b<PX>), B.nblk[GRID_VH]), B.cd, nc, st, v.x);
+            FGI_LAUNCH_CHECK();
+        }
+        for (int i = 0; i < nc; i++) hs[i].act = 0;
+        upload_states(c, st, hs);
+    }
+    return res;
+}
+
+std::vector<CGResult> cg_solve_b(Ctx& c, const Batch& B, const FermionOp& op64, const FermionOp& ops, int sprec,
+                                 const d2* phi, d2* X, double tol, int maxiter) {
+    if ((size_t)B.nc > c.host_b_cap) {
+        if (c.host_bstates) hipHostFree(c.host_bstates);
+        if (c.host_bscal) hipHostFree(c.host_bscal);
+        FGI_HIP(hipHostMalloc((void**)&c.host_bstates, sizeof(CGState) * B.nc, hipHostMallocDefault));
+        FGI_HIP(hipHostMalloc((void**)&c.host_bscal, sizeof(double) * B.nc, hipHostMallocDefault));
+        c.host_b_cap = B.nc;
+    }
+    if (sprec == P64) return cg_run_b<P64, P64>(c, B, op64, op64, phi, X, tol, maxiter);
+    if (sprec == P32) return cg_run_b<P32, P32>(c, B, op64, ops, phi, X, tol, maxiter);
+    return cg_run_b<P16, P32>(c, B, op64, ops, phi, X, tol, maxiter);
 }
 
 CGResult cg_solve(Ctx& c, const FermionOp& op64, const FermionOp& ops, int sprec, const d2* phi, d2* X, double tol,

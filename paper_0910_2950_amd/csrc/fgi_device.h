@@ -68,6 +68,44 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 // --------------------------------------------------------------------------
+// batched chains: independent lattices stored one after another in every
+// field; a kernel launched over all of them finds its chain from its block.
+// --------------------------------------------------------------------------
+enum GridKind { GRID_VH = 0, GRID_V = 1, GRID_4V = 2 };
+
+struct ChainDesc {
+    Geom g;
+    long site0;     // sum of Vh of the chains before (spinor offsets)
+    long vol0;      // sum of V (per-site densities)
+    long link0;     // sum of 4V (link / momentum offsets)
+    double beta, kappa;
+    int blk0[3];    // first block of the chain in the Vh-, V- and 4V-sized grids
+    int nblk[3];    // its number of blocks there
+    const void* user_U;   // user-layout buffers (pack / unpack)
+    void* user_P;
+    const void* user_eta;
+};
+
+// chain owning global block `blk` of a grid of the given kind (binary search)
+__device__ __forceinline__ int find_chain(const ChainDesc* cd, int nchains, int blk, int kind) {
+    int lo = 0, hi = nchains - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (cd[mid].blk0[kind] <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// element offsets of one chain's part of a concatenated field
+__device__ __forceinline__ size_t gauge_chunk_off(const ChainDesc& c, int prec, int recon) {
+    return (prec == 0 || recon == 18) ? 9 * (size_t)c.link0 : 3 * (size_t)c.link0;
+}
+__device__ __forceinline__ size_t spinor_chunk_off(const ChainDesc& c, int prec) {
+    return prec == 0 ? 12 * (size_t)c.site0 : (prec == 1 ? 6 * (size_t)c.site0 : 3 * (size_t)c.site0);
+}
+
+// --------------------------------------------------------------------------
 // complex numbers and 3x3 matrices, templated on the real type
 // --------------------------------------------------------------------------
 template <typename R> struct cx { R re, im; };

@@ -49,6 +49,8 @@ struct CGState {
     int iters;         // iterations completed
     int base;          // iteration index of the first iteration of the current batch
     unsigned counter;  // arrival counter of the last-block reductions (0 between kernels)
+    int act;           // batched solves: 1 when this chain takes part in a masked step
+    int pad;
 };
 
 // one instantiated CG batch graph, keyed by everything its kernels capture
@@ -72,6 +74,10 @@ struct Ctx {
     DevBuf s_x, s_r, s_p, s_q, s_t, s_norms;
     DevBuf h0, hf0, partial, scal, state;
     DevBuf phi2, eta2, user_tmp, aux, chi, X2;
+    DevBuf cdesc, bstate, bscal, bh0, bh1, bres;  // batched chains
+    CGState* host_bstates = nullptr;          // pinned [host_b_cap]
+    double* host_bscal = nullptr;             // pinned [host_b_cap]
+    size_t host_b_cap = 0;
     double* host_scal = nullptr;   // pinned, 64 doubles
     CGState* host_state = nullptr; // pinned
     int* host_aux = nullptr;       // pinned (persistent-solver error flag)
@@ -97,6 +103,15 @@ struct Ctx {
     int cg_batch = 8;          // iterations launched between host polls
     int dslash_split = 0;      // 0 = automatic
     double ru_delta = 0.1;     // reliable-update trigger |r| drop
+};
+
+// A batch of independent chains: their descriptors on the device and the
+// total block counts of the Vh-, V- and 4V-sized grids over all of them.
+struct Batch {
+    const ChainDesc* cd = nullptr;   // device array [nc]
+    int nc = 0;
+    int nblk[3] = {0, 0, 0};
+    long sites = 0, vol = 0, links = 0;  // totals: sum Vh, sum V, sum 4V
 };
 
 // ---------------- gauge.hip ----------------
@@ -130,6 +145,16 @@ int dot_partials(Ctx&, long n, const double* x, const double* y, double* partial
 void zero_doubles(Ctx&, double* p, size_t n);
 // exp of one su(3) element (test hook of the device exponential)
 void exp_su3_batch(Ctx&, int n, const double* p, double h, void* out);
+
+// batched versions (every chain with its own geometry, beta, kappa)
+void pack_b(Ctx&, const Batch&, void* internal, int field /*0 U, 1 P, 2 eta*/, int to_internal);
+void make_sloppy_b(Ctx&, const Batch&, const d2* U, void* sloppy, int prec, int recon);
+void ham_density_b(Ctx&, const Batch&, const d2* U, const double* P, double* h);
+void diff_sums_b(Ctx&, const Batch&, const double* h1, const double* h0, double* partial, double* out);
+void final_sums_b(Ctx&, const Batch&, const double* partial, int kind, double* out);
+void gauge_force_b(Ctx&, const Batch&, const d2* U, double* F, double coef, int accumulate);
+void link_update_b(Ctx&, const Batch&, double h, const double* X, const d2* src, d2* dst, void* sloppy, int prec,
+                   int recon);
 
 // ---------------- fermion.hip ----------------
 struct FermionOp {
@@ -166,6 +191,13 @@ int pf_density_partials(Ctx&, const Geom&, const d2* phi, const d2* X, const d2*
 void spinor_copy(Ctx&, const Geom&, const d2* src, d2* dst);
 // b = a with storage conversion (P64/P32/P16 -> P64/P32/P16)
 void convert_spinor(Ctx&, const Geom&, int prec_a, SpinorPtr a, int prec_b, SpinorPtr b);
+
+// batched fermion operations (all chains of B; FP64 fields concatenated chain by chain)
+void pf_heatbath_b(Ctx&, const Batch&, const FermionOp& op64, const d2* eta, d2* phi);
+void fermion_force_b(Ctx&, const Batch&, const FermionOp& op64, const d2* Xe, double* F, double coef);
+void pf_density_b(Ctx&, const Batch&, const d2* phi, const d2* X, const d2* eta, double* partial, double* out);
+std::vector<CGResult> cg_solve_b(Ctx&, const Batch&, const FermionOp& op64, const FermionOp& ops, int sprec,
+                                 const d2* phi, d2* X, double tol, int maxiter);
 
 
 }  // namespace fgi

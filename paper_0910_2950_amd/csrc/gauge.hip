@@ -15,8 +15,8 @@ __device__ __forceinline__ int lex_index(const Geom& g, int p, int s) {
 }
 
 // ---------------------------------------------------------------- layout ---
-__global__ void k_pack_gauge(Geom g, const d2* __restrict__ user, d2* __restrict__ U, int to_internal) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void pack_gauge_body(const Geom& g, const d2* __restrict__ user, d2* __restrict__ U,
+                                                int to_internal, int t) {
     if (t >= 4 * g.V) return;
     int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
     int i = lex_index(g, p, s);
@@ -31,8 +31,12 @@ __global__ void k_pack_gauge(Geom g, const d2* __restrict__ user, d2* __restrict
     }
 }
 
-__global__ void k_pack_mom(Geom g, const double* __restrict__ user, double* __restrict__ P, int to_internal) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_pack_gauge(Geom g, const d2* __restrict__ user, d2* __restrict__ U, int to_internal) {
+    pack_gauge_body(g, user, U, to_internal, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__device__ __forceinline__ void pack_mom_body(const Geom& g, const double* __restrict__ user, double* __restrict__ P,
+                                              int to_internal, int t) {
     if (t >= 4 * g.V) return;
     int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
     int i = lex_index(g, p, s);
@@ -47,9 +51,13 @@ __global__ void k_pack_mom(Geom g, const double* __restrict__ user, double* __re
     }
 }
 
+__global__ void k_pack_mom(Geom g, const double* __restrict__ user, double* __restrict__ P, int to_internal) {
+    pack_mom_body(g, user, P, to_internal, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // user even spinor: entry k (= checkerboard index of the k-th even site) holds [4][3] complex
-__global__ void k_pack_even(Geom g, const d2* __restrict__ user, d2* __restrict__ X, int to_internal) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void pack_even_body(const Geom& g, const d2* __restrict__ user, d2* __restrict__ X,
+                                               int to_internal, int s) {
     if (s >= g.Vh) return;
     if (to_internal) {
 #pragma unroll
@@ -58,6 +66,21 @@ __global__ void k_pack_even(Geom g, const d2* __restrict__ user, d2* __restrict_
 #pragma unroll
         for (int k = 0; k < 12; k++) ((d2*)user)[(size_t)s * 12 + k] = X[(size_t)k * g.Vh + s];
     }
+}
+
+__global__ void k_pack_even(Geom g, const d2* __restrict__ user, d2* __restrict__ X, int to_internal) {
+    pack_even_body(g, user, X, to_internal, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// batched: field 0 links, 1 momenta, 2 even spinor (the chain's user pointer)
+__global__ void k_pack_b(const ChainDesc* __restrict__ cd, int nc, void* internal, int field, int to_internal) {
+    const int kind = field == 2 ? GRID_VH : GRID_4V;
+    const int c = find_chain(cd, nc, blockIdx.x, kind);
+    const ChainDesc& d = cd[c];
+    const int t = (blockIdx.x - d.blk0[kind]) * blockDim.x + threadIdx.x;
+    if (field == 0) pack_gauge_body(d.g, (const d2*)d.user_U, (d2*)internal + 9 * d.link0, to_internal, t);
+    else if (field == 1) pack_mom_body(d.g, (const double*)d.user_P, (double*)internal + 8 * d.link0, to_internal, t);
+    else pack_even_body(d.g, (const d2*)d.user_eta, (d2*)internal + 12 * d.site0, to_internal, t);
 }
 
 void pack_gauge(Ctx& c, const Geom& g, const void* user, d2* U) {
@@ -86,8 +109,8 @@ void unpack_even_spinor(Ctx& c, const Geom& g, const d2* X, void* user) {
 }
 
 // sloppy copies of the FP64 master gauge field
-__global__ void k_make_sloppy(Geom g, const d2* __restrict__ U, void* __restrict__ out, int prec, int recon) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void make_sloppy_body(const Geom& g, const d2* __restrict__ U, void* __restrict__ out,
+                                                 int prec, int recon, int t) {
     if (t >= 4 * g.V) return;
     int s = t % g.Vh, r = t / g.Vh;  // r = mu * 2 + p
     const d2* in = U + (size_t)(r * 9) * g.Vh + s;
@@ -112,6 +135,25 @@ __global__ void k_make_sloppy(Geom g, const d2* __restrict__ U, void* __restrict
     }
 }
 
+__global__ void k_make_sloppy(Geom g, const d2* __restrict__ U, void* __restrict__ out, int prec, int recon) {
+    make_sloppy_body(g, U, out, prec, recon, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// byte offset of a chain's sloppy links in the concatenated sloppy field
+__device__ __forceinline__ size_t sloppy_byte_off(const ChainDesc& d, int prec, int recon) {
+    if (prec == P32 && recon == 18) return 9 * (size_t)d.link0 * sizeof(f2);
+    if (prec == P32) return 3 * (size_t)d.link0 * sizeof(f4);
+    return 3 * (size_t)d.link0 * sizeof(h4);
+}
+
+__global__ void k_make_sloppy_b(const ChainDesc* __restrict__ cd, int nc, const d2* __restrict__ U,
+                                void* __restrict__ out, int prec, int recon) {
+    const int c = find_chain(cd, nc, blockIdx.x, GRID_4V);
+    const ChainDesc& d = cd[c];
+    make_sloppy_body(d.g, U + 9 * d.link0, (char*)out + sloppy_byte_off(d, prec, recon), prec, recon,
+                     (blockIdx.x - d.blk0[GRID_4V]) * blockDim.x + threadIdx.x);
+}
+
 void make_sloppy(Ctx& c, const Geom& g, const d2* U, void* sloppy, int prec, int recon) {
     hipLaunchKernelGGL(k_make_sloppy, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, U, sloppy, prec, recon);
     FGI_LAUNCH_CHECK();
@@ -120,9 +162,8 @@ void make_sloppy(Ctx& c, const Geom& g, const d2* U, void* sloppy, int prec, int
 // ----------------------------------------------------------- densities ---
 // h(x) = beta sum_{mu<nu} (1 - ReTr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+]/3)
 //        + 1/2 sum_mu |p_mu(x)|^2
-__global__ void k_ham_density(Geom g, double beta, const d2* __restrict__ U, const double* __restrict__ P,
-                              double* __restrict__ h) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void ham_density_body(const Geom& g, double beta, const d2* __restrict__ U,
+                                                 const double* __restrict__ P, double* __restrict__ h, int t) {
     if (t >= g.V) return;
     int p = t / g.Vh, s = t % g.Vh;
     Coord c = cb_coords(g, p, s);
@@ -158,6 +199,19 @@ __global__ void k_ham_density(Geom g, double beta, const d2* __restrict__ U, con
     h[t] = acc;
 }
 
+__global__ void k_ham_density(Geom g, double beta, const d2* __restrict__ U, const double* __restrict__ P,
+                              double* __restrict__ h) {
+    ham_density_body(g, beta, U, P, h, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void k_ham_density_b(const ChainDesc* __restrict__ cd, int nc, const d2* __restrict__ U,
+                                const double* __restrict__ P, double* __restrict__ h) {
+    const int c = find_chain(cd, nc, blockIdx.x, GRID_V);
+    const ChainDesc& d = cd[c];
+    ham_density_body(d.g, d.beta, U ? U + 9 * d.link0 : nullptr, P ? P + 8 * d.link0 : nullptr, h + d.vol0,
+                     (blockIdx.x - d.blk0[GRID_V]) * blockDim.x + threadIdx.x);
+}
+
 void ham_density(Ctx& c, const Geom& g, double beta, const d2* U, const double* P, double* h) {
     hipLaunchKernelGGL(k_ham_density, dim3(nblocks(g.V, BS)), dim3(BS), 0, c.stream, g, beta, U, P, h);
     FGI_LAUNCH_CHECK();
@@ -171,6 +225,28 @@ __global__ void k_diff_partials(int n, const double* __restrict__ h1, const doub
     if (t < n) v[0] = h0 ? h1[t] - h0[t] : h1[t];
     block_sum<1>(v, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
+// partial[blk0 + b] = sum over chain-local block b of (h1 - h0) on the chain's V sites
+__global__ void k_diff_partials_b(const ChainDesc* __restrict__ cd, int nc, const double* __restrict__ h1,
+                                  const double* __restrict__ h0, double* __restrict__ partial) {
+    __shared__ double lds[16];
+    const int c = find_chain(cd, nc, blockIdx.x, GRID_V);
+    const ChainDesc& d = cd[c];
+    const int t = (blockIdx.x - d.blk0[GRID_V]) * blockDim.x + threadIdx.x;
+    double v[1] = {0.0};
+    if (t < d.g.V) v[0] = h0 ? h1[d.vol0 + t] - h0[d.vol0 + t] : h1[d.vol0 + t];
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
+// out[c] = fixed-order sum of chain c's partials (one block per chain)
+__global__ void k_final_sum_b(const ChainDesc* __restrict__ cd, const double* __restrict__ partial, int kind,
+                              double* __restrict__ out) {
+    __shared__ double lds[16];
+    const ChainDesc& d = cd[blockIdx.x];
+    double s = sum_partials(partial + d.blk0[kind], d.nblk[kind], lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 int diff_partials(Ctx& c, int n, const double* h1, const double* h0, double* partial) {
@@ -196,9 +272,8 @@ void final_sum(Ctx& c, const double* partial, int n, double* out) {
 //                                     + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)];
 // the part of S_G holding U_mu(x) is -beta/3 ReTr(U_mu(x) A_mu(x)), so
 // F_mu(x) = -e S = -(beta/6) TA(U_mu(x) A_mu(x)).
-__global__ void __launch_bounds__(256) k_gauge_force(Geom g, double beta, const d2* __restrict__ U,
-                                                    double* __restrict__ F, double coef, int accumulate) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gauge_force_body(const Geom& g, double beta, const d2* __restrict__ U,
+                                                 double* __restrict__ F, double coef, int accumulate, int t) {
     if (t >= 4 * g.V) return;
     int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
     Coord c = cb_coords(g, p, s);
@@ -230,6 +305,20 @@ __global__ void __launch_bounds__(256) k_gauge_force(Geom g, double beta, const 
         double v = f * x[a];
         o[(size_t)a * g.Vh] = accumulate ? o[(size_t)a * g.Vh] + v : v;
     }
+}
+
+__global__ void __launch_bounds__(256) k_gauge_force(Geom g, double beta, const d2* __restrict__ U,
+                                                    double* __restrict__ F, double coef, int accumulate) {
+    gauge_force_body(g, beta, U, F, coef, accumulate, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_gauge_force_b(const ChainDesc* __restrict__ cd, int nc,
+                                                      const d2* __restrict__ U, double* __restrict__ F, double coef,
+                                                      int accumulate) {
+    const int c = find_chain(cd, nc, blockIdx.x, GRID_4V);
+    const ChainDesc& d = cd[c];
+    gauge_force_body(d.g, d.beta, U + 9 * d.link0, F + 8 * d.link0, coef, accumulate,
+                     (blockIdx.x - d.blk0[GRID_4V]) * blockDim.x + threadIdx.x);
 }
 
 void gauge_force(Ctx& c, const Geom& g, double beta, const d2* U, double* F, double coef, int accumulate) {
@@ -338,9 +427,9 @@ void gauge_force_tangent(Ctx& c, const Geom& g, double beta, const d2* U, const 
 }
 
 // ------------------------------------------------------------ updates ----
-__global__ void k_link_update(Geom g, double h, const double* __restrict__ X, const d2* __restrict__ src,
-                              d2* __restrict__ dst, void* __restrict__ sloppy, int prec, int recon) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void link_update_body(const Geom& g, double h, const double* __restrict__ X,
+                                                 const d2* __restrict__ src, d2* __restrict__ dst,
+                                                 void* __restrict__ sloppy, int prec, int recon, int t) {
     if (t >= 4 * g.V) return;
     int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
     double x[8];
@@ -371,6 +460,21 @@ __global__ void k_link_update(Geom g, double h, const double* __restrict__ X, co
             }
         }
     }
+}
+
+__global__ void k_link_update(Geom g, double h, const double* __restrict__ X, const d2* __restrict__ src,
+                              d2* __restrict__ dst, void* __restrict__ sloppy, int prec, int recon) {
+    link_update_body(g, h, X, src, dst, sloppy, prec, recon, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void k_link_update_b(const ChainDesc* __restrict__ cd, int nc, double h, const double* __restrict__ X,
+                                const d2* __restrict__ src, d2* __restrict__ dst, void* __restrict__ sloppy, int prec,
+                                int recon) {
+    const int c = find_chain(cd, nc, blockIdx.x, GRID_4V);
+    const ChainDesc& d = cd[c];
+    link_update_body(d.g, h, X + 8 * d.link0, src + 9 * d.link0, dst + 9 * d.link0,
+                     sloppy ? (char*)sloppy + sloppy_byte_off(d, prec, recon) : nullptr, prec, recon,
+                     (blockIdx.x - d.blk0[GRID_4V]) * blockDim.x + threadIdx.x);
 }
 
 void link_update(Ctx& c, const Geom& g, double h, const double* X, const d2* src, d2* dst, void* sloppy, int prec,
@@ -418,8 +522,7 @@ void zero_doubles(Ctx& c, double* p, size_t n) {
 }
 
 // Gram-Schmidt on rows 0 and 1, row 2 = conj(row0 x row1)
-__global__ void k_reunitarize(Geom g, d2* __restrict__ U) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void reunitarize_body(const Geom& g, d2* __restrict__ U, int t) {
     if (t >= 4 * g.V) return;
     int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
     M3<double> u = gauge_load(U, mu, p, s, g.Vh);
@@ -438,6 +541,10 @@ __global__ void k_reunitarize(Geom g, d2* __restrict__ U) {
     gauge_store(U, mu, p, s, g.Vh, u);
 }
 
+__global__ void k_reunitarize(Geom g, d2* __restrict__ U) {
+    reunitarize_body(g, U, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 void reunitarize(Ctx& c, const Geom& g, d2* U) {
     hipLaunchKernelGGL(k_reunitarize, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, U);
     FGI_LAUNCH_CHECK();
@@ -454,6 +561,46 @@ __global__ void k_exp_batch(int n, const double* __restrict__ p, double h, d2* _
 
 void exp_su3_batch(Ctx& c, int n, const double* p, double h, void* out) {
     hipLaunchKernelGGL(k_exp_batch, dim3(nblocks(n, BS)), dim3(BS), 0, c.stream, n, p, h, (d2*)out);
+    FGI_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------ batched launchers ---
+void pack_b(Ctx& c, const Batch& B, void* internal, int field, int to_internal) {
+    int nb = field == 2 ? B.nblk[GRID_VH] : B.nblk[GRID_4V];
+    hipLaunchKernelGGL(k_pack_b, dim3(nb), dim3(BS), 0, c.stream, B.cd, B.nc, internal, field, to_internal);
+    FGI_LAUNCH_CHECK();
+}
+
+void make_sloppy_b(Ctx& c, const Batch& B, const d2* U, void* sloppy, int prec, int recon) {
+    hipLaunchKernelGGL(k_make_sloppy_b, dim3(B.nblk[GRID_4V]), dim3(BS), 0, c.stream, B.cd, B.nc, U, sloppy, prec, recon);
+    FGI_LAUNCH_CHECK();
+}
+
+void ham_density_b(Ctx& c, const Batch& B, const d2* U, const double* P, double* h) {
+    hipLaunchKernelGGL(k_ham_density_b, dim3(B.nblk[GRID_V]), dim3(BS), 0, c.stream, B.cd, B.nc, U, P, h);
+    FGI_LAUNCH_CHECK();
+}
+
+void diff_sums_b(Ctx& c, const Batch& B, const double* h1, const double* h0, double* partial, double* out) {
+    hipLaunchKernelGGL(k_diff_partials_b, dim3(B.nblk[GRID_V]), dim3(BS), 0, c.stream, B.cd, B.nc, h1, h0, partial);
+    FGI_LAUNCH_CHECK();
+    final_sums_b(c, B, partial, GRID_V, out);
+}
+
+void final_sums_b(Ctx& c, const Batch& B, const double* partial, int kind, double* out) {
+    hipLaunchKernelGGL(k_final_sum_b, dim3(B.nc), dim3(BS), 0, c.stream, B.cd, partial, kind, out);
+    FGI_LAUNCH_CHECK();
+}
+
+void gauge_force_b(Ctx& c, const Batch& B, const d2* U, double* F, double coef, int accumulate) {
+    hipLaunchKernelGGL(k_gauge_force_b, dim3(B.nblk[GRID_4V]), dim3(BS), 0, c.stream, B.cd, B.nc, U, F, coef, accumulate);
+    FGI_LAUNCH_CHECK();
+}
+
+void link_update_b(Ctx& c, const Batch& B, double h, const double* X, const d2* src, d2* dst, void* sloppy, int prec,
+                   int recon) {
+    hipLaunchKernelGGL(k_link_update_b, dim3(B.nblk[GRID_4V]), dim3(BS), 0, c.stream, B.cd, B.nc, h, X, src, dst, sloppy,
+                       prec, recon);
     FGI_LAUNCH_CHECK();
 }
 

@@ -55,6 +55,12 @@ class fgi_integrator(ctypes.Structure):
     _fields_ = [("nlevels", ctypes.c_int), ("pad", ctypes.c_int), ("lev", fgi_level * MAX_LEVELS)]
 
 
+class fgi_chain(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("pad", ctypes.c_int), ("beta", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("U", ctypes.c_void_p), ("P", ctypes.c_void_p),
+                ("eta", ctypes.c_void_p)]
+
+
 class fgi_stats(ctypes.Structure):
     _fields_ = [("solves", ctypes.c_long), ("cg_iters", ctypes.c_long), ("cg_iters_max", ctypes.c_int),
                 ("reliable_updates", ctypes.c_int), ("max_rel_resid", ctypes.c_double),
@@ -94,6 +100,8 @@ SIGNATURES = {
     "fgi_integrator_builtin": (_i, [_i, _d, _P(fgi_integrator)]),
     "fgi_trajectory": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _P(fgi_integrator), _d, _i, _vp, _vp, _vp, _vp,
                             _i, _P(_d), _P(fgi_stats), _vp]),
+    "fgi_trajectory_batched": (_i, [_vp, _i, _vp, _P(fgi_action), _P(fgi_integrator), _d, _i, _P(_d),
+                                    _P(fgi_stats), _vp]),
     "fgi_link_update": (_i, [_vp, _P(fgi_geom), _d, _vp, _vp, _vp]),
     "fgi_reunitarize": (_i, [_vp, _P(fgi_geom), _vp, _vp]),
     "fgi_exp_su3": (_i, [_vp, _i, _vp, _d, _vp, _vp]),
@@ -380,6 +388,30 @@ class Context:
         d = st.as_dict()
         d["status"] = rc
         return dH.value, d
+
+    def trajectory_batched(self, chains, act, integ, tau, nsteps, allow_noconv=False):
+        """chains: list of dicts with dims, beta, kappa, U, P, eta (tensors on the
+        device, U and P updated in place).  Returns (dH list, stats)."""
+        n = len(chains)
+        arr = (fgi_chain * n)()
+        for i, ch in enumerate(chains):
+            su, sp, se = self._shapes(ch["dims"])
+            arr[i].dims = (ctypes.c_int * 4)(*[int(d) for d in ch["dims"]])
+            arr[i].beta = float(ch["beta"])
+            arr[i].kappa = float(ch.get("kappa", 0.0))
+            arr[i].U = _ptr(ch["U"], torch.complex128, su, "U")
+            arr[i].P = _ptr(ch["P"], torch.float64, sp, "P")
+            arr[i].eta = _ptr(ch.get("eta"), torch.complex128, se, "eta")
+        if isinstance(integ, str):
+            integ = integrator_builtin(integ)
+        dH = (ctypes.c_double * n)()
+        st = fgi_stats()
+        rc = _check(lib().fgi_trajectory_batched(self.h, n, ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(act.c()),
+                                                 ctypes.byref(integ), float(tau), int(nsteps), dH, ctypes.byref(st),
+                                                 _stream()), (FGI_ENOCONV,) if allow_noconv else ())
+        d = st.as_dict()
+        d["status"] = rc
+        return list(dH), d
 
     # ---- utilities
     def link_update(self, dims, h, P, U):

@@ -39,6 +39,8 @@ def test_struct_layouts_match_c_sizes():
     assert ctypes.sizeof(fgi.fgi_level) == 16 + 16 * 24
     assert ctypes.sizeof(fgi.fgi_integrator) == 8 + 4 * ctypes.sizeof(fgi.fgi_level)
     assert ctypes.sizeof(fgi.fgi_action) == 4 * 8 + 4 * 4
+    # fgi_chain: int dims[4], int pad, double beta, double kappa, 3 pointers
+    assert ctypes.sizeof(fgi.fgi_chain) == 64 and fgi.fgi_chain.beta.offset == 24
 
 
 @pytest.mark.parametrize("name", ["PQP", "QPQ", "PQPQP", "CAMPOSTRINI", "FG"])

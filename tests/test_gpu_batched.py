@@ -1,0 +1,90 @@
+"""Batched independent chains (row a10): one set of launches per MD sub-step
+for chains of different sizes and couplings.  Chains are independent, so each
+chain of a batch must reproduce, bitwise, its own single-chain trajectory, and
+match the CPU oracle to the FP64 parity tolerance."""
+import numpy as np
+import pytest
+import torch
+
+from paper_0910_2950_amd import fgi, synth
+from paper_0910_2950_amd.fgi import Action, Context
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+MIX = [((4, 4, 4, 4), 5.6, 0.150), ((2, 2, 2, 2), 6.0, 0.157), ((6, 4, 4, 6), 5.8, 0.153),
+       ((4, 4, 4, 4), 5.5, 0.155), ((4, 6, 2, 8), 5.9, 0.151)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def make_chains(spec, seed0, fermions=True):
+    out = []
+    for k, (dims, beta, kappa) in enumerate(spec):
+        U, P, eta, _ = synth.hot_start(dims, seed0 + k, fermions=fermions)
+        out.append(dict(dims=dims, beta=beta, kappa=kappa if fermions else 0.0, U0=U, P0=P, eta0=eta))
+    return out
+
+
+def run_batch(ctx, chains, act, name, n):
+    args = [dict(dims=c["dims"], beta=c["beta"], kappa=c["kappa"], U=dev(c["U0"]), P=dev(c["P0"]),
+                 eta=dev(c["eta0"]) if c["eta0"] is not None else None) for c in chains]
+    dH, st = ctx.trajectory_batched(args, act, name, 1.0, n)
+    return [(a["U"].cpu().numpy(), a["P"].cpu().numpy(), d) for a, d in zip(args, dH)], st
+
+
+def run_single(ctx, ch, act, name, n):
+    a = Action(beta=ch["beta"], kappa=ch["kappa"], cg_tol=act.cg_tol, prec=act.prec, link_recon=act.link_recon)
+    U, P = dev(ch["U0"]), dev(ch["P0"])
+    dH, _ = ctx.trajectory(ch["dims"], a, name, 1.0, n, U, P, dev(ch["eta0"]) if ch["eta0"] is not None else None)
+    return U.cpu().numpy(), P.cpu().numpy(), dH
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mp16"])
+def test_batch_equals_single_chains(ctx, prec):
+    chains = make_chains(MIX, 0x09102950 + 400)
+    act = Action(beta=0.0, cg_tol=1e-12 if prec == "fp64" else 1e-10, prec=prec, link_recon=12)
+    out, st = run_batch(ctx, chains, act, "FG", 3)
+    assert st["solves"] == len(chains) * (3 * 3 + 1 + 1)
+    for ch, (U, P, dH) in zip(chains, out):
+        Us, Ps, dHs = run_single(ctx, ch, act, "FG", 3)
+        assert np.array_equal(U, Us) and np.array_equal(P, Ps), ch["dims"]
+        assert dH == dHs
+
+
+def test_batch_matches_oracle(ctx, orc):
+    chains = make_chains(MIX, 0x09102950 + 401)
+    act = Action(beta=0.0, cg_tol=1e-14)
+    out, _ = run_batch(ctx, chains, act, "FG", 3)
+    for ch, (U, P, dH) in zip(chains, out):
+        Uo, Po, dHo, _, _ = orc.trajectory(ch["dims"], ch["beta"], orc.table("FG"), 1.0, 3, ch["U0"], ch["P0"],
+                                           kappa=ch["kappa"], eta=ch["eta0"], tol=1e-14)
+        assert np.max(np.abs(U - Uo)) < 1e-12
+        assert np.max(np.abs(P - Po)) < 1e-12 * np.max(np.abs(Po))
+        assert abs(dH - dHo) < 1e-9
+
+
+def test_batch_pure_gauge(ctx, orc):
+    chains = make_chains(MIX, 0x09102950 + 402, fermions=False)
+    act = Action(beta=0.0)
+    out, _ = run_batch(ctx, chains, act, "PQPQP", 4)
+    for ch, (U, P, dH) in zip(chains, out):
+        Uo, Po, dHo, _, _ = orc.trajectory(ch["dims"], ch["beta"], orc.table("PQPQP"), 1.0, 4, ch["U0"], ch["P0"])
+        assert np.max(np.abs(U - Uo)) < 1e-12 and abs(dH - dHo) < 1e-9
+
+
+def test_batch_rejects_mixed_fermion_content(ctx):
+    chains = make_chains(MIX[:2], 0x09102950 + 403)
+    chains[1]["kappa"] = 0.0
+    with pytest.raises(fgi.FgiError) as e:
+        run_batch(ctx, chains, Action(beta=0.0), "FG", 2)
+    assert e.value.code == fgi.FGI_EINVAL
