@@ -138,16 +138,13 @@ int fgi_create(fgi_ctx** out, int device);
 int fgi_destroy(fgi_ctx* ctx);
 /* Text of the calling thread's last failure ("" if none). */
 const char* fgi_last_error(void);
-/* Tuning/diagnostic options: "persistent" (0, default: per-phase kernels in
- * batches; 1: each inner CG run is one persistent cooperative launch with grid
- * barriers between its phases), "cg_batch" (iterations per batch between host
- * polls in the per-phase mode; each batch is one replay of a captured HIP
- * graph), "graphs" (0: launch the batch kernels one by one instead), "ru_delta"
- * (reliable-update residual
+/* Tuning/diagnostic options: "cg_batch" (CG iterations launched between host
+ * polls; each batch is one replay of a captured HIP graph), "graphs" (0: launch
+ * the batch kernels one by one instead), "ru_delta" (reliable-update residual
  * drop), "profile" (1: after every CG solve, time 16 back-to-back launches of
  * the bare Dslash hop on the solve's operator with HIP events), "profile_prec"
  * (profile only solves whose inner precision is 0 FP64 / 1 FP32 / 2 FP16;
- * -1 all), "profile_reset". */
+ * -1 all), "profile_reset".  An unknown name is FGI_EINVAL. */
 int fgi_set_option(fgi_ctx* ctx, const char* name, double value);
 /* Accumulated Dslash profile since the last reset: total ms of the timed bare
  * hop launches, their number, and output sites summed over them. */

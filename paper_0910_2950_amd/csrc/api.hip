@@ -249,7 +249,6 @@ int fgi_create(fgi_ctx** out, int device) {
         c->c.device = device;
         FGI_HIP(hipHostMalloc((void**)&c->c.host_scal, 64 * sizeof(double), hipHostMallocDefault));
         FGI_HIP(hipHostMalloc((void**)&c->c.host_state, sizeof(CGState), hipHostMallocDefault));
-        FGI_HIP(hipHostMalloc((void**)&c->c.host_aux, 64, hipHostMallocDefault));
         void* st = c->c.state.get(sizeof(CGState));
         FGI_HIP(hipMemset(st, 0, sizeof(CGState)));
         FGI_HIP(hipDeviceSynchronize());
@@ -266,7 +265,7 @@ int fgi_destroy(fgi_ctx* ctx) {
         DevBuf* bufs[] = {&c.gauge, &c.gauge_disp, &c.sloppy, &c.sloppy_disp, &c.mom, &c.force, &c.force2,
                           &c.scratch_mom, &c.eta, &c.phi, &c.X, &c.Xo, &c.Ye, &c.Yo, &c.tmp_e, &c.tmp_o,
                           &c.cg_r, &c.cg_p, &c.cg_q, &c.s_x, &c.s_r, &c.s_p, &c.s_q, &c.s_t, &c.s_norms,
-                          &c.h0, &c.hf0, &c.partial, &c.scal, &c.state, &c.phi2, &c.eta2, &c.user_tmp, &c.aux,
+                          &c.h0, &c.hf0, &c.partial, &c.scal, &c.state, &c.phi2, &c.eta2, &c.user_tmp,
                           &c.chi, &c.X2, &c.cdesc, &c.bstate, &c.bscal, &c.bh0, &c.bh1, &c.bres};
         for (DevBuf* b : bufs) b->release();
         for (hipEvent_t e : c.ev_pool) hipEventDestroy(e);
@@ -274,7 +273,6 @@ int fgi_destroy(fgi_ctx* ctx) {
         if (c.cap_stream) hipStreamDestroy(c.cap_stream);
         if (c.host_scal) hipHostFree(c.host_scal);
         if (c.host_state) hipHostFree(c.host_state);
-        if (c.host_aux) hipHostFree(c.host_aux);
         if (c.host_bstates) hipHostFree(c.host_bstates);
         if (c.host_bscal) hipHostFree(c.host_bscal);
         delete ctx;
@@ -292,8 +290,6 @@ int fgi_set_option(fgi_ctx* ctx, const char* name, double value) {
         } else if (n == "ru_delta") {
             if (!(value > 0 && value < 1)) throw Error(FGI_EINVAL, "ru_delta must be in (0,1)");
             c.ru_delta = value;
-        } else if (n == "persistent") {
-            c.use_persistent = value != 0;
         } else if (n == "graphs") {
             c.use_graphs = value != 0;
         } else if (n == "profile") {
@@ -331,7 +327,7 @@ int fgi_gauge_action(fgi_ctx* ctx, const fgi_geom* gg, double beta, const void* 
         pack_gauge(c, g, U, u);
         double* h = (double*)c.h0.get(sizeof(double) * g.V);
         ham_density(c, g, beta, u, nullptr, h);
-        double* part = (double*)c.partial.get(sizeof(double) * 65536);
+        double* part = partial_buf(c, g);
         double* scal = (double*)c.scal.get(sizeof(double) * 64);
         int nb = diff_partials(c, g.V, h, nullptr, part);
         final_sum(c, part, nb, scal);
@@ -350,7 +346,7 @@ int fgi_kinetic(fgi_ctx* ctx, const fgi_geom* gg, const void* P, double* T, void
         pack_mom(c, g, (const double*)P, pm);
         double* h = (double*)c.h0.get(sizeof(double) * g.V);
         ham_density(c, g, 0.0, nullptr, pm, h);
-        double* part = (double*)c.partial.get(sizeof(double) * 65536);
+        double* part = partial_buf(c, g);
         double* scal = (double*)c.scal.get(sizeof(double) * 64);
         int nb = diff_partials(c, g.V, h, nullptr, part);
         final_sum(c, part, nb, scal);
@@ -580,7 +576,7 @@ int fgi_pf_action(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const
         d2* x = (d2*)c.X.get(spinor_bytes(g));
         pack_even_spinor(c, g, phi, ph);
         f.solve(f.U, f.Us, act->kappa, ph, x);
-        double* part = (double*)c.partial.get(sizeof(double) * 65536);
+        double* part = partial_buf(c, g);
         double* scal = (double*)c.scal.get(sizeof(double) * 64);
         int nb = pf_density_partials(c, g, ph, x, nullptr, part);
         final_sum(c, part, nb, scal);
@@ -705,7 +701,7 @@ int fgi_hasen_action(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, co
         setup_fermion_fields(c, f, g, U);
         pack_even_spinor(c, g, phi2, f.phi[1]);
         f.hasen_solve(f.U, f.Us);
-        double* part = (double*)c.partial.get(sizeof(double) * 65536);
+        double* part = partial_buf(c, g);
         double* scal = (double*)c.scal.get(sizeof(double) * 64);
         int nb = pf_density_partials(c, g, f.chi, f.X2, nullptr, part);
         final_sum(c, part, nb, scal);
@@ -772,7 +768,7 @@ int fgi_poisson_brackets(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act
             }
         }
         double* fm = (double*)c.force.get(mom_bytes(g));
-        double* part = (double*)c.partial.get(sizeof(double) * 65536);
+        double* part = partial_buf(c, g);
         double* scal = (double*)c.scal.get(sizeof(double) * 64);
         const int terms = FGI_TERM_GAUGE | FGI_TERM_FERMION;
         // SST = sum F^2
@@ -951,7 +947,7 @@ extern "C" int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action
         }
         double* h0 = (double*)c.h0.get(sizeof(double) * g.V);
         double* h1 = (double*)c.hf0.get(sizeof(double) * g.V);
-        double* part = (double*)c.partial.get(sizeof(double) * 65536);
+        double* part = partial_buf(c, g);
         double* scal = (double*)c.scal.get(sizeof(double) * 64);
         d2 *eta = nullptr, *eta_2 = nullptr;
         double sf0 = 0.0;
@@ -1119,7 +1115,6 @@ extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain
             B.vol += d.g.V;
             B.links += 4L * d.g.V;
         }
-        if (B.nblk[GRID_VH] > 65536 || B.nblk[GRID_V] > 65536) throw Error(FGI_EINVAL, "batch too large");
         auto t0 = std::chrono::steady_clock::now();
         StreamScope ss(c, stream);
         ChainDesc* dcd = (ChainDesc*)c.cdesc.get(sizeof(ChainDesc) * nchains);
@@ -1152,7 +1147,7 @@ extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain
         }
         double* h0 = (double*)c.bh0.get(sizeof(double) * B.vol);
         double* h1 = (double*)c.bh1.get(sizeof(double) * B.vol);
-        double* part = (double*)c.partial.get(sizeof(double) * 65536);
+        double* part = partial_buf(c, B);
         double* res = (double*)c.bres.get(sizeof(double) * 2 * nchains);  // not shared with the solver's scalars
         ham_density_b(c, B, f.U, f.P, h0);
 

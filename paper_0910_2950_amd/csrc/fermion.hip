@@ -56,57 +56,57 @@ __device__ __forceinline__ void p_update(const cx<R> r[4][3], cx<R> p[4][3], R b
         }
 }
 
-// neighbour spinor loaders used by the hop sum
+// Neighbour spinor loaders used by the hop sum: fetch() issues the raw loads
+// of one site, get() converts them to the working precision (the FP16
+// conversion and its per-site scale fuse into one mixed-precision FMA) and
+// returns the factor the hop applies with its accumulating FMAs (1 here).
 template <int PIN, int G5IN, typename R> struct LoadPlain {
     SpinorPtr in;
-    __device__ __forceinline__ void operator()(int s, int Vh, cx<R> psi[4][3]) const {
-        SpinorIO<PIN, R>::load(in, s, Vh, psi);
+    typedef RawSp<PIN> Raw;
+    __device__ __forceinline__ void fetch(int s, int Vh, Raw& raw) const { fetch_sp<PIN>(in, s, Vh, raw); }
+    __device__ __forceinline__ R get(const Raw& raw, cx<R> psi[4][3]) const {
+        SpinorIO<PIN, R>::decode(raw, psi);
         if (G5IN) flip_lower(psi);
+        return R(1);
     }
 };
 
-// CG direction formed on the fly: p_new = r + beta p_old, rounded to p's storage
-template <int PP, int PX, typename R> struct LoadPNew {
-    SpinorPtr p, r;
-    R beta;
-    __device__ __forceinline__ void operator()(int s, int Vh, cx<R> v[4][3]) const {
-        cx<R> a[4][3];
-        SpinorIO<PX, R>::load(r, s, Vh, a);
-        SpinorIO<PP, R>::load(p, s, Vh, v);
-        p_update(a, v, beta);
-        if (PP == P16) quantize16(v);
-    }
-};
-
-template <int MU, int PL, int RECON, typename R, typename L>
-__device__ __forceinline__ void hop_dir(const Geom& g, int p, int s, const Coord& c, const void* links, const L& load,
-                                        cx<R> acc[4][3]) {
+// The eight hops of D, k = 2 mu + d: d = 0 the forward hop (1 - g_mu) U_mu(x)
+// psi(x + mu), d = 1 the backward hop (1 + g_mu) U_mu(x - mu)^+ psi(x - mu).
+// Each hop projects to a half spinor, multiplies by the link and accumulates
+// the rebuilt spinor times w = (storage scale) x (antiperiodic sign in t).
+template <int K, int PL, int RECON, typename R, typename L>
+__device__ __forceinline__ void hop(const Geom& g, int p, int s, const Coord& c, const void* links, const L& load,
+                                    cx<R> acc[4][3]) {
+    constexpr int MU = K >> 1;
+    constexpr bool FWD = (K & 1) == 0;
+    const int sn = cb_neighbour(g, c, MU, FWD ? +1 : -1);
     cx<R> psi[4][3], h[2][3], uh[2][3];
-    {   // forward hop: (1 - g_mu) U_mu(x) psi(x + mu)
-        int sn = cb_neighbour(g, c, MU, +1);
-        load(sn, g.Vh, psi);
-        spin_proj<MU, -1>(psi, h);
-        M3<R> u = LinkIO<PL, RECON, R>::load(links, MU, p, s, g.Vh);
-#pragma unroll
-        for (int j = 0; j < 2; j++)
-#pragma unroll
-            for (int a = 0; a < 3; a++) uh[j][a] = u.e[a][0] * h[j][0] + u.e[a][1] * h[j][1] + u.e[a][2] * h[j][2];
-        R bc = (MU == 3 && c.c[3] == g.L[3] - 1) ? R(-1) : R(1);
-        spin_recon_acc<MU, -1>(acc, uh, bc);
-    }
-    {   // backward hop: (1 + g_mu) U_mu(x - mu)^+ psi(x - mu)
-        int sn = cb_neighbour(g, c, MU, -1);
-        load(sn, g.Vh, psi);
-        spin_proj<MU, +1>(psi, h);
-        M3<R> u = LinkIO<PL, RECON, R>::load(links, MU, 1 - p, sn, g.Vh);
+    typename L::Raw rs;
+    load.fetch(sn, g.Vh, rs);
+    R w = load.get(rs, psi);
+    spin_proj<MU, FWD ? -1 : +1>(psi, h);
+    // the link is loaded after the projection: loads issued any earlier only
+    // raise the register count (and lower occupancy on large lattices)
+    RawLink<PL, RECON> rl;
+    fetch_link<PL, RECON>(links, MU, FWD ? p : 1 - p, FWD ? s : sn, g.Vh, rl);
+    const M3<R> u = LinkIO<PL, RECON, R>::decode(rl);
+    if constexpr (FWD) {
 #pragma unroll
         for (int j = 0; j < 2; j++)
 #pragma unroll
             for (int a = 0; a < 3; a++)
-                uh[j][a] = cmul(u.e[0][a], h[j][0]) + cmul(u.e[1][a], h[j][1]) + cmul(u.e[2][a], h[j][2]);
-        R bc = (MU == 3 && c.c[3] == 0) ? R(-1) : R(1);
-        spin_recon_acc<MU, +1>(acc, uh, bc);
+                uh[j][a] = cdot3(u.e[a][0], h[j][0], u.e[a][1], h[j][1], u.e[a][2], h[j][2]);
+        if (MU == 3 && c.c[3] == g.L[3] - 1) w = -w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+                uh[j][a] = cdot3c(u.e[0][a], h[j][0], u.e[1][a], h[j][1], u.e[2][a], h[j][2]);
+        if (MU == 3 && c.c[3] == 0) w = -w;
     }
+    spin_recon_acc<MU, FWD ? -1 : +1>(acc, uh, w);
 }
 
 template <int PL, int RECON, typename R, typename L>
@@ -117,51 +117,35 @@ __device__ __forceinline__ void hop_sum(const Geom& g, int p, int s, const void*
     for (int i = 0; i < 4; i++)
 #pragma unroll
         for (int k = 0; k < 3; k++) acc[i][k] = {R(0), R(0)};
-    hop_dir<0, PL, RECON>(g, p, s, c, links, load, acc);
-    hop_dir<1, PL, RECON>(g, p, s, c, links, load, acc);
-    hop_dir<2, PL, RECON>(g, p, s, c, links, load, acc);
-    hop_dir<3, PL, RECON>(g, p, s, c, links, load, acc);
+    hop<0, PL, RECON>(g, p, s, c, links, load, acc);
+    hop<1, PL, RECON>(g, p, s, c, links, load, acc);
+    hop<2, PL, RECON>(g, p, s, c, links, load, acc);
+    hop<3, PL, RECON>(g, p, s, c, links, load, acc);
+    hop<4, PL, RECON>(g, p, s, c, links, load, acc);
+    hop<5, PL, RECON>(g, p, s, c, links, load, acc);
+    hop<6, PL, RECON>(g, p, s, c, links, load, acc);
+    hop<7, PL, RECON>(g, p, s, c, links, load, acc);
 }
 
-// ------------------------------------------------ last-block reductions ---
-// Every block writes its partial; the last block to arrive (atomic counter)
-// sums all partials in a fixed order and publishes the scalar, so the value
-// does not depend on block scheduling.  Returns true in the last block.
-// b, nb: the block's logical index and the number of blocks taking part
-// (the chain's blocks in a batched launch); partials are stored by logical
-// index, so a chain reduces identically alone or inside a batch.
-__device__ __forceinline__ bool last_block_sum(double v, double* partial, unsigned* counter, double* lds,
-                                               double* total, int b, int nb) {
-    __shared__ int is_last;
-    double a[1] = {v};
-    block_sum<1>(a, lds);
-    if (threadIdx.x == 0) {
-        __hip_atomic_store(partial + b, a[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        unsigned prev = atomicAdd(counter, 1u);
-        is_last = (prev == (unsigned)nb - 1);
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double t = 0.0;
-    for (int k = threadIdx.x; k < nb; k += blockDim.x) t += __hip_atomic_load(partial + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    double tt[1] = {t};
-    block_sum<1>(tt, lds);
-    *total = tt[0];
-    if (threadIdx.x == 0) *counter = 0u;
-    return true;
-}
+// ------------------------------------------------------------ reductions ---
+// No atomics and no grid-scope fences: a reducing kernel writes one partial per
+// block (indexed by the block's logical number inside its chain), and the
+// kernel after it on the stream sums them in a fixed order (sum_partials), so
+// every value is independent of block scheduling and identical wherever it is
+// computed.  A last-block-done scheme would need an agent-scope release per
+// block, i.e. a write-back of the XCD's L2, which costs several microseconds
+// per launch on this part.
 
 // ---------------------------------------------------------- the kernel ---
 enum Mode {
     M_HOP = 0,    // out = [g5] acc
-    M_SCHUR = 1,  // out = center - kappa^2 [g5] acc          [|out|^2 -> *result]
-    M_CGQ = 2,    // CG: p = r + beta p (stored), q = p - kappa^2 acc, pAp = |q|^2 (= <p, Mhat^+ Mhat p>)
-    M_CGX = 3,    // CG: Ap = q - kappa^2 g5 acc; x += alpha p; r -= alpha Ap; |r|^2, next beta
-    M_RESID = 4,  // r = aux - (center - kappa^2 g5 acc), |r|^2 -> *result
-    M_HOPP = 5    // CG: out = D (r + beta p_old), the new direction formed per neighbour
+    M_SCHUR = 1,  // out = center - kappa^2 [g5] acc          [|out|^2 partials]
+    M_CGQ = 2,    // CG: q = p - kappa^2 acc (center p), |q|^2 partials (pAp)
+    M_CGX = 3,    // CG: Ap = q - kappa^2 g5 acc; x += alpha p; r -= alpha Ap; |r|^2 partials
+    M_RESID = 4   // r = aux - (center - kappa^2 g5 acc), |r|^2 partials
 };
+// With a CG state and partials, an M_HOP launch carries one extra block per
+// chain (logical index nb) that sums the M_CGQ partials into st->pAp.
 
 struct DArgs {
     Geom g;
@@ -169,9 +153,7 @@ struct DArgs {
     double kappa2;
     const void* links;
     SpinorPtr in, center, out, aux, x, r;
-    double* partial;
-    unsigned* counter;
-    double* result;
+    double* partial;   // per-block partials written (reducing modes) or read (M_HOP in CG)
     CGState* st;
     int iter;   // absolute index, or the offset from st->base inside a CG batch
     int g5out;
@@ -182,35 +164,35 @@ template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5
 __device__ __forceinline__ void dslash_body(const DArgs& A, int b, int nb, double* lds) {
     typedef typename Real<PIN == P64 ? P64 : P32>::T R;
     const Geom& g = A.g;
-    const int iter = A.st ? A.st->base + A.iter : A.iter;
-    if (A.st) {  // uniform over the chain's blocks: converged / masked chains no-op
-        if (A.gate ? !A.st->act : A.st->stop_at <= iter) return;
+    // solver state, read through the pointer (a private copy indexed by the
+    // iteration parity would be placed in LDS); nothing read here is written
+    // by the same launch
+    const CGState* S = A.st;
+    const int iter = S ? S->base + A.iter : A.iter;
+    if (S) {  // uniform over the chain's blocks: converged / masked chains no-op
+        if (A.gate ? !S->act : S->stop_at <= iter) return;
+        if constexpr (MODE == M_HOP) {
+            if (b >= nb) {  // the reduction block: pAp of this iteration
+                if (A.partial) {
+                    const double pAp = sum_partials(A.partial, nb, lds);
+                    if (threadIdx.x == 0) A.st->pAp = pAp;
+                }
+                return;
+            }
+        }
     }
     int s = b * DBS + threadIdx.x;
     double nrm = 0.0;
     if (s < g.Vh) {
         cx<R> acc[4][3];
-        if constexpr (MODE == M_HOPP) {
-            LoadPNew<PIN, PX, R> ld{A.in, A.r, R(A.st->beta)};
-            hop_sum<PL, RECON, R>(g, A.p_out, s, A.links, ld, acc);
-        } else {
-            LoadPlain<PIN, G5IN, R> ld{A.in};
-            hop_sum<PL, RECON, R>(g, A.p_out, s, A.links, ld, acc);
-        }
+        LoadPlain<PIN, G5IN, R> ld{A.in};
+        hop_sum<PL, RECON, R>(g, A.p_out, s, A.links, ld, acc);
         if (A.g5out) flip_lower(acc);
-        if (MODE == M_HOP || MODE == M_HOPP) {
+        if (MODE == M_HOP) {
             SpinorIO<POUT, R>::store(A.out, s, g.Vh, acc);
         } else {
             cx<R> cen[4][3];
             SpinorIO<PC, R>::load(A.center, s, g.Vh, cen);
-            if constexpr (MODE == M_CGQ) {
-                // the new search direction at this site, stored in place of p_old
-                cx<R> rr[4][3];
-                SpinorIO<PX, R>::load(A.r, s, g.Vh, rr);
-                p_update(rr, cen, R(A.st->beta));
-                SpinorIO<PC, R>::store(A.center, s, g.Vh, cen);
-                if (PC == P16) quantize16(cen);
-            }
             const R k2 = R(A.kappa2);
 #pragma unroll
             for (int i = 0; i < 4; i++)
@@ -236,7 +218,7 @@ __device__ __forceinline__ void dslash_body(const DArgs& A, int b, int nb, doubl
                 SpinorIO<POUT, R>::store(A.out, s, g.Vh, acc);
             } else if (MODE == M_CGX) {
                 typedef typename Real<PX>::T RX;
-                const RX al = RX(A.st->rr[iter & 1] / A.st->pAp);
+                const RX al = RX(S->rr[iter & 1] / S->pAp);
                 cx<RX> pv[4][3], xv[4][3], rv[4][3];
                 SpinorIO<PC, RX>::load(A.aux, s, g.Vh, pv);  // p has the precision of q
                 SpinorIO<PX, RX>::load(A.x, s, g.Vh, xv);
@@ -255,27 +237,20 @@ __device__ __forceinline__ void dslash_body(const DArgs& A, int b, int nb, doubl
             }
         }
     }
-    if (MODE == M_HOP || MODE == M_HOPP) return;
-    if (MODE == M_SCHUR && !A.result) return;
-    double total;
-    bool last = last_block_sum(nrm, A.partial, A.counter, lds, &total, b, nb);
-    if (!last || threadIdx.x != 0) return;
-    if (MODE == M_CGQ) {
-        A.st->pAp = total;
-    } else if (MODE == M_CGX) {
-        A.st->beta = total / A.st->rr[iter & 1];
-        A.st->rr[(iter + 1) & 1] = total;
-        A.st->iters = iter + 1;
-        if (total <= A.st->rr_stop) A.st->stop_at = iter + 1;
-    } else {
-        *A.result = total;
-    }
+    if (MODE == M_HOP || !A.partial) return;
+    double v[1] = {nrm};
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) A.partial[b] = v[0];
 }
 
 template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN>
 __global__ void __launch_bounds__(DBS) k_dslash(DArgs A) {
     __shared__ double lds[DBS / 64];
-    dslash_body<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN>(A, xcd_block(blockIdx.x, gridDim.x), gridDim.x, lds);
+    // site blocks in XCD-aware order (the same order in every kernel of the
+    // solver, so a site stays on one XCD); a reduction block comes last
+    const int nb = (A.g.Vh + DBS - 1) / DBS;
+    const int b = (int)blockIdx.x < nb ? xcd_block(blockIdx.x, nb) : blockIdx.x;
+    dslash_body<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN>(A, b, nb, lds);
 }
 
 // one chain's part of a concatenated spinor field / link field
@@ -299,12 +274,13 @@ template <int PL, int RECON> __device__ __forceinline__ size_t link_byte_off(con
 }
 
 // batched launch: every chain of the batch with its own geometry, kappa,
-// solver state (base.st[c]) and result slot (base.result[c])
+// solver state (base.st[c]) and partials slice; nsb site blocks in all, and
+// blocks past them (an M_HOP with partials) are the chains' reduction blocks
 template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN>
-__global__ void __launch_bounds__(DBS) k_dslash_b(DArgs base, const ChainDesc* __restrict__ cd, int nc) {
+__global__ void __launch_bounds__(DBS) k_dslash_b(DArgs base, const ChainDesc* __restrict__ cd, int nc, int nsb) {
     __shared__ double lds[DBS / 64];
-    const int gb = xcd_block(blockIdx.x, gridDim.x);
-    const int c = find_chain(cd, nc, gb, GRID_VH);
+    const int gb = (int)blockIdx.x < nsb ? xcd_block(blockIdx.x, nsb) : blockIdx.x;
+    const int c = gb < nsb ? find_chain(cd, nc, gb, GRID_VH) : gb - nsb;
     const ChainDesc& d = cd[c];
     DArgs A = base;
     A.g = d.g;
@@ -318,218 +294,90 @@ __global__ void __launch_bounds__(DBS) k_dslash_b(DArgs base, const ChainDesc* _
     A.r = spin_off<PX>(base.r, d);
     A.partial = base.partial ? base.partial + d.blk0[GRID_VH] : nullptr;
     A.st = base.st ? base.st + c : nullptr;
-    A.counter = A.st ? &A.st->counter : nullptr;
-    A.result = base.result ? base.result + c : nullptr;
-    dslash_body<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN>(A, gb - d.blk0[GRID_VH], d.nblk[GRID_VH], lds);
+    const int b = gb < nsb ? gb - d.blk0[GRID_VH] : d.nblk[GRID_VH];
+    dslash_body<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN>(A, b, d.nblk[GRID_VH], lds);
 }
 
-// advance the batch base (last node of a CG batch)
-__global__ void k_advance(CGState* st, int n) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) st->base += n;
-}
-
-__global__ void k_advance_b(CGState* st, int nc, int n) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < nc) st[c].base += n;
-}
-
-// --------------------------------------------------- persistent CG kernel ---
-// All iterations of one inner CG run in a single cooperative launch: the four
-// Dslash-shaped phases of an iteration are separated by grid barriers.  Every
-// block owns one contiguous chunk of even and odd checkerboard sites (XCD-aware
-// block order) in every phase, so its links and spinors stay in its XCD's L2.
-// The scalar recurrences (alpha, beta, |r|^2) are identical in every block: a
-// barrier's last arriving block sums the block partials in a fixed order and
-// publishes the total with the release of the barrier.
-struct PArgs {
-    Geom g;
-    double kappa2;
-    const void* links;
-    SpinorPtr x, r, p, q, t;
-    double* part;        // [gridDim] block partials
-    double* total;       // [2] published reduction results
-    unsigned* bar;       // [0] arrivals, [1] generation
-    CGState* st;
-    int* err;            // set to 1 when a barrier wait exceeds its spin limit
-    int max_iters;       // iterations allowed in this launch (>= 1)
-    int chunk;           // sites per block (multiple of the block size)
-};
-
-// Grid barrier with an optional fixed-order reduction of part[0..nb) into
-// *total by the last arriving block.  Waits are bounded: after 2^26 polls
-// (about a second) the block flags *err; every block checks *err after each
-// barrier and leaves the iteration loop, so the kernel always terminates.
-__device__ __forceinline__ double grid_barrier(unsigned* bar, double* part, double* total, bool reduce, int* err,
-                                               double* lds, bool* abort) {
-    __shared__ double result;
-    __shared__ int last;
-    __shared__ int aborted;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned gen = __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        unsigned arrived = atomicAdd(bar, 1u);
-        last = (arrived == gridDim.x - 1);
-        if (!last) {
-            long spins = 0;
-            while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (++spins > (1L << 26)) {
-                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        __threadfence();
-        aborted = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    *abort = aborted != 0;
-    if (last) {
-        if (reduce) {
-            double t = 0.0;
-            for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x)
-                t += __hip_atomic_load(part + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            double v[1] = {t};
-            block_sum<1>(v, lds);
-            if (threadIdx.x == 0) {
-                __hip_atomic_store(total, v[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                result = v[0];
-            }
-        }
-        if (threadIdx.x == 0) {
-            __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __syncthreads();
-        return reduce ? result : 0.0;
-    }
-    if (reduce) {
-        if (threadIdx.x == 0) result = __hip_atomic_load(total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        return result;
-    }
-    return 0.0;
-}
-
-template <int PP, int PX, int PL, int RECON>
-__global__ void __launch_bounds__(DBS) k_cg_persistent(PArgs A) {
+// First kernel of a CG iteration: p = r + beta p, stored in p's precision.
+// Later iterations of a run take |r_iter|^2 from the previous M_CGX's
+// partials, summed in every block in the same order (so all blocks agree
+// bitwise), and beta = rr / rr_prev; block 0 records rr and beta, or the
+// stop once rr <= rr_stop, for the kernels after it.  The first iteration of
+// a run (start or reliable update) takes rr and beta from the host.
+template <int PP, int PX>
+__device__ __forceinline__ void cg_p_body(int Vh, SpinorPtr p, SpinorPtr r, CGState* st, const double* partial,
+                                          int j, int b, int nb, double* lds) {
     typedef typename Real<PP == P64 ? P64 : P32>::T R;
-    typedef typename Real<PX>::T RX;
+    const int iter = st->base + j;
+    if (st->stop_at <= iter) return;
+    double beta = st->beta;
+    if (iter != st->base0) {
+        const double rr = sum_partials(partial, nb, lds);
+        const bool stop = rr <= st->rr_stop;
+        beta = rr / st->rr[(iter - 1) & 1];
+        if (b == 0 && threadIdx.x == 0) {
+            st->rr[iter & 1] = rr;
+            if (stop) st->stop_at = iter;
+            else st->beta = beta;
+        }
+        if (stop) return;
+    }
+    const int s = b * DBS + threadIdx.x;
+    if (s >= Vh) return;
+    cx<R> rv[4][3], pv[4][3];
+    SpinorIO<PX, R>::load(r, s, Vh, rv);
+    SpinorIO<PP, R>::load(p, s, Vh, pv);
+    p_update(rv, pv, R(beta));
+    SpinorIO<PP, R>::store(p, s, Vh, pv);
+}
+
+template <int PP, int PX>
+__global__ void __launch_bounds__(DBS) k_cg_p(int Vh, SpinorPtr p, SpinorPtr r, CGState* st, const double* partial,
+                                              int j) {
     __shared__ double lds[DBS / 64];
-    const Geom& g = A.g;
-    const int b = xcd_block(blockIdx.x, gridDim.x);
-    const int s0 = b * A.chunk, s1 = min(s0 + A.chunk, g.Vh);
-    const R k2 = R(A.kappa2);
-    // every block reads the state before the first barrier; block 0 rewrites it
-    // only after the last one
-    const CGState S = *A.st;
-    int iter = S.base;
-    if (S.stop_at <= iter) return;
-    double rr = S.rr[iter & 1];
-    double rr_prev = S.rr[(iter + 1) & 1];
-    double beta = S.beta;
-    bool stopped = false, abort = false;
-    for (int j = 0; j < A.max_iters; j++) {
-        // t = D_oe (r + beta p)
-        for (int s = s0 + (int)threadIdx.x; s < s1; s += DBS) {
-            cx<R> acc[4][3];
-            LoadPNew<PP, PX, R> ld{A.p, A.r, R(beta)};
-            hop_sum<PL, RECON, R>(g, 1, s, A.links, ld, acc);
-            SpinorIO<PP, R>::store(A.t, s, g.Vh, acc);
-        }
-        grid_barrier(A.bar, A.part, A.total, false, A.err, lds, &abort);
-        if (abort) break;
-        // p = r + beta p; q = p - k^2 D_eo t; pAp = |q|^2
-        double nq = 0.0;
-        for (int s = s0 + (int)threadIdx.x; s < s1; s += DBS) {
-            cx<R> acc[4][3], cen[4][3], rv[4][3];
-            LoadPlain<PP, 0, R> ld{A.t};
-            hop_sum<PL, RECON, R>(g, 0, s, A.links, ld, acc);
-            SpinorIO<PX, R>::load(A.r, s, g.Vh, rv);
-            SpinorIO<PP, R>::load(A.p, s, g.Vh, cen);
-            p_update(rv, cen, R(beta));
-            SpinorIO<PP, R>::store(A.p, s, g.Vh, cen);
-            if (PP == P16) quantize16(cen);
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-#pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    acc[i][k] = cen[i][k] - k2 * acc[i][k];
-                    nq += double(acc[i][k].re) * double(acc[i][k].re) + double(acc[i][k].im) * double(acc[i][k].im);
-                }
-            SpinorIO<PP, R>::store(A.q, s, g.Vh, acc);
-        }
-        {
-            double v[1] = {nq};
-            block_sum<1>(v, lds);
-            if (threadIdx.x == 0) __hip_atomic_store(A.part + blockIdx.x, v[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        const double pAp = grid_barrier(A.bar, A.part, A.total, true, A.err, lds, &abort);
-        if (abort) break;
-        const double alpha = rr / pAp;
-        // t = D_oe g5 q
-        for (int s = s0 + (int)threadIdx.x; s < s1; s += DBS) {
-            cx<R> acc[4][3];
-            LoadPlain<PP, 1, R> ld{A.q};
-            hop_sum<PL, RECON, R>(g, 1, s, A.links, ld, acc);
-            SpinorIO<PP, R>::store(A.t, s, g.Vh, acc);
-        }
-        grid_barrier(A.bar, A.part, A.total, false, A.err, lds, &abort);
-        if (abort) break;
-        // Ap = q - k^2 g5 D_eo t; x += alpha p; r -= alpha Ap
-        double nr = 0.0;
-        for (int s = s0 + (int)threadIdx.x; s < s1; s += DBS) {
-            cx<R> acc[4][3], cen[4][3];
-            LoadPlain<PP, 0, R> ld{A.t};
-            hop_sum<PL, RECON, R>(g, 0, s, A.links, ld, acc);
-            flip_lower(acc);
-            SpinorIO<PP, R>::load(A.q, s, g.Vh, cen);
-            cx<RX> pv[4][3], xv[4][3], rv[4][3];
-            SpinorIO<PP, RX>::load(A.p, s, g.Vh, pv);
-            SpinorIO<PX, RX>::load(A.x, s, g.Vh, xv);
-            SpinorIO<PX, RX>::load(A.r, s, g.Vh, rv);
-            const RX al = RX(alpha);
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-#pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    cx<R> a = cen[i][k] - k2 * acc[i][k];
-                    cx<RX> ap = {RX(a.re), RX(a.im)};
-                    xv[i][k] = xv[i][k] + al * pv[i][k];
-                    rv[i][k] = rv[i][k] - al * ap;
-                    nr += double(rv[i][k].re) * double(rv[i][k].re) + double(rv[i][k].im) * double(rv[i][k].im);
-                }
-            SpinorIO<PX, RX>::store(A.x, s, g.Vh, xv);
-            SpinorIO<PX, RX>::store(A.r, s, g.Vh, rv);
-        }
-        {
-            double v[1] = {nr};
-            block_sum<1>(v, lds);
-            if (threadIdx.x == 0) __hip_atomic_store(A.part + blockIdx.x, v[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        const double rr_new = grid_barrier(A.bar, A.part, A.total + 1, true, A.err, lds, &abort);
-        if (abort) break;
-        beta = rr_new / rr;
-        rr_prev = rr;
-        rr = rr_new;
-        iter++;
-        if (rr_new <= S.rr_stop) {
-            stopped = true;
-            break;
+    const int nb = (Vh + DBS - 1) / DBS;
+    cg_p_body<PP, PX>(Vh, p, r, st, partial, j, xcd_block(blockIdx.x, nb), nb, lds);
+}
+
+template <int PP, int PX>
+__global__ void __launch_bounds__(DBS) k_cg_p_b(const ChainDesc* __restrict__ cd, int nc, SpinorPtr p, SpinorPtr r,
+                                                CGState* st, const double* partial, int j) {
+    __shared__ double lds[DBS / 64];
+    const int gb = xcd_block(blockIdx.x, gridDim.x);
+    const int c = find_chain(cd, nc, gb, GRID_VH);
+    const ChainDesc& d = cd[c];
+    cg_p_body<PP, PX>(d.g.Vh, spin_off<PP>(p, d), spin_off<PX>(r, d), st + c, partial + d.blk0[GRID_VH], j,
+                      gb - d.blk0[GRID_VH], d.nblk[GRID_VH], lds);
+}
+
+// Last node of a CG batch: fold the |r|^2 partials of the batch's last
+// iteration into the state (so the host sees a finished run at once) and
+// move the batch base.  The next batch's first direction update sums the
+// same partials again, in the same order, and agrees bitwise.
+__device__ __forceinline__ void advance_body(CGState* st, const double* partial, int nb, int n, double* lds) {
+    const int it = st->base + n;  // first iteration of the next batch
+    if (st->stop_at == INT_MAX) {
+        const double rr = sum_partials(partial, nb, lds);
+        if (threadIdx.x == 0) {
+            st->rr[it & 1] = rr;
+            if (rr <= st->rr_stop) st->stop_at = it;
         }
     }
-    if (b == 0 && threadIdx.x == 0 && !abort) {
-        CGState o = S;
-        o.rr[iter & 1] = rr;            // |r|^2 after the last iteration
-        o.rr[(iter + 1) & 1] = rr_prev; // and before it (a restart needs both)
-        o.beta = beta;
-        o.base = iter;
-        o.iters = iter;
-        o.stop_at = stopped ? iter : INT_MAX;
-        *A.st = o;
-    }
+    __syncthreads();
+    if (threadIdx.x == 0) st->base = it;
+}
+
+__global__ void __launch_bounds__(DBS) k_advance(CGState* st, const double* partial, int nb, int n) {
+    __shared__ double lds[DBS / 64];
+    advance_body(st, partial, nb, n, lds);
+}
+
+// one block per chain
+__global__ void __launch_bounds__(DBS) k_advance_b(const ChainDesc* __restrict__ cd, CGState* st,
+                                                   const double* partial, int n) {
+    __shared__ double lds[DBS / 64];
+    const ChainDesc& d = cd[blockIdx.x];
+    advance_body(st + blockIdx.x, partial + d.blk0[GRID_VH], d.nblk[GRID_VH], n, lds);
 }
 
 // conversion between storage precisions (through FP64 registers)
@@ -760,7 +608,8 @@ static SpinorPtr sp(const void* v, float* norm = nullptr) { return SpinorPtr{(vo
 
 template <int MODE, int PIN, int PC, int POUT, int PX, int G5IN>
 static void launch_dslash(Ctx& c, const FermionOp& op, DArgs& a) {
-    int nb = nblk(a.g.Vh, DBS);
+    // an M_HOP inside CG (state and partials) carries the pAp reduction block
+    int nb = nblk(a.g.Vh, DBS) + ((MODE == M_HOP && a.st && a.partial) ? 1 : 0);
     if constexpr (PIN == P64) {
         if (op.prec != P64) throw Error(-1, "FP64 spinors need FP64 links");
         hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, P64, 18, G5IN>), dim3(nb), dim3(DBS), 0, c.stream, a);
@@ -787,7 +636,6 @@ static DArgs base_args(const FermionOp& op, int p_out) {
 }
 
 static CGState* dev_state(Ctx& c) { return (CGState*)c.state.get(sizeof(CGState)); }
-static unsigned* dev_counter(Ctx& c) { return (unsigned*)((char*)c.state.get(sizeof(CGState)) + offsetof(CGState, counter)); }
 
 void dslash(Ctx& c, const FermionOp& op, int out_parity, int prec_in, SpinorPtr in, int prec_out, SpinorPtr out) {
     DArgs a = base_args(op, out_parity);
@@ -862,7 +710,7 @@ void fermion_force(Ctx& c, const FermionOp& op64, const d2* Xe, double* F, doubl
 
 // ---------------------------------------------------------------- CG ------
 static double norm2_sync(Ctx& c, const Geom& g, const d2* v) {
-    double* part = (double*)c.partial.get(sizeof(double) * 65536);
+    double* part = partial_buf(c, g);
     double* scal = (double*)c.scal.get(sizeof(double) * 64);
     int nb = nblk(g.Vh, DBS);
     hipLaunchKernelGGL(k_norm2_partials, dim3(nb), dim3(DBS), 0, c.stream, g.Vh, v, part);
@@ -891,10 +739,9 @@ static double true_residual(Ctx& c, const FermionOp& op64, const d2* phi, const 
     b.aux = sp(phi);
     b.out = sp(r64);
     b.g5out = 1;
-    b.partial = (double*)c.partial.get(sizeof(double) * 65536);
-    b.counter = dev_counter(c);
-    b.result = scal + 1;
+    b.partial = partial_buf(c, g);
     launch_dslash<M_RESID, P64, P64, P64, P64, 0>(c, op64, b);
+    final_sum(c, b.partial, nblk(g.Vh, DBS), scal + 1);
     FGI_HIP(hipMemcpyAsync(c.host_scal + 1, scal + 1, sizeof(double), hipMemcpyDeviceToHost, c.stream));
     FGI_HIP(hipStreamSynchronize(c.stream));
     return c.host_scal[1];
@@ -904,34 +751,38 @@ struct CGVecs {
     SpinorPtr x, r, p, q, t;  // x, r in PX; p, q, t in PP
 };
 
-// One CG iteration on A = Mhat^+ Mhat in four Dslash-shaped kernels; the
-// iteration index is st->base + j so a captured batch can be replayed.
-//   t = D_oe (r + beta p)            [p formed per neighbour]
-//   p = r + beta p; q = p - k^2 D_eo t; pAp = |q|^2
-//   t = D_oe g5 q                    [bare hop: the profiled kernel]
-//   Ap = q - k^2 g5 D_eo t; x += alpha p; r -= alpha Ap; rr, beta
+// One CG iteration on A = Mhat^+ Mhat: a direction update and four
+// Dslash-shaped kernels; the iteration index is st->base + j so a captured
+// batch can be replayed.
+//   rr = sum of the previous |r|^2 partials, beta, stop test; p = r + beta p
+//   t = D_oe p
+//   q = p - k^2 D_eo t; |q|^2 partials
+//   t = D_oe g5 q; pAp = sum of the |q|^2 partials  [one extra block]
+//   Ap = q - k^2 g5 D_eo t; x += alpha p; r -= alpha Ap; |r|^2 partials
+// Each reduction's partials are consumed by the next kernel that reads them,
+// before the next reduction writes, so one buffer serves both.
 template <int PP, int PX>
 static void cg_iteration(Ctx& c, const FermionOp& ops, const CGVecs& v, int j) {
     CGState* st = dev_state(c);
-    double* part = (double*)c.partial.get(sizeof(double) * 65536);
-    unsigned* cnt = dev_counter(c);
+    double* part = partial_buf(c, *ops.g);
+    const int Vh = ops.g->Vh;
+    hipLaunchKernelGGL((k_cg_p<PP, PX>), dim3(nblk(Vh, DBS)), dim3(DBS), 0, c.stream, Vh, v.p, v.r, st,
+                       (const double*)part, j);
+    FGI_LAUNCH_CHECK();
     {
         DArgs a = base_args(ops, 1);
         a.in = v.p;
-        a.r = v.r;
         a.out = v.t;
         a.st = st;
         a.iter = j;
-        launch_dslash<M_HOPP, PP, PP, PP, PX, 0>(c, ops, a);
+        launch_dslash<M_HOP, PP, PP, PP, PX, 0>(c, ops, a);
     }
     {
         DArgs a = base_args(ops, 0);
         a.in = v.t;
         a.center = v.p;
-        a.r = v.r;
         a.out = v.q;
         a.partial = part;
-        a.counter = cnt;
         a.st = st;
         a.iter = j;
         launch_dslash<M_CGQ, PP, PP, PP, PX, 0>(c, ops, a);
@@ -940,6 +791,7 @@ static void cg_iteration(Ctx& c, const FermionOp& ops, const CGVecs& v, int j) {
         DArgs a = base_args(ops, 1);
         a.in = v.q;
         a.out = v.t;
+        a.partial = part;
         a.st = st;
         a.iter = j;
         launch_dslash<M_HOP, PP, PP, PP, PX, 1>(c, ops, a);
@@ -953,18 +805,18 @@ static void cg_iteration(Ctx& c, const FermionOp& ops, const CGVecs& v, int j) {
         a.r = v.r;
         a.g5out = 1;
         a.partial = part;
-        a.counter = cnt;
         a.st = st;
         a.iter = j;
         launch_dslash<M_CGX, PP, PP, PP, PX, 0>(c, ops, a);
     }
 }
 
-// B iterations then base += B, on c.stream
+// B iterations then the batch's closing reduction and base += B, on c.stream
 template <int PP, int PX>
 static void cg_batch_eager(Ctx& c, const FermionOp& ops, const CGVecs& v, int B) {
     for (int j = 0; j < B; j++) cg_iteration<PP, PX>(c, ops, v, j);
-    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c.stream, dev_state(c), B);
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(DBS), 0, c.stream, dev_state(c), (const double*)partial_buf(c, *ops.g),
+                       nblk(ops.g->Vh, DBS), B);
     FGI_LAUNCH_CHECK();
 }
 
@@ -1018,7 +870,8 @@ static std::string graph_key(const char* what, Ctx& c, const FermionOp& ops, con
     char key[512];
     snprintf(key, sizeof key, "%s/%d/%d/%p/%.17g/%d/%d/%d/%d/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%d", what, PP, PX,
              ops.links, ops.kappa, ops.prec, ops.recon, ops.g->L[0], ops.g->L[1], ops.g->L[2], ops.g->L[3],
-             ops.g->Vh, v.x.v, v.r.v, v.p.v, v.q.v, v.t.v, (void*)v.p.norm, (void*)dev_state(c), c.partial.p, n);
+             ops.g->Vh, v.x.v, v.r.v, v.p.v, v.q.v, v.t.v, (void*)v.p.norm, (void*)dev_state(c),
+             (void*)partial_buf(c, *ops.g), n);
     return key;
 }
 
@@ -1042,66 +895,6 @@ static void zero_spinor(Ctx& c, const Geom& g, void* v, int prec) {
     if (prec == P16) throw Error(-1, "zero_spinor: FP16");
     hipLaunchKernelGGL(k_zero, dim3(nblk((long)n, 256)), dim3(256), 0, c.stream, n, (double*)v);
     FGI_LAUNCH_CHECK();
-}
-
-// Resources of the persistent solver: barrier words, error flag, totals.
-struct PersistentAux {
-    unsigned bar[2];
-    int err;
-    int pad;
-    double total[2];
-};
-
-__global__ void k_reset_aux(PersistentAux* a) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        a->bar[0] = 0;
-        a->bar[1] = 0;
-        a->err = 0;
-    }
-}
-
-template <int PP, int PX, int PL, int RC>
-static void launch_persistent_t(Ctx& c, PArgs& a) {
-    const void* f = (const void*)k_cg_persistent<PP, PX, PL, RC>;
-    int per_cu = 0;
-    FGI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, DBS, 0));
-    int dev = 0, ncu = 0;
-    FGI_HIP(hipGetDevice(&dev));
-    FGI_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    int need = nblk(a.g.Vh, DBS);
-    int nb = std::min(need, std::max(1, per_cu) * ncu);
-    a.chunk = nblk(nblk(a.g.Vh, nb), DBS) * DBS;
-    nb = nblk(a.g.Vh, a.chunk);
-    void* args[] = {&a};
-    FGI_HIP(hipLaunchCooperativeKernel(f, dim3(nb), dim3(DBS), args, 0, c.stream));
-}
-
-template <int PP, int PX>
-static void launch_persistent(Ctx& c, const FermionOp& ops, const CGVecs& v, int max_iters, PersistentAux* aux) {
-    PArgs a{};
-    a.g = *ops.g;
-    a.kappa2 = ops.kappa * ops.kappa;
-    a.links = ops.links;
-    a.x = v.x;
-    a.r = v.r;
-    a.p = v.p;
-    a.q = v.q;
-    a.t = v.t;
-    a.part = (double*)c.partial.get(sizeof(double) * 65536);
-    a.total = aux->total;
-    a.bar = aux->bar;
-    a.err = &aux->err;
-    a.st = dev_state(c);
-    a.max_iters = max_iters;
-    hipLaunchKernelGGL(k_reset_aux, dim3(1), dim3(64), 0, c.stream, aux);
-    FGI_LAUNCH_CHECK();
-    if constexpr (PP == P64) {
-        launch_persistent_t<PP, PX, P64, 18>(c, a);
-    } else {
-        if (ops.prec == P32 && ops.recon == 18) launch_persistent_t<PP, PX, P32, 18>(c, a);
-        else if (ops.prec == P32) launch_persistent_t<PP, PX, P32, 12>(c, a);
-        else launch_persistent_t<PP, PX, P16, 12>(c, a);
-    }
 }
 
 template <int PP, int PX>
@@ -1140,7 +933,7 @@ static CGResult cg_run(Ctx& c, const FermionOp& op64, const FermionOp& ops, cons
         convert<P64, PX>(c, g, sp(phi), v.r);
         convert<P64, PP>(c, g, sp(phi), v.p);
     }
-    c.partial.get(sizeof(double) * 65536);  // allocate before any capture
+    partial_buf(c, g);  // allocate before any capture
     CGState* st = dev_state(c);
     CGState h{};
     h.rr[0] = bb;
@@ -1148,36 +941,22 @@ static CGResult cg_run(Ctx& c, const FermionOp& op64, const FermionOp& ops, cons
     h.beta = 0.0;
     h.stop_at = INT_MAX;
     h.base = 0;
-    h.counter = 0;
+    h.base0 = 0;
     hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, c.stream, st, h);
     FGI_LAUNCH_CHECK();
     const bool prof = c.profile && (c.profile_prec < 0 || c.profile_prec == PP);
     const int B = c.cg_batch;
-    const bool persistent = c.use_persistent;
-    PersistentAux* aux = (PersistentAux*)c.aux.get(sizeof(PersistentAux));
     GraphEntry* ge = nullptr;
-    if (c.use_graphs && !persistent)
+    if (c.use_graphs)
         ge = &cached_graph(c, graph_key<PP, PX>("cg", c, ops, v, B), [&] { cg_batch_eager<PP, PX>(c, ops, v, B); });
     int k = 0;  // iteration index of the next batch
     for (;;) {
-        int kend;
-        CGState hs;
-        if (persistent) {
-            launch_persistent<PP, PX>(c, ops, v, maxiter - k, aux);
-            FGI_HIP(hipMemcpyAsync(c.host_state, st, sizeof(CGState), hipMemcpyDeviceToHost, c.stream));
-            FGI_HIP(hipMemcpyAsync(c.host_aux, &aux->err, sizeof(int), hipMemcpyDeviceToHost, c.stream));
-            FGI_HIP(hipStreamSynchronize(c.stream));
-            if (*c.host_aux) throw Error(-2, "CG: grid barrier wait exceeded its limit");
-            hs = *c.host_state;
-            kend = hs.base;
-        } else {
-            if (ge) FGI_HIP(hipGraphLaunch(ge->exec, c.stream));
-            else cg_batch_eager<PP, PX>(c, ops, v, B);
-            FGI_HIP(hipMemcpyAsync(c.host_state, st, sizeof(CGState), hipMemcpyDeviceToHost, c.stream));
-            FGI_HIP(hipStreamSynchronize(c.stream));
-            hs = *c.host_state;
-            kend = hs.stop_at <= k + B ? hs.stop_at : k + B;
-        }
+        if (ge) FGI_HIP(hipGraphLaunch(ge->exec, c.stream));
+        else cg_batch_eager<PP, PX>(c, ops, v, B);
+        FGI_HIP(hipMemcpyAsync(c.host_state, st, sizeof(CGState), hipMemcpyDeviceToHost, c.stream));
+        FGI_HIP(hipStreamSynchronize(c.stream));
+        const CGState hs = *c.host_state;
+        const int kend = hs.stop_at <= k + B ? hs.stop_at : k + B;
         bool inner_done = hs.stop_at <= kend;
         if (inner_done || kend >= maxiter) {
             if (PX != P64) {
@@ -1204,8 +983,8 @@ static CGResult cg_run(Ctx& c, const FermionOp& op64, const FermionOp& ops, cons
             u.rr[kend & 1] = rr;
             u.stop_at = INT_MAX;
             u.base = kend;
+            u.base0 = kend;
             u.rr_stop = (PX == P64) ? target : std::max(c.ru_delta * c.ru_delta * rr, target);
-            u.counter = 0;
             hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, c.stream, st, u);
             FGI_LAUNCH_CHECK();
             k = kend;
@@ -1243,20 +1022,22 @@ static CGResult cg_run(Ctx& c, const FermionOp& op64, const FermionOp& ops, cons
 // ====================================================== batched chains ======
 template <int MODE, int PIN, int PC, int POUT, int PX, int G5IN>
 static void launch_dslash_b(Ctx& c, const Batch& B, const FermionOp& op, DArgs& a) {
-    const int nb = B.nblk[GRID_VH];
+    const int nsb = B.nblk[GRID_VH];
+    // an M_HOP inside CG (states and partials) carries one pAp reduction block per chain
+    const int nb = nsb + ((MODE == M_HOP && a.st && a.partial) ? B.nc : 0);
     if constexpr (PIN == P64) {
         hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P64, 18, G5IN>), dim3(nb), dim3(DBS), 0, c.stream, a,
-                           B.cd, B.nc);
+                           B.cd, B.nc, nsb);
     } else {
         if (op.prec == P32 && op.recon == 18)
             hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P32, 18, G5IN>), dim3(nb), dim3(DBS), 0, c.stream,
-                               a, B.cd, B.nc);
+                               a, B.cd, B.nc, nsb);
         else if (op.prec == P32)
             hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P32, 12, G5IN>), dim3(nb), dim3(DBS), 0, c.stream,
-                               a, B.cd, B.nc);
+                               a, B.cd, B.nc, nsb);
         else
             hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P16, 12, G5IN>), dim3(nb), dim3(DBS), 0, c.stream,
-                               a, B.cd, B.nc);
+                               a, B.cd, B.nc, nsb);
     }
     FGI_LAUNCH_CHECK();
 }
@@ -1328,6 +1109,7 @@ void pf_density_b(Ctx& c, const Batch& B, const d2* phi, const d2* X, const d2* 
 }
 
 // r = phi - Mhat^+ Mhat X and |r|^2 -> res[c] for the chains with act set
+// (res[c] of the other chains is meaningless)
 static void true_residual_b(Ctx& c, const Batch& B, const FermionOp& op64, const d2* phi, const d2* X, d2* r64,
                             CGState* st, double* res) {
     size_t n = sizeof(d2) * 12 * (size_t)B.sites;
@@ -1346,30 +1128,31 @@ static void true_residual_b(Ctx& c, const Batch& B, const FermionOp& op64, const
     b.aux = sp(phi);
     b.out = sp(r64);
     b.g5out = 1;
-    b.partial = (double*)c.partial.get(sizeof(double) * 65536);
+    b.partial = partial_buf(c, B);
     b.st = st;
     b.gate = 1;
-    b.result = res;
     launch_dslash_b<M_RESID, P64, P64, P64, P64, 0>(c, B, op64, b);
+    final_sums_b(c, B, b.partial, GRID_VH, res);
 }
 
 template <int PP, int PX>
 static void cg_iteration_b(Ctx& c, const Batch& B, const FermionOp& ops, const CGVecs& v, int j, CGState* st) {
-    double* part = (double*)c.partial.get(sizeof(double) * 65536);
+    double* part = partial_buf(c, B);
+    hipLaunchKernelGGL((k_cg_p_b<PP, PX>), dim3(B.nblk[GRID_VH]), dim3(DBS), 0, c.stream, B.cd, B.nc, v.p, v.r, st,
+                       (const double*)part, j);
+    FGI_LAUNCH_CHECK();
     {
         DArgs a = base_args_b(ops, 1);
         a.in = v.p;
-        a.r = v.r;
         a.out = v.t;
         a.st = st;
         a.iter = j;
-        launch_dslash_b<M_HOPP, PP, PP, PP, PX, 0>(c, B, ops, a);
+        launch_dslash_b<M_HOP, PP, PP, PP, PX, 0>(c, B, ops, a);
     }
     {
         DArgs a = base_args_b(ops, 0);
         a.in = v.t;
         a.center = v.p;
-        a.r = v.r;
         a.out = v.q;
         a.partial = part;
         a.st = st;
@@ -1380,6 +1163,7 @@ static void cg_iteration_b(Ctx& c, const Batch& B, const FermionOp& ops, const C
         DArgs a = base_args_b(ops, 1);
         a.in = v.q;
         a.out = v.t;
+        a.partial = part;
         a.st = st;
         a.iter = j;
         launch_dslash_b<M_HOP, PP, PP, PP, PX, 1>(c, B, ops, a);
@@ -1402,7 +1186,7 @@ static void cg_iteration_b(Ctx& c, const Batch& B, const FermionOp& ops, const C
 template <int PP, int PX>
 static void cg_batch_b(Ctx& c, const Batch& B, const FermionOp& ops, const CGVecs& v, int nit, CGState* st) {
     for (int j = 0; j < nit; j++) cg_iteration_b<PP, PX>(c, B, ops, v, j, st);
-    hipLaunchKernelGGL(k_advance_b, dim3(nblk(B.nc, 64)), dim3(64), 0, c.stream, st, B.nc, nit);
+    hipLaunchKernelGGL(k_advance_b, dim3(B.nc), dim3(DBS), 0, c.stream, B.cd, st, (const double*)partial_buf(c, B), nit);
     FGI_LAUNCH_CHECK();
 }
 
@@ -1431,7 +1215,7 @@ static std::vector<CGResult> cg_run_b(Ctx& c, const Batch& B, const FermionOp& o
     const int nc = B.nc;
     const size_t n64 = sizeof(d2) * 12 * (size_t)B.sites;
     std::vector<CGResult> res(nc, CGResult{0, 0, 0.0, 0});
-    double* part = (double*)c.partial.get(sizeof(double) * 65536);
+    double* part = partial_buf(c, B);
     double* dres = (double*)c.bscal.get(sizeof(double) * nc);
     CGState* st = (CGState*)c.bstate.get(sizeof(CGState) * nc);
     hipLaunchKernelGGL(k_norm2_partials_b, dim3(B.nblk[GRID_VH]), dim3(DBS), 0, c.stream, B.cd, nc, phi, part);
@@ -1534,8 +1318,8 @@ static std::vector<CGResult> cg_run_b(Ctx& c, const Batch& B, const FermionOp& o
             hs[i].rr[kend[i] & 1] = rr;
             hs[i].stop_at = INT_MAX;
             hs[i].base = kend[i];
+            hs[i].base0 = kend[i];
             hs[i].rr_stop = (PX == P64) ? target[i] : std::max(c.ru_delta * c.ru_delta * rr, target[i]);
-            hs[i].counter = 0;
         }
         upload_states(c, st, hs);  // act still set for the restarting chains
         if (restart && PX != P64) {

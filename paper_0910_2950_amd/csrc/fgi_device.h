@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace fgi {
 
 // --------------------------------------------------------------------------
@@ -119,6 +121,57 @@ template <typename R> __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> 
 }
 template <typename R> __device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
 template <typename R> __device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
+// a0 b0 + a1 b1 + a2 b2 and conj(a0) b0 + conj(a1) b1 + conj(a2) b2, each
+// component one chain of fused multiply-adds (a row or column of a link times
+// a colour vector)
+template <typename R>
+__device__ __forceinline__ cx<R> cdot3(cx<R> a0, cx<R> b0, cx<R> a1, cx<R> b1, cx<R> a2, cx<R> b2) {
+    R re = a0.re * b0.re;
+    re = fma(-a0.im, b0.im, re);
+    re = fma(a1.re, b1.re, re);
+    re = fma(-a1.im, b1.im, re);
+    re = fma(a2.re, b2.re, re);
+    re = fma(-a2.im, b2.im, re);
+    R im = a0.re * b0.im;
+    im = fma(a0.im, b0.re, im);
+    im = fma(a1.re, b1.im, im);
+    im = fma(a1.im, b1.re, im);
+    im = fma(a2.re, b2.im, im);
+    im = fma(a2.im, b2.re, im);
+    return {re, im};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> cdot3c(cx<R> a0, cx<R> b0, cx<R> a1, cx<R> b1, cx<R> a2, cx<R> b2) {
+    R re = a0.re * b0.re;
+    re = fma(a0.im, b0.im, re);
+    re = fma(a1.re, b1.re, re);
+    re = fma(a1.im, b1.im, re);
+    re = fma(a2.re, b2.re, re);
+    re = fma(a2.im, b2.im, re);
+    R im = a0.re * b0.im;
+    im = fma(-a0.im, b0.re, im);
+    im = fma(a1.re, b1.im, im);
+    im = fma(-a1.im, b1.re, im);
+    im = fma(a2.re, b2.im, im);
+    im = fma(-a2.im, b2.re, im);
+    return {re, im};
+}
+// conj(a b - c d) as two FMA chains
+template <typename R> __device__ __forceinline__ cx<R> conj_cross(cx<R> a, cx<R> b, cx<R> c, cx<R> d) {
+    R re = a.re * b.re;
+    re = fma(-a.im, b.im, re);
+    re = fma(-c.re, d.re, re);
+    re = fma(c.im, d.im, re);
+    R im = -a.re * b.im;
+    im = fma(-a.im, b.re, im);
+    im = fma(c.re, d.im, im);
+    im = fma(c.im, d.re, im);
+    return {re, im};
+}
+// y + w z with one fused multiply-add per component
+template <typename R> __device__ __forceinline__ cx<R> axpy(R w, cx<R> z, cx<R> y) {
+    return {fma(w, z.re, y.re), fma(w, z.im, y.im)};
+}
 template <typename R> __device__ __forceinline__ cx<R> times_i(cx<R> a) { return {-a.im, a.re}; }
 template <typename R> __device__ __forceinline__ cx<R> times_mi(cx<R> a) { return {a.im, -a.re}; }
 // a * conj(b)
@@ -349,26 +402,27 @@ __device__ __forceinline__ void spin_proj(const cx<R> p[4][3], cx<R> h[2][3]) {
     }
 }
 
-// acc += s * reconstruct(h), s = +/-1 boundary sign
 template <int MU, int SIGN, typename R>
-__device__ __forceinline__ void spin_recon_acc(cx<R> acc[4][3], const cx<R> h[2][3], R s) {
+__device__ __forceinline__ void spin_recon_acc(cx<R> acc[4][3], const cx<R> h[2][3], R w) {
+    // acc += w * (the four-spinor rebuilt from the projected half spinor h);
+    // w carries the storage scale and boundary sign, every term is one FMA
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        cx<R> a = s * h[0][c], b = s * h[1][c];
-        acc[0][c] = acc[0][c] + a;
-        acc[1][c] = acc[1][c] + b;
+        const cx<R> a = h[0][c], b = h[1][c];
+        acc[0][c] = axpy(w, a, acc[0][c]);
+        acc[1][c] = axpy(w, b, acc[1][c]);
         if (MU == 0) {
-            if (SIGN < 0) { acc[2][c] = acc[2][c] + times_i(b);  acc[3][c] = acc[3][c] + times_i(a); }
-            else          { acc[2][c] = acc[2][c] + times_mi(b); acc[3][c] = acc[3][c] + times_mi(a); }
+            if (SIGN < 0) { acc[2][c] = axpy(w, times_i(b), acc[2][c]);  acc[3][c] = axpy(w, times_i(a), acc[3][c]); }
+            else          { acc[2][c] = axpy(w, times_mi(b), acc[2][c]); acc[3][c] = axpy(w, times_mi(a), acc[3][c]); }
         } else if (MU == 1) {
-            if (SIGN < 0) { acc[2][c] = acc[2][c] - b; acc[3][c] = acc[3][c] + a; }
-            else          { acc[2][c] = acc[2][c] + b; acc[3][c] = acc[3][c] - a; }
+            if (SIGN < 0) { acc[2][c] = axpy(w, -b, acc[2][c]); acc[3][c] = axpy(w, a, acc[3][c]); }
+            else          { acc[2][c] = axpy(w, b, acc[2][c]);  acc[3][c] = axpy(w, -a, acc[3][c]); }
         } else if (MU == 2) {
-            if (SIGN < 0) { acc[2][c] = acc[2][c] + times_i(a);  acc[3][c] = acc[3][c] + times_mi(b); }
-            else          { acc[2][c] = acc[2][c] + times_mi(a); acc[3][c] = acc[3][c] + times_i(b); }
+            if (SIGN < 0) { acc[2][c] = axpy(w, times_i(a), acc[2][c]);  acc[3][c] = axpy(w, times_mi(b), acc[3][c]); }
+            else          { acc[2][c] = axpy(w, times_mi(a), acc[2][c]); acc[3][c] = axpy(w, times_i(b), acc[3][c]); }
         } else {
-            if (SIGN < 0) { acc[2][c] = acc[2][c] - a; acc[3][c] = acc[3][c] - b; }
-            else          { acc[2][c] = acc[2][c] + a; acc[3][c] = acc[3][c] + b; }
+            if (SIGN < 0) { acc[2][c] = axpy(w, -a, acc[2][c]); acc[3][c] = axpy(w, -b, acc[3][c]); }
+            else          { acc[2][c] = axpy(w, a, acc[2][c]);  acc[3][c] = axpy(w, b, acc[3][c]); }
         }
     }
 }
@@ -393,9 +447,34 @@ struct SpinorPtr {
     float* norm;
 };
 
+// One site's spinor exactly as stored (no conversion): a kernel can issue the
+// loads of several neighbours before it decodes any of them.
+template <int P> struct RawSp;
+template <> struct RawSp<P64> { d2 v[12]; };
+template <> struct RawSp<P32> { f4 v[6]; };
+template <> struct RawSp<P16> { h8 v[3]; float n; };
+
+template <int P> __device__ __forceinline__ void fetch_sp(const SpinorPtr& f, int s, int Vh, RawSp<P>& r) {
+    if constexpr (P == P64) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) r.v[k] = ((const d2*)f.v)[(size_t)k * Vh + s];
+    } else if constexpr (P == P32) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) r.v[k] = ((const f4*)f.v)[(size_t)k * Vh + s];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; k++) r.v[k] = ((const h8*)f.v)[(size_t)k * Vh + s];
+        r.n = f.norm[s];
+    }
+}
+
 template <int P, typename R> struct SpinorIO;
 
 template <typename R> struct SpinorIO<P64, R> {
+    static __device__ __forceinline__ void decode(const RawSp<P64>& r, cx<R> p[4][3]) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) p[k / 3][k % 3] = {R(r.v[k].x), R(r.v[k].y)};
+    }
     static __device__ __forceinline__ void load(const SpinorPtr& f, int s, int Vh, cx<R> p[4][3]) {
         const d2* b = (const d2*)f.v;
 #pragma unroll
@@ -415,6 +494,13 @@ template <typename R> struct SpinorIO<P64, R> {
 };
 
 template <typename R> struct SpinorIO<P32, R> {
+    static __device__ __forceinline__ void decode(const RawSp<P32>& r, cx<R> p[4][3]) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            p[(2 * k) / 3][(2 * k) % 3] = {R(r.v[k].x), R(r.v[k].y)};
+            p[(2 * k + 1) / 3][(2 * k + 1) % 3] = {R(r.v[k].z), R(r.v[k].w)};
+        }
+    }
     static __device__ __forceinline__ void load(const SpinorPtr& f, int s, int Vh, cx<R> p[4][3]) {
         const f4* b = (const f4*)f.v;
 #pragma unroll
@@ -437,6 +523,15 @@ template <typename R> struct SpinorIO<P32, R> {
 };
 
 template <typename R> struct SpinorIO<P16, R> {
+    static __device__ __forceinline__ void decode(const RawSp<P16>& r, cx<R> p[4][3]) {
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                int e = 4 * k + j;
+                p[e / 3][e % 3] = {R(float(r.v[k][2 * j]) * r.n), R(float(r.v[k][2 * j + 1]) * r.n)};
+            }
+    }
     static __device__ __forceinline__ void load(const SpinorPtr& f, int s, int Vh, cx<R> p[4][3]) {
         const h8* b = (const h8*)f.v;
         float nrm = f.norm[s];
@@ -477,7 +572,30 @@ template <typename R> struct SpinorIO<P16, R> {
 // link field loads: base points at the whole gauge field; (mu, p, s) selects a link
 template <int P, int RECON, typename R> struct LinkIO;
 
+// one link exactly as stored, and its fetch
+template <int P, int RECON> struct RawLink;
+template <> struct RawLink<P64, 18> { d2 v[9]; };
+template <> struct RawLink<P32, 18> { f2 v[9]; };
+template <> struct RawLink<P32, 12> { f4 v[3]; };
+template <> struct RawLink<P16, 12> { h4 v[3]; };
+
+template <int P, int RECON>
+__device__ __forceinline__ void fetch_link(const void* base, int mu, int p, int s, int Vh, RawLink<P, RECON>& r) {
+    constexpr int N = RECON == 18 ? 9 : 3;
+    typedef decltype(r.v[0]) T0;
+    typedef typename std::remove_reference<T0>::type T;
+    const T* b = (const T*)base + (size_t)((mu * 2 + p) * N) * Vh + s;
+#pragma unroll
+    for (int k = 0; k < N; k++) r.v[k] = b[(size_t)k * Vh];
+}
+
 template <typename R> struct LinkIO<P64, 18, R> {
+    static __device__ __forceinline__ M3<R> decode(const RawLink<P64, 18>& r) {
+        M3<R> u;
+#pragma unroll
+        for (int k = 0; k < 9; k++) u.e[k / 3][k % 3] = {R(r.v[k].x), R(r.v[k].y)};
+        return u;
+    }
     static __device__ __forceinline__ M3<R> load(const void* base, int mu, int p, int s, int Vh) {
         const d2* b = (const d2*)base + (size_t)((mu * 2 + p) * 9) * Vh + s;
         M3<R> u;
@@ -491,6 +609,12 @@ template <typename R> struct LinkIO<P64, 18, R> {
 };
 
 template <typename R> struct LinkIO<P32, 18, R> {
+    static __device__ __forceinline__ M3<R> decode(const RawLink<P32, 18>& r) {
+        M3<R> u;
+#pragma unroll
+        for (int k = 0; k < 9; k++) u.e[k / 3][k % 3] = {R(r.v[k].x), R(r.v[k].y)};
+        return u;
+    }
     static __device__ __forceinline__ M3<R> load(const void* base, int mu, int p, int s, int Vh) {
         const f2* b = (const f2*)base + (size_t)((mu * 2 + p) * 9) * Vh + s;
         M3<R> u;
@@ -505,12 +629,23 @@ template <typename R> struct LinkIO<P32, 18, R> {
 
 // third row of an SU(3) matrix from the first two: row2 = conj(row0 x row1)
 template <typename R> __device__ __forceinline__ void recon_row2(M3<R>& u) {
-    u.e[2][0] = conj(u.e[0][1] * u.e[1][2] - u.e[0][2] * u.e[1][1]);
-    u.e[2][1] = conj(u.e[0][2] * u.e[1][0] - u.e[0][0] * u.e[1][2]);
-    u.e[2][2] = conj(u.e[0][0] * u.e[1][1] - u.e[0][1] * u.e[1][0]);
+    u.e[2][0] = conj_cross(u.e[0][1], u.e[1][2], u.e[0][2], u.e[1][1]);
+    u.e[2][1] = conj_cross(u.e[0][2], u.e[1][0], u.e[0][0], u.e[1][2]);
+    u.e[2][2] = conj_cross(u.e[0][0], u.e[1][1], u.e[0][1], u.e[1][0]);
 }
 
 template <typename R> struct LinkIO<P32, 12, R> {
+    static __device__ __forceinline__ M3<R> decode(const RawLink<P32, 12>& r) {
+        M3<R> u;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            int e0 = 2 * k, e1 = 2 * k + 1;
+            u.e[e0 / 3][e0 % 3] = {R(r.v[k].x), R(r.v[k].y)};
+            u.e[e1 / 3][e1 % 3] = {R(r.v[k].z), R(r.v[k].w)};
+        }
+        recon_row2(u);
+        return u;
+    }
     static __device__ __forceinline__ M3<R> load(const void* base, int mu, int p, int s, int Vh) {
         const f4* b = (const f4*)base + (size_t)((mu * 2 + p) * 3) * Vh + s;
         M3<R> u;
@@ -527,6 +662,17 @@ template <typename R> struct LinkIO<P32, 12, R> {
 };
 
 template <typename R> struct LinkIO<P16, 12, R> {
+    static __device__ __forceinline__ M3<R> decode(const RawLink<P16, 12>& r) {
+        M3<R> u;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            int e0 = 2 * k, e1 = 2 * k + 1;
+            u.e[e0 / 3][e0 % 3] = {R(float(r.v[k].x)), R(float(r.v[k].y))};
+            u.e[e1 / 3][e1 % 3] = {R(float(r.v[k].z)), R(float(r.v[k].w))};
+        }
+        recon_row2(u);
+        return u;
+    }
     static __device__ __forceinline__ M3<R> load(const void* base, int mu, int p, int s, int Vh) {
         const h4* b = (const h4*)base + (size_t)((mu * 2 + p) * 3) * Vh + s;
         M3<R> u;

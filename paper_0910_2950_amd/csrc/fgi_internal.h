@@ -38,19 +38,20 @@ struct DevBuf {
     void release();
 };
 
-// Device-resident reduction/iteration state of one CG solve.  Written by the
-// solver kernels, copied to pinned host memory when the host polls.
+// Device-resident iteration state of one CG solve.  Written by the solver
+// kernels and by the host between batches; copied to pinned host memory when
+// the host polls.  Reductions never use atomics: a kernel writes one partial
+// per block and the kernel after it sums them in a fixed order.
 struct CGState {
     double rr[2];      // |r|^2 of the iteration vectors, slot k & 1 holds iteration k's
     double pAp;        // <p, A p> of the current iteration
     double rr_stop;    // inner stopping target
-    double beta;       // p_k = r_k + beta p_{k-1} (0 at a start)
+    double beta;       // p_k = r_k + beta p_{k-1} of the current iteration
     int stop_at;       // first iteration index that must not run (INT_MAX while running)
-    int iters;         // iterations completed
     int base;          // iteration index of the first iteration of the current batch
-    unsigned counter;  // arrival counter of the last-block reductions (0 between kernels)
+    int base0;         // first iteration of the current run (start or reliable update):
+                       // its rr and beta come from the host, later ones from partials
     int act;           // batched solves: 1 when this chain takes part in a masked step
-    int pad;
 };
 
 // one instantiated CG batch graph, keyed by everything its kernels capture
@@ -73,14 +74,13 @@ struct Ctx {
     DevBuf eta, phi, X, Xo, Ye, Yo, tmp_e, tmp_o, cg_r, cg_p, cg_q;
     DevBuf s_x, s_r, s_p, s_q, s_t, s_norms;
     DevBuf h0, hf0, partial, scal, state;
-    DevBuf phi2, eta2, user_tmp, aux, chi, X2;
+    DevBuf phi2, eta2, user_tmp, chi, X2;
     DevBuf cdesc, bstate, bscal, bh0, bh1, bres;  // batched chains
     CGState* host_bstates = nullptr;          // pinned [host_b_cap]
     double* host_bscal = nullptr;             // pinned [host_b_cap]
     size_t host_b_cap = 0;
     double* host_scal = nullptr;   // pinned, 64 doubles
     CGState* host_state = nullptr; // pinned
-    int* host_aux = nullptr;       // pinned (persistent-solver error flag)
     // Live profile of the bare Dslash hop inside CG: when on, after every solve
     // 16 back-to-back launches of t = D_oe g5 q (the solve's operator and
     // vectors, one captured graph) are bracketed by HIP events on the solve's
@@ -92,10 +92,7 @@ struct Ctx {
     long dslash_launches = 0;
     long dslash_sites = 0;     // output sites summed over profiled launches
     // inner CG: batches of per-phase kernels replayed as HIP graphs (default)
-    // or launched eagerly, or one persistent cooperative launch per inner run
-    // (slower on this part: its grid barriers need agent-scope fences, which
-    // write back and invalidate the XCD L2 caches four times per iteration)
-    bool use_persistent = false;
+    // or launched eagerly
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
     std::vector<GraphEntry> graphs;
@@ -113,6 +110,19 @@ struct Batch {
     int nblk[3] = {0, 0, 0};
     long sites = 0, vol = 0, links = 0;  // totals: sum Vh, sum V, sum 4V
 };
+
+// Block-partial buffer of the reductions, with room for every grid launched
+// over `vol` sites in `nchains` chains: the largest reduction grid (64 doubles
+// per even site, blocks of 256) has vol / 8 blocks plus one rounding block per
+// chain.  Every caller asks with the same arguments for a given lattice or
+// batch, so the buffer never moves while a call is using it.
+inline double* partial_buf(Ctx& c, long vol, long nchains = 1) {
+    long n = vol / 4 + 8 * nchains + 64;
+    if (n < 65536) n = 65536;
+    return (double*)c.partial.get(sizeof(double) * (size_t)n);
+}
+inline double* partial_buf(Ctx& c, const Geom& g) { return partial_buf(c, g.V, 1); }
+inline double* partial_buf(Ctx& c, const Batch& B) { return partial_buf(c, B.vol, B.nc); }
 
 // ---------------- gauge.hip ----------------
 void pack_gauge(Ctx&, const Geom&, const void* user, d2* internal);
