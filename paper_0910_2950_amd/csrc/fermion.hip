@@ -164,13 +164,14 @@ template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5
 __device__ __forceinline__ void dslash_body(const DArgs& A, int b, int nb, double* lds) {
     typedef typename Real<PIN == P64 ? P64 : P32>::T R;
     const Geom& g = A.g;
-    // solver state, read through the pointer (a private copy indexed by the
-    // iteration parity would be placed in LDS); nothing read here is written
-    // by the same launch
-    const CGState* S = A.st;
-    const int iter = S ? S->base + A.iter : A.iter;
-    if (S) {  // uniform over the chain's blocks: converged / masked chains no-op
-        if (A.gate ? !S->act : S->stop_at <= iter) return;
+    // Solver state, read up front in one batch of loads (reading each field
+    // where it is used puts a memory round trip per branch in front of the
+    // data loads).  Nothing read here is written by the same launch.
+    StateView S{INT_MAX, 0, 0, 1, {0.0, 0.0}, 0.0, 0.0, 0.0};
+    if (A.st) S = load_state(A.st);
+    const int iter = S.base + A.iter;
+    if (A.st) {  // uniform over the chain's blocks: converged / masked chains no-op
+        if (A.gate ? !S.act : S.stop_at <= iter) return;
         if constexpr (MODE == M_HOP) {
             if (b >= nb) {  // the reduction block: pAp of this iteration
                 if (A.partial) {
@@ -218,7 +219,7 @@ __device__ __forceinline__ void dslash_body(const DArgs& A, int b, int nb, doubl
                 SpinorIO<POUT, R>::store(A.out, s, g.Vh, acc);
             } else if (MODE == M_CGX) {
                 typedef typename Real<PX>::T RX;
-                const RX al = RX(S->rr[iter & 1] / S->pAp);
+                const RX al = RX(((iter & 1) ? S.rr[1] : S.rr[0]) / S.pAp);
                 cx<RX> pv[4][3], xv[4][3], rv[4][3];
                 SpinorIO<PC, RX>::load(A.aux, s, g.Vh, pv);  // p has the precision of q
                 SpinorIO<PX, RX>::load(A.x, s, g.Vh, xv);
@@ -308,13 +309,22 @@ template <int PP, int PX>
 __device__ __forceinline__ void cg_p_body(int Vh, SpinorPtr p, SpinorPtr r, CGState* st, const double* partial,
                                           int j, int b, int nb, double* lds) {
     typedef typename Real<PP == P64 ? P64 : P32>::T R;
-    const int iter = st->base + j;
-    if (st->stop_at <= iter) return;
-    double beta = st->beta;
-    if (iter != st->base0) {
+    // the state and the site's r and p are loaded before anything waits on
+    // them, so their latencies overlap with each other and with the partials
+    const StateView S = load_state(st);
+    const int s = b * DBS + threadIdx.x;
+    const int sl = s < Vh ? s : Vh - 1;
+    RawSp<PX> rr_raw;
+    RawSp<PP> pp_raw;
+    fetch_sp<PX>(r, sl, Vh, rr_raw);
+    fetch_sp<PP>(p, sl, Vh, pp_raw);
+    const int iter = S.base + j;
+    if (S.stop_at <= iter) return;
+    double beta = S.beta;
+    if (iter != S.base0) {
         const double rr = sum_partials(partial, nb, lds);
-        const bool stop = rr <= st->rr_stop;
-        beta = rr / st->rr[(iter - 1) & 1];
+        const bool stop = rr <= S.rr_stop;
+        beta = rr / ((iter & 1) ? S.rr[0] : S.rr[1]);  // |r|^2 of iteration iter - 1
         if (b == 0 && threadIdx.x == 0) {
             st->rr[iter & 1] = rr;
             if (stop) st->stop_at = iter;
@@ -322,11 +332,10 @@ __device__ __forceinline__ void cg_p_body(int Vh, SpinorPtr p, SpinorPtr r, CGSt
         }
         if (stop) return;
     }
-    const int s = b * DBS + threadIdx.x;
     if (s >= Vh) return;
     cx<R> rv[4][3], pv[4][3];
-    SpinorIO<PX, R>::load(r, s, Vh, rv);
-    SpinorIO<PP, R>::load(p, s, Vh, pv);
+    SpinorIO<PX, R>::decode(rr_raw, rv);
+    SpinorIO<PP, R>::decode(pp_raw, pv);
     p_update(rv, pv, R(beta));
     SpinorIO<PP, R>::store(p, s, Vh, pv);
 }

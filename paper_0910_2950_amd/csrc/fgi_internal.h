@@ -42,17 +42,35 @@ struct DevBuf {
 // kernels and by the host between batches; copied to pinned host memory when
 // the host polls.  Reductions never use atomics: a kernel writes one partial
 // per block and the kernel after it sums them in a fixed order.
-struct CGState {
-    double rr[2];      // |r|^2 of the iteration vectors, slot k & 1 holds iteration k's
-    double pAp;        // <p, A p> of the current iteration
-    double rr_stop;    // inner stopping target
-    double beta;       // p_k = r_k + beta p_{k-1} of the current iteration
+struct alignas(64) CGState {
     int stop_at;       // first iteration index that must not run (INT_MAX while running)
     int base;          // iteration index of the first iteration of the current batch
     int base0;         // first iteration of the current run (start or reliable update):
                        // its rr and beta come from the host, later ones from partials
     int act;           // batched solves: 1 when this chain takes part in a masked step
+    double rr[2];      // |r|^2 of the iteration vectors, slot k & 1 holds iteration k's
+    double pAp;        // <p, A p> of the current iteration
+    double rr_stop;    // inner stopping target
+    double beta;       // p_k = r_k + beta p_{k-1} of the current iteration
+    double pad;
 };
+static_assert(sizeof(CGState) == 64, "CGState is read as 16-byte vectors");
+
+// All fields of a state in four 16-byte loads issued together (kernels read
+// the state once, up front, instead of one memory round trip per use).
+struct StateView {
+    int stop_at, base, base0, act;
+    double rr[2], pAp, rr_stop, beta;
+};
+__device__ __forceinline__ StateView load_state(const CGState* st) {
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    typedef double dd2 __attribute__((ext_vector_type(2)));
+    const i4 a = *(const i4*)st;
+    const dd2 r = *(const dd2*)&st->rr[0];
+    const dd2 q = *(const dd2*)&st->pAp;
+    const dd2 t = *(const dd2*)&st->beta;
+    return StateView{a.x, a.y, a.z, a.w, {r.x, r.y}, q.x, q.y, t.x};
+}
 
 // one instantiated CG batch graph, keyed by everything its kernels capture
 struct GraphEntry {
