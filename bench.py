@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--cg-batch", type=int, default=16)
     ap.add_argument("--graphs", type=int, default=1, help="replay CG batches as HIP graphs (0: eager launches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 32^3x64 Dslash roofline point")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 96-chain batched workload")
+    ap.add_argument("--batched-steps", type=int, default=2, help="timed batched trajectories")
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle CG iterations timed for the CPU baseline")
     ap.add_argument("--calibrate", action="store_true", help="step-size sweep for the matched step counts")
     ap.add_argument("--cal-traj", type=int, default=6)
@@ -178,6 +181,99 @@ class Runner:
             self.ctx.set_option("profile", 0)
             prof = self.ctx.get_profile()
         return recs, t1 - t0, prof
+
+
+def tile_field(torch, U, dims, f=2):
+    """U (4, V, 3, 3), x fastest, repeated f times along every axis: the same
+    configuration on an f^4 times larger torus (still a valid SU(3) field)."""
+    X, Y, Z, T = dims
+    u = U.reshape(4, T, Z, Y, X, 3, 3).repeat(1, f, f, f, f, 1, 1)
+    return u.reshape(4, -1, 3, 3).contiguous(), (f * X, f * Y, f * Z, f * T)
+
+
+def dslash_roofline_large(R, U_therm, prec, recon):
+    """The same bare-hop timing as the main roofline, on the thermalised field
+    tiled to 32^3x64 (16 waves of sites per SIMD instead of one): 16 HIP-event
+    timed launches after each of two short CG solves (32 iterations)."""
+    torch, fgi = R.torch, R.fgi
+    Ub, dims_b = tile_field(torch, U_therm, R.dims, 2)
+    V = int(np.prod(dims_b))
+    g = torch.Generator(device=R.dev)
+    g.manual_seed(R.args.seed + 300000)
+    phi = torch.randn((V // 2, 4, 3), dtype=torch.complex128, device=R.dev, generator=g)
+    act = fgi.Action(beta=R.args.beta, kappa=R.args.kappa, cg_tol=1e-30, cg_maxiter=32, prec=prec, link_recon=recon)
+    R.ctx.set_option("profile_prec", PREC_ID[prec] if prec != "mp32" else 1)
+    R.ctx.set_option("profile", 1)
+    R.ctx.cg_solve(dims_b, act, Ub, phi, allow_noconv=True)
+    R.ctx.set_option("profile_reset", 1)
+    for _ in range(2):
+        R.ctx.cg_solve(dims_b, act, Ub, phi, allow_noconv=True)
+    ms, launches, sites = R.ctx.get_profile()
+    R.ctx.set_option("profile", 0)
+    del Ub, phi
+    torch.cuda.empty_cache()
+    bps = DSLASH_BYTES[(prec, recon)]
+    avg_s = ms / 1e3 / launches
+    achieved = sites / launches * bps / avg_s / 1e9
+    return dict(lattice=list(dims_b), bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), avg_launch_us=round(avg_s * 1e6, 3), launches_timed=launches,
+                algorithmic_bytes_per_launch=sites / launches * bps,
+                kernel="bare even-odd Dslash hop t = D_oe g5 q (%s/%d), %d output sites per launch, on the "
+                       "thermalised 16^3x32 field repeated 2x2x2x2" % (prec, recon, V // 2))
+
+
+BATCH_SPEC = [((4, 4, 4, 4), 32), ((6, 6, 6, 6), 32), ((8, 8, 8, 8), 24), ((8, 8, 8, 16), 8)]
+
+
+def batched_leg(R, prec, nsteps, steps):
+    """96 independent chains of uneven sizes (32x 4^4, 32x 6^4, 24x 8^4,
+    8x 8^3x16), beta ~ U[5.5, 6.0], kappa ~ U[0.150, 0.157], each a seeded Haar
+    start with Gaussian momenta and pseudofermion noise: FG trajectories of all
+    chains in one batched call (one set of launches per MD sub-step) against
+    the same trajectories run chain by chain."""
+    torch, fgi, synth = R.torch, R.fgi, R.synth
+    rng = synth.rng(R.args.seed + 500000)
+    dims_list = [d for d, n in BATCH_SPEC for _ in range(n)]
+    betas = rng.uniform(5.5, 6.0, len(dims_list))
+    kappas = rng.uniform(0.150, 0.157, len(dims_list))
+    host = []
+    for k, dims in enumerate(dims_list):
+        U0, P0, eta, _ = synth.hot_start(dims, R.args.seed + 600000 + k, fermions=True)
+        host.append((R.to_dev(U0), R.to_dev(P0), R.to_dev(eta)))
+    act = fgi.Action(beta=0.0, cg_tol=R.args.tol, cg_maxiter=50000, prec=prec, link_recon=12 if prec != "fp64" else 18)
+
+    def fresh():
+        return [dict(dims=d, beta=b, kappa=kp, U=U.clone(), P=P.clone(), eta=e)
+                for d, b, kp, (U, P, e) in zip(dims_list, betas, kappas, host)]
+
+    R.ctx.trajectory_batched(fresh(), act, "FG", 1.0, nsteps)  # warmup (graph capture)
+    times, iters = [], []
+    for _ in range(steps):
+        chains = fresh()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dH, st = R.ctx.trajectory_batched(chains, act, "FG", 1.0, nsteps)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        iters.append(st["cg_iters"])
+    t_batch = float(np.mean(times))
+    # the same trajectories chain by chain
+    chains = fresh()
+    integ = fgi.integrator_builtin("FG")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ch in chains:
+        a1 = fgi.Action(beta=float(ch["beta"]), kappa=float(ch["kappa"]), cg_tol=R.args.tol, cg_maxiter=50000,
+                        prec=prec, link_recon=act.link_recon)
+        R.ctx.trajectory(ch["dims"], a1, integ, 1.0, nsteps, ch["U"], ch["P"], ch["eta"])
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    return dict(workload="96 chains (32x 4^4, 32x 6^4, 24x 8^4, 8x 8^3x16), beta~U[5.5,6.0], kappa~U[0.150,0.157], "
+                         "Haar starts; FG n=%d tau=1, %s CG tol %.0e" % (nsteps, prec, R.args.tol),
+                chains=len(dims_list), s_per_batched_trajectory=round(t_batch, 5),
+                chain_trajectories_per_s=round(len(dims_list) / t_batch, 2),
+                s_chain_by_chain=round(t_seq, 4), speedup_vs_chain_by_chain=round(t_seq / t_batch, 2),
+                cg_iters_per_batched_trajectory=float(np.mean(iters)), timed=steps)
 
 
 def summarise(recs):
@@ -320,6 +416,19 @@ def main():
                     algorithmic_bytes_per_launch=bytes_per_launch, avg_launch_us=round(avg_s * 1e6, 3),
                     launches_timed=launches)
 
+    large = None
+    if not args.no_large:
+        large = dslash_roofline_large(R, U, args.prec, 12 if args.prec == "mp16" else args.recon)
+        log("Dslash %s on %s: %.1f GB/s (%.1f%% of HBM peak), %.2f us per launch" %
+            (args.prec, "x".join(map(str, large["lattice"])), large["achieved"], 100 * large["frac"],
+             large["avg_launch_us"]))
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg(R, args.prec, 8, args.batched_steps)
+        log("batched 96 chains: %.4f s per trajectory of all chains (%.1f chain-trajectories/s), chain by chain "
+            "%.3f s, speedup %.1fx" % (batched["s_per_batched_trajectory"], batched["chain_trajectories_per_s"],
+                                      batched["s_chain_by_chain"], batched["speedup_vs_chain_by_chain"]))
+
     cpu = None
     if not args.no_cpu_baseline:
         iters_fp64 = (lf["cg_iters_per_traj"] / lf["solves_per_traj"] * fg["solves_per_traj"]) if lf else \
@@ -338,7 +447,7 @@ def main():
                            lattice=list(R.dims), integrator="FG", n_steps=args.n_fg, plaquette=round(plaq, 6)),
                fg=fg, lf_fp64=lf,
                speedup_vs_lf_fp64=(round(lf["s_per_traj"] / s_per_traj, 3) if lf else None),
-               roofline=roof, cpu_baseline=cpu)
+               roofline=roof, roofline_32x32x32x64=large, batched=batched, cpu_baseline=cpu)
     print(json.dumps(out), flush=True)
 
 
