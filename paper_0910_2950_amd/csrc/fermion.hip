@@ -75,7 +75,7 @@ template <int PIN, int G5IN, typename R> struct LoadPlain {
 // psi(x + mu), d = 1 the backward hop (1 + g_mu) U_mu(x - mu)^+ psi(x - mu).
 // Each hop projects to a half spinor, multiplies by the link and accumulates
 // the rebuilt spinor times w = (storage scale) x (antiperiodic sign in t).
-template <int K, int PL, int RECON, typename R, typename L>
+template <int K, int PL, int RECON, bool NT, typename R, typename L>
 __device__ __forceinline__ void hop(const Geom& g, int p, int s, const Coord& c, const void* links, const L& load,
                                     cx<R> acc[4][3]) {
     constexpr int MU = K >> 1;
@@ -89,7 +89,7 @@ __device__ __forceinline__ void hop(const Geom& g, int p, int s, const Coord& c,
     // the link is loaded after the projection: loads issued any earlier only
     // raise the register count (and lower occupancy on large lattices)
     RawLink<PL, RECON> rl;
-    fetch_link<PL, RECON>(links, MU, FWD ? p : 1 - p, FWD ? s : sn, g.Vh, rl);
+    fetch_link<PL, RECON, NT>(links, MU, FWD ? p : 1 - p, FWD ? s : sn, g.Vh, rl);
     const M3<R> u = LinkIO<PL, RECON, R>::decode(rl);
     if constexpr (FWD) {
 #pragma unroll
@@ -109,7 +109,7 @@ __device__ __forceinline__ void hop(const Geom& g, int p, int s, const Coord& c,
     spin_recon_acc<MU, FWD ? -1 : +1>(acc, uh, w);
 }
 
-template <int PL, int RECON, typename R, typename L>
+template <int PL, int RECON, bool NT, typename R, typename L>
 __device__ __forceinline__ void hop_sum(const Geom& g, int p, int s, const void* links, const L& load,
                                         cx<R> acc[4][3]) {
     Coord c = cb_coords(g, p, s);
@@ -117,14 +117,14 @@ __device__ __forceinline__ void hop_sum(const Geom& g, int p, int s, const void*
     for (int i = 0; i < 4; i++)
 #pragma unroll
         for (int k = 0; k < 3; k++) acc[i][k] = {R(0), R(0)};
-    hop<0, PL, RECON>(g, p, s, c, links, load, acc);
-    hop<1, PL, RECON>(g, p, s, c, links, load, acc);
-    hop<2, PL, RECON>(g, p, s, c, links, load, acc);
-    hop<3, PL, RECON>(g, p, s, c, links, load, acc);
-    hop<4, PL, RECON>(g, p, s, c, links, load, acc);
-    hop<5, PL, RECON>(g, p, s, c, links, load, acc);
-    hop<6, PL, RECON>(g, p, s, c, links, load, acc);
-    hop<7, PL, RECON>(g, p, s, c, links, load, acc);
+    hop<0, PL, RECON, NT>(g, p, s, c, links, load, acc);
+    hop<1, PL, RECON, NT>(g, p, s, c, links, load, acc);
+    hop<2, PL, RECON, NT>(g, p, s, c, links, load, acc);
+    hop<3, PL, RECON, NT>(g, p, s, c, links, load, acc);
+    hop<4, PL, RECON, NT>(g, p, s, c, links, load, acc);
+    hop<5, PL, RECON, NT>(g, p, s, c, links, load, acc);
+    hop<6, PL, RECON, NT>(g, p, s, c, links, load, acc);
+    hop<7, PL, RECON, NT>(g, p, s, c, links, load, acc);
 }
 
 // ------------------------------------------------------------ reductions ---
@@ -160,7 +160,8 @@ struct DArgs {
     int gate;   // with st: 0 skip once st->stop_at <= iteration, 1 skip unless st->act
 };
 
-template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN>
+// NT: the links are streamed with non-temporal loads (see links_streamed)
+template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN, bool NT>
 __device__ __forceinline__ void dslash_body(const DArgs& A, int b, int nb, double* lds) {
     typedef typename Real<PIN == P64 ? P64 : P32>::T R;
     const Geom& g = A.g;
@@ -187,7 +188,7 @@ __device__ __forceinline__ void dslash_body(const DArgs& A, int b, int nb, doubl
     if (s < g.Vh) {
         cx<R> acc[4][3];
         LoadPlain<PIN, G5IN, R> ld{A.in};
-        hop_sum<PL, RECON, R>(g, A.p_out, s, A.links, ld, acc);
+        hop_sum<PL, RECON, NT, R>(g, A.p_out, s, A.links, ld, acc);
         if (A.g5out) flip_lower(acc);
         if (MODE == M_HOP) {
             SpinorIO<POUT, R>::store(A.out, s, g.Vh, acc);
@@ -244,14 +245,14 @@ __device__ __forceinline__ void dslash_body(const DArgs& A, int b, int nb, doubl
     if (threadIdx.x == 0) A.partial[b] = v[0];
 }
 
-template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN>
+template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN, bool NT>
 __global__ void __launch_bounds__(DBS) k_dslash(DArgs A) {
     __shared__ double lds[DBS / 64];
     // site blocks in XCD-aware order (the same order in every kernel of the
     // solver, so a site stays on one XCD); a reduction block comes last
     const int nb = (A.g.Vh + DBS - 1) / DBS;
     const int b = (int)blockIdx.x < nb ? xcd_block(blockIdx.x, nb) : blockIdx.x;
-    dslash_body<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN>(A, b, nb, lds);
+    dslash_body<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN, NT>(A, b, nb, lds);
 }
 
 // one chain's part of a concatenated spinor field / link field
@@ -296,7 +297,7 @@ __global__ void __launch_bounds__(DBS) k_dslash_b(DArgs base, const ChainDesc* _
     A.partial = base.partial ? base.partial + d.blk0[GRID_VH] : nullptr;
     A.st = base.st ? base.st + c : nullptr;
     const int b = gb < nsb ? gb - d.blk0[GRID_VH] : d.nblk[GRID_VH];
-    dslash_body<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN>(A, b, d.nblk[GRID_VH], lds);
+    dslash_body<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN, false>(A, b, d.nblk[GRID_VH], lds);
 }
 
 // First kernel of a CG iteration: p = r + beta p, stored in p's precision.
@@ -615,22 +616,37 @@ __global__ void __launch_bounds__(256) k_fermion_force_b(const ChainDesc* __rest
 // ------------------------------------------------------- host launchers ---
 static SpinorPtr sp(const void* v, float* norm = nullptr) { return SpinorPtr{(void*)v, norm}; }
 
+// Links are streamed (non-temporal loads) when the whole link field of the
+// operator is larger than the L2 caches together (8 XCDs x 4 MB): then they
+// cannot stay cached between launches anyway, and streaming them keeps the
+// neighbour spinors in L2.  Smaller fields are reused from L2 across the CG's
+// kernels, so they are loaded normally.  Batched launches always load them
+// normally (batches are many small lattices).
+static const double kL2Bytes = 32.0 * (1 << 20);
+static int links_streamed(const FermionOp& op, long nlinks) {
+    const double per = op.prec == P64 ? 144 : (op.prec == P32 ? (op.recon == 18 ? 72 : 48) : 24);
+    return per * (double)nlinks > kL2Bytes ? 1 : 0;
+}
+
+template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN>
+static void launch_dslash_nt(Ctx& c, bool nt, int nb, DArgs& a) {
+    if (nt) hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN, true>), dim3(nb), dim3(DBS), 0, c.stream, a);
+    else hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN, false>), dim3(nb), dim3(DBS), 0, c.stream, a);
+}
+
 template <int MODE, int PIN, int PC, int POUT, int PX, int G5IN>
 static void launch_dslash(Ctx& c, const FermionOp& op, DArgs& a) {
+    const bool nt = links_streamed(op, 4L * a.g.V);
     // an M_HOP inside CG (state and partials) carries the pAp reduction block
     int nb = nblk(a.g.Vh, DBS) + ((MODE == M_HOP && a.st && a.partial) ? 1 : 0);
     if constexpr (PIN == P64) {
         if (op.prec != P64) throw Error(-1, "FP64 spinors need FP64 links");
-        hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, P64, 18, G5IN>), dim3(nb), dim3(DBS), 0, c.stream, a);
+        launch_dslash_nt<MODE, PIN, PC, POUT, PX, P64, 18, G5IN>(c, nt, nb, a);
     } else {
-        if (op.prec == P32 && op.recon == 18)
-            hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, P32, 18, G5IN>), dim3(nb), dim3(DBS), 0, c.stream, a);
-        else if (op.prec == P32)
-            hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, P32, 12, G5IN>), dim3(nb), dim3(DBS), 0, c.stream, a);
-        else if (op.prec == P16)
-            hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, P16, 12, G5IN>), dim3(nb), dim3(DBS), 0, c.stream, a);
-        else
-            throw Error(-1, "sloppy spinors need sloppy links");
+        if (op.prec == P32 && op.recon == 18) launch_dslash_nt<MODE, PIN, PC, POUT, PX, P32, 18, G5IN>(c, nt, nb, a);
+        else if (op.prec == P32) launch_dslash_nt<MODE, PIN, PC, POUT, PX, P32, 12, G5IN>(c, nt, nb, a);
+        else if (op.prec == P16) launch_dslash_nt<MODE, PIN, PC, POUT, PX, P16, 12, G5IN>(c, nt, nb, a);
+        else throw Error(-1, "sloppy spinors need sloppy links");
     }
     FGI_LAUNCH_CHECK();
 }

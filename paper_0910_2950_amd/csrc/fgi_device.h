@@ -579,14 +579,24 @@ template <> struct RawLink<P32, 18> { f2 v[9]; };
 template <> struct RawLink<P32, 12> { f4 v[3]; };
 template <> struct RawLink<P16, 12> { h4 v[3]; };
 
-template <int P, int RECON>
+// nt: non-temporal loads, for link fields larger than the L2 caches together
+// (each link is read once per launch; streaming them keeps the L2 for the
+// neighbour spinors, which are read eight times)
+// (a compile-time choice: a run-time branch between the two loads is merged
+// by the compiler, which then drops the non-temporal hint)
+template <int P, int RECON, bool NT>
 __device__ __forceinline__ void fetch_link(const void* base, int mu, int p, int s, int Vh, RawLink<P, RECON>& r) {
     constexpr int N = RECON == 18 ? 9 : 3;
     typedef decltype(r.v[0]) T0;
     typedef typename std::remove_reference<T0>::type T;
     const T* b = (const T*)base + (size_t)((mu * 2 + p) * N) * Vh + s;
+    if constexpr (NT) {
 #pragma unroll
-    for (int k = 0; k < N; k++) r.v[k] = b[(size_t)k * Vh];
+        for (int k = 0; k < N; k++) r.v[k] = __builtin_nontemporal_load(b + (size_t)k * Vh);
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; k++) r.v[k] = b[(size_t)k * Vh];
+    }
 }
 
 template <typename R> struct LinkIO<P64, 18, R> {
