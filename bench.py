@@ -69,6 +69,7 @@ def parse():
     ap.add_argument("--no-large", action="store_true", help="skip the 32^3x64 Dslash roofline point")
     ap.add_argument("--no-batched", action="store_true", help="skip the 96-chain batched workload")
     ap.add_argument("--batched-steps", type=int, default=2, help="timed batched trajectories")
+    ap.add_argument("--no-hasenbusch", action="store_true", help="skip the 32^3x64 Hasenbusch MD-step leg")
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle CG iterations timed for the CPU baseline")
     ap.add_argument("--calibrate", action="store_true", help="step-size sweep for the matched step counts")
     ap.add_argument("--cal-traj", type=int, default=6)
@@ -220,6 +221,48 @@ def dslash_roofline_large(R, U_therm, prec, recon):
                 algorithmic_bytes_per_launch=sites / launches * bps,
                 kernel="bare even-odd Dslash hop t = D_oe g5 q (%s/%d), %d output sites per launch, on the "
                        "thermalised 16^3x32 field repeated 2x2x2x2" % (prec, recon, V // 2))
+
+
+def hasenbusch_leg(R, U_therm, prec):
+    """The large-lattice workload: Nf=2 at kappa = 0.158 with Hasenbusch mass
+    preconditioning (kappa' = 0.150) on three nested FG time scales (S_2
+    outermost, S_1, then S_G with two sub-steps each), on the thermalised
+    16^3x32 field repeated 2x2x2x2 to 32^3x64.  One outer MD step of length
+    1/8, i.e. a trajectory call with tau = 1/8 and one step: it includes the
+    Hasenbusch heatbath solve and the two final-action solves."""
+    torch, fgi = R.torch, R.fgi
+    Ub, dims_b = tile_field(torch, U_therm, R.dims, 2)
+    V = int(np.prod(dims_b))
+    g = torch.Generator(device=R.dev)
+    g.manual_seed(R.args.seed + 400000)
+    P = torch.randn((4, V, 8), dtype=torch.float64, device=R.dev, generator=g)
+    eta1 = torch.randn((V // 2, 4, 3), dtype=torch.complex128, device=R.dev, generator=g)
+    eta2 = torch.randn((V // 2, 4, 3), dtype=torch.complex128, device=R.dev, generator=g)
+    FG = [("P", 1 / 6, 0.0), ("Q", 0.5, 0.0), ("G", 2 / 3, 1 / 72), ("Q", 0.5, 0.0), ("P", 1 / 6, 0.0)]
+    integ = fgi.integrator_from_levels([(FG, fgi.TERM_HASEN, 1), (FG, fgi.TERM_FERMION, 2), (FG, fgi.TERM_GAUGE, 2)])
+    act = fgi.Action(beta=R.args.beta, kappa=0.158, kappa_hasen=0.150, cg_tol=R.args.tol, cg_maxiter=100000,
+                     prec=prec, link_recon=12 if prec != "fp64" else 18)
+    R.ctx.set_option("profile_prec", PREC_ID[prec] if prec != "mp32" else 1)
+    R.ctx.set_option("profile_reset", 1)
+    R.ctx.set_option("profile", 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dH, st = R.ctx.trajectory(dims_b, act, integ, 0.125, 1, Ub, P, eta1, eta2)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    R.ctx.set_option("profile", 0)
+    ms, launches, sites = R.ctx.get_profile()
+    del Ub, P, eta1, eta2
+    torch.cuda.empty_cache()
+    bps = DSLASH_BYTES[(prec, 12 if prec != "fp64" else 18)]
+    hop_s = ms / 1e3 / max(launches, 1)
+    return dict(workload="Nf=2 32x32x32x64 beta=%.2f kappa=0.158, Hasenbusch kappa'=0.150, nested FG (S2 / S1 x2 / "
+                         "SG x2), thermalised 16^3x32 field repeated 2x2x2x2; one outer MD step of 1/8 incl. "
+                         "heatbath and final-action solves; %s CG tol %.0e" % (R.args.beta, prec, R.args.tol),
+                s_per_outer_step=round(sec, 4), dH=dH, solves=st["solves"], cg_iters=st["cg_iters"],
+                cg_iters_max=st["cg_iters_max"], max_rel_resid=st["max_rel_resid"],
+                dslash_achieved_GBs=round(sites / max(launches, 1) * bps / hop_s / 1e9, 1) if launches else None,
+                dslash_avg_launch_us=round(hop_s * 1e6, 3) if launches else None)
 
 
 BATCH_SPEC = [((4, 4, 4, 4), 32), ((6, 6, 6, 6), 32), ((8, 8, 8, 8), 24), ((8, 8, 8, 16), 8)]
@@ -422,6 +465,12 @@ def main():
         log("Dslash %s on %s: %.1f GB/s (%.1f%% of HBM peak), %.2f us per launch" %
             (args.prec, "x".join(map(str, large["lattice"])), large["achieved"], 100 * large["frac"],
              large["avg_launch_us"]))
+    hasen = None
+    if not args.no_hasenbusch:
+        hasen = hasenbusch_leg(R, U, args.prec)
+        log("Hasenbusch 32^3x64: %.2f s per outer step, %d solves, %d CG iterations (max %d per solve), dH=%+.3e, "
+            "Dslash %.1f GB/s" % (hasen["s_per_outer_step"], hasen["solves"], hasen["cg_iters"],
+                                  hasen["cg_iters_max"], hasen["dH"], hasen["dslash_achieved_GBs"] or 0))
     batched = None
     if not args.no_batched:
         batched = batched_leg(R, args.prec, 8, args.batched_steps)
@@ -447,7 +496,8 @@ def main():
                            lattice=list(R.dims), integrator="FG", n_steps=args.n_fg, plaquette=round(plaq, 6)),
                fg=fg, lf_fp64=lf,
                speedup_vs_lf_fp64=(round(lf["s_per_traj"] / s_per_traj, 3) if lf else None),
-               roofline=roof, roofline_32x32x32x64=large, batched=batched, cpu_baseline=cpu)
+               roofline=roof, roofline_32x32x32x64=large, hasenbusch_32x32x32x64=hasen, batched=batched,
+               cpu_baseline=cpu)
     print(json.dumps(out), flush=True)
 
 
