@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 96-chain batched workload")
     ap.add_argument("--batched-steps", type=int, default=2, help="timed batched trajectories")
     ap.add_argument("--no-hasenbusch", action="store_true", help="skip the 32^3x64 Hasenbusch MD-step leg")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default CG schedule (block 256, XCD order, --cg-batch) instead of tuning per leg")
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle CG iterations timed for the CPU baseline")
     ap.add_argument("--calibrate", action="store_true", help="step-size sweep for the matched step counts")
     ap.add_argument("--cal-traj", type=int, default=6)
@@ -149,6 +151,23 @@ class Runner:
             log("therm %2d dH=%+.4e acc=%d plaq=%.5f cg_iters=%d solves=%d %.2fs" %
                 (k, dH, acc, plaq, st["cg_iters"], st["solves"], st["seconds"]))
         return U, plaq
+
+    def tune(self, U, prec, recon):
+        """Autotune the CG schedule on the thermalised field for one precision
+        (untimed); returns the choices, which apply() re-selects before a leg."""
+        P, eta = self.synth.refresh(self.dims, self.args.seed + 700000)
+        act = self.fgi.Action(beta=self.args.beta, kappa=self.args.kappa, cg_tol=self.args.tol, cg_maxiter=50000,
+                              prec=prec, link_recon=recon)
+        t = self.ctx.autotune_cg(self.dims, act, U, self.to_dev(eta))
+        log("autotune %s: block %d, order %d, cg_batch %d" % (prec, t["dslash_block"], t["xcd_order"], t["cg_batch"]))
+        return t
+
+    def apply(self, t):
+        if t is None:
+            return
+        self.ctx.set_option("dslash_block", t["dslash_block"])
+        self.ctx.set_option("xcd_order", t["xcd_order"])
+        self.ctx.set_option("cg_batch", t["cg_batch"])
 
     def fresh_inputs(self, n, base):
         out = []
@@ -289,6 +308,11 @@ def batched_leg(R, prec, nsteps, steps):
         return [dict(dims=d, beta=b, kappa=kp, U=U.clone(), P=P.clone(), eta=e)
                 for d, b, kp, (U, P, e) in zip(dims_list, betas, kappas, host)]
 
+    tuning = None
+    if not R.args.no_autotune:
+        tuning = R.ctx.autotune_batched(fresh(), act)
+        log("autotune batched: block %d, order %d, cg_batch %d" % (tuning["dslash_block"], tuning["xcd_order"],
+                                                                  tuning["cg_batch"]))
     R.ctx.trajectory_batched(fresh(), act, "FG", 1.0, nsteps)  # warmup (graph capture)
     times, iters = [], []
     for _ in range(steps):
@@ -316,7 +340,7 @@ def batched_leg(R, prec, nsteps, steps):
                 chains=len(dims_list), s_per_batched_trajectory=round(t_batch, 5),
                 chain_trajectories_per_s=round(len(dims_list) / t_batch, 2),
                 s_chain_by_chain=round(t_seq, 4), speedup_vs_chain_by_chain=round(t_seq / t_batch, 2),
-                cg_iters_per_batched_trajectory=float(np.mean(iters)), timed=steps)
+                cg_iters_per_batched_trajectory=float(np.mean(iters)), timed=steps, schedule=tuning)
 
 
 def summarise(recs):
@@ -421,12 +445,19 @@ def main():
     inputs = R.fresh_inputs(args.warmup + args.steps, args.seed + 100000)
     log("setup (thermalisation + inputs) %.1fs" % (time.perf_counter() - t_setup))
 
+    tune_fg = tune_lf = None
+    if not args.no_autotune:
+        tune_fg = R.tune(U, args.prec, args.recon if args.prec != "mp16" else 12)
+        if args.lf_steps > 0:
+            tune_lf = R.tune(U, "fp64", 18)
+    R.apply(tune_fg)
     # warmup (untimed)
     if args.warmup:
         R.run_leg(U, act_fg, "FG", args.n_fg, inputs[:args.warmup])
     # timed FG leg with live Dslash event timing
     recs, sec, prof = R.run_leg(U, act_fg, "FG", args.n_fg, inputs[args.warmup:], profile=True)
     fg = summarise(recs)
+    fg["schedule"] = tune_fg
     s_per_traj = sec / args.steps
     log("FG-%s n=%d: %.4f s/traj  <dH^2>=%.4e acc=%.3f solves=%.1f iters=%.0f" %
         (args.prec, args.n_fg, s_per_traj, fg["mean_dH2"], fg["acceptance"], fg["solves_per_traj"],
@@ -435,10 +466,11 @@ def main():
     # FP64 leapfrog leg at its matched step count
     lf = None
     if args.lf_steps > 0:
+        R.apply(tune_lf)
         lf_inputs = R.fresh_inputs(args.lf_steps, args.seed + 200000)
         recs_lf, sec_lf, _ = R.run_leg(U, R.action("fp64"), "PQP", args.n_lf, lf_inputs)
         lf = summarise(recs_lf)
-        lf.update(n=args.n_lf, s_per_traj=sec_lf / args.lf_steps, trajectories=args.lf_steps)
+        lf.update(n=args.n_lf, s_per_traj=sec_lf / args.lf_steps, trajectories=args.lf_steps, schedule=tune_lf)
         log("LF-fp64 n=%d: %.4f s/traj  <dH^2>=%.4e acc=%.3f iters=%.0f" %
             (args.n_lf, lf["s_per_traj"], lf["mean_dH2"], lf["acceptance"], lf["cg_iters_per_traj"]))
 
@@ -459,6 +491,7 @@ def main():
                     algorithmic_bytes_per_launch=bytes_per_launch, avg_launch_us=round(avg_s * 1e6, 3),
                     launches_timed=launches)
 
+    R.apply(tune_fg)
     large = None
     if not args.no_large:
         large = dslash_roofline_large(R, U, args.prec, 12 if args.prec == "mp16" else args.recon)

@@ -139,7 +139,9 @@ int fgi_destroy(fgi_ctx* ctx);
 /* Text of the calling thread's last failure ("" if none). */
 const char* fgi_last_error(void);
 /* Tuning/diagnostic options: "cg_batch" (CG iterations launched between host
- * polls; each batch is one replay of a captured HIP graph), "graphs" (0: launch
+ * polls; each batch is one replay of a captured HIP graph), "dslash_block"
+ * (64, 128 or 256 even sites per block of the Dslash-shaped kernels),
+ * "xcd_order" (1: XCD-aware block order, 0: linear), "graphs" (0: launch
  * the batch kernels one by one instead), "ru_delta" (reliable-update residual
  * drop), "profile" (1: after every CG solve, time 16 back-to-back launches of
  * the bare Dslash hop on the solve's operator with HIP events), "profile_prec"
@@ -149,6 +151,26 @@ int fgi_set_option(fgi_ctx* ctx, const char* name, double value);
 /* Accumulated Dslash profile since the last reset: total ms of the timed bare
  * hop launches, their number, and output sites summed over them. */
 int fgi_get_profile(fgi_ctx* ctx, double* ms, long* launches, long* sites);
+
+/* Schedule of the CG kernels chosen by fgi_autotune_* (also settable with
+ * fgi_set_option: "dslash_block", "xcd_order", "cg_batch"). */
+typedef struct {
+    int dslash_block;             /* even sites (threads) per block of the Dslash-shaped kernels: 64, 128, 256 */
+    int xcd_order;                /* 1: blocks ordered so each XCD owns a contiguous slab of sites; 0: linear */
+    int cg_batch;                 /* CG iterations launched between host polls */
+    int pad;
+    double sched_us_per_iter[6];  /* measured: candidate (block 64, 128, 256) x (order 0, 1), index 2 k + order */
+    double batch_ms_per_solve[5]; /* measured: full solve with cg_batch 4, 8, 16, 32, 64 */
+} fgi_tuning;
+/* Autotuner: times every (block, order) schedule on a 64-iteration solve of
+ * the caller's system (U, phi in the user layout, act's precision), then
+ * every cg_batch on full solves at act->cg_tol, each candidate once untimed
+ * first; leaves the fastest choices set in the context and reports all
+ * timings in *out (may be NULL).  Results of later calls do not depend on
+ * the schedule beyond rounding of the reductions (the same schedule always
+ * gives the same bits).  Synchronises the stream. */
+int fgi_autotune_cg(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* phi,
+                    fgi_tuning* out, void* stream);
 
 /* ------------------------------------------------ Hamiltonian (Section 2) */
 /* *S = S_G(U) (FP64). */
@@ -263,6 +285,11 @@ typedef struct {
 int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain* chains, const fgi_action* act,
                            const fgi_integrator* integ, double tau, int nsteps, double* dH, fgi_stats* st,
                            void* stream);
+/* The autotuner of fgi_autotune_cg on a batch of chains (every chain with
+ * fermions; phi = Mhat^+ eta per chain): the block size sets the Dslash grid
+ * of every chain, the order and cg_batch apply to the whole batch. */
+int fgi_autotune_batched(fgi_ctx* ctx, int nchains, const fgi_chain* chains, const fgi_action* act,
+                         fgi_tuning* out, void* stream);
 
 /* --------------------------------------------------------- utilities */
 /* U <- exp(h P) U on every link (exact su(3) exponential). */

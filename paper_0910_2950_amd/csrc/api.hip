@@ -290,6 +290,12 @@ int fgi_set_option(fgi_ctx* ctx, const char* name, double value) {
         } else if (n == "ru_delta") {
             if (!(value > 0 && value < 1)) throw Error(FGI_EINVAL, "ru_delta must be in (0,1)");
             c.ru_delta = value;
+        } else if (n == "dslash_block") {
+            if (!(value == 64 || value == 128 || value == 256))
+                throw Error(FGI_EINVAL, "dslash_block must be 64, 128 or 256");
+            c.ds_bs = (int)value;
+        } else if (n == "xcd_order") {
+            c.ds_xcd = value != 0;
         } else if (n == "graphs") {
             c.use_graphs = value != 0;
         } else if (n == "profile") {
@@ -1074,6 +1080,50 @@ struct BDriver {
 
 }  // namespace
 
+namespace {
+// Chain table and block counts of a batch (host side).  The Dslash grid
+// (GRID_DS) uses the context's current Dslash block size.
+void describe_batch(Ctx& c, int nchains, const fgi_chain* chains, std::vector<ChainDesc>& cd, Batch& B) {
+    const bool ferm = chains[0].kappa != 0.0;
+    cd.assign(nchains, ChainDesc{});
+    B = Batch{};
+    B.nc = nchains;
+    for (int i = 0; i < nchains; i++) {
+        const fgi_chain& ch = chains[i];
+        if ((ch.kappa != 0.0) != ferm) throw Error(FGI_EINVAL, "all chains need fermions or none");
+        need(ch.U, "chain U", 16);
+        need(ch.P, "chain P", 8);
+        if (ferm) need(ch.eta, "chain eta", 16);
+        ChainDesc& d = cd[i];
+        d.g = make_geom(ch.dims);
+        d.site0 = B.sites;
+        d.vol0 = B.vol;
+        d.link0 = B.links;
+        d.beta = ch.beta;
+        d.kappa = ch.kappa;
+        const long n[4] = {d.g.Vh, d.g.V, 4L * d.g.V, d.g.Vh};
+        const int bsz[4] = {256, 256, 256, c.ds_bs};
+        for (int k = 0; k < 4; k++) {
+            d.blk0[k] = B.nblk[k];
+            d.nblk[k] = (int)((n[k] + bsz[k] - 1) / bsz[k]);
+            B.nblk[k] += d.nblk[k];
+        }
+        d.user_U = ch.U;
+        d.user_P = ch.P;
+        d.user_eta = ch.eta;
+        B.sites += d.g.Vh;
+        B.vol += d.g.V;
+        B.links += 4L * d.g.V;
+    }
+}
+
+void upload_batch(Ctx& c, const std::vector<ChainDesc>& cd, Batch& B) {
+    ChainDesc* dcd = (ChainDesc*)c.cdesc.get(sizeof(ChainDesc) * cd.size());
+    FGI_HIP(hipMemcpyAsync(dcd, cd.data(), sizeof(ChainDesc) * cd.size(), hipMemcpyHostToDevice, c.stream));
+    B.cd = dcd;
+}
+}  // namespace
+
 extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain* chains, const fgi_action* act,
                                       const fgi_integrator* integ, double tau, int nsteps, double* dH, fgi_stats* st,
                                       void* stream) {
@@ -1086,40 +1136,12 @@ extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain
         if (act->kappa_hasen != 0.0) throw Error(FGI_EINVAL, "batched chains take one pseudofermion");
         if (act->fg_exact) throw Error(FGI_EINVAL, "batched chains use the displacement force-gradient form");
         const bool ferm = chains[0].kappa != 0.0;
-        std::vector<ChainDesc> cd(nchains);
+        std::vector<ChainDesc> cd;
         Batch B;
-        B.nc = nchains;
-        for (int i = 0; i < nchains; i++) {
-            const fgi_chain& ch = chains[i];
-            if ((ch.kappa != 0.0) != ferm) throw Error(FGI_EINVAL, "all chains need fermions or none");
-            need(ch.U, "chain U", 16);
-            need(ch.P, "chain P", 8);
-            if (ferm) need(ch.eta, "chain eta", 16);
-            ChainDesc& d = cd[i];
-            d.g = make_geom(ch.dims);
-            d.site0 = B.sites;
-            d.vol0 = B.vol;
-            d.link0 = B.links;
-            d.beta = ch.beta;
-            d.kappa = ch.kappa;
-            const long n[3] = {d.g.Vh, d.g.V, 4L * d.g.V};
-            for (int k = 0; k < 3; k++) {
-                d.blk0[k] = B.nblk[k];
-                d.nblk[k] = (int)((n[k] + 255) / 256);
-                B.nblk[k] += d.nblk[k];
-            }
-            d.user_U = ch.U;
-            d.user_P = ch.P;
-            d.user_eta = ch.eta;
-            B.sites += d.g.Vh;
-            B.vol += d.g.V;
-            B.links += 4L * d.g.V;
-        }
+        describe_batch(c, nchains, chains, cd, B);
         auto t0 = std::chrono::steady_clock::now();
         StreamScope ss(c, stream);
-        ChainDesc* dcd = (ChainDesc*)c.cdesc.get(sizeof(ChainDesc) * nchains);
-        FGI_HIP(hipMemcpyAsync(dcd, cd.data(), sizeof(ChainDesc) * nchains, hipMemcpyHostToDevice, c.stream));
-        B.cd = dcd;
+        upload_batch(c, cd, B);
         BFields f(c, *act);
         f.B = B;
         f.st = st;
@@ -1174,5 +1196,152 @@ extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain
         if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (!finite) throw Error(FGI_ENONFINITE, "dH is not finite");
         if (f.nonconv) throw Error(FGI_ENOCONV, "a CG solve reached cg_maxiter");
+    });
+}
+
+// ------------------------------------------------------------ autotuner ---
+// Schedules of the CG kernels picked by measurement on the caller's own
+// system: the Dslash block size (64, 128 or 256 even sites per block) and
+// block order (XCD-aware or linear) by timing a 64-iteration solve with each,
+// then the iterations per host poll (cg_batch 4 ... 64) by timing full solves
+// at the caller's tolerance.  Every candidate runs once untimed first (it
+// captures its HIP graphs).  The winners stay set in the context.
+namespace {
+const int kTuneBlocks[3] = {64, 128, 256};
+const int kTuneBatches[5] = {4, 8, 16, 32, 64};
+
+template <typename Solve>
+double time_solve(Ctx& c, Solve solve) {
+    solve();  // untimed: graph capture, first touch
+    FGI_HIP(hipStreamSynchronize(c.stream));
+    auto t0 = std::chrono::steady_clock::now();
+    int iters = solve();
+    FGI_HIP(hipStreamSynchronize(c.stream));
+    double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return iters > 0 ? s / iters : s;
+}
+
+// phase 1 with `solve64` (returns iterations), phase 2 with `solve_full`
+template <typename S64, typename SFull, typename Rebuild>
+void tune(Ctx& c, S64 solve64, SFull solve_full, Rebuild rebuild, fgi_tuning* out) {
+    fgi_tuning t{};
+    const int saved_batch = c.cg_batch;
+    double best = 1e300;
+    int bb = 256, bx = 1;
+    c.cg_batch = 16;
+    for (int k = 0; k < 3; k++)
+        for (int x = 0; x < 2; x++) {
+            c.ds_bs = kTuneBlocks[k];
+            c.ds_xcd = x;
+            rebuild();
+            const double us = 1e6 * time_solve(c, solve64);
+            t.sched_us_per_iter[2 * k + x] = us;
+            if (us < best) {
+                best = us;
+                bb = kTuneBlocks[k];
+                bx = x;
+            }
+        }
+    c.ds_bs = bb;
+    c.ds_xcd = bx;
+    rebuild();
+    best = 1e300;
+    int bn = saved_batch;
+    for (int k = 0; k < 5; k++) {
+        c.cg_batch = kTuneBatches[k];
+        const double ms = 1e3 * time_solve(c, [&] { solve_full(); return 1; });
+        t.batch_ms_per_solve[k] = ms;
+        if (ms < best) {
+            best = ms;
+            bn = kTuneBatches[k];
+        }
+    }
+    c.cg_batch = bn;
+    t.dslash_block = bb;
+    t.xcd_order = bx;
+    t.cg_batch = bn;
+    if (out) *out = t;
+}
+}  // namespace
+
+int fgi_autotune_cg(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* phi,
+                    fgi_tuning* out, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        check_action(act);
+        if (act->kappa == 0) throw Error(FGI_EINVAL, "kappa must be nonzero");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(phi, "phi", 16);
+        StreamScope ss(c, stream);
+        fgi_action a64 = *act;
+        a64.cg_maxiter = 64;
+        Fields f(c, g, *act), f64(c, g, a64);
+        f.U = (d2*)c.gauge.get(gauge_bytes(g));
+        pack_gauge(c, g, U, f.U);
+        if (f.sp != P64) {
+            f.Us = c.sloppy.get(sloppy_bytes(g));
+            make_sloppy(c, g, f.U, f.Us, f.sp, f.rc);
+        }
+        f64.U = f.U;
+        f64.Us = f.Us;
+        d2* ph = (d2*)c.phi.get(spinor_bytes(g));
+        d2* x = (d2*)c.X.get(spinor_bytes(g));
+        pack_even_spinor(c, g, phi, ph);
+        tune(
+            c, [&] { return f64.solve(f.U, f.Us, act->kappa, ph, x).iters; },
+            [&] { f.solve(f.U, f.Us, act->kappa, ph, x); }, [] {}, out);
+    });
+}
+
+int fgi_autotune_batched(fgi_ctx* ctx, int nchains, const fgi_chain* chains, const fgi_action* act, fgi_tuning* out,
+                         void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (nchains < 1 || !chains) throw Error(FGI_EINVAL, "need chains");
+        check_action(act);
+        if (chains[0].kappa == 0.0) throw Error(FGI_EINVAL, "the CG schedule is tuned on chains with fermions");
+        std::vector<ChainDesc> cd;
+        Batch B;
+        describe_batch(c, nchains, chains, cd, B);
+        StreamScope ss(c, stream);
+        upload_batch(c, cd, B);
+        fgi_action a64 = *act;
+        a64.cg_maxiter = 64;
+        BFields f(c, *act), f64(c, a64);
+        f.B = B;
+        f.fermions = true;
+        const size_t gb = sizeof(d2) * 9 * (size_t)B.links, sb = sizeof(d2) * 12 * (size_t)B.sites;
+        const size_t slb = sizeof(float) * 18 * (size_t)B.links;
+        f.U = (d2*)c.gauge.get(gb);
+        pack_b(c, B, f.U, 0, 1);
+        f.phi = (d2*)c.phi.get(sb);
+        f.X = (d2*)c.X.get(sb);
+        d2* eta = (d2*)c.eta.get(sb);
+        pack_b(c, B, eta, 2, 1);
+        if (f.sp != P64) {
+            f.Us = c.sloppy.get(slb);
+            make_sloppy_b(c, B, f.U, f.Us, f.sp, f.rc);
+        }
+        pf_heatbath_b(c, B, f.op64(f.U), eta, f.phi);
+        f64.U = f.U;
+        f64.Us = f.Us;
+        f64.phi = f.phi;
+        f64.X = f.X;
+        f64.fermions = true;
+        auto rebuild = [&] {  // the Dslash grid follows the block size
+            describe_batch(c, nchains, chains, cd, B);
+            upload_batch(c, cd, B);
+            f.B = B;
+            f64.B = B;
+        };
+        tune(
+            c,
+            [&] {
+                f64.solve(f.U, f.Us, f.phi, f.X);
+                return 64;
+            },
+            [&] { f.solve(f.U, f.Us, f.phi, f.X); }, rebuild, out);
     });
 }

@@ -17,7 +17,10 @@
 
 namespace fgi {
 
-static const int DBS = 256;  // threads per block of every Dslash-shaped kernel
+// Threads per block of the Dslash-shaped kernels: at most DBS (launch bounds and
+// LDS sizes); the block size in use (64, 128 or 256) is part of the tuned
+// schedule, as is the XCD-aware block order.  Helper kernels use DBS.
+static const int DBS = 256;
 static inline int nblk(long n, int bs) { return (int)((n + bs - 1) / bs); }
 
 // --------------------------------------------------------------- hop sum ---
@@ -158,6 +161,7 @@ struct DArgs {
     int iter;   // absolute index, or the offset from st->base inside a CG batch
     int g5out;
     int gate;   // with st: 0 skip once st->stop_at <= iteration, 1 skip unless st->act
+    int xcd;    // XCD-aware block order
 };
 
 // NT: the links are streamed with non-temporal loads (see links_streamed)
@@ -183,7 +187,7 @@ __device__ __forceinline__ void dslash_body(const DArgs& A, int b, int nb, doubl
             }
         }
     }
-    int s = b * DBS + threadIdx.x;
+    int s = b * blockDim.x + threadIdx.x;
     double nrm = 0.0;
     if (s < g.Vh) {
         cx<R> acc[4][3];
@@ -250,8 +254,8 @@ __global__ void __launch_bounds__(DBS) k_dslash(DArgs A) {
     __shared__ double lds[DBS / 64];
     // site blocks in XCD-aware order (the same order in every kernel of the
     // solver, so a site stays on one XCD); a reduction block comes last
-    const int nb = (A.g.Vh + DBS - 1) / DBS;
-    const int b = (int)blockIdx.x < nb ? xcd_block(blockIdx.x, nb) : blockIdx.x;
+    const int nb = (A.g.Vh + blockDim.x - 1) / blockDim.x;
+    const int b = (int)blockIdx.x < nb ? (A.xcd ? xcd_block(blockIdx.x, nb) : (int)blockIdx.x) : blockIdx.x;
     dslash_body<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN, NT>(A, b, nb, lds);
 }
 
@@ -281,8 +285,8 @@ template <int PL, int RECON> __device__ __forceinline__ size_t link_byte_off(con
 template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN>
 __global__ void __launch_bounds__(DBS) k_dslash_b(DArgs base, const ChainDesc* __restrict__ cd, int nc, int nsb) {
     __shared__ double lds[DBS / 64];
-    const int gb = (int)blockIdx.x < nsb ? xcd_block(blockIdx.x, nsb) : blockIdx.x;
-    const int c = gb < nsb ? find_chain(cd, nc, gb, GRID_VH) : gb - nsb;
+    const int gb = (int)blockIdx.x < nsb ? (base.xcd ? xcd_block(blockIdx.x, nsb) : (int)blockIdx.x) : blockIdx.x;
+    const int c = gb < nsb ? find_chain(cd, nc, gb, GRID_DS) : gb - nsb;
     const ChainDesc& d = cd[c];
     DArgs A = base;
     A.g = d.g;
@@ -294,10 +298,10 @@ __global__ void __launch_bounds__(DBS) k_dslash_b(DArgs base, const ChainDesc* _
     A.out = spin_off<POUT>(base.out, d);
     A.x = spin_off<PX>(base.x, d);
     A.r = spin_off<PX>(base.r, d);
-    A.partial = base.partial ? base.partial + d.blk0[GRID_VH] : nullptr;
+    A.partial = base.partial ? base.partial + d.blk0[GRID_DS] : nullptr;
     A.st = base.st ? base.st + c : nullptr;
-    const int b = gb < nsb ? gb - d.blk0[GRID_VH] : d.nblk[GRID_VH];
-    dslash_body<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN, false>(A, b, d.nblk[GRID_VH], lds);
+    const int b = gb < nsb ? gb - d.blk0[GRID_DS] : d.nblk[GRID_DS];
+    dslash_body<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN, false>(A, b, d.nblk[GRID_DS], lds);
 }
 
 // First kernel of a CG iteration: p = r + beta p, stored in p's precision.
@@ -313,7 +317,7 @@ __device__ __forceinline__ void cg_p_body(int Vh, SpinorPtr p, SpinorPtr r, CGSt
     // the state and the site's r and p are loaded before anything waits on
     // them, so their latencies overlap with each other and with the partials
     const StateView S = load_state(st);
-    const int s = b * DBS + threadIdx.x;
+    const int s = b * blockDim.x + threadIdx.x;
     const int sl = s < Vh ? s : Vh - 1;
     RawSp<PX> rr_raw;
     RawSp<PP> pp_raw;
@@ -342,22 +346,22 @@ __device__ __forceinline__ void cg_p_body(int Vh, SpinorPtr p, SpinorPtr r, CGSt
 }
 
 template <int PP, int PX>
+// np: the number of |r|^2 partials (blocks of the M_CGX launch, the same grid)
 __global__ void __launch_bounds__(DBS) k_cg_p(int Vh, SpinorPtr p, SpinorPtr r, CGState* st, const double* partial,
-                                              int j) {
+                                              int np, int xcd, int j) {
     __shared__ double lds[DBS / 64];
-    const int nb = (Vh + DBS - 1) / DBS;
-    cg_p_body<PP, PX>(Vh, p, r, st, partial, j, xcd_block(blockIdx.x, nb), nb, lds);
+    cg_p_body<PP, PX>(Vh, p, r, st, partial, j, xcd ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x, np, lds);
 }
 
 template <int PP, int PX>
 __global__ void __launch_bounds__(DBS) k_cg_p_b(const ChainDesc* __restrict__ cd, int nc, SpinorPtr p, SpinorPtr r,
-                                                CGState* st, const double* partial, int j) {
+                                                CGState* st, const double* partial, int xcd, int j) {
     __shared__ double lds[DBS / 64];
-    const int gb = xcd_block(blockIdx.x, gridDim.x);
-    const int c = find_chain(cd, nc, gb, GRID_VH);
+    const int gb = xcd ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int c = find_chain(cd, nc, gb, GRID_DS);
     const ChainDesc& d = cd[c];
-    cg_p_body<PP, PX>(d.g.Vh, spin_off<PP>(p, d), spin_off<PX>(r, d), st + c, partial + d.blk0[GRID_VH], j,
-                      gb - d.blk0[GRID_VH], d.nblk[GRID_VH], lds);
+    cg_p_body<PP, PX>(d.g.Vh, spin_off<PP>(p, d), spin_off<PX>(r, d), st + c, partial + d.blk0[GRID_DS], j,
+                      gb - d.blk0[GRID_DS], d.nblk[GRID_DS], lds);
 }
 
 // Last node of a CG batch: fold the |r|^2 partials of the batch's last
@@ -387,7 +391,7 @@ __global__ void __launch_bounds__(DBS) k_advance_b(const ChainDesc* __restrict__
                                                    const double* partial, int n) {
     __shared__ double lds[DBS / 64];
     const ChainDesc& d = cd[blockIdx.x];
-    advance_body(st + blockIdx.x, partial + d.blk0[GRID_VH], d.nblk[GRID_VH], n, lds);
+    advance_body(st + blockIdx.x, partial + d.blk0[GRID_DS], d.nblk[GRID_DS], n, lds);
 }
 
 // conversion between storage precisions (through FP64 registers)
@@ -630,15 +634,16 @@ static int links_streamed(const FermionOp& op, long nlinks) {
 
 template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN>
 static void launch_dslash_nt(Ctx& c, bool nt, int nb, DArgs& a) {
-    if (nt) hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN, true>), dim3(nb), dim3(DBS), 0, c.stream, a);
-    else hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN, false>), dim3(nb), dim3(DBS), 0, c.stream, a);
+    if (nt) hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN, true>), dim3(nb), dim3(c.ds_bs), 0, c.stream, a);
+    else hipLaunchKernelGGL((k_dslash<MODE, PIN, PC, POUT, PX, PL, RECON, G5IN, false>), dim3(nb), dim3(c.ds_bs), 0, c.stream, a);
 }
 
 template <int MODE, int PIN, int PC, int POUT, int PX, int G5IN>
 static void launch_dslash(Ctx& c, const FermionOp& op, DArgs& a) {
     const bool nt = links_streamed(op, 4L * a.g.V);
+    a.xcd = c.ds_xcd;
     // an M_HOP inside CG (state and partials) carries the pAp reduction block
-    int nb = nblk(a.g.Vh, DBS) + ((MODE == M_HOP && a.st && a.partial) ? 1 : 0);
+    int nb = nblk(a.g.Vh, c.ds_bs) + ((MODE == M_HOP && a.st && a.partial) ? 1 : 0);
     if constexpr (PIN == P64) {
         if (op.prec != P64) throw Error(-1, "FP64 spinors need FP64 links");
         launch_dslash_nt<MODE, PIN, PC, POUT, PX, P64, 18, G5IN>(c, nt, nb, a);
@@ -766,7 +771,7 @@ static double true_residual(Ctx& c, const FermionOp& op64, const d2* phi, const 
     b.g5out = 1;
     b.partial = partial_buf(c, g);
     launch_dslash<M_RESID, P64, P64, P64, P64, 0>(c, op64, b);
-    final_sum(c, b.partial, nblk(g.Vh, DBS), scal + 1);
+    final_sum(c, b.partial, nblk(g.Vh, c.ds_bs), scal + 1);
     FGI_HIP(hipMemcpyAsync(c.host_scal + 1, scal + 1, sizeof(double), hipMemcpyDeviceToHost, c.stream));
     FGI_HIP(hipStreamSynchronize(c.stream));
     return c.host_scal[1];
@@ -791,8 +796,8 @@ static void cg_iteration(Ctx& c, const FermionOp& ops, const CGVecs& v, int j) {
     CGState* st = dev_state(c);
     double* part = partial_buf(c, *ops.g);
     const int Vh = ops.g->Vh;
-    hipLaunchKernelGGL((k_cg_p<PP, PX>), dim3(nblk(Vh, DBS)), dim3(DBS), 0, c.stream, Vh, v.p, v.r, st,
-                       (const double*)part, j);
+    hipLaunchKernelGGL((k_cg_p<PP, PX>), dim3(nblk(Vh, c.ds_bs)), dim3(c.ds_bs), 0, c.stream, Vh, v.p, v.r, st,
+                       (const double*)part, nblk(Vh, c.ds_bs), c.ds_xcd, j);
     FGI_LAUNCH_CHECK();
     {
         DArgs a = base_args(ops, 1);
@@ -841,7 +846,7 @@ template <int PP, int PX>
 static void cg_batch_eager(Ctx& c, const FermionOp& ops, const CGVecs& v, int B) {
     for (int j = 0; j < B; j++) cg_iteration<PP, PX>(c, ops, v, j);
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(DBS), 0, c.stream, dev_state(c), (const double*)partial_buf(c, *ops.g),
-                       nblk(ops.g->Vh, DBS), B);
+                       nblk(ops.g->Vh, c.ds_bs), B);
     FGI_LAUNCH_CHECK();
 }
 
@@ -893,10 +898,10 @@ static GraphEntry& cached_graph(Ctx& c, const std::string& key, Body body) {
 template <int PP, int PX>
 static std::string graph_key(const char* what, Ctx& c, const FermionOp& ops, const CGVecs& v, int n) {
     char key[512];
-    snprintf(key, sizeof key, "%s/%d/%d/%p/%.17g/%d/%d/%d/%d/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%d", what, PP, PX,
-             ops.links, ops.kappa, ops.prec, ops.recon, ops.g->L[0], ops.g->L[1], ops.g->L[2], ops.g->L[3],
+    snprintf(key, sizeof key, "%s/%d/%d/%p/%.17g/%d/%d/%d/%d/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%d/%d/%d", what, PP,
+             PX, ops.links, ops.kappa, ops.prec, ops.recon, ops.g->L[0], ops.g->L[1], ops.g->L[2], ops.g->L[3],
              ops.g->Vh, v.x.v, v.r.v, v.p.v, v.q.v, v.t.v, (void*)v.p.norm, (void*)dev_state(c),
-             (void*)partial_buf(c, *ops.g), n);
+             (void*)partial_buf(c, *ops.g), n, c.ds_bs, c.ds_xcd);
     return key;
 }
 
@@ -1047,21 +1052,22 @@ static CGResult cg_run(Ctx& c, const FermionOp& op64, const FermionOp& ops, cons
 // ====================================================== batched chains ======
 template <int MODE, int PIN, int PC, int POUT, int PX, int G5IN>
 static void launch_dslash_b(Ctx& c, const Batch& B, const FermionOp& op, DArgs& a) {
-    const int nsb = B.nblk[GRID_VH];
+    const int nsb = B.nblk[GRID_DS];
+    a.xcd = c.ds_xcd;
     // an M_HOP inside CG (states and partials) carries one pAp reduction block per chain
     const int nb = nsb + ((MODE == M_HOP && a.st && a.partial) ? B.nc : 0);
     if constexpr (PIN == P64) {
-        hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P64, 18, G5IN>), dim3(nb), dim3(DBS), 0, c.stream, a,
+        hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P64, 18, G5IN>), dim3(nb), dim3(c.ds_bs), 0, c.stream, a,
                            B.cd, B.nc, nsb);
     } else {
         if (op.prec == P32 && op.recon == 18)
-            hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P32, 18, G5IN>), dim3(nb), dim3(DBS), 0, c.stream,
+            hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P32, 18, G5IN>), dim3(nb), dim3(c.ds_bs), 0, c.stream,
                                a, B.cd, B.nc, nsb);
         else if (op.prec == P32)
-            hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P32, 12, G5IN>), dim3(nb), dim3(DBS), 0, c.stream,
+            hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P32, 12, G5IN>), dim3(nb), dim3(c.ds_bs), 0, c.stream,
                                a, B.cd, B.nc, nsb);
         else
-            hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P16, 12, G5IN>), dim3(nb), dim3(DBS), 0, c.stream,
+            hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P16, 12, G5IN>), dim3(nb), dim3(c.ds_bs), 0, c.stream,
                                a, B.cd, B.nc, nsb);
     }
     FGI_LAUNCH_CHECK();
@@ -1157,14 +1163,14 @@ static void true_residual_b(Ctx& c, const Batch& B, const FermionOp& op64, const
     b.st = st;
     b.gate = 1;
     launch_dslash_b<M_RESID, P64, P64, P64, P64, 0>(c, B, op64, b);
-    final_sums_b(c, B, b.partial, GRID_VH, res);
+    final_sums_b(c, B, b.partial, GRID_DS, res);
 }
 
 template <int PP, int PX>
 static void cg_iteration_b(Ctx& c, const Batch& B, const FermionOp& ops, const CGVecs& v, int j, CGState* st) {
     double* part = partial_buf(c, B);
-    hipLaunchKernelGGL((k_cg_p_b<PP, PX>), dim3(B.nblk[GRID_VH]), dim3(DBS), 0, c.stream, B.cd, B.nc, v.p, v.r, st,
-                       (const double*)part, j);
+    hipLaunchKernelGGL((k_cg_p_b<PP, PX>), dim3(B.nblk[GRID_DS]), dim3(c.ds_bs), 0, c.stream, B.cd, B.nc, v.p, v.r, st,
+                       (const double*)part, c.ds_xcd, j);
     FGI_LAUNCH_CHECK();
     {
         DArgs a = base_args_b(ops, 1);
@@ -1291,9 +1297,11 @@ static std::vector<CGResult> cg_run_b(Ctx& c, const Batch& B, const FermionOp& o
     const int Bi = c.cg_batch;
     GraphEntry* ge = nullptr;
     if (c.use_graphs) {
-        char key[256];
-        snprintf(key, sizeof key, "bcg/%d/%d/%p/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%d", PP, PX, ops.links, ops.prec,
-                 ops.recon, nc, (void*)B.cd, v.x.v, v.r.v, v.p.v, v.q.v, v.t.v, (void*)st, (void*)part, Bi);
+        // the grid sizes are baked into the graph (the chain table is read at run time)
+        char key[320];
+        snprintf(key, sizeof key, "bcg/%d/%d/%p/%d/%d/%d/%d/%ld/%p/%p/%p/%p/%p/%p/%p/%p/%d/%d/%d", PP, PX, ops.links,
+                 ops.prec, ops.recon, nc, B.nblk[GRID_DS], B.sites, (void*)B.cd, v.x.v, v.r.v, v.p.v, v.q.v, v.t.v,
+                 (void*)st, (void*)part, Bi, c.ds_bs, c.ds_xcd);
         ge = &cached_graph(c, key, [&] { cg_batch_b<PP, PX>(c, B, ops, v, Bi, st); });
     }
     int left = 0;

@@ -73,7 +73,9 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // batched chains: independent lattices stored one after another in every
 // field; a kernel launched over all of them finds its chain from its block.
 // --------------------------------------------------------------------------
-enum GridKind { GRID_VH = 0, GRID_V = 1, GRID_4V = 2 };
+// GRID_VH, GRID_V, GRID_4V: blocks of 256 even sites, sites or links;
+// GRID_DS: even sites in blocks of the Dslash block size (a tuned schedule)
+enum GridKind { GRID_VH = 0, GRID_V = 1, GRID_4V = 2, GRID_DS = 3 };
 
 struct ChainDesc {
     Geom g;
@@ -81,8 +83,8 @@ struct ChainDesc {
     long vol0;      // sum of V (per-site densities)
     long link0;     // sum of 4V (link / momentum offsets)
     double beta, kappa;
-    int blk0[3];    // first block of the chain in the Vh-, V- and 4V-sized grids
-    int nblk[3];    // its number of blocks there
+    int blk0[4];    // first block of the chain in each grid kind
+    int nblk[4];    // its number of blocks there
     const void* user_U;   // user-layout buffers (pack / unpack)
     void* user_P;
     const void* user_eta;

@@ -116,7 +116,10 @@ struct Ctx {
     std::vector<GraphEntry> graphs;
     // solver tuning
     int cg_batch = 8;          // iterations launched between host polls
-    int dslash_split = 0;      // 0 = automatic
+    // schedule of the Dslash-shaped kernels (set by hand or by fgi_autotune_cg):
+    // threads (= even sites) per block, and XCD-aware block order on/off
+    int ds_bs = 256;
+    int ds_xcd = 1;
     double ru_delta = 0.1;     // reliable-update trigger |r| drop
 };
 
@@ -125,7 +128,7 @@ struct Ctx {
 struct Batch {
     const ChainDesc* cd = nullptr;   // device array [nc]
     int nc = 0;
-    int nblk[3] = {0, 0, 0};
+    int nblk[4] = {0, 0, 0, 0};
     long sites = 0, vol = 0, links = 0;  // totals: sum Vh, sum V, sum 4V
 };
 

@@ -61,6 +61,16 @@ class fgi_chain(ctypes.Structure):
                 ("eta", ctypes.c_void_p)]
 
 
+class fgi_tuning(ctypes.Structure):
+    _fields_ = [("dslash_block", ctypes.c_int), ("xcd_order", ctypes.c_int), ("cg_batch", ctypes.c_int),
+                ("pad", ctypes.c_int), ("sched_us_per_iter", ctypes.c_double * 6),
+                ("batch_ms_per_solve", ctypes.c_double * 5)]
+
+    def as_dict(self):
+        return dict(dslash_block=self.dslash_block, xcd_order=self.xcd_order, cg_batch=self.cg_batch,
+                    sched_us_per_iter=list(self.sched_us_per_iter), batch_ms_per_solve=list(self.batch_ms_per_solve))
+
+
 class fgi_stats(ctypes.Structure):
     _fields_ = [("solves", ctypes.c_long), ("cg_iters", ctypes.c_long), ("cg_iters_max", ctypes.c_int),
                 ("reliable_updates", ctypes.c_int), ("max_rel_resid", ctypes.c_double),
@@ -102,6 +112,8 @@ SIGNATURES = {
                             _i, _P(_d), _P(fgi_stats), _vp]),
     "fgi_trajectory_batched": (_i, [_vp, _i, _vp, _P(fgi_action), _P(fgi_integrator), _d, _i, _P(_d),
                                     _P(fgi_stats), _vp]),
+    "fgi_autotune_cg": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _P(fgi_tuning), _vp]),
+    "fgi_autotune_batched": (_i, [_vp, _i, _vp, _P(fgi_action), _P(fgi_tuning), _vp]),
     "fgi_link_update": (_i, [_vp, _P(fgi_geom), _d, _vp, _vp, _vp]),
     "fgi_reunitarize": (_i, [_vp, _P(fgi_geom), _vp, _vp]),
     "fgi_exp_su3": (_i, [_vp, _i, _vp, _d, _vp, _vp]),
@@ -412,6 +424,31 @@ class Context:
         d = st.as_dict()
         d["status"] = rc
         return list(dH), d
+
+    def autotune_cg(self, dims, act, U, phi):
+        """Time the CG schedules on this system, keep the fastest; returns the choices and timings."""
+        su, _, se = self._shapes(dims)
+        t = fgi_tuning()
+        _check(lib().fgi_autotune_cg(self.h, _geom(dims), ctypes.byref(act.c()), _ptr(U, torch.complex128, su, "U"),
+                                     _ptr(phi, torch.complex128, se, "phi"), ctypes.byref(t), _stream()))
+        return t.as_dict()
+
+    def autotune_batched(self, chains, act):
+        """The autotuner on a batch of chains (dicts with dims, beta, kappa, U, P, eta as for trajectory_batched)."""
+        n = len(chains)
+        arr = (fgi_chain * n)()
+        for i, ch in enumerate(chains):
+            su, sp, se = self._shapes(ch["dims"])
+            arr[i].dims = (ctypes.c_int * 4)(*[int(d) for d in ch["dims"]])
+            arr[i].beta = float(ch["beta"])
+            arr[i].kappa = float(ch.get("kappa", 0.0))
+            arr[i].U = _ptr(ch["U"], torch.complex128, su, "U")
+            arr[i].P = _ptr(ch["P"], torch.float64, sp, "P")
+            arr[i].eta = _ptr(ch.get("eta"), torch.complex128, se, "eta")
+        t = fgi_tuning()
+        _check(lib().fgi_autotune_batched(self.h, n, ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(act.c()),
+                                          ctypes.byref(t), _stream()))
+        return t.as_dict()
 
     # ---- utilities
     def link_update(self, dims, h, P, U):
