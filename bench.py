@@ -90,10 +90,10 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel_key):
+def read_traffic(kernel_key, lattice="16x16x16x32"):
     """HBM bytes per launch of the profiled Dslash from the committed rocprofv3
     counter summary, or None when it is absent or the kernel source changed."""
-    path = os.path.join(ROOT, "profiles", "dslash_hbm_traffic_16x16x16x32.txt")
+    path = os.path.join(ROOT, "profiles", "dslash_hbm_traffic_%s.txt" % lattice)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -214,7 +214,7 @@ def tile_field(torch, U, dims, f=2):
 def dslash_roofline_large(R, U_therm, prec, recon):
     """The same bare-hop timing as the main roofline, on the thermalised field
     tiled to 32^3x64 (16 waves of sites per SIMD instead of one): 16 HIP-event
-    timed launches after each of two short CG solves (32 iterations)."""
+    timed launches after each of two CG solves of 32 full iterations."""
     torch, fgi = R.torch, R.fgi
     Ub, dims_b = tile_field(torch, U_therm, R.dims, 2)
     V = int(np.prod(dims_b))
@@ -224,19 +224,25 @@ def dslash_roofline_large(R, U_therm, prec, recon):
     act = fgi.Action(beta=R.args.beta, kappa=R.args.kappa, cg_tol=1e-30, cg_maxiter=32, prec=prec, link_recon=recon)
     R.ctx.set_option("profile_prec", PREC_ID[prec] if prec != "mp32" else 1)
     R.ctx.set_option("profile", 1)
+    # no inner stops (reliable updates) in these fixed-length solves, so every
+    # CG launch does its full work (the profiled averages then describe the kernels)
+    R.ctx.set_option("ru_delta", 1e-30)
     R.ctx.cg_solve(dims_b, act, Ub, phi, allow_noconv=True)
     R.ctx.set_option("profile_reset", 1)
     for _ in range(2):
         R.ctx.cg_solve(dims_b, act, Ub, phi, allow_noconv=True)
     ms, launches, sites = R.ctx.get_profile()
     R.ctx.set_option("profile", 0)
+    R.ctx.set_option("ru_delta", 0.1)
     del Ub, phi
     torch.cuda.empty_cache()
     bps = DSLASH_BYTES[(prec, recon)]
     avg_s = ms / 1e3 / launches
     achieved = sites / launches * bps / avg_s / 1e9
     return dict(lattice=list(dims_b), bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), avg_launch_us=round(avg_s * 1e6, 3), launches_timed=launches,
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=read_traffic("%s/%d" % (prec, recon), "x".join(map(str, dims_b))),
+                avg_launch_us=round(avg_s * 1e6, 3), launches_timed=launches,
                 algorithmic_bytes_per_launch=sites / launches * bps,
                 kernel="bare even-odd Dslash hop t = D_oe g5 q (%s/%d), %d output sites per launch, on the "
                        "thermalised 16^3x32 field repeated 2x2x2x2" % (prec, recon, V // 2))
