@@ -595,23 +595,15 @@ double oracle_pf_action(const int L[4], double kappa, const cplx *U, const cplx 
     return s;
 }
 
-/* Generic bilinear force.  For full-lattice X = (X_e, D_oe X_e) and
- * Y = (Y_e, g5 D_oe g5 Y_e) (so that Y_o = D_eo^+ Y_e) the derivative of
- * 2 Re[Y^+ D X] along link (mu, x) is
- *     2 Re Tr[T^a W] * bc,  W = sum_s [U X(x+mu)]_s [(1-g_mu) Y(x)]_s^+
- *                             + sum_s [U (1+g_mu) Y(x+mu)]_s [X(x)]_s^+,
- * with Re Tr[T^a W] = -[TA(W)]_a / 2; this adds coef * bc * [TA W]_a to F. */
-static void force_xy_add(const int L[4], const cplx *U, const cplx *Xe, const cplx *Ye, double coef, double *F) {
+/* Full-lattice vectors of the force: X = (X_e, D_oe X_e) and
+ * Y = (Y_e, g5 D_oe g5 Y_e), so that Y_o = D_eo^+ Y_e. */
+static void full_xy(const int L[4], const cplx *U, const cplx *Xe, const cplx *Ye, cplx *X, cplx *Y) {
     long V = lat_volume(L);
-    gamma_init();
-    cplx *X = malloc(sizeof(cplx) * 12 * V), *Y = malloc(sizeof(cplx) * 12 * V);
     cplx *t = malloc(sizeof(cplx) * 12 * V);
-    /* X = (X_e, D_oe X_e) */
     even_to_full(L, Xe, X);
     oracle_dhop(L, U, X, t);
     for (long i = 0; i < V; i++)
         if (lat_parity(L, i) == 1) memcpy(X + i * 12, t + i * 12, 12 * sizeof(cplx));
-    /* Y = (Y_e, g5 D_oe g5 Y_e) */
     even_to_full(L, Ye, Y);
     apply_g5(V, Y);
     oracle_dhop(L, U, Y, t);
@@ -619,6 +611,21 @@ static void force_xy_add(const int L[4], const cplx *U, const cplx *Xe, const cp
     even_to_full(L, Ye, Y);
     for (long i = 0; i < V; i++)
         if (lat_parity(L, i) == 1) memcpy(Y + i * 12, t + i * 12, 12 * sizeof(cplx));
+    free(t);
+}
+
+/* Generic bilinear force of full-lattice vectors X, Y.  The derivative of
+ * 2 Re[Y^+ D X] along link (mu, x) is
+ *     2 Re Tr[T^a W] * bc,  W = sum_s [U X(x+mu)]_s [(1-g_mu) Y(x)]_s^+
+ *                             + sum_s [U (1+g_mu) Y(x+mu)]_s [X(x)]_s^+,
+ * with Re Tr[T^a W] = -[TA(W)]_a / 2; this adds coef * bc * [TA W]_a to F.
+ * When Vm is given, W is replaced by Vm_l W: the same bilinear with the
+ * link U_l replaced by its derivative V_l U_l inside e_a D (both the link
+ * and its adjoint in the backward hop, where d(-U^+ T^a) = U^+ V T^a). */
+static void bilinear_add(const int L[4], const cplx *U, const cplx *X, const cplx *Y, const mat3 *Vm,
+                         double coef, double *F) {
+    long V = lat_volume(L);
+    gamma_init();
 #pragma omp parallel for collapse(2) schedule(static)
     for (int mu = 0; mu < 4; mu++)
         for (long i = 0; i < V; i++) {
@@ -636,11 +643,20 @@ static void force_xy_add(const int L[4], const cplx *U, const cplx *Xe, const cp
                 for (int p = 0; p < 3; p++)
                     for (int q = 0; q < 3; q++)
                         W.m[p][q] += a1[s * 3 + p] * conj(b1[s * 3 + q]) + a2[s * 3 + p] * conj(x0[s * 3 + q]);
+            if (Vm) W = m_mul(Vm[(long)mu * V + i], W);
             double x[8];
             alg_components(traceless_antiherm(W), x);
             for (int a = 0; a < 8; a++) F[((long)mu * V + i) * 8 + a] += coef * bc * x[a];
         }
-    free(X); free(Y); free(t);
+}
+
+/* bilinear force of the even parts X_e, Y_e (odd parts from full_xy) */
+static void force_xy_add(const int L[4], const cplx *U, const cplx *Xe, const cplx *Ye, double coef, double *F) {
+    long V = lat_volume(L);
+    cplx *X = malloc(sizeof(cplx) * 12 * V), *Y = malloc(sizeof(cplx) * 12 * V);
+    full_xy(L, U, Xe, Ye, X, Y);
+    bilinear_add(L, U, X, Y, NULL, coef, F);
+    free(X); free(Y);
 }
 
 /* Pseudofermion force for S = phi^+ (Mhat^+ Mhat)^-1 phi given the solution
@@ -656,6 +672,109 @@ void oracle_fermion_force_add(const int L[4], double kappa, const cplx *U, const
     oracle_mhat(L, kappa, U, Xe, ye, 0);
     force_xy_add(L, U, Xe, ye, scale * kappa * kappa, F);
     free(ye);
+}
+
+/* Link field dU_l = V_l U_l, the derivative of exp(t V_l) U_l at t = 0.  The
+ * hopping term is linear in every link and in its adjoint, and
+ * d(U_l^+) = (V_l U_l)^+, so the hopping term built on dU is the derivative
+ * of D along V. */
+static void tangent_links(long V, const cplx *U, const mat3 *Vm, cplx *dU) {
+    for (int mu = 0; mu < 4; mu++)
+        for (long i = 0; i < V; i++) link_put(dU, V, mu, i, m_mul(Vm[(long)mu * V + i], link_get(U, V, mu, i)));
+}
+
+/* odd part of D_{oe} applied to an even vector given on the full lattice
+ * (even sites set, odd zero): out = (0, D_oe in_e) with the links U */
+static void hop_to_odd(const int L[4], const cplx *U, const cplx *in_full, cplx *out_full) {
+    oracle_dhop(L, U, in_full, out_full);
+    zero_parity(L, out_full, 0);
+}
+
+/* derivative of Mhat along V on a compact even vector:
+ *   dMhat in_e = -kappa^2 (dD_eo D_oe + D_eo dD_oe) in_e,
+ * dD the hopping term on the tangent links dU; dagger != 0 applies
+ * dMhat^+ = g5 dMhat g5. */
+static void dmhat(const int L[4], double kappa, const cplx *U, const cplx *dU, const cplx *in, cplx *out,
+                  int dagger) {
+    long V = lat_volume(L), Vh = V / 2;
+    cplx *f = malloc(sizeof(cplx) * 12 * V), *g = malloc(sizeof(cplx) * 12 * V);
+    cplx *h1 = malloc(sizeof(cplx) * 12 * V), *h2 = malloc(sizeof(cplx) * 12 * V);
+    cplx *tmp = malloc(sizeof(cplx) * 12 * Vh), *e1 = malloc(sizeof(cplx) * 12 * Vh);
+    memcpy(tmp, in, sizeof(cplx) * 12 * Vh);
+    if (dagger) apply_g5(Vh, tmp);
+    even_to_full(L, tmp, f);
+    hop_to_odd(L, U, f, g);       /* D_oe in */
+    oracle_dhop(L, dU, g, h1);    /* even part: dD_eo D_oe in */
+    hop_to_odd(L, dU, f, g);      /* dD_oe in */
+    oracle_dhop(L, U, g, h2);     /* even part: D_eo dD_oe in */
+    full_to_even(L, h1, out);
+    full_to_even(L, h2, e1);
+    for (long k = 0; k < Vh * 12; k++) out[k] = -kappa * kappa * (out[k] + e1[k]);
+    if (dagger) apply_g5(Vh, out);
+    free(f); free(g); free(h1); free(h2); free(tmp); free(e1);
+}
+
+/* Directional derivative of the pseudofermion force along a field of algebra
+ * elements V_l (components v[mu][i][8]):
+ *   J_V[F_F] = d/dt F_F(exp(t V) U) at t = 0,
+ * the force gradient of Section 4 for S = phi^+ A^-1 phi, A = Mhat^+ Mhat,
+ * given X_e = A^-1 phi.  Section 4 writes the force as X^+ e_a(A) X and
+ * differentiates it by the Leibniz rule: one derivative of X, which costs
+ * the one extra solve
+ *     Z = d_V X_e = -A^-1 (d_V A) X_e,
+ *     d_V A = dMhat^+ Mhat + Mhat^+ dMhat,
+ * (Section 4's Y, whose operator e^j(S) e_j is -d_V for V = F), one
+ * derivative of the explicit link dependence, and the derivative of the
+ * other X.  Here the force is kept in its hopping-term form
+ * kappa^2 bc [TA W(X, Y)]_a with full-lattice X = (X_e, D_oe X_e),
+ * Y = (Mhat X_e, D_eo^+ Mhat X_e), so the same three contributions read
+ *     J = kappa^2 bc [TA( W(dX, Y) + W(X, dY) + V W(X, Y) )]_a
+ * with the full derivatives of the vectors
+ *     dX = (Z, dD_oe X_e + D_oe Z),
+ *     dY = (dMhat X_e + Mhat Z, g5 dD_oe g5 Y_e + g5 D_oe g5 dY_e)
+ * and V W the explicit derivative of e_a D (bilinear_add with Vm).
+ * scale * J is ADDED to Jout.  Returns the CG iteration count of the Z
+ * solve (-1 on maxiter). */
+int oracle_fermion_force_tangent_add(const int L[4], double kappa, const cplx *U, const cplx *Xe,
+                                     const double *v, double tol, int maxiter, double scale, double *Jout) {
+    long V = lat_volume(L), Vh = V / 2;
+    size_t ne = sizeof(cplx) * 12 * Vh, nf = sizeof(cplx) * 12 * V;
+    mat3 *Vm = malloc(sizeof(mat3) * 4 * V);
+    for (long l = 0; l < 4 * V; l++) Vm[l] = alg_from_components(v + l * 8);
+    cplx *dU = malloc(sizeof(cplx) * 4 * V * 9);
+    tangent_links(V, U, Vm, dU);
+    cplx *Ye = malloc(ne), *a = malloc(ne), *b = malloc(ne), *rhs = malloc(ne), *Z = malloc(ne);
+    cplx *dYe = malloc(ne);
+    /* Y_e = Mhat X_e;  rhs = -(dMhat^+ Y_e + Mhat^+ dMhat X_e) = -(d_V A) X_e */
+    oracle_mhat(L, kappa, U, Xe, Ye, 0);
+    dmhat(L, kappa, U, dU, Xe, a, 0);
+    oracle_mhat(L, kappa, U, a, b, 1);
+    dmhat(L, kappa, U, dU, Ye, rhs, 1);
+    for (long k = 0; k < Vh * 12; k++) rhs[k] = -(rhs[k] + b[k]);
+    int it = oracle_cg(L, kappa, U, rhs, Z, tol, maxiter, NULL);
+    /* dY_e = dMhat X_e + Mhat Z */
+    oracle_mhat(L, kappa, U, Z, b, 0);
+    for (long k = 0; k < Vh * 12; k++) dYe[k] = a[k] + b[k];
+    /* full vectors */
+    cplx *X = malloc(nf), *Y = malloc(nf), *dX = malloc(nf), *dY = malloc(nf);
+    cplx *f = malloc(nf), *g = malloc(nf);
+    full_xy(L, U, Xe, Ye, X, Y);
+    full_xy(L, U, Z, dYe, dX, dY);    /* (Z, D_oe Z) and (dY_e, g5 D_oe g5 dY_e) */
+    even_to_full(L, Xe, f);
+    hop_to_odd(L, dU, f, g);          /* + dD_oe X_e */
+    for (long k = 0; k < V * 12; k++) dX[k] += g[k];
+    even_to_full(L, Ye, f);
+    apply_g5(V, f);
+    hop_to_odd(L, dU, f, g);
+    apply_g5(V, g);                   /* + g5 dD_oe g5 Y_e */
+    for (long k = 0; k < V * 12; k++) dY[k] += g[k];
+    double c = scale * kappa * kappa;
+    bilinear_add(L, U, dX, Y, NULL, c, Jout);
+    bilinear_add(L, U, X, dY, NULL, c, Jout);
+    bilinear_add(L, U, X, Y, Vm, c, Jout);
+    free(Vm); free(dU); free(Ye); free(a); free(b); free(rhs); free(Z); free(dYe);
+    free(X); free(Y); free(dX); free(dY); free(f); free(g);
+    return it;
 }
 
 /* Hasenbusch mass preconditioning: S_F = S_1 + S_2 with a heavier kappa2,
@@ -709,26 +828,63 @@ typedef struct {
     double beta, kappa, cg_tol;
     int cg_maxiter;
     int fermions;    /* 0: pure gauge */
-    int fg_exact;    /* G stages: 0 displacement form, 1 exact gauge form */
+    int fg_exact;    /* G stages: 0 displacement form, 1 exact form */
 } oracle_action;
 
 typedef struct {
     long solves, cg_iters, cg_fail;
 } oracle_stats;
 
-/* F = F_G + F_F at U (F_F needs one CG solve) */
-static void total_force(const int L[4], const oracle_action *act, const cplx *U, const cplx *phi,
-                        double *F, oracle_stats *st) {
+static void add_solve(oracle_stats *st, const oracle_action *act, int it) {
+    st->solves++;
+    if (it < 0) { st->cg_fail++; st->cg_iters += act->cg_maxiter; }
+    else st->cg_iters += it;
+}
+
+/* F = F_G + F_F at U (F_F needs one CG solve); the solution X_e is copied to
+ * Xout when given */
+static void total_force_x(const int L[4], const oracle_action *act, const cplx *U, const cplx *phi,
+                          double *F, oracle_stats *st, cplx *Xout) {
     oracle_gauge_force(L, act->beta, U, F);
     if (!act->fermions) return;
     long Vh = lat_volume(L) / 2;
     cplx *X = malloc(sizeof(cplx) * 12 * Vh);
     int it = oracle_cg(L, act->kappa, U, phi, X, act->cg_tol, act->cg_maxiter, NULL);
-    st->solves++;
-    if (it < 0) { st->cg_fail++; st->cg_iters += act->cg_maxiter; }
-    else st->cg_iters += it;
+    add_solve(st, act, it);
     oracle_fermion_force_add(L, act->kappa, U, X, 1.0, F);
+    if (Xout) memcpy(Xout, X, sizeof(cplx) * 12 * Vh);
     free(X);
+}
+
+static void total_force(const int L[4], const oracle_action *act, const cplx *U, const cplx *phi,
+                        double *F, oracle_stats *st) {
+    total_force_x(L, act, U, phi, F, st, NULL);
+}
+
+/* J = J_V[F] = d/dt F(exp(t V) U) at t = 0 for the total force F = F_G + F_F;
+ * X_e = A^-1 phi at U (the fermion part costs one more solve) */
+static void total_force_tangent(const int L[4], const oracle_action *act, const cplx *U, const cplx *Xe,
+                                const double *v, double *J, oracle_stats *st) {
+    oracle_gauge_force_tangent(L, act->beta, U, v, J);
+    if (!act->fermions) return;
+    int it = oracle_fermion_force_tangent_add(L, act->kappa, U, Xe, v, act->cg_tol, act->cg_maxiter, 1.0, J);
+    add_solve(st, act, it);
+}
+
+/* J_V[F] of the total force at U (pure gauge when fermions == 0); stats3 as
+ * in oracle_force (two solves with fermions: X, then d_V X) */
+void oracle_force_tangent(const int L[4], double beta, double kappa, int fermions, double cg_tol,
+                          int cg_maxiter, const cplx *U, const cplx *phi, const double *v, double *J,
+                          long *stats3) {
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 1};
+    oracle_stats st = {0, 0, 0};
+    long V = lat_volume(L), Vh = V / 2;
+    cplx *X = fermions ? malloc(sizeof(cplx) * 12 * Vh) : NULL;
+    double *F = malloc(sizeof(double) * 4 * V * 8);
+    total_force_x(L, &act, U, phi, F, &st, X);
+    total_force_tangent(L, &act, U, X, v, J, &st);
+    if (stats3) { stats3[0] = st.solves; stats3[1] = st.cg_iters; stats3[2] = st.cg_fail; }
+    free(X); free(F);
 }
 
 void oracle_force(const int L[4], double beta, double kappa, int fermions, double cg_tol,
@@ -783,6 +939,7 @@ int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, d
     double *tmp = malloc(sizeof(double) * V);
     double *F = malloc(sizeof(double) * 4 * V * 8), *F2 = malloc(sizeof(double) * 4 * V * 8);
     cplx *Ud = malloc(sizeof(cplx) * 4 * V * 9);
+    cplx *Xg = fermions ? malloc(sizeof(cplx) * 12 * Vh) : NULL;
     double *hf0 = NULL, *hf1 = NULL;
 
     /* start Hamiltonian, per site */
@@ -815,12 +972,13 @@ int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, d
         } else if (K[s] == 'Q') {
             oracle_link_update(L, w * dt, P, U);
         } else if (K[s] == 'G') {
-            total_force(L, &act, U, phi, F, &st);
             if (fg_exact) {
-                oracle_gauge_force_tangent(L, beta, U, F, F2);
+                total_force_x(L, &act, U, phi, F, &st, Xg);
+                total_force_tangent(L, &act, U, Xg, F, F2, &st);
                 for (long k = 0; k < 4 * V * 8; k++)
                     P[k] += w * dt * F[k] + 2.0 * XI[s] * dt * dt * dt * F2[k];
             } else {
+                total_force(L, &act, U, phi, F, &st);
                 memcpy(Ud, U, sizeof(cplx) * 4 * V * 9);
                 oracle_link_update(L, 2.0 * XI[s] / w * dt * dt, F, Ud);
                 total_force(L, &act, Ud, phi, F2, &st);
@@ -847,7 +1005,7 @@ int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, d
     *dH = d;
     if (st.cg_fail) status = -3;
     if (stats3) { stats3[0] = st.solves; stats3[1] = st.cg_iters; stats3[2] = st.cg_fail; }
-    free(K); free(W); free(XI); free(h0); free(h1); free(tmp); free(F); free(F2); free(Ud);
+    free(K); free(W); free(XI); free(h0); free(h1); free(tmp); free(F); free(F2); free(Ud); free(Xg);
     free(phi); free(hf0); free(hf1);
     return status;
 }

@@ -75,6 +75,9 @@ def _declare(L):
     L.oracle_pf_action.restype = _d
     L.oracle_fermion_force_add.argtypes = [_ip, _d, _vp, _vp, _d, _vp]
     L.oracle_force.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _lp]
+    L.oracle_force_tangent.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _vp, _lp]
+    L.oracle_fermion_force_tangent_add.argtypes = [_ip, _d, _vp, _vp, _vp, _d, _i, _d, _vp]
+    L.oracle_fermion_force_tangent_add.restype = _i
     L.oracle_trajectory.argtypes = [_ip, _d, _d, _i, _d, _i, _i, _i, ctypes.c_char_p, _vp, _vp,
                                     _d, _i, _vp, _vp, _vp, _vp, _dp, _lp]
     L.oracle_trajectory.restype = _i
@@ -238,6 +241,31 @@ def force(dims, beta, U, kappa=0.0, phi=None, tol=1e-14, maxiter=10000):
     lib().oracle_force(_dims(dims), beta, kappa, int(ferm), tol, maxiter, _ptr(U),
                        _ptr(phi_a) if ferm else None, _ptr(F), st)
     return F, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2])
+
+
+def force_tangent(dims, beta, U, V, kappa=0.0, phi=None, tol=1e-14, maxiter=10000):
+    """J_V[F] = d/dt F(exp(t V) U) at t = 0 for the total force (gauge, plus the
+    pseudofermion force when phi is given); returns (J, stats)"""
+    U = _c(U, np.complex128)
+    V = _c(V, np.float64)
+    J = np.zeros((4, volume(dims), 8))
+    st = (ctypes.c_long * 3)()
+    ferm = phi is not None
+    phi_a = _c(phi, np.complex128) if ferm else None
+    lib().oracle_force_tangent(_dims(dims), beta, kappa, int(ferm), tol, maxiter, _ptr(U),
+                               _ptr(phi_a) if ferm else None, _ptr(V), _ptr(J), st)
+    return J, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2])
+
+
+def fermion_force_tangent(dims, kappa, U, X, V, tol=1e-14, maxiter=10000):
+    """J_V[F_F] given X = (Mhat^+ Mhat)^-1 phi (one more solve inside)"""
+    U = _c(U, np.complex128)
+    X = _c(X, np.complex128)
+    V = _c(V, np.float64)
+    J = np.zeros((4, volume(dims), 8))
+    lib().oracle_fermion_force_tangent_add(_dims(dims), kappa, _ptr(U), _ptr(X), _ptr(V), tol, maxiter, 1.0,
+                                           _ptr(J))
+    return J
 
 
 def trajectory(dims, beta, stages, tau, nsteps, U, P, kappa=0.0, eta=None, tol=1e-14,

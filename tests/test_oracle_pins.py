@@ -306,6 +306,67 @@ def test_fermion_force_finite_difference(orc, dims):
     assert np.max(np.abs(fd - got)) < 1e-6 * max(1.0, np.max(np.abs(got)))
 
 
+def _comp(M):
+    """components x_a = -2 Tr(T^a M) of an anti-Hermitian traceless M"""
+    return -2.0 * np.einsum("aij,...ji->...a", T, M).real
+
+
+@pytest.mark.parametrize("dims", [L2, (4, 4, 2, 2)])
+def test_fermion_force_tangent_finite_difference(orc, dims):
+    """Section 4 force gradient of the pseudofermion action against the
+    definition d/dt F_F(exp(tV) U): Richardson-extrapolated central
+    differences of the (separately pinned) force, O(h^4) error."""
+    kappa = 0.155
+    U = rand_links(dims, 71)
+    phi = synth.gaussian_noise(synth.rng(72), dims)
+    Vd = synth.rng(73).standard_normal((4, synth.volume(dims), 8))
+    X, _, _ = orc.cg(dims, kappa, U, phi, tol=1e-14)
+    J = orc.fermion_force_tangent(dims, kappa, U, X, Vd)
+
+    def FF(W):
+        Xw, _, _ = orc.cg(dims, kappa, W, phi, tol=1e-15)
+        return orc.fermion_force(dims, kappa, W, Xw)
+
+    def central(h):
+        return (FF(orc.link_update(dims, h, Vd, U)) - FF(orc.link_update(dims, -h, Vd, U))) / (2 * h)
+
+    h = 2e-3
+    fd = (4 * central(h / 2) - central(h)) / 3
+    assert np.max(np.abs(fd - J)) < 1e-9 * np.max(np.abs(J))
+
+
+@pytest.mark.parametrize("fermions", [False, True])
+def test_force_tangent_chart_commutator(orc, fermions):
+    """In the chart exp(tV) U the second derivatives do not commute on one
+    link: <W, J_V[F]> - <V, J_W[F]> = <[W, V], F> for any two directions.
+    The solve-derivative part is symmetric, so this pins the explicit link
+    terms (a dropped or mis-signed one breaks it)."""
+    dims, beta, kappa = (4, 4, 2, 2), 5.6, 0.155
+    U = rand_links(dims, 75)
+    phi = synth.gaussian_noise(synth.rng(76), dims) if fermions else None
+    g = synth.rng(77)
+    Vd, Wd = g.standard_normal((2, 4, synth.volume(dims), 8))
+    JV, st = orc.force_tangent(dims, beta, U, Vd, kappa=kappa, phi=phi)
+    JW, _ = orc.force_tangent(dims, beta, U, Wd, kappa=kappa, phi=phi)
+    F, _ = orc.force(dims, beta, U, kappa, phi)
+    Vm, Wm = alg(Vd), alg(Wd)
+    lhs = np.sum(Wd * JV) - np.sum(Vd * JW)
+    rhs = np.sum(_comp(Wm @ Vm - Vm @ Wm) * F)
+    assert abs(lhs - rhs) < 1e-11 * np.sum(np.abs(Wd * JV))
+    assert st["solves"] == (2 if fermions else 0)
+
+
+def test_force_tangent_total_is_sum(orc):
+    dims, beta, kappa = L2, 5.6, 0.155
+    U = rand_links(dims, 78)
+    phi = synth.gaussian_noise(synth.rng(79), dims)
+    Vd = synth.rng(80).standard_normal((4, synth.volume(dims), 8))
+    J, _ = orc.force_tangent(dims, beta, U, Vd, kappa=kappa, phi=phi)
+    X, _, _ = orc.cg(dims, kappa, U, phi)
+    ref = orc.gauge_force_tangent(dims, beta, U, Vd) + orc.fermion_force_tangent(dims, kappa, U, X, Vd)
+    assert np.max(np.abs(J - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
 def test_total_force_is_sum(orc):
     dims, beta, kappa = L2, 5.6, 0.155
     U = rand_links(dims, 81)

@@ -128,6 +128,37 @@ def test_dt_scaling_fermions(orc):
     assert abs(out["PQPQP"] - 2) < 0.4 and abs(out["FG"] - 4) < 0.4, out
 
 
+def test_fg_exact_fermions_is_fourth_order(orc):
+    """Exact G stage with the Section 4 pseudofermion force gradient: the
+    h^3 kick cancels the dt^2 error only if J_F[F] is the true gradient."""
+    U0, P0, eta = start(L2, synth.SEED_BASE + 5, True)
+    dh = []
+    for n in (8, 16):
+        _, _, d, _, _ = orc.trajectory(L2, 5.6, table("FG"), 1.0, n, U0, P0, kappa=0.155, eta=eta,
+                                       fg_exact=True)
+        dh.append(abs(d))
+    assert abs(np.log2(dh[0] / dh[1]) - 4) < 0.3, dh
+
+
+def test_fg_exact_fermions_reversible_and_same_solve_count(orc):
+    """Section 4/5: the exact force gradient costs one solve (for d_V X) in
+    place of the displaced force's solve, so both G forms count 3n + 1 plus
+    the two solves that measure S_F at the ends (phi given, not eta)."""
+    dims = (4, 4, 2, 2)
+    U0, P0, eta = start(dims, synth.SEED_BASE + 1, True)
+    phi = orc.pf_heatbath(dims, 0.155, U0, eta)
+    args = dict(kappa=0.155, phi=phi, tol=1e-14, fg_exact=True)
+    n = 4
+    U1, P1, dH, st, status = orc.trajectory(dims, 5.6, table("FG"), 1.0, n, U0, P0, **args)
+    assert status == 0 and st["solves"] == 3 * n + 1 + 2
+    _, _, _, st_d, _ = orc.trajectory(dims, 5.6, table("FG"), 1.0, n, U0, P0, **dict(args, fg_exact=False))
+    assert st_d["solves"] == st["solves"]
+    U2, P2, dH2, _, _ = orc.trajectory(dims, 5.6, table("FG"), 1.0, n, U1, -P1, **args)
+    assert np.max(np.abs(U2 - U0)) < 1e-11
+    assert np.max(np.abs(-P2 - P0)) < 1e-11 * np.max(np.abs(P0))
+    assert abs(dH + dH2) < 1e-9
+
+
 @pytest.mark.parametrize("name,solves", [("PQP", lambda n: n + 1), ("PQPQP", lambda n: 2 * n + 1),
                                          ("FG", lambda n: 3 * n + 1),
                                          ("CAMPOSTRINI", lambda n: 3 * n)])
