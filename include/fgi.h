@@ -75,8 +75,9 @@ typedef struct {
     int cg_maxiter;     /* CG iteration cap */
     int prec;           /* FGI_FP64 | FGI_MP32 | FGI_MP16 (CG inner precision) */
     int link_recon;     /* 18 or 12: storage of the FP32 sloppy links (FP16 uses 12) */
-    int fg_exact;       /* G stages: 0 = displacement form, 1 = exact gauge force
-                           gradient (pure gauge only) */
+    int fg_exact;       /* G stages: 0 = displacement form, 1 = exact force gradient
+                           (gauge and pseudofermion, Section 4; not with
+                           kappa_hasen, not for batched chains) */
 } fgi_action;
 
 /* One stage of an integrator step (Table 1), coefficients multiply the step h:
@@ -198,6 +199,20 @@ int fgi_gauge_hvp(fgi_ctx* ctx, const fgi_geom* g, double beta, const void* U, c
  * (even field; NULL or act->kappa == 0 for pure gauge).  One CG solve. */
 int fgi_force(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* phi, void* F,
               fgi_stats* st, void* stream);
+/* J = J_V[F] = d/dt F(exp(t V) U) at t = 0 for the total force F = F_G + F_F
+ * of fgi_force (pure gauge when phi is NULL or act->kappa == 0), V a field of
+ * su(3) components in the momentum layout; V == NULL takes V = F(U), which
+ * gives the Section 4 force gradient G = J_F[F] itself.  The pseudofermion
+ * part follows Section 4's Leibniz rule: with X = A^-1 phi, A = Mhat^+ Mhat,
+ * one more CG solve gives d_V X = -A^-1 (d_V A) X, then
+ *   J_F = kappa^2 bc TA(U [C(dX, Y) + C(X, dY)] + V U C(X, Y))
+ * over the full-lattice force vectors.  Two solves (one for X, one for d_V X),
+ * counted in *st (may be NULL), both in act->prec to act->cg_tol.  FGI_EINVAL
+ * with act->kappa_hasen != 0 (the Hasenbusch terms have no exact gradient
+ * here); FGI_ENOCONV when a solve hits cg_maxiter (J is still written).
+ * Synchronises the stream. */
+int fgi_total_force_gradient(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U,
+                             const void* phi, const void* V, void* J, fgi_stats* st, void* stream);
 /* F = F_F(X): the pseudofermion force of Section 4, e_a S = -X^+ e_a(A) X
  * for A = Mhat^+ Mhat, given the solution X = A^-1 phi (even field). */
 int fgi_fermion_force(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* X,

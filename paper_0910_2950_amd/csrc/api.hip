@@ -193,6 +193,26 @@ struct Fields {
         }
     }
 
+    // J = J_V[F_terms](u) = d/dt F_terms(exp(t V) u) at t = 0: the gauge part
+    // analytic, the pseudofermion part by the Section 4 Leibniz rule with one
+    // more solve (for d_V X).  X must hold the S_F solve at u.
+    void force_tangent(const d2* u, const void* us, int terms, const double* Vd, double* J) {
+        const bool ferm = act.kappa != 0.0 && (terms & (FGI_TERM_FERMION | FGI_TERM_HASEN));
+        if (ferm && act.kappa_hasen != 0.0)
+            throw Error(FGI_EINVAL, "the exact force gradient is not available for the Hasenbusch terms");
+        if (terms & FGI_TERM_GAUGE) gauge_force_tangent(c, g, act.beta, u, Vd, J, 1.0, 0);
+        else zero_mom(J);
+        if (!ferm) return;
+        d2* W = (d2*)c.gauge_tan.get(gauge_bytes(g));
+        tangent_links(c, g, Vd, u, W);
+        const FermionOp o64 = op64(u, act.kappa), oW = op64(W, act.kappa);
+        d2* rhs = (d2*)c.tg_rhs.get(spinor_bytes(g));
+        d2* Z = (d2*)c.tg_z.get(spinor_bytes(g));
+        fermion_tangent_rhs(c, o64, oW, X, rhs);
+        solve(u, us, act.kappa, rhs, Z);
+        fermion_force_tangent(c, o64, oW, Vd, X, Z, J, 1.0);
+    }
+
     // chi = Mhat2^+ phi2 at u; X2 = (Mhat^+ Mhat)^-1 chi
     void hasen_solve(const d2* u, const void* us) {
         d2* t = (d2*)c.tmp_o.get(spinor_bytes(g));
@@ -266,7 +286,9 @@ int fgi_destroy(fgi_ctx* ctx) {
                           &c.scratch_mom, &c.eta, &c.phi, &c.X, &c.Xo, &c.Ye, &c.Yo, &c.tmp_e, &c.tmp_o,
                           &c.cg_r, &c.cg_p, &c.cg_q, &c.s_x, &c.s_r, &c.s_p, &c.s_q, &c.s_t, &c.s_norms,
                           &c.h0, &c.hf0, &c.partial, &c.scal, &c.state, &c.phi2, &c.eta2, &c.user_tmp,
-                          &c.chi, &c.X2, &c.cdesc, &c.bstate, &c.bscal, &c.bh0, &c.bh1, &c.bres};
+                          &c.chi, &c.X2, &c.cdesc, &c.bstate, &c.bscal, &c.bh0, &c.bh1, &c.bres,
+                          &c.gauge_tan, &c.tg_dmx, &c.tg_rhs, &c.tg_z, &c.tg_dxo, &c.tg_dye, &c.tg_dyo,
+                          &c.force3};
         for (DevBuf* b : bufs) b->release();
         for (hipEvent_t e : c.ev_pool) hipEventDestroy(e);
         for (GraphEntry& e : c.graphs) hipGraphExecDestroy(e.exec);
@@ -626,6 +648,51 @@ int fgi_force(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const voi
     });
 }
 
+int fgi_total_force_gradient(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U,
+                             const void* phi, const void* Vd, void* J, fgi_stats* st, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        check_action(act);
+        if (act->kappa_hasen != 0) throw Error(FGI_EINVAL, "no exact force gradient for the Hasenbusch terms");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(J, "J", 8);
+        if (Vd) need(Vd, "V", 8);
+        const bool ferm = act->kappa != 0 && phi;
+        if (ferm) need(phi, "phi", 16);
+        StreamScope ss(c, stream);
+        fgi_action a = *act;
+        if (!ferm) a.kappa = 0;
+        Fields f(c, g, a);
+        f.st = st;
+        f.U = (d2*)c.gauge.get(gauge_bytes(g));
+        pack_gauge(c, g, U, f.U);
+        if (ferm && f.sp != P64) {
+            f.Us = c.sloppy.get(sloppy_bytes(g));
+            make_sloppy(c, g, f.U, f.Us, f.sp, f.rc);
+        }
+        if (ferm) {
+            f.phi[0] = (d2*)c.phi.get(spinor_bytes(g));
+            pack_even_spinor(c, g, phi, f.phi[0]);
+            f.X = (d2*)c.X.get(spinor_bytes(g));
+        }
+        const int terms = FGI_TERM_GAUGE | FGI_TERM_FERMION;
+        double* fm = (double*)c.force.get(mom_bytes(g));
+        double* v = fm;
+        f.force(f.U, f.Us, terms, fm, 1.0, false);   // F(U), and X at U
+        if (Vd) {
+            v = (double*)c.force2.get(mom_bytes(g));
+            pack_mom(c, g, (const double*)Vd, v);
+        }
+        double* jm = (double*)c.force3.get(mom_bytes(g));
+        f.force_tangent(f.U, f.Us, terms, v, jm);
+        unpack_mom(c, g, jm, (double*)J);
+        FGI_HIP(hipStreamSynchronize(c.stream));
+        if (f.nonconv) throw Error(FGI_ENOCONV, "CG reached cg_maxiter");
+    });
+}
+
 int fgi_fermion_force(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* X,
                       void* F, void* stream) {
     return guarded([&] {
@@ -904,11 +971,13 @@ struct Driver {
     void fg_stage(int l, double w, double xi, double h) {
         int terms = I.lev[l].terms;
         if (f.act.fg_exact) {
-            if (f.act.kappa != 0.0 && (terms & (FGI_TERM_FERMION | FGI_TERM_HASEN)))
-                throw Error(FGI_EINVAL, "exact force gradient is available for the gauge action only");
+            // p += w h F + 2 xi h^3 J_F[F]: F, then its derivative along itself
+            // (one solve each for the pseudofermion force)
+            double* J = (double*)f.c.force3.get(mom_bytes(f.g));
             f.force(f.U, f.Us, terms, f.F, 1.0, false);
+            f.force_tangent(f.U, f.Us, terms, f.F, J);
             mom_axpy(f.c, f.g, w * h, f.F, f.P);
-            gauge_force_tangent(f.c, f.g, f.act.beta, f.U, f.F, f.P, 2.0 * xi * h * h * h, 1);
+            mom_axpy(f.c, f.g, 2.0 * xi * h * h * h, J, f.P);
             return;
         }
         f.force(f.U, f.Us, terms, f.F, 1.0, false);
@@ -927,6 +996,8 @@ extern "C" int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action
         if (!gg || !dH) throw Error(FGI_EINVAL, "null argument");
         check_action(act);
         check_integrator(integ);
+        if (act->fg_exact && act->kappa_hasen != 0)
+            throw Error(FGI_EINVAL, "the exact force gradient is not available for the Hasenbusch terms");
         if (nsteps < 1) throw Error(FGI_EINVAL, "nsteps must be >= 1");
         if (!std::isfinite(tau)) throw Error(FGI_EINVAL, "tau must be finite");
         Geom g = make_geom(gg->dims);

@@ -470,18 +470,19 @@ __global__ void k_pf_density(int Vh, const d2* __restrict__ phi, const d2* __res
 //   C = sum_k h-_k(X(x+mu)) h-_k(Y(x))^+ + h+_k(Y(x+mu)) h+_k(X(x))^+,
 // h-/h+ the two independent spin components of (1 -/+ g_mu) (colour vectors),
 // bc = -1 on the time boundary link.
+// C(A, B) of the link (mu, x) for full-lattice vectors A, B (parity p site s,
+// its forward neighbour sn of the other parity)
 template <int MU>
-__device__ __forceinline__ void ff_link(const Geom& g, int p, int s, const Coord& c, const d2* U,
-                                        const SpinorPtr X[2], const SpinorPtr Y[2], double coef, double* F) {
-    int sn = cb_neighbour(g, c, MU, +1);
+__device__ __forceinline__ M3<double> outer_c(const Geom& g, int p, int s, int sn, const SpinorPtr A[2],
+                                              const SpinorPtr B[2]) {
     cx<double> a[4][3], h1[2][3], h2[2][3], h3[2][3], h4[2][3];
-    SpinorIO<P64, double>::load(X[1 - p], sn, g.Vh, a);
+    SpinorIO<P64, double>::load(A[1 - p], sn, g.Vh, a);
     spin_proj<MU, -1>(a, h1);
-    SpinorIO<P64, double>::load(Y[p], s, g.Vh, a);
+    SpinorIO<P64, double>::load(B[p], s, g.Vh, a);
     spin_proj<MU, -1>(a, h2);
-    SpinorIO<P64, double>::load(Y[1 - p], sn, g.Vh, a);
+    SpinorIO<P64, double>::load(B[1 - p], sn, g.Vh, a);
     spin_proj<MU, +1>(a, h3);
-    SpinorIO<P64, double>::load(X[p], s, g.Vh, a);
+    SpinorIO<P64, double>::load(A[p], s, g.Vh, a);
     spin_proj<MU, +1>(a, h4);
     M3<double> C;
 #pragma unroll
@@ -490,13 +491,26 @@ __device__ __forceinline__ void ff_link(const Geom& g, int p, int s, const Coord
         for (int j = 0; j < 3; j++)
             C.e[i][j] = mulc(h1[0][i], h2[0][j]) + mulc(h1[1][i], h2[1][j]) + mulc(h3[0][i], h4[0][j]) +
                         mulc(h3[1][i], h4[1][j]);
-    M3<double> W = m3_mul(gauge_load(U, MU, p, s, g.Vh), C);
+    return C;
+}
+
+template <int MU>
+__device__ __forceinline__ void ff_add(const Geom& g, int p, int s, const Coord& c, const M3<double>& W, double coef,
+                                       double* F) {
     double x[8];
     ta_components(W, x);
     double f = coef * ((MU == 3 && c.c[3] == g.L[3] - 1) ? -1.0 : 1.0);
     double* o = F + (size_t)((MU * 2 + p) * 8) * g.Vh + s;
 #pragma unroll
     for (int k = 0; k < 8; k++) o[(size_t)k * g.Vh] += f * x[k];
+}
+
+template <int MU>
+__device__ __forceinline__ void ff_link(const Geom& g, int p, int s, const Coord& c, const d2* U,
+                                        const SpinorPtr X[2], const SpinorPtr Y[2], double coef, double* F) {
+    int sn = cb_neighbour(g, c, MU, +1);
+    M3<double> C = outer_c<MU>(g, p, s, sn, X, Y);
+    ff_add<MU>(g, p, s, c, m3_mul(gauge_load(U, MU, p, s, g.Vh), C), coef, F);
 }
 
 __global__ void __launch_bounds__(256) k_fermion_force(Geom g, const d2* __restrict__ U, SpinorPtr Xe, SpinorPtr Xo,
@@ -510,6 +524,62 @@ __global__ void __launch_bounds__(256) k_fermion_force(Geom g, const d2* __restr
     ff_link<1>(g, p, s, c, U, X, Y, coef, F);
     ff_link<2>(g, p, s, c, U, X, Y, coef, F);
     ff_link<3>(g, p, s, c, U, X, Y, coef, F);
+}
+
+// Derivative along V of the force kappa^2 bc TA(U C(X, Y)) (Section 4's
+// Leibniz rule on the force): the vectors move to dX, dY and the link U to
+// V U, so per link
+//   J += coef bc TA( U [C(dX, Y) + C(X, dY)] + V U C(X, Y) ).
+template <int MU>
+__device__ __forceinline__ void ff_tangent_link(const Geom& g, int p, int s, const Coord& c, const d2* U,
+                                                const double* Vd, const SpinorPtr X[2], const SpinorPtr Y[2],
+                                                const SpinorPtr dX[2], const SpinorPtr dY[2], double coef,
+                                                double* J) {
+    int sn = cb_neighbour(g, c, MU, +1);
+    M3<double> C1 = outer_c<MU>(g, p, s, sn, dX, Y);
+    M3<double> C2 = outer_c<MU>(g, p, s, sn, X, dY);
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) C1.e[i][j] = C1.e[i][j] + C2.e[i][j];
+    M3<double> u = gauge_load(U, MU, p, s, g.Vh);
+    double v[8];
+    mom_load(Vd, MU, p, s, g.Vh, v);
+    M3<double> W0 = m3_mul(alg_matrix(v), m3_mul(u, outer_c<MU>(g, p, s, sn, X, Y)));
+    M3<double> W = m3_mul(u, C1);
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) W.e[i][j] = W.e[i][j] + W0.e[i][j];
+    ff_add<MU>(g, p, s, c, W, coef, J);
+}
+
+__global__ void __launch_bounds__(256) k_fermion_force_tangent(Geom g, const d2* __restrict__ U,
+                                                              const double* __restrict__ Vd, SpinorPtr Xe,
+                                                              SpinorPtr Xo, SpinorPtr Ye, SpinorPtr Yo, SpinorPtr dXe,
+                                                              SpinorPtr dXo, SpinorPtr dYe, SpinorPtr dYo, double coef,
+                                                              double* __restrict__ J) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.V) return;
+    int p = t / g.Vh, s = t % g.Vh;
+    Coord c = cb_coords(g, p, s);
+    SpinorPtr X[2] = {Xe, Xo}, Y[2] = {Ye, Yo}, dX[2] = {dXe, dXo}, dY[2] = {dYe, dYo};
+    ff_tangent_link<0>(g, p, s, c, U, Vd, X, Y, dX, dY, coef, J);
+    ff_tangent_link<1>(g, p, s, c, U, Vd, X, Y, dX, dY, coef, J);
+    ff_tangent_link<2>(g, p, s, c, U, Vd, X, Y, dX, dY, coef, J);
+    ff_tangent_link<3>(g, p, s, c, U, Vd, X, Y, dX, dY, coef, J);
+}
+
+// out = a x + b [g5] y on FP64 even/odd vectors (out may alias x or y)
+__global__ void k_sp_lincomb(int Vh, double a, const d2* x, double b, const d2* y, int g5y, d2* out) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= Vh) return;
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const double by = (g5y && k >= 6) ? -b : b;
+        d2 u = x[(size_t)k * Vh + s], v = y[(size_t)k * Vh + s];
+        out[(size_t)k * Vh + s] = d2{a * u.x + by * v.x, a * u.y + by * v.y};
+    }
 }
 
 // ------------------------------------------------- batched small kernels ---
@@ -736,6 +806,79 @@ void fermion_force(Ctx& c, const FermionOp& op64, const d2* Xe, double* F, doubl
     d2* t = (d2*)c.tmp_o.get(n);
     mhat(c, op64, P64, sp(Xe), sp(t), sp(Ye), 0);
     fermion_force_xy(c, op64, Xe, Ye, F, coef * op64.kappa * op64.kappa);
+}
+
+// ------------------------------------------------ force gradient (Section 4) ---
+// J_V[F_F] = d/dt F_F(exp(tV) U) for S = phi^+ A^-1 phi, A = Mhat^+ Mhat.
+// With dD the hopping term on the tangent links V U (opW):
+//   dMhat = -kappa^2 (dD_eo D_oe + D_eo dD_oe),
+//   Z = d_V X_e = -A^-1 (dMhat^+ Y_e + Mhat^+ dMhat X_e),   Y_e = Mhat X_e,
+//   dX = (Z, dD_oe X_e + D_oe Z),
+//   dY = (dMhat X_e + Mhat Z, g5 dD_oe g5 Y_e + g5 D_oe g5 dY_e),
+//   J += coef kappa^2 bc TA(U [C(dX, Y) + C(X, dY)] + V U C(X, Y)).
+namespace {
+void lincomb(Ctx& c, const Geom& g, double a, const d2* x, double b, const d2* y, int g5y, d2* out) {
+    hipLaunchKernelGGL(k_sp_lincomb, dim3(nblk(g.Vh, DBS)), dim3(DBS), 0, c.stream, g.Vh, a, x, b, y, g5y, out);
+    FGI_LAUNCH_CHECK();
+}
+// out_o = [g5] D_oe g5 in_e  (the odd half of the Y vectors)
+void hop_g5(Ctx& c, const FermionOp& op, const d2* in, d2* out, int g5out) {
+    DArgs a = base_args(op, 1);
+    a.in = sp(in);
+    a.out = sp(out);
+    a.g5out = g5out;
+    launch_dslash<M_HOP, P64, P64, P64, P64, 1>(c, op, a);
+}
+}  // namespace
+
+void fermion_tangent_rhs(Ctx& c, const FermionOp& op64, const FermionOp& opW, const d2* Xe, d2* rhs) {
+    const Geom& g = *op64.g;
+    const size_t n = sizeof(d2) * 12 * (size_t)g.Vh;
+    const double k2 = op64.kappa * op64.kappa;
+    d2 *Ye = (d2*)c.Ye.get(n), *Yo = (d2*)c.Yo.get(n), *Xo = (d2*)c.Xo.get(n);
+    d2 *to = (d2*)c.tmp_o.get(n), *te = (d2*)c.tmp_e.get(n);
+    d2 *dmx = (d2*)c.tg_dmx.get(n), *dxo = (d2*)c.tg_dxo.get(n), *dye = (d2*)c.tg_dye.get(n);
+    d2* dyo = (d2*)c.tg_dyo.get(n);
+    mhat(c, op64, P64, sp(Xe), sp(to), sp(Ye), 0);            // Y_e = Mhat X_e
+    dslash(c, op64, 1, P64, sp(Xe), P64, sp(Xo));             // X_o = D_oe X_e
+    hop_g5(c, op64, Ye, Yo, 1);                                // Y_o = g5 D_oe g5 Y_e
+    // dMhat X_e = -kappa^2 (dD_eo X_o + D_eo dD_oe X_e)
+    dslash(c, opW, 1, P64, sp(Xe), P64, sp(dxo));             // dD_oe X_e (first part of dX_o)
+    dslash(c, op64, 0, P64, sp(dxo), P64, sp(te));
+    dslash(c, opW, 0, P64, sp(Xo), P64, sp(dmx));
+    lincomb(c, g, -k2, te, -k2, dmx, 0, dmx);
+    // dMhat^+ Y_e = -kappa^2 g5 (dD_eo D_oe g5 Y_e + D_eo dD_oe g5 Y_e), with D_oe g5 Y_e = g5 Y_o
+    hop_g5(c, opW, Ye, dyo, 0);                                // dD_oe g5 Y_e (g5 of it: first part of dY_o)
+    dslash(c, op64, 0, P64, sp(dyo), P64, sp(dye));            // D_eo dD_oe g5 Y_e
+    {
+        DArgs a = base_args(opW, 0);                           // dD_eo g5 Y_o
+        a.in = sp(Yo);
+        a.out = sp(te);
+        launch_dslash<M_HOP, P64, P64, P64, P64, 1>(c, opW, a);
+    }
+    lincomb(c, g, 1.0, te, 1.0, dye, 0, te);
+    mhat(c, op64, P64, sp(dmx), sp(to), sp(rhs), 1);          // Mhat^+ dMhat X_e
+    lincomb(c, g, -1.0, rhs, k2, te, 1, rhs);                  // -(Mhat^+ dMhat X_e + dMhat^+ Y_e)
+}
+
+void fermion_force_tangent(Ctx& c, const FermionOp& op64, const FermionOp& opW, const double* Vd, const d2* Xe,
+                           const d2* Z, double* J, double coef) {
+    const Geom& g = *op64.g;
+    const size_t n = sizeof(d2) * 12 * (size_t)g.Vh;
+    d2 *Ye = (d2*)c.Ye.get(n), *Yo = (d2*)c.Yo.get(n), *Xo = (d2*)c.Xo.get(n);
+    d2* to = (d2*)c.tmp_o.get(n);
+    d2 *dmx = (d2*)c.tg_dmx.get(n), *dxo = (d2*)c.tg_dxo.get(n), *dye = (d2*)c.tg_dye.get(n);
+    d2* dyo = (d2*)c.tg_dyo.get(n);
+    dslash(c, op64, 1, P64, sp(Z), P64, sp(to));               // dX_o = dD_oe X_e + D_oe Z
+    lincomb(c, g, 1.0, dxo, 1.0, to, 0, dxo);
+    mhat(c, op64, P64, sp(Z), sp(to), sp(dye), 0);             // dY_e = dMhat X_e + Mhat Z
+    lincomb(c, g, 1.0, dye, 1.0, dmx, 0, dye);
+    hop_g5(c, op64, dye, to, 1);                               // dY_o = g5 D_oe g5 dY_e + g5 dD_oe g5 Y_e
+    lincomb(c, g, 1.0, to, 1.0, dyo, 1, dyo);
+    hipLaunchKernelGGL(k_fermion_force_tangent, dim3(nblk(g.V, 256)), dim3(256), 0, c.stream, g,
+                       (const d2*)op64.links, Vd, sp(Xe), sp(Xo), sp(Ye), sp(Yo), sp(Z), sp(dxo), sp(dye), sp(dyo),
+                       coef * op64.kappa * op64.kappa, J);
+    FGI_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------- CG ------

@@ -93,6 +93,8 @@ struct Ctx {
     DevBuf s_x, s_r, s_p, s_q, s_t, s_norms;
     DevBuf h0, hf0, partial, scal, state;
     DevBuf phi2, eta2, user_tmp, chi, X2;
+    // force gradient of the pseudofermion force: tangent links and vectors
+    DevBuf gauge_tan, tg_dmx, tg_rhs, tg_z, tg_dxo, tg_dye, tg_dyo, force3;
     DevBuf cdesc, bstate, bscal, bh0, bh1, bres;  // batched chains
     CGState* host_bstates = nullptr;          // pinned [host_b_cap]
     double* host_bscal = nullptr;             // pinned [host_b_cap]
@@ -167,6 +169,8 @@ void gauge_force_tangent(Ctx&, const Geom&, double beta, const d2* U, const doub
 // dst = exp(h X) src on every link; sloppy copy of dst written when sloppy != null
 void link_update(Ctx&, const Geom&, double h, const double* X, const d2* src, d2* dst, void* sloppy,
                  int prec, int recon);
+// W = V U on every link (FP64 internal layout): the links of the derivative of D along V
+void tangent_links(Ctx&, const Geom&, const double* Vd, const d2* U, d2* W);
 // y += a x over the 4 * 2 * 8 * Vh momentum components
 void mom_axpy(Ctx&, const Geom&, double a, const double* x, double* y);
 void reunitarize(Ctx&, const Geom&, d2* U);
@@ -216,6 +220,13 @@ void pf_heatbath(Ctx&, const FermionOp& op64, const d2* eta, d2* phi);
 void fermion_force(Ctx&, const FermionOp& op64, const d2* Xe, double* F, double c);
 // F += coef * TA(U C(X, Y)), X = (X_e, D_oe X_e), Y = (Y_e, g5 D_oe g5 Y_e)
 void fermion_force_xy(Ctx&, const FermionOp& op64, const d2* Xe, const d2* Ye, double* F, double coef);
+// Force gradient of the pseudofermion force along V (Section 4), in two halves
+// around the one extra solve.  opW is the operator on the tangent links V U.
+//   rhs = -(d_V A) X_e,  A = Mhat^+ Mhat     (also keeps Y_e, X_o, ... for the second half)
+void fermion_tangent_rhs(Ctx&, const FermionOp& op64, const FermionOp& opW, const d2* Xe, d2* rhs);
+//   J += coef * J_V[F_F] given Z = A^-1 rhs (after fermion_tangent_rhs on the same X_e)
+void fermion_force_tangent(Ctx&, const FermionOp& op64, const FermionOp& opW, const double* Vd, const d2* Xe,
+                           const d2* Z, double* J, double coef);
 // partials of Re phi^+ X - |eta|^2 (eta may be null) per even site; returns nblocks
 int pf_density_partials(Ctx&, const Geom&, const d2* phi, const d2* X, const d2* eta, double* partial);
 // for the Hasenbusch pair: out = Mhat(kappa2)^+ in etc. use mhat with another op

@@ -484,6 +484,25 @@ void link_update(Ctx& c, const Geom& g, double h, const double* X, const d2* src
     FGI_LAUNCH_CHECK();
 }
 
+// W_l = V_l U_l: the derivative of exp(t V_l) U_l at t = 0.  The hopping term
+// is linear in each link and its adjoint, and d(U^+) = (V U)^+, so the
+// hopping term on W is the derivative of D along V (Section 4, e_j acting
+// on the fermion kernel).
+__global__ void k_tangent_links(Geom g, const double* __restrict__ Vd, const d2* __restrict__ U,
+                                d2* __restrict__ W) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * g.V) return;
+    int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
+    double x[8];
+    mom_load(Vd, mu, p, s, g.Vh, x);
+    gauge_store(W, mu, p, s, g.Vh, m3_mul(alg_matrix(x), gauge_load(U, mu, p, s, g.Vh)));
+}
+
+void tangent_links(Ctx& c, const Geom& g, const double* Vd, const d2* U, d2* W) {
+    hipLaunchKernelGGL(k_tangent_links, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, Vd, U, W);
+    FGI_LAUNCH_CHECK();
+}
+
 __global__ void k_axpy(long n, double a, const double* __restrict__ x, double* __restrict__ y) {
     long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) y[t] += a * x[t];

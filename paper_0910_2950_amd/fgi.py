@@ -100,6 +100,7 @@ SIGNATURES = {
     "fgi_force_terms": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _i, _vp, _P(fgi_stats), _vp]),
     "fgi_force": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _P(fgi_stats), _vp]),
     "fgi_fermion_force": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _vp]),
+    "fgi_total_force_gradient": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _vp, _P(fgi_stats), _vp]),
     "fgi_dslash": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _i, _i, _vp]),
     "fgi_mhat": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _i, _vp]),
     "fgi_cg_solve": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _P(fgi_stats), _vp]),
@@ -290,6 +291,17 @@ class Context:
                                _ptr(phi, torch.complex128, se, "phi"), _ptr(F, torch.float64, sp, "F"),
                                ctypes.byref(st), _stream()), (FGI_ENOCONV,) if allow_noconv else ())
         return F, st.as_dict()
+
+    def total_force_gradient(self, dims, act, U, phi=None, V=None, J=None, allow_noconv=False):
+        """J = d/dt F(exp(t V) U) at t = 0 for the total force; V None: V = F(U)"""
+        su, sp, se = self._shapes(dims)
+        J = torch.empty(sp, dtype=torch.float64, device=U.device) if J is None else J
+        st = fgi_stats()
+        _check(lib().fgi_total_force_gradient(self.h, _geom(dims), ctypes.byref(act.c()),
+                                              _ptr(U, torch.complex128, su, "U"), _ptr(phi, torch.complex128, se, "phi"),
+                                              _ptr(V, torch.float64, sp, "V"), _ptr(J, torch.float64, sp, "J"),
+                                              ctypes.byref(st), _stream()), (FGI_ENOCONV,) if allow_noconv else ())
+        return J, st.as_dict()
 
     def hasen_heatbath(self, dims, act, U, eta2):
         su, _, se = self._shapes(dims)
