@@ -17,6 +17,7 @@ Prints one JSON line (see the keys below).  --calibrate runs the step-size
 sweep that fixes the matched step counts instead.
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -70,6 +71,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 96-chain batched workload")
     ap.add_argument("--batched-steps", type=int, default=2, help="timed batched trajectories")
     ap.add_argument("--no-hasenbusch", action="store_true", help="skip the 32^3x64 Hasenbusch MD-step leg")
+    ap.add_argument("--exact-steps", type=int, default=2,
+                    help="trajectories of the exact force-gradient form on the first timed inputs (0: skip)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default CG schedule (block 256, XCD order, --cg-batch) instead of tuning per leg")
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle CG iterations timed for the CPU baseline")
@@ -469,6 +472,21 @@ def main():
         (args.prec, args.n_fg, s_per_traj, fg["mean_dH2"], fg["acceptance"], fg["solves_per_traj"],
          fg["cg_iters_per_traj"]))
 
+    # exact G stage (Section 4 force gradient, one solve for d_V X in place of
+    # the displaced force's solve) on the same starts as the first timed
+    # trajectories: its cost and dH beside the displacement form's
+    exact = None
+    if args.exact_steps > 0:
+        k = min(args.exact_steps, args.steps)
+        act_ex = dataclasses.replace(act_fg, fg_exact=True)
+        recs_ex, sec_ex, _ = R.run_leg(U, act_ex, "FG", args.n_fg, inputs[args.warmup:args.warmup + k])
+        exact = summarise(recs_ex)
+        exact.update(n=args.n_fg, s_per_traj=sec_ex / k, trajectories=k,
+                     dH=[r["dH"] for r in recs_ex], dH_displacement_same_start=[r["dH"] for r in recs[:k]])
+        log("FG-%s exact form n=%d: %.4f s/traj solves=%.1f iters=%.0f dH=%s (displacement %s)" %
+            (args.prec, args.n_fg, exact["s_per_traj"], exact["solves_per_traj"], exact["cg_iters_per_traj"],
+             ["%+.3e" % d for d in exact["dH"]], ["%+.3e" % d for d in exact["dH_displacement_same_start"]]))
+
     # FP64 leapfrog leg at its matched step count
     lf = None
     if args.lf_steps > 0:
@@ -533,7 +551,7 @@ def main():
                                     "tau=1, CG tol %.0e" % ("x".join(map(str, R.dims)), args.beta, args.kappa,
                                                             args.therm, args.prec, args.n_fg, args.tol),
                            lattice=list(R.dims), integrator="FG", n_steps=args.n_fg, plaquette=round(plaq, 6)),
-               fg=fg, lf_fp64=lf,
+               fg=fg, fg_exact=exact, lf_fp64=lf,
                speedup_vs_lf_fp64=(round(lf["s_per_traj"] / s_per_traj, 3) if lf else None),
                roofline=roof, roofline_32x32x32x64=large, hasenbusch_32x32x32x64=hasen, batched=batched,
                cpu_baseline=cpu)

@@ -514,8 +514,9 @@ __device__ __forceinline__ void ff_link(const Geom& g, int p, int s, const Coord
 }
 
 __global__ void __launch_bounds__(256) k_fermion_force(Geom g, const d2* __restrict__ U, SpinorPtr Xe, SpinorPtr Xo,
-                                                      SpinorPtr Ye, SpinorPtr Yo, double coef, double* __restrict__ F) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+                                                      SpinorPtr Ye, SpinorPtr Yo, double coef, double* __restrict__ F,
+                                                      int xcd) {
+    int t = slab_thread(g.Vh, 2, xcd);
     if (t >= g.V) return;
     int p = t / g.Vh, s = t % g.Vh;
     Coord c = cb_coords(g, p, s);
@@ -558,8 +559,8 @@ __global__ void __launch_bounds__(256) k_fermion_force_tangent(Geom g, const d2*
                                                               const double* __restrict__ Vd, SpinorPtr Xe,
                                                               SpinorPtr Xo, SpinorPtr Ye, SpinorPtr Yo, SpinorPtr dXe,
                                                               SpinorPtr dXo, SpinorPtr dYe, SpinorPtr dYo, double coef,
-                                                              double* __restrict__ J) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+                                                              double* __restrict__ J, int xcd) {
+    int t = slab_thread(g.Vh, 2, xcd);
     if (t >= g.V) return;
     int p = t / g.Vh, s = t % g.Vh;
     Coord c = cb_coords(g, p, s);
@@ -793,8 +794,8 @@ void fermion_force_xy(Ctx& c, const FermionOp& op64, const d2* Xe, const d2* Ye,
         a.g5out = 1;
         launch_dslash<M_HOP, P64, P64, P64, P64, 1>(c, op64, a);
     }
-    hipLaunchKernelGGL(k_fermion_force, dim3(nblk(g.V, 256)), dim3(256), 0, c.stream, g, (const d2*)op64.links, sp(Xe),
-                       sp(Xo), sp(Ye), sp(Yo), coef, F);
+    hipLaunchKernelGGL(k_fermion_force, dim3(slab_blocks(g.Vh, 2, 256, c.ds_xcd)), dim3(256), 0, c.stream, g,
+                       (const d2*)op64.links, sp(Xe), sp(Xo), sp(Ye), sp(Yo), coef, F, c.ds_xcd);
     FGI_LAUNCH_CHECK();
 }
 
@@ -875,9 +876,9 @@ void fermion_force_tangent(Ctx& c, const FermionOp& op64, const FermionOp& opW, 
     lincomb(c, g, 1.0, dye, 1.0, dmx, 0, dye);
     hop_g5(c, op64, dye, to, 1);                               // dY_o = g5 D_oe g5 dY_e + g5 dD_oe g5 Y_e
     lincomb(c, g, 1.0, to, 1.0, dyo, 1, dyo);
-    hipLaunchKernelGGL(k_fermion_force_tangent, dim3(nblk(g.V, 256)), dim3(256), 0, c.stream, g,
+    hipLaunchKernelGGL(k_fermion_force_tangent, dim3(slab_blocks(g.Vh, 2, 256, c.ds_xcd)), dim3(256), 0, c.stream, g,
                        (const d2*)op64.links, Vd, sp(Xe), sp(Xo), sp(Ye), sp(Yo), sp(Z), sp(dxo), sp(dye), sp(dyo),
-                       coef * op64.kappa * op64.kappa, J);
+                       coef * op64.kappa * op64.kappa, J, c.ds_xcd);
     FGI_LAUNCH_CHECK();
 }
 

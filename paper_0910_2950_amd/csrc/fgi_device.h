@@ -69,6 +69,19 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + (x < r ? x : r) + k;
 }
 
+// Thread index of a launch over nt arrays of Vh sites ([type][s], type =
+// mu * 2 + parity for links, the parity for sites), blocks of blockDim.x.
+// xcd = 0: linear.  xcd = 1: the nt blocks of each group of blockDim.x sites
+// are adjacent and every XCD owns a contiguous range of groups (xcd_block),
+// so the neighbour links and vectors a block reads were mostly fetched into
+// its own XCD's L2 by the blocks beside it.  Past the end: nt * Vh.
+__device__ __forceinline__ int slab_thread(int Vh, int nt, int xcd) {
+    if (!xcd) return blockIdx.x * blockDim.x + threadIdx.x;
+    const int B = xcd_block(blockIdx.x, gridDim.x);
+    const int s = (B / nt) * blockDim.x + threadIdx.x;
+    return s < Vh ? (B % nt) * Vh + s : nt * Vh;
+}
+
 // --------------------------------------------------------------------------
 // batched chains: independent lattices stored one after another in every
 // field; a kernel launched over all of them finds its chain from its block.

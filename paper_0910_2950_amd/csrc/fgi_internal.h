@@ -147,6 +147,11 @@ inline double* partial_buf(Ctx& c, long vol, long nchains = 1) {
 inline double* partial_buf(Ctx& c, const Geom& g) { return partial_buf(c, g.V, 1); }
 inline double* partial_buf(Ctx& c, const Batch& B) { return partial_buf(c, B.vol, B.nc); }
 
+// blocks of `bs` threads for slab_thread over nt arrays of Vh sites
+inline int slab_blocks(long Vh, int nt, int bs, int xcd) {
+    return xcd ? nt * (int)((Vh + bs - 1) / bs) : (int)((nt * Vh + bs - 1) / bs);
+}
+
 // ---------------- gauge.hip ----------------
 void pack_gauge(Ctx&, const Geom&, const void* user, d2* internal);
 void unpack_gauge(Ctx&, const Geom&, const d2* internal, void* user);

@@ -308,8 +308,8 @@ __device__ __forceinline__ void gauge_force_body(const Geom& g, double beta, con
 }
 
 __global__ void __launch_bounds__(256) k_gauge_force(Geom g, double beta, const d2* __restrict__ U,
-                                                    double* __restrict__ F, double coef, int accumulate) {
-    gauge_force_body(g, beta, U, F, coef, accumulate, blockIdx.x * blockDim.x + threadIdx.x);
+                                                    double* __restrict__ F, double coef, int accumulate, int xcd) {
+    gauge_force_body(g, beta, U, F, coef, accumulate, slab_thread(g.Vh, 8, xcd));
 }
 
 __global__ void __launch_bounds__(256) k_gauge_force_b(const ChainDesc* __restrict__ cd, int nc,
@@ -322,7 +322,8 @@ __global__ void __launch_bounds__(256) k_gauge_force_b(const ChainDesc* __restri
 }
 
 void gauge_force(Ctx& c, const Geom& g, double beta, const d2* U, double* F, double coef, int accumulate) {
-    hipLaunchKernelGGL(k_gauge_force, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, beta, U, F, coef, accumulate);
+    hipLaunchKernelGGL(k_gauge_force, dim3(slab_blocks(g.Vh, 8, BS, c.ds_xcd)), dim3(BS), 0, c.stream, g, beta, U, F,
+                       coef, accumulate, c.ds_xcd);
     FGI_LAUNCH_CHECK();
 }
 
@@ -340,8 +341,8 @@ __device__ __forceinline__ M3<double> valg(const double* Vd, int mu, int p, int 
 //         = coef * (-J_V[F_G] + [V, F_G] / 2)   (per link commutator)
 __global__ void __launch_bounds__(256) k_gauge_tangent(Geom g, double beta, const d2* __restrict__ U,
                                                       const double* __restrict__ Vd, double* __restrict__ J,
-                                                      double coef, int accumulate, int mode) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+                                                      double coef, int accumulate, int mode, int xcd) {
+    int t = slab_thread(g.Vh, 8, xcd);
     if (t >= 4 * g.V) return;
     int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
     Coord c = cb_coords(g, p, s);
@@ -421,8 +422,8 @@ __global__ void __launch_bounds__(256) k_gauge_tangent(Geom g, double beta, cons
 
 void gauge_force_tangent(Ctx& c, const Geom& g, double beta, const d2* U, const double* Vd, double* J, double coef,
                          int accumulate, int mode) {
-    hipLaunchKernelGGL(k_gauge_tangent, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, beta, U, Vd, J, coef,
-                       accumulate, mode);
+    hipLaunchKernelGGL(k_gauge_tangent, dim3(slab_blocks(g.Vh, 8, BS, c.ds_xcd)), dim3(BS), 0, c.stream, g, beta, U,
+                       Vd, J, coef, accumulate, mode, c.ds_xcd);
     FGI_LAUNCH_CHECK();
 }
 
