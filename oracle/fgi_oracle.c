@@ -1183,3 +1183,110 @@ void oracle_brackets(const int L[4], double beta, double kappa, int fermions, do
     *TST = (fp - fm) / (2.0 * h);
     free(F); free(Ud);
 }
+
+/* ------------------------------------------------------------------ */
+/* Markov chain: counter-based draws and the HMC accept/reject loop    */
+/* ------------------------------------------------------------------ */
+
+/* Philox4x32-10, from its definition in Salmon, Moraes, Dror and Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3" (SC11, 2011): the state is a
+ * 128-bit counter (four 32-bit words) and a 64-bit key; a round multiplies
+ * words 0 and 2 by 0xD2511F53 and 0xCD9E8D57 into 64-bit products, and the new
+ * words are (hi(w2 M1) ^ w1 ^ k0, lo(w2 M1), hi(w0 M0) ^ w3 ^ k1, lo(w0 M0));
+ * between rounds the key advances by (0x9E3779B9, 0xBB67AE85).  Ten rounds. */
+void oracle_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t w[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; round++) {
+        if (round) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t a = (uint64_t)w[0] * 0xD2511F53u;
+        uint64_t b = (uint64_t)w[2] * 0xCD9E8D57u;
+        uint32_t nw[4];
+        nw[0] = (uint32_t)(b >> 32) ^ w[1] ^ k0;
+        nw[1] = (uint32_t)b;
+        nw[2] = (uint32_t)(a >> 32) ^ w[3] ^ k1;
+        nw[3] = (uint32_t)a;
+        memcpy(w, nw, sizeof w);
+    }
+    memcpy(out, w, sizeof w);
+}
+
+/* uniform in (0, 1): 32 bits of a and the top 20 of b as m, (m + 1/2) 2^-52 */
+static double unif52(uint32_t a, uint32_t b) {
+    uint64_t m = ((uint64_t)a << 20) | (uint64_t)(b >> 12);
+    return ((double)m + 0.5) / 4503599627370496.0;
+}
+
+/* Box-Muller pair of the counter (c0, c1, c2, 0) under the seed's key */
+static void normal_pair(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, double *z0, double *z1) {
+    uint32_t ctr[4] = {c0, c1, c2, 0u}, key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)}, x[4];
+    oracle_philox(ctr, key, x);
+    double r = sqrt(-2.0 * log(unif52(x[0], x[1])));
+    double phase = 6.283185307179586 * unif52(x[2], x[3]);
+    *z0 = r * cos(phase);
+    *z1 = r * sin(phase);
+}
+
+/* The heatbath draws of trajectory traj of the chain `seed` in the user
+ * layouts (any of P, eta1, eta2 may be NULL):
+ *   P[mu][i][2j + b], b = 0, 1 the pair of counter (4 (mu V + i) + j, traj, 0)
+ *   eta[k][e] = (z0 + i z1) / sqrt(2) of counter (12 k + e, traj, 1 | 2)
+ * (e = 3 spin + colour, k the k-th even site). */
+void oracle_refresh(const int L[4], uint64_t seed, uint32_t traj, double *P, cplx *eta1, cplx *eta2) {
+    long V = lat_volume(L), Vh = V / 2;
+    if (P)
+        for (long l = 0; l < 4 * V; l++)
+            for (int j = 0; j < 4; j++)
+                normal_pair(seed, (uint32_t)(4 * l + j), traj, 0u, &P[l * 8 + 2 * j], &P[l * 8 + 2 * j + 1]);
+    cplx *etas[2] = {eta1, eta2};
+    for (int s = 0; s < 2; s++) {
+        if (!etas[s]) continue;
+        for (long k = 0; k < Vh; k++)
+            for (int e = 0; e < 12; e++) {
+                double z0, z1;
+                normal_pair(seed, (uint32_t)(12 * k + e), traj, (uint32_t)(1 + s), &z0, &z1);
+                etas[s][k * 12 + e] = z0 * 0.7071067811865476 + I * (z1 * 0.7071067811865476);
+            }
+    }
+}
+
+/* the Metropolis uniform of trajectory traj: counter (0, traj, 3) */
+double oracle_metropolis_uniform(uint64_t seed, uint32_t traj) {
+    uint32_t ctr[4] = {0u, traj, 3u, 0u}, key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)}, x[4];
+    oracle_philox(ctr, key, x);
+    return unif52(x[0], x[1]);
+}
+
+/* HMC Markov chain: for t = traj0 .. traj0 + ntraj - 1, draw P and eta for
+ * trajectory t, run one trajectory (oracle_trajectory) from the chain's
+ * links, accept when metropolis == 0 or u_t < exp(-dH), then reunitarise the
+ * chain's links.  U is updated in place; dH, acc, plaq (average plaquette
+ * after each trajectory) may be NULL.  Returns 0, or -3 when a solve failed. */
+int oracle_hmc_run(const int L[4], double beta, double kappa, int fermions, double cg_tol, int cg_maxiter,
+                   int fg_exact, int nstages, const char *kinds, const double *ws, const double *xis, double tau,
+                   int nsteps, cplx *U, uint64_t seed, uint32_t traj0, int ntraj, int metropolis, double *dH,
+                   int *acc, double *plaq) {
+    long V = lat_volume(L), Vh = V / 2;
+    double *P = malloc(sizeof(double) * 4 * V * 8);
+    cplx *Ut = malloc(sizeof(cplx) * 4 * V * 9);
+    cplx *eta = fermions ? malloc(sizeof(cplx) * 12 * Vh) : NULL;
+    int status = 0;
+    for (int k = 0; k < ntraj; k++) {
+        uint32_t t = traj0 + (uint32_t)k;
+        oracle_refresh(L, seed, t, P, eta, NULL);
+        memcpy(Ut, U, sizeof(cplx) * 4 * V * 9);
+        double d = 0.0;
+        long st3[3];
+        int rc = oracle_trajectory(L, beta, kappa, fermions, cg_tol, cg_maxiter, fg_exact, nstages, kinds, ws, xis,
+                                   tau, nsteps, Ut, P, eta, NULL, &d, st3);
+        if (rc) status = rc;
+        int a = !metropolis || oracle_metropolis_uniform(seed, t) < exp(-d);
+        if (a) memcpy(U, Ut, sizeof(cplx) * 4 * V * 9);
+        oracle_reunitarize(L, U);
+        if (dH) dH[k] = d;
+        if (acc) acc[k] = a;
+        if (plaq) plaq[k] = oracle_plaquette(L, U);
+    }
+    free(P); free(Ut); free(eta);
+    return status;
+}

@@ -90,6 +90,13 @@ def _declare(L):
     L.oracle_trajectory_nested.argtypes = [_ip, _d, _d, _d, _d, _i, _i, _vp, _vp, _vp, ctypes.c_char_p, _vp, _vp,
                                            _d, _i, _vp, _vp, _vp, _vp, _dp, _lp]
     L.oracle_trajectory_nested.restype = _i
+    L.oracle_philox.argtypes = [_vp, _vp, _vp]
+    L.oracle_refresh.argtypes = [_ip, ctypes.c_uint64, ctypes.c_uint32, _vp, _vp, _vp]
+    L.oracle_metropolis_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
+    L.oracle_metropolis_uniform.restype = _d
+    L.oracle_hmc_run.argtypes = [_ip, _d, _d, _i, _d, _i, _i, _i, ctypes.c_char_p, _vp, _vp, _d, _i, _vp,
+                                 ctypes.c_uint64, ctypes.c_uint32, _i, _i, _vp, _vp, _vp]
+    L.oracle_hmc_run.restype = _i
 
 
 def _dims(dims):
@@ -354,6 +361,52 @@ def trajectory_nested(dims, beta, levels, tau, nsteps, U, P, kappa=0.0, kappa2=0
                                             _ptr(U), _ptr(P), _ptr(e1) if e1 is not None else None,
                                             _ptr(e2) if e2 is not None else None, ctypes.byref(dH), st)
     return U, P, dH.value, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2]), status
+
+
+# ---------------------------------------------------------------------------
+# Markov chain: Philox4x32-10 draws and the HMC accept/reject loop
+# ---------------------------------------------------------------------------
+
+def philox(ctr, key):
+    """Philox4x32-10 of one counter (four uint32) under a key (two uint32)."""
+    c = np.array(ctr, dtype=np.uint32)
+    k = np.array(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox(_ptr(c), _ptr(k), _ptr(o))
+    return [int(x) for x in o]
+
+
+def refresh(dims, seed, traj, momenta=True, eta1=True, eta2=False):
+    """(P, eta1, eta2) drawn for trajectory traj of the chain `seed` (None where not asked)."""
+    V = volume(dims)
+    P = np.zeros((4, V, 8)) if momenta else None
+    e1 = np.zeros((V // 2, 4, 3), np.complex128) if eta1 else None
+    e2 = np.zeros((V // 2, 4, 3), np.complex128) if eta2 else None
+    lib().oracle_refresh(_dims(dims), int(seed), int(traj), _ptr(P) if momenta else None,
+                         _ptr(e1) if eta1 else None, _ptr(e2) if eta2 else None)
+    return P, e1, e2
+
+
+def metropolis_uniform(seed, traj):
+    return lib().oracle_metropolis_uniform(int(seed), int(traj))
+
+
+def hmc_run(dims, beta, stages, tau, nsteps, U, seed, traj0, ntraj, kappa=0.0, fermions=False, tol=1e-14,
+            maxiter=10000, fg_exact=False, metropolis=True):
+    """HMC chain of ntraj trajectories from U; returns (U_final, dH list, accepted list, plaquettes, status)."""
+    U = np.array(U, dtype=np.complex128, copy=True, order="C")
+    kinds = "".join(s[0] for s in stages).encode()
+    ws = np.array([s[1] for s in stages], np.float64)
+    xis = np.array([s[2] if len(s) > 2 else 0.0 for s in stages], np.float64)
+    n = max(int(ntraj), 1)
+    dH = np.zeros(n)
+    acc = np.zeros(n, np.int32)
+    plaq = np.zeros(n)
+    status = lib().oracle_hmc_run(_dims(dims), beta, kappa, int(bool(fermions)), tol, maxiter, int(bool(fg_exact)),
+                                  len(stages), kinds, _ptr(ws), _ptr(xis), tau, nsteps, _ptr(U), int(seed),
+                                  int(traj0), int(ntraj), int(bool(metropolis)), _ptr(dH), _ptr(acc), _ptr(plaq))
+    k = int(ntraj)
+    return U, list(dH[:k]), [bool(a) for a in acc[:k]], list(plaq[:k]), status
 
 
 # ---------------------------------------------------------------------------
