@@ -46,6 +46,8 @@
 #ifndef FGI_H
 #define FGI_H
 
+#include <stdint.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -276,6 +278,37 @@ int fgi_integrator_builtin(int which, double alpha, fgi_integrator* out);
 int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const fgi_integrator* integ, double tau,
                    int nsteps, void* U, void* P, const void* eta1, const void* eta2, int pf_is_phi, double* dH,
                    fgi_stats* st, void* stream);
+
+/* ------------------------------------------- Markov chain (HMC, Section 2) */
+/* The heatbath draws of trajectory `traj` of the chain with this seed, from
+ * the counter-based generator Philox4x32-10 (Salmon, Moraes, Dror and Shaw,
+ * SC11, 2011; key = the seed's low and high 32-bit words):
+ *   P    (momentum layout, may be NULL): p_a ~ N(0, 1), component 2j + b of
+ *        link l = mu V + i from counter (4 l + j, traj, 0, 0), b = 0, 1 the
+ *        Box-Muller pair;
+ *   eta1, eta2 (even layout, may be NULL): Re, Im ~ N(0, 1/2), spin-colour
+ *        component e of even site k from counter (12 k + e, traj, 1 | 2, 0).
+ * A counter's four words give two uniforms (m + 1/2) 2^-52 (m from words 0,1
+ * and 2,3: 32 + 20 bits) and z0, z1 = sqrt(-2 ln u1) (cos, sin)(2 pi u2).
+ * traj < 2^32.  Synchronises the stream. */
+int fgi_refresh(fgi_ctx* ctx, const fgi_geom* g, uint64_t seed, uint64_t traj, void* P, void* eta1, void* eta2,
+                void* stream);
+/* Philox4x32-10 of one counter (host; the library's generator, for tests). */
+int fgi_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out);
+/* ntraj HMC trajectories of a Markov chain on U (user layout, updated in
+ * place), entirely on the device: trajectory t = traj0 + k draws its momenta
+ * and noise with fgi_refresh(seed, t), runs one fgi_trajectory from the
+ * chain's links, and is accepted when metropolis == 0 or u < exp(-dH) with
+ * u the uniform of counter (0, t, 3, 0); the links are reunitarised after
+ * every trajectory.  dH[k], accepted[k] and the average plaquette
+ * plaq[k] = ReTr U_P / 3 of the chain after trajectory k (each may be NULL)
+ * are written for k < ntraj.  The chain's state is U and the next index, so
+ * a run of n then m trajectories gives the same bits as one run of n + m.
+ * traj0 + ntraj <= 2^32.  FGI_ENOCONV (after the last trajectory) when a solve
+ * hit cg_maxiter, FGI_ENONFINITE on a non-finite dH.  Synchronises the stream. */
+int fgi_hmc_run(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const fgi_integrator* integ, double tau,
+                int nsteps, void* U, uint64_t seed, uint64_t traj0, int ntraj, int metropolis, double* dH,
+                int* accepted, double* plaq, fgi_stats* st, void* stream);
 
 /* ------------------------------------------------ batched chains
  * Many independent chains of different lattice sizes and couplings advanced

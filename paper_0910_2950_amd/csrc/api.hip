@@ -9,6 +9,7 @@
 
 #include "../../include/fgi.h"
 #include "fgi_internal.h"
+#include "rng.h"
 
 struct fgi_ctx {
     fgi::Ctx c;
@@ -288,7 +289,7 @@ int fgi_destroy(fgi_ctx* ctx) {
                           &c.h0, &c.hf0, &c.partial, &c.scal, &c.state, &c.phi2, &c.eta2, &c.user_tmp,
                           &c.chi, &c.X2, &c.cdesc, &c.bstate, &c.bscal, &c.bh0, &c.bh1, &c.bres,
                           &c.gauge_tan, &c.tg_dmx, &c.tg_rhs, &c.tg_z, &c.tg_dxo, &c.tg_dye, &c.tg_dyo,
-                          &c.force3};
+                          &c.force3, &c.chain_U};
         for (DevBuf* b : bufs) b->release();
         for (hipEvent_t e : c.ev_pool) hipEventDestroy(e);
         for (GraphEntry& e : c.graphs) hipGraphExecDestroy(e.exec);
@@ -988,18 +989,83 @@ struct Driver {
 
 }  // namespace
 
+namespace {
+
+void check_trajectory_args(const fgi_action* act, const fgi_integrator* integ, int nsteps, double tau) {
+    check_action(act);
+    check_integrator(integ);
+    if (act->fg_exact && act->kappa_hasen != 0)
+        throw Error(FGI_EINVAL, "the exact force gradient is not available for the Hasenbusch terms");
+    if (nsteps < 1) throw Error(FGI_EINVAL, "nsteps must be >= 1");
+    if (!std::isfinite(tau)) throw Error(FGI_EINVAL, "tau must be finite");
+}
+
+// Scratch of one trajectory in the internal layouts (links f.U are set by the caller)
+void trajectory_buffers(Ctx& c, const Geom& g, Fields& f) {
+    const bool ferm = f.act.kappa != 0.0, hasen = f.act.kappa_hasen != 0.0;
+    f.Ud = (d2*)c.gauge_disp.get(gauge_bytes(g));
+    f.P = (double*)c.mom.get(mom_bytes(g));
+    f.F = (double*)c.force.get(mom_bytes(g));
+    if (ferm && f.sp != P64) {
+        f.Us = c.sloppy.get(sloppy_bytes(g));
+        f.Uds = c.sloppy_disp.get(sloppy_bytes(g));
+    }
+    if (ferm) {
+        f.phi[0] = (d2*)c.phi.get(spinor_bytes(g));
+        f.X = (d2*)c.X.get(spinor_bytes(g));
+        if (hasen) {
+            f.phi[1] = (d2*)c.phi2.get(spinor_bytes(g));
+            f.X2 = (d2*)c.X2.get(spinor_bytes(g));
+            f.chi = (d2*)c.chi.get(spinor_bytes(g));
+        }
+    }
+}
+
+// One trajectory on packed fields: f.U and f.P hold the start, and for
+// fermions either the noise (eta, eta_2: pseudofermions by heatbath) or, with
+// phi_given, the pseudofermions themselves in f.phi.  f.U, f.P end as the
+// final fields; returns dH (per-site differences of the gauge and kinetic
+// densities plus the pseudofermion energies).
+double trajectory_packed(Fields& f, const fgi_integrator& integ, double tau, int nsteps, const d2* eta,
+                         const d2* eta_2, bool phi_given) {
+    Ctx& c = f.c;
+    const Geom& g = f.g;
+    const bool ferm = f.act.kappa != 0.0, hasen = f.act.kappa_hasen != 0.0;
+    if (ferm && f.sp != P64) make_sloppy(c, g, f.U, f.Us, f.sp, f.rc);
+    double* h0 = (double*)c.h0.get(sizeof(double) * g.V);
+    double* h1 = (double*)c.hf0.get(sizeof(double) * g.V);
+    double* part = partial_buf(c, g);
+    double* scal = (double*)c.scal.get(sizeof(double) * 64);
+    double sf0 = 0.0;
+    if (ferm) {
+        const double k1 = hasen ? f.act.kappa_hasen : f.act.kappa;
+        if (phi_given) {
+            sf0 = f.pf_energy(f.U, f.Us, nullptr, nullptr, part, scal);
+        } else {
+            pf_heatbath(c, f.op64(f.U, k1), eta, f.phi[0]);
+            if (hasen) f.hasen_heatbath(f.U, f.Us, eta_2);
+        }
+    }
+    ham_density(c, g, f.act.beta, f.U, f.P, h0);
+    Driver d(f, integ);
+    d.run(0, nsteps, tau / nsteps);
+    ham_density(c, g, f.act.beta, f.U, f.P, h1);
+    int nb = diff_partials(c, g.V, h1, h0, part);
+    final_sum(c, part, nb, scal);
+    double dh = sync_scalar(c, scal, 0);
+    if (ferm) dh += f.pf_energy(f.U, f.Us, phi_given ? nullptr : eta, phi_given ? nullptr : eta_2, part, scal) - sf0;
+    return dh;
+}
+
+}  // namespace
+
 extern "C" int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const fgi_integrator* integ,
                               double tau, int nsteps, void* U, void* P, const void* eta1, const void* eta2,
                               int pf_is_phi, double* dH, fgi_stats* st, void* stream) {
     return guarded([&] {
         Ctx& c = ctx_of(ctx);
         if (!gg || !dH) throw Error(FGI_EINVAL, "null argument");
-        check_action(act);
-        check_integrator(integ);
-        if (act->fg_exact && act->kappa_hasen != 0)
-            throw Error(FGI_EINVAL, "the exact force gradient is not available for the Hasenbusch terms");
-        if (nsteps < 1) throw Error(FGI_EINVAL, "nsteps must be >= 1");
-        if (!std::isfinite(tau)) throw Error(FGI_EINVAL, "tau must be finite");
+        check_trajectory_args(act, integ, nsteps, tau);
         Geom g = make_geom(gg->dims);
         need(U, "U", 16);
         need(P, "P", 8);
@@ -1012,56 +1078,22 @@ extern "C" int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action
         Fields f(c, g, *act);
         f.st = st;
         f.U = (d2*)c.gauge.get(gauge_bytes(g));
-        f.Ud = (d2*)c.gauge_disp.get(gauge_bytes(g));
-        f.P = (double*)c.mom.get(mom_bytes(g));
-        f.F = (double*)c.force.get(mom_bytes(g));
+        trajectory_buffers(c, g, f);
         pack_gauge(c, g, U, f.U);
         pack_mom(c, g, (const double*)P, f.P);
-        if (ferm && f.sp != P64) {
-            f.Us = c.sloppy.get(sloppy_bytes(g));
-            f.Uds = c.sloppy_disp.get(sloppy_bytes(g));
-            make_sloppy(c, g, f.U, f.Us, f.sp, f.rc);
-        }
-        double* h0 = (double*)c.h0.get(sizeof(double) * g.V);
-        double* h1 = (double*)c.hf0.get(sizeof(double) * g.V);
-        double* part = partial_buf(c, g);
-        double* scal = (double*)c.scal.get(sizeof(double) * 64);
         d2 *eta = nullptr, *eta_2 = nullptr;
-        double sf0 = 0.0;
-        if (ferm) {
-            f.phi[0] = (d2*)c.phi.get(spinor_bytes(g));
-            f.X = (d2*)c.X.get(spinor_bytes(g));
+        if (ferm && pf_is_phi) {
+            pack_even_spinor(c, g, eta1, f.phi[0]);
+            if (hasen) pack_even_spinor(c, g, eta2, f.phi[1]);
+        } else if (ferm) {
+            eta = (d2*)c.eta.get(spinor_bytes(g));
+            pack_even_spinor(c, g, eta1, eta);
             if (hasen) {
-                f.phi[1] = (d2*)c.phi2.get(spinor_bytes(g));
-                f.X2 = (d2*)c.X2.get(spinor_bytes(g));
-                f.chi = (d2*)c.chi.get(spinor_bytes(g));
-            }
-            const double k1 = hasen ? act->kappa_hasen : act->kappa;
-            if (pf_is_phi) {
-                pack_even_spinor(c, g, eta1, f.phi[0]);
-                if (hasen) pack_even_spinor(c, g, eta2, f.phi[1]);
-                sf0 = f.pf_energy(f.U, f.Us, nullptr, nullptr, part, scal);
-            } else {
-                eta = (d2*)c.eta.get(spinor_bytes(g));
-                pack_even_spinor(c, g, eta1, eta);
-                pf_heatbath(c, f.op64(f.U, k1), eta, f.phi[0]);
-                if (hasen) {
-                    eta_2 = (d2*)c.eta2.get(spinor_bytes(g));
-                    pack_even_spinor(c, g, eta2, eta_2);
-                    f.hasen_heatbath(f.U, f.Us, eta_2);
-                }
+                eta_2 = (d2*)c.eta2.get(spinor_bytes(g));
+                pack_even_spinor(c, g, eta2, eta_2);
             }
         }
-        ham_density(c, g, act->beta, f.U, f.P, h0);
-
-        Driver d(f, *integ);
-        d.run(0, nsteps, tau / nsteps);
-
-        ham_density(c, g, act->beta, f.U, f.P, h1);
-        int nb = diff_partials(c, g.V, h1, h0, part);
-        final_sum(c, part, nb, scal);
-        double dh = sync_scalar(c, scal, 0);
-        if (ferm) dh += f.pf_energy(f.U, f.Us, eta, eta_2, part, scal) - sf0;
+        const double dh = trajectory_packed(f, *integ, tau, nsteps, eta, eta_2, pf_is_phi != 0);
         unpack_gauge(c, g, f.U, U);
         unpack_mom(c, g, f.P, (double*)P);
         FGI_HIP(hipStreamSynchronize(c.stream));
@@ -1069,6 +1101,94 @@ extern "C" int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action
         if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (!std::isfinite(dh)) throw Error(FGI_ENONFINITE, "dH is not finite");
         if (f.nonconv) throw Error(FGI_ENOCONV, "a CG solve reached cg_maxiter");
+    });
+}
+
+extern "C" int fgi_refresh(fgi_ctx* ctx, const fgi_geom* gg, uint64_t seed, uint64_t traj, void* P, void* eta1,
+                           void* eta2, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        if (traj > 0xffffffffull) throw Error(FGI_EINVAL, "trajectory index beyond 2^32 - 1");
+        Geom g = make_geom(gg->dims);
+        StreamScope ss(c, stream);
+        if (P) {
+            need(P, "P", 8);
+            double* pm = (double*)c.mom.get(mom_bytes(g));
+            refresh_momenta(c, g, seed, (uint32_t)traj, pm);
+            unpack_mom(c, g, pm, (double*)P);
+        }
+        void* etas[2] = {eta1, eta2};
+        for (int k = 0; k < 2; k++) {
+            if (!etas[k]) continue;
+            need(etas[k], k ? "eta2" : "eta1", 16);
+            d2* e = (d2*)c.eta.get(spinor_bytes(g));
+            refresh_noise(c, g, seed, (uint32_t)traj, k ? RNG_ETA2 : RNG_ETA1, e);
+            unpack_even_spinor(c, g, e, etas[k]);
+        }
+        FGI_HIP(hipStreamSynchronize(c.stream));
+    });
+}
+
+extern "C" int fgi_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+    return guarded([&] {
+        if (!ctr || !key || !out) throw Error(FGI_EINVAL, "null argument");
+        philox_host(ctr, key, out);
+    });
+}
+
+extern "C" int fgi_hmc_run(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const fgi_integrator* integ,
+                           double tau, int nsteps, void* U, uint64_t seed, uint64_t traj0, int ntraj, int metropolis,
+                           double* dH, int* accepted, double* plaq, fgi_stats* st, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        check_trajectory_args(act, integ, nsteps, tau);
+        if (ntraj < 0) throw Error(FGI_EINVAL, "negative trajectory count");
+        if (traj0 + (uint64_t)ntraj > 0x100000000ull) throw Error(FGI_EINVAL, "trajectory index beyond 2^32 - 1");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        if (ntraj == 0) return;
+        const bool ferm = act->kappa != 0.0, hasen = act->kappa_hasen != 0.0;
+        auto t0 = std::chrono::steady_clock::now();
+        StreamScope ss(c, stream);
+        Fields f(c, g, *act);
+        f.st = st;
+        d2* Ucur = (d2*)c.chain_U.get(gauge_bytes(g));   // the chain's links
+        f.U = (d2*)c.gauge.get(gauge_bytes(g));         // the trial trajectory's links
+        trajectory_buffers(c, g, f);
+        d2* eta = ferm ? (d2*)c.eta.get(spinor_bytes(g)) : nullptr;
+        d2* eta_2 = hasen ? (d2*)c.eta2.get(spinor_bytes(g)) : nullptr;
+        double* scal = (double*)c.scal.get(sizeof(double) * 64);
+        double* part = partial_buf(c, g);
+        pack_gauge(c, g, U, Ucur);
+        bool nonconv = false;
+        for (int k = 0; k < ntraj; k++) {
+            const uint32_t t = (uint32_t)(traj0 + (uint64_t)k);
+            FGI_HIP(hipMemcpyAsync(f.U, Ucur, gauge_bytes(g), hipMemcpyDeviceToDevice, c.stream));
+            refresh_momenta(c, g, seed, t, f.P);
+            if (ferm) refresh_noise(c, g, seed, t, RNG_ETA1, eta);
+            if (hasen) refresh_noise(c, g, seed, t, RNG_ETA2, eta_2);
+            f.nonconv = false;
+            const double dh = trajectory_packed(f, *integ, tau, nsteps, eta, eta_2, false);
+            if (!std::isfinite(dh)) throw Error(FGI_ENONFINITE, "dH is not finite");
+            nonconv = nonconv || f.nonconv;
+            const bool acc = !metropolis || metropolis_uniform(seed, t) < std::exp(-dh);
+            if (acc) std::swap(Ucur, f.U);
+            reunitarize(c, g, Ucur);
+            if (dH) dH[k] = dh;
+            if (accepted) accepted[k] = acc ? 1 : 0;
+            if (plaq) {  // average plaquette ReTr U_P / 3 = 1 - S_G(beta = 1) / (6 V)
+                ham_density(c, g, 1.0, Ucur, nullptr, (double*)c.h0.get(sizeof(double) * g.V));
+                int nb = diff_partials(c, g.V, (const double*)c.h0.get(sizeof(double) * g.V), nullptr, part);
+                final_sum(c, part, nb, scal + 8);
+                plaq[k] = 1.0 - sync_scalar(c, scal + 8, 8) / (6.0 * g.V);
+            }
+        }
+        unpack_gauge(c, g, Ucur, U);
+        FGI_HIP(hipStreamSynchronize(c.stream));
+        if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (nonconv) throw Error(FGI_ENOCONV, "a CG solve reached cg_maxiter");
     });
 }
 

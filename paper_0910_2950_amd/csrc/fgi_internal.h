@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -95,6 +96,7 @@ struct Ctx {
     DevBuf phi2, eta2, user_tmp, chi, X2;
     // force gradient of the pseudofermion force: tangent links and vectors
     DevBuf gauge_tan, tg_dmx, tg_rhs, tg_z, tg_dxo, tg_dye, tg_dyo, force3;
+    DevBuf chain_U;   // the accepted links of an on-device Markov chain
     DevBuf cdesc, bstate, bscal, bh0, bh1, bres;  // batched chains
     CGState* host_bstates = nullptr;          // pinned [host_b_cap]
     double* host_bscal = nullptr;             // pinned [host_b_cap]
@@ -195,6 +197,15 @@ void final_sums_b(Ctx&, const Batch&, const double* partial, int kind, double* o
 void gauge_force_b(Ctx&, const Batch&, const d2* U, double* F, double coef, int accumulate);
 void link_update_b(Ctx&, const Batch&, double h, const double* X, const d2* src, d2* dst, void* sloppy, int prec,
                    int recon);
+
+// ---------------- chain.hip ----------------
+// Heatbath draws of trajectory traj of the chain with this seed (rng.h streams):
+// P internal momenta, eta internal even noise of stream 1 (eta1) or 2 (eta2)
+void refresh_momenta(Ctx&, const Geom&, uint64_t seed, uint32_t traj, double* P);
+void refresh_noise(Ctx&, const Geom&, uint64_t seed, uint32_t traj, int stream, d2* eta);
+// the Metropolis uniform of trajectory traj (host)
+double metropolis_uniform(uint64_t seed, uint32_t traj);
+void philox_host(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
 // ---------------- fermion.hip ----------------
 struct FermionOp {

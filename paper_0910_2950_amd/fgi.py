@@ -71,6 +71,15 @@ class fgi_tuning(ctypes.Structure):
                     sched_us_per_iter=list(self.sched_us_per_iter), batch_ms_per_solve=list(self.batch_ms_per_solve))
 
 
+def philox4x32_10(ctr, key):
+    """The library's Philox4x32-10 of one counter (host)."""
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xffffffff for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xffffffff for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    _check(lib().fgi_philox4x32_10(c, k, o))
+    return [int(x) for x in o]
+
+
 class fgi_stats(ctypes.Structure):
     _fields_ = [("solves", ctypes.c_long), ("cg_iters", ctypes.c_long), ("cg_iters_max", ctypes.c_int),
                 ("reliable_updates", ctypes.c_int), ("max_rel_resid", ctypes.c_double),
@@ -111,6 +120,10 @@ SIGNATURES = {
     "fgi_integrator_builtin": (_i, [_i, _d, _P(fgi_integrator)]),
     "fgi_trajectory": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _P(fgi_integrator), _d, _i, _vp, _vp, _vp, _vp,
                             _i, _P(_d), _P(fgi_stats), _vp]),
+    "fgi_refresh": (_i, [_vp, _P(fgi_geom), ctypes.c_uint64, ctypes.c_uint64, _vp, _vp, _vp, _vp]),
+    "fgi_philox4x32_10": (_i, [_P(ctypes.c_uint32), _P(ctypes.c_uint32), _P(ctypes.c_uint32)]),
+    "fgi_hmc_run": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _P(fgi_integrator), _d, _i, _vp, ctypes.c_uint64,
+                         ctypes.c_uint64, _i, _i, _P(_d), _P(_i), _P(_d), _P(fgi_stats), _vp]),
     "fgi_trajectory_batched": (_i, [_vp, _i, _vp, _P(fgi_action), _P(fgi_integrator), _d, _i, _P(_d),
                                     _P(fgi_stats), _vp]),
     "fgi_autotune_cg": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _P(fgi_tuning), _vp]),
@@ -412,6 +425,35 @@ class Context:
         d = st.as_dict()
         d["status"] = rc
         return dH.value, d
+
+    # ---- Markov chain on the device
+    def refresh(self, dims, seed, traj, momenta=True, eta1=True, eta2=False):
+        """Heatbath draws (P, eta1, eta2) of trajectory traj of the chain `seed` (None where not asked)."""
+        su, sp, se = self._shapes(dims)
+        P = torch.empty(sp, dtype=torch.float64, device="cuda") if momenta else None
+        e1 = torch.empty(se, dtype=torch.complex128, device="cuda") if eta1 else None
+        e2 = torch.empty(se, dtype=torch.complex128, device="cuda") if eta2 else None
+        _check(lib().fgi_refresh(self.h, _geom(dims), int(seed), int(traj), _ptr(P, torch.float64, sp, "P"),
+                                 _ptr(e1, torch.complex128, se, "eta1"), _ptr(e2, torch.complex128, se, "eta2"),
+                                 _stream()))
+        return P, e1, e2
+
+    def hmc_run(self, dims, act, integ, tau, nsteps, U, seed, traj0, ntraj, metropolis=True, allow_noconv=False):
+        """ntraj chain trajectories on U (updated in place); returns dH, accepted, plaquette lists and stats."""
+        su, _, _ = self._shapes(dims)
+        if isinstance(integ, str):
+            integ = integrator_builtin(integ)
+        n = max(int(ntraj), 1)
+        dH, acc, plaq = (ctypes.c_double * n)(), (ctypes.c_int * n)(), (ctypes.c_double * n)()
+        st = fgi_stats()
+        rc = _check(lib().fgi_hmc_run(self.h, _geom(dims), ctypes.byref(act.c()), ctypes.byref(integ), float(tau),
+                                      int(nsteps), _ptr(U, torch.complex128, su, "U"), int(seed), int(traj0),
+                                      int(ntraj), int(bool(metropolis)), dH, acc, plaq, ctypes.byref(st), _stream()),
+                    (FGI_ENOCONV,) if allow_noconv else ())
+        d = st.as_dict()
+        d["status"] = rc
+        k = int(ntraj)
+        return list(dH)[:k], [bool(a) for a in list(acc)[:k]], list(plaq)[:k], d
 
     def trajectory_batched(self, chains, act, integ, tau, nsteps, allow_noconv=False):
         """chains: list of dicts with dims, beta, kappa, U, P, eta (tensors on the
