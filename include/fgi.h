@@ -144,7 +144,10 @@ const char* fgi_last_error(void);
 /* Tuning/diagnostic options: "cg_batch" (CG iterations launched between host
  * polls; each batch is one replay of a captured HIP graph), "dslash_block"
  * (64, 128 or 256 even sites per block of the Dslash-shaped kernels),
- * "xcd_order" (1: XCD-aware block order, 0: linear), "graphs" (0: launch
+ * "xcd_order" (1: XCD-aware block order, 0: linear), "fg_start" (1, the default: in the displacement form of an FG stage the
+ * solves of the displaced force start from the solutions at the undisplaced
+ * links, which are a function of the stage's links alone, so the stage stays
+ * reversible; 0: from zero), "graphs" (0: launch
  * the batch kernels one by one instead), "ru_delta" (reliable-update residual
  * drop), "profile" (1: after every CG solve, time 16 back-to-back launches of
  * the bare Dslash hop on the solve's operator with HIP events), "profile_prec"

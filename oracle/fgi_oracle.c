@@ -526,22 +526,29 @@ static void normal_op(const int L[4], double kappa, const cplx *U, const cplx *i
     oracle_mhat(L, kappa, U, tmp, out, 1);
 }
 
-/* Conjugate gradient on A = Mhat^+ Mhat from a zero start.  Stops when the
- * true residual |phi - A x| <= tol |phi| (when the recursive residual first
- * passes the target the true residual is formed; if it has not passed, CG
- * restarts from it).  Returns the iteration count, or -1 on maxiter. */
-int oracle_cg(const int L[4], double kappa, const cplx *U, const cplx *phi, cplx *x, double tol,
-              int maxiter, double *rel_resid) {
+/* Conjugate gradient on A = Mhat^+ Mhat from a zero start, or (start != 0)
+ * from the x given on entry, whose true residual phi - A x is then the first
+ * residual and direction.  Stops when the true residual |phi - A x| <=
+ * tol |phi| (when the recursive residual first passes the target the true
+ * residual is formed; if it has not passed, CG restarts from it).  Returns
+ * the iteration count, or -1 on maxiter. */
+int oracle_cg_from(const int L[4], double kappa, const cplx *U, const cplx *phi, cplx *x, double tol,
+                   int maxiter, double *rel_resid, int start) {
     long n = (lat_volume(L) / 2) * 12;
     cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n);
     cplx *Ap = malloc(sizeof(cplx) * n), *tmp = malloc(sizeof(cplx) * n);
     double bb = vdot_re(n, phi, phi), target = tol * tol * bb;
-    memset(x, 0, sizeof(cplx) * n);
-    memcpy(r, phi, sizeof(cplx) * n);
+    if (!start || bb == 0.0) {
+        memset(x, 0, sizeof(cplx) * n);
+        memcpy(r, phi, sizeof(cplx) * n);
+    } else {
+        normal_op(L, kappa, U, x, Ap, tmp);
+        for (long k = 0; k < n; k++) r[k] = phi[k] - Ap[k];
+    }
     memcpy(p, r, sizeof(cplx) * n);
-    double rr = bb;
+    double rr = vdot_re(n, r, r);
     int it = 0, status = -1;
-    if (bb == 0.0) { status = 0; goto done; }
+    if (bb == 0.0 || rr <= target) { status = 0; goto done; }
     while (it < maxiter) {
         normal_op(L, kappa, U, p, Ap, tmp);
         double alpha = rr / vdot_re(n, p, Ap);
@@ -569,6 +576,11 @@ done:
     }
     free(r); free(p); free(Ap); free(tmp);
     return status;
+}
+
+int oracle_cg(const int L[4], double kappa, const cplx *U, const cplx *phi, cplx *x, double tol,
+              int maxiter, double *rel_resid) {
+    return oracle_cg_from(L, kappa, U, phi, x, tol, maxiter, rel_resid, 0);
 }
 
 /* heatbath: phi = Mhat^+ eta */
@@ -793,19 +805,26 @@ int oracle_hasen_heatbath(const int L[4], double kappa, double kappa2, const cpl
     return it;
 }
 
-/* S_2 value: Re chi^+ X2, X2 = (Mhat^+ Mhat)^-1 chi (returns X2 when asked) */
-double oracle_hasen_action(const int L[4], double kappa, double kappa2, const cplx *U, const cplx *phi2,
-                           double tol, int maxiter, cplx *X2out, int *iters) {
+/* S_2 value: Re chi^+ X2, X2 = (Mhat^+ Mhat)^-1 chi (returns X2 when asked);
+ * start != 0: the solve starts from the X2out given on entry */
+static double hasen_action_from(const int L[4], double kappa, double kappa2, const cplx *U, const cplx *phi2,
+                                double tol, int maxiter, cplx *X2out, int *iters, int start) {
     long Vh = lat_volume(L) / 2;
     cplx *chi = malloc(sizeof(cplx) * 12 * Vh), *x = malloc(sizeof(cplx) * 12 * Vh);
     oracle_mhat(L, kappa2, U, phi2, chi, 1);
-    int it = oracle_cg(L, kappa, U, chi, x, tol, maxiter, NULL);
+    if (start) memcpy(x, X2out, sizeof(cplx) * 12 * Vh);
+    int it = oracle_cg_from(L, kappa, U, chi, x, tol, maxiter, NULL, start);
     if (iters) *iters = it;
     double s = 0;
     for (long k = 0; k < Vh; k++) s += vdot_re(12, chi + k * 12, x + k * 12);
     if (X2out) memcpy(X2out, x, sizeof(cplx) * 12 * Vh);
     free(chi); free(x);
     return s;
+}
+
+double oracle_hasen_action(const int L[4], double kappa, double kappa2, const cplx *U, const cplx *phi2,
+                           double tol, int maxiter, cplx *X2out, int *iters) {
+    return hasen_action_from(L, kappa, kappa2, U, phi2, tol, maxiter, X2out, iters, 0);
 }
 
 /* Force of S_2 given X2 = (Mhat^+ Mhat)^-1 Mhat2^+ phi2:
@@ -841,19 +860,25 @@ static void add_solve(oracle_stats *st, const oracle_action *act, int it) {
     else st->cg_iters += it;
 }
 
-/* F = F_G + F_F at U (F_F needs one CG solve); the solution X_e is copied to
- * Xout when given */
-static void total_force_x(const int L[4], const oracle_action *act, const cplx *U, const cplx *phi,
-                          double *F, oracle_stats *st, cplx *Xout) {
+/* F = F_G + F_F at U (F_F needs one CG solve, from zero or from X0 when
+ * given); the solution X_e is copied to Xout when given */
+static void total_force_from(const int L[4], const oracle_action *act, const cplx *U, const cplx *phi,
+                             double *F, oracle_stats *st, cplx *Xout, const cplx *X0) {
     oracle_gauge_force(L, act->beta, U, F);
     if (!act->fermions) return;
     long Vh = lat_volume(L) / 2;
     cplx *X = malloc(sizeof(cplx) * 12 * Vh);
-    int it = oracle_cg(L, act->kappa, U, phi, X, act->cg_tol, act->cg_maxiter, NULL);
+    if (X0) memcpy(X, X0, sizeof(cplx) * 12 * Vh);
+    int it = oracle_cg_from(L, act->kappa, U, phi, X, act->cg_tol, act->cg_maxiter, NULL, X0 != NULL);
     add_solve(st, act, it);
     oracle_fermion_force_add(L, act->kappa, U, X, 1.0, F);
     if (Xout) memcpy(Xout, X, sizeof(cplx) * 12 * Vh);
     free(X);
+}
+
+static void total_force_x(const int L[4], const oracle_action *act, const cplx *U, const cplx *phi,
+                          double *F, oracle_stats *st, cplx *Xout) {
+    total_force_from(L, act, U, phi, F, st, Xout, NULL);
 }
 
 static void total_force(const int L[4], const oracle_action *act, const cplx *U, const cplx *phi,
@@ -907,6 +932,9 @@ void oracle_force(const int L[4], double beta, double kappa, int fermions, doubl
  *          exact form:        p += w dt F + 2 xi dt^3 J_F[F]
  *          displacement form: U' = exp((2 xi / w) dt^2 F(U)) U,
  *                             p += w dt F(U')   (same to O(dt^5)).
+ * With fg_start, the solve of the displaced force F(U') starts from the
+ * solution at U (both are functions of the stage's U alone, so the stage
+ * stays a momentum kick by a function of U); without it, from zero.
  * Consecutive P stages (the last of one step and the first of the next) are
  * merged into one, so every P stage costs one force evaluation.
  * eta (compact even sites) is the pseudofermion heatbath noise:
@@ -918,7 +946,7 @@ void oracle_force(const int L[4], double beta, double kappa, int fermions, doubl
 int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, double cg_tol,
                       int cg_maxiter, int fg_exact, int nstages, const char *kinds,
                       const double *ws, const double *xis, double tau, int nsteps, cplx *U,
-                      double *P, const cplx *eta, const cplx *phi_in, double *dH, long *stats3) {
+                      double *P, const cplx *eta, const cplx *phi_in, double *dH, long *stats3, int fg_start) {
     oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, fg_exact};
     oracle_stats st = {0, 0, 0};
     long V = lat_volume(L), Vh = V / 2;
@@ -978,10 +1006,10 @@ int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, d
                 for (long k = 0; k < 4 * V * 8; k++)
                     P[k] += w * dt * F[k] + 2.0 * XI[s] * dt * dt * dt * F2[k];
             } else {
-                total_force(L, &act, U, phi, F, &st);
+                total_force_x(L, &act, U, phi, F, &st, Xg);
                 memcpy(Ud, U, sizeof(cplx) * 4 * V * 9);
                 oracle_link_update(L, 2.0 * XI[s] / w * dt * dt, F, Ud);
-                total_force(L, &act, Ud, phi, F2, &st);
+                total_force_from(L, &act, Ud, phi, F2, &st, NULL, fg_start ? Xg : NULL);
                 for (long k = 0; k < 4 * V * 8; k++) P[k] += w * dt * F2[k];
             }
         }
@@ -1029,6 +1057,8 @@ typedef struct {
     cplx *U;
     double *P;
     oracle_stats st;
+    int fg_start;        /* displaced solves start from the undisplaced solutions */
+    cplx *X1, *X2;       /* the last solutions of the S_F (S_1) and S_2 solves */
 } nested_run;
 
 static void count_solve(nested_run *r, int it) {
@@ -1036,8 +1066,9 @@ static void count_solve(nested_run *r, int it) {
     if (it < 0) { r->st.cg_fail++; r->st.cg_iters += r->maxiter; } else r->st.cg_iters += it;
 }
 
-/* F = sum of the forces of the selected terms at links W */
-static void terms_force(nested_run *r, const cplx *W, int terms, double *F) {
+/* F = sum of the forces of the selected terms at links W; with from_last the
+ * solves start from the last solutions (r->X1, r->X2), which they replace */
+static void terms_force(nested_run *r, const cplx *W, int terms, double *F, int from_last) {
     const int *L = r->L;
     long V = lat_volume(L), Vh = V / 2;
     memset(F, 0, sizeof(double) * 4 * V * 8);
@@ -1048,19 +1079,17 @@ static void terms_force(nested_run *r, const cplx *W, int terms, double *F) {
         free(g);
     }
     if (r->kappa == 0.0) return;
-    cplx *x = malloc(sizeof(cplx) * 12 * Vh);
     if (terms & TERM_FERM) {
         double k1 = r->kappa2 != 0.0 ? r->kappa2 : r->kappa;
-        count_solve(r, oracle_cg(L, k1, W, r->phi1, x, r->tol, r->maxiter, NULL));
-        oracle_fermion_force_add(L, k1, W, x, 1.0, F);
+        count_solve(r, oracle_cg_from(L, k1, W, r->phi1, r->X1, r->tol, r->maxiter, NULL, from_last));
+        oracle_fermion_force_add(L, k1, W, r->X1, 1.0, F);
     }
     if ((terms & TERM_HASEN) && r->kappa2 != 0.0) {
         int it;
-        oracle_hasen_action(L, r->kappa, r->kappa2, W, r->phi2, r->tol, r->maxiter, x, &it);
+        hasen_action_from(L, r->kappa, r->kappa2, W, r->phi2, r->tol, r->maxiter, r->X2, &it, from_last);
         count_solve(r, it);
-        oracle_hasen_force_add(L, r->kappa, r->kappa2, W, r->phi2, x, 1.0, F);
+        oracle_hasen_force_add(L, r->kappa, r->kappa2, W, r->phi2, r->X2, 1.0, F);
     }
-    free(x);
 }
 
 /* run level l for n steps of size h: the step table repeated n times with
@@ -1082,16 +1111,16 @@ static void run_level(nested_run *r, int l, int n, double h) {
     for (int s = 0; s < m; s++) {
         double w = Wt[s];
         if (K[s] == 'P') {
-            terms_force(r, r->U, r->terms[l], F);
+            terms_force(r, r->U, r->terms[l], F, 0);
             for (long k = 0; k < 4 * V * 8; k++) r->P[k] += w * h * F[k];
         } else if (K[s] == 'Q') {
             if (l + 1 < r->nlevels) run_level(r, l + 1, r->nsub[l + 1], w * h / r->nsub[l + 1]);
             else oracle_link_update(L, w * h, r->P, r->U);
         } else {
-            terms_force(r, r->U, r->terms[l], F);
+            terms_force(r, r->U, r->terms[l], F, 0);
             memcpy(Ud, r->U, sizeof(cplx) * 4 * V * 9);
             oracle_link_update(L, 2.0 * XI[s] / w * h * h, F, Ud);
-            terms_force(r, Ud, r->terms[l], F);
+            terms_force(r, Ud, r->terms[l], F, r->fg_start);
             for (long k = 0; k < 4 * V * 8; k++) r->P[k] += w * h * F[k];
         }
     }
@@ -1105,7 +1134,8 @@ static void run_level(nested_run *r, int l, int n, double h) {
 int oracle_trajectory_nested(const int L[4], double beta, double kappa, double kappa2, double cg_tol,
                              int cg_maxiter, int nlevels, const int *nstages, const int *terms, const int *nsub,
                              const char *kinds, const double *ws, const double *xis, double tau, int nsteps,
-                             cplx *U, double *P, const cplx *eta1, const cplx *eta2, double *dH, long *stats3) {
+                             cplx *U, double *P, const cplx *eta1, const cplx *eta2, double *dH, long *stats3,
+                             int fg_start) {
     long V = lat_volume(L), Vh = V / 2;
     const char *kp[8];
     const double *wp[8], *xp[8];
@@ -1115,7 +1145,9 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
         off += nstages[l];
     }
     nested_run r = {L, beta, kappa, kappa2, cg_tol, cg_maxiter, nlevels, nstages, terms, nsub, kp, wp, xp,
-                    NULL, NULL, U, P, {0, 0, 0}};
+                    NULL, NULL, U, P, {0, 0, 0}, fg_start, NULL, NULL};
+    r.X1 = calloc(12 * Vh, sizeof(cplx));
+    r.X2 = calloc(12 * Vh, sizeof(cplx));
     cplx *phi1 = NULL, *phi2 = NULL;
     double *h0 = malloc(sizeof(double) * V), *h1 = malloc(sizeof(double) * V), *tmp = malloc(sizeof(double) * V);
     gauge_density(L, beta, U, h0);
@@ -1151,7 +1183,7 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
     }
     *dH = d;
     if (stats3) { stats3[0] = r.st.solves; stats3[1] = r.st.cg_iters; stats3[2] = r.st.cg_fail; }
-    free(phi1); free(phi2); free(h0); free(h1); free(tmp);
+    free(phi1); free(phi2); free(h0); free(h1); free(tmp); free(r.X1); free(r.X2);
     return r.st.cg_fail ? -3 : 0;
 }
 
@@ -1265,7 +1297,7 @@ double oracle_metropolis_uniform(uint64_t seed, uint32_t traj) {
 int oracle_hmc_run(const int L[4], double beta, double kappa, int fermions, double cg_tol, int cg_maxiter,
                    int fg_exact, int nstages, const char *kinds, const double *ws, const double *xis, double tau,
                    int nsteps, cplx *U, uint64_t seed, uint32_t traj0, int ntraj, int metropolis, double *dH,
-                   int *acc, double *plaq) {
+                   int *acc, double *plaq, int fg_start) {
     long V = lat_volume(L), Vh = V / 2;
     double *P = malloc(sizeof(double) * 4 * V * 8);
     cplx *Ut = malloc(sizeof(cplx) * 4 * V * 9);
@@ -1278,7 +1310,7 @@ int oracle_hmc_run(const int L[4], double beta, double kappa, int fermions, doub
         double d = 0.0;
         long st3[3];
         int rc = oracle_trajectory(L, beta, kappa, fermions, cg_tol, cg_maxiter, fg_exact, nstages, kinds, ws, xis,
-                                   tau, nsteps, Ut, P, eta, NULL, &d, st3);
+                                   tau, nsteps, Ut, P, eta, NULL, &d, st3, fg_start);
         if (rc) status = rc;
         int a = !metropolis || oracle_metropolis_uniform(seed, t) < exp(-d);
         if (a) memcpy(U, Ut, sizeof(cplx) * 4 * V * 9);

@@ -79,7 +79,7 @@ def _declare(L):
     L.oracle_fermion_force_tangent_add.argtypes = [_ip, _d, _vp, _vp, _vp, _d, _i, _d, _vp]
     L.oracle_fermion_force_tangent_add.restype = _i
     L.oracle_trajectory.argtypes = [_ip, _d, _d, _i, _d, _i, _i, _i, ctypes.c_char_p, _vp, _vp,
-                                    _d, _i, _vp, _vp, _vp, _vp, _dp, _lp]
+                                    _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i]
     L.oracle_trajectory.restype = _i
     L.oracle_brackets.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _d, _dp, _dp]
     L.oracle_hasen_heatbath.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _d, _i]
@@ -88,14 +88,16 @@ def _declare(L):
     L.oracle_hasen_action.restype = _d
     L.oracle_hasen_force_add.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _d, _vp]
     L.oracle_trajectory_nested.argtypes = [_ip, _d, _d, _d, _d, _i, _i, _vp, _vp, _vp, ctypes.c_char_p, _vp, _vp,
-                                           _d, _i, _vp, _vp, _vp, _vp, _dp, _lp]
+                                           _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i]
     L.oracle_trajectory_nested.restype = _i
     L.oracle_philox.argtypes = [_vp, _vp, _vp]
     L.oracle_refresh.argtypes = [_ip, ctypes.c_uint64, ctypes.c_uint32, _vp, _vp, _vp]
     L.oracle_metropolis_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
     L.oracle_metropolis_uniform.restype = _d
     L.oracle_hmc_run.argtypes = [_ip, _d, _d, _i, _d, _i, _i, _i, ctypes.c_char_p, _vp, _vp, _d, _i, _vp,
-                                 ctypes.c_uint64, ctypes.c_uint32, _i, _i, _vp, _vp, _vp]
+                                 ctypes.c_uint64, ctypes.c_uint32, _i, _i, _vp, _vp, _vp, _i]
+    L.oracle_cg_from.argtypes = [_ip, _d, _vp, _vp, _vp, _d, _i, _dp, _i]
+    L.oracle_cg_from.restype = _i
     L.oracle_hmc_run.restype = _i
 
 
@@ -238,6 +240,16 @@ def fermion_force(dims, kappa, U, Xe):
     return F
 
 
+def cg_from(dims, kappa, U, phi, x0, tol=1e-10, maxiter=10000):
+    """CG started from x0; returns (X, iterations or -1, final relative residual)."""
+    U = _c(U, np.complex128)
+    phi = _c(phi, np.complex128)
+    X = np.array(x0, dtype=np.complex128, copy=True, order="C")
+    rel = ctypes.c_double(0)
+    it = lib().oracle_cg_from(_dims(dims), kappa, _ptr(U), _ptr(phi), _ptr(X), tol, maxiter, ctypes.byref(rel), 1)
+    return X, it, rel.value
+
+
 def force(dims, beta, U, kappa=0.0, phi=None, tol=1e-14, maxiter=10000):
     """total force F = F_G (+ F_F when phi is given); returns (F, stats)"""
     U = _c(U, np.complex128)
@@ -276,9 +288,10 @@ def fermion_force_tangent(dims, kappa, U, X, V, tol=1e-14, maxiter=10000):
 
 
 def trajectory(dims, beta, stages, tau, nsteps, U, P, kappa=0.0, eta=None, tol=1e-14,
-               maxiter=10000, fg_exact=False, phi=None):
+               maxiter=10000, fg_exact=False, phi=None, fg_start=True):
     """One MD trajectory.  stages: list of (kind, w, xi) with kind in 'PQG'.
-    Fermions: give eta (phi = Mhat^+ eta) or phi itself.
+    Fermions: give eta (phi = Mhat^+ eta) or phi itself.  fg_start: the
+    displaced force's solve of a G stage starts from the undisplaced solution.
     Returns (U_final, P_final, dH, stats, status)."""
     U = np.array(U, dtype=np.complex128, copy=True, order="C")
     P = np.array(P, dtype=np.float64, copy=True, order="C")
@@ -295,7 +308,7 @@ def trajectory(dims, beta, stages, tau, nsteps, U, P, kappa=0.0, eta=None, tol=1
                                      tau, nsteps, _ptr(U), _ptr(P),
                                      _ptr(eta_a) if eta_a is not None else None,
                                      _ptr(phi_a) if phi_a is not None else None,
-                                     ctypes.byref(dH), st)
+                                     ctypes.byref(dH), st, int(bool(fg_start)))
     return U, P, dH.value, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2]), status
 
 
@@ -341,7 +354,7 @@ def hasen_force(dims, kappa, kappa2, U, phi2, X2):
 
 
 def trajectory_nested(dims, beta, levels, tau, nsteps, U, P, kappa=0.0, kappa2=0.0, eta1=None, eta2=None,
-                      tol=1e-14, maxiter=10000):
+                      tol=1e-14, maxiter=10000, fg_start=True):
     """levels: list of (stages, terms, nsub), level 0 outermost; terms bit 1 gauge,
     2 S_F (or S_1 with Hasenbusch), 4 S_2.  Returns (U, P, dH, stats, status)."""
     U = np.array(U, dtype=np.complex128, copy=True, order="C")
@@ -359,7 +372,8 @@ def trajectory_nested(dims, beta, levels, tau, nsteps, U, P, kappa=0.0, kappa2=0
     status = lib().oracle_trajectory_nested(_dims(dims), beta, kappa, kappa2, tol, maxiter, len(levels), _ptr(ns),
                                             _ptr(terms), _ptr(nsub), kinds, _ptr(ws), _ptr(xis), tau, nsteps,
                                             _ptr(U), _ptr(P), _ptr(e1) if e1 is not None else None,
-                                            _ptr(e2) if e2 is not None else None, ctypes.byref(dH), st)
+                                            _ptr(e2) if e2 is not None else None, ctypes.byref(dH), st,
+                                            int(bool(fg_start)))
     return U, P, dH.value, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2]), status
 
 
@@ -392,7 +406,7 @@ def metropolis_uniform(seed, traj):
 
 
 def hmc_run(dims, beta, stages, tau, nsteps, U, seed, traj0, ntraj, kappa=0.0, fermions=False, tol=1e-14,
-            maxiter=10000, fg_exact=False, metropolis=True):
+            maxiter=10000, fg_exact=False, metropolis=True, fg_start=True):
     """HMC chain of ntraj trajectories from U; returns (U_final, dH list, accepted list, plaquettes, status)."""
     U = np.array(U, dtype=np.complex128, copy=True, order="C")
     kinds = "".join(s[0] for s in stages).encode()
@@ -404,7 +418,8 @@ def hmc_run(dims, beta, stages, tau, nsteps, U, seed, traj0, ntraj, kappa=0.0, f
     plaq = np.zeros(n)
     status = lib().oracle_hmc_run(_dims(dims), beta, kappa, int(bool(fermions)), tol, maxiter, int(bool(fg_exact)),
                                   len(stages), kinds, _ptr(ws), _ptr(xis), tau, nsteps, _ptr(U), int(seed),
-                                  int(traj0), int(ntraj), int(bool(metropolis)), _ptr(dH), _ptr(acc), _ptr(plaq))
+                                  int(traj0), int(ntraj), int(bool(metropolis)), _ptr(dH), _ptr(acc), _ptr(plaq),
+                                  int(bool(fg_start)))
     k = int(ntraj)
     return U, list(dH[:k]), [bool(a) for a in acc[:k]], list(plaq[:k]), status
 

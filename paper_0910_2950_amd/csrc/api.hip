@@ -158,15 +158,17 @@ struct Fields {
         return FermionOp{&g, kappa, us, sp, rc};
     }
 
-    CGResult solve(const d2* u, const void* us, double kappa, const d2* rhs, d2* x) {
-        CGResult r = cg_solve(c, op64(u, kappa), ops(u, us, kappa), sp, rhs, x, act.cg_tol, act.cg_maxiter);
+    CGResult solve(const d2* u, const void* us, double kappa, const d2* rhs, d2* x, bool guess = false) {
+        CGResult r = cg_solve(c, op64(u, kappa), ops(u, us, kappa), sp, rhs, x, act.cg_tol, act.cg_maxiter, guess);
         accumulate_stats(st, r);
         if (!r.converged) nonconv = true;
         return r;
     }
 
-    // out (+)= coef * F_terms(u)
-    void force(const d2* u, const void* us, int terms, double* out, double coef, bool accumulate) {
+    // out (+)= coef * F_terms(u); guess: the solves start from the solutions
+    // held in X, X2 (those of the previous force evaluation)
+    void force(const d2* u, const void* us, int terms, double* out, double coef, bool accumulate,
+               bool guess = false) {
         bool have = accumulate;
         if (st) st->force_evals++;
         if (terms & FGI_TERM_GAUGE) {
@@ -181,13 +183,13 @@ struct Fields {
         if (!have) zero_mom(out);
         const double k1 = act.kappa_hasen != 0.0 ? act.kappa_hasen : act.kappa;
         if (terms & FGI_TERM_FERMION) {
-            solve(u, us, k1, phi[0], X);
+            solve(u, us, k1, phi[0], X, guess);
             fermion_force(c, op64(u, k1), X, out, coef);
         }
         if ((terms & FGI_TERM_HASEN) && act.kappa_hasen != 0.0) {
             // S_2 = chi^+ (Mhat^+ Mhat)^-1 chi, chi = Mhat2^+ phi2: the ordinary force
             // of X2 at kappa plus -kappa2^2 TA(U C(X2, phi2)) from the U dependence of chi
-            hasen_solve(u, us);
+            hasen_solve(u, us, guess);
             fermion_force(c, op64(u, act.kappa), X2, out, coef);
             fermion_force_xy(c, op64(u, act.kappa_hasen), X2, phi[1], out,
                              -coef * act.kappa_hasen * act.kappa_hasen);
@@ -215,11 +217,11 @@ struct Fields {
     }
 
     // chi = Mhat2^+ phi2 at u; X2 = (Mhat^+ Mhat)^-1 chi
-    void hasen_solve(const d2* u, const void* us) {
+    void hasen_solve(const d2* u, const void* us, bool guess = false) {
         d2* t = (d2*)c.tmp_o.get(spinor_bytes(g));
         mhat(c, op64(u, act.kappa_hasen), P64, SpinorPtr{phi[1], nullptr}, SpinorPtr{t, nullptr},
              SpinorPtr{chi, nullptr}, 1);
-        solve(u, us, act.kappa, chi, X2);
+        solve(u, us, act.kappa, chi, X2, guess);
     }
 
     // phi2 = Mhat2 (Mhat2^+ Mhat2)^-1 Mhat^+ eta2 at u (one solve at kappa2)
@@ -319,6 +321,8 @@ int fgi_set_option(fgi_ctx* ctx, const char* name, double value) {
             c.ds_bs = (int)value;
         } else if (n == "xcd_order") {
             c.ds_xcd = value != 0;
+        } else if (n == "fg_start") {
+            c.fg_start = value != 0;
         } else if (n == "graphs") {
             c.use_graphs = value != 0;
         } else if (n == "profile") {
@@ -983,7 +987,7 @@ struct Driver {
         }
         f.force(f.U, f.Us, terms, f.F, 1.0, false);
         link_update(f.c, f.g, 2.0 * xi / w * h * h, f.F, f.U, f.Ud, f.Uds, f.sp, f.rc);
-        f.force(f.Ud, f.Uds, terms, f.P, w * h, true);
+        f.force(f.Ud, f.Uds, terms, f.P, w * h, true, f.c.fg_start != 0);
     }
 };
 
@@ -1218,14 +1222,16 @@ struct BFields {
         if (sp == P64) return op64(u);
         return FermionOp{nullptr, 0.0, us, sp, rc};
     }
-    void solve(const d2* u, const void* us, const d2* rhs, d2* x) {
-        std::vector<CGResult> r = cg_solve_b(c, B, op64(u), ops(u, us), sp, rhs, x, act.cg_tol, act.cg_maxiter);
+    void solve(const d2* u, const void* us, const d2* rhs, d2* x, bool guess = false) {
+        std::vector<CGResult> r =
+            cg_solve_b(c, B, op64(u), ops(u, us), sp, rhs, x, act.cg_tol, act.cg_maxiter, guess);
         for (const CGResult& q : r) {
             accumulate_stats(st, q);
             if (!q.converged) nonconv = true;
         }
     }
-    void force(const d2* u, const void* us, int terms, double* out, double coef, bool accumulate) {
+    void force(const d2* u, const void* us, int terms, double* out, double coef, bool accumulate,
+               bool guess = false) {
         bool have = accumulate;
         if (st) st->force_evals++;
         if (terms & FGI_TERM_GAUGE) {
@@ -1234,7 +1240,7 @@ struct BFields {
         }
         if (!have) zero_doubles(c, out, 8 * (size_t)B.links);
         if (fermions && (terms & FGI_TERM_FERMION)) {
-            solve(u, us, phi, X);
+            solve(u, us, phi, X, guess);
             fermion_force_b(c, B, op64(u), X, out, coef);
         }
     }
@@ -1261,7 +1267,7 @@ struct BDriver {
                 } else {
                     f.force(f.U, f.Us, L.terms, f.F, 1.0, false);
                     link_update_b(f.c, f.B, 2.0 * s.xi / s.w * h * h, f.F, f.U, f.Ud, f.Uds, f.sp, f.rc);
-                    f.force(f.Ud, f.Uds, L.terms, f.P, s.w * h, true);
+                    f.force(f.Ud, f.Uds, L.terms, f.P, s.w * h, true, f.c.fg_start != 0);
                 }
             }
         }

@@ -1071,30 +1071,44 @@ static void zero_spinor(Ctx& c, const Geom& g, void* v, int prec) {
     FGI_LAUNCH_CHECK();
 }
 
+// guess: X holds the starting point on entry (else CG starts from zero); the
+// run then begins like a reliable update, from the true residual phi - A X,
+// and stops on |phi - A X| <= tol |phi| as always.
 template <int PP, int PX>
 static CGResult cg_run(Ctx& c, const FermionOp& op64, const FermionOp& ops, const d2* phi, d2* X, double tol,
-                       int maxiter) {
+                       int maxiter, bool guess) {
     const Geom& g = *op64.g;
     const size_t n64 = sizeof(d2) * 12 * (size_t)g.Vh;
     CGResult res{0, 0, 0.0, 0};
     double bb = norm2_sync(c, g, phi);
-    zero_spinor(c, g, X, P64);
+    if (!guess || bb == 0.0) zero_spinor(c, g, X, P64);
     if (bb == 0.0) {
         res.converged = 1;
         return res;
     }
     const double target = tol * tol * bb;
     d2* r64 = (d2*)c.cg_r.get(n64);
+    double rr0 = bb;  // |r|^2 of the starting point
+    if (guess) {
+        rr0 = true_residual(c, op64, phi, X, r64);
+        if (!std::isfinite(rr0)) throw Error(-4, "CG: non-finite residual of the starting point");
+        if (rr0 <= target) {
+            res.converged = 1;
+            res.rel_resid = std::sqrt(rr0 / bb);
+            return res;
+        }
+    }
+    const d2* r_start = guess ? r64 : phi;
     CGVecs v;
     float* norms = (float*)c.s_norms.get(sizeof(float) * 3 * (size_t)g.Vh);
     if (PX == P64) {
-        spinor_copy(c, g, phi, r64);
+        if (!guess) spinor_copy(c, g, phi, r64);
         v.x = sp(X);
         v.r = sp(r64);
         v.p = sp(c.cg_p.get(n64));
         v.q = sp(c.cg_q.get(n64));
         v.t = sp(c.s_t.get(n64));
-        spinor_copy(c, g, phi, (d2*)v.p.v);
+        spinor_copy(c, g, r_start, (d2*)v.p.v);
     } else {
         size_t nx = sizeof(float) * 24 * (size_t)g.Vh;
         size_t np = PP == P32 ? nx : sizeof(_Float16) * 24 * (size_t)g.Vh;
@@ -1104,14 +1118,14 @@ static CGResult cg_run(Ctx& c, const FermionOp& op64, const FermionOp& ops, cons
         v.q = sp(c.s_q.get(np), norms + g.Vh);
         v.t = sp(c.s_t.get(np), norms + 2 * (size_t)g.Vh);
         zero_spinor(c, g, v.x.v, P32);
-        convert<P64, PX>(c, g, sp(phi), v.r);
-        convert<P64, PP>(c, g, sp(phi), v.p);
+        convert<P64, PX>(c, g, sp(r_start), v.r);
+        convert<P64, PP>(c, g, sp(r_start), v.p);
     }
     partial_buf(c, g);  // allocate before any capture
     CGState* st = dev_state(c);
     CGState h{};
-    h.rr[0] = bb;
-    h.rr_stop = (PX == P64) ? target : std::max(c.ru_delta * c.ru_delta * bb, target);
+    h.rr[0] = rr0;
+    h.rr_stop = (PX == P64) ? target : std::max(c.ru_delta * c.ru_delta * rr0, target);
     h.beta = 0.0;
     h.stop_at = INT_MAX;
     h.base = 0;
@@ -1386,7 +1400,7 @@ static void download_doubles(Ctx& c, const double* dev, int n) {
 // reliable updates in masked steps.
 template <int PP, int PX>
 static std::vector<CGResult> cg_run_b(Ctx& c, const Batch& B, const FermionOp& op64, const FermionOp& ops,
-                                      const d2* phi, d2* X, double tol, int maxiter) {
+                                      const d2* phi, d2* X, double tol, int maxiter, bool guess) {
     const int nc = B.nc;
     const size_t n64 = sizeof(d2) * 12 * (size_t)B.sites;
     std::vector<CGResult> res(nc, CGResult{0, 0, 0.0, 0});
@@ -1397,19 +1411,45 @@ static std::vector<CGResult> cg_run_b(Ctx& c, const Batch& B, const FermionOp& o
     FGI_LAUNCH_CHECK();
     final_sums_b(c, B, part, GRID_VH, dres);
     download_doubles(c, dres, nc);
-    std::vector<double> bb(c.host_bscal, c.host_bscal + nc), target(nc);
-    zero_doubles(c, (double*)X, 24 * (size_t)B.sites);
+    std::vector<double> bb(c.host_bscal, c.host_bscal + nc), target(nc), rr0(bb);
+    if (!guess) zero_doubles(c, (double*)X, 24 * (size_t)B.sites);
     d2* r64 = (d2*)c.cg_r.get(n64);
+    std::vector<CGState> hs(nc);
+    std::vector<int> done(nc, 0);
+    for (int i = 0; i < nc; i++) {
+        target[i] = tol * tol * bb[i];
+        hs[i] = CGState{};
+        hs[i].act = bb[i] != 0.0;
+    }
+    if (guess) {  // every chain with a nonzero right-hand side starts from its true residual
+        upload_states(c, st, hs);
+        true_residual_b(c, B, op64, phi, X, r64, st, dres);
+        download_doubles(c, dres, nc);
+        bool any_zero = false;
+        for (int i = 0; i < nc; i++) {
+            hs[i].act = bb[i] == 0.0;
+            any_zero = any_zero || bb[i] == 0.0;
+            if (bb[i] == 0.0) continue;
+            rr0[i] = c.host_bscal[i];
+            if (!std::isfinite(rr0[i])) throw Error(-4, "batched CG: non-finite residual of the starting point");
+        }
+        if (any_zero) {  // phi = 0: the solution is 0, whatever the start
+            upload_states(c, st, hs);
+            FGI_B_LAUNCH((k_zero_spinor_b<P64>), B.nblk[GRID_VH]), B.cd, nc, st, sp(X));
+            FGI_LAUNCH_CHECK();
+        }
+    }
     CGVecs v;
     float* norms = (float*)c.s_norms.get(sizeof(float) * 3 * (size_t)B.sites);
+    const d2* r_start = guess ? r64 : phi;
     if (PX == P64) {
-        FGI_HIP(hipMemcpyAsync(r64, phi, n64, hipMemcpyDeviceToDevice, c.stream));
+        if (!guess) FGI_HIP(hipMemcpyAsync(r64, phi, n64, hipMemcpyDeviceToDevice, c.stream));
         v.x = sp(X);
         v.r = sp(r64);
         v.p = sp(c.cg_p.get(n64));
         v.q = sp(c.cg_q.get(n64));
         v.t = sp(c.s_t.get(n64));
-        FGI_HIP(hipMemcpyAsync(v.p.v, phi, n64, hipMemcpyDeviceToDevice, c.stream));
+        FGI_HIP(hipMemcpyAsync(v.p.v, r_start, n64, hipMemcpyDeviceToDevice, c.stream));
     } else {
         size_t nx = sizeof(float) * 24 * (size_t)B.sites;
         size_t np = PP == P32 ? nx : sizeof(_Float16) * 24 * (size_t)B.sites;
@@ -1419,22 +1459,21 @@ static std::vector<CGResult> cg_run_b(Ctx& c, const Batch& B, const FermionOp& o
         v.q = sp(c.s_q.get(np), norms + B.sites);
         v.t = sp(c.s_t.get(np), norms + 2 * (size_t)B.sites);
         zero_doubles(c, (double*)v.x.v, 12 * (size_t)B.sites);
-        FGI_B_LAUNCH((k_convert_b<P64, PX>), B.nblk[GRID_VH]), B.cd, nc, nullptr, sp(phi), v.r);
-        FGI_B_LAUNCH((k_convert_b<P64, PP>), B.nblk[GRID_VH]), B.cd, nc, nullptr, sp(phi), v.p);
+        FGI_B_LAUNCH((k_convert_b<P64, PX>), B.nblk[GRID_VH]), B.cd, nc, nullptr, sp(r_start), v.r);
+        FGI_B_LAUNCH((k_convert_b<P64, PP>), B.nblk[GRID_VH]), B.cd, nc, nullptr, sp(r_start), v.p);
         FGI_LAUNCH_CHECK();
     }
-    std::vector<CGState> hs(nc);
-    std::vector<int> done(nc, 0);
     for (int i = 0; i < nc; i++) {
-        target[i] = tol * tol * bb[i];
         CGState& h = hs[i];
         h = CGState{};
-        h.rr[0] = bb[i];
-        h.rr_stop = (PX == P64) ? target[i] : std::max(c.ru_delta * c.ru_delta * bb[i], target[i]);
-        h.stop_at = bb[i] == 0.0 ? 0 : INT_MAX;
-        if (bb[i] == 0.0) {
+        h.rr[0] = rr0[i];
+        h.rr_stop = (PX == P64) ? target[i] : std::max(c.ru_delta * c.ru_delta * rr0[i], target[i]);
+        const bool zero = bb[i] == 0.0, there = guess && !zero && rr0[i] <= target[i];
+        h.stop_at = (zero || there) ? 0 : INT_MAX;
+        if (zero || there) {
             done[i] = 1;
             res[i].converged = 1;
+            res[i].rel_resid = zero ? 0.0 : std::sqrt(rr0[i] / bb[i]);
         }
     }
     upload_states(c, st, hs);
@@ -1511,7 +1550,7 @@ static std::vector<CGResult> cg_run_b(Ctx& c, const Batch& B, const FermionOp& o
 }
 
 std::vector<CGResult> cg_solve_b(Ctx& c, const Batch& B, const FermionOp& op64, const FermionOp& ops, int sprec,
-                                 const d2* phi, d2* X, double tol, int maxiter) {
+                                 const d2* phi, d2* X, double tol, int maxiter, bool guess) {
     if ((size_t)B.nc > c.host_b_cap) {
         if (c.host_bstates) hipHostFree(c.host_bstates);
         if (c.host_bscal) hipHostFree(c.host_bscal);
@@ -1519,16 +1558,16 @@ std::vector<CGResult> cg_solve_b(Ctx& c, const Batch& B, const FermionOp& op64, 
         FGI_HIP(hipHostMalloc((void**)&c.host_bscal, sizeof(double) * B.nc, hipHostMallocDefault));
         c.host_b_cap = B.nc;
     }
-    if (sprec == P64) return cg_run_b<P64, P64>(c, B, op64, op64, phi, X, tol, maxiter);
-    if (sprec == P32) return cg_run_b<P32, P32>(c, B, op64, ops, phi, X, tol, maxiter);
-    return cg_run_b<P16, P32>(c, B, op64, ops, phi, X, tol, maxiter);
+    if (sprec == P64) return cg_run_b<P64, P64>(c, B, op64, op64, phi, X, tol, maxiter, guess);
+    if (sprec == P32) return cg_run_b<P32, P32>(c, B, op64, ops, phi, X, tol, maxiter, guess);
+    return cg_run_b<P16, P32>(c, B, op64, ops, phi, X, tol, maxiter, guess);
 }
 
 CGResult cg_solve(Ctx& c, const FermionOp& op64, const FermionOp& ops, int sprec, const d2* phi, d2* X, double tol,
-                  int maxiter) {
-    if (sprec == P64) return cg_run<P64, P64>(c, op64, op64, phi, X, tol, maxiter);
-    if (sprec == P32) return cg_run<P32, P32>(c, op64, ops, phi, X, tol, maxiter);
-    return cg_run<P16, P32>(c, op64, ops, phi, X, tol, maxiter);
+                  int maxiter, bool guess) {
+    if (sprec == P64) return cg_run<P64, P64>(c, op64, op64, phi, X, tol, maxiter, guess);
+    if (sprec == P32) return cg_run<P32, P32>(c, op64, ops, phi, X, tol, maxiter, guess);
+    return cg_run<P16, P32>(c, op64, ops, phi, X, tol, maxiter, guess);
 }
 
 }  // namespace fgi

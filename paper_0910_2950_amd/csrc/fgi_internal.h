@@ -125,6 +125,10 @@ struct Ctx {
     int ds_bs = 256;
     int ds_xcd = 1;
     double ru_delta = 0.1;     // reliable-update trigger |r| drop
+    // FG displacement form: the solves of the displaced force start from the
+    // undisplaced solutions (a deterministic function of the stage's links, so
+    // the stage stays reversible); 0 starts them from zero
+    int fg_start = 1;
 };
 
 // A batch of independent chains: their descriptors on the device and the
@@ -226,10 +230,11 @@ struct CGResult {
     double rel_resid;
     int reliable_updates;
 };
-// X = (Mhat^+ Mhat)^-1 phi from a zero start; FP64 op64 for the true residual,
-// sloppy op for the inner iterations (same op for FP64 mode)
+// X = (Mhat^+ Mhat)^-1 phi from a zero start, or (guess) from the X given on
+// entry; FP64 op64 for the true residual, sloppy op for the inner iterations
+// (same op for FP64 mode)
 CGResult cg_solve(Ctx&, const FermionOp& op64, const FermionOp& ops, int sprec, const d2* phi, d2* X,
-                  double tol, int maxiter);
+                  double tol, int maxiter, bool guess = false);
 // phi = Mhat^+ eta
 void pf_heatbath(Ctx&, const FermionOp& op64, const d2* eta, d2* phi);
 // F += c * F_F(X_e) (pseudofermion force given the solution X_e)
@@ -255,7 +260,7 @@ void pf_heatbath_b(Ctx&, const Batch&, const FermionOp& op64, const d2* eta, d2*
 void fermion_force_b(Ctx&, const Batch&, const FermionOp& op64, const d2* Xe, double* F, double coef);
 void pf_density_b(Ctx&, const Batch&, const d2* phi, const d2* X, const d2* eta, double* partial, double* out);
 std::vector<CGResult> cg_solve_b(Ctx&, const Batch&, const FermionOp& op64, const FermionOp& ops, int sprec,
-                                 const d2* phi, d2* X, double tol, int maxiter);
+                                 const d2* phi, d2* X, double tol, int maxiter, bool guess = false);
 
 
 }  // namespace fgi

@@ -159,6 +159,36 @@ def test_fg_exact_fermions_reversible_and_same_solve_count(orc):
     assert abs(dH + dH2) < 1e-9
 
 
+def test_cg_from_a_start(orc):
+    """CG from a starting point reaches the same solution; from the solution
+    itself it takes no iteration; from a nearby point, fewer iterations."""
+    dims, kappa = (4, 4, 4, 4), 0.155
+    U, _, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 50, fermions=True)
+    phi = orc.pf_heatbath(dims, kappa, U, eta)
+    X, it0, _ = orc.cg(dims, kappa, U, phi, tol=1e-12)
+    X1, it1, rel1 = orc.cg_from(dims, kappa, U, phi, X, tol=1e-12)
+    assert it1 == 0 and np.array_equal(X1, X) and rel1 <= 1e-12
+    Xn = X * (1 + 1e-3 * synth.rng(51).standard_normal(X.shape))
+    X2, it2, rel2 = orc.cg_from(dims, kappa, U, phi, Xn, tol=1e-12)
+    assert rel2 <= 1e-12 and 0 < it2 < it0
+    assert np.max(np.abs(X2 - X)) < 1e-9 * np.max(np.abs(X))
+
+
+def test_fg_start_changes_results_only_at_solver_tolerance(orc):
+    """The displaced force's solve started from the undisplaced solution: same
+    trajectory to the solver tolerance, fewer CG iterations, same solves."""
+    dims = (4, 4, 2, 2)
+    U0, P0, eta = start(dims, synth.SEED_BASE + 52, True)
+    out = {}
+    for fs in (False, True):
+        out[fs] = orc.trajectory(dims, 5.6, table("FG"), 1.0, 4, U0, P0, kappa=0.155, eta=eta, tol=1e-12,
+                                 fg_start=fs)
+    (Ua, Pa, da, sa, _), (Ub, Pb, db, sb, _) = out[False], out[True]
+    assert np.max(np.abs(Ua - Ub)) < 1e-9 and np.max(np.abs(Pa - Pb)) < 1e-8 * np.max(np.abs(Pa))
+    assert abs(da - db) < 1e-8
+    assert sa["solves"] == sb["solves"] and sb["cg_iters"] < sa["cg_iters"]
+
+
 @pytest.mark.parametrize("name,solves", [("PQP", lambda n: n + 1), ("PQPQP", lambda n: 2 * n + 1),
                                          ("FG", lambda n: 3 * n + 1),
                                          ("CAMPOSTRINI", lambda n: 3 * n)])
