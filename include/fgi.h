@@ -144,13 +144,14 @@ const char* fgi_last_error(void);
 /* Tuning/diagnostic options: "cg_batch" (CG iterations launched between host
  * polls; each batch is one replay of a captured HIP graph), "dslash_block"
  * (64, 128 or 256 even sites per block of the Dslash-shaped kernels),
- * "xcd_order" (1: XCD-aware block order, 0: linear), "fg_start" (1, the default: in the displacement form of an FG stage the
- * solves of the displaced force start from the solutions at the undisplaced
- * links, which are a function of the stage's links alone, so the stage stays
- * reversible; 0: from zero), "graphs" (0: launch
- * the batch kernels one by one instead), "ru_delta" (reliable-update residual
- * drop), "profile" (1: after every CG solve, time 16 back-to-back launches of
- * the bare Dslash hop on the solve's operator with HIP events), "profile_prec"
+ * "xcd_order" (1: XCD-aware block order, 0: linear; also the block order of
+ * the force kernels), "fg_start" (1, the default: in the displacement form of
+ * an FG stage the solves of the displaced force start from the solutions at
+ * the undisplaced links, which are a function of the stage's links alone, so
+ * the stage stays reversible; 0: from zero), "graphs" (0: launch the batch
+ * kernels one by one instead), "ru_delta" (reliable-update residual drop),
+ * "profile" (1: after every CG solve, time 16 back-to-back launches of the
+ * bare Dslash hop on the solve's operator with HIP events), "profile_prec"
  * (profile only solves whose inner precision is 0 FP64 / 1 FP32 / 2 FP16;
  * -1 all), "profile_reset".  An unknown name is FGI_EINVAL. */
 int fgi_set_option(fgi_ctx* ctx, const char* name, double value);
