@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 96-chain batched workload")
     ap.add_argument("--batched-steps", type=int, default=2, help="timed batched trajectories")
     ap.add_argument("--no-hasenbusch", action="store_true", help="skip the 32^3x64 Hasenbusch MD-step leg")
+    ap.add_argument("--fg-start", type=int, default=1, choices=[0, 1],
+                    help="1: the displaced force's solve of an FG stage starts from the undisplaced solution")
     ap.add_argument("--exact-steps", type=int, default=2,
                     help="trajectories of the exact force-gradient form on the first timed inputs (0: skip)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -124,6 +126,7 @@ class Runner:
         self.ctx = fgi.Context(0)
         self.ctx.set_option("cg_batch", args.cg_batch)
         self.ctx.set_option("graphs", args.graphs)
+        self.ctx.set_option("fg_start", args.fg_start)
 
     def action(self, prec, recon=18):
         return self.fgi.Action(beta=self.args.beta, kappa=self.args.kappa, cg_tol=self.args.tol,
@@ -547,9 +550,12 @@ def main():
                scaling="weak", vs_baseline=None, dtype="f32 arithmetic, f16 storage, f64 reliable updates/"
                "Hamiltonian" if args.prec == "mp16" else args.prec, data="synthetic",
                config=dict(workload="Nf=2 Wilson %s beta=%.2f kappa=%.4f, thermalised by %d FP64 HMC "
-                                    "trajectories from a seeded hot start; FG (%s, displacement form) at n=%d, "
+                                    "trajectories from a seeded hot start; FG (%s, displacement form%s) at n=%d, "
                                     "tau=1, CG tol %.0e" % ("x".join(map(str, R.dims)), args.beta, args.kappa,
-                                                            args.therm, args.prec, args.n_fg, args.tol),
+                                                            args.therm, args.prec,
+                                                            ", displaced solve started from the undisplaced "
+                                                            "solution" if args.fg_start else "", args.n_fg,
+                                                            args.tol),
                            lattice=list(R.dims), integrator="FG", n_steps=args.n_fg, plaquette=round(plaq, 6)),
                fg=fg, fg_exact=exact, lf_fp64=lf,
                speedup_vs_lf_fp64=(round(lf["s_per_traj"] / s_per_traj, 3) if lf else None),
