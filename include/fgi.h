@@ -46,6 +46,7 @@
 #ifndef FGI_H
 #define FGI_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -282,6 +283,25 @@ int fgi_integrator_builtin(int which, double alpha, fgi_integrator* out);
 int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const fgi_integrator* integ, double tau,
                    int nsteps, void* U, void* P, const void* eta1, const void* eta2, int pf_is_phi, double* dH,
                    fgi_stats* st, void* stream);
+
+/* ------------------------------------------- internal layouts */
+/* The internal (structure-of-arrays, checkerboard) layout of a field kind,
+ * for callers that keep fields packed between calls: bytes to allocate
+ * (device memory, 256-byte aligned from hipMalloc suffices); pack converts
+ * the user layout into it, unpack back (bitwise round trip).  Asynchronous
+ * on the stream.  FGI_EINVAL for an unknown kind or a null/misaligned pointer. */
+#define FGI_FIELD_LINKS 0   /* complex128 [4][V][3][3] <-> double2 [4][2][9][V/2] */
+#define FGI_FIELD_MOMENTA 1 /* float64 [4][V][8] <-> double [4][2][8][V/2] */
+#define FGI_FIELD_EVEN 2    /* complex128 [V/2][4][3] <-> double2 [12][V/2] */
+int fgi_field_bytes(const fgi_geom* g, int kind, size_t* bytes);
+int fgi_field_pack(fgi_ctx* ctx, const fgi_geom* g, int kind, const void* user, void* internal, void* stream);
+int fgi_field_unpack(fgi_ctx* ctx, const fgi_geom* g, int kind, const void* internal, void* user, void* stream);
+/* fgi_trajectory on packed fields: U, P (updated in place) and eta1, eta2 (or
+ * the pseudofermions with pf_is_phi) in the internal layouts; no packing or
+ * unpacking inside.  Same results as fgi_trajectory, bitwise. */
+int fgi_trajectory_packed(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const fgi_integrator* integ,
+                          double tau, int nsteps, void* U, void* P, const void* eta1, const void* eta2, int pf_is_phi,
+                          double* dH, fgi_stats* st, void* stream);
 
 /* ------------------------------------------- Markov chain (HMC, Section 2) */
 /* The heatbath draws of trajectory `traj` of the chain with this seed, from

@@ -1108,6 +1108,85 @@ extern "C" int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action
     });
 }
 
+extern "C" int fgi_field_bytes(const fgi_geom* gg, int kind, size_t* bytes) {
+    return guarded([&] {
+        if (!gg || !bytes) throw Error(FGI_EINVAL, "null argument");
+        Geom g = make_geom(gg->dims);
+        if (kind == FGI_FIELD_LINKS) *bytes = gauge_bytes(g);
+        else if (kind == FGI_FIELD_MOMENTA) *bytes = mom_bytes(g);
+        else if (kind == FGI_FIELD_EVEN) *bytes = spinor_bytes(g);
+        else throw Error(FGI_EINVAL, "unknown field kind");
+    });
+}
+
+namespace {
+void field_convert(fgi_ctx* ctx, const fgi_geom* gg, int kind, const void* src, void* dst, void* stream, bool pack) {
+    Ctx& c = ctx_of(ctx);
+    if (!gg) throw Error(FGI_EINVAL, "null geometry");
+    Geom g = make_geom(gg->dims);
+    const size_t align = kind == FGI_FIELD_MOMENTA ? 8 : 16;
+    if (kind < FGI_FIELD_LINKS || kind > FGI_FIELD_EVEN) throw Error(FGI_EINVAL, "unknown field kind");
+    need(src, "source", align);
+    need(dst, "destination", align);
+    StreamScope ss(c, stream);
+    if (kind == FGI_FIELD_LINKS) {
+        if (pack) pack_gauge(c, g, src, (d2*)dst);
+        else unpack_gauge(c, g, (const d2*)src, dst);
+    } else if (kind == FGI_FIELD_MOMENTA) {
+        if (pack) pack_mom(c, g, (const double*)src, (double*)dst);
+        else unpack_mom(c, g, (const double*)src, (double*)dst);
+    } else {
+        if (pack) pack_even_spinor(c, g, src, (d2*)dst);
+        else unpack_even_spinor(c, g, (const d2*)src, dst);
+    }
+}
+}  // namespace
+
+extern "C" int fgi_field_pack(fgi_ctx* ctx, const fgi_geom* gg, int kind, const void* user, void* internal,
+                              void* stream) {
+    return guarded([&] { field_convert(ctx, gg, kind, user, internal, stream, true); });
+}
+
+extern "C" int fgi_field_unpack(fgi_ctx* ctx, const fgi_geom* gg, int kind, const void* internal, void* user,
+                                void* stream) {
+    return guarded([&] { field_convert(ctx, gg, kind, internal, user, stream, false); });
+}
+
+extern "C" int fgi_trajectory_packed(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act,
+                                     const fgi_integrator* integ, double tau, int nsteps, void* U, void* P,
+                                     const void* eta1, const void* eta2, int pf_is_phi, double* dH, fgi_stats* st,
+                                     void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg || !dH) throw Error(FGI_EINVAL, "null argument");
+        check_trajectory_args(act, integ, nsteps, tau);
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(P, "P", 8);
+        const bool ferm = act->kappa != 0.0, hasen = act->kappa_hasen != 0.0;
+        if (ferm) need(eta1, "eta1", 16);
+        if (hasen) need(eta2, "eta2", 16);
+        auto t0 = std::chrono::steady_clock::now();
+        StreamScope ss(c, stream);
+        Fields f(c, g, *act);
+        f.st = st;
+        f.U = (d2*)U;
+        trajectory_buffers(c, g, f);
+        f.P = (double*)P;
+        if (ferm && pf_is_phi) {  // the pseudofermions are only read
+            f.phi[0] = (d2*)eta1;
+            if (hasen) f.phi[1] = (d2*)eta2;
+        }
+        const double dh = trajectory_packed(f, *integ, tau, nsteps, pf_is_phi ? nullptr : (const d2*)eta1,
+                                            pf_is_phi ? nullptr : (const d2*)eta2, pf_is_phi != 0);
+        FGI_HIP(hipStreamSynchronize(c.stream));
+        *dH = dh;
+        if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (!std::isfinite(dh)) throw Error(FGI_ENONFINITE, "dH is not finite");
+        if (f.nonconv) throw Error(FGI_ENOCONV, "a CG solve reached cg_maxiter");
+    });
+}
+
 extern "C" int fgi_refresh(fgi_ctx* ctx, const fgi_geom* gg, uint64_t seed, uint64_t traj, void* P, void* eta1,
                            void* eta2, void* stream) {
     return guarded([&] {

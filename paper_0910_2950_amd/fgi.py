@@ -121,6 +121,11 @@ SIGNATURES = {
     "fgi_trajectory": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _P(fgi_integrator), _d, _i, _vp, _vp, _vp, _vp,
                             _i, _P(_d), _P(fgi_stats), _vp]),
     "fgi_refresh": (_i, [_vp, _P(fgi_geom), ctypes.c_uint64, ctypes.c_uint64, _vp, _vp, _vp, _vp]),
+    "fgi_field_bytes": (_i, [_P(fgi_geom), _i, _P(ctypes.c_size_t)]),
+    "fgi_field_pack": (_i, [_vp, _P(fgi_geom), _i, _vp, _vp, _vp]),
+    "fgi_field_unpack": (_i, [_vp, _P(fgi_geom), _i, _vp, _vp, _vp]),
+    "fgi_trajectory_packed": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _P(fgi_integrator), _d, _i, _vp, _vp, _vp,
+                                   _vp, _i, _P(_d), _P(fgi_stats), _vp]),
     "fgi_philox4x32_10": (_i, [_P(ctypes.c_uint32), _P(ctypes.c_uint32), _P(ctypes.c_uint32)]),
     "fgi_hmc_run": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _P(fgi_integrator), _d, _i, _vp, ctypes.c_uint64,
                          ctypes.c_uint64, _i, _i, _P(_d), _P(_i), _P(_d), _P(fgi_stats), _vp]),
@@ -421,6 +426,54 @@ class Context:
                                          _ptr(P, torch.float64, sp, "P"), _ptr(eta1, torch.complex128, se, "eta1"),
                                          _ptr(eta2, torch.complex128, se, "eta2"), int(bool(pf_is_phi)),
                                          ctypes.byref(dH), ctypes.byref(st), _stream()),
+                    (FGI_ENOCONV,) if allow_noconv else ())
+        d = st.as_dict()
+        d["status"] = rc
+        return dH.value, d
+
+    # ---- internal layouts
+    FIELD_KINDS = {"links": 0, "momenta": 1, "even": 2}
+
+    def field_bytes(self, dims, kind):
+        n = ctypes.c_size_t()
+        _check(lib().fgi_field_bytes(_geom(dims), self.FIELD_KINDS[kind], ctypes.byref(n)))
+        return n.value
+
+    def _user_spec(self, dims, kind):
+        su, sp, se = self._shapes(dims)
+        return {"links": (su, torch.complex128), "momenta": (sp, torch.float64), "even": (se, torch.complex128)}[kind]
+
+    def field_pack(self, dims, kind, user):
+        """The internal layout of a user-layout field (a uint8 device buffer)."""
+        shape, dtype = self._user_spec(dims, kind)
+        out = torch.empty(self.field_bytes(dims, kind), dtype=torch.uint8, device=user.device)
+        _check(lib().fgi_field_pack(self.h, _geom(dims), self.FIELD_KINDS[kind], _ptr(user, dtype, shape, kind),
+                                    ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def field_unpack(self, dims, kind, internal):
+        shape, dtype = self._user_spec(dims, kind)
+        if internal.numel() != self.field_bytes(dims, kind) or internal.dtype != torch.uint8:
+            raise FgiError(FGI_EINVAL, "internal buffer of the wrong size or dtype")
+        out = torch.empty(shape, dtype=dtype, device=internal.device)
+        _check(lib().fgi_field_unpack(self.h, _geom(dims), self.FIELD_KINDS[kind],
+                                      ctypes.c_void_p(internal.data_ptr()), _ptr(out, dtype, shape, kind), _stream()))
+        return out
+
+    def trajectory_packed(self, dims, act, integ, tau, nsteps, U, P, eta1=None, eta2=None, pf_is_phi=False,
+                          allow_noconv=False):
+        """fgi_trajectory on internal-layout buffers (from field_pack); U, P updated in place."""
+        if isinstance(integ, str):
+            integ = integrator_builtin(integ)
+        for t, k in ((U, "links"), (P, "momenta"), (eta1, "even"), (eta2, "even")):
+            if t is not None and (t.dtype != torch.uint8 or t.numel() != self.field_bytes(dims, k)):
+                raise FgiError(FGI_EINVAL, "internal %s buffer of the wrong size or dtype" % k)
+        vp = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        dH = ctypes.c_double()
+        st = fgi_stats()
+        rc = _check(lib().fgi_trajectory_packed(self.h, _geom(dims), ctypes.byref(act.c()), ctypes.byref(integ),
+                                                float(tau), int(nsteps), vp(U), vp(P), vp(eta1), vp(eta2),
+                                                int(bool(pf_is_phi)), ctypes.byref(dH), ctypes.byref(st), _stream()),
                     (FGI_ENOCONV,) if allow_noconv else ())
         d = st.as_dict()
         d["status"] = rc

@@ -106,3 +106,42 @@ def test_chain_argument_checks(ctx):
     assert e.value.code == fgi.FGI_EINVAL
     dH, acc, plaq, _ = ctx.hmc_run(dims, Action(beta=6.0), "FG", 1.0, 2, U, 1, 0, 0)
     assert dH == [] and acc == []
+
+
+# ------------------------------------------------ packed fields -------------
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 4, 6)])
+def test_field_pack_round_trip(ctx, dims):
+    U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 72, fermions=True)
+    V = synth.volume(dims)
+    assert ctx.field_bytes(dims, "links") == 4 * V * 9 * 16
+    assert ctx.field_bytes(dims, "momenta") == 4 * V * 8 * 8
+    assert ctx.field_bytes(dims, "even") == V // 2 * 12 * 16
+    for kind, a in (("links", U0), ("momenta", P0), ("even", eta)):
+        t = dev(a)
+        back = ctx.field_unpack(dims, kind, ctx.field_pack(dims, kind, t))
+        assert torch.equal(back, t), kind
+    # the internal links are the SoA checkerboard layout: link (mu, parity p, site s), entry k
+    Ui = ctx.field_pack(dims, "links", dev(U0)).view(torch.float64).view(4, 2, 9, V // 2, 2)
+    for i in (7, V - 3):
+        c = np.unravel_index(i, dims[::-1])[::-1]
+        p, s = int(sum(c)) % 2, i // 2
+        assert np.array_equal(host(Ui[2, p, :, s, 0]), U0[2, i].ravel().real)
+        assert np.array_equal(host(Ui[2, p, :, s, 1]), U0[2, i].ravel().imag)
+
+
+@pytest.mark.parametrize("pf_is_phi", [False, True])
+def test_trajectory_packed_equals_trajectory(ctx, pf_is_phi):
+    dims = (6, 4, 4, 6)
+    U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 73, fermions=True)
+    act = Action(beta=5.6, kappa=0.155, cg_tol=1e-10, prec="mp16", link_recon=12)
+    U, P = dev(U0), dev(P0)
+    dH, st = ctx.trajectory(dims, act, "FG", 1.0, 3, U, P, dev(eta), pf_is_phi=pf_is_phi)
+    Ui, Pi = ctx.field_pack(dims, "links", dev(U0)), ctx.field_pack(dims, "momenta", dev(P0))
+    ei = ctx.field_pack(dims, "even", dev(eta))
+    dH2, st2 = ctx.trajectory_packed(dims, act, "FG", 1.0, 3, Ui, Pi, ei, pf_is_phi=pf_is_phi)
+    assert dH2 == dH and st2["cg_iters"] == st["cg_iters"]
+    assert torch.equal(ctx.field_unpack(dims, "links", Ui), U)
+    assert torch.equal(ctx.field_unpack(dims, "momenta", Pi), P)
+    with pytest.raises(fgi.FgiError):
+        ctx.trajectory_packed(dims, act, "FG", 1.0, 3, Ui[:-16], Pi, ei)
