@@ -75,6 +75,9 @@ def parse():
                     help="1: the displaced force's solve of an FG stage starts from the undisplaced solution")
     ap.add_argument("--exact-steps", type=int, default=2,
                     help="trajectories of the exact force-gradient form on the first timed inputs (0: skip)")
+    ap.add_argument("--tune-alpha", type=int, default=0, metavar="K",
+                    help="Omelyan alpha from Poisson brackets measured over K trajectories (0: skip)")
+    ap.add_argument("--n-omelyan", type=int, default=38, help="PQPQP step count of the alpha-tuning leg")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default CG schedule (block 256, XCD order, --cg-batch) instead of tuning per leg")
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle CG iterations timed for the CPU baseline")
@@ -355,6 +358,38 @@ def batched_leg(R, prec, nsteps, steps):
                 cg_iters_per_batched_trajectory=float(np.mean(iters)), timed=steps, schedule=tuning)
 
 
+def tune_alpha_leg(R, U_therm, k, n):
+    """Section 3 tuning: {S,{S,T}} and {T,{S,T}} measured on the GPU at both ends
+    of k PQPQP(0.1932) trajectories, the alpha minimising the predicted <dH^2>,
+    and the same k starts rerun at that alpha."""
+    from paper_0910_2950_amd.tuning import predicted_dh2, tune_omelyan_alpha
+    torch, ctx, dims = R.torch, R.ctx, R.dims
+    act = R.action(R.args.prec, 12 if R.args.prec == "mp16" else R.args.recon)
+    inputs = R.fresh_inputs(k, R.args.seed + 300000)
+    dS, dT, dh0 = [], [], []
+    t0 = time.perf_counter()
+    for P0, eta in inputs:
+        phi = ctx.pf_heatbath(dims, act, U_therm, eta)
+        s0, q0 = ctx.poisson_brackets(dims, act, U_therm, P0, phi, h=1e-4)
+        U, P = U_therm.clone(), P0.clone()
+        dH, _ = ctx.trajectory(dims, act, R.fgi.integrator_builtin("PQPQP", 0.1932), 1.0, n, U, P, eta)
+        s1, q1 = ctx.poisson_brackets(dims, act, U, P, phi, h=1e-4)
+        dS.append(s1 - s0)
+        dT.append(q1 - q0)
+        dh0.append(dH)
+    alpha = tune_omelyan_alpha(dS, dT)
+    dh1 = []
+    for P0, eta in inputs:
+        U, P = U_therm.clone(), P0.clone()
+        dH, _ = ctx.trajectory(dims, act, R.fgi.integrator_builtin("PQPQP", alpha), 1.0, n, U, P, eta)
+        dh1.append(dH)
+    return dict(trajectories=k, n=n, alpha_tuned=alpha,
+                predicted_dH2={"0.1932": predicted_dh2(0.1932, dS, dT, 1.0 / n),
+                               "tuned": predicted_dh2(alpha, dS, dT, 1.0 / n)},
+                measured_dH2={"0.1932": float(np.mean(np.square(dh0))), "tuned": float(np.mean(np.square(dh1)))},
+                dH={"0.1932": dh0, "tuned": dh1}, seconds=time.perf_counter() - t0)
+
+
 def summarise(recs):
     dh = np.array([r["dH"] for r in recs])
     return dict(mean_dH=float(dh.mean()), mean_dH2=float((dh ** 2).mean()),
@@ -531,6 +566,14 @@ def main():
         log("Hasenbusch 32^3x64: %.2f s per outer step, %d solves, %d CG iterations (max %d per solve), dH=%+.3e, "
             "Dslash %.1f GB/s" % (hasen["s_per_outer_step"], hasen["solves"], hasen["cg_iters"],
                                   hasen["cg_iters_max"], hasen["dH"], hasen["dslash_achieved_GBs"] or 0))
+    alpha_leg = None
+    if args.tune_alpha > 0:
+        R.apply(tune_fg)
+        alpha_leg = tune_alpha_leg(R, U, args.tune_alpha, args.n_omelyan)
+        log("alpha tuning (PQPQP n=%d, %d trajectories): alpha %.4f, predicted <dH^2> %.3e -> %.3e, measured "
+            "%.3e -> %.3e" % (args.n_omelyan, args.tune_alpha, alpha_leg["alpha_tuned"],
+                              alpha_leg["predicted_dH2"]["0.1932"], alpha_leg["predicted_dH2"]["tuned"],
+                              alpha_leg["measured_dH2"]["0.1932"], alpha_leg["measured_dH2"]["tuned"]))
     batched = None
     if not args.no_batched:
         batched = batched_leg(R, args.prec, 8, args.batched_steps)
@@ -560,6 +603,7 @@ def main():
                fg=fg, fg_exact=exact, lf_fp64=lf,
                speedup_vs_lf_fp64=(round(lf["s_per_traj"] / s_per_traj, 3) if lf else None),
                roofline=roof, roofline_32x32x32x64=large, hasenbusch_32x32x32x64=hasen, batched=batched,
+               alpha_tuning=alpha_leg,
                cpu_baseline=cpu)
     print(json.dumps(out), flush=True)
 

@@ -211,3 +211,47 @@ def test_wrong_fg_factor_fails(start):
         raw.append(abs(ham(q, p) - ham(q0, p0)))
     r = [raw[i] / raw[i + 1] for i in range(2)]
     assert r[-1] < 6, (raw, r)  # only second order
+
+
+# ------------------------------------------------- bracket tuning (Sec. 3) --
+
+def test_tuned_alpha_minimises_measured_dh2():
+    """alpha from measured bracket changes (the dt^2 shadow terms of PQPQP)
+    against brute force: the alpha that minimises the mean dH^2 of actual
+    PQPQP(alpha) trajectories over an ensemble of starts.  They agree to
+    O(dt^2), and the tuned alpha beats the Table 1 default where the
+    ensemble's brackets favour another value."""
+    from paper_0910_2950_amd.tuning import tune_omelyan_alpha, predicted_dh2, pqpqp_dt2_coeffs
+    g = np.random.Generator(np.random.PCG64(0x09102950 + 7))
+    starts = [(0.8 * g.standard_normal(N), g.standard_normal(N)) for _ in range(48)]
+    n = 24
+    dS, dT = [], []
+    for q0, p0 in starts:
+        q1, p1 = integrate(q0, p0, table("PQPQP", 0.1932), 1.0, n)
+        b0, b1 = brackets(q0, p0), brackets(q1, p1)
+        dS.append(b1["SST"] - b0["SST"])
+        dT.append(b1["TST"] - b0["TST"])
+    alpha = tune_omelyan_alpha(dS, dT)
+    grid = np.linspace(0.12, 0.26, 57)
+    meas = []
+    for al in grid:
+        d = [ham(*integrate(q0, p0, table("PQPQP", al), 1.0, n)) - ham(q0, p0) for q0, p0 in starts]
+        meas.append(np.mean(np.square(d)))
+    k = int(np.argmin(meas))
+    c = np.polyfit(grid[k - 3:k + 4], meas[k - 3:k + 4], 2)
+    alpha_bf = -c[1] / (2 * c[0])
+    assert abs(alpha - alpha_bf) < 0.01, (alpha, alpha_bf)
+    # the prediction itself tracks the measured <dH^2> near the minimum
+    pred = predicted_dh2(alpha, dS, dT, 1.0 / n)
+    assert 0.5 < pred / np.interp(alpha, grid, meas) < 2.0
+    # consistency of the coefficient helper with Table 1's special values
+    assert abs(pqpqp_dt2_coeffs(1 / 6)[1]) < 1e-16
+
+
+def test_tune_alpha_closed_cases():
+    """dTST = 0 leaves only a(alpha): the minimum is its root (1 - 1/sqrt3)/2;
+    dSST = 0 leaves b(alpha): the minimum is 1/6."""
+    from paper_0910_2950_amd.tuning import tune_omelyan_alpha
+    r = np.random.Generator(np.random.PCG64(3)).standard_normal(20)
+    assert abs(tune_omelyan_alpha(r, 0 * r) - 0.5 * (1 - 1 / np.sqrt(3))) < 1e-9
+    assert abs(tune_omelyan_alpha(0 * r, r) - 1 / 6) < 1e-9
