@@ -328,8 +328,10 @@ int fgi_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out);
  * plaq[k] = ReTr U_P / 3 of the chain after trajectory k (each may be NULL)
  * are written for k < ntraj.  The chain's state is U and the next index, so
  * a run of n then m trajectories gives the same bits as one run of n + m.
- * traj0 + ntraj <= 2^32.  FGI_ENOCONV (after the last trajectory) when a solve
- * hit cg_maxiter, FGI_ENONFINITE on a non-finite dH.  Synchronises the stream. */
+ * traj0 + ntraj <= 2^32.  FGI_ENOCONV (after the last trajectory, U written)
+ * when a solve hit cg_maxiter; FGI_ENONFINITE on a non-finite dH: the run
+ * stops there and U is left as it was before the call (the outputs of the
+ * finished trajectories are written).  Synchronises the stream. */
 int fgi_hmc_run(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const fgi_integrator* integ, double tau,
                 int nsteps, void* U, uint64_t seed, uint64_t traj0, int ntraj, int metropolis, double* dH,
                 int* accepted, double* plaq, fgi_stats* st, void* stream);

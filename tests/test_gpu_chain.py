@@ -145,3 +145,32 @@ def test_trajectory_packed_equals_trajectory(ctx, pf_is_phi):
     assert torch.equal(ctx.field_unpack(dims, "momenta", Pi), P)
     with pytest.raises(fgi.FgiError):
         ctx.trajectory_packed(dims, act, "FG", 1.0, 3, Ui[:-16], Pi, ei)
+
+
+def test_hasenbusch_chain_matches_composed_oracle(ctx, orc):
+    """A Hasenbusch chain on nested FG scales (noise streams 1 and 2) against
+    the oracle's pinned pieces composed trajectory by trajectory: its draws,
+    nested trajectory, Metropolis uniform and reunitarisation."""
+    dims = (4, 4, 2, 2)
+    K, K2, beta, seed = 0.155, 0.140, 5.6, 41
+    FG = [("P", 1 / 6, 0.0), ("Q", 0.5, 0.0), ("G", 2 / 3, 1 / 72), ("Q", 0.5, 0.0), ("P", 1 / 6, 0.0)]
+    levels = [(FG, 4, 1), (FG, 2, 2), (FG, 1, 2)]
+    U0, _, _, _ = synth.hot_start(dims, synth.SEED_BASE + 74, fermions=False)
+    act = Action(beta=beta, kappa=K, kappa_hasen=K2, cg_tol=1e-14)
+    U = dev(U0)
+    dH, acc, plaq, st = ctx.hmc_run(dims, act, fgi.integrator_from_levels(levels), 1.0, 2, U, seed, 5, 3)
+    Uo = U0.copy()
+    for k in range(3):
+        t = 5 + k
+        P, e1, e2 = orc.refresh(dims, seed, t, eta2=True)
+        U1, _, d, _, status = orc.trajectory_nested(dims, beta, levels, 1.0, 2, Uo, P, kappa=K, kappa2=K2,
+                                                    eta1=e1, eta2=e2)
+        assert status == 0 and abs(d - dH[k]) < 1e-9
+        u = orc.metropolis_uniform(seed, t)
+        assert abs(u - np.exp(-d)) > 1e-6
+        assert acc[k] == (u < np.exp(-d))
+        if acc[k]:
+            Uo = U1
+        Uo = orc.reunitarize(dims, Uo)
+        assert abs(plaq[k] - orc.plaquette(dims, Uo)) < 1e-12
+    assert relmax(host(U), Uo) < 1e-11
