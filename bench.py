@@ -248,9 +248,10 @@ def dslash_roofline_large(R, U_therm, prec, recon):
     bps = DSLASH_BYTES[(prec, recon)]
     avg_s = ms / 1e3 / launches
     achieved = sites / launches * bps / avg_s / 1e9
+    traffic = read_traffic("%s/%d" % (prec, recon), "x".join(map(str, dims_b)))
     return dict(lattice=list(dims_b), bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4),
-                traffic=read_traffic("%s/%d" % (prec, recon), "x".join(map(str, dims_b))),
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                traffic_GBs=round(traffic / avg_s / 1e9, 1) if traffic else None,
                 avg_launch_us=round(avg_s * 1e6, 3), launches_timed=launches,
                 algorithmic_bytes_per_launch=sites / launches * bps,
                 kernel="bare even-odd Dslash hop t = D_oe g5 q (%s/%d), %d output sites per launch, on the "
@@ -398,7 +399,54 @@ def summarise(recs):
                 solves_per_traj=float(np.mean([r["solves"] for r in recs])),
                 cg_iters_per_traj=float(np.mean([r["cg_iters"] for r in recs])),
                 cg_iters_max=int(max(r["cg_iters_max"] for r in recs)),
-                max_rel_resid=float(max(r["max_rel_resid"] for r in recs)))
+                max_rel_resid=float(max(r["max_rel_resid"] for r in recs)),
+                reliable_updates_per_traj=float(np.mean([r["reliable_updates"] for r in recs])),
+                force_evals_per_traj=float(np.mean([r["force_evals"] for r in recs])))
+
+
+# Compulsory bytes per unit of work (each input read once, each output written
+# once), for the whole-trajectory roofline: one CG iteration per even site for
+# each inner precision (four hops plus the vectors of k_cg_p, M_CGQ and M_CGX),
+# one reliable update per even site (the FP64 residual phi - Mhat^+ Mhat X:
+# four FP64 hops plus its vectors, and the FP32 accumulator fold, conversion
+# and clear), one force evaluation (fermion force per site plus its four FP64
+# hops per even site, gauge force per link) and one link update per link.
+def cg_iteration_bytes(prec, recon):
+    hop = DSLASH_BYTES[(prec, recon)]
+    if prec == "fp64":
+        vec, vx = 192, 192
+    elif prec == "mp32":
+        vec, vx = 96, 96
+    else:
+        vec, vx = 52, 96
+    # k_cg_p: r in, p in/out; M_CGQ: p in, q out; M_CGX: q, p in, x and r in/out
+    return 4 * hop + (vx + 2 * vec) + 2 * vec + (2 * vec + 4 * vx)
+
+
+RU_BYTES = 4 * DSLASH_BYTES[("fp64", 18)] + 3 * 192 + (96 + 2 * 192) + (192 + 96) + 96
+FERMION_FORCE_SITE_BYTES, FP64_HOP_BYTES = 1472, DSLASH_BYTES[("fp64", 18)]
+GAUGE_FORCE_LINK_BYTES, LINK_UPDATE_BYTES = 272, 352
+
+
+def trajectory_roofline(summary, dims, prec, recon, link_updates, fermions, seconds):
+    """t_roof = compulsory bytes of the trajectory (from its own counters) / 8 TB/s,
+    and its ratio to the measured time."""
+    V = int(np.prod(dims))
+    Vh = V // 2
+    it = summary["cg_iters_per_traj"] * Vh * cg_iteration_bytes(prec, recon)
+    ru = summary["reliable_updates_per_traj"] * Vh * RU_BYTES
+    nf = summary["force_evals_per_traj"]
+    force = nf * 4 * V * GAUGE_FORCE_LINK_BYTES
+    if fermions:
+        force += nf * (V * FERMION_FORCE_SITE_BYTES + 4 * Vh * FP64_HOP_BYTES)
+    upd = link_updates * 4 * V * (LINK_UPDATE_BYTES + (24 if prec == "mp16" else 48 if prec == "mp32" else 0))
+    total = it + ru + force + upd
+    t_roof = total / (HBM_PEAK_GBS * 1e9)
+    return dict(t_roof_ms=round(t_roof * 1e3, 2), t_measured_ms=round(seconds * 1e3, 2),
+                frac=round(t_roof / seconds, 4), bytes=dict(cg_iterations=it, reliable_updates=ru,
+                                                             force_evaluations=force, link_updates=upd,
+                                                             total=total),
+                cg_iteration_bytes_per_even_site=cg_iteration_bytes(prec, recon))
 
 
 def cpu_baseline(args, dims, iters_per_traj, force_evals_per_traj, links_updates_per_traj):
@@ -506,6 +554,10 @@ def main():
     fg = summarise(recs)
     fg["schedule"] = tune_fg
     s_per_traj = sec / args.steps
+    fg["trajectory_roofline"] = trajectory_roofline(fg, R.dims, args.prec, 12 if args.prec == "mp16" else args.recon,
+                                                    3 * args.n_fg, True, s_per_traj)
+    log("FG trajectory roofline: %.1f ms of compulsory HBM traffic at 8 TB/s against %.1f ms measured (%.1f%%)" %
+        (fg["trajectory_roofline"]["t_roof_ms"], s_per_traj * 1e3, 100 * fg["trajectory_roofline"]["frac"]))
     log("FG-%s n=%d: %.4f s/traj  <dH^2>=%.4e acc=%.3f solves=%.1f iters=%.0f" %
         (args.prec, args.n_fg, s_per_traj, fg["mean_dH2"], fg["acceptance"], fg["solves_per_traj"],
          fg["cg_iters_per_traj"]))
@@ -533,6 +585,7 @@ def main():
         recs_lf, sec_lf, _ = R.run_leg(U, R.action("fp64"), "PQP", args.n_lf, lf_inputs)
         lf = summarise(recs_lf)
         lf.update(n=args.n_lf, s_per_traj=sec_lf / args.lf_steps, trajectories=args.lf_steps, schedule=tune_lf)
+        lf["trajectory_roofline"] = trajectory_roofline(lf, R.dims, "fp64", 18, args.n_lf, True, lf["s_per_traj"])
         log("LF-fp64 n=%d: %.4f s/traj  <dH^2>=%.4e acc=%.3f iters=%.0f" %
             (args.n_lf, lf["s_per_traj"], lf["mean_dH2"], lf["acceptance"], lf["cg_iters_per_traj"]))
 
@@ -546,8 +599,10 @@ def main():
         avg_s = ms / 1e3 / launches
         bytes_per_launch = sites / launches * bps
         achieved = bytes_per_launch / avg_s / 1e9
+        traffic = read_traffic(key)
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=read_traffic(key),
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    traffic_GBs=round(traffic / avg_s / 1e9, 1) if traffic else None,
                     kernel="bare even-odd Dslash hop t = D_oe g5 q of the CG (%s storage), %d output sites "
                            "per launch; HIP events around 16 back-to-back launches after every solve" % (key, V // 2),
                     algorithmic_bytes_per_launch=bytes_per_launch, avg_launch_us=round(avg_s * 1e6, 3),
