@@ -25,7 +25,11 @@
  *    of the generator, which cancels in every quantity computed here).
  *  - force F_a = -e_a S (the S-hat flow of Section 2: p' = p + h F),
  *    link flow (T-hat): U' = exp(h P) U.
- *  - gauge action S_G = beta * sum_{x, mu<nu} (1 - Re Tr U_{mu nu}(x) / 3).
+ *  - gauge action S_G = beta * sum_x [c0 sum_{mu<nu} (1 - Re Tr U_{mu nu}(x) / 3)
+ *                                      + c1 sum_{mu!=nu} (1 - Re Tr R_{mu nu}(x) / 3)],
+ *    c0 = 1 - 8 c1, R_{mu nu}(x) the 2x1 rectangle two links along mu and one
+ *    along nu; c1 = 0 is the Wilson action, c1 = -1/12 the tree-level
+ *    Symanzik action of Luscher and Weisz (1985), c1 = -0.331 Iwasaki's.
  *  - Wilson operator M = 1 - kappa D, with
  *      D psi(x) = sum_mu [(1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^+ psi(x-mu)],
  *    DeGrand-Rossi gamma matrices, antiperiodic in t, periodic in space.
@@ -213,23 +217,64 @@ static mat3 plaquette(const int L[4], const cplx *U, long i, int mu, int nu) {
     return m_mul(m_mul(a, b), m_mul(m_dag(c), m_dag(d)));
 }
 
-/* per-site gauge action density h_G(x) = beta sum_{mu<nu} (1 - ReTr U_mn / 3) */
-static void gauge_density(const int L[4], double beta, const cplx *U, double *h) {
+/* Ordered product of the links along a lattice path starting at site i: step
+ * +(d+1) goes forward along d (factor U_d(y), then y -> y + d), step -(d+1)
+ * goes back (y -> y - d, then factor U_d(y)^+).  When Vm is given, *dP is the
+ * derivative of the product under U_l -> exp(t V_l) U_l at t = 0 for every
+ * link l at once (product rule with dU = V U and d(U^+) = -U^+ V). */
+static mat3 path_product(const int L[4], const cplx *U, long i, const int *steps, int n,
+                         const mat3 *Vm, mat3 *dP) {
+    long V = lat_volume(L), y = i;
+    mat3 P = m_unit(), D = m_zero();
+    for (int k = 0; k < n; k++) {
+        int d = abs(steps[k]) - 1;
+        mat3 f, df = m_zero();
+        if (steps[k] > 0) {
+            f = link_get(U, V, d, y);
+            if (Vm) df = m_mul(Vm[(long)d * V + y], f);
+            y = lat_step(L, y, d, +1);
+        } else {
+            y = lat_step(L, y, d, -1);
+            f = m_dag(link_get(U, V, d, y));
+            if (Vm) df = m_scale(m_mul(f, Vm[(long)d * V + y]), -1.0);
+        }
+        if (Vm) D = m_add(m_mul(D, f), m_mul(P, df));
+        P = m_mul(P, f);
+    }
+    if (dP) *dP = D;
+    return P;
+}
+
+/* the 2x1 rectangle R_{mu nu}(x): two steps along mu, one along nu, back */
+static mat3 rectangle(const int L[4], const cplx *U, long i, int mu, int nu) {
+    int m = mu + 1, n = nu + 1;
+    int steps[6] = {m, m, n, -m, -m, -n};
+    return path_product(L, U, i, steps, 6, NULL, NULL);
+}
+
+/* per-site gauge action density
+ * h_G(x) = beta [c0 sum_{mu<nu} (1 - ReTr U_mn / 3) + c1 sum_{mu!=nu} (1 - ReTr R_mn / 3)] */
+static void gauge_density(const int L[4], double beta, double c1, const cplx *U, double *h) {
     long V = lat_volume(L);
+    double c0 = 1.0 - 8.0 * c1;
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < V; i++) {
-        double s = 0;
+        double sp = 0, sr = 0;
         for (int mu = 0; mu < 4; mu++)
             for (int nu = mu + 1; nu < 4; nu++)
-                s += 1.0 - creal(m_trace(plaquette(L, U, i, mu, nu))) / 3.0;
-        h[i] = beta * s;
+                sp += 1.0 - creal(m_trace(plaquette(L, U, i, mu, nu))) / 3.0;
+        if (c1 != 0.0)
+            for (int mu = 0; mu < 4; mu++)
+                for (int nu = 0; nu < 4; nu++)
+                    if (nu != mu) sr += 1.0 - creal(m_trace(rectangle(L, U, i, mu, nu))) / 3.0;
+        h[i] = beta * (c0 * sp + c1 * sr);
     }
 }
 
-double oracle_gauge_action(const int L[4], double beta, const cplx *U) {
+double oracle_gauge_action(const int L[4], double beta, double c1, const cplx *U) {
     long V = lat_volume(L);
     double *h = malloc(sizeof(double) * V), s = 0;
-    gauge_density(L, beta, U, h);
+    gauge_density(L, beta, c1, U, h);
     for (long i = 0; i < V; i++) s += h[i];
     free(h);
     return s;
@@ -238,7 +283,40 @@ double oracle_gauge_action(const int L[4], double beta, const cplx *U) {
 /* average plaquette ReTr U_P / 3 over all 6V plaquettes */
 double oracle_plaquette(const int L[4], const cplx *U) {
     long V = lat_volume(L);
-    return 1.0 - oracle_gauge_action(L, 1.0, U) / (6.0 * V);
+    return 1.0 - oracle_gauge_action(L, 1.0, 0.0, U) / (6.0 * V);
+}
+
+/* Sum of the 18 rectangle staples of link (mu, x): the 5-link paths from
+ * x + mu back to x that close a 2x1 rectangle through U_mu(x).  For each
+ * nu != mu: the rectangle two long along mu with U_mu(x) as its first or
+ * second mu link, on the +nu or the -nu side (4 paths), and the rectangle two
+ * long along nu on either side (2 paths).  Every rectangle of the action that
+ * contains U_mu(x) appears once, so the part of S_G holding U_mu(x) is
+ * -beta c1 / 3 ReTr(U_mu(x) A^R_mu(x)).  With Vm, *dA is the derivative of the
+ * sum along V (path_product). */
+static mat3 rect_staple_sum(const int L[4], const cplx *U, long i, int mu, const mat3 *Vm, mat3 *dA) {
+    long xpm = lat_step(L, i, mu, +1);
+    int m = mu + 1;
+    mat3 A = m_zero(), D = m_zero();
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == mu) continue;
+        int n = nu + 1;
+        const int shapes[6][5] = {
+            {m, n, -m, -m, -n},   /* along mu, +nu side, U_mu(x) first */
+            {n, -m, -m, -n, m},   /* along mu, +nu side, U_mu(x) second */
+            {m, -n, -m, -m, n},   /* along mu, -nu side, first */
+            {-n, -m, -m, n, m},   /* along mu, -nu side, second */
+            {n, n, -m, -n, -n},   /* along nu, +nu side */
+            {-n, -n, -m, n, n},   /* along nu, -nu side */
+        };
+        for (int k = 0; k < 6; k++) {
+            mat3 dP;
+            A = m_add(A, path_product(L, U, xpm, shapes[k], 5, Vm, Vm ? &dP : NULL));
+            if (Vm) D = m_add(D, dP);
+        }
+    }
+    if (dA) *dA = D;
+    return A;
 }
 
 /* sum of the 6 staples attached to link (mu, x):
@@ -262,14 +340,17 @@ static mat3 staple_sum(const int L[4], const cplx *U, long i, int mu) {
     return A;
 }
 
-/* F_a(mu,x) = -e_a S_G = -(beta/6) [TA(U_mu(x) A_mu(x))]_a
+/* F_a(mu,x) = -e_a S_G = -(beta/6) [TA(U_mu(x) (c0 A_mu(x) + c1 A^R_mu(x)))]_a
  * (e_a of -beta/3 ReTr(U A) is -beta/3 ReTr(T^a U A) = +beta/6 [TA(UA)]_a) */
-void oracle_gauge_force(const int L[4], double beta, const cplx *U, double *F) {
+void oracle_gauge_force(const int L[4], double beta, double c1, const cplx *U, double *F) {
     long V = lat_volume(L);
+    double c0 = 1.0 - 8.0 * c1;
 #pragma omp parallel for collapse(2) schedule(static)
     for (int mu = 0; mu < 4; mu++)
         for (long i = 0; i < V; i++) {
-            mat3 W = m_mul(link_get(U, V, mu, i), staple_sum(L, U, i, mu));
+            mat3 A = m_scale(staple_sum(L, U, i, mu), c0);
+            if (c1 != 0.0) A = m_add(A, m_scale(rect_staple_sum(L, U, i, mu, NULL, NULL), c1));
+            mat3 W = m_mul(link_get(U, V, mu, i), A);
             double x[8];
             alg_components(traceless_antiherm(W), x);
             for (int a = 0; a < 8; a++) F[((long)mu * V + i) * 8 + a] = -beta / 6.0 * x[a];
@@ -280,9 +361,11 @@ void oracle_gauge_force(const int L[4], double beta, const cplx *U, double *F) {
  * elements V_l (components v[mu][i][8]):
  *   J_V[F_G](l) = d/dt F_G(exp(t V) U) at t = 0,
  * written out with the product rule on U_mu(x) A_mu(x), using
- * d U_l = V_l U_l and d U_l^+ = -U_l^+ V_l for every link l. */
-void oracle_gauge_force_tangent(const int L[4], double beta, const cplx *U, const double *v,
+ * d U_l = V_l U_l and d U_l^+ = -U_l^+ V_l for every link l (the rectangle
+ * staples through path_product). */
+void oracle_gauge_force_tangent(const int L[4], double beta, double c1, const cplx *U, const double *v,
                                 double *J) {
+    double c0 = 1.0 - 8.0 * c1;
     long V = lat_volume(L);
     mat3 *Vm = malloc(sizeof(mat3) * 4 * V);
     for (long l = 0; l < 4 * V; l++) Vm[l] = alg_from_components(v + l * 8);
@@ -315,6 +398,13 @@ void oracle_gauge_force_tangent(const int L[4], double beta, const cplx *U, cons
                 dA = m_add(dA, m_mul(m_mul(ddd, m_dag(e)), f));
                 dA = m_add(dA, m_mul(m_mul(m_dag(d), ded), f));
                 dA = m_add(dA, m_mul(m_mul(m_dag(d), m_dag(e)), df));
+            }
+            A = m_scale(A, c0);
+            dA = m_scale(dA, c0);
+            if (c1 != 0.0) {
+                mat3 dR;
+                A = m_add(A, m_scale(rect_staple_sum(L, U, i, mu, Vm, &dR), c1));
+                dA = m_add(dA, m_scale(dR, c1));
             }
             mat3 dW = m_add(m_mul(du, A), m_mul(u, dA));
             double x[8];
@@ -848,6 +938,7 @@ typedef struct {
     int cg_maxiter;
     int fermions;    /* 0: pure gauge */
     int fg_exact;    /* G stages: 0 displacement form, 1 exact form */
+    double c1;       /* rectangle coefficient of the gauge action */
 } oracle_action;
 
 typedef struct {
@@ -864,7 +955,7 @@ static void add_solve(oracle_stats *st, const oracle_action *act, int it) {
  * given); the solution X_e is copied to Xout when given */
 static void total_force_from(const int L[4], const oracle_action *act, const cplx *U, const cplx *phi,
                              double *F, oracle_stats *st, cplx *Xout, const cplx *X0) {
-    oracle_gauge_force(L, act->beta, U, F);
+    oracle_gauge_force(L, act->beta, act->c1, U, F);
     if (!act->fermions) return;
     long Vh = lat_volume(L) / 2;
     cplx *X = malloc(sizeof(cplx) * 12 * Vh);
@@ -890,7 +981,7 @@ static void total_force(const int L[4], const oracle_action *act, const cplx *U,
  * X_e = A^-1 phi at U (the fermion part costs one more solve) */
 static void total_force_tangent(const int L[4], const oracle_action *act, const cplx *U, const cplx *Xe,
                                 const double *v, double *J, oracle_stats *st) {
-    oracle_gauge_force_tangent(L, act->beta, U, v, J);
+    oracle_gauge_force_tangent(L, act->beta, act->c1, U, v, J);
     if (!act->fermions) return;
     int it = oracle_fermion_force_tangent_add(L, act->kappa, U, Xe, v, act->cg_tol, act->cg_maxiter, 1.0, J);
     add_solve(st, act, it);
@@ -900,8 +991,8 @@ static void total_force_tangent(const int L[4], const oracle_action *act, const 
  * in oracle_force (two solves with fermions: X, then d_V X) */
 void oracle_force_tangent(const int L[4], double beta, double kappa, int fermions, double cg_tol,
                           int cg_maxiter, const cplx *U, const cplx *phi, const double *v, double *J,
-                          long *stats3) {
-    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 1};
+                          long *stats3, double c1) {
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 1, c1};
     oracle_stats st = {0, 0, 0};
     long V = lat_volume(L), Vh = V / 2;
     cplx *X = fermions ? malloc(sizeof(cplx) * 12 * Vh) : NULL;
@@ -913,8 +1004,8 @@ void oracle_force_tangent(const int L[4], double beta, double kappa, int fermion
 }
 
 void oracle_force(const int L[4], double beta, double kappa, int fermions, double cg_tol,
-                  int cg_maxiter, const cplx *U, const cplx *phi, double *F, long *stats3) {
-    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 0};
+                  int cg_maxiter, const cplx *U, const cplx *phi, double *F, long *stats3, double c1) {
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 0, c1};
     oracle_stats st = {0, 0, 0};
     total_force(L, &act, U, phi, F, &st);
     if (stats3) { stats3[0] = st.solves; stats3[1] = st.cg_iters; stats3[2] = st.cg_fail; }
@@ -946,8 +1037,9 @@ void oracle_force(const int L[4], double beta, double kappa, int fermions, doubl
 int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, double cg_tol,
                       int cg_maxiter, int fg_exact, int nstages, const char *kinds,
                       const double *ws, const double *xis, double tau, int nsteps, cplx *U,
-                      double *P, const cplx *eta, const cplx *phi_in, double *dH, long *stats3, int fg_start) {
-    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, fg_exact};
+                      double *P, const cplx *eta, const cplx *phi_in, double *dH, long *stats3, int fg_start,
+                      double c1) {
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, fg_exact, c1};
     oracle_stats st = {0, 0, 0};
     long V = lat_volume(L), Vh = V / 2;
     double dt = tau / nsteps;
@@ -971,7 +1063,7 @@ int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, d
     double *hf0 = NULL, *hf1 = NULL;
 
     /* start Hamiltonian, per site */
-    gauge_density(L, beta, U, h0);
+    gauge_density(L, beta, c1, U, h0);
     kinetic_density(L, P, tmp);
     for (long i = 0; i < V; i++) h0[i] += tmp[i];
     if (fermions) {
@@ -1015,7 +1107,7 @@ int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, d
         }
     }
 
-    gauge_density(L, beta, U, h1);
+    gauge_density(L, beta, c1, U, h1);
     kinetic_density(L, P, tmp);
     for (long i = 0; i < V; i++) h1[i] += tmp[i];
     double d = 0;
@@ -1048,7 +1140,7 @@ int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, d
 
 typedef struct {
     const int *L;
-    double beta, kappa, kappa2, tol;
+    double beta, c1, kappa, kappa2, tol;
     int maxiter, nlevels;
     const int *nstages, *terms, *nsub;
     const char *const *kinds;
@@ -1074,7 +1166,7 @@ static void terms_force(nested_run *r, const cplx *W, int terms, double *F, int 
     memset(F, 0, sizeof(double) * 4 * V * 8);
     if (terms & TERM_GAUGE) {
         double *g = malloc(sizeof(double) * 4 * V * 8);
-        oracle_gauge_force(L, r->beta, W, g);
+        oracle_gauge_force(L, r->beta, r->c1, W, g);
         for (long k = 0; k < 4 * V * 8; k++) F[k] += g[k];
         free(g);
     }
@@ -1135,7 +1227,7 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
                              int cg_maxiter, int nlevels, const int *nstages, const int *terms, const int *nsub,
                              const char *kinds, const double *ws, const double *xis, double tau, int nsteps,
                              cplx *U, double *P, const cplx *eta1, const cplx *eta2, double *dH, long *stats3,
-                             int fg_start) {
+                             int fg_start, double c1) {
     long V = lat_volume(L), Vh = V / 2;
     const char *kp[8];
     const double *wp[8], *xp[8];
@@ -1144,13 +1236,13 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
         kp[l] = kinds + off; wp[l] = ws + off; xp[l] = xis + off;
         off += nstages[l];
     }
-    nested_run r = {L, beta, kappa, kappa2, cg_tol, cg_maxiter, nlevels, nstages, terms, nsub, kp, wp, xp,
+    nested_run r = {L, beta, c1, kappa, kappa2, cg_tol, cg_maxiter, nlevels, nstages, terms, nsub, kp, wp, xp,
                     NULL, NULL, U, P, {0, 0, 0}, fg_start, NULL, NULL};
     r.X1 = calloc(12 * Vh, sizeof(cplx));
     r.X2 = calloc(12 * Vh, sizeof(cplx));
     cplx *phi1 = NULL, *phi2 = NULL;
     double *h0 = malloc(sizeof(double) * V), *h1 = malloc(sizeof(double) * V), *tmp = malloc(sizeof(double) * V);
-    gauge_density(L, beta, U, h0);
+    gauge_density(L, beta, c1, U, h0);
     kinetic_density(L, P, tmp);
     for (long i = 0; i < V; i++) h0[i] += tmp[i];
     double sf0 = 0.0;
@@ -1167,7 +1259,7 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
     r.phi1 = phi1;
     r.phi2 = phi2;
     run_level(&r, 0, nsteps, tau / nsteps);
-    gauge_density(L, beta, U, h1);
+    gauge_density(L, beta, c1, U, h1);
     kinetic_density(L, P, tmp);
     double d = 0;
     for (long i = 0; i < V; i++) d += (h1[i] + tmp[i]) - h0[i];
@@ -1193,9 +1285,9 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
  *         difference with step h (needs two force evaluations).         */
 void oracle_brackets(const int L[4], double beta, double kappa, int fermions, double cg_tol,
                      int cg_maxiter, const cplx *U, const double *P, const cplx *phi, double h,
-                     double *SST, double *TST) {
+                     double *SST, double *TST, double c1) {
     long V = lat_volume(L), n = 4 * V * 8;
-    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 0};
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 0, c1};
     oracle_stats st = {0, 0, 0};
     double *F = malloc(sizeof(double) * n);
     cplx *Ud = malloc(sizeof(cplx) * 4 * V * 9);
@@ -1297,7 +1389,7 @@ double oracle_metropolis_uniform(uint64_t seed, uint32_t traj) {
 int oracle_hmc_run(const int L[4], double beta, double kappa, int fermions, double cg_tol, int cg_maxiter,
                    int fg_exact, int nstages, const char *kinds, const double *ws, const double *xis, double tau,
                    int nsteps, cplx *U, uint64_t seed, uint32_t traj0, int ntraj, int metropolis, double *dH,
-                   int *acc, double *plaq, int fg_start) {
+                   int *acc, double *plaq, int fg_start, double c1) {
     long V = lat_volume(L), Vh = V / 2;
     double *P = malloc(sizeof(double) * 4 * V * 8);
     cplx *Ut = malloc(sizeof(cplx) * 4 * V * 9);
@@ -1310,7 +1402,7 @@ int oracle_hmc_run(const int L[4], double beta, double kappa, int fermions, doub
         double d = 0.0;
         long st3[3];
         int rc = oracle_trajectory(L, beta, kappa, fermions, cg_tol, cg_maxiter, fg_exact, nstages, kinds, ws, xis,
-                                   tau, nsteps, Ut, P, eta, NULL, &d, st3, fg_start);
+                                   tau, nsteps, Ut, P, eta, NULL, &d, st3, fg_start, c1);
         if (rc) status = rc;
         int a = !metropolis || oracle_metropolis_uniform(seed, t) < exp(-d);
         if (a) memcpy(U, Ut, sizeof(cplx) * 4 * V * 9);

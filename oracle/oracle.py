@@ -53,12 +53,12 @@ _i = ctypes.c_int
 def _declare(L):
     L.oracle_threads.argtypes = []
     L.oracle_threads.restype = _i
-    L.oracle_gauge_action.argtypes = [_ip, _d, _vp]
+    L.oracle_gauge_action.argtypes = [_ip, _d, _d, _vp]
     L.oracle_gauge_action.restype = _d
     L.oracle_plaquette.argtypes = [_ip, _vp]
     L.oracle_plaquette.restype = _d
-    L.oracle_gauge_force.argtypes = [_ip, _d, _vp, _vp]
-    L.oracle_gauge_force_tangent.argtypes = [_ip, _d, _vp, _vp, _vp]
+    L.oracle_gauge_force.argtypes = [_ip, _d, _d, _vp, _vp]
+    L.oracle_gauge_force_tangent.argtypes = [_ip, _d, _d, _vp, _vp, _vp]
     L.oracle_kinetic.argtypes = [_ip, _vp]
     L.oracle_kinetic.restype = _d
     L.oracle_exp_su3.argtypes = [_vp, _d, _vp]
@@ -74,28 +74,28 @@ def _declare(L):
     L.oracle_pf_action.argtypes = [_ip, _d, _vp, _vp, _d, _i, _ip]
     L.oracle_pf_action.restype = _d
     L.oracle_fermion_force_add.argtypes = [_ip, _d, _vp, _vp, _d, _vp]
-    L.oracle_force.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _lp]
-    L.oracle_force_tangent.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _vp, _lp]
+    L.oracle_force.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _lp, _d]
+    L.oracle_force_tangent.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _vp, _lp, _d]
     L.oracle_fermion_force_tangent_add.argtypes = [_ip, _d, _vp, _vp, _vp, _d, _i, _d, _vp]
     L.oracle_fermion_force_tangent_add.restype = _i
     L.oracle_trajectory.argtypes = [_ip, _d, _d, _i, _d, _i, _i, _i, ctypes.c_char_p, _vp, _vp,
-                                    _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i]
+                                    _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i, _d]
     L.oracle_trajectory.restype = _i
-    L.oracle_brackets.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _d, _dp, _dp]
+    L.oracle_brackets.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _d, _dp, _dp, _d]
     L.oracle_hasen_heatbath.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _d, _i]
     L.oracle_hasen_heatbath.restype = _i
     L.oracle_hasen_action.argtypes = [_ip, _d, _d, _vp, _vp, _d, _i, _vp, _ip]
     L.oracle_hasen_action.restype = _d
     L.oracle_hasen_force_add.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _d, _vp]
     L.oracle_trajectory_nested.argtypes = [_ip, _d, _d, _d, _d, _i, _i, _vp, _vp, _vp, ctypes.c_char_p, _vp, _vp,
-                                           _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i]
+                                           _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i, _d]
     L.oracle_trajectory_nested.restype = _i
     L.oracle_philox.argtypes = [_vp, _vp, _vp]
     L.oracle_refresh.argtypes = [_ip, ctypes.c_uint64, ctypes.c_uint32, _vp, _vp, _vp]
     L.oracle_metropolis_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
     L.oracle_metropolis_uniform.restype = _d
     L.oracle_hmc_run.argtypes = [_ip, _d, _d, _i, _d, _i, _i, _i, ctypes.c_char_p, _vp, _vp, _d, _i, _vp,
-                                 ctypes.c_uint64, ctypes.c_uint32, _i, _i, _vp, _vp, _vp, _i]
+                                 ctypes.c_uint64, ctypes.c_uint32, _i, _i, _vp, _vp, _vp, _i, _d]
     L.oracle_cg_from.argtypes = [_ip, _d, _vp, _vp, _vp, _d, _i, _dp, _i]
     L.oracle_cg_from.restype = _i
     L.oracle_hmc_run.restype = _i
@@ -122,9 +122,10 @@ def volume(dims):
     return int(np.prod(dims))
 
 
-def gauge_action(dims, beta, U):
+def gauge_action(dims, beta, U, c1=0.0):
+    """S_G with plaquettes (weight c0 = 1 - 8 c1) and 2x1 rectangles (weight c1)"""
     U = _c(U, np.complex128)
-    return lib().oracle_gauge_action(_dims(dims), beta, _ptr(U))
+    return lib().oracle_gauge_action(_dims(dims), beta, c1, _ptr(U))
 
 
 def plaquette(dims, U):
@@ -132,19 +133,19 @@ def plaquette(dims, U):
     return lib().oracle_plaquette(_dims(dims), _ptr(U))
 
 
-def gauge_force(dims, beta, U):
+def gauge_force(dims, beta, U, c1=0.0):
     U = _c(U, np.complex128)
     F = np.zeros((4, volume(dims), 8))
-    lib().oracle_gauge_force(_dims(dims), beta, _ptr(U), _ptr(F))
+    lib().oracle_gauge_force(_dims(dims), beta, c1, _ptr(U), _ptr(F))
     return F
 
 
-def gauge_force_tangent(dims, beta, U, Vdir):
+def gauge_force_tangent(dims, beta, U, Vdir, c1=0.0):
     """J_V[F_G] = d/dt F_G(exp(t V) U) at t = 0."""
     U = _c(U, np.complex128)
     Vdir = _c(Vdir, np.float64)
     J = np.zeros((4, volume(dims), 8))
-    lib().oracle_gauge_force_tangent(_dims(dims), beta, _ptr(U), _ptr(Vdir), _ptr(J))
+    lib().oracle_gauge_force_tangent(_dims(dims), beta, c1, _ptr(U), _ptr(Vdir), _ptr(J))
     return J
 
 
@@ -250,7 +251,7 @@ def cg_from(dims, kappa, U, phi, x0, tol=1e-10, maxiter=10000):
     return X, it, rel.value
 
 
-def force(dims, beta, U, kappa=0.0, phi=None, tol=1e-14, maxiter=10000):
+def force(dims, beta, U, kappa=0.0, phi=None, tol=1e-14, maxiter=10000, c1=0.0):
     """total force F = F_G (+ F_F when phi is given); returns (F, stats)"""
     U = _c(U, np.complex128)
     F = np.zeros((4, volume(dims), 8))
@@ -258,11 +259,11 @@ def force(dims, beta, U, kappa=0.0, phi=None, tol=1e-14, maxiter=10000):
     ferm = phi is not None
     phi_a = _c(phi, np.complex128) if ferm else None
     lib().oracle_force(_dims(dims), beta, kappa, int(ferm), tol, maxiter, _ptr(U),
-                       _ptr(phi_a) if ferm else None, _ptr(F), st)
+                       _ptr(phi_a) if ferm else None, _ptr(F), st, c1)
     return F, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2])
 
 
-def force_tangent(dims, beta, U, V, kappa=0.0, phi=None, tol=1e-14, maxiter=10000):
+def force_tangent(dims, beta, U, V, kappa=0.0, phi=None, tol=1e-14, maxiter=10000, c1=0.0):
     """J_V[F] = d/dt F(exp(t V) U) at t = 0 for the total force (gauge, plus the
     pseudofermion force when phi is given); returns (J, stats)"""
     U = _c(U, np.complex128)
@@ -272,7 +273,7 @@ def force_tangent(dims, beta, U, V, kappa=0.0, phi=None, tol=1e-14, maxiter=1000
     ferm = phi is not None
     phi_a = _c(phi, np.complex128) if ferm else None
     lib().oracle_force_tangent(_dims(dims), beta, kappa, int(ferm), tol, maxiter, _ptr(U),
-                               _ptr(phi_a) if ferm else None, _ptr(V), _ptr(J), st)
+                               _ptr(phi_a) if ferm else None, _ptr(V), _ptr(J), st, c1)
     return J, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2])
 
 
@@ -288,7 +289,7 @@ def fermion_force_tangent(dims, kappa, U, X, V, tol=1e-14, maxiter=10000):
 
 
 def trajectory(dims, beta, stages, tau, nsteps, U, P, kappa=0.0, eta=None, tol=1e-14,
-               maxiter=10000, fg_exact=False, phi=None, fg_start=True):
+               maxiter=10000, fg_exact=False, phi=None, fg_start=True, c1=0.0):
     """One MD trajectory.  stages: list of (kind, w, xi) with kind in 'PQG'.
     Fermions: give eta (phi = Mhat^+ eta) or phi itself.  fg_start: the
     displaced force's solve of a G stage starts from the undisplaced solution.
@@ -308,11 +309,11 @@ def trajectory(dims, beta, stages, tau, nsteps, U, P, kappa=0.0, eta=None, tol=1
                                      tau, nsteps, _ptr(U), _ptr(P),
                                      _ptr(eta_a) if eta_a is not None else None,
                                      _ptr(phi_a) if phi_a is not None else None,
-                                     ctypes.byref(dH), st, int(bool(fg_start)))
+                                     ctypes.byref(dH), st, int(bool(fg_start)), c1)
     return U, P, dH.value, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2]), status
 
 
-def brackets(dims, beta, U, P, kappa=0.0, phi=None, h=1e-4, tol=1e-14, maxiter=10000):
+def brackets(dims, beta, U, P, kappa=0.0, phi=None, h=1e-4, tol=1e-14, maxiter=10000, c1=0.0):
     """(SST, TST) = ({S,{S,T}}, {T,{S,T}}) at (U, P); TST by central difference."""
     U = _c(U, np.complex128)
     P = _c(P, np.float64)
@@ -321,7 +322,7 @@ def brackets(dims, beta, U, P, kappa=0.0, phi=None, h=1e-4, tol=1e-14, maxiter=1
     sst = ctypes.c_double(0)
     tst = ctypes.c_double(0)
     lib().oracle_brackets(_dims(dims), beta, kappa, int(ferm), tol, maxiter, _ptr(U), _ptr(P),
-                          _ptr(phi_a) if ferm else None, h, ctypes.byref(sst), ctypes.byref(tst))
+                          _ptr(phi_a) if ferm else None, h, ctypes.byref(sst), ctypes.byref(tst), c1)
     return sst.value, tst.value
 
 
@@ -354,7 +355,7 @@ def hasen_force(dims, kappa, kappa2, U, phi2, X2):
 
 
 def trajectory_nested(dims, beta, levels, tau, nsteps, U, P, kappa=0.0, kappa2=0.0, eta1=None, eta2=None,
-                      tol=1e-14, maxiter=10000, fg_start=True):
+                      tol=1e-14, maxiter=10000, fg_start=True, c1=0.0):
     """levels: list of (stages, terms, nsub), level 0 outermost; terms bit 1 gauge,
     2 S_F (or S_1 with Hasenbusch), 4 S_2.  Returns (U, P, dH, stats, status)."""
     U = np.array(U, dtype=np.complex128, copy=True, order="C")
@@ -373,7 +374,7 @@ def trajectory_nested(dims, beta, levels, tau, nsteps, U, P, kappa=0.0, kappa2=0
                                             _ptr(terms), _ptr(nsub), kinds, _ptr(ws), _ptr(xis), tau, nsteps,
                                             _ptr(U), _ptr(P), _ptr(e1) if e1 is not None else None,
                                             _ptr(e2) if e2 is not None else None, ctypes.byref(dH), st,
-                                            int(bool(fg_start)))
+                                            int(bool(fg_start)), c1)
     return U, P, dH.value, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2]), status
 
 
@@ -406,7 +407,7 @@ def metropolis_uniform(seed, traj):
 
 
 def hmc_run(dims, beta, stages, tau, nsteps, U, seed, traj0, ntraj, kappa=0.0, fermions=False, tol=1e-14,
-            maxiter=10000, fg_exact=False, metropolis=True, fg_start=True):
+            maxiter=10000, fg_exact=False, metropolis=True, fg_start=True, c1=0.0):
     """HMC chain of ntraj trajectories from U; returns (U_final, dH list, accepted list, plaquettes, status)."""
     U = np.array(U, dtype=np.complex128, copy=True, order="C")
     kinds = "".join(s[0] for s in stages).encode()
@@ -419,7 +420,7 @@ def hmc_run(dims, beta, stages, tau, nsteps, U, seed, traj0, ntraj, kappa=0.0, f
     status = lib().oracle_hmc_run(_dims(dims), beta, kappa, int(bool(fermions)), tol, maxiter, int(bool(fg_exact)),
                                   len(stages), kinds, _ptr(ws), _ptr(xis), tau, nsteps, _ptr(U), int(seed),
                                   int(traj0), int(ntraj), int(bool(metropolis)), _ptr(dH), _ptr(acc), _ptr(plaq),
-                                  int(bool(fg_start)))
+                                  int(bool(fg_start)), c1)
     k = int(ntraj)
     return U, list(dH[:k]), [bool(a) for a in acc[:k]], list(plaq[:k]), status
 
