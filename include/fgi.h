@@ -81,6 +81,13 @@ typedef struct {
     int fg_exact;       /* G stages: 0 = displacement form, 1 = exact force gradient
                            (gauge and pseudofermion, Section 4; not with
                            kappa_hasen, not for batched chains) */
+    double c1;          /* rectangle coefficient of the gauge action (finite):
+                           S_G = beta sum_x [c0 sum_{mu<nu} (1 - ReTr P_{mu nu}(x)/3)
+                                 + c1 sum_{mu!=nu} (1 - ReTr R_{mu nu}(x)/3)],
+                           c0 = 1 - 8 c1, R the 2x1 rectangle two links along mu;
+                           0 = Wilson, -1/12 tree-level Symanzik, -0.331 Iwasaki.
+                           Forces, force gradients, brackets, trajectories and
+                           chains all take it; batched chains need c1 = 0. */
 } fgi_action;
 
 /* One stage of an integrator step (Table 1), coefficients multiply the step h:
@@ -181,8 +188,14 @@ int fgi_autotune_cg(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, cons
                     fgi_tuning* out, void* stream);
 
 /* ------------------------------------------------ Hamiltonian (Section 2) */
-/* *S = S_G(U) (FP64). */
+/* *S = S_G(U) (FP64), Wilson plaquette action. */
 int fgi_gauge_action(fgi_ctx* ctx, const fgi_geom* g, double beta, const void* U, double* S, void* stream);
+/* *S = S_G(U) (FP64) of the improved gauge action with rectangle coefficient
+ * c1 (as fgi_action.c1; the conclusions of the paper note that the
+ * force-gradient construction holds for any common action).  FGI_EINVAL for a
+ * non-finite c1. */
+int fgi_improved_gauge_action(fgi_ctx* ctx, const fgi_geom* g, double beta, double c1, const void* U, double* S,
+                              void* stream);
 /* *T = 1/2 sum p_a^2 over all links (FP64). */
 int fgi_kinetic(fgi_ctx* ctx, const fgi_geom* g, const void* P, double* T, void* stream);
 

@@ -112,6 +112,7 @@ void check_action(const fgi_action* a) {
     if (a->kappa != 0 && (a->cg_tol <= 0 || a->cg_maxiter <= 0)) throw Error(FGI_EINVAL, "bad CG settings");
     if (a->kappa_hasen != 0 && (a->kappa == 0 || a->kappa_hasen >= a->kappa))
         throw Error(FGI_EINVAL, "Hasenbusch kappa' must satisfy 0 < kappa' < kappa");
+    if (!std::isfinite(a->c1)) throw Error(FGI_EINVAL, "the rectangle coefficient c1 must be finite");
 }
 
 int sloppy_prec(const fgi_action* a) { return a->prec == FGI_FP64 ? P64 : (a->prec == FGI_MP32 ? P32 : P16); }
@@ -172,7 +173,7 @@ struct Fields {
         bool have = accumulate;
         if (st) st->force_evals++;
         if (terms & FGI_TERM_GAUGE) {
-            gauge_force(c, g, act.beta, u, out, coef, have ? 1 : 0);
+            gauge_force(c, g, act.beta, u, out, coef, have ? 1 : 0, act.c1);
             have = true;
         }
         bool ferm = act.kappa != 0.0 && (terms & (FGI_TERM_FERMION | FGI_TERM_HASEN));
@@ -203,7 +204,7 @@ struct Fields {
         const bool ferm = act.kappa != 0.0 && (terms & (FGI_TERM_FERMION | FGI_TERM_HASEN));
         if (ferm && act.kappa_hasen != 0.0)
             throw Error(FGI_EINVAL, "the exact force gradient is not available for the Hasenbusch terms");
-        if (terms & FGI_TERM_GAUGE) gauge_force_tangent(c, g, act.beta, u, Vd, J, 1.0, 0);
+        if (terms & FGI_TERM_GAUGE) gauge_force_tangent(c, g, act.beta, u, Vd, J, 1.0, 0, 0, act.c1);
         else zero_mom(J);
         if (!ferm) return;
         d2* W = (d2*)c.gauge_tan.get(gauge_bytes(g));
@@ -350,16 +351,22 @@ int fgi_get_profile(fgi_ctx* ctx, double* ms, long* launches, long* sites) {
 }
 
 int fgi_gauge_action(fgi_ctx* ctx, const fgi_geom* gg, double beta, const void* U, double* S, void* stream) {
+    return fgi_improved_gauge_action(ctx, gg, beta, 0.0, U, S, stream);
+}
+
+int fgi_improved_gauge_action(fgi_ctx* ctx, const fgi_geom* gg, double beta, double c1, const void* U, double* S,
+                              void* stream) {
     return guarded([&] {
         Ctx& c = ctx_of(ctx);
         if (!gg || !S) throw Error(FGI_EINVAL, "null argument");
+        if (!std::isfinite(c1)) throw Error(FGI_EINVAL, "the rectangle coefficient c1 must be finite");
         Geom g = make_geom(gg->dims);
         need(U, "U", 16);
         StreamScope ss(c, stream);
         d2* u = (d2*)c.gauge.get(gauge_bytes(g));
         pack_gauge(c, g, U, u);
         double* h = (double*)c.h0.get(sizeof(double) * g.V);
-        ham_density(c, g, beta, u, nullptr, h);
+        ham_density(c, g, beta, u, nullptr, h, c1);
         double* part = partial_buf(c, g);
         double* scal = (double*)c.scal.get(sizeof(double) * 64);
         int nb = diff_partials(c, g.V, h, nullptr, part);
@@ -1050,10 +1057,10 @@ double trajectory_packed(Fields& f, const fgi_integrator& integ, double tau, int
             if (hasen) f.hasen_heatbath(f.U, f.Us, eta_2);
         }
     }
-    ham_density(c, g, f.act.beta, f.U, f.P, h0);
+    ham_density(c, g, f.act.beta, f.U, f.P, h0, f.act.c1);
     Driver d(f, integ);
     d.run(0, nsteps, tau / nsteps);
-    ham_density(c, g, f.act.beta, f.U, f.P, h1);
+    ham_density(c, g, f.act.beta, f.U, f.P, h1, f.act.c1);
     int nb = diff_partials(c, g.V, h1, h0, part);
     final_sum(c, part, nb, scal);
     double dh = sync_scalar(c, scal, 0);
@@ -1411,6 +1418,7 @@ extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain
         if (nsteps < 1 || !std::isfinite(tau)) throw Error(FGI_EINVAL, "bad tau / nsteps");
         if (act->kappa_hasen != 0.0) throw Error(FGI_EINVAL, "batched chains take one pseudofermion");
         if (act->fg_exact) throw Error(FGI_EINVAL, "batched chains use the displacement force-gradient form");
+        if (act->c1 != 0.0) throw Error(FGI_EINVAL, "batched chains take the Wilson gauge action (c1 = 0)");
         const bool ferm = chains[0].kappa != 0.0;
         std::vector<ChainDesc> cd;
         Batch B;

@@ -167,16 +167,20 @@ void pack_even_spinor(Ctx&, const Geom&, const void* user, d2* internal);
 void unpack_even_spinor(Ctx&, const Geom&, const d2* internal, void* user);
 void make_sloppy(Ctx&, const Geom&, const d2* u64, void* sloppy, int prec, int recon);
 // per-site h = beta * sum_{mu<nu}(1 - ReTr U_P/3) [when U != null] + kinetic of P [when P != null]
-void ham_density(Ctx&, const Geom&, double beta, const d2* U, const double* P, double* h);
+// h = gauge action density (plaquettes at beta (1 - 8 c1), rectangles at
+// beta c1; none when U is null) + kinetic density (when P is given)
+void ham_density(Ctx&, const Geom&, double beta, const d2* U, const double* P, double* h, double c1 = 0.0);
 // partial[b] = sum over block b of (h1 - h0) [or h1 when h0 == null]; returns nblocks
 int diff_partials(Ctx&, int n, const double* h1, const double* h0, double* partial);
 void final_sum(Ctx&, const double* partial, int n, double* out);
 // F_G into F: mode 0: F = c * F_G; 1: F += c * F_G
-void gauge_force(Ctx&, const Geom&, double beta, const d2* U, double* F, double c, int accumulate);
+// F (+)= c F_G(U) for the gauge action with rectangle coefficient c1
+void gauge_force(Ctx&, const Geom&, double beta, const d2* U, double* F, double c, int accumulate,
+                 double c1 = 0.0);
 // mode 0: J = c * d/dt F_G(exp(t V) U); mode 1: J = c * (-J_V[F_G] + [V, F_G]/2),
 // the Hessian of S_G in the chart exp(omega) U at omega = 0 applied to V (+ J when accumulate)
 void gauge_force_tangent(Ctx&, const Geom&, double beta, const d2* U, const double* Vd, double* J,
-                         double c, int accumulate, int mode = 0);
+                         double c, int accumulate, int mode = 0, double c1 = 0.0);
 // dst = exp(h X) src on every link; sloppy copy of dst written when sloppy != null
 void link_update(Ctx&, const Geom&, double h, const double* X, const d2* src, d2* dst, void* sloppy,
                  int prec, int recon);

@@ -212,9 +212,13 @@ __global__ void k_ham_density_b(const ChainDesc* __restrict__ cd, int nc, const 
                      (blockIdx.x - d.blk0[GRID_V]) * blockDim.x + threadIdx.x);
 }
 
-void ham_density(Ctx& c, const Geom& g, double beta, const d2* U, const double* P, double* h) {
-    hipLaunchKernelGGL(k_ham_density, dim3(nblocks(g.V, BS)), dim3(BS), 0, c.stream, g, beta, U, P, h);
+void rect_density_add(Ctx& c, const Geom& g, double bc1, const d2* U, double* h);
+
+void ham_density(Ctx& c, const Geom& g, double beta, const d2* U, const double* P, double* h, double c1) {
+    hipLaunchKernelGGL(k_ham_density, dim3(nblocks(g.V, BS)), dim3(BS), 0, c.stream, g, beta * (1.0 - 8.0 * c1), U,
+                       P, h);
     FGI_LAUNCH_CHECK();
+    if (c1 != 0.0 && U) rect_density_add(c, g, beta * c1, U, h);
 }
 
 __global__ void k_diff_partials(int n, const double* __restrict__ h1, const double* __restrict__ h0,
@@ -321,10 +325,13 @@ __global__ void __launch_bounds__(256) k_gauge_force_b(const ChainDesc* __restri
                      (blockIdx.x - d.blk0[GRID_4V]) * blockDim.x + threadIdx.x);
 }
 
-void gauge_force(Ctx& c, const Geom& g, double beta, const d2* U, double* F, double coef, int accumulate) {
+void rect_force(Ctx& c, const Geom& g, double beta, double c1, const d2* U, double* F, double coef);
+
+void gauge_force(Ctx& c, const Geom& g, double beta, const d2* U, double* F, double coef, int accumulate, double c1) {
     hipLaunchKernelGGL(k_gauge_force, dim3(slab_blocks(g.Vh, 8, BS, c.ds_xcd)), dim3(BS), 0, c.stream, g, beta, U, F,
-                       coef, accumulate, c.ds_xcd);
+                       coef * (1.0 - 8.0 * c1), accumulate, c.ds_xcd);
     FGI_LAUNCH_CHECK();
+    if (c1 != 0.0) rect_force(c, g, beta, c1, U, F, coef);
 }
 
 // Tangent of the gauge force along a field of su(3) elements V:
@@ -420,10 +427,215 @@ __global__ void __launch_bounds__(256) k_gauge_tangent(Geom g, double beta, cons
     }
 }
 
+void rect_tangent(Ctx& c, const Geom& g, double beta, double c1, const d2* U, const double* Vd, double* J,
+                  double coef, int mode);
+
 void gauge_force_tangent(Ctx& c, const Geom& g, double beta, const d2* U, const double* Vd, double* J, double coef,
-                         int accumulate, int mode) {
+                         int accumulate, int mode, double c1) {
     hipLaunchKernelGGL(k_gauge_tangent, dim3(slab_blocks(g.Vh, 8, BS, c.ds_xcd)), dim3(BS), 0, c.stream, g, beta, U,
-                       Vd, J, coef, accumulate, mode, c.ds_xcd);
+                       Vd, J, coef * (1.0 - 8.0 * c1), accumulate, mode, c.ds_xcd);
+    FGI_LAUNCH_CHECK();
+    if (c1 != 0.0) rect_tangent(c, g, beta, c1, U, Vd, J, coef, mode);
+}
+
+// ------------------------------------------------- rectangle (2x1) terms ---
+// Improved gauge action
+//   S_G = beta sum_x [c0 sum_{mu<nu} (1 - ReTr P_{mu nu}(x)/3) + c1 sum_{mu!=nu} (1 - ReTr R_{mu nu}(x)/3)],
+// c0 = 1 - 8 c1, R_{mu nu}(x) the rectangle two links along mu and one along nu
+// (c1 = -1/12: tree-level Symanzik, Luscher and Weisz 1985; c1 = -0.331:
+// Iwasaki).  Everything is linear in (c0, c1): the plaquette kernels above run
+// with their coefficient scaled by c0 and the kernels below add the c1 part.
+
+__device__ __forceinline__ int coord_parity(const Coord& y) { return (y.c[0] + y.c[1] + y.c[2] + y.c[3]) & 1; }
+
+__device__ __forceinline__ void coord_step(const Geom& g, Coord& y, int d, int fwd) {
+    if (fwd) y.c[d] = y.c[d] + 1 == g.L[d] ? 0 : y.c[d] + 1;
+    else y.c[d] = (y.c[d] == 0 ? g.L[d] : y.c[d]) - 1;
+}
+
+__device__ __forceinline__ M3<double> link_at(const Geom& g, const d2* U, int d, const Coord& y) {
+    return gauge_load(U, d, coord_parity(y), cb_index(g, y), g.Vh);
+}
+
+// The 18 rectangle staples of link (mu, x) are the 5-link paths from x + mu
+// back to x that close a 2x1 rectangle through U_mu(x); per nu != mu, six
+// shapes, written as steps (+-1: along +-mu, +-2: along +-nu):
+//   two long along mu, +nu side, U_mu(x) the first or the second mu link;
+//   the same on the -nu side; two long along nu on the +nu and -nu sides.
+__constant__ int RECT_SHAPES[6][5] = {{1, 2, -1, -1, -2}, {2, -1, -1, -2, 1}, {1, -2, -1, -1, 2},
+                                      {-2, -1, -1, 2, 1},  {2, 2, -1, -2, -2}, {-2, -2, -1, 2, 2}};
+
+// One factor of a path walked from y: a step along +d multiplies U_d(y) and
+// moves to y + d; a step along -d moves to y - d and multiplies U_d(y)^+.
+// With TAN, dl is the derivative of the factor along V (V U, or -U^+ V).
+template <bool TAN>
+__device__ __forceinline__ M3<double> path_factor(const Geom& g, const d2* __restrict__ U,
+                                                  const double* __restrict__ Vd, Coord& y, int d, int fwd,
+                                                  M3<double>& dl) {
+    if (!fwd) coord_step(g, y, d, 0);
+    const int par = coord_parity(y), s = cb_index(g, y);
+    const M3<double> u = gauge_load(U, d, par, s, g.Vh);
+    if (TAN) {
+        const M3<double> v = valg(Vd, d, par, s, g.Vh);
+        if (fwd) {
+            dl = m3_mul(v, u);
+        } else {
+            dl = m3_mul_dn(u, v);
+            m3_scale(dl, -1.0);
+        }
+    }
+    if (fwd) coord_step(g, y, d, 1);
+    return fwd ? u : m3_dag(u);
+}
+
+// A = sum of the 18 rectangle staples of link (mu, x); with TAN, dA = its
+// derivative along V by the product rule, factor by factor.
+template <bool TAN>
+__device__ __forceinline__ void rect_staples(const Geom& g, const d2* __restrict__ U, const double* __restrict__ Vd,
+                                             const Coord& c, int mu, M3<double>& A, M3<double>& dA) {
+    A = m3_zero<double>();
+    if (TAN) dA = m3_zero<double>();
+#pragma unroll 1
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == mu) continue;
+#pragma unroll 1
+        for (int k = 0; k < 6; k++) {
+            Coord y = c;
+            coord_step(g, y, mu, 1);
+            M3<double> P, D, dl;
+#pragma unroll 1
+            for (int j = 0; j < 5; j++) {
+                const int st = RECT_SHAPES[k][j];
+                const int d = (st == 1 || st == -1) ? mu : nu;
+                const M3<double> f = path_factor<TAN>(g, U, Vd, y, d, st > 0, dl);
+                if (j == 0) {
+                    P = f;
+                    if (TAN) D = dl;
+                } else {
+                    if (TAN) {
+                        D = m3_mul(D, f);
+                        m3_acc(D, m3_mul(P, dl));
+                    }
+                    P = m3_mul(P, f);
+                }
+            }
+            m3_acc(A, P);
+            if (TAN) m3_acc(dA, D);
+        }
+    }
+}
+
+// h(x) += bc1 sum_{mu != nu} (1 - ReTr R_{mu nu}(x) / 3), with
+// ReTr R = ReTr(a b^+), a = U_mu(x) U_mu(x+mu) U_nu(x+2mu), b = U_nu(x) U_mu(x+nu) U_mu(x+mu+nu)
+__global__ void __launch_bounds__(256) k_rect_density(Geom g, double bc1, const d2* __restrict__ U,
+                                                     double* __restrict__ h) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.V) return;
+    const int p = t / g.Vh, s = t % g.Vh;
+    const Coord c = cb_coords(g, p, s);
+    double acc = 0.0;
+#pragma unroll 1
+    for (int mu = 0; mu < 4; mu++) {
+        Coord xm = c;
+        coord_step(g, xm, mu, 1);
+        Coord x2m = xm;
+        coord_step(g, x2m, mu, 1);
+        const M3<double> aa = m3_mul(gauge_load(U, mu, p, s, g.Vh), link_at(g, U, mu, xm));
+#pragma unroll 1
+        for (int nu = 0; nu < 4; nu++) {
+            if (nu == mu) continue;
+            Coord xn = c, xmn = xm;
+            coord_step(g, xn, nu, 1);
+            coord_step(g, xmn, nu, 1);
+            const M3<double> a = m3_mul(aa, link_at(g, U, nu, x2m));
+            const M3<double> b = m3_mul(m3_mul(gauge_load(U, nu, p, s, g.Vh), link_at(g, U, mu, xn)),
+                                        link_at(g, U, mu, xmn));
+            double tr = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) tr += a.e[i][j].re * b.e[i][j].re + a.e[i][j].im * b.e[i][j].im;
+            acc += 1.0 - tr / 3.0;
+        }
+    }
+    h[t] += bc1 * acc;
+}
+
+void rect_density_add(Ctx& c, const Geom& g, double bc1, const d2* U, double* h) {
+    hipLaunchKernelGGL(k_rect_density, dim3(nblocks(g.V, BS)), dim3(BS), 0, c.stream, g, bc1, U, h);
+    FGI_LAUNCH_CHECK();
+}
+
+// F_mu(x) += f TA(U_mu(x) A^R_mu(x)), f = -beta c1 coef / 6
+__global__ void __launch_bounds__(256) k_rect_force(Geom g, double f, const d2* __restrict__ U,
+                                                   double* __restrict__ F, int xcd) {
+    const int t = slab_thread(g.Vh, 8, xcd);
+    if (t >= 4 * g.V) return;
+    const int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
+    const Coord c = cb_coords(g, p, s);
+    M3<double> A, dA;
+    rect_staples<false>(g, U, nullptr, c, mu, A, dA);
+    const M3<double> W = m3_mul(gauge_load(U, mu, p, s, g.Vh), A);
+    double x[8];
+    ta_components(W, x);
+    double* o = F + (size_t)(r * 8) * g.Vh + s;
+#pragma unroll
+    for (int a = 0; a < 8; a++) o[(size_t)a * g.Vh] += f * x[a];
+}
+
+void rect_force(Ctx& c, const Geom& g, double beta, double c1, const d2* U, double* F, double coef) {
+    hipLaunchKernelGGL(k_rect_force, dim3(slab_blocks(g.Vh, 8, BS, c.ds_xcd)), dim3(BS), 0, c.stream, g,
+                       -beta * c1 * coef / 6.0, U, F, c.ds_xcd);
+    FGI_LAUNCH_CHECK();
+}
+
+// J += coef * (mode 0: J_V[F_R]; mode 1: -J_V[F_R] + [V, F_R] / 2) for the
+// rectangle part F_R = -(beta c1 / 6) TA(U A^R) of the force
+__global__ void __launch_bounds__(256) k_rect_tangent(Geom g, double bc1, const d2* __restrict__ U,
+                                                     const double* __restrict__ Vd, double* __restrict__ J,
+                                                     double coef, int mode, int xcd) {
+    const int t = slab_thread(g.Vh, 8, xcd);
+    if (t >= 4 * g.V) return;
+    const int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
+    const Coord c = cb_coords(g, p, s);
+    M3<double> A, dA;
+    rect_staples<true>(g, U, Vd, c, mu, A, dA);
+    const M3<double> u = gauge_load(U, mu, p, s, g.Vh);
+    const M3<double> vl = valg(Vd, mu, p, s, g.Vh);
+    M3<double> dW = m3_mul(m3_mul(vl, u), A);
+    m3_acc(dW, m3_mul(u, dA));
+    double x[8];
+    ta_components(dW, x);
+    const double f = -bc1 / 6.0;
+    if (mode == 1) {
+        double fx[8];
+        ta_components(m3_mul(u, A), fx);
+#pragma unroll
+        for (int a = 0; a < 8; a++) fx[a] *= f;
+        const M3<double> Fm = alg_matrix(fx);
+        M3<double> C = m3_mul(vl, Fm);
+        const M3<double> D = m3_mul(Fm, vl);
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) C.e[i][j] = C.e[i][j] - D.e[i][j];
+        double cx8[8];
+        ta_components(C, cx8);
+#pragma unroll
+        for (int a = 0; a < 8; a++) x[a] = -f * x[a] + 0.5 * cx8[a];
+    } else {
+#pragma unroll
+        for (int a = 0; a < 8; a++) x[a] = f * x[a];
+    }
+    double* o = J + (size_t)(r * 8) * g.Vh + s;
+#pragma unroll
+    for (int a = 0; a < 8; a++) o[(size_t)a * g.Vh] += coef * x[a];
+}
+
+void rect_tangent(Ctx& c, const Geom& g, double beta, double c1, const d2* U, const double* Vd, double* J,
+                  double coef, int mode) {
+    hipLaunchKernelGGL(k_rect_tangent, dim3(slab_blocks(g.Vh, 8, BS, c.ds_xcd)), dim3(BS), 0, c.stream, g,
+                       beta * c1, U, Vd, J, coef, mode, c.ds_xcd);
     FGI_LAUNCH_CHECK();
 }
 

@@ -39,7 +39,7 @@ class fgi_geom(ctypes.Structure):
 class fgi_action(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("kappa", ctypes.c_double), ("kappa_hasen", ctypes.c_double),
                 ("cg_tol", ctypes.c_double), ("cg_maxiter", ctypes.c_int), ("prec", ctypes.c_int),
-                ("link_recon", ctypes.c_int), ("fg_exact", ctypes.c_int)]
+                ("link_recon", ctypes.c_int), ("fg_exact", ctypes.c_int), ("c1", ctypes.c_double)]
 
 
 class fgi_stage(ctypes.Structure):
@@ -100,6 +100,7 @@ SIGNATURES = {
     "fgi_set_option": (_i, [_vp, ctypes.c_char_p, _d]),
     "fgi_get_profile": (_i, [_vp, _P(_d), _P(ctypes.c_long), _P(ctypes.c_long)]),
     "fgi_gauge_action": (_i, [_vp, _P(fgi_geom), _d, _vp, _P(_d), _vp]),
+    "fgi_improved_gauge_action": (_i, [_vp, _P(fgi_geom), _d, _d, _vp, _P(_d), _vp]),
     "fgi_kinetic": (_i, [_vp, _P(fgi_geom), _vp, _P(_d), _vp]),
     "fgi_gauge_force": (_i, [_vp, _P(fgi_geom), _d, _vp, _vp, _vp]),
     "fgi_force_gradient": (_i, [_vp, _P(fgi_geom), _d, _vp, _vp, _vp, _vp]),
@@ -174,10 +175,11 @@ class Action:
     prec: str = "fp64"
     link_recon: int = 18
     fg_exact: bool = False
+    c1: float = 0.0      # rectangle coefficient of the gauge action (0: Wilson)
 
     def c(self):
         return fgi_action(self.beta, self.kappa, self.kappa_hasen, self.cg_tol, int(self.cg_maxiter),
-                          PREC[self.prec], int(self.link_recon), int(bool(self.fg_exact)))
+                          PREC[self.prec], int(self.link_recon), int(bool(self.fg_exact)), float(self.c1))
 
 
 def integrator_builtin(which, alpha=0.1932):
@@ -270,6 +272,13 @@ class Context:
         S = ctypes.c_double()
         _check(lib().fgi_gauge_action(self.h, _geom(dims), beta, _ptr(U, torch.complex128, su, "U"),
                                       ctypes.byref(S), _stream()))
+        return S.value
+
+    def improved_gauge_action(self, dims, beta, c1, U):
+        su, _, _ = self._shapes(dims)
+        S = ctypes.c_double()
+        _check(lib().fgi_improved_gauge_action(self.h, _geom(dims), beta, c1, _ptr(U, torch.complex128, su, "U"),
+                                               ctypes.byref(S), _stream()))
         return S.value
 
     def kinetic(self, dims, P):

@@ -38,11 +38,39 @@ def test_struct_layouts_match_c_sizes():
     assert ctypes.sizeof(fgi.fgi_stage) == 24
     assert ctypes.sizeof(fgi.fgi_level) == 16 + 16 * 24
     assert ctypes.sizeof(fgi.fgi_integrator) == 8 + 4 * ctypes.sizeof(fgi.fgi_level)
-    assert ctypes.sizeof(fgi.fgi_action) == 4 * 8 + 4 * 4
+    assert ctypes.sizeof(fgi.fgi_action) == 4 * 8 + 4 * 4 + 8 and fgi.fgi_action.c1.offset == 48
     # fgi_chain: int dims[4], int pad, double beta, double kappa, 3 pointers
     assert ctypes.sizeof(fgi.fgi_chain) == 64 and fgi.fgi_chain.beta.offset == 24
     # fgi_tuning: 4 ints, 6 + 5 doubles
     assert ctypes.sizeof(fgi.fgi_tuning) == 16 + 11 * 8 and fgi.fgi_tuning.sched_us_per_iter.offset == 16
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """sizeof and offsetof as gcc lays the header's structs out, against ctypes"""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("no gcc")
+    structs = {"fgi_action": fgi.fgi_action, "fgi_stage": fgi.fgi_stage, "fgi_level": fgi.fgi_level,
+               "fgi_integrator": fgi.fgi_integrator, "fgi_stats": fgi.fgi_stats, "fgi_chain": fgi.fgi_chain,
+               "fgi_tuning": fgi.fgi_tuning}
+    lines = []
+    for name, cls in structs.items():
+        lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (name, name))
+        for f in cls._fields_:
+            if f[0] != "pad":
+                lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (name, f[0], name, f[0]))
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"fgi.h\"\nint main(void) {\n"
+                   + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    for line in filter(None, out):
+        name, field, val = line.split()
+        cls = structs[name]
+        got = ctypes.sizeof(cls) if field == "sizeof" else getattr(cls, field).offset
+        assert got == int(val), (name, field, got, val)
 
 
 @pytest.mark.parametrize("name", ["PQP", "QPQ", "PQPQP", "CAMPOSTRINI", "FG"])
