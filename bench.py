@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 96-chain batched workload")
     ap.add_argument("--batched-steps", type=int, default=2, help="timed batched trajectories")
     ap.add_argument("--no-hasenbusch", action="store_true", help="skip the 32^3x64 Hasenbusch MD-step leg")
+    ap.add_argument("--improved-steps", type=int, default=2,
+                    help="FG trajectories with the tree-level Symanzik gauge action (0: skip)")
     ap.add_argument("--fg-start", type=int, default=1, choices=[0, 1],
                     help="1: the displaced force's solve of an FG stage starts from the undisplaced solution")
     ap.add_argument("--exact-steps", type=int, default=2,
@@ -391,6 +393,47 @@ def tune_alpha_leg(R, U_therm, k, n):
                 dH={"0.1932": dh0, "tuned": dh1}, seconds=time.perf_counter() - t0)
 
 
+# SU(3) products per link of the rectangle force: 18 five-link staples (4 products
+# each) and U A; 198 flops per 3x3 complex product (27 complex multiply-adds)
+RECT_FORCE_FLOPS_PER_LINK = (18 * 4 + 1) * 198
+FP64_PEAK_TFLOPS = 78.6
+
+
+def improved_gauge_leg(R, U_therm, act_fg, inputs, n, steps, c1=-1.0 / 12.0):
+    """FG trajectories with the tree-level Symanzik gauge action (plaquettes
+    at 1 - 8 c1, rectangles at c1) on the same starts as the first timed
+    Wilson trajectories, and the rectangle force kernel timed alone: the total
+    gauge force with and without the rectangle term, HIP events on the
+    library's stream around 20 calls each (the difference is the rectangle
+    kernel; packing and the plaquette kernel are common to both)."""
+    torch = R.torch
+    act = dataclasses.replace(act_fg, c1=c1)
+    recs, sec, _ = R.run_leg(U_therm, act, "FG", n, inputs[:steps])
+    out = summarise(recs)
+    out.update(c1=c1, n=n, trajectories=steps, s_per_traj=sec / steps, dH=[r["dH"] for r in recs])
+    F = torch.empty((4, int(np.prod(R.dims)), 8), dtype=torch.float64, device=R.dev)
+    ms = {}
+    for key, cc in (("wilson", 0.0), ("improved", c1)):
+        a = R.fgi.Action(beta=R.args.beta, c1=cc)
+        R.ctx.force(R.dims, a, U_therm, F=F)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            R.ctx.force(R.dims, a, U_therm, F=F)
+        e1.record()
+        torch.cuda.synchronize()
+        ms[key] = e0.elapsed_time(e1) / 20
+    t_rect = (ms["improved"] - ms["wilson"]) * 1e-3
+    links = 4 * int(np.prod(R.dims))
+    tf = RECT_FORCE_FLOPS_PER_LINK * links / t_rect / 1e12 if t_rect > 0 else None
+    out.update(gauge_force_call_ms=dict(wilson=round(ms["wilson"], 4), improved=round(ms["improved"], 4)),
+               rect_force_kernel=dict(bound="alu", us=round(t_rect * 1e6, 2), flops_per_link=RECT_FORCE_FLOPS_PER_LINK,
+                                      achieved_TFLOPs=round(tf, 2) if tf else None, peak_TFLOPs=FP64_PEAK_TFLOPS,
+                                      frac=round(tf / FP64_PEAK_TFLOPS, 4) if tf else None))
+    return out
+
+
 def summarise(recs):
     dh = np.array([r["dH"] for r in recs])
     return dict(mean_dH=float(dh.mean()), mean_dH2=float((dh ** 2).mean()),
@@ -629,6 +672,16 @@ def main():
             "%.3e -> %.3e" % (args.n_omelyan, args.tune_alpha, alpha_leg["alpha_tuned"],
                               alpha_leg["predicted_dH2"]["0.1932"], alpha_leg["predicted_dH2"]["tuned"],
                               alpha_leg["measured_dH2"]["0.1932"], alpha_leg["measured_dH2"]["tuned"]))
+    improved = None
+    if args.improved_steps > 0:
+        R.apply(tune_fg)
+        k = min(args.improved_steps, args.steps)
+        improved = improved_gauge_leg(R, U, act_fg, inputs[args.warmup:args.warmup + k], args.n_fg, k)
+        log("FG-%s Symanzik gauge action (c1=-1/12) n=%d: %.4f s/traj (Wilson %.4f), dH=%s; gauge force call "
+            "%.3f ms -> %.3f ms, rectangle kernel %.1f us = %.1f TFLOP/s FP64" %
+            (args.prec, args.n_fg, improved["s_per_traj"], s_per_traj, ["%+.3e" % d for d in improved["dH"]],
+             improved["gauge_force_call_ms"]["wilson"], improved["gauge_force_call_ms"]["improved"],
+             improved["rect_force_kernel"]["us"], improved["rect_force_kernel"]["achieved_TFLOPs"] or 0))
     batched = None
     if not args.no_batched:
         batched = batched_leg(R, args.prec, 8, args.batched_steps)
@@ -658,7 +711,7 @@ def main():
                fg=fg, fg_exact=exact, lf_fp64=lf,
                speedup_vs_lf_fp64=(round(lf["s_per_traj"] / s_per_traj, 3) if lf else None),
                roofline=roof, roofline_32x32x32x64=large, hasenbusch_32x32x32x64=hasen, batched=batched,
-               alpha_tuning=alpha_leg,
+               alpha_tuning=alpha_leg, improved_gauge=improved,
                cpu_baseline=cpu)
     print(json.dumps(out), flush=True)
 
