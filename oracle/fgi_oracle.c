@@ -930,6 +930,227 @@ void oracle_hasen_force_add(const int L[4], double kappa, double kappa2, const c
 }
 
 /* ------------------------------------------------------------------ */
+/* stout smearing of the links the fermions see                       */
+/* (Morningstar and Peardon, Phys. Rev. D 69 (2004) 054501)           */
+/* ------------------------------------------------------------------ */
+
+/* exp of an n x n complex matrix (row-major) by Taylor series with scaling and
+ * squaring, as mat_exp: scaled to Frobenius norm below 1/8, 24 terms. */
+static void matn_exp(int n, const cplx *X, cplx *out) {
+    cplx *Y = malloc(sizeof(cplx) * n * n), *term = malloc(sizeof(cplx) * n * n);
+    cplx *tmp = malloc(sizeof(cplx) * n * n);
+    double nrm = 0;
+    for (int k = 0; k < n * n; k++) nrm += creal(X[k] * conj(X[k]));
+    nrm = sqrt(nrm);
+    int s = 0;
+    while (nrm > 0.125) { nrm *= 0.5; s++; }
+    for (int k = 0; k < n * n; k++) Y[k] = X[k] * ldexp(1.0, -s);
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) out[i * n + j] = term[i * n + j] = (i == j);
+    for (int m = 1; m <= 24; m++) {
+        for (int i = 0; i < n; i++)
+            for (int j = 0; j < n; j++) {
+                cplx a = 0;
+                for (int k = 0; k < n; k++) a += term[i * n + k] * Y[k * n + j];
+                tmp[i * n + j] = a / m;
+            }
+        for (int k = 0; k < n * n; k++) { term[k] = tmp[k]; out[k] += tmp[k]; }
+    }
+    for (int r = 0; r < s; r++) {
+        for (int i = 0; i < n; i++)
+            for (int j = 0; j < n; j++) {
+                cplx a = 0;
+                for (int k = 0; k < n; k++) a += out[i * n + k] * out[k * n + j];
+                tmp[i * n + j] = a;
+            }
+        memcpy(out, tmp, sizeof(cplx) * n * n);
+    }
+    free(Y); free(term); free(tmp);
+}
+
+/* derivative of exp at A along B: d/dt exp(A + t B) at t = 0, the upper right
+ * block of exp([[A, B], [0, A]]) */
+static mat3 dexp(mat3 A, mat3 B) {
+    cplx N[36], E[36];
+    memset(N, 0, sizeof N);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            N[i * 6 + j] = N[(i + 3) * 6 + j + 3] = A.m[i][j];
+            N[i * 6 + j + 3] = B.m[i][j];
+        }
+    matn_exp(6, N, E);
+    mat3 D;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) D.m[i][j] = E[i * 6 + j + 3];
+    return D;
+}
+
+/* The two staples of link (mu, x) in plane nu, as paths from x to x + mu:
+ * U_nu(x) U_mu(x+nu) U_nu(x+mu)^+ and U_nu(x-nu)^+ U_mu(x-nu) U_nu(x-nu+mu). */
+static void stout_paths(int mu, int nu, int up[3], int dn[3]) {
+    up[0] = nu + 1; up[1] = mu + 1; up[2] = -(nu + 1);
+    dn[0] = -(nu + 1); dn[1] = mu + 1; dn[2] = nu + 1;
+}
+
+/* C_mu(x) = rho * (sum of its 6 staples); with xi given, *dC its derivative
+ * under U_l -> exp(t xi_l) U_l (path_product) */
+static mat3 stout_C(const int L[4], double rho, const cplx *U, long i, int mu, const mat3 *xi, mat3 *dC) {
+    mat3 C = m_zero(), D = m_zero();
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == mu) continue;
+        int up[3], dn[3];
+        stout_paths(mu, nu, up, dn);
+        mat3 d1, d2;
+        C = m_add(C, path_product(L, U, i, up, 3, xi, xi ? &d1 : NULL));
+        C = m_add(C, path_product(L, U, i, dn, 3, xi, xi ? &d2 : NULL));
+        if (xi) D = m_add(D, m_add(d1, d2));
+    }
+    if (dC) *dC = m_scale(D, rho);
+    return m_scale(C, rho);
+}
+
+/* One stout level: Omega = C U^+, U' = exp(TA(Omega)) U on every link. */
+static void stout_level(const int L[4], double rho, const cplx *U, cplx *Up) {
+    long V = lat_volume(L);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int mu = 0; mu < 4; mu++)
+        for (long i = 0; i < V; i++) {
+            mat3 u = link_get(U, V, mu, i);
+            mat3 Om = m_mul(stout_C(L, rho, U, i, mu, NULL, NULL), m_dag(u));
+            link_put(Up, V, mu, i, m_mul(mat_exp(traceless_antiherm(Om)), u));
+        }
+}
+
+/* n levels of stout smearing with parameter rho (n = 0: a copy) */
+void oracle_stout_smear(const int L[4], double rho, int n, const cplx *U, cplx *Us) {
+    long V = lat_volume(L);
+    memcpy(Us, U, sizeof(cplx) * 4 * V * 9);
+    cplx *T = malloc(sizeof(cplx) * 4 * V * 9);
+    for (int k = 0; k < n; k++) {
+        stout_level(L, rho, Us, T);
+        memcpy(Us, T, sizeof(cplx) * 4 * V * 9);
+    }
+    free(T);
+}
+
+/* Tangent of one level: the links move as dU_l = xi_l U_l; the smeared links
+ * then move as dU'_l = xi'_l U'_l, with (product rule, then the derivative of
+ * exp) dC from the staples, dOmega = dC U^+ - Omega xi, dA = TA(dOmega),
+ * dU' = dexp_A(dA) U + exp(A) xi U. */
+static void stout_level_jvp(const int L[4], double rho, const cplx *U, const mat3 *xi, mat3 *xip) {
+    long V = lat_volume(L);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int mu = 0; mu < 4; mu++)
+        for (long i = 0; i < V; i++) {
+            long l = (long)mu * V + i;
+            mat3 u = link_get(U, V, mu, i), dC;
+            mat3 C = stout_C(L, rho, U, i, mu, xi, &dC);
+            mat3 Om = m_mul(C, m_dag(u));
+            mat3 dOm = m_add(m_mul(dC, m_dag(u)), m_scale(m_mul(Om, xi[l]), -1.0));
+            mat3 A = traceless_antiherm(Om), dA = traceless_antiherm(dOm);
+            mat3 E = mat_exp(A);
+            mat3 up = m_mul(E, u);
+            mat3 dup = m_add(m_mul(dexp(A, dA), u), m_mul(m_mul(E, xi[l]), u));
+            xip[l] = m_mul(dup, m_dag(up));
+        }
+}
+
+/* Adjoint of one level: given G' per smeared link (su(3), pairing
+ * <X, Y> = -2 Re Tr(X Y) = sum_a x_a y_a), G per input link with
+ * <G, xi> = <G', xi'> for every xi.  Per link l, with A = TA(Omega), E = exp(A),
+ * Gamma = exp(-A) dexp_A(G'_l) (the adjoint of the exp derivative):
+ *   G_l += E^+ G'_l E - TA(Gamma Omega),
+ * and, with M = rho U_l^+ Gamma, every link k on a staple S = Lf f R of C_l
+ * receives TA(U_k R M Lf) when it is a forward factor f = U_k and
+ * -TA(R M Lf U_k^+) when it is a backward one f = U_k^+. */
+static void stout_level_vjp(const int L[4], double rho, const cplx *U, const mat3 *Gp, mat3 *G) {
+    long V = lat_volume(L);
+    for (long l = 0; l < 4 * V; l++) G[l] = m_zero();
+    for (int mu = 0; mu < 4; mu++)
+        for (long i = 0; i < V; i++) {
+            long l = (long)mu * V + i;
+            mat3 u = link_get(U, V, mu, i);
+            mat3 Om = m_mul(stout_C(L, rho, U, i, mu, NULL, NULL), m_dag(u));
+            mat3 A = traceless_antiherm(Om), E = mat_exp(A);
+            mat3 Gam = m_mul(mat_exp(m_scale(A, -1.0)), dexp(A, Gp[l]));
+            G[l] = m_add(G[l], m_mul(m_mul(m_dag(E), Gp[l]), E));
+            G[l] = m_add(G[l], m_scale(traceless_antiherm(m_mul(Gam, Om)), -1.0));
+            mat3 M = m_scale(m_mul(m_dag(u), Gam), rho);
+            for (int nu = 0; nu < 4; nu++) {
+                if (nu == mu) continue;
+                int paths[2][3];
+                stout_paths(mu, nu, paths[0], paths[1]);
+                for (int w = 0; w < 2; w++) {
+                    /* the path's links and their orientation */
+                    long site[3];
+                    int dir[3], fwd[3];
+                    long y = i;
+                    for (int k = 0; k < 3; k++) {
+                        int st = paths[w][k], d = abs(st) - 1;
+                        dir[k] = d; fwd[k] = st > 0;
+                        if (st > 0) { site[k] = y; y = lat_step(L, y, d, +1); }
+                        else { y = lat_step(L, y, d, -1); site[k] = y; }
+                    }
+                    mat3 f[3];
+                    for (int k = 0; k < 3; k++) {
+                        mat3 uk = link_get(U, V, dir[k], site[k]);
+                        f[k] = fwd[k] ? uk : m_dag(uk);
+                    }
+                    for (int k = 0; k < 3; k++) {
+                        mat3 Lf = m_unit(), R = m_unit();
+                        for (int j = 0; j < k; j++) Lf = m_mul(Lf, f[j]);
+                        for (int j = k + 1; j < 3; j++) R = m_mul(R, f[j]);
+                        long lk = (long)dir[k] * V + site[k];
+                        mat3 uk = link_get(U, V, dir[k], site[k]);
+                        mat3 RML = m_mul(m_mul(R, M), Lf);
+                        if (fwd[k]) G[lk] = m_add(G[lk], traceless_antiherm(m_mul(uk, RML)));
+                        else G[lk] = m_add(G[lk], m_scale(traceless_antiherm(m_mul(RML, m_dag(uk))), -1.0));
+                    }
+                }
+            }
+        }
+}
+
+/* The n levels U_0 = U, U_{k+1} = stout(U_k), stored consecutively in Ul
+ * (n + 1 fields); returns Ul. */
+static cplx *stout_levels(const int L[4], double rho, int n, const cplx *U) {
+    long V = lat_volume(L), sz = 4 * V * 9;
+    cplx *Ul = malloc(sizeof(cplx) * sz * (n + 1));
+    memcpy(Ul, U, sizeof(cplx) * sz);
+    for (int k = 0; k < n; k++) stout_level(L, rho, Ul + k * sz, Ul + (k + 1) * sz);
+    return Ul;
+}
+
+/* Tangent of n levels: v (components per thin link) -> vout (per smeared link) */
+void oracle_stout_jvp(const int L[4], double rho, int n, const cplx *U, const double *v, double *vout) {
+    long V = lat_volume(L), sz = 4 * V * 9;
+    cplx *Ul = stout_levels(L, rho, n, U);
+    mat3 *a = malloc(sizeof(mat3) * 4 * V), *b = malloc(sizeof(mat3) * 4 * V);
+    for (long l = 0; l < 4 * V; l++) a[l] = alg_from_components(v + l * 8);
+    for (int k = 0; k < n; k++) {
+        stout_level_jvp(L, rho, Ul + k * sz, a, b);
+        mat3 *t = a; a = b; b = t;
+    }
+    for (long l = 0; l < 4 * V; l++) alg_components(traceless_antiherm(a[l]), vout + l * 8);
+    free(Ul); free(a); free(b);
+}
+
+/* Adjoint of n levels: g (components per smeared link) -> gout (per thin link).
+ * With g = the force on the smeared links, gout is the force on the thin ones. */
+void oracle_stout_vjp(const int L[4], double rho, int n, const cplx *U, const double *g, double *gout) {
+    long V = lat_volume(L), sz = 4 * V * 9;
+    cplx *Ul = stout_levels(L, rho, n, U);
+    mat3 *a = malloc(sizeof(mat3) * 4 * V), *b = malloc(sizeof(mat3) * 4 * V);
+    for (long l = 0; l < 4 * V; l++) a[l] = alg_from_components(g + l * 8);
+    for (int k = n - 1; k >= 0; k--) {
+        stout_level_vjp(L, rho, Ul + k * sz, a, b);
+        mat3 *t = a; a = b; b = t;
+    }
+    for (long l = 0; l < 4 * V; l++) alg_components(a[l], gout + l * 8);
+    free(Ul); free(a); free(b);
+}
+
+/* ------------------------------------------------------------------ */
 /* total force and integrator                                          */
 /* ------------------------------------------------------------------ */
 
@@ -939,7 +1160,17 @@ typedef struct {
     int fermions;    /* 0: pure gauge */
     int fg_exact;    /* G stages: 0 displacement form, 1 exact form */
     double c1;       /* rectangle coefficient of the gauge action */
+    double stout_rho;
+    int stout_n;     /* stout levels of the links the fermions see (0: thin links) */
 } oracle_action;
+
+/* the links the fermion operator sees: a new smeared copy, or NULL for U itself */
+static cplx *fermion_links(const int L[4], const oracle_action *act, const cplx *U) {
+    if (act->stout_n <= 0) return NULL;
+    cplx *Us = malloc(sizeof(cplx) * 4 * lat_volume(L) * 9);
+    oracle_stout_smear(L, act->stout_rho, act->stout_n, U, Us);
+    return Us;
+}
 
 typedef struct {
     long solves, cg_iters, cg_fail;
@@ -957,14 +1188,25 @@ static void total_force_from(const int L[4], const oracle_action *act, const cpl
                              double *F, oracle_stats *st, cplx *Xout, const cplx *X0) {
     oracle_gauge_force(L, act->beta, act->c1, U, F);
     if (!act->fermions) return;
-    long Vh = lat_volume(L) / 2;
+    long V = lat_volume(L), Vh = V / 2;
+    cplx *Us = fermion_links(L, act, U);
+    const cplx *Uf = Us ? Us : U;
     cplx *X = malloc(sizeof(cplx) * 12 * Vh);
     if (X0) memcpy(X, X0, sizeof(cplx) * 12 * Vh);
-    int it = oracle_cg_from(L, act->kappa, U, phi, X, act->cg_tol, act->cg_maxiter, NULL, X0 != NULL);
+    int it = oracle_cg_from(L, act->kappa, Uf, phi, X, act->cg_tol, act->cg_maxiter, NULL, X0 != NULL);
     add_solve(st, act, it);
-    oracle_fermion_force_add(L, act->kappa, U, X, 1.0, F);
+    if (Us) {
+        /* the force on the smeared links, carried back to the thin ones */
+        double *Ff = calloc(4 * V * 8, sizeof(double)), *G = malloc(sizeof(double) * 4 * V * 8);
+        oracle_fermion_force_add(L, act->kappa, Us, X, 1.0, Ff);
+        oracle_stout_vjp(L, act->stout_rho, act->stout_n, U, Ff, G);
+        for (long k = 0; k < 4 * V * 8; k++) F[k] += G[k];
+        free(Ff); free(G);
+    } else {
+        oracle_fermion_force_add(L, act->kappa, U, X, 1.0, F);
+    }
     if (Xout) memcpy(Xout, X, sizeof(cplx) * 12 * Vh);
-    free(X);
+    free(X); free(Us);
 }
 
 static void total_force_x(const int L[4], const oracle_action *act, const cplx *U, const cplx *phi,
@@ -992,7 +1234,7 @@ static void total_force_tangent(const int L[4], const oracle_action *act, const 
 void oracle_force_tangent(const int L[4], double beta, double kappa, int fermions, double cg_tol,
                           int cg_maxiter, const cplx *U, const cplx *phi, const double *v, double *J,
                           long *stats3, double c1) {
-    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 1, c1};
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 1, c1, 0.0, 0};
     oracle_stats st = {0, 0, 0};
     long V = lat_volume(L), Vh = V / 2;
     cplx *X = fermions ? malloc(sizeof(cplx) * 12 * Vh) : NULL;
@@ -1004,8 +1246,9 @@ void oracle_force_tangent(const int L[4], double beta, double kappa, int fermion
 }
 
 void oracle_force(const int L[4], double beta, double kappa, int fermions, double cg_tol,
-                  int cg_maxiter, const cplx *U, const cplx *phi, double *F, long *stats3, double c1) {
-    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 0, c1};
+                  int cg_maxiter, const cplx *U, const cplx *phi, double *F, long *stats3, double c1,
+                  double stout_rho, int stout_n) {
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 0, c1, stout_rho, stout_n};
     oracle_stats st = {0, 0, 0};
     total_force(L, &act, U, phi, F, &st);
     if (stats3) { stats3[0] = st.solves; stats3[1] = st.cg_iters; stats3[2] = st.cg_fail; }
@@ -1038,8 +1281,9 @@ int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, d
                       int cg_maxiter, int fg_exact, int nstages, const char *kinds,
                       const double *ws, const double *xis, double tau, int nsteps, cplx *U,
                       double *P, const cplx *eta, const cplx *phi_in, double *dH, long *stats3, int fg_start,
-                      double c1) {
-    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, fg_exact, c1};
+                      double c1, double stout_rho, int stout_n) {
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, fg_exact, c1, stout_rho, stout_n};
+    if (fg_exact && fermions && stout_n > 0) return -2;
     oracle_stats st = {0, 0, 0};
     long V = lat_volume(L), Vh = V / 2;
     double dt = tau / nsteps;
@@ -1070,18 +1314,21 @@ int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, d
         phi = malloc(sizeof(cplx) * 12 * Vh);
         hf0 = malloc(sizeof(double) * Vh);
         hf1 = malloc(sizeof(double) * Vh);
+        cplx *Us = fermion_links(L, &act, U);
+        const cplx *Uf = Us ? Us : U;
         if (eta) {
-            oracle_pf_heatbath(L, kappa, U, eta, phi);
+            oracle_pf_heatbath(L, kappa, Uf, eta, phi);
             for (long k = 0; k < Vh; k++) hf0[k] = vdot_re(12, eta + k * 12, eta + k * 12);
         } else {
             cplx *X0 = malloc(sizeof(cplx) * 12 * Vh);
             memcpy(phi, phi_in, sizeof(cplx) * 12 * Vh);
-            int it = oracle_cg(L, kappa, U, phi, X0, cg_tol, cg_maxiter, NULL);
+            int it = oracle_cg(L, kappa, Uf, phi, X0, cg_tol, cg_maxiter, NULL);
             st.solves++;
             if (it < 0) { st.cg_fail++; st.cg_iters += cg_maxiter; } else st.cg_iters += it;
             pf_density(Vh, phi, X0, hf0);
             free(X0);
         }
+        free(Us);
     }
 
     for (int s = 0; s < n; s++) {
@@ -1115,7 +1362,9 @@ int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, d
     int status = 0;
     if (fermions) {
         cplx *X = malloc(sizeof(cplx) * 12 * Vh);
-        int it = oracle_cg(L, kappa, U, phi, X, cg_tol, cg_maxiter, NULL);
+        cplx *Us = fermion_links(L, &act, U);
+        int it = oracle_cg(L, kappa, Us ? Us : U, phi, X, cg_tol, cg_maxiter, NULL);
+        free(Us);
         st.solves++;
         if (it < 0) { st.cg_fail++; st.cg_iters += cg_maxiter; } else st.cg_iters += it;
         pf_density(Vh, phi, X, hf1);
@@ -1285,9 +1534,9 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
  *         difference with step h (needs two force evaluations).         */
 void oracle_brackets(const int L[4], double beta, double kappa, int fermions, double cg_tol,
                      int cg_maxiter, const cplx *U, const double *P, const cplx *phi, double h,
-                     double *SST, double *TST, double c1) {
+                     double *SST, double *TST, double c1, double stout_rho, int stout_n) {
     long V = lat_volume(L), n = 4 * V * 8;
-    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 0, c1};
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 0, c1, stout_rho, stout_n};
     oracle_stats st = {0, 0, 0};
     double *F = malloc(sizeof(double) * n);
     cplx *Ud = malloc(sizeof(cplx) * 4 * V * 9);
@@ -1389,7 +1638,7 @@ double oracle_metropolis_uniform(uint64_t seed, uint32_t traj) {
 int oracle_hmc_run(const int L[4], double beta, double kappa, int fermions, double cg_tol, int cg_maxiter,
                    int fg_exact, int nstages, const char *kinds, const double *ws, const double *xis, double tau,
                    int nsteps, cplx *U, uint64_t seed, uint32_t traj0, int ntraj, int metropolis, double *dH,
-                   int *acc, double *plaq, int fg_start, double c1) {
+                   int *acc, double *plaq, int fg_start, double c1, double stout_rho, int stout_n) {
     long V = lat_volume(L), Vh = V / 2;
     double *P = malloc(sizeof(double) * 4 * V * 8);
     cplx *Ut = malloc(sizeof(cplx) * 4 * V * 9);
@@ -1402,7 +1651,7 @@ int oracle_hmc_run(const int L[4], double beta, double kappa, int fermions, doub
         double d = 0.0;
         long st3[3];
         int rc = oracle_trajectory(L, beta, kappa, fermions, cg_tol, cg_maxiter, fg_exact, nstages, kinds, ws, xis,
-                                   tau, nsteps, Ut, P, eta, NULL, &d, st3, fg_start, c1);
+                                   tau, nsteps, Ut, P, eta, NULL, &d, st3, fg_start, c1, stout_rho, stout_n);
         if (rc) status = rc;
         int a = !metropolis || oracle_metropolis_uniform(seed, t) < exp(-d);
         if (a) memcpy(U, Ut, sizeof(cplx) * 4 * V * 9);

@@ -74,14 +74,14 @@ def _declare(L):
     L.oracle_pf_action.argtypes = [_ip, _d, _vp, _vp, _d, _i, _ip]
     L.oracle_pf_action.restype = _d
     L.oracle_fermion_force_add.argtypes = [_ip, _d, _vp, _vp, _d, _vp]
-    L.oracle_force.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _lp, _d]
+    L.oracle_force.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _lp, _d, _d, _i]
     L.oracle_force_tangent.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _vp, _lp, _d]
     L.oracle_fermion_force_tangent_add.argtypes = [_ip, _d, _vp, _vp, _vp, _d, _i, _d, _vp]
     L.oracle_fermion_force_tangent_add.restype = _i
     L.oracle_trajectory.argtypes = [_ip, _d, _d, _i, _d, _i, _i, _i, ctypes.c_char_p, _vp, _vp,
-                                    _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i, _d]
+                                    _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i, _d, _d, _i]
     L.oracle_trajectory.restype = _i
-    L.oracle_brackets.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _d, _dp, _dp, _d]
+    L.oracle_brackets.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _d, _dp, _dp, _d, _d, _i]
     L.oracle_hasen_heatbath.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _d, _i]
     L.oracle_hasen_heatbath.restype = _i
     L.oracle_hasen_action.argtypes = [_ip, _d, _d, _vp, _vp, _d, _i, _vp, _ip]
@@ -95,10 +95,13 @@ def _declare(L):
     L.oracle_metropolis_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
     L.oracle_metropolis_uniform.restype = _d
     L.oracle_hmc_run.argtypes = [_ip, _d, _d, _i, _d, _i, _i, _i, ctypes.c_char_p, _vp, _vp, _d, _i, _vp,
-                                 ctypes.c_uint64, ctypes.c_uint32, _i, _i, _vp, _vp, _vp, _i, _d]
+                                 ctypes.c_uint64, ctypes.c_uint32, _i, _i, _vp, _vp, _vp, _i, _d, _d, _i]
     L.oracle_cg_from.argtypes = [_ip, _d, _vp, _vp, _vp, _d, _i, _dp, _i]
     L.oracle_cg_from.restype = _i
     L.oracle_hmc_run.restype = _i
+    L.oracle_stout_smear.argtypes = [_ip, _d, _i, _vp, _vp]
+    L.oracle_stout_jvp.argtypes = [_ip, _d, _i, _vp, _vp, _vp]
+    L.oracle_stout_vjp.argtypes = [_ip, _d, _i, _vp, _vp, _vp]
 
 
 def _dims(dims):
@@ -251,15 +254,16 @@ def cg_from(dims, kappa, U, phi, x0, tol=1e-10, maxiter=10000):
     return X, it, rel.value
 
 
-def force(dims, beta, U, kappa=0.0, phi=None, tol=1e-14, maxiter=10000, c1=0.0):
-    """total force F = F_G (+ F_F when phi is given); returns (F, stats)"""
+def force(dims, beta, U, kappa=0.0, phi=None, tol=1e-14, maxiter=10000, c1=0.0, stout_rho=0.0, stout_n=0):
+    """total force F = F_G (+ F_F when phi is given, on stout_n levels of
+    stout-smeared links, carried back to the thin links); returns (F, stats)"""
     U = _c(U, np.complex128)
     F = np.zeros((4, volume(dims), 8))
     st = (ctypes.c_long * 3)()
     ferm = phi is not None
     phi_a = _c(phi, np.complex128) if ferm else None
     lib().oracle_force(_dims(dims), beta, kappa, int(ferm), tol, maxiter, _ptr(U),
-                       _ptr(phi_a) if ferm else None, _ptr(F), st, c1)
+                       _ptr(phi_a) if ferm else None, _ptr(F), st, c1, stout_rho, int(stout_n))
     return F, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2])
 
 
@@ -289,7 +293,7 @@ def fermion_force_tangent(dims, kappa, U, X, V, tol=1e-14, maxiter=10000):
 
 
 def trajectory(dims, beta, stages, tau, nsteps, U, P, kappa=0.0, eta=None, tol=1e-14,
-               maxiter=10000, fg_exact=False, phi=None, fg_start=True, c1=0.0):
+               maxiter=10000, fg_exact=False, phi=None, fg_start=True, c1=0.0, stout_rho=0.0, stout_n=0):
     """One MD trajectory.  stages: list of (kind, w, xi) with kind in 'PQG'.
     Fermions: give eta (phi = Mhat^+ eta) or phi itself.  fg_start: the
     displaced force's solve of a G stage starts from the undisplaced solution.
@@ -309,11 +313,12 @@ def trajectory(dims, beta, stages, tau, nsteps, U, P, kappa=0.0, eta=None, tol=1
                                      tau, nsteps, _ptr(U), _ptr(P),
                                      _ptr(eta_a) if eta_a is not None else None,
                                      _ptr(phi_a) if phi_a is not None else None,
-                                     ctypes.byref(dH), st, int(bool(fg_start)), c1)
+                                     ctypes.byref(dH), st, int(bool(fg_start)), c1, stout_rho, int(stout_n))
     return U, P, dH.value, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2]), status
 
 
-def brackets(dims, beta, U, P, kappa=0.0, phi=None, h=1e-4, tol=1e-14, maxiter=10000, c1=0.0):
+def brackets(dims, beta, U, P, kappa=0.0, phi=None, h=1e-4, tol=1e-14, maxiter=10000, c1=0.0, stout_rho=0.0,
+             stout_n=0):
     """(SST, TST) = ({S,{S,T}}, {T,{S,T}}) at (U, P); TST by central difference."""
     U = _c(U, np.complex128)
     P = _c(P, np.float64)
@@ -322,7 +327,8 @@ def brackets(dims, beta, U, P, kappa=0.0, phi=None, h=1e-4, tol=1e-14, maxiter=1
     sst = ctypes.c_double(0)
     tst = ctypes.c_double(0)
     lib().oracle_brackets(_dims(dims), beta, kappa, int(ferm), tol, maxiter, _ptr(U), _ptr(P),
-                          _ptr(phi_a) if ferm else None, h, ctypes.byref(sst), ctypes.byref(tst), c1)
+                          _ptr(phi_a) if ferm else None, h, ctypes.byref(sst), ctypes.byref(tst), c1, stout_rho,
+                          int(stout_n))
     return sst.value, tst.value
 
 
@@ -379,6 +385,36 @@ def trajectory_nested(dims, beta, levels, tau, nsteps, U, P, kappa=0.0, kappa2=0
 
 
 # ---------------------------------------------------------------------------
+# stout smearing (Morningstar and Peardon 2004)
+# ---------------------------------------------------------------------------
+
+def stout_smear(dims, rho, n, U):
+    """n levels of U <- exp(TA(C U^+)) U, C = rho * (sum of the 6 staples)"""
+    U = _c(U, np.complex128)
+    out = np.empty_like(U)
+    lib().oracle_stout_smear(_dims(dims), rho, n, _ptr(U), _ptr(out))
+    return out
+
+
+def stout_jvp(dims, rho, n, U, v):
+    """tangent of the smearing: thin-link su(3) components v -> smeared-link components"""
+    U = _c(U, np.complex128)
+    v = _c(v, np.float64)
+    out = np.zeros_like(v)
+    lib().oracle_stout_jvp(_dims(dims), rho, n, _ptr(U), _ptr(v), _ptr(out))
+    return out
+
+
+def stout_vjp(dims, rho, n, U, g):
+    """adjoint of stout_jvp: a force on the smeared links -> the force on the thin links"""
+    U = _c(U, np.complex128)
+    g = _c(g, np.float64)
+    out = np.zeros_like(g)
+    lib().oracle_stout_vjp(_dims(dims), rho, n, _ptr(U), _ptr(g), _ptr(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Markov chain: Philox4x32-10 draws and the HMC accept/reject loop
 # ---------------------------------------------------------------------------
 
@@ -407,7 +443,7 @@ def metropolis_uniform(seed, traj):
 
 
 def hmc_run(dims, beta, stages, tau, nsteps, U, seed, traj0, ntraj, kappa=0.0, fermions=False, tol=1e-14,
-            maxiter=10000, fg_exact=False, metropolis=True, fg_start=True, c1=0.0):
+            maxiter=10000, fg_exact=False, metropolis=True, fg_start=True, c1=0.0, stout_rho=0.0, stout_n=0):
     """HMC chain of ntraj trajectories from U; returns (U_final, dH list, accepted list, plaquettes, status)."""
     U = np.array(U, dtype=np.complex128, copy=True, order="C")
     kinds = "".join(s[0] for s in stages).encode()
@@ -420,7 +456,7 @@ def hmc_run(dims, beta, stages, tau, nsteps, U, seed, traj0, ntraj, kappa=0.0, f
     status = lib().oracle_hmc_run(_dims(dims), beta, kappa, int(bool(fermions)), tol, maxiter, int(bool(fg_exact)),
                                   len(stages), kinds, _ptr(ws), _ptr(xis), tau, nsteps, _ptr(U), int(seed),
                                   int(traj0), int(ntraj), int(bool(metropolis)), _ptr(dH), _ptr(acc), _ptr(plaq),
-                                  int(bool(fg_start)), c1)
+                                  int(bool(fg_start)), c1, stout_rho, int(stout_n))
     k = int(ntraj)
     return U, list(dH[:k]), [bool(a) for a in acc[:k]], list(plaq[:k]), status
 

@@ -1,0 +1,193 @@
+"""Pins of the oracle's stout smearing (no GPU).
+
+Morningstar and Peardon's stout links: per level U' = exp(TA(Omega)) U with
+Omega = C U^+, C = rho * (sum of the six staples).  The fermion operator sees
+the smeared links; its force is carried back to the thin links by the adjoint
+of the smearing's tangent map.  The paper's conclusions name smearing among the
+settings its force-gradient construction covers.  Checks:
+
+  - one level against a numpy implementation over shifted link arrays with
+    scipy's expm (another enumeration and another exponential), two levels
+    as two applications of it; rho = 0 and n = 0 leave the links bitwise;
+  - smeared links are SU(3) and gauge covariant;
+  - the tangent map against central differences of the smearing;
+  - the adjoint identity <vjp(g), v> = <g, jvp(v)> for random g, v;
+  - the pseudofermion force through the smearing against central
+    differences of S_F(smear(U)) with respect to the thin links;
+  - trajectories: reversibility, dt^4 scaling of FG's dH, rho = 0 equal to
+    no smearing (to rounding; zero levels bitwise), the exact G stage refused
+    with smearing.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from paper_0910_2950_amd import synth
+from oracle.oracle import table
+
+T = 0.5j * synth.gell_mann()
+D1 = (4, 2, 2, 4)
+
+
+def rand_links(dims, seed):
+    return synth.haar_su3(synth.rng(seed), 4 * synth.volume(dims)).reshape(4, -1, 3, 3)
+
+
+def _dag(A):
+    return np.conj(np.swapaxes(A, -1, -2))
+
+
+def _ta(W):
+    A = 0.5 * (W - _dag(W))
+    return A - np.trace(A, axis1=-2, axis2=-1)[..., None, None] / 3 * np.eye(3)
+
+
+def numpy_stout_level(dims, rho, U):
+    Lx, Ly, Lz, Lt = dims
+    G = U.reshape(4, Lt, Lz, Ly, Lx, 3, 3)
+    at = lambda A, mu, k: np.roll(A, -k, axis=3 - mu)
+    out = np.empty_like(G)
+    for mu in range(4):
+        C = np.zeros_like(G[mu])
+        for nu in range(4):
+            if nu == mu:
+                continue
+            C += G[nu] @ at(G[mu], nu, 1) @ _dag(at(G[nu], mu, 1))
+            Gm = at(G[nu], nu, -1)
+            C += _dag(Gm) @ at(G[mu], nu, -1) @ at(at(G[nu], nu, -1), mu, 1)
+        X = _ta(rho * C @ _dag(G[mu]))
+        E = np.array([scipy.linalg.expm(x) for x in X.reshape(-1, 3, 3)]).reshape(X.shape)
+        out[mu] = E @ G[mu]
+    return out.reshape(U.shape)
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), D1, (6, 4, 2, 4)])
+def test_level_matches_numpy(orc, dims):
+    U = rand_links(dims, 500)
+    ref1 = numpy_stout_level(dims, 0.12, U)
+    assert np.max(np.abs(orc.stout_smear(dims, 0.12, 1, U) - ref1)) < 1e-13
+    ref2 = numpy_stout_level(dims, 0.12, ref1)
+    assert np.max(np.abs(orc.stout_smear(dims, 0.12, 2, U) - ref2)) < 1e-13
+
+
+def test_trivial_parameters_and_su3(orc):
+    U = rand_links(D1, 501)
+    assert np.array_equal(orc.stout_smear(D1, 0.0, 2, U), U)
+    assert np.array_equal(orc.stout_smear(D1, 0.1, 0, U), U)
+    Us = orc.stout_smear(D1, 0.15, 3, U)
+    assert np.max(np.abs(Us @ _dag(Us) - np.eye(3))) < 1e-13
+    assert np.max(np.abs(np.linalg.det(Us) - 1)) < 1e-13
+    # smoothing: the average plaquette rises
+    assert orc.plaquette(D1, Us) > orc.plaquette(D1, U) + 0.1
+
+
+def test_gauge_covariance(orc):
+    dims = D1
+    V = synth.volume(dims)
+    U = rand_links(dims, 502)
+    Om = synth.haar_su3(synth.rng(503), V)
+    c = np.stack(np.unravel_index(np.arange(V), dims[::-1])[::-1], axis=1)
+
+    def gt(W):
+        out = np.empty_like(W)
+        for mu in range(4):
+            cp = c.copy()
+            cp[:, mu] = (cp[:, mu] + 1) % dims[mu]
+            ip = cp[:, 0] + dims[0] * (cp[:, 1] + dims[1] * (cp[:, 2] + dims[2] * cp[:, 3]))
+            out[mu] = Om @ W[mu] @ _dag(Om[ip])
+        return out
+    assert np.max(np.abs(orc.stout_smear(dims, 0.1, 2, gt(U)) - gt(orc.stout_smear(dims, 0.1, 2, U)))) < 1e-13
+
+
+def _components(X):
+    return -2 * np.einsum("aij,...ji->...a", T, X).real
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_tangent_finite_difference(orc, n):
+    U = rand_links(D1, 504)
+    v = synth.rng(505).standard_normal((4, synth.volume(D1), 8))
+    J = orc.stout_jvp(D1, 0.1, n, U, v)
+    h = 1e-5
+    Up = orc.stout_smear(D1, 0.1, n, orc.link_update(D1, h, v, U))
+    Um = orc.stout_smear(D1, 0.1, n, orc.link_update(D1, -h, v, U))
+    xi = (Up - Um) / (2 * h) @ _dag(orc.stout_smear(D1, 0.1, n, U))
+    assert np.max(np.abs(_components(xi) - J)) < 1e-8 * np.max(np.abs(J))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_adjoint_identity(orc, n):
+    dims = (4, 4, 2, 2)
+    U = rand_links(dims, 506)
+    for k in range(3):
+        g = synth.rng(507 + k).standard_normal((4, synth.volume(dims), 8))
+        v = synth.rng(517 + k).standard_normal((4, synth.volume(dims), 8))
+        a = np.sum(orc.stout_vjp(dims, 0.13, n, U, g) * v)
+        b = np.sum(g * orc.stout_jvp(dims, 0.13, n, U, v))
+        assert abs(a - b) < 1e-12 * abs(b)
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_fermion_force_through_smearing(orc, n):
+    dims, kappa, rho = (4, 2, 2, 2), 0.155, 0.1
+    V = synth.volume(dims)
+    U = rand_links(dims, 520)
+    eta = synth.gaussian_noise(synth.rng(521), dims)
+    phi = orc.pf_heatbath(dims, kappa, orc.stout_smear(dims, rho, n, U), eta)
+
+    def S(W):
+        return orc.pf_action(dims, kappa, orc.stout_smear(dims, rho, n, W), phi, tol=1e-14)[0]
+    F, _ = orc.force(dims, 0.0, U, kappa=kappa, phi=phi, stout_rho=rho, stout_n=n)
+    h = 1e-5
+    for (mu, i) in [(0, 0), (1, 5), (3, V - 1), (2, V // 2 + 1)]:
+        fd = []
+        for a in range(8):
+            Up, Um = U.copy(), U.copy()
+            Up[mu, i] = scipy.linalg.expm(h * T[a]) @ U[mu, i]
+            Um[mu, i] = scipy.linalg.expm(-h * T[a]) @ U[mu, i]
+            fd.append(-(S(Up) - S(Um)) / (2 * h))
+        assert np.max(np.abs(np.array(fd) - F[mu, i])) < 1e-6 * np.max(np.abs(F[mu, i])), (mu, i)
+
+
+def _start(dims, seed):
+    U, P, eta, _ = synth.hot_start(dims, seed, fermions=True)
+    return U, P, eta
+
+
+@pytest.mark.parametrize("name", ["PQPQP", "FG"])
+def test_reversibility(orc, name):
+    dims = (4, 4, 2, 2)
+    U0, P0, eta = _start(dims, synth.SEED_BASE + 530)
+    phi = orc.pf_heatbath(dims, 0.155, orc.stout_smear(dims, 0.1, 2, U0), eta)
+    args = dict(kappa=0.155, phi=phi, tol=1e-14, stout_rho=0.1, stout_n=2)
+    U1, P1, dH, _, status = orc.trajectory(dims, 5.6, table(name), 1.0, 4, U0, P0, **args)
+    assert status == 0
+    U2, P2, dH2, _, _ = orc.trajectory(dims, 5.6, table(name), 1.0, 4, U1, -P1, **args)
+    assert np.max(np.abs(U2 - U0)) < 1e-11
+    assert np.max(np.abs(-P2 - P0)) < 1e-11 * np.max(np.abs(P0))
+    assert abs(dH + dH2) < 1e-9
+
+
+def test_fg_fourth_order_with_smearing(orc):
+    dims = (4, 4, 2, 2)
+    U0, P0, eta = _start(dims, synth.SEED_BASE + 531)
+    dh = []
+    for n in (8, 16):
+        _, _, d, _, _ = orc.trajectory(dims, 5.6, table("FG"), 1.0, n, U0, P0, kappa=0.155, eta=eta,
+                                       stout_rho=0.1, stout_n=2)
+        dh.append(abs(d))
+    assert abs(np.log2(dh[0] / dh[1]) - 4) < 0.3, dh
+
+
+def test_zero_rho_is_thin_links_and_exact_form_refused(orc):
+    dims = (4, 4, 2, 2)
+    U0, P0, eta = _start(dims, synth.SEED_BASE + 532)
+    a = orc.trajectory(dims, 5.6, table("FG"), 1.0, 3, U0, P0, kappa=0.155, eta=eta)
+    b = orc.trajectory(dims, 5.6, table("FG"), 1.0, 3, U0, P0, kappa=0.155, eta=eta, stout_rho=0.0, stout_n=2)
+    # equal up to the rounding of the force's round trip through su(3) matrices
+    assert np.max(np.abs(a[0] - b[0])) < 1e-13 and np.max(np.abs(a[1] - b[1])) < 1e-12 and abs(a[2] - b[2]) < 1e-11
+    z = orc.trajectory(dims, 5.6, table("FG"), 1.0, 3, U0, P0, kappa=0.155, eta=eta, stout_rho=0.1, stout_n=0)
+    assert np.array_equal(a[0], z[0]) and np.array_equal(a[1], z[1]) and a[2] == z[2]
+    c = orc.trajectory(dims, 5.6, table("FG"), 1.0, 3, U0, P0, kappa=0.155, eta=eta, fg_exact=True,
+                       stout_rho=0.1, stout_n=1)
+    assert c[4] == -2
