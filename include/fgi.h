@@ -88,6 +88,18 @@ typedef struct {
                            0 = Wilson, -1/12 tree-level Symanzik, -0.331 Iwasaki.
                            Forces, force gradients, brackets, trajectories and
                            chains all take it; batched chains need c1 = 0. */
+    double stout_rho;   /* stout smearing of the links the fermion operator sees
+                           (Morningstar-Peardon): 0 <= rho <= 0.5 ... */
+    int stout_n;        /* ... applied stout_n times (0 = thin links, at most 8).
+                           It applies where the library builds the fermion
+                           operator itself: fgi_force, fgi_poisson_brackets,
+                           fgi_trajectory(_packed), fgi_hmc_run; the fermion force
+                           on the smeared links is carried back to the thin links
+                           (fgi_stout_force).  Not with fg_exact (FGI_EINVAL), not
+                           for batched chains.  The operator-level entry points
+                           (dslash, mhat, cg_solve, pf_*, fermion_force, hasen_*)
+                           act on the links they are given. */
+    int pad;
 } fgi_action;
 
 /* One stage of an integrator step (Table 1), coefficients multiply the step h:
@@ -202,6 +214,20 @@ int fgi_kinetic(fgi_ctx* ctx, const fgi_geom* g, const void* P, double* T, void*
 /* ------------------------------------------- forces (Sections 2 and 4) */
 /* F = gauge force -e_a S_G on every link (momentum layout). */
 int fgi_gauge_force(fgi_ctx* ctx, const fgi_geom* g, double beta, const void* U, void* F, void* stream);
+/* ------------------------------------------------------- stout smearing */
+/* Us = n levels of stout smearing of U (Morningstar and Peardon, Phys. Rev. D
+ * 69 (2004) 054501): per level U' = exp(TA(Omega)) U, Omega = C U^+,
+ * C = rho * (sum of the six staples); the conclusions of the paper count
+ * smearing among the settings the force-gradient construction covers.
+ * Links layout in and out; 0 <= n <= 8, 0 <= rho <= 0.5, else FGI_EINVAL. */
+int fgi_stout_smear(fgi_ctx* ctx, const fgi_geom* g, double rho, int n, const void* U, void* Us, void* stream);
+/* F = the force on the thin links U of an action that depends on U only
+ * through its smearing, given Fs, that action's force on the smeared links
+ * (momentum layout; the adjoint of the smearing's tangent map, level by
+ * level).  Same limits as fgi_stout_smear. */
+int fgi_stout_force(fgi_ctx* ctx, const fgi_geom* g, double rho, int n, const void* U, const void* Fs, void* F,
+                    void* stream);
+
 /* J = d/dt F_G(exp(t V) U) at t = 0 for a field V of su(3) components
  * (momentum layout).  With V = F_G this is the gauge force gradient of
  * Section 4 that enters the Table 1 force-gradient stage. */

@@ -1065,7 +1065,9 @@ static void stout_level_jvp(const int L[4], double rho, const cplx *U, const mat
  * -TA(R M Lf U_k^+) when it is a backward one f = U_k^+. */
 static void stout_level_vjp(const int L[4], double rho, const cplx *U, const mat3 *Gp, mat3 *G) {
     long V = lat_volume(L);
-    for (long l = 0; l < 4 * V; l++) G[l] = m_zero();
+    mat3 *Ms = malloc(sizeof(mat3) * 4 * V);
+    /* the per-link terms (independent across links) */
+#pragma omp parallel for collapse(2) schedule(static)
     for (int mu = 0; mu < 4; mu++)
         for (long i = 0; i < V; i++) {
             long l = (long)mu * V + i;
@@ -1073,9 +1075,13 @@ static void stout_level_vjp(const int L[4], double rho, const cplx *U, const mat
             mat3 Om = m_mul(stout_C(L, rho, U, i, mu, NULL, NULL), m_dag(u));
             mat3 A = traceless_antiherm(Om), E = mat_exp(A);
             mat3 Gam = m_mul(mat_exp(m_scale(A, -1.0)), dexp(A, Gp[l]));
-            G[l] = m_add(G[l], m_mul(m_mul(m_dag(E), Gp[l]), E));
-            G[l] = m_add(G[l], m_scale(traceless_antiherm(m_mul(Gam, Om)), -1.0));
-            mat3 M = m_scale(m_mul(m_dag(u), Gam), rho);
+            G[l] = m_add(m_mul(m_mul(m_dag(E), Gp[l]), E), m_scale(traceless_antiherm(m_mul(Gam, Om)), -1.0));
+            Ms[l] = m_scale(m_mul(m_dag(u), Gam), rho);
+        }
+    /* the staple terms, scattered to the links of each staple in turn */
+    for (int mu = 0; mu < 4; mu++)
+        for (long i = 0; i < V; i++) {
+            mat3 M = Ms[(long)mu * V + i];
             for (int nu = 0; nu < 4; nu++) {
                 if (nu == mu) continue;
                 int paths[2][3];
@@ -1109,6 +1115,7 @@ static void stout_level_vjp(const int L[4], double rho, const cplx *U, const mat
                 }
             }
         }
+    free(Ms);
 }
 
 /* The n levels U_0 = U, U_{k+1} = stout(U_k), stored consecutively in Ul
@@ -1400,7 +1407,17 @@ typedef struct {
     oracle_stats st;
     int fg_start;        /* displaced solves start from the undisplaced solutions */
     cplx *X1, *X2;       /* the last solutions of the S_F (S_1) and S_2 solves */
+    double stout_rho;
+    int stout_n;         /* stout levels of the links the fermions see */
 } nested_run;
+
+/* the links the fermion terms see at W: a new smeared copy, or NULL for W */
+static cplx *nested_fermion_links(const nested_run *r, const cplx *W) {
+    if (r->stout_n <= 0) return NULL;
+    cplx *Ws = malloc(sizeof(cplx) * 4 * lat_volume(r->L) * 9);
+    oracle_stout_smear(r->L, r->stout_rho, r->stout_n, W, Ws);
+    return Ws;
+}
 
 static void count_solve(nested_run *r, int it) {
     r->st.solves++;
@@ -1419,18 +1436,30 @@ static void terms_force(nested_run *r, const cplx *W, int terms, double *F, int 
         for (long k = 0; k < 4 * V * 8; k++) F[k] += g[k];
         free(g);
     }
-    if (r->kappa == 0.0) return;
+    if (r->kappa == 0.0 || !(terms & (TERM_FERM | TERM_HASEN))) return;
+    /* with smearing the fermion forces are taken on the smeared links and
+     * carried back to W */
+    cplx *Ws = nested_fermion_links(r, W);
+    const cplx *Wf = Ws ? Ws : W;
+    double *Ff = Ws ? calloc(4 * V * 8, sizeof(double)) : F;
     if (terms & TERM_FERM) {
         double k1 = r->kappa2 != 0.0 ? r->kappa2 : r->kappa;
-        count_solve(r, oracle_cg_from(L, k1, W, r->phi1, r->X1, r->tol, r->maxiter, NULL, from_last));
-        oracle_fermion_force_add(L, k1, W, r->X1, 1.0, F);
+        count_solve(r, oracle_cg_from(L, k1, Wf, r->phi1, r->X1, r->tol, r->maxiter, NULL, from_last));
+        oracle_fermion_force_add(L, k1, Wf, r->X1, 1.0, Ff);
     }
     if ((terms & TERM_HASEN) && r->kappa2 != 0.0) {
         int it;
-        hasen_action_from(L, r->kappa, r->kappa2, W, r->phi2, r->tol, r->maxiter, r->X2, &it, from_last);
+        hasen_action_from(L, r->kappa, r->kappa2, Wf, r->phi2, r->tol, r->maxiter, r->X2, &it, from_last);
         count_solve(r, it);
-        oracle_hasen_force_add(L, r->kappa, r->kappa2, W, r->phi2, r->X2, 1.0, F);
+        oracle_hasen_force_add(L, r->kappa, r->kappa2, Wf, r->phi2, r->X2, 1.0, Ff);
     }
+    if (Ws) {
+        double *G = malloc(sizeof(double) * 4 * V * 8);
+        oracle_stout_vjp(L, r->stout_rho, r->stout_n, W, Ff, G);
+        for (long k = 0; k < 4 * V * 8; k++) F[k] += G[k];
+        free(G); free(Ff); free(Ws);
+    }
+    (void)Vh;
 }
 
 /* run level l for n steps of size h: the step table repeated n times with
@@ -1476,7 +1505,7 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
                              int cg_maxiter, int nlevels, const int *nstages, const int *terms, const int *nsub,
                              const char *kinds, const double *ws, const double *xis, double tau, int nsteps,
                              cplx *U, double *P, const cplx *eta1, const cplx *eta2, double *dH, long *stats3,
-                             int fg_start, double c1) {
+                             int fg_start, double c1, double stout_rho, int stout_n) {
     long V = lat_volume(L), Vh = V / 2;
     const char *kp[8];
     const double *wp[8], *xp[8];
@@ -1489,6 +1518,8 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
                     NULL, NULL, U, P, {0, 0, 0}, fg_start, NULL, NULL};
     r.X1 = calloc(12 * Vh, sizeof(cplx));
     r.X2 = calloc(12 * Vh, sizeof(cplx));
+    r.stout_rho = stout_rho;
+    r.stout_n = stout_n;
     cplx *phi1 = NULL, *phi2 = NULL;
     double *h0 = malloc(sizeof(double) * V), *h1 = malloc(sizeof(double) * V), *tmp = malloc(sizeof(double) * V);
     gauge_density(L, beta, c1, U, h0);
@@ -1496,14 +1527,17 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
     for (long i = 0; i < V; i++) h0[i] += tmp[i];
     double sf0 = 0.0;
     if (kappa != 0.0) {
+        cplx *Us = nested_fermion_links(&r, U);
+        const cplx *Uf = Us ? Us : U;
         phi1 = malloc(sizeof(cplx) * 12 * Vh);
-        oracle_pf_heatbath(L, kappa2 != 0.0 ? kappa2 : kappa, U, eta1, phi1);
+        oracle_pf_heatbath(L, kappa2 != 0.0 ? kappa2 : kappa, Uf, eta1, phi1);
         sf0 += vdot_re(12 * Vh, eta1, eta1);
         if (kappa2 != 0.0) {
             phi2 = malloc(sizeof(cplx) * 12 * Vh);
-            count_solve(&r, oracle_hasen_heatbath(L, kappa, kappa2, U, eta2, phi2, cg_tol, cg_maxiter));
+            count_solve(&r, oracle_hasen_heatbath(L, kappa, kappa2, Uf, eta2, phi2, cg_tol, cg_maxiter));
             sf0 += vdot_re(12 * Vh, eta2, eta2);
         }
+        free(Us);
     }
     r.phi1 = phi1;
     r.phi2 = phi2;
@@ -1514,13 +1548,16 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
     for (long i = 0; i < V; i++) d += (h1[i] + tmp[i]) - h0[i];
     if (kappa != 0.0) {
         int it;
-        double s1 = oracle_pf_action(L, kappa2 != 0.0 ? kappa2 : kappa, U, phi1, cg_tol, cg_maxiter, &it);
+        cplx *Us = nested_fermion_links(&r, U);
+        const cplx *Uf = Us ? Us : U;
+        double s1 = oracle_pf_action(L, kappa2 != 0.0 ? kappa2 : kappa, Uf, phi1, cg_tol, cg_maxiter, &it);
         count_solve(&r, it);
         if (kappa2 != 0.0) {
-            s1 += oracle_hasen_action(L, kappa, kappa2, U, phi2, cg_tol, cg_maxiter, NULL, &it);
+            s1 += oracle_hasen_action(L, kappa, kappa2, Uf, phi2, cg_tol, cg_maxiter, NULL, &it);
             count_solve(&r, it);
         }
         d += s1 - sf0;
+        free(Us);
     }
     *dH = d;
     if (stats3) { stats3[0] = r.st.solves; stats3[1] = r.st.cg_iters; stats3[2] = r.st.cg_fail; }

@@ -113,6 +113,8 @@ void check_action(const fgi_action* a) {
     if (a->kappa_hasen != 0 && (a->kappa == 0 || a->kappa_hasen >= a->kappa))
         throw Error(FGI_EINVAL, "Hasenbusch kappa' must satisfy 0 < kappa' < kappa");
     if (!std::isfinite(a->c1)) throw Error(FGI_EINVAL, "the rectangle coefficient c1 must be finite");
+    if (a->stout_n < 0 || a->stout_n > 8) throw Error(FGI_EINVAL, "stout_n must be in [0, 8]");
+    if (!(a->stout_rho >= 0.0 && a->stout_rho <= 0.5)) throw Error(FGI_EINVAL, "stout_rho must be in [0, 0.5]");
 }
 
 int sloppy_prec(const fgi_action* a) { return a->prec == FGI_FP64 ? P64 : (a->prec == FGI_MP32 ? P32 : P16); }
@@ -166,8 +168,29 @@ struct Fields {
         return r;
     }
 
+    // The links the fermion operator sees at thin links u: u itself, or its
+    // stout smearing (levels kept in c.stout_lev for the force's
+    // back-propagation) with a sloppy copy when the solves need one
+    struct FLinks {
+        const d2* u;
+        const void* us;
+    };
+    FLinks flinks(const d2* u, const void* us) {
+        if (act.stout_n <= 0) return {u, us};
+        d2* lev = (d2*)c.stout_lev.get(gauge_bytes(g) * act.stout_n);
+        const d2* top = stout_smear(c, g, act.stout_rho, act.stout_n, u, lev);
+        void* s = nullptr;
+        if (sp != P64) {
+            s = c.stout_sloppy.get(sloppy_bytes(g));
+            make_sloppy(c, g, top, s, sp, rc);
+        }
+        return {top, s};
+    }
+
     // out (+)= coef * F_terms(u); guess: the solves start from the solutions
-    // held in X, X2 (those of the previous force evaluation)
+    // held in X, X2 (those of the previous force evaluation).  With stout
+    // smearing the pseudofermion forces are taken on the smeared links and
+    // carried back to u.
     void force(const d2* u, const void* us, int terms, double* out, double coef, bool accumulate,
                bool guess = false) {
         bool have = accumulate;
@@ -182,19 +205,31 @@ struct Fields {
             return;
         }
         if (!have) zero_mom(out);
+        const bool smear = act.stout_n > 0;
+        const FLinks fl = flinks(u, us);
+        double* fo = out;
+        double fc = coef;
+        if (smear) {
+            fo = (double*)c.stout_F.get(mom_bytes(g));
+            zero_mom(fo);
+            fc = 1.0;
+        }
         const double k1 = act.kappa_hasen != 0.0 ? act.kappa_hasen : act.kappa;
         if (terms & FGI_TERM_FERMION) {
-            solve(u, us, k1, phi[0], X, guess);
-            fermion_force(c, op64(u, k1), X, out, coef);
+            solve(fl.u, fl.us, k1, phi[0], X, guess);
+            fermion_force(c, op64(fl.u, k1), X, fo, fc);
         }
         if ((terms & FGI_TERM_HASEN) && act.kappa_hasen != 0.0) {
             // S_2 = chi^+ (Mhat^+ Mhat)^-1 chi, chi = Mhat2^+ phi2: the ordinary force
             // of X2 at kappa plus -kappa2^2 TA(U C(X2, phi2)) from the U dependence of chi
-            hasen_solve(u, us, guess);
-            fermion_force(c, op64(u, act.kappa), X2, out, coef);
-            fermion_force_xy(c, op64(u, act.kappa_hasen), X2, phi[1], out,
-                             -coef * act.kappa_hasen * act.kappa_hasen);
+            hasen_solve(fl.u, fl.us, guess);
+            fermion_force(c, op64(fl.u, act.kappa), X2, fo, fc);
+            fermion_force_xy(c, op64(fl.u, act.kappa_hasen), X2, phi[1], fo,
+                             -fc * act.kappa_hasen * act.kappa_hasen);
         }
+        if (smear)
+            stout_backprop(c, g, act.stout_rho, act.stout_n, u, (const d2*)c.stout_lev.get(gauge_bytes(g) * act.stout_n),
+                           fo, out, coef, 1);
     }
 
     // J = J_V[F_terms](u) = d/dt F_terms(exp(t V) u) at t = 0: the gauge part
@@ -204,6 +239,8 @@ struct Fields {
         const bool ferm = act.kappa != 0.0 && (terms & (FGI_TERM_FERMION | FGI_TERM_HASEN));
         if (ferm && act.kappa_hasen != 0.0)
             throw Error(FGI_EINVAL, "the exact force gradient is not available for the Hasenbusch terms");
+        if (ferm && act.stout_n > 0)
+            throw Error(FGI_EINVAL, "the exact force gradient is not available with stout smearing");
         if (terms & FGI_TERM_GAUGE) gauge_force_tangent(c, g, act.beta, u, Vd, J, 1.0, 0, 0, act.c1);
         else zero_mom(J);
         if (!ferm) return;
@@ -225,8 +262,12 @@ struct Fields {
         solve(u, us, act.kappa, chi, X2, guess);
     }
 
-    // phi2 = Mhat2 (Mhat2^+ Mhat2)^-1 Mhat^+ eta2 at u (one solve at kappa2)
-    void hasen_heatbath(const d2* u, const void* us, const d2* eta2) {
+    // phi2 = Mhat2 (Mhat2^+ Mhat2)^-1 Mhat^+ eta2 at the fermion links of u
+    // (one solve at kappa2)
+    void hasen_heatbath(const d2* thin, const void* thin_s, const d2* eta2) {
+        const FLinks fl = flinks(thin, thin_s);
+        const d2* u = fl.u;
+        const void* us = fl.us;
         d2* t = (d2*)c.tmp_o.get(spinor_bytes(g));
         mhat(c, op64(u, act.kappa), P64, SpinorPtr{(void*)eta2, nullptr}, SpinorPtr{t, nullptr},
              SpinorPtr{chi, nullptr}, 1);
@@ -236,8 +277,12 @@ struct Fields {
     }
 
     // sum over the pseudofermion terms of Re phi^+ X - |eta|^2 (eta may be null):
-    // the fermion part of H at u minus its heatbath value
-    double pf_energy(const d2* u, const void* us, const d2* eta1, const d2* eta2, double* part, double* scal) {
+    // the fermion part of H at the fermion links of u minus its heatbath value
+    double pf_energy(const d2* thin, const void* thin_s, const d2* eta1, const d2* eta2, double* part,
+                     double* scal) {
+        const FLinks fl = flinks(thin, thin_s);
+        const d2* u = fl.u;
+        const void* us = fl.us;
         const double k1 = act.kappa_hasen != 0.0 ? act.kappa_hasen : act.kappa;
         solve(u, us, k1, phi[0], X);
         int nb = pf_density_partials(c, g, phi[0], X, eta1, part);
@@ -292,7 +337,8 @@ int fgi_destroy(fgi_ctx* ctx) {
                           &c.h0, &c.hf0, &c.partial, &c.scal, &c.state, &c.phi2, &c.eta2, &c.user_tmp,
                           &c.chi, &c.X2, &c.cdesc, &c.bstate, &c.bscal, &c.bh0, &c.bh1, &c.bres,
                           &c.gauge_tan, &c.tg_dmx, &c.tg_rhs, &c.tg_z, &c.tg_dxo, &c.tg_dye, &c.tg_dyo,
-                          &c.force3, &c.chain_U};
+                          &c.force3, &c.chain_U, &c.stout_lev, &c.stout_F, &c.stout_ga, &c.stout_gb,
+                          &c.stout_part, &c.stout_M, &c.stout_sloppy};
         for (DevBuf* b : bufs) b->release();
         for (hipEvent_t e : c.ev_pool) hipEventDestroy(e);
         for (GraphEntry& e : c.graphs) hipGraphExecDestroy(e.exec);
@@ -406,6 +452,53 @@ int fgi_gauge_force(fgi_ctx* ctx, const fgi_geom* gg, double beta, const void* U
         double* f = (double*)c.force.get(mom_bytes(g));
         pack_gauge(c, g, U, u);
         gauge_force(c, g, beta, u, f, 1.0, 0);
+        unpack_mom(c, g, f, (double*)F);
+    });
+}
+
+int fgi_stout_smear(fgi_ctx* ctx, const fgi_geom* gg, double rho, int n, const void* U, void* Us, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        if (n < 0 || n > 8 || !(rho >= 0.0 && rho <= 0.5)) throw Error(FGI_EINVAL, "need 0 <= n <= 8, 0 <= rho <= 0.5");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(Us, "Us", 16);
+        StreamScope ss(c, stream);
+        d2* u = (d2*)c.gauge.get(gauge_bytes(g));
+        pack_gauge(c, g, U, u);
+        if (n == 0) {
+            unpack_gauge(c, g, u, Us);
+            return;
+        }
+        d2* lev = (d2*)c.stout_lev.get(gauge_bytes(g) * n);
+        unpack_gauge(c, g, stout_smear(c, g, rho, n, u, lev), Us);
+    });
+}
+
+int fgi_stout_force(fgi_ctx* ctx, const fgi_geom* gg, double rho, int n, const void* U, const void* Fs, void* F,
+                    void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        if (n < 0 || n > 8 || !(rho >= 0.0 && rho <= 0.5)) throw Error(FGI_EINVAL, "need 0 <= n <= 8, 0 <= rho <= 0.5");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(Fs, "Fs", 8);
+        need(F, "F", 8);
+        StreamScope ss(c, stream);
+        d2* u = (d2*)c.gauge.get(gauge_bytes(g));
+        double* fs = (double*)c.force2.get(mom_bytes(g));
+        double* f = (double*)c.force.get(mom_bytes(g));
+        pack_gauge(c, g, U, u);
+        pack_mom(c, g, (const double*)Fs, fs);
+        if (n == 0) {
+            unpack_mom(c, g, fs, (double*)F);
+            return;
+        }
+        d2* lev = (d2*)c.stout_lev.get(gauge_bytes(g) * n);
+        stout_smear(c, g, rho, n, u, lev);
+        stout_backprop(c, g, rho, n, u, lev, fs, f, 1.0, 0);
         unpack_mom(c, g, f, (double*)F);
     });
 }
@@ -1007,6 +1100,8 @@ void check_trajectory_args(const fgi_action* act, const fgi_integrator* integ, i
     check_integrator(integ);
     if (act->fg_exact && act->kappa_hasen != 0)
         throw Error(FGI_EINVAL, "the exact force gradient is not available for the Hasenbusch terms");
+    if (act->fg_exact && act->kappa != 0 && act->stout_n > 0)
+        throw Error(FGI_EINVAL, "the exact force gradient is not available with stout smearing");
     if (nsteps < 1) throw Error(FGI_EINVAL, "nsteps must be >= 1");
     if (!std::isfinite(tau)) throw Error(FGI_EINVAL, "tau must be finite");
 }
@@ -1053,7 +1148,7 @@ double trajectory_packed(Fields& f, const fgi_integrator& integ, double tau, int
         if (phi_given) {
             sf0 = f.pf_energy(f.U, f.Us, nullptr, nullptr, part, scal);
         } else {
-            pf_heatbath(c, f.op64(f.U, k1), eta, f.phi[0]);
+            pf_heatbath(c, f.op64(f.flinks(f.U, f.Us).u, k1), eta, f.phi[0]);
             if (hasen) f.hasen_heatbath(f.U, f.Us, eta_2);
         }
     }
@@ -1419,6 +1514,7 @@ extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain
         if (act->kappa_hasen != 0.0) throw Error(FGI_EINVAL, "batched chains take one pseudofermion");
         if (act->fg_exact) throw Error(FGI_EINVAL, "batched chains use the displacement force-gradient form");
         if (act->c1 != 0.0) throw Error(FGI_EINVAL, "batched chains take the Wilson gauge action (c1 = 0)");
+        if (act->stout_n != 0) throw Error(FGI_EINVAL, "batched chains take thin fermion links (stout_n = 0)");
         const bool ferm = chains[0].kappa != 0.0;
         std::vector<ChainDesc> cd;
         Batch B;

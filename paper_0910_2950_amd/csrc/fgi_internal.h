@@ -97,6 +97,9 @@ struct Ctx {
     // force gradient of the pseudofermion force: tangent links and vectors
     DevBuf gauge_tan, tg_dmx, tg_rhs, tg_z, tg_dxo, tg_dye, tg_dyo, force3;
     DevBuf chain_U;   // the accepted links of an on-device Markov chain
+    // stout smearing: the smeared levels, the fermion force on the top level and
+    // its back-propagation scratch, the sloppy copy of the smeared links
+    DevBuf stout_lev, stout_F, stout_ga, stout_gb, stout_part, stout_M, stout_sloppy;
     DevBuf cdesc, bstate, bscal, bh0, bh1, bres;  // batched chains
     CGState* host_bstates = nullptr;          // pinned [host_b_cap]
     double* host_bscal = nullptr;             // pinned [host_b_cap]
@@ -186,6 +189,12 @@ void link_update(Ctx&, const Geom&, double h, const double* X, const d2* src, d2
                  int prec, int recon);
 // W = V U on every link (FP64 internal layout): the links of the derivative of D along V
 void tangent_links(Ctx&, const Geom&, const double* Vd, const d2* U, d2* W);
+// n stout levels of U into levels (n consecutive gauge fields); returns the top level
+const d2* stout_smear(Ctx&, const Geom&, double rho, int n, const d2* U, d2* levels);
+// F (+)= coef * (force on the thin links U) given the force Fs on the top smeared
+// level; levels as written by stout_smear for the same U
+void stout_backprop(Ctx&, const Geom&, double rho, int n, const d2* U, const d2* levels, const double* Fs,
+                    double* F, double coef, int accumulate);
 // y += a x over the 4 * 2 * 8 * Vh momentum components
 void mom_axpy(Ctx&, const Geom&, double a, const double* x, double* y);
 void reunitarize(Ctx&, const Geom&, d2* U);

@@ -39,7 +39,8 @@ class fgi_geom(ctypes.Structure):
 class fgi_action(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("kappa", ctypes.c_double), ("kappa_hasen", ctypes.c_double),
                 ("cg_tol", ctypes.c_double), ("cg_maxiter", ctypes.c_int), ("prec", ctypes.c_int),
-                ("link_recon", ctypes.c_int), ("fg_exact", ctypes.c_int), ("c1", ctypes.c_double)]
+                ("link_recon", ctypes.c_int), ("fg_exact", ctypes.c_int), ("c1", ctypes.c_double),
+                ("stout_rho", ctypes.c_double), ("stout_n", ctypes.c_int), ("pad", ctypes.c_int)]
 
 
 class fgi_stage(ctypes.Structure):
@@ -101,6 +102,8 @@ SIGNATURES = {
     "fgi_get_profile": (_i, [_vp, _P(_d), _P(ctypes.c_long), _P(ctypes.c_long)]),
     "fgi_gauge_action": (_i, [_vp, _P(fgi_geom), _d, _vp, _P(_d), _vp]),
     "fgi_improved_gauge_action": (_i, [_vp, _P(fgi_geom), _d, _d, _vp, _P(_d), _vp]),
+    "fgi_stout_smear": (_i, [_vp, _P(fgi_geom), _d, _i, _vp, _vp, _vp]),
+    "fgi_stout_force": (_i, [_vp, _P(fgi_geom), _d, _i, _vp, _vp, _vp, _vp]),
     "fgi_kinetic": (_i, [_vp, _P(fgi_geom), _vp, _P(_d), _vp]),
     "fgi_gauge_force": (_i, [_vp, _P(fgi_geom), _d, _vp, _vp, _vp]),
     "fgi_force_gradient": (_i, [_vp, _P(fgi_geom), _d, _vp, _vp, _vp, _vp]),
@@ -176,10 +179,13 @@ class Action:
     link_recon: int = 18
     fg_exact: bool = False
     c1: float = 0.0      # rectangle coefficient of the gauge action (0: Wilson)
+    stout_rho: float = 0.0
+    stout_n: int = 0     # stout levels of the links the fermion operator sees (0: thin links)
 
     def c(self):
         return fgi_action(self.beta, self.kappa, self.kappa_hasen, self.cg_tol, int(self.cg_maxiter),
-                          PREC[self.prec], int(self.link_recon), int(bool(self.fg_exact)), float(self.c1))
+                          PREC[self.prec], int(self.link_recon), int(bool(self.fg_exact)), float(self.c1),
+                          float(self.stout_rho), int(self.stout_n), 0)
 
 
 def integrator_builtin(which, alpha=0.1932):
@@ -280,6 +286,20 @@ class Context:
         _check(lib().fgi_improved_gauge_action(self.h, _geom(dims), beta, c1, _ptr(U, torch.complex128, su, "U"),
                                                ctypes.byref(S), _stream()))
         return S.value
+
+    def stout_smear(self, dims, rho, n, U, Us=None):
+        su, _, _ = self._shapes(dims)
+        Us = torch.empty(su, dtype=torch.complex128, device=U.device) if Us is None else Us
+        _check(lib().fgi_stout_smear(self.h, _geom(dims), rho, int(n), _ptr(U, torch.complex128, su, "U"),
+                                     _ptr(Us, torch.complex128, su, "Us"), _stream()))
+        return Us
+
+    def stout_force(self, dims, rho, n, U, Fs, F=None):
+        su, sp, _ = self._shapes(dims)
+        F = torch.empty(sp, dtype=torch.float64, device=U.device) if F is None else F
+        _check(lib().fgi_stout_force(self.h, _geom(dims), rho, int(n), _ptr(U, torch.complex128, su, "U"),
+                                     _ptr(Fs, torch.float64, sp, "Fs"), _ptr(F, torch.float64, sp, "F"), _stream()))
+        return F
 
     def kinetic(self, dims, P):
         _, sp, _ = self._shapes(dims)

@@ -191,3 +191,33 @@ def test_zero_rho_is_thin_links_and_exact_form_refused(orc):
     c = orc.trajectory(dims, 5.6, table("FG"), 1.0, 3, U0, P0, kappa=0.155, eta=eta, fg_exact=True,
                        stout_rho=0.1, stout_n=1)
     assert c[4] == -2
+
+
+def test_nested_driver_with_smearing_reduces_to_single_level(orc):
+    dims = (4, 4, 2, 2)
+    U0, P0, eta = _start(dims, synth.SEED_BASE + 533)
+    args = dict(kappa=0.155, stout_rho=0.12, stout_n=2)
+    a = orc.trajectory(dims, 5.6, table("FG"), 1.0, 3, U0, P0, eta=eta, **args)
+    b = orc.trajectory_nested(dims, 5.6, [(table("FG"), 7, 1)], 1.0, 3, U0, P0, eta1=eta, **args)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert abs(a[2] - b[2]) < 1e-10 and a[3]["solves"] == b[3]["solves"]
+
+
+def test_hasenbusch_with_smearing_reversible_and_fourth_order(orc):
+    """Both pseudofermion terms on smeared links, nested FG scales"""
+    dims = (4, 4, 2, 2)
+    U0, P0, _, _ = synth.hot_start(dims, synth.SEED_BASE + 534, fermions=False)
+    e1 = synth.gaussian_noise(synth.rng(535), dims)
+    e2 = synth.gaussian_noise(synth.rng(536), dims)
+    levels = [(table("FG"), 4, 1), (table("FG"), 2, 2), (table("FG"), 1, 2)]
+    args = dict(kappa=0.155, kappa2=0.14, eta1=e1, eta2=e2, stout_rho=0.1, stout_n=1)
+    dh = []
+    for n in (2, 4):
+        U1, P1, d, st, status = orc.trajectory_nested(dims, 5.6, levels, 1.0, n, U0, P0, **args)
+        assert status == 0
+        dh.append(abs(d))
+    assert abs(np.log2(dh[0] / dh[1]) - 4) < 0.5, dh
+    # the pure-gauge and smeared parts move together: smearing changes the result
+    U2, _, d2, _, _ = orc.trajectory_nested(dims, 5.6, levels, 1.0, 4, U0, P0, kappa=0.155, kappa2=0.14, eta1=e1,
+                                            eta2=e2)
+    assert np.max(np.abs(U2 - U1)) > 1e-4
