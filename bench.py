@@ -449,6 +449,41 @@ def improved_gauge_leg(R, U_therm, inputs, n, c1=-1.0 / 12.0):
     return out
 
 
+def stout_leg(R, U_therm, rho=0.1, n=2, reps=20):
+    """Cost of stout smearing at the benchmark lattice: fgi_stout_smear and
+    fgi_stout_force at n levels against the same calls at zero levels (which
+    only pack and unpack), HIP events on the library's stream; the difference
+    per level is the smearing kernel, and the adjoint kernels plus a
+    re-smearing for the force.  Per force evaluation with smeared fermions the
+    library runs n smearing levels and n adjoint levels."""
+    torch = R.torch
+    V = int(np.prod(R.dims))
+    Us = torch.empty_like(U_therm)
+    Fs = torch.randn((4, V, 8), dtype=torch.float64, device=R.dev)
+    F = torch.empty_like(Fs)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    ms = {}
+    for k in (0, n):
+        ms["smear", k] = timed(lambda: R.ctx.stout_smear(R.dims, rho, k, U_therm, Us))
+        ms["force", k] = timed(lambda: R.ctx.stout_force(R.dims, rho, k, U_therm, Fs, F))
+    smear_us = (ms["smear", n] - ms["smear", 0]) * 1e3 / n
+    back_us = (ms["force", n] - ms["force", 0]) * 1e3 / n - smear_us
+    return dict(rho=rho, n=n, smear_us_per_level=round(smear_us, 2), adjoint_us_per_level=round(back_us, 2),
+                per_force_evaluation_ms=round(n * (smear_us + back_us) / 1e3, 4),
+                call_ms={"smear_n0": round(ms["smear", 0], 4), "smear_n": round(ms["smear", n], 4),
+                         "force_n0": round(ms["force", 0], 4), "force_n": round(ms["force", n], 4)})
+
+
 def summarise(recs):
     dh = np.array([r["dH"] for r in recs])
     return dict(mean_dH=float(dh.mean()), mean_dH2=float((dh ** 2).mean()),
@@ -697,6 +732,12 @@ def main():
              ["%+.3e" % d for d in improved["symanzik"]["dH"]], improved["gauge_force_call_ms"]["wilson"],
              improved["gauge_force_call_ms"]["symanzik"], improved["rect_force_kernel"]["us"],
              improved["rect_force_kernel"]["achieved_TFLOPs"] or 0))
+    stout = None
+    if args.improved_steps > 0:
+        stout = stout_leg(R, U)
+        log("stout smearing (rho %.2f, %d levels) at %s: %.1f us per level, adjoint %.1f us per level, %.3f ms per "
+            "force evaluation" % (stout["rho"], stout["n"], "x".join(map(str, R.dims)), stout["smear_us_per_level"],
+                                  stout["adjoint_us_per_level"], stout["per_force_evaluation_ms"]))
     batched = None
     if not args.no_batched:
         batched = batched_leg(R, args.prec, 8, args.batched_steps)
@@ -726,7 +767,7 @@ def main():
                fg=fg, fg_exact=exact, lf_fp64=lf,
                speedup_vs_lf_fp64=(round(lf["s_per_traj"] / s_per_traj, 3) if lf else None),
                roofline=roof, roofline_32x32x32x64=large, hasenbusch_32x32x32x64=hasen, batched=batched,
-               alpha_tuning=alpha_leg, improved_gauge=improved,
+               alpha_tuning=alpha_leg, improved_gauge=improved, stout=stout,
                cpu_baseline=cpu)
     print(json.dumps(out), flush=True)
 
