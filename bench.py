@@ -740,7 +740,12 @@ def main():
                                   stout["adjoint_us_per_level"], stout["per_force_evaluation_ms"]))
     batched = None
     if not args.no_batched:
-        batched = batched_leg(R, args.prec, 8, args.batched_steps)
+        try:
+            batched = batched_leg(R, args.prec, 8, args.batched_steps)
+        except R.fgi.FgiError as e:
+            batched = dict(error=str(e))
+            log("batched 96 chains: %s" % e)
+    if batched and "error" not in batched:
         log("batched 96 chains: %.4f s per trajectory of all chains (%.1f chain-trajectories/s), chain by chain "
             "%.3f s, speedup %.1fx" % (batched["s_per_batched_trajectory"], batched["chain_trajectories_per_s"],
                                       batched["s_chain_by_chain"], batched["speedup_vs_chain_by_chain"]))
