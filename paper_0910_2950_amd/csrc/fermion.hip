@@ -1379,7 +1379,11 @@ static void cg_batch_b(Ctx& c, const Batch& B, const FermionOp& ops, const CGVec
     FGI_LAUNCH_CHECK();
 }
 
+// The pinned staging buffer is rewritten only after the stream has drained, so
+// an earlier upload still queued behind kernels cannot pick up a later state
+// (two uploads in a row at a reliable update differ in the act flags).
 static void upload_states(Ctx& c, CGState* dev, const std::vector<CGState>& h) {
+    FGI_HIP(hipStreamSynchronize(c.stream));
     std::copy(h.begin(), h.end(), c.host_bstates);
     FGI_HIP(hipMemcpyAsync(dev, c.host_bstates, sizeof(CGState) * h.size(), hipMemcpyHostToDevice, c.stream));
 }
