@@ -77,7 +77,8 @@ def parse():
                     help="1: the displaced force's solve of an FG stage starts from the undisplaced solution")
     ap.add_argument("--exact-steps", type=int, default=2,
                     help="trajectories of the exact force-gradient form on the first timed inputs (0: skip)")
-    ap.add_argument("--tune-alpha", type=int, default=0, metavar="K",
+    ap.add_argument("--chain-steps", type=int, default=3, help="on-device Markov-chain trajectories (0: skip)")
+    ap.add_argument("--tune-alpha", type=int, default=8, metavar="K",
                     help="Omelyan alpha from Poisson brackets measured over K trajectories (0: skip)")
     ap.add_argument("--n-omelyan", type=int, default=38, help="PQPQP step count of the alpha-tuning leg")
     ap.add_argument("--no-autotune", action="store_true",
@@ -391,6 +392,23 @@ def tune_alpha_leg(R, U_therm, k, n):
                                "tuned": predicted_dh2(alpha, dS, dT, 1.0 / n)},
                 measured_dH2={"0.1932": float(np.mean(np.square(dh0))), "tuned": float(np.mean(np.square(dh1)))},
                 dH={"0.1932": dh0, "tuned": dh1}, seconds=time.perf_counter() - t0)
+
+
+def chain_leg(R, U_therm, act, n, ntraj, seed=0x5EED):
+    """The on-device Markov chain (fgi_hmc_run): ntraj FG trajectories from the
+    thermalised links with momenta, noise and the Metropolis uniform drawn on
+    the device from (seed, trajectory index), accept/reject and
+    reunitarisation, against the per-trajectory cost of the timed leg (whose
+    inputs were resident before timing)."""
+    torch = R.torch
+    U = U_therm.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dH, acc, plaq, st = R.ctx.hmc_run(R.dims, act, "FG", 1.0, n, U, seed, 0, ntraj)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    return dict(trajectories=ntraj, n=n, s_per_traj=sec / ntraj, dH=dH, accepted=acc, plaquette=plaq,
+                solves_per_traj=st["solves"] / ntraj, cg_iters_per_traj=st["cg_iters"] / ntraj)
 
 
 # SU(3) products per link of the rectangle force: 18 five-link staples (4 products
@@ -722,6 +740,13 @@ def main():
             "%.3e -> %.3e" % (args.n_omelyan, args.tune_alpha, alpha_leg["alpha_tuned"],
                               alpha_leg["predicted_dH2"]["0.1932"], alpha_leg["predicted_dH2"]["tuned"],
                               alpha_leg["measured_dH2"]["0.1932"], alpha_leg["measured_dH2"]["tuned"]))
+    chain = None
+    if args.chain_steps > 0:
+        R.apply(tune_fg)
+        chain = chain_leg(R, U, act_fg, args.n_fg, args.chain_steps)
+        log("on-device chain (fgi_hmc_run) FG-%s n=%d: %.4f s/traj (timed leg %.4f), accepted %s, dH %s" %
+            (args.prec, args.n_fg, chain["s_per_traj"], s_per_traj, chain["accepted"],
+             ["%+.3e" % d for d in chain["dH"]]))
     improved = None
     if args.improved_steps > 0:
         k = min(args.improved_steps, args.steps)
@@ -772,7 +797,7 @@ def main():
                fg=fg, fg_exact=exact, lf_fp64=lf,
                speedup_vs_lf_fp64=(round(lf["s_per_traj"] / s_per_traj, 3) if lf else None),
                roofline=roof, roofline_32x32x32x64=large, hasenbusch_32x32x32x64=hasen, batched=batched,
-               alpha_tuning=alpha_leg, improved_gauge=improved, stout=stout,
+               alpha_tuning=alpha_leg, chain=chain, improved_gauge=improved, stout=stout,
                cpu_baseline=cpu)
     print(json.dumps(out), flush=True)
 
