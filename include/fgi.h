@@ -87,7 +87,7 @@ typedef struct {
                            c0 = 1 - 8 c1, R the 2x1 rectangle two links along mu;
                            0 = Wilson, -1/12 tree-level Symanzik, -0.331 Iwasaki.
                            Forces, force gradients, brackets, trajectories and
-                           chains all take it; batched chains need c1 = 0. */
+                           chains (batched ones too) all take it. */
     double stout_rho;   /* stout smearing of the links the fermion operator sees
                            (Morningstar-Peardon): 0 <= rho <= 0.5 ... */
     int stout_n;        /* ... applied stout_n times (0 = thin links, at most 8).

@@ -1416,7 +1416,7 @@ struct BFields {
         bool have = accumulate;
         if (st) st->force_evals++;
         if (terms & FGI_TERM_GAUGE) {
-            gauge_force_b(c, B, u, out, coef, have ? 1 : 0);
+            gauge_force_b(c, B, u, out, coef, have ? 1 : 0, act.c1);
             have = true;
         }
         if (!have) zero_doubles(c, out, 8 * (size_t)B.links);
@@ -1513,7 +1513,6 @@ extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain
         if (nsteps < 1 || !std::isfinite(tau)) throw Error(FGI_EINVAL, "bad tau / nsteps");
         if (act->kappa_hasen != 0.0) throw Error(FGI_EINVAL, "batched chains take one pseudofermion");
         if (act->fg_exact) throw Error(FGI_EINVAL, "batched chains use the displacement force-gradient form");
-        if (act->c1 != 0.0) throw Error(FGI_EINVAL, "batched chains take the Wilson gauge action (c1 = 0)");
         if (act->stout_n != 0) throw Error(FGI_EINVAL, "batched chains take thin fermion links (stout_n = 0)");
         const bool ferm = chains[0].kappa != 0.0;
         std::vector<ChainDesc> cd;
@@ -1551,12 +1550,12 @@ extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain
         double* h1 = (double*)c.bh1.get(sizeof(double) * B.vol);
         double* part = partial_buf(c, B);
         double* res = (double*)c.bres.get(sizeof(double) * 2 * nchains);  // not shared with the solver's scalars
-        ham_density_b(c, B, f.U, f.P, h0);
+        ham_density_b(c, B, f.U, f.P, h0, f.act.c1);
 
         BDriver d{f, *integ};
         d.run(0, nsteps, tau / nsteps);
 
-        ham_density_b(c, B, f.U, f.P, h1);
+        ham_density_b(c, B, f.U, f.P, h1, f.act.c1);
         diff_sums_b(c, B, h1, h0, part, res);
         if (ferm) {
             f.solve(f.U, f.Us, f.phi, f.X);

@@ -208,10 +208,10 @@ void exp_su3_batch(Ctx&, int n, const double* p, double h, void* out);
 // batched versions (every chain with its own geometry, beta, kappa)
 void pack_b(Ctx&, const Batch&, void* internal, int field /*0 U, 1 P, 2 eta*/, int to_internal);
 void make_sloppy_b(Ctx&, const Batch&, const d2* U, void* sloppy, int prec, int recon);
-void ham_density_b(Ctx&, const Batch&, const d2* U, const double* P, double* h);
+void ham_density_b(Ctx&, const Batch&, const d2* U, const double* P, double* h, double c1 = 0.0);
 void diff_sums_b(Ctx&, const Batch&, const double* h1, const double* h0, double* partial, double* out);
 void final_sums_b(Ctx&, const Batch&, const double* partial, int kind, double* out);
-void gauge_force_b(Ctx&, const Batch&, const d2* U, double* F, double coef, int accumulate);
+void gauge_force_b(Ctx&, const Batch&, const d2* U, double* F, double coef, int accumulate, double c1 = 0.0);
 void link_update_b(Ctx&, const Batch&, double h, const double* X, const d2* src, d2* dst, void* sloppy, int prec,
                    int recon);
 

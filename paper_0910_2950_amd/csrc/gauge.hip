@@ -204,11 +204,12 @@ __global__ void k_ham_density(Geom g, double beta, const d2* __restrict__ U, con
     ham_density_body(g, beta, U, P, h, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// bscale multiplies each chain's beta (1 - 8 c1 for the plaquettes of the improved action)
 __global__ void k_ham_density_b(const ChainDesc* __restrict__ cd, int nc, const d2* __restrict__ U,
-                                const double* __restrict__ P, double* __restrict__ h) {
+                                const double* __restrict__ P, double* __restrict__ h, double bscale) {
     const int c = find_chain(cd, nc, blockIdx.x, GRID_V);
     const ChainDesc& d = cd[c];
-    ham_density_body(d.g, d.beta, U ? U + 9 * d.link0 : nullptr, P ? P + 8 * d.link0 : nullptr, h + d.vol0,
+    ham_density_body(d.g, d.beta * bscale, U ? U + 9 * d.link0 : nullptr, P ? P + 8 * d.link0 : nullptr, h + d.vol0,
                      (blockIdx.x - d.blk0[GRID_V]) * blockDim.x + threadIdx.x);
 }
 
@@ -527,9 +528,8 @@ __device__ __forceinline__ void rect_staples(const Geom& g, const d2* __restrict
 
 // h(x) += bc1 sum_{mu != nu} (1 - ReTr R_{mu nu}(x) / 3), with
 // ReTr R = ReTr(a b^+), a = U_mu(x) U_mu(x+mu) U_nu(x+2mu), b = U_nu(x) U_mu(x+nu) U_mu(x+mu+nu)
-__global__ void __launch_bounds__(256) k_rect_density(Geom g, double bc1, const d2* __restrict__ U,
-                                                     double* __restrict__ h) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void rect_density_body(const Geom& g, double bc1, const d2* __restrict__ U,
+                                                  double* __restrict__ h, int t) {
     if (t >= g.V) return;
     const int p = t / g.Vh, s = t % g.Vh;
     const Coord c = cb_coords(g, p, s);
@@ -561,15 +561,28 @@ __global__ void __launch_bounds__(256) k_rect_density(Geom g, double bc1, const 
     h[t] += bc1 * acc;
 }
 
+__global__ void __launch_bounds__(256) k_rect_density(Geom g, double bc1, const d2* __restrict__ U,
+                                                     double* __restrict__ h) {
+    rect_density_body(g, bc1, U, h, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// batched chains: chain c adds its beta * c1 times its rectangle sum
+__global__ void __launch_bounds__(256) k_rect_density_b(const ChainDesc* __restrict__ cd, int nc, double c1,
+                                                       const d2* __restrict__ U, double* __restrict__ h) {
+    const int c = find_chain(cd, nc, blockIdx.x, GRID_V);
+    const ChainDesc& d = cd[c];
+    rect_density_body(d.g, d.beta * c1, U + 9 * d.link0, h + d.vol0,
+                      (blockIdx.x - d.blk0[GRID_V]) * blockDim.x + threadIdx.x);
+}
+
 void rect_density_add(Ctx& c, const Geom& g, double bc1, const d2* U, double* h) {
     hipLaunchKernelGGL(k_rect_density, dim3(nblocks(g.V, BS)), dim3(BS), 0, c.stream, g, bc1, U, h);
     FGI_LAUNCH_CHECK();
 }
 
 // F_mu(x) += f TA(U_mu(x) A^R_mu(x)), f = -beta c1 coef / 6
-__global__ void __launch_bounds__(256) k_rect_force(Geom g, double f, const d2* __restrict__ U,
-                                                   double* __restrict__ F, int xcd) {
-    const int t = slab_thread(g.Vh, 8, xcd);
+__device__ __forceinline__ void rect_force_body(const Geom& g, double f, const d2* __restrict__ U,
+                                                double* __restrict__ F, int t) {
     if (t >= 4 * g.V) return;
     const int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
     const Coord c = cb_coords(g, p, s);
@@ -581,6 +594,20 @@ __global__ void __launch_bounds__(256) k_rect_force(Geom g, double f, const d2* 
     double* o = F + (size_t)(r * 8) * g.Vh + s;
 #pragma unroll
     for (int a = 0; a < 8; a++) o[(size_t)a * g.Vh] += f * x[a];
+}
+
+__global__ void __launch_bounds__(256) k_rect_force(Geom g, double f, const d2* __restrict__ U,
+                                                   double* __restrict__ F, int xcd) {
+    rect_force_body(g, f, U, F, slab_thread(g.Vh, 8, xcd));
+}
+
+// batched chains: f = -beta_c c1 coef / 6 per chain
+__global__ void __launch_bounds__(256) k_rect_force_b(const ChainDesc* __restrict__ cd, int nc, double c1, double coef,
+                                                     const d2* __restrict__ U, double* __restrict__ F) {
+    const int c = find_chain(cd, nc, blockIdx.x, GRID_4V);
+    const ChainDesc& d = cd[c];
+    rect_force_body(d.g, -d.beta * c1 * coef / 6.0, U + 9 * d.link0, F + 8 * d.link0,
+                    (blockIdx.x - d.blk0[GRID_4V]) * blockDim.x + threadIdx.x);
 }
 
 void rect_force(Ctx& c, const Geom& g, double beta, double c1, const d2* U, double* F, double coef) {
@@ -808,9 +835,14 @@ void make_sloppy_b(Ctx& c, const Batch& B, const d2* U, void* sloppy, int prec, 
     FGI_LAUNCH_CHECK();
 }
 
-void ham_density_b(Ctx& c, const Batch& B, const d2* U, const double* P, double* h) {
-    hipLaunchKernelGGL(k_ham_density_b, dim3(B.nblk[GRID_V]), dim3(BS), 0, c.stream, B.cd, B.nc, U, P, h);
+void ham_density_b(Ctx& c, const Batch& B, const d2* U, const double* P, double* h, double c1) {
+    hipLaunchKernelGGL(k_ham_density_b, dim3(B.nblk[GRID_V]), dim3(BS), 0, c.stream, B.cd, B.nc, U, P, h,
+                       1.0 - 8.0 * c1);
     FGI_LAUNCH_CHECK();
+    if (c1 != 0.0 && U) {
+        hipLaunchKernelGGL(k_rect_density_b, dim3(B.nblk[GRID_V]), dim3(BS), 0, c.stream, B.cd, B.nc, c1, U, h);
+        FGI_LAUNCH_CHECK();
+    }
 }
 
 void diff_sums_b(Ctx& c, const Batch& B, const double* h1, const double* h0, double* partial, double* out) {
@@ -824,9 +856,14 @@ void final_sums_b(Ctx& c, const Batch& B, const double* partial, int kind, doubl
     FGI_LAUNCH_CHECK();
 }
 
-void gauge_force_b(Ctx& c, const Batch& B, const d2* U, double* F, double coef, int accumulate) {
-    hipLaunchKernelGGL(k_gauge_force_b, dim3(B.nblk[GRID_4V]), dim3(BS), 0, c.stream, B.cd, B.nc, U, F, coef, accumulate);
+void gauge_force_b(Ctx& c, const Batch& B, const d2* U, double* F, double coef, int accumulate, double c1) {
+    hipLaunchKernelGGL(k_gauge_force_b, dim3(B.nblk[GRID_4V]), dim3(BS), 0, c.stream, B.cd, B.nc, U, F,
+                       coef * (1.0 - 8.0 * c1), accumulate);
     FGI_LAUNCH_CHECK();
+    if (c1 != 0.0) {
+        hipLaunchKernelGGL(k_rect_force_b, dim3(B.nblk[GRID_4V]), dim3(BS), 0, c.stream, B.cd, B.nc, c1, coef, U, F);
+        FGI_LAUNCH_CHECK();
+    }
 }
 
 void link_update_b(Ctx& c, const Batch& B, double h, const double* X, const d2* src, d2* dst, void* sloppy, int prec,

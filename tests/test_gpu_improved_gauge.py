@@ -10,8 +10,10 @@ c1) on the GPU against the oracle, through the C ABI.
   - an on-device chain against the oracle's chain (identical decisions);
   - at 16^3x32 in the benchmark's launch configuration (block 256, XCD
     order): action, force on every link and the tangent, against the oracle;
-  - c1 = 0 leaves the Wilson results bitwise unchanged; non-finite c1 and
-    batched chains with c1 != 0 are rejected.
+  - batched chains of uneven sizes with c1: each bitwise equal to its own
+    single-chain run (FP64 and MP16) and to the oracle;
+  - c1 = 0 leaves the Wilson results bitwise unchanged; non-finite c1 is
+    rejected.
 """
 import math
 
@@ -146,7 +148,7 @@ def test_zero_c1_is_wilson_bitwise(ctx):
     assert torch.equal(F1, F2)
 
 
-def test_bad_c1_and_batched_rejected(ctx):
+def test_bad_c1_rejected(ctx):
     dims = (4, 4, 4, 4)
     U0, P0, _, _ = synth.hot_start(dims, synth.SEED_BASE + 409, fermions=False)
     for bad in (math.nan, math.inf):
@@ -158,10 +160,32 @@ def test_bad_c1_and_batched_rejected(ctx):
             ctx.trajectory(dims, Action(beta=5.6, c1=bad), "FG", 1.0, 2, U, P)
         assert e.value.code == fgi.FGI_EINVAL
         assert np.array_equal(host(U), U0)
-    chains = [dict(dims=dims, beta=5.6, kappa=0.0, U=dev(U0), P=dev(P0), eta=None)]
-    with pytest.raises(fgi.FgiError) as e:
-        ctx.trajectory_batched(chains, Action(beta=5.6, c1=-1 / 12), "FG", 1.0, 2)
-    assert e.value.code == fgi.FGI_EINVAL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mp16"])
+def test_batched_chains_equal_single_runs(ctx, orc, prec):
+    """Chains of uneven sizes and couplings in one batched call, each bitwise
+    equal to its own single-chain trajectory with the same c1; FP64 also
+    against the oracle."""
+    c1 = -0.331
+    mix = [((4, 4, 4, 4), 5.6, 0.155), ((6, 4, 4, 6), 5.8, 0.150), ((4, 4, 2, 2), 5.5, 0.156)]
+    tol = 1e-14 if prec == "fp64" else 1e-10
+    chs = []
+    for k, (dims, beta, kappa) in enumerate(mix):
+        U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 420 + k, fermions=True)
+        chs.append((dims, beta, kappa, U0, P0, eta))
+    args = [dict(dims=d, beta=b, kappa=k, U=dev(U0), P=dev(P0), eta=dev(e)) for d, b, k, U0, P0, e in chs]
+    act = Action(beta=0.0, cg_tol=tol, prec=prec, link_recon=12 if prec == "mp16" else 18, c1=c1)
+    dH, _ = ctx.trajectory_batched(args, act, "FG", 1.0, 3)
+    for (dims, beta, kappa, U0, P0, eta), a, d in zip(chs, args, dH):
+        a1 = Action(beta=beta, kappa=kappa, cg_tol=tol, prec=prec, link_recon=act.link_recon, c1=c1)
+        U, P = dev(U0), dev(P0)
+        d1, _ = ctx.trajectory(dims, a1, "FG", 1.0, 3, U, P, dev(eta))
+        assert torch.equal(U, a["U"]) and torch.equal(P, a["P"]) and d1 == d
+        if prec == "fp64":
+            Uo, Po, dHo, _, _ = orc.trajectory(dims, beta, orc.table("FG"), 1.0, 3, U0, P0, kappa=kappa, eta=eta,
+                                               c1=c1)
+            assert relmax(host(U), Uo) < 1e-12 and abs(d - dHo) < 1e-9
 
 
 @pytest.fixture(scope="module")
