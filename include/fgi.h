@@ -93,10 +93,11 @@ typedef struct {
     int stout_n;        /* ... applied stout_n times (0 = thin links, at most 8).
                            It applies where the library builds the fermion
                            operator itself: fgi_force, fgi_poisson_brackets,
-                           fgi_trajectory(_packed), fgi_hmc_run; the fermion force
+                           fgi_trajectory(_packed), fgi_hmc_run,
+                           fgi_trajectory_batched; the fermion force
                            on the smeared links is carried back to the thin links
-                           (fgi_stout_force).  Not with fg_exact (FGI_EINVAL), not
-                           for batched chains.  The operator-level entry points
+                           (fgi_stout_force); batched chains too.  Not with
+                           fg_exact (FGI_EINVAL).  The operator-level entry points
                            (dslash, mhat, cg_solve, pf_*, fermion_force, hasen_*)
                            act on the links they are given. */
     int pad;

@@ -1411,6 +1411,22 @@ struct BFields {
             if (!q.converged) nonconv = true;
         }
     }
+    // the links the fermion operator sees (Fields::flinks for every chain)
+    struct FLinks {
+        const d2* u;
+        const void* us;
+    };
+    FLinks flinks(const d2* u, const void* us) {
+        if (act.stout_n <= 0) return {u, us};
+        d2* lev = (d2*)c.stout_lev.get(sizeof(d2) * 9 * (size_t)B.links * act.stout_n);
+        const d2* top = stout_smear_b(c, B, act.stout_rho, act.stout_n, u, lev);
+        void* s = nullptr;
+        if (sp != P64) {
+            s = c.stout_sloppy.get(sizeof(float) * 18 * (size_t)B.links);
+            make_sloppy_b(c, B, top, s, sp, rc);
+        }
+        return {top, s};
+    }
     void force(const d2* u, const void* us, int terms, double* out, double coef, bool accumulate,
                bool guess = false) {
         bool have = accumulate;
@@ -1421,8 +1437,20 @@ struct BFields {
         }
         if (!have) zero_doubles(c, out, 8 * (size_t)B.links);
         if (fermions && (terms & FGI_TERM_FERMION)) {
-            solve(u, us, phi, X, guess);
-            fermion_force_b(c, B, op64(u), X, out, coef);
+            const FLinks fl = flinks(u, us);
+            if (act.stout_n > 0) {
+                const size_t nm = 8 * (size_t)B.links;
+                double* fo = (double*)c.stout_F.get(sizeof(double) * nm);
+                zero_doubles(c, fo, nm);
+                solve(fl.u, fl.us, phi, X, guess);
+                fermion_force_b(c, B, op64(fl.u), X, fo, 1.0);
+                stout_backprop_b(c, B, act.stout_rho, act.stout_n, u,
+                                 (const d2*)c.stout_lev.get(sizeof(d2) * 9 * (size_t)B.links * act.stout_n), fo, out,
+                                 coef, 1);
+            } else {
+                solve(u, us, phi, X, guess);
+                fermion_force_b(c, B, op64(u), X, out, coef);
+            }
         }
     }
 };
@@ -1513,7 +1541,6 @@ extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain
         if (nsteps < 1 || !std::isfinite(tau)) throw Error(FGI_EINVAL, "bad tau / nsteps");
         if (act->kappa_hasen != 0.0) throw Error(FGI_EINVAL, "batched chains take one pseudofermion");
         if (act->fg_exact) throw Error(FGI_EINVAL, "batched chains use the displacement force-gradient form");
-        if (act->stout_n != 0) throw Error(FGI_EINVAL, "batched chains take thin fermion links (stout_n = 0)");
         const bool ferm = chains[0].kappa != 0.0;
         std::vector<ChainDesc> cd;
         Batch B;
@@ -1544,7 +1571,7 @@ extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain
                 f.Uds = c.sloppy_disp.get(slb);
                 make_sloppy_b(c, B, f.U, f.Us, f.sp, f.rc);
             }
-            pf_heatbath_b(c, B, f.op64(f.U), eta, f.phi);
+            pf_heatbath_b(c, B, f.op64(f.flinks(f.U, f.Us).u), eta, f.phi);
         }
         double* h0 = (double*)c.bh0.get(sizeof(double) * B.vol);
         double* h1 = (double*)c.bh1.get(sizeof(double) * B.vol);
@@ -1558,7 +1585,8 @@ extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain
         ham_density_b(c, B, f.U, f.P, h1, f.act.c1);
         diff_sums_b(c, B, h1, h0, part, res);
         if (ferm) {
-            f.solve(f.U, f.Us, f.phi, f.X);
+            const BFields::FLinks fl = f.flinks(f.U, f.Us);
+            f.solve(fl.u, fl.us, f.phi, f.X);
             pf_density_b(c, B, f.phi, f.X, eta, part, res + nchains);
         }
         std::vector<double> out(2 * nchains, 0.0);

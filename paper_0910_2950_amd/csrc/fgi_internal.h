@@ -212,6 +212,10 @@ void ham_density_b(Ctx&, const Batch&, const d2* U, const double* P, double* h, 
 void diff_sums_b(Ctx&, const Batch&, const double* h1, const double* h0, double* partial, double* out);
 void final_sums_b(Ctx&, const Batch&, const double* partial, int kind, double* out);
 void gauge_force_b(Ctx&, const Batch&, const d2* U, double* F, double coef, int accumulate, double c1 = 0.0);
+// stout smearing and its force back-propagation for every chain of a batch
+const d2* stout_smear_b(Ctx&, const Batch&, double rho, int n, const d2* U, d2* levels);
+void stout_backprop_b(Ctx&, const Batch&, double rho, int n, const d2* U, const d2* levels, const double* Fs,
+                      double* F, double coef, int accumulate);
 void link_update_b(Ctx&, const Batch&, double h, const double* X, const d2* src, d2* dst, void* sloppy, int prec,
                    int recon);
 

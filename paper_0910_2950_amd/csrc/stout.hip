@@ -70,10 +70,9 @@ __device__ __forceinline__ void link_of(const Geom& g, int t, int& mu, int& p, i
 
 }  // namespace
 
-// U' = exp(TA(C U^+)) U on every link
-__global__ void __launch_bounds__(256) k_stout_level(Geom g, double rho, const d2* __restrict__ U,
-                                                    d2* __restrict__ Up) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// U' = exp(TA(C U^+)) U on link t
+__device__ __forceinline__ void stout_level_body(const Geom& g, double rho, const d2* __restrict__ U,
+                                                 d2* __restrict__ Up, int t) {
     if (t >= 4 * g.V) return;
     int mu, p, s;
     Coord x;
@@ -85,11 +84,24 @@ __global__ void __launch_bounds__(256) k_stout_level(Geom g, double rho, const d
     gauge_store(Up, mu, p, s, g.Vh, m3_mul(E, u));
 }
 
+__global__ void __launch_bounds__(256) k_stout_level(Geom g, double rho, const d2* __restrict__ U,
+                                                    d2* __restrict__ Up) {
+    stout_level_body(g, rho, U, Up, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// batched chains (links of chain c from 9 * link0, 256 links per block)
+__global__ void __launch_bounds__(256) k_stout_level_b(const ChainDesc* __restrict__ cd, int nc, double rho,
+                                                      const d2* __restrict__ U, d2* __restrict__ Up) {
+    const int c = find_chain(cd, nc, blockIdx.x, GRID_4V);
+    const ChainDesc& d = cd[c];
+    stout_level_body(d.g, rho, U + 9 * d.link0, Up + 9 * d.link0,
+                     (blockIdx.x - d.blk0[GRID_4V]) * blockDim.x + threadIdx.x);
+}
+
 // Per link: part = E^+ G' E - TA(Gamma Omega) (components), M = rho U^+ Gamma
-__global__ void __launch_bounds__(256) k_stout_gamma(Geom g, double rho, const d2* __restrict__ U,
-                                                    const double* __restrict__ Gp, double* __restrict__ part,
-                                                    d2* __restrict__ Mout) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void stout_gamma_body(const Geom& g, double rho, const d2* __restrict__ U,
+                                                 const double* __restrict__ Gp, double* __restrict__ part,
+                                                 d2* __restrict__ Mout, int t) {
     if (t >= 4 * g.V) return;
     int mu, p, s;
     Coord x;
@@ -137,11 +149,25 @@ __global__ void __launch_bounds__(256) k_stout_gamma(Geom g, double rho, const d
     gauge_store(Mout, mu, p, s, g.Vh, M);
 }
 
+__global__ void __launch_bounds__(256) k_stout_gamma(Geom g, double rho, const d2* __restrict__ U,
+                                                    const double* __restrict__ Gp, double* __restrict__ part,
+                                                    d2* __restrict__ Mout) {
+    stout_gamma_body(g, rho, U, Gp, part, Mout, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_stout_gamma_b(const ChainDesc* __restrict__ cd, int nc, double rho,
+                                                      const d2* __restrict__ U, const double* __restrict__ Gp,
+                                                      double* __restrict__ part, d2* __restrict__ Mout) {
+    const int c = find_chain(cd, nc, blockIdx.x, GRID_4V);
+    const ChainDesc& d = cd[c];
+    stout_gamma_body(d.g, rho, U + 9 * d.link0, Gp + 8 * d.link0, part + 8 * d.link0, Mout + 9 * d.link0,
+                     (blockIdx.x - d.blk0[GRID_4V]) * blockDim.x + threadIdx.x);
+}
+
 // G_k = part_k + the 18 staple terms of link k = (d, y) (coef, accumulate into G)
-__global__ void __launch_bounds__(256) k_stout_gather(Geom g, const d2* __restrict__ U, const d2* __restrict__ M,
-                                                     const double* __restrict__ part, double* __restrict__ G,
-                                                     double coef, int accumulate) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void stout_gather_body(const Geom& g, const d2* __restrict__ U, const d2* __restrict__ M,
+                                                  const double* __restrict__ part, double* __restrict__ G,
+                                                  double coef, int accumulate, int t) {
     if (t >= 4 * g.V) return;
     int d, p, s;
     Coord y;
@@ -180,6 +206,22 @@ __global__ void __launch_bounds__(256) k_stout_gather(Geom g, const d2* __restri
     }
 }
 
+__global__ void __launch_bounds__(256) k_stout_gather(Geom g, const d2* __restrict__ U, const d2* __restrict__ M,
+                                                     const double* __restrict__ part, double* __restrict__ G,
+                                                     double coef, int accumulate) {
+    stout_gather_body(g, U, M, part, G, coef, accumulate, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_stout_gather_b(const ChainDesc* __restrict__ cd, int nc,
+                                                       const d2* __restrict__ U, const d2* __restrict__ M,
+                                                       const double* __restrict__ part, double* __restrict__ G,
+                                                       double coef, int accumulate) {
+    const int c = find_chain(cd, nc, blockIdx.x, GRID_4V);
+    const ChainDesc& d = cd[c];
+    stout_gather_body(d.g, U + 9 * d.link0, M + 9 * d.link0, part + 8 * d.link0, G + 8 * d.link0, coef, accumulate,
+                      (blockIdx.x - d.blk0[GRID_4V]) * blockDim.x + threadIdx.x);
+}
+
 const d2* stout_smear(Ctx& c, const Geom& g, double rho, int n, const d2* U, d2* levels) {
     const size_t sz = (size_t)4 * 9 * g.V;
     const d2* in = U;
@@ -209,6 +251,40 @@ void stout_backprop(Ctx& c, const Geom& g, double rho, int n, const d2* U, const
         double* Gout = k == 0 ? F : ((n - 1 - k) % 2 == 0 ? ga : gb);
         hipLaunchKernelGGL(k_stout_gather, dim3(nblocks(4L * g.V, BS)), dim3(BS), 0, c.stream, g, Uk, M, part, Gout,
                            k == 0 ? coef : 1.0, k == 0 ? accumulate : 0);
+        FGI_LAUNCH_CHECK();
+        Gin = Gout;
+    }
+}
+
+const d2* stout_smear_b(Ctx& c, const Batch& B, double rho, int n, const d2* U, d2* levels) {
+    const size_t sz = (size_t)9 * B.links;
+    const d2* in = U;
+    for (int k = 0; k < n; k++) {
+        d2* out = levels + k * sz;
+        hipLaunchKernelGGL(k_stout_level_b, dim3(B.nblk[GRID_4V]), dim3(BS), 0, c.stream, B.cd, B.nc, rho, in, out);
+        FGI_LAUNCH_CHECK();
+        in = out;
+    }
+    return in;
+}
+
+void stout_backprop_b(Ctx& c, const Batch& B, double rho, int n, const d2* U, const d2* levels, const double* Fs,
+                      double* F, double coef, int accumulate) {
+    const size_t sz = (size_t)9 * B.links;
+    const size_t mb = sizeof(double) * 8 * (size_t)B.links;
+    double* ga = (double*)c.stout_ga.get(mb);
+    double* gb = (double*)c.stout_gb.get(mb);
+    double* part = (double*)c.stout_part.get(mb);
+    d2* M = (d2*)c.stout_M.get(sizeof(d2) * sz);
+    const double* Gin = Fs;
+    for (int k = n - 1; k >= 0; k--) {
+        const d2* Uk = k == 0 ? U : levels + (k - 1) * sz;
+        hipLaunchKernelGGL(k_stout_gamma_b, dim3(B.nblk[GRID_4V]), dim3(BS), 0, c.stream, B.cd, B.nc, rho, Uk, Gin,
+                           part, M);
+        FGI_LAUNCH_CHECK();
+        double* Gout = k == 0 ? F : ((n - 1 - k) % 2 == 0 ? ga : gb);
+        hipLaunchKernelGGL(k_stout_gather_b, dim3(B.nblk[GRID_4V]), dim3(BS), 0, c.stream, B.cd, B.nc, Uk, M, part,
+                           Gout, k == 0 ? coef : 1.0, k == 0 ? accumulate : 0);
         FGI_LAUNCH_CHECK();
         Gin = Gout;
     }

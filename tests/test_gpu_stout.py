@@ -9,9 +9,10 @@
     a chain with identical decisions;
   - 16^3x32 in the benchmark's launch configuration: the smearing and its
     adjoint against the oracle;
+  - batched chains of uneven sizes with smearing: each bitwise equal to its
+    own single-chain run (FP64 and MP16) and to the oracle;
   - zero levels leave the thin-link path bitwise; the exact G stage with
-    smearing, batched chains with smearing and out-of-range parameters are
-    rejected.
+    smearing and out-of-range parameters are rejected.
 """
 import numpy as np
 import pytest
@@ -168,10 +169,32 @@ def test_zero_levels_bitwise_and_rejections(ctx):
     with pytest.raises(fgi.FgiError) as e:
         ctx.stout_smear(dims, 0.1, 9, dev(U0))
     assert e.value.code == fgi.FGI_EINVAL
-    chains = [dict(dims=dims, beta=5.6, kappa=K, U=dev(U0), P=dev(P0), eta=dev(eta))]
-    with pytest.raises(fgi.FgiError) as e:
-        ctx.trajectory_batched(chains, Action(beta=5.6, kappa=K, stout_rho=0.1, stout_n=1), "FG", 1.0, 2)
-    assert e.value.code == fgi.FGI_EINVAL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mp16"])
+def test_batched_chains_equal_single_runs(ctx, orc, prec):
+    """Chains of uneven sizes and couplings with smeared fermion links (and the
+    improved gauge action) in one batched call, each bitwise equal to its own
+    single-chain run; FP64 also against the oracle."""
+    mix = [((4, 4, 4, 4), 5.6, 0.155), ((6, 4, 4, 6), 5.8, 0.150), ((4, 4, 2, 2), 5.5, 0.140)]
+    tol = 1e-14 if prec == "fp64" else 1e-10
+    sm = dict(stout_rho=0.12, stout_n=2, c1=-1 / 12)
+    chs = []
+    for k, (dims, beta, kappa) in enumerate(mix):
+        U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 620 + k, fermions=True)
+        chs.append((dims, beta, kappa, U0, P0, eta))
+    args = [dict(dims=d, beta=b, kappa=k, U=dev(U0), P=dev(P0), eta=dev(e)) for d, b, k, U0, P0, e in chs]
+    act = Action(beta=0.0, cg_tol=tol, prec=prec, link_recon=12 if prec == "mp16" else 18, **sm)
+    dH, _ = ctx.trajectory_batched(args, act, "FG", 1.0, 3)
+    for (dims, beta, kappa, U0, P0, eta), a, d in zip(chs, args, dH):
+        a1 = Action(beta=beta, kappa=kappa, cg_tol=tol, prec=prec, link_recon=act.link_recon, **sm)
+        U, P = dev(U0), dev(P0)
+        d1, _ = ctx.trajectory(dims, a1, "FG", 1.0, 3, U, P, dev(eta))
+        assert torch.equal(U, a["U"]) and torch.equal(P, a["P"]) and d1 == d
+        if prec == "fp64":
+            Uo, Po, dHo, _, _ = orc.trajectory(dims, beta, orc.table("FG"), 1.0, 3, U0, P0, kappa=kappa, eta=eta,
+                                               **sm)
+            assert relmax(host(U), Uo) < 1e-12 and abs(d - dHo) < 1e-9
 
 
 @pytest.fixture(scope="module")
