@@ -117,18 +117,19 @@ def test_mixed_precision_trajectory(ctx, orc):
     assert relmax(host(U), Uo) < 1e-8 and relmax(host(P), Po) < 1e-8 and abs(dH - dHo) < 1e-6
 
 
-def test_nested_hasenbusch(ctx, orc):
+@pytest.mark.parametrize("c1", [0.0, -0.331])
+def test_nested_hasenbusch(ctx, orc, c1):
     dims = (4, 4, 2, 2)
     FG = orc.table("FG")
     levels = [(FG, 4, 1), (FG, 2, 2), (FG, 1, 2)]
     U0, P0, _, _ = synth.hot_start(dims, synth.SEED_BASE + 607, fermions=False)
     e1 = synth.gaussian_noise(synth.rng(608), dims)
     e2 = synth.gaussian_noise(synth.rng(609), dims)
-    act = Action(beta=5.6, kappa=K, kappa_hasen=0.14, cg_tol=1e-14, stout_rho=0.1, stout_n=1)
+    act = Action(beta=5.6, kappa=K, kappa_hasen=0.14, cg_tol=1e-14, stout_rho=0.1, stout_n=1, c1=c1)
     U, P = dev(U0), dev(P0)
     dH, st = ctx.trajectory(dims, act, fgi.integrator_from_levels(levels), 1.0, 2, U, P, dev(e1), dev(e2))
     Uo, Po, dHo, sto, status = orc.trajectory_nested(dims, 5.6, levels, 1.0, 2, U0, P0, kappa=K, kappa2=0.14,
-                                                     eta1=e1, eta2=e2, stout_rho=0.1, stout_n=1)
+                                                     eta1=e1, eta2=e2, stout_rho=0.1, stout_n=1, c1=c1)
     assert status == 0 and st["solves"] == sto["solves"]
     assert relmax(host(U), Uo) < 1e-12 and relmax(host(P), Po) < 1e-12 and abs(dH - dHo) < 1e-9
 
