@@ -1486,9 +1486,9 @@ static std::vector<CGResult> cg_run_b(Ctx& c, const Batch& B, const FermionOp& o
     if (c.use_graphs) {
         // the grid sizes are baked into the graph (the chain table is read at run time)
         char key[320];
-        snprintf(key, sizeof key, "bcg/%d/%d/%p/%d/%d/%d/%d/%ld/%p/%p/%p/%p/%p/%p/%p/%p/%d/%d/%d", PP, PX, ops.links,
-                 ops.prec, ops.recon, nc, B.nblk[GRID_DS], B.sites, (void*)B.cd, v.x.v, v.r.v, v.p.v, v.q.v, v.t.v,
-                 (void*)st, (void*)part, Bi, c.ds_bs, c.ds_xcd);
+        snprintf(key, sizeof key, "bcg/%d/%d/%p/%d/%d/%d/%d/%ld/%p/%p/%p/%p/%p/%p/%p/%p/%p/%d/%d/%d", PP, PX,
+                 ops.links, ops.prec, ops.recon, nc, B.nblk[GRID_DS], B.sites, (void*)B.cd, v.x.v, v.r.v, v.p.v,
+                 v.q.v, v.t.v, (void*)v.p.norm, (void*)st, (void*)part, Bi, c.ds_bs, c.ds_xcd);
         ge = &cached_graph(c, key, [&] { cg_batch_b<PP, PX>(c, B, ops, v, Bi, st); });
     }
     int left = 0;
