@@ -1409,6 +1409,7 @@ typedef struct {
     cplx *X1, *X2;       /* the last solutions of the S_F (S_1) and S_2 solves */
     double stout_rho;
     int stout_n;         /* stout levels of the links the fermions see */
+    int fg_exact;        /* G stages in the exact form */
 } nested_run;
 
 /* the links the fermion terms see at W: a new smeared copy, or NULL for W */
@@ -1465,6 +1466,21 @@ static void terms_force(nested_run *r, const cplx *W, int terms, double *F, int 
 /* run level l for n steps of size h: the step table repeated n times with
  * neighbouring P stages merged; a Q stage of an outer level runs the next
  * level for w*h in nsub[l+1] steps; the innermost Q stage updates the links */
+/* J = J_V[F_terms] at W (the exact form's force gradient): the gauge part and
+ * the S_F (or S_1) part, whose solution X1 at W the force evaluation just
+ * left in r->X1 (one more solve for d_V X1).  The S_2 term and smeared links
+ * have no exact form here (oracle_trajectory_nested refuses them). */
+static void terms_tangent(nested_run *r, const cplx *W, int terms, const double *v, double *J) {
+    const int *L = r->L;
+    long V = lat_volume(L);
+    memset(J, 0, sizeof(double) * 4 * V * 8);
+    if (terms & TERM_GAUGE) oracle_gauge_force_tangent(L, r->beta, r->c1, W, v, J);
+    if (r->kappa != 0.0 && (terms & TERM_FERM)) {
+        double k1 = r->kappa2 != 0.0 ? r->kappa2 : r->kappa;
+        count_solve(r, oracle_fermion_force_tangent_add(L, k1, W, r->X1, v, r->tol, r->maxiter, 1.0, J));
+    }
+}
+
 static void run_level(nested_run *r, int l, int n, double h) {
     const int *L = r->L;
     long V = lat_volume(L);
@@ -1486,6 +1502,12 @@ static void run_level(nested_run *r, int l, int n, double h) {
         } else if (K[s] == 'Q') {
             if (l + 1 < r->nlevels) run_level(r, l + 1, r->nsub[l + 1], w * h / r->nsub[l + 1]);
             else oracle_link_update(L, w * h, r->P, r->U);
+        } else if (r->fg_exact) {
+            double *J = malloc(sizeof(double) * 4 * V * 8);
+            terms_force(r, r->U, r->terms[l], F, 0);
+            terms_tangent(r, r->U, r->terms[l], F, J);
+            for (long k = 0; k < 4 * V * 8; k++) r->P[k] += w * h * F[k] + 2.0 * XI[s] * h * h * h * J[k];
+            free(J);
         } else {
             terms_force(r, r->U, r->terms[l], F, 0);
             memcpy(Ud, r->U, sizeof(cplx) * 4 * V * 9);
@@ -1505,7 +1527,8 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
                              int cg_maxiter, int nlevels, const int *nstages, const int *terms, const int *nsub,
                              const char *kinds, const double *ws, const double *xis, double tau, int nsteps,
                              cplx *U, double *P, const cplx *eta1, const cplx *eta2, double *dH, long *stats3,
-                             int fg_start, double c1, double stout_rho, int stout_n) {
+                             int fg_start, double c1, double stout_rho, int stout_n, int fg_exact) {
+    if (fg_exact && kappa != 0.0 && (kappa2 != 0.0 || stout_n > 0)) return -2;
     long V = lat_volume(L), Vh = V / 2;
     const char *kp[8];
     const double *wp[8], *xp[8];
@@ -1520,6 +1543,7 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
     r.X2 = calloc(12 * Vh, sizeof(cplx));
     r.stout_rho = stout_rho;
     r.stout_n = stout_n;
+    r.fg_exact = fg_exact;
     cplx *phi1 = NULL, *phi2 = NULL;
     double *h0 = malloc(sizeof(double) * V), *h1 = malloc(sizeof(double) * V), *tmp = malloc(sizeof(double) * V);
     gauge_density(L, beta, c1, U, h0);

@@ -88,7 +88,7 @@ def _declare(L):
     L.oracle_hasen_action.restype = _d
     L.oracle_hasen_force_add.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _d, _vp]
     L.oracle_trajectory_nested.argtypes = [_ip, _d, _d, _d, _d, _i, _i, _vp, _vp, _vp, ctypes.c_char_p, _vp, _vp,
-                                           _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i, _d, _d, _i]
+                                           _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i, _d, _d, _i, _i]
     L.oracle_trajectory_nested.restype = _i
     L.oracle_philox.argtypes = [_vp, _vp, _vp]
     L.oracle_refresh.argtypes = [_ip, ctypes.c_uint64, ctypes.c_uint32, _vp, _vp, _vp]
@@ -361,7 +361,7 @@ def hasen_force(dims, kappa, kappa2, U, phi2, X2):
 
 
 def trajectory_nested(dims, beta, levels, tau, nsteps, U, P, kappa=0.0, kappa2=0.0, eta1=None, eta2=None,
-                      tol=1e-14, maxiter=10000, fg_start=True, c1=0.0, stout_rho=0.0, stout_n=0):
+                      tol=1e-14, maxiter=10000, fg_start=True, c1=0.0, stout_rho=0.0, stout_n=0, fg_exact=False):
     """levels: list of (stages, terms, nsub), level 0 outermost; terms bit 1 gauge,
     2 S_F (or S_1 with Hasenbusch), 4 S_2.  Returns (U, P, dH, stats, status)."""
     U = np.array(U, dtype=np.complex128, copy=True, order="C")
@@ -380,7 +380,8 @@ def trajectory_nested(dims, beta, levels, tau, nsteps, U, P, kappa=0.0, kappa2=0
                                             _ptr(terms), _ptr(nsub), kinds, _ptr(ws), _ptr(xis), tau, nsteps,
                                             _ptr(U), _ptr(P), _ptr(e1) if e1 is not None else None,
                                             _ptr(e2) if e2 is not None else None, ctypes.byref(dH), st,
-                                            int(bool(fg_start)), c1, stout_rho, int(stout_n))
+                                            int(bool(fg_start)), c1, stout_rho, int(stout_n),
+                                            int(bool(fg_exact)))
     return U, P, dH.value, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2]), status
 
 

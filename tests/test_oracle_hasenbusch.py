@@ -103,3 +103,46 @@ def test_nested_solve_count(orc):
     outer = 3 * n + 1
     middle = (2 * n) * (3 * 2 + 1)
     assert st["solves"] == outer + middle + 1 + 2
+
+
+def test_nested_exact_form_reduces_to_single_level(orc):
+    """One level, exact G stages: the pinned single-level exact trajectory."""
+    dims = (4, 4, 2, 2)
+    U, P, eta1, _ = start(dims, 6)
+    a = orc.trajectory(dims, 5.6, table("FG"), 1.0, 3, U, P, kappa=K, eta=eta1, fg_exact=True)
+    b = orc.trajectory_nested(dims, 5.6, [(table("FG"), 3, 1)], 1.0, 3, U, P, kappa=K, eta1=eta1, fg_exact=True)
+    assert b[4] == 0 and a[3]["solves"] == b[3]["solves"]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and abs(a[2] - b[2]) < 1e-10
+
+
+def test_nested_exact_form_order_and_reversibility(orc):
+    """S_F on the outer scale, S_G on the inner one (two sub-steps), FG with
+    exact G stages on both: dH falls as dt^4 and stays within a few percent of
+    the displacement form's; the pure-gauge nested exact trajectory reverses."""
+    dims = (4, 4, 2, 2)
+    U, P, eta1, _ = start(dims, 7)
+    levels = [(table("FG"), 2, 1), (table("FG"), 1, 2)]
+    dh, dh_disp = [], []
+    for n in (8, 16):
+        _, _, d, _, status = orc.trajectory_nested(dims, 5.6, levels, 1.0, n, U, P, kappa=K, eta1=eta1,
+                                                   fg_exact=True)
+        assert status == 0
+        dh.append(abs(d))
+        dh_disp.append(abs(orc.trajectory_nested(dims, 5.6, levels, 1.0, n, U, P, kappa=K, eta1=eta1)[2]))
+    assert abs(np.log2(dh[0] / dh[1]) - 4) < 0.3, dh
+    assert abs(dh[1] / dh_disp[1] - 1) < 0.2, (dh, dh_disp)
+    two = [(table("FG"), 1, 1), (table("FG"), 1, 2)]
+    Ug1, Pg1, dg, _, _ = orc.trajectory_nested(dims, 5.6, two, 1.0, 3, U, P, fg_exact=True)
+    Ug2, Pg2, dg2, _, _ = orc.trajectory_nested(dims, 5.6, two, 1.0, 3, Ug1, -Pg1, fg_exact=True)
+    assert np.max(np.abs(Ug2 - U)) < 1e-12 and np.max(np.abs(-Pg2 - P)) < 1e-11 and abs(dg + dg2) < 1e-10
+
+
+def test_nested_exact_form_refused_for_hasenbusch_and_smearing(orc):
+    dims = (4, 4, 2, 2)
+    U, P, eta1, eta2 = start(dims, 8)
+    r = orc.trajectory_nested(dims, 5.6, levels_fg3(), 1.0, 2, U, P, kappa=K, kappa2=0.14, eta1=eta1, eta2=eta2,
+                              fg_exact=True)
+    assert r[4] == -2
+    r = orc.trajectory_nested(dims, 5.6, [(table("FG"), 3, 1)], 1.0, 2, U, P, kappa=K, eta1=eta1, fg_exact=True,
+                              stout_rho=0.1, stout_n=1)
+    assert r[4] == -2
