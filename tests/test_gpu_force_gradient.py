@@ -146,3 +146,20 @@ def test_fg_exact_rejected_with_hasenbusch(ctx):
     with pytest.raises(fgi.FgiError) as e:
         ctx.total_force_gradient(dims, act, U, dev(eta))
     assert e.value.code == fgi.FGI_EINVAL
+
+
+@pytest.mark.parametrize("c1", [0.0, -1.0 / 12.0])
+def test_nested_fg_exact(ctx, orc, c1):
+    """Nested scales (S_F outer, S_G inner with two sub-steps), exact G stages on
+    both, against the oracle's nested driver."""
+    dims = (4, 4, 2, 2)
+    U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 2, fermions=True)
+    FG = orc.table("FG")
+    levels = [(FG, 2, 1), (FG, 1, 2)]
+    act = Action(beta=5.6, kappa=0.155, cg_tol=1e-14, fg_exact=True, c1=c1)
+    U, P = dev(U0), dev(P0)
+    dH, st = ctx.trajectory(dims, act, fgi.integrator_from_levels(levels), 1.0, 3, U, P, dev(eta))
+    Uo, Po, dHo, sto, status = orc.trajectory_nested(dims, 5.6, levels, 1.0, 3, U0, P0, kappa=0.155, eta1=eta,
+                                                     fg_exact=True, c1=c1)
+    assert status == 0 and st["solves"] == sto["solves"]
+    assert relmax(host(U), Uo) < 1e-12 and relmax(host(P), Po) < 1e-12 and abs(dH - dHo) < 1e-9
