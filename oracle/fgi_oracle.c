@@ -837,14 +837,15 @@ static void dmhat(const int L[4], double kappa, const cplx *U, const cplx *dU, c
  * and V W the explicit derivative of e_a D (bilinear_add with Vm).
  * scale * J is ADDED to Jout.  Returns the CG iteration count of the Z
  * solve (-1 on maxiter). */
-int oracle_fermion_force_tangent_add(const int L[4], double kappa, const cplx *U, const cplx *Xe,
-                                     const double *v, double tol, int maxiter, double scale, double *Jout) {
+/* The body of the force gradient above for links U, tangent links dU = V U
+ * (Vm the V_l), given X_e: the solve's right-hand side gets extra_rhs added
+ * when given (the derivative of a U-dependent source, for S_2 below), and
+ * Z = d_V X_e is copied to Zout when given. */
+static int pf_tangent_core(const int L[4], double kappa, const cplx *U, const cplx *dU, const mat3 *Vm,
+                           const cplx *Xe, const cplx *extra_rhs, double tol, int maxiter, double scale,
+                           double *Jout, cplx *Zout) {
     long V = lat_volume(L), Vh = V / 2;
     size_t ne = sizeof(cplx) * 12 * Vh, nf = sizeof(cplx) * 12 * V;
-    mat3 *Vm = malloc(sizeof(mat3) * 4 * V);
-    for (long l = 0; l < 4 * V; l++) Vm[l] = alg_from_components(v + l * 8);
-    cplx *dU = malloc(sizeof(cplx) * 4 * V * 9);
-    tangent_links(V, U, Vm, dU);
     cplx *Ye = malloc(ne), *a = malloc(ne), *b = malloc(ne), *rhs = malloc(ne), *Z = malloc(ne);
     cplx *dYe = malloc(ne);
     /* Y_e = Mhat X_e;  rhs = -(dMhat^+ Y_e + Mhat^+ dMhat X_e) = -(d_V A) X_e */
@@ -853,6 +854,8 @@ int oracle_fermion_force_tangent_add(const int L[4], double kappa, const cplx *U
     oracle_mhat(L, kappa, U, a, b, 1);
     dmhat(L, kappa, U, dU, Ye, rhs, 1);
     for (long k = 0; k < Vh * 12; k++) rhs[k] = -(rhs[k] + b[k]);
+    if (extra_rhs)
+        for (long k = 0; k < Vh * 12; k++) rhs[k] += extra_rhs[k];
     int it = oracle_cg(L, kappa, U, rhs, Z, tol, maxiter, NULL);
     /* dY_e = dMhat X_e + Mhat Z */
     oracle_mhat(L, kappa, U, Z, b, 0);
@@ -874,8 +877,21 @@ int oracle_fermion_force_tangent_add(const int L[4], double kappa, const cplx *U
     bilinear_add(L, U, dX, Y, NULL, c, Jout);
     bilinear_add(L, U, X, dY, NULL, c, Jout);
     bilinear_add(L, U, X, Y, Vm, c, Jout);
-    free(Vm); free(dU); free(Ye); free(a); free(b); free(rhs); free(Z); free(dYe);
+    if (Zout) memcpy(Zout, Z, ne);
+    free(Ye); free(a); free(b); free(rhs); free(Z); free(dYe);
     free(X); free(Y); free(dX); free(dY); free(f); free(g);
+    return it;
+}
+
+int oracle_fermion_force_tangent_add(const int L[4], double kappa, const cplx *U, const cplx *Xe,
+                                     const double *v, double tol, int maxiter, double scale, double *Jout) {
+    long V = lat_volume(L);
+    mat3 *Vm = malloc(sizeof(mat3) * 4 * V);
+    for (long l = 0; l < 4 * V; l++) Vm[l] = alg_from_components(v + l * 8);
+    cplx *dU = malloc(sizeof(cplx) * 4 * V * 9);
+    tangent_links(V, U, Vm, dU);
+    int it = pf_tangent_core(L, kappa, U, dU, Vm, Xe, NULL, tol, maxiter, scale, Jout, NULL);
+    free(Vm); free(dU);
     return it;
 }
 
@@ -927,6 +943,49 @@ void oracle_hasen_force_add(const int L[4], double kappa, double kappa2, const c
                             const cplx *X2, double scale, double *F) {
     oracle_fermion_force_add(L, kappa, U, X2, scale, F);
     force_xy_add(L, U, X2, phi2, -scale * kappa2 * kappa2, F);
+}
+
+/* Directional derivative along V of the S_2 force above (the force gradient
+ * of the Hasenbusch ratio term, Section 4's Leibniz rule with a source that
+ * depends on U).  With chi = Mhat2^+ phi2 and X2 = A^-1 chi, A = Mhat^+ Mhat:
+ *   d_V X2 = A^-1 (d_V chi - (d_V A) X2),   d_V chi = dMhat2^+ phi2
+ * (one solve), the first force term differentiates as the plain
+ * pseudofermion force of X2 with that d_V X2, and the second,
+ * -kappa2^2 bc TA W(X, Y) with X = (X2, D_oe X2), Y = (phi2, g5 D_oe g5 phi2),
+ * by the vectors and the links:
+ *   dX = (d_V X2, dD_oe X2 + D_oe d_V X2),  dY = (0, g5 dD_oe g5 phi2).
+ * scale * J is ADDED to Jout; returns the solve's iteration count (-1 on
+ * maxiter). */
+int oracle_hasen_force_tangent_add(const int L[4], double kappa, double kappa2, const cplx *U, const cplx *phi2,
+                                   const cplx *X2, const double *v, double tol, int maxiter, double scale,
+                                   double *Jout) {
+    long V = lat_volume(L), Vh = V / 2;
+    size_t ne = sizeof(cplx) * 12 * Vh, nf = sizeof(cplx) * 12 * V;
+    mat3 *Vm = malloc(sizeof(mat3) * 4 * V);
+    for (long l = 0; l < 4 * V; l++) Vm[l] = alg_from_components(v + l * 8);
+    cplx *dU = malloc(sizeof(cplx) * 4 * V * 9);
+    tangent_links(V, U, Vm, dU);
+    cplx *dchi = malloc(ne), *Z = malloc(ne), *zero = calloc(12 * Vh, sizeof(cplx));
+    dmhat(L, kappa2, U, dU, phi2, dchi, 1);
+    int it = pf_tangent_core(L, kappa, U, dU, Vm, X2, dchi, tol, maxiter, scale, Jout, Z);
+    cplx *X = malloc(nf), *Y = malloc(nf), *dX = malloc(nf), *dY = malloc(nf), *f = malloc(nf), *g = malloc(nf);
+    full_xy(L, U, X2, phi2, X, Y);
+    full_xy(L, U, Z, zero, dX, dY);   /* (Z, D_oe Z); dY zero so far */
+    even_to_full(L, X2, f);
+    hop_to_odd(L, dU, f, g);          /* + dD_oe X2 */
+    for (long k = 0; k < V * 12; k++) dX[k] += g[k];
+    even_to_full(L, phi2, f);
+    apply_g5(V, f);
+    hop_to_odd(L, dU, f, g);
+    apply_g5(V, g);                   /* g5 dD_oe g5 phi2 */
+    for (long k = 0; k < V * 12; k++) dY[k] += g[k];
+    double c = -scale * kappa2 * kappa2;
+    bilinear_add(L, U, dX, Y, NULL, c, Jout);
+    bilinear_add(L, U, X, dY, NULL, c, Jout);
+    bilinear_add(L, U, X, Y, Vm, c, Jout);
+    free(Vm); free(dU); free(dchi); free(Z); free(zero);
+    free(X); free(Y); free(dX); free(dY); free(f); free(g);
+    return it;
 }
 
 /* ------------------------------------------------------------------ */
@@ -1466,10 +1525,10 @@ static void terms_force(nested_run *r, const cplx *W, int terms, double *F, int 
 /* run level l for n steps of size h: the step table repeated n times with
  * neighbouring P stages merged; a Q stage of an outer level runs the next
  * level for w*h in nsub[l+1] steps; the innermost Q stage updates the links */
-/* J = J_V[F_terms] at W (the exact form's force gradient): the gauge part and
- * the S_F (or S_1) part, whose solution X1 at W the force evaluation just
- * left in r->X1 (one more solve for d_V X1).  The S_2 term and smeared links
- * have no exact form here (oracle_trajectory_nested refuses them). */
+/* J = J_V[F_terms] at W (the exact form's force gradient): the gauge part,
+ * the S_F (or S_1) part and the S_2 part, whose solutions X1, X2 at W the
+ * force evaluation just left in r->X1, r->X2 (one more solve each).  Smeared
+ * links have no exact form here (oracle_trajectory_nested refuses them). */
 static void terms_tangent(nested_run *r, const cplx *W, int terms, const double *v, double *J) {
     const int *L = r->L;
     long V = lat_volume(L);
@@ -1479,6 +1538,9 @@ static void terms_tangent(nested_run *r, const cplx *W, int terms, const double 
         double k1 = r->kappa2 != 0.0 ? r->kappa2 : r->kappa;
         count_solve(r, oracle_fermion_force_tangent_add(L, k1, W, r->X1, v, r->tol, r->maxiter, 1.0, J));
     }
+    if (r->kappa2 != 0.0 && (terms & TERM_HASEN))
+        count_solve(r, oracle_hasen_force_tangent_add(L, r->kappa, r->kappa2, W, r->phi2, r->X2, v, r->tol,
+                                                      r->maxiter, 1.0, J));
 }
 
 static void run_level(nested_run *r, int l, int n, double h) {
@@ -1528,7 +1590,7 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
                              const char *kinds, const double *ws, const double *xis, double tau, int nsteps,
                              cplx *U, double *P, const cplx *eta1, const cplx *eta2, double *dH, long *stats3,
                              int fg_start, double c1, double stout_rho, int stout_n, int fg_exact) {
-    if (fg_exact && kappa != 0.0 && (kappa2 != 0.0 || stout_n > 0)) return -2;
+    if (fg_exact && kappa != 0.0 && stout_n > 0) return -2;
     long V = lat_volume(L), Vh = V / 2;
     const char *kp[8];
     const double *wp[8], *xp[8];

@@ -87,6 +87,8 @@ def _declare(L):
     L.oracle_hasen_action.argtypes = [_ip, _d, _d, _vp, _vp, _d, _i, _vp, _ip]
     L.oracle_hasen_action.restype = _d
     L.oracle_hasen_force_add.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _d, _vp]
+    L.oracle_hasen_force_tangent_add.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _vp, _d, _i, _d, _vp]
+    L.oracle_hasen_force_tangent_add.restype = _i
     L.oracle_trajectory_nested.argtypes = [_ip, _d, _d, _d, _d, _i, _i, _vp, _vp, _vp, ctypes.c_char_p, _vp, _vp,
                                            _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i, _d, _d, _i, _i]
     L.oracle_trajectory_nested.restype = _i
@@ -358,6 +360,16 @@ def hasen_force(dims, kappa, kappa2, U, phi2, X2):
     lib().oracle_hasen_force_add(_dims(dims), kappa, kappa2, _ptr(U), _ptr(_c(phi2, np.complex128)),
                                  _ptr(_c(X2, np.complex128)), 1.0, _ptr(F))
     return F
+
+
+def hasen_force_tangent(dims, kappa, kappa2, U, phi2, X2, V, tol=1e-14, maxiter=10000):
+    """J_V[F_2] = d/dt F_2(exp(tV) U) at t = 0 for the S_2 force, given X2 at U (one more solve)"""
+    U = _c(U, np.complex128)
+    J = np.zeros((4, volume(dims), 8))
+    lib().oracle_hasen_force_tangent_add(_dims(dims), kappa, kappa2, _ptr(U), _ptr(_c(phi2, np.complex128)),
+                                         _ptr(_c(X2, np.complex128)), _ptr(_c(V, np.float64)), tol, maxiter, 1.0,
+                                         _ptr(J))
+    return J
 
 
 def trajectory_nested(dims, beta, levels, tau, nsteps, U, P, kappa=0.0, kappa2=0.0, eta1=None, eta2=None,

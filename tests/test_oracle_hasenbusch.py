@@ -137,12 +137,77 @@ def test_nested_exact_form_order_and_reversibility(orc):
     assert np.max(np.abs(Ug2 - U)) < 1e-12 and np.max(np.abs(-Pg2 - P)) < 1e-11 and abs(dg + dg2) < 1e-10
 
 
-def test_nested_exact_form_refused_for_hasenbusch_and_smearing(orc):
+def test_nested_exact_hasenbusch_order_and_solves(orc):
+    """Three nested FG scales (S_2, S_1, S_G) with exact G stages: dH falls as
+    dt^4, close to the displacement form's; each G stage of a fermion level
+    costs one solve more than its force (d_V X), like the displaced force."""
     dims = (4, 4, 2, 2)
     U, P, eta1, eta2 = start(dims, 8)
-    r = orc.trajectory_nested(dims, 5.6, levels_fg3(), 1.0, 2, U, P, kappa=K, kappa2=0.14, eta1=eta1, eta2=eta2,
-                              fg_exact=True)
-    assert r[4] == -2
+    args = dict(kappa=K, kappa2=K2, eta1=eta1, eta2=eta2)
+    dh, dd = [], []
+    for n in (4, 8):
+        Ue, Pe, d, st, status = orc.trajectory_nested(dims, 5.6, levels_fg3(), 1.0, n, U, P, fg_exact=True, **args)
+        assert status == 0
+        Ud, Pd, d2, st2, _ = orc.trajectory_nested(dims, 5.6, levels_fg3(), 1.0, n, U, P, **args)
+        dh.append(abs(d))
+        dd.append(abs(d2))
+        assert st["solves"] == st2["solves"]
+    assert abs(np.log2(dh[0] / dh[1]) - 4) < 0.4, dh
+    assert abs(dh[1] / dd[1] - 1) < 0.3, (dh, dd)
+
+
+def test_nested_exact_form_refused_for_smearing(orc):
+    dims = (4, 4, 2, 2)
+    U, P, eta1, eta2 = start(dims, 8)
     r = orc.trajectory_nested(dims, 5.6, [(table("FG"), 3, 1)], 1.0, 2, U, P, kappa=K, eta1=eta1, fg_exact=True,
                               stout_rho=0.1, stout_n=1)
     assert r[4] == -2
+
+
+def _alg(p):
+    T = 0.5j * synth.gell_mann()
+    return np.einsum("...a,aij->...ij", p, T)
+
+
+def _comp(M):
+    T = 0.5j * synth.gell_mann()
+    return -2 * np.einsum("aij,...ji->...a", T, M).real
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 2, 2)])
+def test_hasen_force_tangent_finite_difference(orc, dims):
+    """The S_2 force gradient against Richardson-extrapolated central
+    differences of the (separately pinned) S_2 force, its X2 re-solved at
+    each displaced field."""
+    U = synth.haar_su3(synth.rng(140), 4 * synth.volume(dims)).reshape(4, -1, 3, 3)
+    phi2 = synth.gaussian_noise(synth.rng(141), dims)
+    Vd = synth.rng(142).standard_normal((4, synth.volume(dims), 8))
+    _, X2 = orc.hasen_action(dims, K, K2, U, phi2)
+    J = orc.hasen_force_tangent(dims, K, K2, U, phi2, X2, Vd)
+
+    def F2(W):
+        _, Xw = orc.hasen_action(dims, K, K2, W, phi2, tol=1e-15)
+        return orc.hasen_force(dims, K, K2, W, phi2, Xw)
+
+    def central(h):
+        return (F2(orc.link_update(dims, h, Vd, U)) - F2(orc.link_update(dims, -h, Vd, U))) / (2 * h)
+
+    h = 2e-3
+    fd = (4 * central(h / 2) - central(h)) / 3
+    assert np.max(np.abs(fd - J)) < 1e-9 * np.max(np.abs(J))
+
+
+def test_hasen_force_tangent_chart_commutator(orc):
+    """<W, J_V F_2> - <V, J_W F_2> = <[W, V], F_2>: pins the explicit link
+    terms of both force parts (the solve terms are symmetric)."""
+    dims = (4, 4, 2, 2)
+    U = synth.haar_su3(synth.rng(143), 4 * synth.volume(dims)).reshape(4, -1, 3, 3)
+    phi2 = synth.gaussian_noise(synth.rng(144), dims)
+    Vd, Wd = synth.rng(145).standard_normal((2, 4, synth.volume(dims), 8))
+    _, X2 = orc.hasen_action(dims, K, K2, U, phi2)
+    JV = orc.hasen_force_tangent(dims, K, K2, U, phi2, X2, Vd)
+    JW = orc.hasen_force_tangent(dims, K, K2, U, phi2, X2, Wd)
+    F = orc.hasen_force(dims, K, K2, U, phi2, X2)
+    lhs = np.sum(Wd * JV) - np.sum(Vd * JW)
+    rhs = np.sum(_comp(_alg(Wd) @ _alg(Vd) - _alg(Vd) @ _alg(Wd)) * F)
+    assert abs(lhs - rhs) < 1e-11 * np.sum(np.abs(Wd * JV))
