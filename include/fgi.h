@@ -79,8 +79,9 @@ typedef struct {
     int prec;           /* FGI_FP64 | FGI_MP32 | FGI_MP16 (CG inner precision) */
     int link_recon;     /* 18 or 12: storage of the FP32 sloppy links (FP16 uses 12) */
     int fg_exact;       /* G stages: 0 = displacement form, 1 = exact force gradient
-                           (gauge and pseudofermion, Section 4; not with
-                           kappa_hasen, not for batched chains) */
+                           (Section 4; every action term, the Hasenbusch ratio
+                           term included; not with stout smearing, not for
+                           batched chains) */
     double c1;          /* rectangle coefficient of the gauge action (finite):
                            S_G = beta sum_x [c0 sum_{mu<nu} (1 - ReTr P_{mu nu}(x)/3)
                                  + c1 sum_{mu!=nu} (1 - ReTr R_{mu nu}(x)/3)],
@@ -255,8 +256,9 @@ int fgi_force(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void
  *   J_F = kappa^2 bc TA(U [C(dX, Y) + C(X, dY)] + V U C(X, Y))
  * over the full-lattice force vectors.  Two solves (one for X, one for d_V X),
  * counted in *st (may be NULL), both in act->prec to act->cg_tol.  FGI_EINVAL
- * with act->kappa_hasen != 0 (the Hasenbusch terms have no exact gradient
- * here); FGI_ENOCONV when a solve hits cg_maxiter (J is still written).
+ * with act->kappa_hasen != 0 (this call takes one pseudofermion; trajectories
+ * with fg_exact take the Hasenbusch terms' gradient); FGI_ENOCONV when a solve
+ * hits cg_maxiter (J is still written).
  * Synchronises the stream. */
 int fgi_total_force_gradient(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U,
                              const void* phi, const void* V, void* J, fgi_stats* st, void* stream);

@@ -235,10 +235,14 @@ struct Fields {
     // J = J_V[F_terms](u) = d/dt F_terms(exp(t V) u) at t = 0: the gauge part
     // analytic, the pseudofermion part by the Section 4 Leibniz rule with one
     // more solve (for d_V X).  X must hold the S_F solve at u.
+    // With Hasenbusch terms, X and X2 must hold the S_1 and S_2 solves at u
+    // (those of the force evaluation just before).  The S_2 part: chi =
+    // Mhat2^+ phi2 moves with u, so d_V X2 = A^-1 (d_V chi - (d_V A) X2) (one
+    // solve), and its chi-dependent force term -kappa2^2 TA(U C(X2, phi2))
+    // differentiates through X2 and the links.
     void force_tangent(const d2* u, const void* us, int terms, const double* Vd, double* J) {
         const bool ferm = act.kappa != 0.0 && (terms & (FGI_TERM_FERMION | FGI_TERM_HASEN));
-        if (ferm && act.kappa_hasen != 0.0)
-            throw Error(FGI_EINVAL, "the exact force gradient is not available for the Hasenbusch terms");
+        const bool hasen = act.kappa_hasen != 0.0;
         if (ferm && act.stout_n > 0)
             throw Error(FGI_EINVAL, "the exact force gradient is not available with stout smearing");
         if (terms & FGI_TERM_GAUGE) gauge_force_tangent(c, g, act.beta, u, Vd, J, 1.0, 0, 0, act.c1);
@@ -246,12 +250,26 @@ struct Fields {
         if (!ferm) return;
         d2* W = (d2*)c.gauge_tan.get(gauge_bytes(g));
         tangent_links(c, g, Vd, u, W);
-        const FermionOp o64 = op64(u, act.kappa), oW = op64(W, act.kappa);
         d2* rhs = (d2*)c.tg_rhs.get(spinor_bytes(g));
         d2* Z = (d2*)c.tg_z.get(spinor_bytes(g));
-        fermion_tangent_rhs(c, o64, oW, X, rhs);
-        solve(u, us, act.kappa, rhs, Z);
-        fermion_force_tangent(c, o64, oW, Vd, X, Z, J, 1.0);
+        if (terms & FGI_TERM_FERMION) {
+            const double k1 = hasen ? act.kappa_hasen : act.kappa;
+            const FermionOp o64 = op64(u, k1), oW = op64(W, k1);
+            fermion_tangent_rhs(c, o64, oW, X, rhs);
+            solve(u, us, k1, rhs, Z);
+            fermion_force_tangent(c, o64, oW, Vd, X, Z, J, 1.0);
+        }
+        if ((terms & FGI_TERM_HASEN) && hasen) {
+            const FermionOp o64 = op64(u, act.kappa), oW = op64(W, act.kappa);
+            const FermionOp o2 = op64(u, act.kappa_hasen), oW2 = op64(W, act.kappa_hasen);
+            d2* dchi = (d2*)c.hs_dchi.get(spinor_bytes(g));
+            dmhat_dag_apply(c, o2, oW2, phi[1], dchi);
+            fermion_tangent_rhs(c, o64, oW, X2, rhs);
+            spinor_lincomb(c, g, 1.0, rhs, 1.0, dchi, 0, rhs);
+            solve(u, us, act.kappa, rhs, Z);
+            fermion_force_tangent(c, o64, oW, Vd, X2, Z, J, 1.0);
+            fermion_force_xy_tangent(c, o2, oW2, Vd, X2, phi[1], Z, J, -act.kappa_hasen * act.kappa_hasen);
+        }
     }
 
     // chi = Mhat2^+ phi2 at u; X2 = (Mhat^+ Mhat)^-1 chi
@@ -338,7 +356,8 @@ int fgi_destroy(fgi_ctx* ctx) {
                           &c.chi, &c.X2, &c.cdesc, &c.bstate, &c.bscal, &c.bh0, &c.bh1, &c.bres,
                           &c.gauge_tan, &c.tg_dmx, &c.tg_rhs, &c.tg_z, &c.tg_dxo, &c.tg_dye, &c.tg_dyo,
                           &c.force3, &c.chain_U, &c.stout_lev, &c.stout_F, &c.stout_ga, &c.stout_gb,
-                          &c.stout_part, &c.stout_M, &c.stout_sloppy};
+                          &c.stout_part, &c.stout_M, &c.stout_sloppy, &c.hs_dchi, &c.hs_xo, &c.hs_yo,
+                          &c.hs_dxo, &c.hs_dyo, &c.hs_zero, &c.hs_t1};
         for (DevBuf* b : bufs) b->release();
         for (hipEvent_t e : c.ev_pool) hipEventDestroy(e);
         for (GraphEntry& e : c.graphs) hipGraphExecDestroy(e.exec);
@@ -759,7 +778,9 @@ int fgi_total_force_gradient(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action*
         Ctx& c = ctx_of(ctx);
         if (!gg) throw Error(FGI_EINVAL, "null geometry");
         check_action(act);
-        if (act->kappa_hasen != 0) throw Error(FGI_EINVAL, "no exact force gradient for the Hasenbusch terms");
+        if (act->kappa_hasen != 0)
+            throw Error(FGI_EINVAL, "this call takes one pseudofermion: no Hasenbusch terms (trajectories with "
+                                    "fg_exact take them)");
         Geom g = make_geom(gg->dims);
         need(U, "U", 16);
         need(J, "J", 8);
@@ -1098,8 +1119,6 @@ namespace {
 void check_trajectory_args(const fgi_action* act, const fgi_integrator* integ, int nsteps, double tau) {
     check_action(act);
     check_integrator(integ);
-    if (act->fg_exact && act->kappa_hasen != 0)
-        throw Error(FGI_EINVAL, "the exact force gradient is not available for the Hasenbusch terms");
     if (act->fg_exact && act->kappa != 0 && act->stout_n > 0)
         throw Error(FGI_EINVAL, "the exact force gradient is not available with stout smearing");
     if (nsteps < 1) throw Error(FGI_EINVAL, "nsteps must be >= 1");

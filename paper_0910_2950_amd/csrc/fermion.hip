@@ -882,6 +882,57 @@ void fermion_force_tangent(Ctx& c, const FermionOp& op64, const FermionOp& opW, 
     FGI_LAUNCH_CHECK();
 }
 
+static void zero_spinor(Ctx& c, const Geom& g, void* v, int prec);
+
+// d_V chi for chi = Mhat^+ phi at op64.kappa: out_e = dMhat^+ in_e =
+// -kappa^2 g5 (dD_eo D_oe + D_eo dD_oe) g5 in_e, dD the hopping term on the
+// tangent links of opW (uses tmp_o, tmp_e and the hs_t1 scratch)
+void dmhat_dag_apply(Ctx& c, const FermionOp& op64, const FermionOp& opW, const d2* in_e, d2* out_e) {
+    const Geom& g = *op64.g;
+    const size_t n = sizeof(d2) * 12 * (size_t)g.Vh;
+    const double k2 = op64.kappa * op64.kappa;
+    d2 *to = (d2*)c.tmp_o.get(n), *te = (d2*)c.tmp_e.get(n), *t1 = (d2*)c.hs_t1.get(n);
+    hop_g5(c, op64, in_e, to, 0);                              // D_oe g5 in
+    {
+        DArgs a = base_args(opW, 0);                           // dD_eo D_oe g5 in
+        a.in = sp(to);
+        a.out = sp(te);
+        launch_dslash<M_HOP, P64, P64, P64, P64, 0>(c, opW, a);
+    }
+    hop_g5(c, opW, in_e, t1, 0);                               // dD_oe g5 in
+    dslash(c, op64, 0, P64, sp(t1), P64, sp(out_e));           // D_eo dD_oe g5 in
+    lincomb(c, g, 0.0, out_e, -k2, te, 0, te);                 // -k2 dD_eo D_oe g5 in
+    lincomb(c, g, -k2, out_e, 1.0, te, 0, out_e);              // -k2 (... + D_eo dD_oe g5 in)
+    lincomb(c, g, 0.0, out_e, 1.0, out_e, 1, out_e);           // g5
+}
+
+// J += coef bc TA(U [C(dX, Y) + C(X, dY)] + V U C(X, Y)) for the bilinear force
+// of fermion_force_xy with X = (X_e, D_oe X_e), Y = (Y_e, g5 D_oe g5 Y_e), when
+// X_e moves by dX_e and Y_e is fixed: dX = (dX_e, dD_oe X_e + D_oe dX_e),
+// dY = (0, g5 dD_oe g5 Y_e)
+void fermion_force_xy_tangent(Ctx& c, const FermionOp& op64, const FermionOp& opW, const double* Vd, const d2* Xe,
+                              const d2* Ye, const d2* dXe, double* J, double coef) {
+    const Geom& g = *op64.g;
+    const size_t n = sizeof(d2) * 12 * (size_t)g.Vh;
+    d2 *xo = (d2*)c.hs_xo.get(n), *yo = (d2*)c.hs_yo.get(n), *dxo = (d2*)c.hs_dxo.get(n);
+    d2 *dyo = (d2*)c.hs_dyo.get(n), *zero = (d2*)c.hs_zero.get(n), *t1 = (d2*)c.hs_t1.get(n);
+    zero_spinor(c, g, zero, P64);
+    dslash(c, op64, 1, P64, sp(Xe), P64, sp(xo));               // X_o = D_oe X_e
+    hop_g5(c, op64, Ye, yo, 1);                                 // Y_o = g5 D_oe g5 Y_e
+    dslash(c, opW, 1, P64, sp(Xe), P64, sp(dxo));               // dD_oe X_e
+    dslash(c, op64, 1, P64, sp(dXe), P64, sp(t1));              // + D_oe dX_e
+    lincomb(c, g, 1.0, dxo, 1.0, t1, 0, dxo);
+    hop_g5(c, opW, Ye, dyo, 1);                                 // dY_o = g5 dD_oe g5 Y_e
+    hipLaunchKernelGGL(k_fermion_force_tangent, dim3(slab_blocks(g.Vh, 2, 256, c.ds_xcd)), dim3(256), 0, c.stream, g,
+                       (const d2*)op64.links, Vd, sp(Xe), sp(xo), sp(Ye), sp(yo), sp(dXe), sp(dxo), sp(zero), sp(dyo),
+                       coef, J, c.ds_xcd);
+    FGI_LAUNCH_CHECK();
+}
+
+void spinor_lincomb(Ctx& c, const Geom& g, double a, const d2* x, double b, const d2* y, int g5y, d2* out) {
+    lincomb(c, g, a, x, b, y, g5y, out);
+}
+
 // ---------------------------------------------------------------- CG ------
 static double norm2_sync(Ctx& c, const Geom& g, const d2* v) {
     double* part = partial_buf(c, g);

@@ -100,6 +100,8 @@ struct Ctx {
     // stout smearing: the smeared levels, the fermion force on the top level and
     // its back-propagation scratch, the sloppy copy of the smeared links
     DevBuf stout_lev, stout_F, stout_ga, stout_gb, stout_part, stout_M, stout_sloppy;
+    // exact force gradient of the Hasenbusch ratio term
+    DevBuf hs_dchi, hs_xo, hs_yo, hs_dxo, hs_dyo, hs_zero, hs_t1;
     DevBuf cdesc, bstate, bscal, bh0, bh1, bres;  // batched chains
     CGState* host_bstates = nullptr;          // pinned [host_b_cap]
     double* host_bscal = nullptr;             // pinned [host_b_cap]
@@ -262,6 +264,13 @@ void fermion_force_xy(Ctx&, const FermionOp& op64, const d2* Xe, const d2* Ye, d
 // around the one extra solve.  opW is the operator on the tangent links V U.
 //   rhs = -(d_V A) X_e,  A = Mhat^+ Mhat     (also keeps Y_e, X_o, ... for the second half)
 void fermion_tangent_rhs(Ctx&, const FermionOp& op64, const FermionOp& opW, const d2* Xe, d2* rhs);
+// out_e = dMhat^+ in_e along the tangent links of opW (d_V of Mhat^+ phi)
+void dmhat_dag_apply(Ctx&, const FermionOp& op64, const FermionOp& opW, const d2* in_e, d2* out_e);
+// J += coef * d_V of the bilinear force of fermion_force_xy(X_e, Y_e) when X_e moves by dX_e, Y_e fixed
+void fermion_force_xy_tangent(Ctx&, const FermionOp& op64, const FermionOp& opW, const double* Vd, const d2* Xe,
+                              const d2* Ye, const d2* dXe, double* J, double coef);
+// out = a x + b [g5] y on FP64 even vectors
+void spinor_lincomb(Ctx&, const Geom&, double a, const d2* x, double b, const d2* y, int g5y, d2* out);
 //   J += coef * J_V[F_F] given Z = A^-1 rhs (after fermion_tangent_rhs on the same X_e)
 void fermion_force_tangent(Ctx&, const FermionOp& op64, const FermionOp& opW, const double* Vd, const d2* Xe,
                            const d2* Z, double* J, double coef);

@@ -134,18 +134,42 @@ def test_trajectory_fg_exact_fermions(ctx, orc, dims, n):
     assert st["solves"] == sto["solves"]
 
 
-def test_fg_exact_rejected_with_hasenbusch(ctx):
+def test_total_force_gradient_rejects_hasenbusch(ctx):
+    """fgi_total_force_gradient takes one pseudofermion; the Hasenbusch terms'
+    gradient runs inside trajectories (below)."""
     dims = (4, 4, 4, 4)
     U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 1, fermions=True)
     act = Action(beta=5.6, kappa=0.155, kappa_hasen=0.15, cg_tol=1e-10, fg_exact=True)
+    with pytest.raises(fgi.FgiError) as e:
+        ctx.total_force_gradient(dims, act, dev(U0), dev(eta))
+    assert e.value.code == fgi.FGI_EINVAL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mp16"])
+def test_nested_hasenbusch_fg_exact(ctx, orc, prec):
+    """Three nested FG scales (S_2 outer, S_1, S_G inner) with exact G stages,
+    the S_2 force gradient included, against the oracle's nested driver (FP64:
+    the 1e-12 / 1e-9 gates and the oracle's solve count; MP16 to the solver
+    tolerance)."""
+    dims = (4, 4, 2, 2)
+    FG = orc.table("FG")
+    levels = [(FG, 4, 1), (FG, 2, 2), (FG, 1, 2)]
+    U0, P0, _, _ = synth.hot_start(dims, synth.SEED_BASE + 3, fermions=False)
+    e1 = synth.gaussian_noise(synth.rng(150), dims)
+    e2 = synth.gaussian_noise(synth.rng(151), dims)
+    tol = 1e-14 if prec == "fp64" else 1e-12
+    act = Action(beta=5.6, kappa=0.155, kappa_hasen=0.14, cg_tol=tol, fg_exact=True, prec=prec,
+                 link_recon=12 if prec == "mp16" else 18)
     U, P = dev(U0), dev(P0)
-    with pytest.raises(fgi.FgiError) as e:
-        ctx.trajectory(dims, act, "FG", 1.0, 2, U, P, dev(eta), dev(eta))
-    assert e.value.code == fgi.FGI_EINVAL
-    assert np.array_equal(host(U), U0) and np.array_equal(host(P), P0)
-    with pytest.raises(fgi.FgiError) as e:
-        ctx.total_force_gradient(dims, act, U, dev(eta))
-    assert e.value.code == fgi.FGI_EINVAL
+    dH, st = ctx.trajectory(dims, act, fgi.integrator_from_levels(levels), 1.0, 2, U, P, dev(e1), dev(e2))
+    Uo, Po, dHo, sto, status = orc.trajectory_nested(dims, 5.6, levels, 1.0, 2, U0, P0, kappa=0.155, kappa2=0.14,
+                                                     eta1=e1, eta2=e2, fg_exact=True)
+    assert status == 0
+    if prec == "fp64":
+        assert st["solves"] == sto["solves"]
+        assert relmax(host(U), Uo) < 1e-12 and relmax(host(P), Po) < 1e-12 and abs(dH - dHo) < 1e-9
+    else:
+        assert relmax(host(U), Uo) < 1e-8 and relmax(host(P), Po) < 1e-8 and abs(dH - dHo) < 1e-6
 
 
 @pytest.mark.parametrize("c1", [0.0, -1.0 / 12.0])
