@@ -243,6 +243,10 @@ int fgi_force_gradient(fgi_ctx* ctx, const fgi_geom* g, double beta, const void*
  * PyTorch autograd wrapper.) */
 int fgi_gauge_hvp(fgi_ctx* ctx, const fgi_geom* g, double beta, const void* U, const void* V, void* HV,
                   void* stream);
+/* The same Hessian-vector product for the improved gauge action with
+ * rectangle coefficient c1 (as fgi_action.c1); FGI_EINVAL for a non-finite c1. */
+int fgi_improved_gauge_hvp(fgi_ctx* ctx, const fgi_geom* g, double beta, double c1, const void* U, const void* V,
+                           void* HV, void* stream);
 /* F = F_G + F_F, the total force of S_G + S_F at U for pseudofermion phi
  * (even field; NULL or act->kappa == 0 for pure gauge).  One CG solve. */
 int fgi_force(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* phi, void* F,

@@ -544,9 +544,15 @@ int fgi_force_gradient(fgi_ctx* ctx, const fgi_geom* gg, double beta, const void
 
 int fgi_gauge_hvp(fgi_ctx* ctx, const fgi_geom* gg, double beta, const void* U, const void* Vd, void* HV,
                   void* stream) {
+    return fgi_improved_gauge_hvp(ctx, gg, beta, 0.0, U, Vd, HV, stream);
+}
+
+int fgi_improved_gauge_hvp(fgi_ctx* ctx, const fgi_geom* gg, double beta, double c1, const void* U, const void* Vd,
+                           void* HV, void* stream) {
     return guarded([&] {
         Ctx& c = ctx_of(ctx);
         if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        if (!std::isfinite(c1)) throw Error(FGI_EINVAL, "the rectangle coefficient c1 must be finite");
         Geom g = make_geom(gg->dims);
         need(U, "U", 16);
         need(Vd, "V", 8);
@@ -557,7 +563,7 @@ int fgi_gauge_hvp(fgi_ctx* ctx, const fgi_geom* gg, double beta, const void* U, 
         double* j = (double*)c.force.get(mom_bytes(g));
         pack_gauge(c, g, U, u);
         pack_mom(c, g, (const double*)Vd, v);
-        gauge_force_tangent(c, g, beta, u, v, j, 1.0, 0, 1);
+        gauge_force_tangent(c, g, beta, u, v, j, 1.0, 0, 1, c1);
         unpack_mom(c, g, j, (double*)HV);
     });
 }

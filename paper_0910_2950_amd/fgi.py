@@ -102,6 +102,7 @@ SIGNATURES = {
     "fgi_get_profile": (_i, [_vp, _P(_d), _P(ctypes.c_long), _P(ctypes.c_long)]),
     "fgi_gauge_action": (_i, [_vp, _P(fgi_geom), _d, _vp, _P(_d), _vp]),
     "fgi_improved_gauge_action": (_i, [_vp, _P(fgi_geom), _d, _d, _vp, _P(_d), _vp]),
+    "fgi_improved_gauge_hvp": (_i, [_vp, _P(fgi_geom), _d, _d, _vp, _vp, _vp, _vp]),
     "fgi_stout_smear": (_i, [_vp, _P(fgi_geom), _d, _i, _vp, _vp, _vp]),
     "fgi_stout_force": (_i, [_vp, _P(fgi_geom), _d, _i, _vp, _vp, _vp, _vp]),
     "fgi_kinetic": (_i, [_vp, _P(fgi_geom), _vp, _P(_d), _vp]),
@@ -328,6 +329,14 @@ class Context:
         HV = torch.empty(sp, dtype=torch.float64, device=U.device) if HV is None else HV
         _check(lib().fgi_gauge_hvp(self.h, _geom(dims), beta, _ptr(U, torch.complex128, su, "U"),
                                    _ptr(V, torch.float64, sp, "V"), _ptr(HV, torch.float64, sp, "HV"), _stream()))
+        return HV
+
+    def improved_gauge_hvp(self, dims, beta, c1, U, V, HV=None):
+        su, sp, _ = self._shapes(dims)
+        HV = torch.empty(sp, dtype=torch.float64, device=U.device) if HV is None else HV
+        _check(lib().fgi_improved_gauge_hvp(self.h, _geom(dims), beta, c1, _ptr(U, torch.complex128, su, "U"),
+                                            _ptr(V, torch.float64, sp, "V"), _ptr(HV, torch.float64, sp, "HV"),
+                                            _stream()))
         return HV
 
     def force(self, dims, act, U, phi=None, F=None, allow_noconv=False):
