@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--exact-steps", type=int, default=2,
                     help="trajectories of the exact force-gradient form on the first timed inputs (0: skip)")
     ap.add_argument("--chain-steps", type=int, default=3, help="on-device Markov-chain trajectories (0: skip)")
+    ap.add_argument("--md-tol", type=float, default=1e-7,
+                    help="force-solve tolerance of the looser-MD leg (0: skip; dH solves keep --tol)")
     ap.add_argument("--tune-alpha", type=int, default=8, metavar="K",
                     help="Omelyan alpha from Poisson brackets measured over K trajectories (0: skip)")
     ap.add_argument("--n-omelyan", type=int, default=38, help="PQPQP step count of the alpha-tuning leg")
@@ -750,6 +752,18 @@ def main():
             "%.3e -> %.3e" % (args.n_omelyan, args.tune_alpha, alpha_leg["alpha_tuned"],
                               alpha_leg["predicted_dH2"]["0.1932"], alpha_leg["predicted_dH2"]["tuned"],
                               alpha_leg["measured_dH2"]["0.1932"], alpha_leg["measured_dH2"]["tuned"]))
+    md_leg = None
+    if args.md_tol > 0:
+        # the timed starts again, the solves inside force evaluations at --md-tol
+        R.apply(tune_fg)
+        act_md = dataclasses.replace(act_fg, cg_tol_md=args.md_tol)
+        recs_md, sec_md, _ = R.run_leg(U, act_md, "FG", args.n_fg, inputs[args.warmup:])
+        md_leg = summarise(recs_md)
+        md_leg.update(cg_tol_md=args.md_tol, n=args.n_fg, s_per_traj=sec_md / args.steps, trajectories=args.steps,
+                      speedup_vs_value=round(s_per_traj / (sec_md / args.steps), 3))
+        log("FG-%s n=%d with MD solves at %.0e: %.4f s/traj  <dH^2>=%.4e (timed leg %.4e) iters=%.0f" %
+            (args.prec, args.n_fg, args.md_tol, md_leg["s_per_traj"], md_leg["mean_dH2"], fg["mean_dH2"],
+             md_leg["cg_iters_per_traj"]))
     chain = None
     if args.chain_steps > 0:
         R.apply(tune_fg)
@@ -807,7 +821,7 @@ def main():
                fg=fg, fg_exact=exact, lf_fp64=lf,
                speedup_vs_lf_fp64=(round(lf["s_per_traj"] / s_per_traj, 3) if lf else None),
                roofline=roof, roofline_32x32x32x64=large, hasenbusch_32x32x32x64=hasen, batched=batched,
-               alpha_tuning=alpha_leg, chain=chain, improved_gauge=improved, stout=stout,
+               alpha_tuning=alpha_leg, md_tolerance=md_leg, chain=chain, improved_gauge=improved, stout=stout,
                cpu_baseline=cpu)
     print(json.dumps(out), flush=True)
 

@@ -102,6 +102,12 @@ typedef struct {
                            (dslash, mhat, cg_solve, pf_*, fermion_force, hasen_*)
                            act on the links they are given. */
     int pad;
+    double cg_tol_md;   /* tolerance of the solves inside force evaluations
+                           (forces, force gradients, brackets, the MD of
+                           trajectories and chains); 0 = cg_tol.  The heatbath
+                           and action solves that enter dH keep cg_tol, so a
+                           looser MD tolerance leaves the accept/reject step
+                           exact.  In [0, 1), else FGI_EINVAL. */
 } fgi_action;
 
 /* One stage of an integrator step (Table 1), coefficients multiply the step h:

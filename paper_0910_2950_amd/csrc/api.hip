@@ -113,6 +113,7 @@ void check_action(const fgi_action* a) {
     if (a->kappa_hasen != 0 && (a->kappa == 0 || a->kappa_hasen >= a->kappa))
         throw Error(FGI_EINVAL, "Hasenbusch kappa' must satisfy 0 < kappa' < kappa");
     if (!std::isfinite(a->c1)) throw Error(FGI_EINVAL, "the rectangle coefficient c1 must be finite");
+    if (!(a->cg_tol_md >= 0.0 && a->cg_tol_md < 1.0)) throw Error(FGI_EINVAL, "cg_tol_md must be in [0, 1)");
     if (a->stout_n < 0 || a->stout_n > 8) throw Error(FGI_EINVAL, "stout_n must be in [0, 8]");
     if (!(a->stout_rho >= 0.0 && a->stout_rho <= 0.5)) throw Error(FGI_EINVAL, "stout_rho must be in [0, 0.5]");
 }
@@ -161,8 +162,12 @@ struct Fields {
         return FermionOp{&g, kappa, us, sp, rc};
     }
 
-    CGResult solve(const d2* u, const void* us, double kappa, const d2* rhs, d2* x, bool guess = false) {
-        CGResult r = cg_solve(c, op64(u, kappa), ops(u, us, kappa), sp, rhs, x, act.cg_tol, act.cg_maxiter, guess);
+    // md: a solve inside a force evaluation (tolerance cg_tol_md when set);
+    // the heatbath and action solves keep cg_tol
+    CGResult solve(const d2* u, const void* us, double kappa, const d2* rhs, d2* x, bool guess = false,
+                   bool md = false) {
+        const double tol = (md && act.cg_tol_md > 0.0) ? act.cg_tol_md : act.cg_tol;
+        CGResult r = cg_solve(c, op64(u, kappa), ops(u, us, kappa), sp, rhs, x, tol, act.cg_maxiter, guess);
         accumulate_stats(st, r);
         if (!r.converged) nonconv = true;
         return r;
@@ -216,13 +221,13 @@ struct Fields {
         }
         const double k1 = act.kappa_hasen != 0.0 ? act.kappa_hasen : act.kappa;
         if (terms & FGI_TERM_FERMION) {
-            solve(fl.u, fl.us, k1, phi[0], X, guess);
+            solve(fl.u, fl.us, k1, phi[0], X, guess, true);
             fermion_force(c, op64(fl.u, k1), X, fo, fc);
         }
         if ((terms & FGI_TERM_HASEN) && act.kappa_hasen != 0.0) {
             // S_2 = chi^+ (Mhat^+ Mhat)^-1 chi, chi = Mhat2^+ phi2: the ordinary force
             // of X2 at kappa plus -kappa2^2 TA(U C(X2, phi2)) from the U dependence of chi
-            hasen_solve(fl.u, fl.us, guess);
+            hasen_solve(fl.u, fl.us, guess, true);
             fermion_force(c, op64(fl.u, act.kappa), X2, fo, fc);
             fermion_force_xy(c, op64(fl.u, act.kappa_hasen), X2, phi[1], fo,
                              -fc * act.kappa_hasen * act.kappa_hasen);
@@ -256,7 +261,7 @@ struct Fields {
             const double k1 = hasen ? act.kappa_hasen : act.kappa;
             const FermionOp o64 = op64(u, k1), oW = op64(W, k1);
             fermion_tangent_rhs(c, o64, oW, X, rhs);
-            solve(u, us, k1, rhs, Z);
+            solve(u, us, k1, rhs, Z, false, true);
             fermion_force_tangent(c, o64, oW, Vd, X, Z, J, 1.0);
         }
         if ((terms & FGI_TERM_HASEN) && hasen) {
@@ -266,18 +271,18 @@ struct Fields {
             dmhat_dag_apply(c, o2, oW2, phi[1], dchi);
             fermion_tangent_rhs(c, o64, oW, X2, rhs);
             spinor_lincomb(c, g, 1.0, rhs, 1.0, dchi, 0, rhs);
-            solve(u, us, act.kappa, rhs, Z);
+            solve(u, us, act.kappa, rhs, Z, false, true);
             fermion_force_tangent(c, o64, oW, Vd, X2, Z, J, 1.0);
             fermion_force_xy_tangent(c, o2, oW2, Vd, X2, phi[1], Z, J, -act.kappa_hasen * act.kappa_hasen);
         }
     }
 
     // chi = Mhat2^+ phi2 at u; X2 = (Mhat^+ Mhat)^-1 chi
-    void hasen_solve(const d2* u, const void* us, bool guess = false) {
+    void hasen_solve(const d2* u, const void* us, bool guess = false, bool md = false) {
         d2* t = (d2*)c.tmp_o.get(spinor_bytes(g));
         mhat(c, op64(u, act.kappa_hasen), P64, SpinorPtr{phi[1], nullptr}, SpinorPtr{t, nullptr},
              SpinorPtr{chi, nullptr}, 1);
-        solve(u, us, act.kappa, chi, X2, guess);
+        solve(u, us, act.kappa, chi, X2, guess, md);
     }
 
     // phi2 = Mhat2 (Mhat2^+ Mhat2)^-1 Mhat^+ eta2 at the fermion links of u
@@ -1428,9 +1433,9 @@ struct BFields {
         if (sp == P64) return op64(u);
         return FermionOp{nullptr, 0.0, us, sp, rc};
     }
-    void solve(const d2* u, const void* us, const d2* rhs, d2* x, bool guess = false) {
-        std::vector<CGResult> r =
-            cg_solve_b(c, B, op64(u), ops(u, us), sp, rhs, x, act.cg_tol, act.cg_maxiter, guess);
+    void solve(const d2* u, const void* us, const d2* rhs, d2* x, bool guess = false, bool md = false) {
+        const double tol = (md && act.cg_tol_md > 0.0) ? act.cg_tol_md : act.cg_tol;
+        std::vector<CGResult> r = cg_solve_b(c, B, op64(u), ops(u, us), sp, rhs, x, tol, act.cg_maxiter, guess);
         for (const CGResult& q : r) {
             accumulate_stats(st, q);
             if (!q.converged) nonconv = true;
@@ -1467,13 +1472,13 @@ struct BFields {
                 const size_t nm = 8 * (size_t)B.links;
                 double* fo = (double*)c.stout_F.get(sizeof(double) * nm);
                 zero_doubles(c, fo, nm);
-                solve(fl.u, fl.us, phi, X, guess);
+                solve(fl.u, fl.us, phi, X, guess, true);
                 fermion_force_b(c, B, op64(fl.u), X, fo, 1.0);
                 stout_backprop_b(c, B, act.stout_rho, act.stout_n, u,
                                  (const d2*)c.stout_lev.get(sizeof(d2) * 9 * (size_t)B.links * act.stout_n), fo, out,
                                  coef, 1);
             } else {
-                solve(u, us, phi, X, guess);
+                solve(u, us, phi, X, guess, true);
                 fermion_force_b(c, B, op64(u), X, out, coef);
             }
         }

@@ -40,7 +40,8 @@ class fgi_action(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("kappa", ctypes.c_double), ("kappa_hasen", ctypes.c_double),
                 ("cg_tol", ctypes.c_double), ("cg_maxiter", ctypes.c_int), ("prec", ctypes.c_int),
                 ("link_recon", ctypes.c_int), ("fg_exact", ctypes.c_int), ("c1", ctypes.c_double),
-                ("stout_rho", ctypes.c_double), ("stout_n", ctypes.c_int), ("pad", ctypes.c_int)]
+                ("stout_rho", ctypes.c_double), ("stout_n", ctypes.c_int), ("pad", ctypes.c_int),
+                ("cg_tol_md", ctypes.c_double)]
 
 
 class fgi_stage(ctypes.Structure):
@@ -182,11 +183,12 @@ class Action:
     c1: float = 0.0      # rectangle coefficient of the gauge action (0: Wilson)
     stout_rho: float = 0.0
     stout_n: int = 0     # stout levels of the links the fermion operator sees (0: thin links)
+    cg_tol_md: float = 0.0   # tolerance of the solves inside force evaluations (0: cg_tol)
 
     def c(self):
         return fgi_action(self.beta, self.kappa, self.kappa_hasen, self.cg_tol, int(self.cg_maxiter),
                           PREC[self.prec], int(self.link_recon), int(bool(self.fg_exact)), float(self.c1),
-                          float(self.stout_rho), int(self.stout_n), 0)
+                          float(self.stout_rho), int(self.stout_n), 0, float(self.cg_tol_md))
 
 
 def integrator_builtin(which, alpha=0.1932):
