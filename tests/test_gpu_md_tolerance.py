@@ -7,8 +7,10 @@ while the heatbath and action solves that enter dH keep cg_tol.
     (gauge and kinetic energy, a fresh 1e-14 solve for S_F at the end) and it
     agrees to the action solves' tolerance, far below the MD tolerance's
     effect on S_F;
-  - the MD map stays reversible (every solve starts from zero or from a
-    solution at the same links), and it takes fewer CG iterations;
+  - the MD map reverses to the MD tolerance (every solve starts from zero or
+    from a solution at the same links; a solve stopping at a looser threshold
+    reacts to last-bit differences of the links by up to that threshold), and
+    it takes fewer CG iterations;
   - invalid values are rejected.
 """
 import numpy as np
@@ -75,8 +77,10 @@ def test_md_tolerance_reversible(ctx, orc):
     dH1, _ = ctx.trajectory(dims, act, "FG", 1.0, 4, U, P, dev(phi), pf_is_phi=True)
     P.neg_()
     dH2, _ = ctx.trajectory(dims, act, "FG", 1.0, 4, U, P, dev(phi), pf_is_phi=True)
-    assert relmax(host(U), U0) < 1e-10 and relmax(-host(P), P0) < 1e-10
-    assert abs(dH1 + dH2) < 1e-7
+    # reversible to the MD tolerance: links that differ in the last bits can make
+    # a solve stop one iteration earlier or later, a force change of order cg_tol_md
+    assert relmax(host(U), U0) < 1e-7 and relmax(-host(P), P0) < 1e-7
+    assert abs(dH1 + dH2) < 1e-5
 
 
 def test_md_tolerance_validated(ctx):
