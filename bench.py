@@ -761,6 +761,17 @@ def main():
         md_leg = summarise(recs_md)
         md_leg.update(cg_tol_md=args.md_tol, n=args.n_fg, s_per_traj=sec_md / args.steps, trajectories=args.steps,
                       speedup_vs_value=round(s_per_traj / (sec_md / args.steps), 3))
+        if lf is not None:
+            # the FP64 leapfrog leg under the same tolerance policy
+            R.apply(tune_lf)
+            recs_lmd, sec_lmd, _ = R.run_leg(U, dataclasses.replace(R.action("fp64"), cg_tol_md=args.md_tol), "PQP",
+                                             args.n_lf, lf_inputs)
+            lmd = summarise(recs_lmd)
+            lmd.update(n=args.n_lf, s_per_traj=sec_lmd / args.lf_steps, trajectories=args.lf_steps)
+            md_leg["lf_fp64"] = lmd
+            md_leg["speedup_vs_lf_fp64"] = round(lmd["s_per_traj"] / md_leg["s_per_traj"], 3)
+            log("LF-fp64 n=%d with MD solves at %.0e: %.4f s/traj  <dH^2>=%.4e; FG speedup %.2f" %
+                (args.n_lf, args.md_tol, lmd["s_per_traj"], lmd["mean_dH2"], md_leg["speedup_vs_lf_fp64"]))
         log("FG-%s n=%d with MD solves at %.0e: %.4f s/traj  <dH^2>=%.4e (timed leg %.4e) iters=%.0f" %
             (args.prec, args.n_fg, args.md_tol, md_leg["s_per_traj"], md_leg["mean_dH2"], fg["mean_dH2"],
              md_leg["cg_iters_per_traj"]))
