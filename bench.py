@@ -423,9 +423,11 @@ def chain_leg(R, U_therm, act, n, ntraj, seed=0x5EED):
                 solves_per_traj=st["solves"] / ntraj, cg_iters_per_traj=st["cg_iters"] / ntraj)
 
 
-# SU(3) products per link of the rectangle force: 18 five-link staples (4 products
-# each) and U A; 198 flops per 3x3 complex product (27 complex multiply-adds)
-RECT_FORCE_FLOPS_PER_LINK = (18 * 4 + 1) * 198
+# SU(3) products per link of the rectangle force: per nu != mu three pairs of
+# five-link staples sharing their first factor (two four-link remainders of 3
+# products each, summed, then 1 product with the shared factor) and U A; 198
+# flops per 3x3 complex product (27 complex multiply-adds)
+RECT_FORCE_FLOPS_PER_LINK = (3 * 3 * 7 + 1) * 198
 FP64_PEAK_TFLOPS = 78.6
 
 
