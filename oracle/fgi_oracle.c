@@ -585,9 +585,30 @@ static void apply_g5(long nsites, cplx *v) {
         for (int k = 6; k < 12; k++) v[i * 12 + k] = -v[i * 12 + k];
 }
 
-/* Mhat psi_e = psi_e - kappa^2 D_eo D_oe psi_e on compact even vectors;
- * dagger != 0 applies Mhat^+ = g5 Mhat g5. */
-void oracle_mhat(const int L[4], double kappa, const cplx *U, const cplx *in, cplx *out, int dagger) {
+/* Clover term of the fermion matrix (not in the paper, which only states that
+ * the integrators apply to any action): per-site 12x12 Hermitian matrices
+ * A(x) = 1 + i kappa csw sum_{mu<nu} sigma_{mu nu} (x) Fhat_{mu nu}(x), index
+ * s*3 + colour, and their inverses; NULL everywhere means the Wilson
+ * operator (A = 1). */
+typedef struct {
+    double csw;
+    cplx *A, *Ainv;   /* [V][12][12] */
+} clover_t;
+
+static void site_mul12(const cplx *A, const cplx *in, cplx *out) {
+    for (int r = 0; r < 12; r++) {
+        cplx v = 0;
+        for (int k = 0; k < 12; k++) v += A[r * 12 + k] * in[k];
+        out[r] = v;
+    }
+}
+
+/* Mhat psi_e = psi_e - kappa^2 D_eo D_oe psi_e on compact even vectors, or
+ * with a clover term A_ee psi_e - kappa^2 D_eo A_oo^-1 D_oe psi_e (the Schur
+ * complement of the odd block); dagger != 0 applies Mhat^+ = g5 Mhat g5
+ * (A commutes with g5 and is Hermitian). */
+static void mhat_cl(const int L[4], double kappa, const cplx *U, const clover_t *cl, const cplx *in, cplx *out,
+                    int dagger) {
     long V = lat_volume(L), Vh = V / 2;
     cplx *f = malloc(sizeof(cplx) * 12 * V), *g = malloc(sizeof(cplx) * 12 * V);
     cplx *tmp = malloc(sizeof(cplx) * 12 * Vh);
@@ -596,11 +617,34 @@ void oracle_mhat(const int L[4], double kappa, const cplx *U, const cplx *in, cp
     even_to_full(L, tmp, f);
     oracle_dhop(L, U, f, g);   /* odd part of g = D_oe psi_e */
     zero_parity(L, g, 0);
-    oracle_dhop(L, U, g, f);   /* even part of f = D_eo D_oe psi_e */
+    if (cl) {
+        for (long i = 0; i < V; i++)
+            if (lat_parity(L, i) == 1) {
+                cplx t[12];
+                site_mul12(cl->Ainv + i * 144, g + i * 12, t);
+                memcpy(g + i * 12, t, sizeof t);
+            }
+    }
+    oracle_dhop(L, U, g, f);   /* even part of f = D_eo (A_oo^-1) D_oe psi_e */
     full_to_even(L, f, out);
-    for (long k = 0; k < Vh * 12; k++) out[k] = tmp[k] - kappa * kappa * out[k];
+    if (cl) {
+        long k = 0;
+        for (long i = 0; i < V; i++)
+            if (lat_parity(L, i) == 0) {
+                cplx t[12];
+                site_mul12(cl->A + i * 144, tmp + k * 12, t);
+                for (int r = 0; r < 12; r++) out[k * 12 + r] = t[r] - kappa * kappa * out[k * 12 + r];
+                k++;
+            }
+    } else {
+        for (long k = 0; k < Vh * 12; k++) out[k] = tmp[k] - kappa * kappa * out[k];
+    }
     if (dagger) apply_g5(Vh, out);
     free(f); free(g); free(tmp);
+}
+
+void oracle_mhat(const int L[4], double kappa, const cplx *U, const cplx *in, cplx *out, int dagger) {
+    mhat_cl(L, kappa, U, NULL, in, out, dagger);
 }
 
 static double vdot_re(long n, const cplx *a, const cplx *b) {
@@ -610,10 +654,10 @@ static double vdot_re(long n, const cplx *a, const cplx *b) {
 }
 
 /* A = Mhat^+ Mhat */
-static void normal_op(const int L[4], double kappa, const cplx *U, const cplx *in, cplx *out,
+static void normal_op(const int L[4], double kappa, const cplx *U, const clover_t *cl, const cplx *in, cplx *out,
                       cplx *tmp) {
-    oracle_mhat(L, kappa, U, in, tmp, 0);
-    oracle_mhat(L, kappa, U, tmp, out, 1);
+    mhat_cl(L, kappa, U, cl, in, tmp, 0);
+    mhat_cl(L, kappa, U, cl, tmp, out, 1);
 }
 
 /* Conjugate gradient on A = Mhat^+ Mhat from a zero start, or (start != 0)
@@ -622,8 +666,8 @@ static void normal_op(const int L[4], double kappa, const cplx *U, const cplx *i
  * tol |phi| (when the recursive residual first passes the target the true
  * residual is formed; if it has not passed, CG restarts from it).  Returns
  * the iteration count, or -1 on maxiter. */
-int oracle_cg_from(const int L[4], double kappa, const cplx *U, const cplx *phi, cplx *x, double tol,
-                   int maxiter, double *rel_resid, int start) {
+static int cg_cl(const int L[4], double kappa, const cplx *U, const clover_t *cl, const cplx *phi, cplx *x,
+                 double tol, int maxiter, double *rel_resid, int start) {
     long n = (lat_volume(L) / 2) * 12;
     cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n);
     cplx *Ap = malloc(sizeof(cplx) * n), *tmp = malloc(sizeof(cplx) * n);
@@ -632,7 +676,7 @@ int oracle_cg_from(const int L[4], double kappa, const cplx *U, const cplx *phi,
         memset(x, 0, sizeof(cplx) * n);
         memcpy(r, phi, sizeof(cplx) * n);
     } else {
-        normal_op(L, kappa, U, x, Ap, tmp);
+        normal_op(L, kappa, U, cl, x, Ap, tmp);
         for (long k = 0; k < n; k++) r[k] = phi[k] - Ap[k];
     }
     memcpy(p, r, sizeof(cplx) * n);
@@ -640,13 +684,13 @@ int oracle_cg_from(const int L[4], double kappa, const cplx *U, const cplx *phi,
     int it = 0, status = -1;
     if (bb == 0.0 || rr <= target) { status = 0; goto done; }
     while (it < maxiter) {
-        normal_op(L, kappa, U, p, Ap, tmp);
+        normal_op(L, kappa, U, cl, p, Ap, tmp);
         double alpha = rr / vdot_re(n, p, Ap);
         for (long k = 0; k < n; k++) { x[k] += alpha * p[k]; r[k] -= alpha * Ap[k]; }
         double rr_new = vdot_re(n, r, r);
         it++;
         if (rr_new <= target) {
-            normal_op(L, kappa, U, x, Ap, tmp);
+            normal_op(L, kappa, U, cl, x, Ap, tmp);
             for (long k = 0; k < n; k++) r[k] = phi[k] - Ap[k];
             rr_new = vdot_re(n, r, r);
             if (rr_new <= target) { status = it; break; }
@@ -660,12 +704,17 @@ int oracle_cg_from(const int L[4], double kappa, const cplx *U, const cplx *phi,
     }
 done:
     if (rel_resid) {
-        normal_op(L, kappa, U, x, Ap, tmp);
+        normal_op(L, kappa, U, cl, x, Ap, tmp);
         for (long k = 0; k < n; k++) r[k] = phi[k] - Ap[k];
         *rel_resid = bb > 0 ? sqrt(vdot_re(n, r, r) / bb) : 0.0;
     }
     free(r); free(p); free(Ap); free(tmp);
     return status;
+}
+
+int oracle_cg_from(const int L[4], double kappa, const cplx *U, const cplx *phi, cplx *x, double tol,
+                   int maxiter, double *rel_resid, int start) {
+    return cg_cl(L, kappa, U, NULL, phi, x, tol, maxiter, rel_resid, start);
 }
 
 int oracle_cg(const int L[4], double kappa, const cplx *U, const cplx *phi, cplx *x, double tol,
@@ -774,6 +823,327 @@ void oracle_fermion_force_add(const int L[4], double kappa, const cplx *U, const
     oracle_mhat(L, kappa, U, Xe, ye, 0);
     force_xy_add(L, U, Xe, ye, scale * kappa * kappa, F);
     free(ye);
+}
+
+/* ------------------------------------------------------------------ */
+/* clover (Sheikholeslami-Wohlert) term                                */
+/* ------------------------------------------------------------------ */
+/* The paper claims its integrators for any action; the clover term is the
+ * standard O(a)-improvement of the Wilson operator, written here in the
+ * hopping normalisation of M = 1 - kappa D:
+ *     M = A - kappa D,  A(x) = 1 + i kappa csw sum_{mu<nu} sigma_{mu nu} Fhat_{mu nu}(x),
+ *     sigma_{mu nu} = (i/2)[g_mu, g_nu],  Fhat_{mu nu} = (Q_{mu nu} - Q_{mu nu}^+) / 8,
+ * Q_{mu nu}(x) the sum of the four plaquette leaves at x in the (mu, nu) plane.
+ * A(x) is Hermitian and commutes with g5.  Even-odd: det M = det A_oo det Mhat
+ * with Mhat = A_ee - kappa^2 D_eo A_oo^-1 D_oe, so the two-flavour action is
+ *     S = phi^+ (Mhat^+ Mhat)^-1 phi - 2 sum_{x odd} log det A(x). */
+
+static void sigma_mn(int mu, int nu, cplx s[4][4]) {
+    for (int a = 0; a < 4; a++)
+        for (int b = 0; b < 4; b++) {
+            cplx v = 0;
+            for (int k = 0; k < 4; k++) v += GAM[mu][a][k] * GAM[nu][k][b] - GAM[nu][a][k] * GAM[mu][k][b];
+            s[a][b] = 0.5 * I * v;
+        }
+}
+
+/* for tests: sigma_{mu nu} (mu, nu = 0..3) as a 4x4 row-major complex matrix */
+void oracle_sigma(int mu, int nu, cplx *out) {
+    cplx s[4][4];
+    gamma_init();
+    sigma_mn(mu, nu, s);
+    memcpy(out, s, sizeof s);
+}
+
+/* the four leaves in the (mu, nu) plane at x: the same counter-clockwise
+ * plaquette loop (+mu before +nu) started at each of its corners, as steps
+ * +-1 along mu and +-2 along nu */
+static const int LEAF[4][4] = {{1, 2, -1, -2}, {2, -1, -2, 1}, {-1, -2, 1, 2}, {-2, 1, 2, -1}};
+
+static void leaf_steps(int mu, int nu, int l, int st[4]) {
+    for (int k = 0; k < 4; k++) {
+        int a = LEAF[l][k], d = (a == 1 || a == -1) ? mu : nu;
+        st[k] = a > 0 ? d + 1 : -(d + 1);
+    }
+}
+
+static mat3 clover_Q(const int L[4], const cplx *U, long i, int mu, int nu) {
+    mat3 Q = m_zero();
+    for (int l = 0; l < 4; l++) {
+        int st[4];
+        leaf_steps(mu, nu, l, st);
+        Q = m_add(Q, path_product(L, U, i, st, 4, NULL, NULL));
+    }
+    return Q;
+}
+
+/* In-place inverse of a 12x12 complex matrix by Gauss-Jordan elimination with
+ * partial pivoting; returns log det (complex: the sum of the logs of the
+ * pivots, i pi per row exchange). */
+static cplx inv12(const cplx *A, cplx *Ainv) {
+    cplx a[12][24];
+    cplx ld = 0;
+    for (int r = 0; r < 12; r++)
+        for (int c = 0; c < 24; c++) a[r][c] = c < 12 ? A[r * 12 + c] : (c - 12 == r ? 1.0 : 0.0);
+    for (int c = 0; c < 12; c++) {
+        int piv = c;
+        for (int r = c + 1; r < 12; r++)
+            if (cabs(a[r][c]) > cabs(a[piv][c])) piv = r;
+        if (piv != c) {
+            for (int k = 0; k < 24; k++) { cplx t = a[c][k]; a[c][k] = a[piv][k]; a[piv][k] = t; }
+            ld += I * M_PI;
+        }
+        cplx d = a[c][c];
+        ld += clog(d);
+        for (int k = 0; k < 24; k++) a[c][k] /= d;
+        for (int r = 0; r < 12; r++) {
+            if (r == c) continue;
+            cplx f = a[r][c];
+            if (f == 0) continue;
+            for (int k = 0; k < 24; k++) a[r][k] -= f * a[c][k];
+        }
+    }
+    for (int r = 0; r < 12; r++)
+        for (int c = 0; c < 12; c++) Ainv[r * 12 + c] = a[r][c + 12];
+    return ld;
+}
+
+/* A(x), A(x)^-1 and log det A(x) (real part; A is Hermitian) for every site */
+static void clover_build(const int L[4], double kappa, double csw, const cplx *U, clover_t *cl, double *logdet) {
+    long V = lat_volume(L);
+    gamma_init();
+    cplx sg[6][4][4];
+    int pm[6], pn[6], np = 0;
+    for (int mu = 0; mu < 4; mu++)
+        for (int nu = mu + 1; nu < 4; nu++) { sigma_mn(mu, nu, sg[np]); pm[np] = mu; pn[np] = nu; np++; }
+    cl->csw = csw;
+    cl->A = malloc(sizeof(cplx) * 144 * V);
+    cl->Ainv = malloc(sizeof(cplx) * 144 * V);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < V; i++) {
+        cplx *A = cl->A + i * 144;
+        for (int r = 0; r < 144; r++) A[r] = (r % 13 == 0) ? 1.0 : 0.0;
+        for (int q = 0; q < 6; q++) {
+            mat3 Q = clover_Q(L, U, i, pm[q], pn[q]);
+            mat3 Fh = m_scale(m_add(Q, m_scale(m_dag(Q), -1.0)), 0.125);
+            for (int s = 0; s < 4; s++)
+                for (int t = 0; t < 4; t++)
+                    for (int a = 0; a < 3; a++)
+                        for (int b = 0; b < 3; b++)
+                            A[(s * 3 + a) * 12 + t * 3 + b] += I * kappa * csw * sg[q][s][t] * Fh.m[a][b];
+        }
+        cplx ld = inv12(A, cl->Ainv + i * 144);
+        if (logdet) logdet[i] = creal(ld);
+    }
+}
+
+static void clover_free(clover_t *cl) {
+    if (!cl) return;
+    free(cl->A); free(cl->Ainv);
+    cl->A = cl->Ainv = NULL;
+}
+
+/* for tests: A(x) and A(x)^-1 ([V][12][12], either may be NULL) and the
+ * per-site log det A(x); returns -2 sum_{x odd} log det A(x) */
+double oracle_clover(const int L[4], double kappa, double csw, const cplx *U, cplx *A, cplx *Ainv, double *logdet) {
+    long V = lat_volume(L);
+    clover_t cl;
+    double *ld = malloc(sizeof(double) * V), s = 0;
+    clover_build(L, kappa, csw, U, &cl, ld);
+    if (A) memcpy(A, cl.A, sizeof(cplx) * 144 * V);
+    if (Ainv) memcpy(Ainv, cl.Ainv, sizeof(cplx) * 144 * V);
+    if (logdet) memcpy(logdet, ld, sizeof(double) * V);
+    for (long i = 0; i < V; i++)
+        if (lat_parity(L, i) == 1) s += -2.0 * ld[i];
+    clover_free(&cl);
+    free(ld);
+    return s;
+}
+
+/* full-lattice M = A - kappa D with the clover term (for tests) */
+void oracle_clover_wilson(const int L[4], double kappa, double csw, const cplx *U, const cplx *in, cplx *out) {
+    long V = lat_volume(L);
+    clover_t cl;
+    clover_build(L, kappa, csw, U, &cl, NULL);
+    oracle_dhop(L, U, in, out);
+    for (long i = 0; i < V; i++) {
+        cplx t[12];
+        site_mul12(cl.A + i * 144, in + i * 12, t);
+        for (int r = 0; r < 12; r++) out[i * 12 + r] = t[r] - kappa * out[i * 12 + r];
+    }
+    clover_free(&cl);
+}
+
+void oracle_clover_mhat(const int L[4], double kappa, double csw, const cplx *U, const cplx *in, cplx *out,
+                        int dagger) {
+    clover_t cl;
+    clover_build(L, kappa, csw, U, &cl, NULL);
+    mhat_cl(L, kappa, U, &cl, in, out, dagger);
+    clover_free(&cl);
+}
+
+/* S_F = Re phi^+ X with X = (Mhat^+ Mhat)^-1 phi for the clover Mhat */
+double oracle_clover_pf_action(const int L[4], double kappa, double csw, const cplx *U, const cplx *phi,
+                               double tol, int maxiter, int *iters) {
+    long Vh = lat_volume(L) / 2;
+    clover_t cl;
+    clover_build(L, kappa, csw, U, &cl, NULL);
+    cplx *X = malloc(sizeof(cplx) * 12 * Vh);
+    double *h = malloc(sizeof(double) * Vh), s = 0;
+    int it = cg_cl(L, kappa, U, &cl, phi, X, tol, maxiter, NULL, 0);
+    if (iters) *iters = it;
+    pf_density(Vh, phi, X, h);
+    for (long k = 0; k < Vh; k++) s += h[k];
+    free(X); free(h);
+    clover_free(&cl);
+    return s;
+}
+
+/* Force of sum_x sum_{mu<nu} Re Tr[Q_{mu nu}(x) Kt_{mu nu}(x)] for given
+ * per-site, per-plane colour matrices Kt ([V][6], planes in the order
+ * (0,1),(0,2),(0,3),(1,2),(1,3),(2,3)): every link of every leaf is
+ * differentiated where it stands in the loop.  A forward factor U at
+ * position k of the loop f_1 ... f_4 started at x gives
+ * e_a = Re Tr[T^a f_k ... f_4 Kt f_1 ... f_(k-1)]; a backward factor U^+
+ * (d(U^+) = -U^+ T^a) gives -Re Tr[T^a f_(k+1) ... f_4 Kt f_1 ... f_k].  With
+ * Re Tr[T^a W] = -[TA W]_a / 2, F_a = -e_a adds coef [TA W]_a / 2 (forward)
+ * or -coef [TA W]_a / 2 (backward). */
+static void leaf_force_add(const int L[4], const cplx *U, const mat3 *Kt, double coef, double *F) {
+    long V = lat_volume(L);
+    for (long i = 0; i < V; i++) {
+        int q = 0;
+        for (int mu = 0; mu < 4; mu++)
+            for (int nu = mu + 1; nu < 4; nu++, q++) {
+                mat3 K = Kt[i * 6 + q];
+                for (int l = 0; l < 4; l++) {
+                    int st[4];
+                    leaf_steps(mu, nu, l, st);
+                    mat3 f[4];
+                    long lk[4];
+                    int dk[4];
+                    long y = i;
+                    for (int k = 0; k < 4; k++) {
+                        int d = abs(st[k]) - 1;
+                        if (st[k] > 0) {
+                            f[k] = link_get(U, V, d, y);
+                            lk[k] = y;
+                            y = lat_step(L, y, d, +1);
+                        } else {
+                            y = lat_step(L, y, d, -1);
+                            f[k] = m_dag(link_get(U, V, d, y));
+                            lk[k] = y;
+                        }
+                        dk[k] = d;
+                    }
+                    for (int k = 0; k < 4; k++) {
+                        int fwd = st[k] > 0;
+                        int from = fwd ? k : k + 1;   /* W = f_from ... f_4 Kt f_1 ... f_(from-1) */
+                        mat3 W = m_unit();
+                        for (int j = from; j < 4; j++) W = m_mul(W, f[j]);
+                        W = m_mul(W, K);
+                        for (int j = 0; j < from; j++) W = m_mul(W, f[j]);
+                        double x[8];
+                        alg_components(traceless_antiherm(W), x);
+                        double sgn = fwd ? 0.5 : -0.5;
+                        for (int a = 0; a < 8; a++) F[((long)dk[k] * V + lk[k]) * 8 + a] += coef * sgn * x[a];
+                    }
+                }
+            }
+    }
+}
+
+/* Kt += (K - K^+) / 8 for K = c * i * Z, where Z_{ba} = sum_{s,t} sigma_{st}
+ * Bm[(t,b),(s,a)] for a 12x12 matrix Bm given by its entries */
+static void kt_add(const cplx sg[4][4], const cplx *Bm, cplx c, mat3 *Kt) {
+    mat3 Z = m_zero();
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            cplx v = 0;
+            for (int s = 0; s < 4; s++)
+                for (int t = 0; t < 4; t++) v += sg[s][t] * Bm[(t * 3 + b) * 12 + s * 3 + a];
+            Z.m[b][a] = v;
+        }
+    mat3 K = m_scale(Z, c * I);
+    *Kt = m_add(*Kt, m_scale(m_add(K, m_scale(m_dag(K), -1.0)), 0.125));
+}
+
+/* Forces of the clover action given the solution X_e = (Mhat^+ Mhat)^-1 phi
+ * (pf_scale: S_F; det_scale: the -2 log det A_oo term), ADDED to F.
+ * With Y_e = Mhat X_e, X_o = A_oo^-1 D_oe X_e, Y_o = A_oo^-1 D_eo^+ Y_e:
+ *   e_a S_F = -2 Re[Y^+ (e_a Mhat) X]
+ *           = 2 kappa^2 Re[Y^+ (e_a D) X]                     (hopping, full X, Y)
+ *             - 2 sum_x w_x Re[Y(x)^+ (e_a A(x)) X(x)]        (w = 1 even, kappa^2 odd),
+ *   e_a S_det = -2 sum_{x odd} Tr[A(x)^-1 e_a A(x)],
+ * and with e_a A = i kappa csw sum sigma (x) e_a Fhat, each clover part is
+ * Re Tr[e_a Fhat K] = Re Tr[e_a Q (K - K^+)/8] for a colour matrix K per site
+ * and plane (kt_add), whose leaf derivatives leaf_force_add takes. */
+static void clover_force_add(const int L[4], double kappa, const cplx *U, const clover_t *cl, const cplx *Xe,
+                             double pf_scale, double det_scale, double *F) {
+    long V = lat_volume(L), Vh = V / 2;
+    gamma_init();
+    cplx sg[6][4][4];
+    int np = 0;
+    for (int mu = 0; mu < 4; mu++)
+        for (int nu = mu + 1; nu < 4; nu++) sigma_mn(mu, nu, sg[np++]);
+    mat3 *Kt = malloc(sizeof(mat3) * 6 * V);
+    for (long k = 0; k < 6 * V; k++) Kt[k] = m_zero();
+    double kc = kappa * cl->csw;
+    if (pf_scale != 0.0 && Xe) {
+        cplx *ye = malloc(sizeof(cplx) * 12 * Vh);
+        cplx *X = malloc(sizeof(cplx) * 12 * V), *Y = malloc(sizeof(cplx) * 12 * V);
+        mhat_cl(L, kappa, U, cl, Xe, ye, 0);
+        full_xy(L, U, Xe, ye, X, Y);
+        for (long i = 0; i < V; i++)
+            if (lat_parity(L, i) == 1) {
+                cplx t[12];
+                site_mul12(cl->Ainv + i * 144, X + i * 12, t);
+                memcpy(X + i * 12, t, sizeof t);
+                site_mul12(cl->Ainv + i * 144, Y + i * 12, t);
+                memcpy(Y + i * 12, t, sizeof t);
+            }
+        bilinear_add(L, U, X, Y, NULL, pf_scale * kappa * kappa, F);
+        /* e_a S_F clover part: -2 w Re[Y^+ (i kc sigma (x) e_a Fhat) X]
+         * = Re Tr[e_a Fhat (-2 w kc i Z)], Z_{ba} = sum sigma_{st} X_{tb} Y*_{sa} */
+        for (long i = 0; i < V; i++) {
+            double w = lat_parity(L, i) == 0 ? 1.0 : kappa * kappa;
+            cplx Bm[144];
+            for (int r = 0; r < 12; r++)
+                for (int c = 0; c < 12; c++) Bm[r * 12 + c] = X[i * 12 + r] * conj(Y[i * 12 + c]);
+            for (int q = 0; q < 6; q++) kt_add(sg[q], Bm, -2.0 * w * kc * pf_scale, Kt + i * 6 + q);
+        }
+        free(ye); free(X); free(Y);
+    }
+    if (det_scale != 0.0) {
+        /* e_a S_det = -2 Tr[A^-1 (i kc sigma (x) e_a Fhat)] = Re Tr[e_a Fhat (-2 kc i Z')],
+         * Z'_{ba} = sum sigma_{st} Ainv[(t,b),(s,a)] */
+        for (long i = 0; i < V; i++)
+            if (lat_parity(L, i) == 1)
+                for (int q = 0; q < 6; q++) kt_add(sg[q], cl->Ainv + i * 144, -2.0 * kc * det_scale, Kt + i * 6 + q);
+    }
+    leaf_force_add(L, U, Kt, 1.0, F);
+    free(Kt);
+}
+
+/* for tests: the clover pseudofermion force (hopping and clover parts) for
+ * the solution X_e, scaled by pf_scale, plus the log det force scaled by
+ * det_scale, ADDED to F (Xe may be NULL when pf_scale is 0) */
+void oracle_clover_force_add(const int L[4], double kappa, double csw, const cplx *U, const cplx *Xe,
+                             double pf_scale, double det_scale, double *F) {
+    clover_t cl;
+    clover_build(L, kappa, csw, U, &cl, NULL);
+    clover_force_add(L, kappa, U, &cl, Xe, pf_scale, det_scale, F);
+    clover_free(&cl);
+}
+
+/* for tests: X_e = (Mhat^+ Mhat)^-1 phi with the clover Mhat; returns the
+ * iteration count or -1 */
+int oracle_clover_cg(const int L[4], double kappa, double csw, const cplx *U, const cplx *phi, cplx *x, double tol,
+                     int maxiter) {
+    clover_t cl;
+    clover_build(L, kappa, csw, U, &cl, NULL);
+    int it = cg_cl(L, kappa, U, &cl, phi, x, tol, maxiter, NULL, 0);
+    clover_free(&cl);
+    return it;
 }
 
 /* Link field dU_l = V_l U_l, the derivative of exp(t V_l) U_l at t = 0.  The
@@ -1228,6 +1598,7 @@ typedef struct {
     double c1;       /* rectangle coefficient of the gauge action */
     double stout_rho;
     int stout_n;     /* stout levels of the links the fermions see (0: thin links) */
+    double csw;      /* clover coefficient of the fermion matrix (0: Wilson) */
 } oracle_action;
 
 /* the links the fermion operator sees: a new smeared copy, or NULL for U itself */
@@ -1259,18 +1630,23 @@ static void total_force_from(const int L[4], const oracle_action *act, const cpl
     const cplx *Uf = Us ? Us : U;
     cplx *X = malloc(sizeof(cplx) * 12 * Vh);
     if (X0) memcpy(X, X0, sizeof(cplx) * 12 * Vh);
-    int it = oracle_cg_from(L, act->kappa, Uf, phi, X, act->cg_tol, act->cg_maxiter, NULL, X0 != NULL);
+    clover_t cl;
+    if (act->csw != 0.0) clover_build(L, act->kappa, act->csw, Uf, &cl, NULL);
+    const clover_t *clp = act->csw != 0.0 ? &cl : NULL;
+    int it = cg_cl(L, act->kappa, Uf, clp, phi, X, act->cg_tol, act->cg_maxiter, NULL, X0 != NULL);
     add_solve(st, act, it);
+    /* the force on the links the fermions see; with smearing it is carried
+     * back to the thin ones */
+    double *Ff = Us ? calloc(4 * V * 8, sizeof(double)) : F;
+    if (clp) clover_force_add(L, act->kappa, Uf, clp, X, 1.0, 1.0, Ff);
+    else oracle_fermion_force_add(L, act->kappa, Uf, X, 1.0, Ff);
     if (Us) {
-        /* the force on the smeared links, carried back to the thin ones */
-        double *Ff = calloc(4 * V * 8, sizeof(double)), *G = malloc(sizeof(double) * 4 * V * 8);
-        oracle_fermion_force_add(L, act->kappa, Us, X, 1.0, Ff);
+        double *G = malloc(sizeof(double) * 4 * V * 8);
         oracle_stout_vjp(L, act->stout_rho, act->stout_n, U, Ff, G);
         for (long k = 0; k < 4 * V * 8; k++) F[k] += G[k];
         free(Ff); free(G);
-    } else {
-        oracle_fermion_force_add(L, act->kappa, U, X, 1.0, F);
     }
+    if (clp) clover_free(&cl);
     if (Xout) memcpy(Xout, X, sizeof(cplx) * 12 * Vh);
     free(X); free(Us);
 }
@@ -1313,8 +1689,8 @@ void oracle_force_tangent(const int L[4], double beta, double kappa, int fermion
 
 void oracle_force(const int L[4], double beta, double kappa, int fermions, double cg_tol,
                   int cg_maxiter, const cplx *U, const cplx *phi, double *F, long *stats3, double c1,
-                  double stout_rho, int stout_n) {
-    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 0, c1, stout_rho, stout_n};
+                  double stout_rho, int stout_n, double csw) {
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 0, c1, stout_rho, stout_n, csw};
     oracle_stats st = {0, 0, 0};
     total_force(L, &act, U, phi, F, &st);
     if (stats3) { stats3[0] = st.solves; stats3[1] = st.cg_iters; stats3[2] = st.cg_fail; }
@@ -1347,9 +1723,9 @@ int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, d
                       int cg_maxiter, int fg_exact, int nstages, const char *kinds,
                       const double *ws, const double *xis, double tau, int nsteps, cplx *U,
                       double *P, const cplx *eta, const cplx *phi_in, double *dH, long *stats3, int fg_start,
-                      double c1, double stout_rho, int stout_n) {
-    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, fg_exact, c1, stout_rho, stout_n};
-    if (fg_exact && fermions && stout_n > 0) return -2;
+                      double c1, double stout_rho, int stout_n, double csw) {
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, fg_exact, c1, stout_rho, stout_n, csw};
+    if (fg_exact && fermions && (stout_n > 0 || csw != 0.0)) return -2;
     oracle_stats st = {0, 0, 0};
     long V = lat_volume(L), Vh = V / 2;
     double dt = tau / nsteps;
@@ -1382,18 +1758,30 @@ int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, d
         hf1 = malloc(sizeof(double) * Vh);
         cplx *Us = fermion_links(L, &act, U);
         const cplx *Uf = Us ? Us : U;
+        clover_t cl;
+        const clover_t *clp = NULL;
+        if (csw != 0.0) {
+            /* the -2 log det A_oo term, per odd site, is part of H */
+            double *ld = malloc(sizeof(double) * V);
+            clover_build(L, kappa, csw, Uf, &cl, ld);
+            clp = &cl;
+            for (long i = 0; i < V; i++)
+                if (lat_parity(L, i) == 1) h0[i] += -2.0 * ld[i];
+            free(ld);
+        }
         if (eta) {
-            oracle_pf_heatbath(L, kappa, Uf, eta, phi);
+            mhat_cl(L, kappa, Uf, clp, eta, phi, 1);
             for (long k = 0; k < Vh; k++) hf0[k] = vdot_re(12, eta + k * 12, eta + k * 12);
         } else {
             cplx *X0 = malloc(sizeof(cplx) * 12 * Vh);
             memcpy(phi, phi_in, sizeof(cplx) * 12 * Vh);
-            int it = oracle_cg(L, kappa, Uf, phi, X0, cg_tol, cg_maxiter, NULL);
+            int it = cg_cl(L, kappa, Uf, clp, phi, X0, cg_tol, cg_maxiter, NULL, 0);
             st.solves++;
             if (it < 0) { st.cg_fail++; st.cg_iters += cg_maxiter; } else st.cg_iters += it;
             pf_density(Vh, phi, X0, hf0);
             free(X0);
         }
+        if (clp) clover_free(&cl);
         free(Us);
     }
 
@@ -1429,7 +1817,19 @@ int oracle_trajectory(const int L[4], double beta, double kappa, int fermions, d
     if (fermions) {
         cplx *X = malloc(sizeof(cplx) * 12 * Vh);
         cplx *Us = fermion_links(L, &act, U);
-        int it = oracle_cg(L, kappa, Us ? Us : U, phi, X, cg_tol, cg_maxiter, NULL);
+        const cplx *Uf = Us ? Us : U;
+        clover_t cl;
+        const clover_t *clp = NULL;
+        if (csw != 0.0) {
+            double *ld = malloc(sizeof(double) * V);
+            clover_build(L, kappa, csw, Uf, &cl, ld);
+            clp = &cl;
+            for (long i = 0; i < V; i++)
+                if (lat_parity(L, i) == 1) d += -2.0 * ld[i];   /* the start's term is in h0 */
+            free(ld);
+        }
+        int it = cg_cl(L, kappa, Uf, clp, phi, X, cg_tol, cg_maxiter, NULL, 0);
+        if (clp) clover_free(&cl);
         free(Us);
         st.solves++;
         if (it < 0) { st.cg_fail++; st.cg_iters += cg_maxiter; } else st.cg_iters += it;
@@ -1774,7 +2174,7 @@ int oracle_hmc_run(const int L[4], double beta, double kappa, int fermions, doub
         double d = 0.0;
         long st3[3];
         int rc = oracle_trajectory(L, beta, kappa, fermions, cg_tol, cg_maxiter, fg_exact, nstages, kinds, ws, xis,
-                                   tau, nsteps, Ut, P, eta, NULL, &d, st3, fg_start, c1, stout_rho, stout_n);
+                                   tau, nsteps, Ut, P, eta, NULL, &d, st3, fg_start, c1, stout_rho, stout_n, 0.0);
         if (rc) status = rc;
         int a = !metropolis || oracle_metropolis_uniform(seed, t) < exp(-d);
         if (a) memcpy(U, Ut, sizeof(cplx) * 4 * V * 9);

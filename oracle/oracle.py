@@ -74,12 +74,21 @@ def _declare(L):
     L.oracle_pf_action.argtypes = [_ip, _d, _vp, _vp, _d, _i, _ip]
     L.oracle_pf_action.restype = _d
     L.oracle_fermion_force_add.argtypes = [_ip, _d, _vp, _vp, _d, _vp]
-    L.oracle_force.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _lp, _d, _d, _i]
+    L.oracle_force.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _lp, _d, _d, _i, _d]
     L.oracle_force_tangent.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _vp, _lp, _d]
     L.oracle_fermion_force_tangent_add.argtypes = [_ip, _d, _vp, _vp, _vp, _d, _i, _d, _vp]
     L.oracle_fermion_force_tangent_add.restype = _i
     L.oracle_trajectory.argtypes = [_ip, _d, _d, _i, _d, _i, _i, _i, ctypes.c_char_p, _vp, _vp,
-                                    _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i, _d, _d, _i]
+                                    _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i, _d, _d, _i, _d]
+    L.oracle_sigma.argtypes = [_i, _i, _vp]
+    L.oracle_clover.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _vp]
+    L.oracle_clover.restype = _d
+    L.oracle_clover_wilson.argtypes = [_ip, _d, _d, _vp, _vp, _vp]
+    L.oracle_clover_mhat.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _i]
+    L.oracle_clover_pf_action.argtypes = [_ip, _d, _d, _vp, _vp, _d, _i, _ip]
+    L.oracle_clover_pf_action.restype = _d
+    L.oracle_clover_force_add.argtypes = [_ip, _d, _d, _vp, _vp, _d, _d, _vp]
+    L.oracle_clover_cg.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _d, _i]
     L.oracle_trajectory.restype = _i
     L.oracle_brackets.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _d, _dp, _dp, _d, _d, _i]
     L.oracle_hasen_heatbath.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _d, _i]
@@ -256,16 +265,18 @@ def cg_from(dims, kappa, U, phi, x0, tol=1e-10, maxiter=10000):
     return X, it, rel.value
 
 
-def force(dims, beta, U, kappa=0.0, phi=None, tol=1e-14, maxiter=10000, c1=0.0, stout_rho=0.0, stout_n=0):
+def force(dims, beta, U, kappa=0.0, phi=None, tol=1e-14, maxiter=10000, c1=0.0, stout_rho=0.0, stout_n=0,
+          csw=0.0):
     """total force F = F_G (+ F_F when phi is given, on stout_n levels of
-    stout-smeared links, carried back to the thin links); returns (F, stats)"""
+    stout-smeared links, carried back to the thin links; with csw != 0 the
+    clover operator and its -2 log det A_oo term); returns (F, stats)"""
     U = _c(U, np.complex128)
     F = np.zeros((4, volume(dims), 8))
     st = (ctypes.c_long * 3)()
     ferm = phi is not None
     phi_a = _c(phi, np.complex128) if ferm else None
     lib().oracle_force(_dims(dims), beta, kappa, int(ferm), tol, maxiter, _ptr(U),
-                       _ptr(phi_a) if ferm else None, _ptr(F), st, c1, stout_rho, int(stout_n))
+                       _ptr(phi_a) if ferm else None, _ptr(F), st, c1, stout_rho, int(stout_n), csw)
     return F, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2])
 
 
@@ -295,7 +306,7 @@ def fermion_force_tangent(dims, kappa, U, X, V, tol=1e-14, maxiter=10000):
 
 
 def trajectory(dims, beta, stages, tau, nsteps, U, P, kappa=0.0, eta=None, tol=1e-14,
-               maxiter=10000, fg_exact=False, phi=None, fg_start=True, c1=0.0, stout_rho=0.0, stout_n=0):
+               maxiter=10000, fg_exact=False, phi=None, fg_start=True, c1=0.0, stout_rho=0.0, stout_n=0, csw=0.0):
     """One MD trajectory.  stages: list of (kind, w, xi) with kind in 'PQG'.
     Fermions: give eta (phi = Mhat^+ eta) or phi itself.  fg_start: the
     displaced force's solve of a G stage starts from the undisplaced solution.
@@ -315,7 +326,7 @@ def trajectory(dims, beta, stages, tau, nsteps, U, P, kappa=0.0, eta=None, tol=1
                                      tau, nsteps, _ptr(U), _ptr(P),
                                      _ptr(eta_a) if eta_a is not None else None,
                                      _ptr(phi_a) if phi_a is not None else None,
-                                     ctypes.byref(dH), st, int(bool(fg_start)), c1, stout_rho, int(stout_n))
+                                     ctypes.byref(dH), st, int(bool(fg_start)), c1, stout_rho, int(stout_n), csw)
     return U, P, dH.value, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2]), status
 
 
@@ -497,3 +508,72 @@ def table(name, alpha=0.1932):
         return [("Q", w1 / 2, 0.0), ("P", w1, 0.0), ("Q", (w1 + w0) / 2, 0.0), ("P", w0, 0.0),
                 ("Q", (w1 + w0) / 2, 0.0), ("P", w1, 0.0), ("Q", w1 / 2, 0.0)]
     raise ValueError(name)
+
+
+# ---- clover term -------------------------------------------------------
+
+
+def sigma(mu, nu):
+    """sigma_{mu nu} = (i/2)[g_mu, g_nu] (mu, nu = 0..3), 4x4"""
+    out = np.zeros((4, 4), np.complex128)
+    lib().oracle_sigma(mu, nu, _ptr(out))
+    return out
+
+
+def clover(dims, kappa, csw, U):
+    """per-site clover matrices A(x), A(x)^-1 ([V, 12, 12], index spin*3 +
+    colour), log det A(x) [V], and the action term -2 sum_{x odd} log det A(x)"""
+    U = _c(U, np.complex128)
+    V = volume(dims)
+    A = np.zeros((V, 12, 12), np.complex128)
+    Ai = np.zeros((V, 12, 12), np.complex128)
+    ld = np.zeros(V)
+    s = lib().oracle_clover(_dims(dims), kappa, csw, _ptr(U), _ptr(A), _ptr(Ai), _ptr(ld))
+    return A, Ai, ld, s
+
+
+def clover_wilson(dims, kappa, csw, U, psi):
+    """full-lattice M psi = A psi - kappa D psi"""
+    U = _c(U, np.complex128)
+    psi = _c(psi, np.complex128)
+    out = np.zeros_like(psi)
+    lib().oracle_clover_wilson(_dims(dims), kappa, csw, _ptr(U), _ptr(psi), _ptr(out))
+    return out
+
+
+def clover_mhat(dims, kappa, csw, U, psi, dagger=False):
+    """Mhat psi_e = A_ee psi_e - kappa^2 D_eo A_oo^-1 D_oe psi_e (or Mhat^+)"""
+    U = _c(U, np.complex128)
+    psi = _c(psi, np.complex128)
+    out = np.zeros_like(psi)
+    lib().oracle_clover_mhat(_dims(dims), kappa, csw, _ptr(U), _ptr(psi), _ptr(out), int(bool(dagger)))
+    return out
+
+
+def clover_pf_action(dims, kappa, csw, U, phi, tol=1e-14, maxiter=10000):
+    """S_F = phi^+ (Mhat^+ Mhat)^-1 phi with the clover Mhat; (S_F, iterations)"""
+    U = _c(U, np.complex128)
+    phi = _c(phi, np.complex128)
+    it = ctypes.c_int(0)
+    s = lib().oracle_clover_pf_action(_dims(dims), kappa, csw, _ptr(U), _ptr(phi), tol, maxiter, ctypes.byref(it))
+    return s, it.value
+
+
+def clover_cg(dims, kappa, csw, U, phi, tol=1e-14, maxiter=10000):
+    """X_e = (Mhat^+ Mhat)^-1 phi with the clover Mhat; (X_e, iterations)"""
+    U = _c(U, np.complex128)
+    phi = _c(phi, np.complex128)
+    X = np.zeros_like(phi)
+    it = lib().oracle_clover_cg(_dims(dims), kappa, csw, _ptr(U), _ptr(phi), _ptr(X), tol, maxiter)
+    return X, it
+
+
+def clover_force(dims, kappa, csw, U, Xe=None, pf_scale=1.0, det_scale=1.0):
+    """the clover pseudofermion force for the solution Xe (hopping and clover
+    parts, times pf_scale) plus the -2 log det A_oo force (times det_scale)"""
+    U = _c(U, np.complex128)
+    F = np.zeros((4, volume(dims), 8))
+    xa = _c(Xe, np.complex128) if Xe is not None else None
+    lib().oracle_clover_force_add(_dims(dims), kappa, csw, _ptr(U), _ptr(xa) if xa is not None else None,
+                                  pf_scale if xa is not None else 0.0, det_scale, _ptr(F))
+    return F
