@@ -108,6 +108,21 @@ typedef struct {
                            and action solves that enter dH keep cg_tol, so a
                            looser MD tolerance leaves the accept/reject step
                            exact.  In [0, 1), else FGI_EINVAL. */
+    double csw;         /* clover (Sheikholeslami-Wohlert) coefficient of the
+                           fermion matrix, M = A - kappa D with
+                           A(x) = 1 + i kappa csw sum_{mu<nu} sigma_{mu nu} Fhat_{mu nu}(x),
+                           sigma_{mu nu} = (i/2)[g_mu, g_nu], Fhat = (Q - Q^+)/8 of
+                           the four-leaf clover Q; even-odd Mhat = A_ee -
+                           kappa^2 D_eo A_oo^-1 D_oe and the action gains
+                           -2 sum_{x odd} log det A(x).  0 = Wilson; in [0, 10],
+                           else FGI_EINVAL.  With kappa != 0 it needs prec =
+                           FGI_FP64 and no Hasenbusch split (FGI_EINVAL); not
+                           with fg_exact or for batched chains (FGI_EINVAL).
+                           fgi_mhat, fgi_pf_heatbath, fgi_cg_solve,
+                           fgi_pf_action (S_F only), fgi_fermion_force (the S_F
+                           force only), fgi_force (with the log det force),
+                           fgi_force_terms, trajectories and fgi_hmc_run take
+                           it; fgi_dslash stays the hopping term. */
 } fgi_action;
 
 /* One stage of an integrator step (Table 1), coefficients multiply the step h:
@@ -276,6 +291,21 @@ int fgi_total_force_gradient(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* 
  * for A = Mhat^+ Mhat, given the solution X = A^-1 phi (even field). */
 int fgi_fermion_force(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* X,
                       void* F, void* stream);
+
+/* Clover term at (kappa, csw) of the links U (the definition at
+ * fgi_action.csw; the paper's conclusions leave the choice of fermion action
+ * open and this is its standard O(a)-improved form).  Each output is optional
+ * (NULL skips it):
+ *   A      [V][12][12] complex: A(x) in lexicographic site order, index
+ *          spin * 3 + colour (DeGrand-Rossi basis; zero between the spin
+ *          pairs {0,1} and {2,3});
+ *   S_det  host double: -2 sum_{x odd} log det A(x);
+ *   F_det  [4][V][8] real: the force -e_a S_det on every link.
+ * kappa csw < 1/6 keeps A(x) positive definite for any links (log det is
+ * taken of the pivots' moduli).  FGI_EINVAL for a non-finite kappa or csw
+ * outside [0, 10].  Synchronises the stream. */
+int fgi_clover_field(fgi_ctx* ctx, const fgi_geom* g, double kappa, double csw, const void* U, void* A,
+                     double* S_det, void* F_det, void* stream);
 
 /* ------------------------------------------- Wilson operator and solver */
 /* out = D_{p,1-p} in: the hopping term from the other parity to parity

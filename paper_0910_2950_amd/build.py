@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfgi.so")
-SOURCES = ["gauge.hip", "fermion.hip", "chain.hip", "stout.hip", "api.hip"]
+SOURCES = ["gauge.hip", "fermion.hip", "chain.hip", "stout.hip", "clover.hip", "api.hip"]
 ARCH = os.environ.get("FGI_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-fno-gpu-rdc",

@@ -116,6 +116,11 @@ void check_action(const fgi_action* a) {
     if (!(a->cg_tol_md >= 0.0 && a->cg_tol_md < 1.0)) throw Error(FGI_EINVAL, "cg_tol_md must be in [0, 1)");
     if (a->stout_n < 0 || a->stout_n > 8) throw Error(FGI_EINVAL, "stout_n must be in [0, 8]");
     if (!(a->stout_rho >= 0.0 && a->stout_rho <= 0.5)) throw Error(FGI_EINVAL, "stout_rho must be in [0, 0.5]");
+    if (!(a->csw >= 0.0 && a->csw <= 10.0)) throw Error(FGI_EINVAL, "csw must be in [0, 10]");
+    if (a->csw != 0.0 && a->kappa != 0.0) {
+        if (a->prec != FGI_FP64) throw Error(FGI_EINVAL, "the clover operator is FP64 only");
+        if (a->kappa_hasen != 0.0) throw Error(FGI_EINVAL, "the clover operator has no Hasenbusch split");
+    }
 }
 
 int sloppy_prec(const fgi_action* a) { return a->prec == FGI_FP64 ? P64 : (a->prec == FGI_MP32 ? P32 : P16); }
@@ -164,10 +169,20 @@ struct Fields {
 
     // md: a solve inside a force evaluation (tolerance cg_tol_md when set);
     // the heatbath and action solves keep cg_tol
+    // the clover term of the links u is built into c.cl_blk by every clover
+    // solve, so the force that follows a solve finds A_ee, A_oo^-1 of its links
+    bool clover() const { return act.csw != 0.0 && act.kappa != 0.0; }
+    d2* clover_at(const d2* u, double kappa, double* det = nullptr) {
+        d2* blk = (d2*)c.cl_blk.get(sizeof(d2) * 72 * (size_t)g.V);
+        clover_build(c, g, kappa, act.csw, u, blk, 1, det);
+        return blk;
+    }
+
     CGResult solve(const d2* u, const void* us, double kappa, const d2* rhs, d2* x, bool guess = false,
                    bool md = false) {
         const double tol = (md && act.cg_tol_md > 0.0) ? act.cg_tol_md : act.cg_tol;
-        CGResult r = cg_solve(c, op64(u, kappa), ops(u, us, kappa), sp, rhs, x, tol, act.cg_maxiter, guess);
+        CGResult r = clover() ? clover_cg(c, op64(u, kappa), clover_at(u, kappa), rhs, x, tol, act.cg_maxiter, guess)
+                              : cg_solve(c, op64(u, kappa), ops(u, us, kappa), sp, rhs, x, tol, act.cg_maxiter, guess);
         accumulate_stats(st, r);
         if (!r.converged) nonconv = true;
         return r;
@@ -222,7 +237,11 @@ struct Fields {
         const double k1 = act.kappa_hasen != 0.0 ? act.kappa_hasen : act.kappa;
         if (terms & FGI_TERM_FERMION) {
             solve(fl.u, fl.us, k1, phi[0], X, guess, true);
-            fermion_force(c, op64(fl.u, k1), X, fo, fc);
+            if (clover())   // S_F and the -2 log det A_oo term
+                clover_force(c, op64(fl.u, k1), act.csw, (const d2*)c.cl_blk.get(sizeof(d2) * 72 * (size_t)g.V), X,
+                             fo, fc, 1.0, 1.0);
+            else
+                fermion_force(c, op64(fl.u, k1), X, fo, fc);
         }
         if ((terms & FGI_TERM_HASEN) && act.kappa_hasen != 0.0) {
             // S_2 = chi^+ (Mhat^+ Mhat)^-1 chi, chi = Mhat2^+ phi2: the ordinary force
@@ -250,6 +269,7 @@ struct Fields {
         const bool hasen = act.kappa_hasen != 0.0;
         if (ferm && act.stout_n > 0)
             throw Error(FGI_EINVAL, "the exact force gradient is not available with stout smearing");
+        if (ferm && clover()) throw Error(FGI_EINVAL, "the exact force gradient is not available with the clover term");
         if (terms & FGI_TERM_GAUGE) gauge_force_tangent(c, g, act.beta, u, Vd, J, 1.0, 0, 0, act.c1);
         else zero_mom(J);
         if (!ferm) return;
@@ -311,6 +331,11 @@ struct Fields {
         int nb = pf_density_partials(c, g, phi[0], X, eta1, part);
         final_sum(c, part, nb, scal + 4);
         double e = sync_scalar(c, scal + 4, 4);
+        if (clover()) {   // -2 sum_{x odd} log det A(x) is part of H
+            double det = 0.0;
+            clover_at(u, k1, &det);
+            e += det;
+        }
         if (act.kappa_hasen != 0.0) {
             hasen_solve(u, us);
             nb = pf_density_partials(c, g, chi, X2, eta2, part);
@@ -362,7 +387,9 @@ int fgi_destroy(fgi_ctx* ctx) {
                           &c.gauge_tan, &c.tg_dmx, &c.tg_rhs, &c.tg_z, &c.tg_dxo, &c.tg_dye, &c.tg_dyo,
                           &c.force3, &c.chain_U, &c.stout_lev, &c.stout_F, &c.stout_ga, &c.stout_gb,
                           &c.stout_part, &c.stout_M, &c.stout_sloppy, &c.hs_dchi, &c.hs_xo, &c.hs_yo,
-                          &c.hs_dxo, &c.hs_dyo, &c.hs_zero, &c.hs_t1};
+                          &c.hs_dxo, &c.hs_dyo, &c.hs_zero, &c.hs_t1, &c.cl_sig, &c.cl_blk, &c.cl_fh,
+                          &c.cl_ld, &c.cl_to, &c.cl_te, &c.cl_ue, &c.cl_r, &c.cl_p, &c.cl_ap, &c.cl_t,
+                          &c.cl_ye, &c.cl_xo, &c.cl_yo};
         for (DevBuf* b : bufs) b->release();
         for (hipEvent_t e : c.ev_pool) hipEventDestroy(e);
         for (GraphEntry& e : c.graphs) hipGraphExecDestroy(e.exec);
@@ -673,7 +700,14 @@ int fgi_mhat(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void
         d2* t = (d2*)c.Xo.get(spinor_bytes(g));
         pack_even_spinor(c, g, in, vin);
         FermionOp op{&g, act->kappa, u, P64, 18};
-        mhat(c, op, P64, SpinorPtr{vin, nullptr}, SpinorPtr{t, nullptr}, SpinorPtr{vout, nullptr}, dagger ? 1 : 0);
+        if (act->csw != 0.0 && act->kappa != 0.0) {
+            d2* blk = (d2*)c.cl_blk.get(sizeof(d2) * 72 * (size_t)g.V);
+            clover_build(c, g, act->kappa, act->csw, u, blk, 1, nullptr);
+            clover_mhat(c, op, blk, vin, vout, dagger ? 1 : 0);
+        } else {
+            mhat(c, op, P64, SpinorPtr{vin, nullptr}, SpinorPtr{t, nullptr}, SpinorPtr{vout, nullptr},
+                 dagger ? 1 : 0);
+        }
         unpack_even_spinor(c, g, vout, out);
     });
 }
@@ -847,8 +881,44 @@ int fgi_fermion_force(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, c
         pack_even_spinor(c, g, X, x);
         double* fm = (double*)c.force.get(mom_bytes(g));
         zero_doubles(c, fm, mom_bytes(g) / sizeof(double));
-        fermion_force(c, FermionOp{&g, act->kappa, u, P64, 18}, x, fm, 1.0);
+        const FermionOp op{&g, act->kappa, u, P64, 18};
+        if (act->csw != 0.0 && act->kappa != 0.0) {
+            d2* blk = (d2*)c.cl_blk.get(sizeof(d2) * 72 * (size_t)g.V);
+            clover_build(c, g, act->kappa, act->csw, u, blk, 1, nullptr);
+            clover_force(c, op, act->csw, blk, x, fm, 1.0, 1.0, 0.0);
+        } else {
+            fermion_force(c, op, x, fm, 1.0);
+        }
         unpack_mom(c, g, fm, (double*)F);
+    });
+}
+
+int fgi_clover_field(fgi_ctx* ctx, const fgi_geom* gg, double kappa, double csw, const void* U, void* A,
+                     double* S_det, void* F_det, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        if (!std::isfinite(kappa) || !(csw >= 0.0 && csw <= 10.0)) throw Error(FGI_EINVAL, "bad kappa or csw");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        if (A) need(A, "A", 16);
+        if (F_det) need(F_det, "F_det", 8);
+        StreamScope ss(c, stream);
+        d2* u = (d2*)c.gauge.get(gauge_bytes(g));
+        pack_gauge(c, g, U, u);
+        d2* blk = (d2*)c.cl_blk.get(sizeof(d2) * 72 * (size_t)g.V);
+        if (A) {
+            clover_build(c, g, kappa, csw, u, blk, 0, nullptr);
+            clover_unpack(c, g, blk, A);
+        }
+        if (S_det || F_det) clover_build(c, g, kappa, csw, u, blk, 1, S_det);
+        if (F_det) {
+            double* fm = (double*)c.force.get(mom_bytes(g));
+            zero_doubles(c, fm, mom_bytes(g) / sizeof(double));
+            clover_force(c, FermionOp{&g, kappa, u, P64, 18}, csw, blk, nullptr, fm, 1.0, 0.0, 1.0);
+            unpack_mom(c, g, fm, (double*)F_det);
+        }
+        FGI_HIP(hipStreamSynchronize(c.stream));
     });
 }
 
@@ -1132,6 +1202,8 @@ void check_trajectory_args(const fgi_action* act, const fgi_integrator* integ, i
     check_integrator(integ);
     if (act->fg_exact && act->kappa != 0 && act->stout_n > 0)
         throw Error(FGI_EINVAL, "the exact force gradient is not available with stout smearing");
+    if (act->fg_exact && act->kappa != 0 && act->csw != 0)
+        throw Error(FGI_EINVAL, "the exact force gradient is not available with the clover term");
     if (nsteps < 1) throw Error(FGI_EINVAL, "nsteps must be >= 1");
     if (!std::isfinite(tau)) throw Error(FGI_EINVAL, "tau must be finite");
 }
@@ -1177,6 +1249,11 @@ double trajectory_packed(Fields& f, const fgi_integrator& integ, double tau, int
         const double k1 = hasen ? f.act.kappa_hasen : f.act.kappa;
         if (phi_given) {
             sf0 = f.pf_energy(f.U, f.Us, nullptr, nullptr, part, scal);
+        } else if (f.clover()) {
+            // phi = Mhat^+ eta; the start's -2 log det A_oo enters H
+            const d2* fu = f.flinks(f.U, f.Us).u;
+            const d2* blk = f.clover_at(fu, k1, &sf0);
+            clover_mhat(c, f.op64(fu, k1), blk, eta, f.phi[0], 1);
         } else {
             pf_heatbath(c, f.op64(f.flinks(f.U, f.Us).u, k1), eta, f.phi[0]);
             if (hasen) f.hasen_heatbath(f.U, f.Us, eta_2);
@@ -1570,6 +1647,7 @@ extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain
         check_integrator(integ);
         if (nsteps < 1 || !std::isfinite(tau)) throw Error(FGI_EINVAL, "bad tau / nsteps");
         if (act->kappa_hasen != 0.0) throw Error(FGI_EINVAL, "batched chains take one pseudofermion");
+        if (act->csw != 0.0) throw Error(FGI_EINVAL, "batched chains have no clover term");
         if (act->fg_exact) throw Error(FGI_EINVAL, "batched chains use the displacement force-gradient form");
         const bool ferm = chains[0].kappa != 0.0;
         std::vector<ChainDesc> cd;

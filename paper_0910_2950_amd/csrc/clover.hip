@@ -1,0 +1,582 @@
+// Clover (Sheikholeslami-Wohlert) term of the Wilson operator, FP64.
+//
+// The paper's conclusions state that its integrators apply to the usual
+// improved actions; the clover term is the standard O(a) improvement of the
+// fermion matrix.  In the hopping normalisation of M = 1 - kappa D:
+//     M = A - kappa D,  A(x) = 1 + i kappa csw sum_{mu<nu} sigma_{mu nu} Fhat_{mu nu}(x),
+//     sigma_{mu nu} = (i/2)[g_mu, g_nu],  Fhat = (Q - Q^+) / 8,
+// Q_{mu nu}(x) the sum of the four plaquette leaves at x.  In the chiral
+// (DeGrand-Rossi) basis A(x) is two Hermitian 6x6 blocks, one per pair of
+// spin components {0,1} and {2,3}.  Even-odd: det M = det A_oo det Mhat with
+//     Mhat = A_ee - kappa^2 D_eo A_oo^-1 D_oe,   Mhat^+ = g5 Mhat g5,
+// so the two-flavour action is phi^+ (Mhat^+ Mhat)^-1 phi - 2 sum_{x odd} log det A(x).
+//
+// Storage: blk[(b * 36 + r * 6 + c) * V + p * Vh + s], block b, row r, column
+// c (index spin' * 3 + colour within the block), site s of parity p; even
+// sites hold A, odd sites A^-1 (or A, for the read-out entry point).
+#include <complex>
+
+#include "fgi_coord.h"
+#include "fgi_internal.h"
+
+namespace fgi {
+namespace {
+
+constexpr int CBS = 256;
+
+// sigma_{mu nu} restricted to its two diagonal 2x2 spin blocks, planes in
+// the order (0,1), (0,2), (0,3), (1,2), (1,3), (2,3)
+struct SigmaBlk {
+    double re[6][2][2][2];
+    double im[6][2][2][2];
+};
+
+SigmaBlk make_sigma() {
+    // DeGrand-Rossi g_1..g_4 (x, y, z, t), the basis of the hopping term
+    typedef std::complex<double> C;
+    const C i(0.0, 1.0);
+    C G[4][4][4] = {};
+    G[0][0][3] = i;   G[0][1][2] = i;   G[0][2][1] = -i;  G[0][3][0] = -i;
+    G[1][0][3] = -1;  G[1][1][2] = 1;   G[1][2][1] = 1;   G[1][3][0] = -1;
+    G[2][0][2] = i;   G[2][1][3] = -i;  G[2][2][0] = -i;  G[2][3][1] = i;
+    G[3][0][2] = 1;   G[3][1][3] = 1;   G[3][2][0] = 1;   G[3][3][1] = 1;
+    SigmaBlk sb{};
+    int q = 0;
+    for (int mu = 0; mu < 4; mu++)
+        for (int nu = mu + 1; nu < 4; nu++, q++) {
+            C s[4][4];
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) {
+                    C v = 0;
+                    for (int k = 0; k < 4; k++) v += G[mu][a][k] * G[nu][k][b] - G[nu][a][k] * G[mu][k][b];
+                    s[a][b] = 0.5 * i * v;
+                }
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) {
+                    if ((a < 2) != (b < 2)) {
+                        if (std::abs(s[a][b]) != 0.0) throw Error(-1, "sigma is not block diagonal");
+                        continue;
+                    }
+                    const int bl = a / 2;
+                    sb.re[q][bl][a % 2][b % 2] = s[a][b].real();
+                    sb.im[q][bl][a % 2][b % 2] = s[a][b].imag();
+                }
+        }
+    return sb;
+}
+
+// the blocks in device memory, read with run-time plane indices:
+// sig[k] = Re, sig[48 + k] = Im of block entry k = ((q * 2 + b) * 2 + s) * 2 + t
+const double* sigma_blocks(Ctx& c) {
+    static const SigmaBlk sb = make_sigma();
+    const bool fresh = c.cl_sig.bytes == 0;
+    double* d = (double*)c.cl_sig.get(sizeof(SigmaBlk));
+    if (fresh) FGI_HIP(hipMemcpyAsync(d, &sb, sizeof(SigmaBlk), hipMemcpyHostToDevice, c.stream));
+    return d;
+}
+
+__device__ __forceinline__ cx<double> sig_at(const double* __restrict__ sig, int q, int b, int s, int t) {
+    const int k = ((q * 2 + b) * 2 + s) * 2 + t;
+    return {sig[k], sig[48 + k]};
+}
+
+__device__ __forceinline__ int plane_index(int mu, int nu) {
+    // (0,1)=0 (0,2)=1 (0,3)=2 (1,2)=3 (1,3)=4 (2,3)=5 for mu < nu
+    return mu == 0 ? nu - 1 : (mu == 1 ? nu + 1 : 5);
+}
+
+__device__ __forceinline__ int site_of(const Geom& g, const Coord& y) { return coord_parity(y) * g.Vh + cb_index(g, y); }
+
+// Fhat_{mu nu}(x) for the six planes, one thread per site (both parities)
+__global__ void __launch_bounds__(CBS) k_clover_fhat(Geom g, const d2* __restrict__ U, d2* __restrict__ fh) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.V) return;
+    const int p = t / g.Vh, s = t % g.Vh;
+    const Coord x = cb_coords(g, p, s);
+#pragma unroll 1
+    for (int mu = 0; mu < 4; mu++)
+#pragma unroll 1
+        for (int nu = mu + 1; nu < 4; nu++) {
+            Coord xm = x, xn = x, xbm = x, xbn = x;
+            coord_step(g, xm, mu, 1);
+            coord_step(g, xn, nu, 1);
+            coord_step(g, xbm, mu, 0);
+            coord_step(g, xbn, nu, 0);
+            Coord xbmn = xbm, xbmbn = xbm, xmbn = xm;
+            coord_step(g, xbmn, nu, 1);
+            coord_step(g, xbmbn, nu, 0);
+            coord_step(g, xmbn, nu, 0);
+            const M3<double> umx = link_at(g, U, mu, x), unx = link_at(g, U, nu, x);
+            // leaf from x: +mu +nu -mu -nu
+            M3<double> Q = m3_mul_nd(m3_mul_nd(m3_mul(umx, link_at(g, U, nu, xm)), link_at(g, U, mu, xn)), unx);
+            // +nu -mu -nu +mu
+            m3_acc(Q, m3_mul(m3_mul_nd(m3_mul_nd(unx, link_at(g, U, mu, xbmn)), link_at(g, U, nu, xbm)),
+                             link_at(g, U, mu, xbm)));
+            // -mu -nu +mu +nu
+            m3_acc(Q, m3_mul_dn(link_at(g, U, mu, xbm),
+                                m3_mul(m3_mul_dn(link_at(g, U, nu, xbmbn), link_at(g, U, mu, xbmbn)),
+                                       link_at(g, U, nu, xbn))));
+            // -nu +mu +nu -mu
+            m3_acc(Q, m3_mul_nd(m3_mul(m3_mul_dn(link_at(g, U, nu, xbn), link_at(g, U, mu, xbn)),
+                                       link_at(g, U, nu, xmbn)),
+                                umx));
+            const int q = plane_index(mu, nu);
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+#pragma unroll
+                for (int b = 0; b < 3; b++)
+                    fh[(size_t)(q * 9 + a * 3 + b) * g.V + t] =
+                        d2{0.125 * (Q.e[a][b].re - Q.e[b][a].re), 0.125 * (Q.e[a][b].im + Q.e[b][a].im)};
+        }
+}
+
+// One 6x6 block of A(x) per thread: b = thread / V, site = thread % V.
+// A = 1 + i kc sum_q sigma_q^b (x) Fhat_q.  log det from Gauss-Jordan
+// elimination without pivoting (A is Hermitian and, for kappa csw < 1/6,
+// positive definite: the pivots are the positive diagonal of its LDL^+
+// factorisation).  Writes A, or A^-1 at odd sites when invert_odd; ld[b V +
+// site] = log det of the block at odd sites, 0 at even ones.
+__global__ void __launch_bounds__(CBS) k_clover_blocks(Geom g, const double* __restrict__ sig, double kc, const d2* __restrict__ fh,
+                                                       d2* __restrict__ blk, double* __restrict__ ld, int invert_odd) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= 2 * g.V) return;
+    const int b = id / g.V, t = id % g.V;
+    const bool odd = t >= g.Vh;
+    cx<double> a[6][6];
+#pragma unroll
+    for (int r = 0; r < 6; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) a[r][c] = {r == c ? 1.0 : 0.0, 0.0};
+#pragma unroll 1
+    for (int q = 0; q < 6; q++) {
+        cx<double> f[3][3];
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            const d2 v = fh[(size_t)(q * 9 + e) * g.V + t];
+            f[e / 3][e % 3] = {v.x, v.y};
+        }
+#pragma unroll
+        for (int s = 0; s < 2; s++)
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                // i kc sigma_su
+                const cx<double> sg = sig_at(sig, q, b, s, u);
+                const cx<double> w = {-kc * sg.im, kc * sg.re};
+#pragma unroll
+                for (int i = 0; i < 3; i++)
+#pragma unroll
+                    for (int j = 0; j < 3; j++) a[s * 3 + i][u * 3 + j] = a[s * 3 + i][u * 3 + j] + w * f[i][j];
+            }
+    }
+    double logdet = 0.0;
+    if (odd) {
+        cx<double> m[6][6];
+#pragma unroll
+        for (int r = 0; r < 6; r++)
+#pragma unroll
+            for (int c = 0; c < 6; c++) m[r][c] = a[r][c];
+        // in-place Gauss-Jordan inversion
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const cx<double> piv = m[k][k];
+            logdet += 0.5 * log(piv.re * piv.re + piv.im * piv.im);
+            const double den = piv.re * piv.re + piv.im * piv.im;
+            const cx<double> inv = {piv.re / den, -piv.im / den};
+            m[k][k] = {1.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < 6; j++) m[k][j] = m[k][j] * inv;
+#pragma unroll
+            for (int i = 0; i < 6; i++) {
+                if (i == k) continue;
+                const cx<double> fct = m[i][k];
+                m[i][k] = {0.0, 0.0};
+#pragma unroll
+                for (int j = 0; j < 6; j++) m[i][j] = m[i][j] - fct * m[k][j];
+            }
+        }
+        if (invert_odd) {
+#pragma unroll
+            for (int r = 0; r < 6; r++)
+#pragma unroll
+                for (int c = 0; c < 6; c++) a[r][c] = m[r][c];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 6; r++)
+#pragma unroll
+        for (int c = 0; c < 6; c++) blk[(size_t)(b * 36 + r * 6 + c) * g.V + t] = d2{a[r][c].re, a[r][c].im};
+    ld[(size_t)b * g.V + t] = logdet;
+}
+
+// out = g5^go (A (g5^gi in) - k2 u) at the Vh sites of one parity (u may be
+// null); in-place (out == in) is allowed
+__global__ void __launch_bounds__(CBS) k_clover_apply(int Vh, int V, int poff, const d2* __restrict__ blk,
+                                                      const d2* in, const d2* __restrict__ u, double k2, int gi,
+                                                      int go, d2* out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= Vh) return;
+    const size_t site = (size_t)poff + s;
+    cx<double> v[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const d2 w = in[(size_t)k * Vh + s];
+        v[k] = (gi && k >= 6) ? cx<double>{-w.x, -w.y} : cx<double>{w.x, w.y};
+    }
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+        for (int r = 0; r < 6; r++) {
+            cx<double> acc = {0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 6; c++) {
+                const d2 e = blk[(size_t)(b * 36 + r * 6 + c) * V + site];
+                acc = acc + cx<double>{e.x, e.y} * v[b * 6 + c];
+            }
+            const int k = b * 6 + r;
+            if (u) {
+                const d2 w = u[(size_t)k * Vh + s];
+                acc = acc - k2 * cx<double>{w.x, w.y};
+            }
+            if (go && k >= 6) acc = -acc;
+            out[(size_t)k * Vh + s] = d2{acc.re, acc.im};
+        }
+}
+
+// Colour matrices Kt_q(x) = (K - K^+) / 8, K = i (cw Z + cd Z') per site and
+// plane, with
+//   Z_{ba}  = sum_{s,t} sigma_{st} X_{t b} conj(Y_{s a})        (pseudofermion part, weight cw by parity)
+//   Z'_{ba} = sum_{s,t} sigma_{st} A^-1[(t,b),(s,a)]            (log det part, odd sites)
+// so that the derivative of the clover terms along e_a is
+// sum_x sum_q Re Tr[e_a Q_q(x) Kt_q(x)].
+__global__ void __launch_bounds__(CBS) k_clover_kt(Geom g, const double* __restrict__ sig, double cw_even, double cw_odd, double cd,
+                                                   const d2* __restrict__ Xe, const d2* __restrict__ Xo,
+                                                   const d2* __restrict__ Ye, const d2* __restrict__ Yo,
+                                                   const d2* __restrict__ blk, d2* __restrict__ kt) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.V) return;
+    const int p = t / g.Vh, s = t % g.Vh;
+    const double cw = p ? cw_odd : cw_even;
+    const d2* X = p ? Xo : Xe;
+    const d2* Y = p ? Yo : Ye;
+    const bool pf = X && cw != 0.0;
+    const bool det = p == 1 && cd != 0.0;
+#pragma unroll 1
+    for (int q = 0; q < 6; q++) {
+        cx<double> Z[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) Z[i][j] = {0.0, 0.0};
+#pragma unroll 1
+        for (int bst = 0; bst < 8; bst++) {
+            const int b = bst >> 2, ss = (bst >> 1) & 1, tt = bst & 1;
+            const cx<double> sg = sig_at(sig, q, b, ss, tt);
+            if (sg.re == 0.0 && sg.im == 0.0) continue;
+#pragma unroll
+            for (int bb = 0; bb < 3; bb++) {
+                cx<double> xv = {0.0, 0.0};
+                if (pf) {
+                    const d2 a = X[(size_t)((2 * b + tt) * 3 + bb) * g.Vh + s];
+                    xv = {cw * a.x, cw * a.y};
+                }
+#pragma unroll
+                for (int aa = 0; aa < 3; aa++) {
+                    cx<double> v = {0.0, 0.0};
+                    if (pf) {
+                        const d2 c = Y[(size_t)((2 * b + ss) * 3 + aa) * g.Vh + s];
+                        v = xv * cx<double>{c.x, -c.y};
+                    }
+                    if (det) {
+                        const d2 e = blk[(size_t)(b * 36 + (tt * 3 + bb) * 6 + ss * 3 + aa) * g.V + t];
+                        v = v + cd * cx<double>{e.x, e.y};
+                    }
+                    Z[bb][aa] = Z[bb][aa] + sg * v;
+                }
+            }
+        }
+        // K = i Z, Kt = (K - K^+)/8 = i (Z + Z^+)/8
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                const cx<double> h = Z[i][j] + conj(Z[j][i]);
+                kt[(size_t)(q * 9 + i * 3 + j) * g.V + t] = d2{-0.125 * h.im, 0.125 * h.re};
+            }
+    }
+}
+
+__device__ __forceinline__ M3<double> kt_at(const Geom& g, const d2* __restrict__ kt, int q, double sgn,
+                                            const Coord& y) {
+    const int t = site_of(g, y);
+    M3<double> m;
+#pragma unroll
+    for (int e = 0; e < 9; e++) {
+        const d2 v = kt[(size_t)(q * 9 + e) * g.V + t];
+        m.e[e / 3][e % 3] = {sgn * v.x, sgn * v.y};
+    }
+    return m;
+}
+
+// Force of sum_x sum_{mu<nu} Re Tr[Q_{mu nu}(x) Kt_{mu nu}(x)], gathered per
+// link U_mu(x): for every nu != mu (with Kt_{nu mu} = -Kt_{mu nu}) the two
+// plaquettes through the link, each entered as a leaf at its four corners.
+// With B = U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+ (the +nu staple) and
+// C = U_nu(x-nu)^+ U_mu(x-nu) U_nu(x-nu+mu) (the -nu path to x+mu),
+//   S_up = B K(x) + K(x+mu) B + U_nu(x+mu) [K(x+mu+nu) U_mu(x+nu)^+ + U_mu(x+nu)^+ K(x+nu)] U_nu(x)^+,
+//   S_dn = K(x) C + C K(x+mu) + U_nu(x-nu)^+ [K(x-nu) U_mu(x-nu) + U_mu(x-nu) K(x-nu+mu)] U_nu(x-nu+mu),
+// e_a of the sum is Re Tr[T^a U (S_up + S_dn^+)], so F_a += coef [TA(U (S_up + S_dn^+))]_a / 2.
+__global__ void __launch_bounds__(CBS) k_clover_force(Geom g, const d2* __restrict__ U, const d2* __restrict__ kt,
+                                                      double coef, double* __restrict__ F) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * g.V) return;
+    const int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
+    const Coord x = cb_coords(g, p, s);
+    Coord xm = x;
+    coord_step(g, xm, mu, 1);
+    M3<double> S = m3_zero<double>();
+#pragma unroll 1
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == mu) continue;
+        const int q = mu < nu ? plane_index(mu, nu) : plane_index(nu, mu);
+        const double sg = mu < nu ? 1.0 : -1.0;
+        Coord xn = x, xbn = x, xmn = xm, xmbn = xm;
+        coord_step(g, xn, nu, 1);
+        coord_step(g, xbn, nu, 0);
+        coord_step(g, xmn, nu, 1);
+        coord_step(g, xmbn, nu, 0);
+        const M3<double> Kx = kt_at(g, kt, q, sg, x), Kxm = kt_at(g, kt, q, sg, xm);
+        {
+            const M3<double> unxm = link_at(g, U, nu, xm), umxn = link_at(g, U, mu, xn), unx = link_at(g, U, nu, x);
+            const M3<double> B = m3_mul_nd(m3_mul_nd(unxm, umxn), unx);
+            m3_acc(S, m3_mul(B, Kx));
+            m3_acc(S, m3_mul(Kxm, B));
+            M3<double> in = m3_mul_nd(kt_at(g, kt, q, sg, xmn), umxn);
+            m3_acc(in, m3_mul_dn(umxn, kt_at(g, kt, q, sg, xn)));
+            m3_acc(S, m3_mul_nd(m3_mul(unxm, in), unx));
+        }
+        {
+            const M3<double> unxbn = link_at(g, U, nu, xbn), umxbn = link_at(g, U, mu, xbn);
+            const M3<double> unxmbn = link_at(g, U, nu, xmbn);
+            const M3<double> C = m3_mul(m3_mul_dn(unxbn, umxbn), unxmbn);
+            M3<double> D = m3_mul(Kx, C);
+            m3_acc(D, m3_mul(C, Kxm));
+            M3<double> in = m3_mul(kt_at(g, kt, q, sg, xbn), umxbn);
+            m3_acc(in, m3_mul(umxbn, kt_at(g, kt, q, sg, xmbn)));
+            m3_acc(D, m3_mul(m3_mul_dn(unxbn, in), unxmbn));
+            m3_acc(S, m3_dag(D));
+        }
+    }
+    const M3<double> W = m3_mul(gauge_load(U, mu, p, s, g.Vh), S);
+    double xa[8];
+    ta_components(W, xa);
+    double* o = F + (size_t)(r * 8) * g.Vh + s;
+#pragma unroll
+    for (int a = 0; a < 8; a++) o[(size_t)a * g.Vh] += 0.5 * coef * xa[a];
+}
+
+// A(x) in the public layout: [V lexicographic][12][12] complex, zero between
+// the chirality blocks
+__global__ void __launch_bounds__(CBS) k_clover_unpack(Geom g, const d2* __restrict__ blk, d2* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.V) return;
+    const int p = t / g.Vh, s = t % g.Vh;
+    const Coord x = cb_coords(g, p, s);
+    const size_t lex = (size_t)x.c[0] + (size_t)g.L[0] * (x.c[1] + (size_t)g.L[1] * (x.c[2] + (size_t)g.L[2] * x.c[3]));
+    d2* o = out + lex * 144;
+    for (int r = 0; r < 12; r++)
+        for (int c = 0; c < 12; c++) {
+            const int b = r / 6;
+            o[r * 12 + c] = (c / 6 == b) ? blk[(size_t)(b * 36 + (r % 6) * 6 + c % 6) * g.V + t] : d2{0.0, 0.0};
+        }
+}
+
+// partial[k] = sum of the block's odd-site log dets (both chirality blocks)
+__global__ void __launch_bounds__(CBS) k_logdet_partials(Geom g, const double* __restrict__ ld,
+                                                         double* __restrict__ partial) {
+    __shared__ double sh[CBS];
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (s < g.Vh) v = ld[(size_t)g.Vh + s] + ld[(size_t)g.V + g.Vh + s];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = CBS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+int nb_of(long n) { return (int)((n + CBS - 1) / CBS); }
+
+size_t spinor_bytes(const Geom& g) { return sizeof(d2) * 12 * (size_t)g.Vh; }
+
+double host_scalar(Ctx& c, const double* dev, int slot) {
+    FGI_HIP(hipMemcpyAsync(c.host_scal + slot, dev, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    FGI_HIP(hipStreamSynchronize(c.stream));
+    return c.host_scal[slot];
+}
+
+// Re <a, b> over the 12 Vh complex components of two even spinors
+double dot_re(Ctx& c, const Geom& g, const d2* a, const d2* b, int slot) {
+    double* part = partial_buf(c, g);
+    double* scal = (double*)c.scal.get(sizeof(double) * 64);
+    const int nb = dot_partials(c, 24L * g.Vh, (const double*)a, (const double*)b, part);
+    final_sum(c, part, nb, scal + slot);
+    return host_scalar(c, scal + slot, slot);
+}
+
+}  // namespace
+
+void clover_build(Ctx& c, const Geom& g, double kappa, double csw, const d2* U, d2* blk, int invert_odd,
+                  double* det_action) {
+    d2* fh = (d2*)c.cl_fh.get(sizeof(d2) * 54 * (size_t)g.V);
+    double* ld = (double*)c.cl_ld.get(sizeof(double) * 2 * (size_t)g.V);
+    hipLaunchKernelGGL(k_clover_fhat, dim3(nb_of(g.V)), dim3(CBS), 0, c.stream, g, U, fh);
+    FGI_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_clover_blocks, dim3(nb_of(2L * g.V)), dim3(CBS), 0, c.stream, g, sigma_blocks(c),
+                       kappa * csw, (const d2*)fh, blk, ld, invert_odd);
+    FGI_LAUNCH_CHECK();
+    if (det_action) {
+        double* part = partial_buf(c, g);
+        double* scal = (double*)c.scal.get(sizeof(double) * 64);
+        const int nb = nb_of(g.Vh);
+        hipLaunchKernelGGL(k_logdet_partials, dim3(nb), dim3(CBS), 0, c.stream, g, (const double*)ld, part);
+        FGI_LAUNCH_CHECK();
+        final_sum(c, part, nb, scal + 48);
+        *det_action = -2.0 * host_scalar(c, scal + 48, 48);
+    }
+}
+
+void clover_unpack(Ctx& c, const Geom& g, const d2* blk, void* out) {
+    hipLaunchKernelGGL(k_clover_unpack, dim3(nb_of(g.V)), dim3(CBS), 0, c.stream, g, blk, (d2*)out);
+    FGI_LAUNCH_CHECK();
+}
+
+void clover_apply(Ctx& c, const Geom& g, const d2* blk, int parity, const d2* in, const d2* u, double k2, int g5in,
+                  int g5out, d2* out) {
+    hipLaunchKernelGGL(k_clover_apply, dim3(nb_of(g.Vh)), dim3(CBS), 0, c.stream, g.Vh, g.V, parity * g.Vh, blk, in,
+                       u, k2, g5in, g5out, out);
+    FGI_LAUNCH_CHECK();
+}
+
+// out_e = Mhat in_e = A_ee in_e - kappa^2 D_eo A_oo^-1 D_oe in_e, or with
+// dagger g5 Mhat g5 in_e
+void clover_mhat(Ctx& c, const FermionOp& op, const d2* blk, const d2* in_e, d2* out_e, int dagger) {
+    const Geom& g = *op.g;
+    d2* to = (d2*)c.cl_to.get(spinor_bytes(g));
+    d2* te = (d2*)c.cl_te.get(spinor_bytes(g));
+    const d2* src = in_e;
+    if (dagger) {
+        spinor_lincomb(c, g, 0.0, in_e, 1.0, in_e, 1, te);   // te = g5 in
+        src = te;
+    }
+    dslash(c, op, 1, P64, SpinorPtr{(void*)src, nullptr}, P64, SpinorPtr{to, nullptr});
+    clover_apply(c, g, blk, 1, to, nullptr, 0.0, 0, 0, to);
+    d2* ue = (d2*)c.cl_ue.get(spinor_bytes(g));
+    dslash(c, op, 0, P64, SpinorPtr{to, nullptr}, P64, SpinorPtr{ue, nullptr});
+    clover_apply(c, g, blk, 0, src, ue, op.kappa * op.kappa, 0, dagger, out_e);
+}
+
+// CG on Mhat^+ Mhat with the clover Mhat, FP64, scalars on the host.  The
+// stopping rule is that of the fused solver: when the recursive residual
+// passes tol |phi| the true residual is formed and decides; if it has not
+// passed, CG restarts from it.
+CGResult clover_cg(Ctx& c, const FermionOp& op, const d2* blk, const d2* phi, d2* x, double tol, int maxiter,
+                   bool guess) {
+    const Geom& g = *op.g;
+    const size_t nb = spinor_bytes(g);
+    d2* r = (d2*)c.cl_r.get(nb);
+    d2* p = (d2*)c.cl_p.get(nb);
+    d2* ap = (d2*)c.cl_ap.get(nb);
+    d2* t = (d2*)c.cl_t.get(nb);
+    auto normal = [&](const d2* in, d2* out) {
+        clover_mhat(c, op, blk, in, t, 0);
+        clover_mhat(c, op, blk, t, out, 1);
+    };
+    auto true_residual = [&]() {
+        normal(x, ap);
+        spinor_lincomb(c, g, 1.0, phi, -1.0, ap, 0, r);
+    };
+    CGResult res{};
+    const double bb = dot_re(c, g, phi, phi, 49);
+    const double target = tol * tol * bb;
+    if (guess) {
+        true_residual();
+    } else {
+        spinor_lincomb(c, g, 0.0, phi, 0.0, phi, 0, x);
+        FGI_HIP(hipMemcpyAsync(r, phi, nb, hipMemcpyDeviceToDevice, c.stream));
+    }
+    FGI_HIP(hipMemcpyAsync(p, r, nb, hipMemcpyDeviceToDevice, c.stream));
+    double rr = dot_re(c, g, r, r, 50);
+    int it = 0;
+    bool conv = bb == 0.0 || rr <= target;
+    while (!conv && it < maxiter) {
+        normal(p, ap);
+        const double pap = dot_re(c, g, p, ap, 51);
+        const double alpha = rr / pap;
+        spinor_lincomb(c, g, 1.0, x, alpha, p, 0, x);
+        spinor_lincomb(c, g, 1.0, r, -alpha, ap, 0, r);
+        double rr_new = dot_re(c, g, r, r, 52);
+        it++;
+        if (rr_new <= target) {
+            true_residual();
+            rr_new = dot_re(c, g, r, r, 53);
+            if (rr_new <= target) {
+                conv = true;
+                rr = rr_new;
+                break;
+            }
+            FGI_HIP(hipMemcpyAsync(p, r, nb, hipMemcpyDeviceToDevice, c.stream));
+            rr = rr_new;
+            res.reliable_updates++;
+            continue;
+        }
+        spinor_lincomb(c, g, 1.0, r, rr_new / rr, p, 0, p);
+        rr = rr_new;
+    }
+    res.iters = it;
+    res.converged = conv ? 1 : 0;
+    res.rel_resid = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+    return res;
+}
+
+// F += coef * (pf_scale F_pf + det_scale F_det) with F_pf the force of
+// phi^+ (Mhat^+ Mhat)^-1 phi given its solution X_e and F_det that of
+// -2 sum_{x odd} log det A(x); blk must hold A_ee and A_oo^-1 of the links of op.
+// With Y_e = Mhat X_e, X_o = A_oo^-1 D_oe X_e, Y_o = A_oo^-1 g5 D_oe g5 Y_e the
+// hopping part is the Wilson bilinear of (X, Y) at kappa^2; the clover parts
+// go through Kt (k_clover_kt) and the leaf derivatives (k_clover_force):
+//   e_a S_F clover = -2 sum_x w_x Re[Y(x)^+ e_a A(x) X(x)], w = 1 even, kappa^2 odd,
+//   e_a S_det      = -2 sum_{x odd} Tr[A(x)^-1 e_a A(x)],
+// e_a A = i kappa csw sum sigma (x) e_a Fhat.
+void clover_force(Ctx& c, const FermionOp& op, double csw, const d2* blk, const d2* Xe, double* F, double coef,
+                  double pf_scale, double det_scale) {
+    const Geom& g = *op.g;
+    const double k = op.kappa, kc = k * csw;
+    const size_t nb = spinor_bytes(g);
+    d2* kt = (d2*)c.cl_fh.get(sizeof(d2) * 54 * (size_t)g.V);
+    d2 *ye = nullptr, *xo = nullptr, *yo = nullptr;
+    const bool pf = Xe && pf_scale != 0.0;
+    if (pf) {
+        ye = (d2*)c.cl_ye.get(nb);
+        xo = (d2*)c.cl_xo.get(nb);
+        yo = (d2*)c.cl_yo.get(nb);
+        d2* te = (d2*)c.cl_t.get(nb);
+        clover_mhat(c, op, blk, Xe, ye, 0);
+        dslash(c, op, 1, P64, SpinorPtr{(void*)Xe, nullptr}, P64, SpinorPtr{xo, nullptr});
+        clover_apply(c, g, blk, 1, xo, nullptr, 0.0, 0, 0, xo);
+        spinor_lincomb(c, g, 0.0, ye, 1.0, ye, 1, te);   // te = g5 Y_e
+        dslash(c, op, 1, P64, SpinorPtr{te, nullptr}, P64, SpinorPtr{yo, nullptr});
+        clover_apply(c, g, blk, 1, yo, nullptr, 0.0, 1, 0, yo);   // A^-1 g5 (D_oe g5 Y_e)
+        fermion_force_xyo(c, op, Xe, xo, ye, yo, F, coef * pf_scale * k * k);
+    }
+    hipLaunchKernelGGL(k_clover_kt, dim3(nb_of(g.V)), dim3(CBS), 0, c.stream, g, sigma_blocks(c),
+                       pf ? -2.0 * kc * pf_scale : 0.0, pf ? -2.0 * k * k * kc * pf_scale : 0.0,
+                       -2.0 * kc * det_scale, (const d2*)Xe, (const d2*)xo, (const d2*)ye, (const d2*)yo, blk, kt);
+    FGI_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_clover_force, dim3(nb_of(4L * g.V)), dim3(CBS), 0, c.stream, g, (const d2*)op.links,
+                       (const d2*)kt, coef, F);
+    FGI_LAUNCH_CHECK();
+}
+
+}  // namespace fgi

@@ -799,6 +799,14 @@ void fermion_force_xy(Ctx& c, const FermionOp& op64, const d2* Xe, const d2* Ye,
     FGI_LAUNCH_CHECK();
 }
 
+void fermion_force_xyo(Ctx& c, const FermionOp& op64, const d2* Xe, const d2* Xo, const d2* Ye, const d2* Yo,
+                       double* F, double coef) {
+    const Geom& g = *op64.g;
+    hipLaunchKernelGGL(k_fermion_force, dim3(slab_blocks(g.Vh, 2, 256, c.ds_xcd)), dim3(256), 0, c.stream, g,
+                       (const d2*)op64.links, sp(Xe), sp(Xo), sp(Ye), sp(Yo), coef, F, c.ds_xcd);
+    FGI_LAUNCH_CHECK();
+}
+
 // pseudofermion force of phi^+ (Mhat^+ Mhat)^-1 phi at op64.kappa: Y_e = Mhat X_e
 void fermion_force(Ctx& c, const FermionOp& op64, const d2* Xe, double* F, double coef) {
     const Geom& g = *op64.g;

@@ -102,6 +102,9 @@ struct Ctx {
     DevBuf stout_lev, stout_F, stout_ga, stout_gb, stout_part, stout_M, stout_sloppy;
     // exact force gradient of the Hasenbusch ratio term
     DevBuf hs_dchi, hs_xo, hs_yo, hs_dxo, hs_dyo, hs_zero, hs_t1;
+    // clover term: blocks (A_ee, A_oo^-1), field strengths / force matrices,
+    // log dets, and the vectors of its operator, solver and force
+    DevBuf cl_sig, cl_blk, cl_fh, cl_ld, cl_to, cl_te, cl_ue, cl_r, cl_p, cl_ap, cl_t, cl_ye, cl_xo, cl_yo;
     DevBuf cdesc, bstate, bscal, bh0, bh1, bres;  // batched chains
     CGState* host_bstates = nullptr;          // pinned [host_b_cap]
     double* host_bscal = nullptr;             // pinned [host_b_cap]
@@ -271,6 +274,9 @@ void fermion_force_xy_tangent(Ctx&, const FermionOp& op64, const FermionOp& opW,
                               const d2* Ye, const d2* dXe, double* J, double coef);
 // out = a x + b [g5] y on FP64 even vectors
 void spinor_lincomb(Ctx&, const Geom&, double a, const d2* x, double b, const d2* y, int g5y, d2* out);
+// F += coef * TA(U C(X, Y)) for given even and odd halves of X and Y
+void fermion_force_xyo(Ctx&, const FermionOp& op64, const d2* Xe, const d2* Xo, const d2* Ye, const d2* Yo,
+                       double* F, double coef);
 //   J += coef * J_V[F_F] given Z = A^-1 rhs (after fermion_tangent_rhs on the same X_e)
 void fermion_force_tangent(Ctx&, const FermionOp& op64, const FermionOp& opW, const double* Vd, const d2* Xe,
                            const d2* Z, double* J, double coef);
@@ -288,5 +294,21 @@ void pf_density_b(Ctx&, const Batch&, const d2* phi, const d2* X, const d2* eta,
 std::vector<CGResult> cg_solve_b(Ctx&, const Batch&, const FermionOp& op64, const FermionOp& ops, int sprec,
                                  const d2* phi, d2* X, double tol, int maxiter, bool guess = false);
 
+
+// ---------------- clover.hip ----------------
+// A_ee and A_oo^-1 (A everywhere when invert_odd == 0) of the clover term at
+// kappa, csw on the FP64 links U into blk (72 d2 per site); with det_action,
+// -2 sum_{x odd} log det A(x) (synchronises)
+void clover_build(Ctx&, const Geom&, double kappa, double csw, const d2* U, d2* blk, int invert_odd,
+                  double* det_action);
+// A(x) as [V][12][12] complex in lexicographic site order (blk built with invert_odd == 0)
+void clover_unpack(Ctx&, const Geom&, const d2* blk, void* out);
+// out_e = [g5] Mhat [g5] in_e with the clover Mhat (dagger)
+void clover_mhat(Ctx&, const FermionOp& op64, const d2* blk, const d2* in_e, d2* out_e, int dagger);
+CGResult clover_cg(Ctx&, const FermionOp& op64, const d2* blk, const d2* phi, d2* x, double tol, int maxiter,
+                   bool guess);
+// F += coef (pf_scale F_pf(X_e) + det_scale F_det); Xe may be null when pf_scale == 0
+void clover_force(Ctx&, const FermionOp& op64, double csw, const d2* blk, const d2* Xe, double* F, double coef,
+                  double pf_scale, double det_scale);
 
 }  // namespace fgi

@@ -1,6 +1,7 @@
 // Gauge-side kernels: layout conversion, Hamiltonian densities, the Wilson
 // gauge (staple) force and its tangent (the force gradient along a field),
 // the exact su(3) link update and reunitarisation.  FP64 throughout.
+#include "fgi_coord.h"
 #include "fgi_internal.h"
 
 namespace fgi {
@@ -446,17 +447,6 @@ void gauge_force_tangent(Ctx& c, const Geom& g, double beta, const d2* U, const 
 // (c1 = -1/12: tree-level Symanzik, Luscher and Weisz 1985; c1 = -0.331:
 // Iwasaki).  Everything is linear in (c0, c1): the plaquette kernels above run
 // with their coefficient scaled by c0 and the kernels below add the c1 part.
-
-__device__ __forceinline__ int coord_parity(const Coord& y) { return (y.c[0] + y.c[1] + y.c[2] + y.c[3]) & 1; }
-
-__device__ __forceinline__ void coord_step(const Geom& g, Coord& y, int d, int fwd) {
-    if (fwd) y.c[d] = y.c[d] + 1 == g.L[d] ? 0 : y.c[d] + 1;
-    else y.c[d] = (y.c[d] == 0 ? g.L[d] : y.c[d]) - 1;
-}
-
-__device__ __forceinline__ M3<double> link_at(const Geom& g, const d2* U, int d, const Coord& y) {
-    return gauge_load(U, d, coord_parity(y), cb_index(g, y), g.Vh);
-}
 
 // The 18 rectangle staples of link (mu, x) are the 5-link paths from x + mu
 // back to x that close a 2x1 rectangle through U_mu(x); per nu != mu, six

@@ -41,7 +41,7 @@ class fgi_action(ctypes.Structure):
                 ("cg_tol", ctypes.c_double), ("cg_maxiter", ctypes.c_int), ("prec", ctypes.c_int),
                 ("link_recon", ctypes.c_int), ("fg_exact", ctypes.c_int), ("c1", ctypes.c_double),
                 ("stout_rho", ctypes.c_double), ("stout_n", ctypes.c_int), ("pad", ctypes.c_int),
-                ("cg_tol_md", ctypes.c_double)]
+                ("cg_tol_md", ctypes.c_double), ("csw", ctypes.c_double)]
 
 
 class fgi_stage(ctypes.Structure):
@@ -106,6 +106,7 @@ SIGNATURES = {
     "fgi_improved_gauge_hvp": (_i, [_vp, _P(fgi_geom), _d, _d, _vp, _vp, _vp, _vp]),
     "fgi_stout_smear": (_i, [_vp, _P(fgi_geom), _d, _i, _vp, _vp, _vp]),
     "fgi_stout_force": (_i, [_vp, _P(fgi_geom), _d, _i, _vp, _vp, _vp, _vp]),
+    "fgi_clover_field": (_i, [_vp, _P(fgi_geom), _d, _d, _vp, _vp, _P(_d), _vp, _vp]),
     "fgi_kinetic": (_i, [_vp, _P(fgi_geom), _vp, _P(_d), _vp]),
     "fgi_gauge_force": (_i, [_vp, _P(fgi_geom), _d, _vp, _vp, _vp]),
     "fgi_force_gradient": (_i, [_vp, _P(fgi_geom), _d, _vp, _vp, _vp, _vp]),
@@ -184,11 +185,12 @@ class Action:
     stout_rho: float = 0.0
     stout_n: int = 0     # stout levels of the links the fermion operator sees (0: thin links)
     cg_tol_md: float = 0.0   # tolerance of the solves inside force evaluations (0: cg_tol)
+    csw: float = 0.0     # clover coefficient of the fermion matrix (0: Wilson; FP64 only)
 
     def c(self):
         return fgi_action(self.beta, self.kappa, self.kappa_hasen, self.cg_tol, int(self.cg_maxiter),
                           PREC[self.prec], int(self.link_recon), int(bool(self.fg_exact)), float(self.c1),
-                          float(self.stout_rho), int(self.stout_n), 0, float(self.cg_tol_md))
+                          float(self.stout_rho), int(self.stout_n), 0, float(self.cg_tol_md), float(self.csw))
 
 
 def integrator_builtin(which, alpha=0.1932):
@@ -303,6 +305,19 @@ class Context:
         _check(lib().fgi_stout_force(self.h, _geom(dims), rho, int(n), _ptr(U, torch.complex128, su, "U"),
                                      _ptr(Fs, torch.float64, sp, "Fs"), _ptr(F, torch.float64, sp, "F"), _stream()))
         return F
+
+    def clover_field(self, dims, kappa, csw, U, A=True, F_det=True):
+        """(A [V,12,12] complex or None, S_det = -2 sum_{x odd} log det A(x), F_det or None)"""
+        su, sp, _ = self._shapes(dims)
+        V = dims[0] * dims[1] * dims[2] * dims[3]
+        Aout = torch.empty((V, 12, 12), dtype=torch.complex128, device=U.device) if A else None
+        Fout = torch.empty(sp, dtype=torch.float64, device=U.device) if F_det else None
+        S = ctypes.c_double()
+        _check(lib().fgi_clover_field(self.h, _geom(dims), kappa, csw, _ptr(U, torch.complex128, su, "U"),
+                                      _ptr(Aout, torch.complex128, (V, 12, 12), "A") if A else None,
+                                      ctypes.byref(S), _ptr(Fout, torch.float64, sp, "F_det") if F_det else None,
+                                      _stream()))
+        return Aout, S.value, Fout
 
     def kinetic(self, dims, P):
         _, sp, _ = self._shapes(dims)

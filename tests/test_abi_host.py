@@ -40,7 +40,8 @@ def test_struct_layouts_match_c_sizes():
     assert ctypes.sizeof(fgi.fgi_integrator) == 8 + 4 * ctypes.sizeof(fgi.fgi_level)
     assert fgi.fgi_action.c1.offset == 48
     assert fgi.fgi_action.stout_rho.offset == 56 and fgi.fgi_action.stout_n.offset == 64
-    assert fgi.fgi_action.cg_tol_md.offset == 72 and ctypes.sizeof(fgi.fgi_action) == 80
+    assert fgi.fgi_action.cg_tol_md.offset == 72 and fgi.fgi_action.csw.offset == 80
+    assert ctypes.sizeof(fgi.fgi_action) == 88
     # fgi_chain: int dims[4], int pad, double beta, double kappa, 3 pointers
     assert ctypes.sizeof(fgi.fgi_chain) == 64 and fgi.fgi_chain.beta.offset == 24
     # fgi_tuning: 4 ints, 6 + 5 doubles
