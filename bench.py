@@ -516,6 +516,45 @@ def stout_leg(R, U_therm, rho=0.1, n=2, reps=20):
                          "force_n0": round(ms["force", 0], 4), "force_n": round(ms["force", n], 4)})
 
 
+def clover_leg(R, U_therm, inputs, n, kappa=0.135, csw=1.0, reps=10):
+    """The clover-improved fermion operator (FP64; csw = 1, kappa = 0.135:
+    kappa csw < 1/6 keeps A(x) positive on any field, and the clover operator
+    stays below its critical kappa on the thermalised beta = 5.6 field, which
+    at csw = 1 lies under the Wilson value of the timed leg) beside the Wilson
+    operator at the same kappa: one FG trajectory (n steps, tau = 1) of each
+    from the thermalised links with the first timed momenta and noise (FP64
+    solves at the timed tolerance), and fgi_mhat with and without the clover
+    term (HIP events around reps calls: pack, clover blocks, two hops and the
+    site-local A_ee, A_oo^-1 products)."""
+    torch = R.torch
+    integ = R.fgi.integrator_builtin("FG", 0.1932)
+    U = torch.empty_like(U_therm)
+    P = torch.empty_like(inputs[0][0])
+    P0, eta = inputs[0]
+    out = dict(kappa=kappa, csw=csw, n=n)
+    for key, cc in (("wilson", 0.0), ("clover", csw)):
+        act = R.fgi.Action(beta=R.args.beta, kappa=kappa, csw=cc, cg_tol=R.args.tol, prec="fp64")
+        U.copy_(U_therm)
+        P.copy_(P0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dH, st = R.ctx.trajectory(R.dims, act, integ, 1.0, n, U, P, eta)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[key] = dict(s_per_traj=sec, dH=dH, solves=st["solves"], cg_iters=st["cg_iters"],
+                        ms_per_cg_iter=round(sec * 1e3 / max(1, st["cg_iters"]), 4))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        R.ctx.mhat(R.dims, act, U_therm, eta)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            R.ctx.mhat(R.dims, act, U_therm, eta)
+        e1.record()
+        torch.cuda.synchronize()
+        out[key]["mhat_call_ms"] = round(e0.elapsed_time(e1) / reps, 4)
+    return out
+
+
 def summarise(recs):
     dh = np.array([r["dH"] for r in recs])
     return dict(mean_dH=float(dh.mean()), mean_dH2=float((dh ** 2).mean()),
@@ -794,6 +833,15 @@ def main():
              ["%+.3e" % d for d in improved["symanzik"]["dH"]], improved["gauge_force_call_ms"]["wilson"],
              improved["gauge_force_call_ms"]["symanzik"], improved["rect_force_kernel"]["us"],
              improved["rect_force_kernel"]["achieved_TFLOPs"] or 0))
+    clover = None
+    if args.improved_steps > 0:
+        clover = clover_leg(R, U, inputs[args.warmup:args.warmup + 1], args.n_fg)
+        log("clover FG-fp64 n=%d at kappa %.3f, csw %.2f: %.3f s/traj, %d CG iterations (%.3f ms each), dH %+.3e; "
+            "Wilson FG-fp64 at the same kappa %.3f s/traj, %d iterations (%.3f ms each); mhat call %.3f -> %.3f ms" %
+            (args.n_fg, clover["kappa"], clover["csw"], clover["clover"]["s_per_traj"], clover["clover"]["cg_iters"],
+             clover["clover"]["ms_per_cg_iter"], clover["clover"]["dH"], clover["wilson"]["s_per_traj"],
+             clover["wilson"]["cg_iters"], clover["wilson"]["ms_per_cg_iter"], clover["wilson"]["mhat_call_ms"],
+             clover["clover"]["mhat_call_ms"]))
     stout = None
     if args.improved_steps > 0:
         stout = stout_leg(R, U)
@@ -834,7 +882,8 @@ def main():
                fg=fg, fg_exact=exact, lf_fp64=lf,
                speedup_vs_lf_fp64=(round(lf["s_per_traj"] / s_per_traj, 3) if lf else None),
                roofline=roof, roofline_32x32x32x64=large, hasenbusch_32x32x32x64=hasen, batched=batched,
-               alpha_tuning=alpha_leg, md_tolerance=md_leg, chain=chain, improved_gauge=improved, stout=stout,
+               alpha_tuning=alpha_leg, md_tolerance=md_leg, chain=chain, improved_gauge=improved, clover=clover,
+               stout=stout,
                cpu_baseline=cpu)
     print(json.dumps(out), flush=True)
 
