@@ -14,6 +14,8 @@
 // Storage: blk[(b * 36 + r * 6 + c) * V + p * Vh + s], block b, row r, column
 // c (index spin' * 3 + colour within the block), site s of parity p; even
 // sites hold A, odd sites A^-1 (or A, for the read-out entry point).
+#include <algorithm>
+#include <cmath>
 #include <complex>
 
 #include "fgi_coord.h"
@@ -425,6 +427,83 @@ double dot_re(Ctx& c, const Geom& g, const d2* a, const d2* b, int slot) {
     return host_scalar(c, scal + slot, slot);
 }
 
+// ---- CG scalars on the device: st[0] = |r|^2, st[1] = alpha, st[2] = beta.
+// Reductions sum per-block partials in a fixed order in one block.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n) {
+    __shared__ double sh[CBS];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += CBS) v += part[i];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = CBS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// mode 0: st[0] = sum (|r|^2 of a restart); 1: alpha = st[0] / sum (<p, A p>);
+// 2: beta = sum / st[0], st[0] = sum (|r|^2 of the new residual)
+__global__ void __launch_bounds__(CBS) k_cl_scalar(const double* __restrict__ part, int n, int mode,
+                                                   double* __restrict__ st) {
+    const double v = sum_partials(part, n);
+    if (threadIdx.x != 0) return;
+    if (mode == 0) {
+        st[0] = v;
+    } else if (mode == 1) {
+        st[1] = st[0] / v;
+    } else {
+        st[2] = v / st[0];
+        st[0] = v;
+    }
+}
+
+// x += alpha p, r -= alpha A p; partial[b] = sum over the block of |r|^2
+__global__ void __launch_bounds__(CBS) k_cl_xr(int Vh, const double* __restrict__ st, const d2* __restrict__ p,
+                                               const d2* __restrict__ ap, d2* __restrict__ x, d2* __restrict__ r,
+                                               double* __restrict__ part) {
+    __shared__ double sh[CBS];
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (s < Vh) {
+        const double a = st[1];
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            const size_t i = (size_t)k * Vh + s;
+            const d2 pv = p[i], qv = ap[i];
+            d2 xv = x[i], rv = r[i];
+            xv.x += a * pv.x;
+            xv.y += a * pv.y;
+            rv.x -= a * qv.x;
+            rv.y -= a * qv.y;
+            x[i] = xv;
+            r[i] = rv;
+            acc += rv.x * rv.x + rv.y * rv.y;
+        }
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = CBS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// p = r + beta p
+__global__ void __launch_bounds__(CBS) k_cl_p(int Vh, const double* __restrict__ st, const d2* __restrict__ r,
+                                              d2* __restrict__ p) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= Vh) return;
+    const double b = st[2];
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const size_t i = (size_t)k * Vh + s;
+        const d2 rv = r[i], pv = p[i];
+        p[i] = d2{rv.x + b * pv.x, rv.y + b * pv.y};
+    }
+}
+
 }  // namespace
 
 void clover_build(Ctx& c, const Geom& g, double kappa, double csw, const d2* U, d2* blk, int invert_odd,
@@ -460,27 +539,27 @@ void clover_apply(Ctx& c, const Geom& g, const d2* blk, int parity, const d2* in
 }
 
 // out_e = Mhat in_e = A_ee in_e - kappa^2 D_eo A_oo^-1 D_oe in_e, or with
-// dagger g5 Mhat g5 in_e
+// dagger g5 Mhat g5 in_e (the g5 on the input folded into the first hop and
+// into the A_ee product, the one on the output into that product's store)
 void clover_mhat(Ctx& c, const FermionOp& op, const d2* blk, const d2* in_e, d2* out_e, int dagger) {
     const Geom& g = *op.g;
     d2* to = (d2*)c.cl_to.get(spinor_bytes(g));
-    d2* te = (d2*)c.cl_te.get(spinor_bytes(g));
-    const d2* src = in_e;
-    if (dagger) {
-        spinor_lincomb(c, g, 0.0, in_e, 1.0, in_e, 1, te);   // te = g5 in
-        src = te;
-    }
-    dslash(c, op, 1, P64, SpinorPtr{(void*)src, nullptr}, P64, SpinorPtr{to, nullptr});
+    if (dagger) hop_oe_g5(c, op, in_e, to);
+    else dslash(c, op, 1, P64, SpinorPtr{(void*)in_e, nullptr}, P64, SpinorPtr{to, nullptr});
     clover_apply(c, g, blk, 1, to, nullptr, 0.0, 0, 0, to);
     d2* ue = (d2*)c.cl_ue.get(spinor_bytes(g));
     dslash(c, op, 0, P64, SpinorPtr{to, nullptr}, P64, SpinorPtr{ue, nullptr});
-    clover_apply(c, g, blk, 0, src, ue, op.kappa * op.kappa, 0, dagger, out_e);
+    clover_apply(c, g, blk, 0, in_e, ue, op.kappa * op.kappa, dagger, dagger, out_e);
 }
 
-// CG on Mhat^+ Mhat with the clover Mhat, FP64, scalars on the host.  The
-// stopping rule is that of the fused solver: when the recursive residual
-// passes tol |phi| the true residual is formed and decides; if it has not
-// passed, CG restarts from it.
+// CG on Mhat^+ Mhat with the clover Mhat, FP64.  The recurrence scalars stay
+// on the device (k_cl_scalar); the host reads |r|^2 once per batch of
+// CL_BATCH iterations.  Stopping rule as in the fused solver: once the
+// recursive residual has passed tol |phi|, the true residual is formed and
+// decides; if it has not passed, CG restarts from it.  A batch may run a few
+// iterations past the point where the recursive residual first passed.
+constexpr int CL_BATCH = 8;
+
 CGResult clover_cg(Ctx& c, const FermionOp& op, const d2* blk, const d2* phi, d2* x, double tol, int maxiter,
                    bool guess) {
     const Geom& g = *op.g;
@@ -489,6 +568,12 @@ CGResult clover_cg(Ctx& c, const FermionOp& op, const d2* blk, const d2* phi, d2
     d2* p = (d2*)c.cl_p.get(nb);
     d2* ap = (d2*)c.cl_ap.get(nb);
     d2* t = (d2*)c.cl_t.get(nb);
+    double* part = partial_buf(c, g);
+    const long ndot = 24L * g.Vh;
+    double* part2 = part + (ndot + 255) / 256 + 64;   // after the dot partials
+    double* scal = (double*)c.scal.get(sizeof(double) * 64);
+    double* st = scal + 56;                           // rr, alpha, beta
+    const int nbv = nb_of(g.Vh);
     auto normal = [&](const d2* in, d2* out) {
         clover_mhat(c, op, blk, in, t, 0);
         clover_mhat(c, op, blk, t, out, 1);
@@ -496,6 +581,12 @@ CGResult clover_cg(Ctx& c, const FermionOp& op, const d2* blk, const d2* phi, d2
     auto true_residual = [&]() {
         normal(x, ap);
         spinor_lincomb(c, g, 1.0, phi, -1.0, ap, 0, r);
+    };
+    auto set_rr = [&]() {   // st[0] = |r|^2, returned to the host
+        const int n = dot_partials(c, ndot, (const double*)r, (const double*)r, part);
+        hipLaunchKernelGGL(k_cl_scalar, dim3(1), dim3(CBS), 0, c.stream, (const double*)part, n, 0, st);
+        FGI_LAUNCH_CHECK();
+        return host_scalar(c, st, 56);
     };
     CGResult res{};
     const double bb = dot_re(c, g, phi, phi, 49);
@@ -507,32 +598,33 @@ CGResult clover_cg(Ctx& c, const FermionOp& op, const d2* blk, const d2* phi, d2
         FGI_HIP(hipMemcpyAsync(r, phi, nb, hipMemcpyDeviceToDevice, c.stream));
     }
     FGI_HIP(hipMemcpyAsync(p, r, nb, hipMemcpyDeviceToDevice, c.stream));
-    double rr = dot_re(c, g, r, r, 50);
+    double rr = set_rr();
     int it = 0;
     bool conv = bb == 0.0 || rr <= target;
     while (!conv && it < maxiter) {
-        normal(p, ap);
-        const double pap = dot_re(c, g, p, ap, 51);
-        const double alpha = rr / pap;
-        spinor_lincomb(c, g, 1.0, x, alpha, p, 0, x);
-        spinor_lincomb(c, g, 1.0, r, -alpha, ap, 0, r);
-        double rr_new = dot_re(c, g, r, r, 52);
-        it++;
-        if (rr_new <= target) {
+        const int nbatch = std::min(CL_BATCH, maxiter - it);
+        for (int k = 0; k < nbatch; k++) {
+            normal(p, ap);
+            const int n1 = dot_partials(c, ndot, (const double*)p, (const double*)ap, part);
+            hipLaunchKernelGGL(k_cl_scalar, dim3(1), dim3(CBS), 0, c.stream, (const double*)part, n1, 1, st);
+            hipLaunchKernelGGL(k_cl_xr, dim3(nbv), dim3(CBS), 0, c.stream, g.Vh, (const double*)st, (const d2*)p,
+                               (const d2*)ap, x, r, part2);
+            hipLaunchKernelGGL(k_cl_scalar, dim3(1), dim3(CBS), 0, c.stream, (const double*)part2, nbv, 2, st);
+            hipLaunchKernelGGL(k_cl_p, dim3(nbv), dim3(CBS), 0, c.stream, g.Vh, (const double*)st, (const d2*)r, p);
+            FGI_LAUNCH_CHECK();
+        }
+        it += nbatch;
+        rr = host_scalar(c, st, 56);
+        if (!(rr > target)) {   // passed (or not a number: the true residual decides)
             true_residual();
-            rr_new = dot_re(c, g, r, r, 53);
-            if (rr_new <= target) {
+            rr = set_rr();
+            if (rr <= target) {
                 conv = true;
-                rr = rr_new;
                 break;
             }
             FGI_HIP(hipMemcpyAsync(p, r, nb, hipMemcpyDeviceToDevice, c.stream));
-            rr = rr_new;
             res.reliable_updates++;
-            continue;
         }
-        spinor_lincomb(c, g, 1.0, r, rr_new / rr, p, 0, p);
-        rr = rr_new;
     }
     res.iters = it;
     res.converged = conv ? 1 : 0;

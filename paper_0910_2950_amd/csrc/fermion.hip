@@ -799,14 +799,6 @@ void fermion_force_xy(Ctx& c, const FermionOp& op64, const d2* Xe, const d2* Ye,
     FGI_LAUNCH_CHECK();
 }
 
-void fermion_force_xyo(Ctx& c, const FermionOp& op64, const d2* Xe, const d2* Xo, const d2* Ye, const d2* Yo,
-                       double* F, double coef) {
-    const Geom& g = *op64.g;
-    hipLaunchKernelGGL(k_fermion_force, dim3(slab_blocks(g.Vh, 2, 256, c.ds_xcd)), dim3(256), 0, c.stream, g,
-                       (const d2*)op64.links, sp(Xe), sp(Xo), sp(Ye), sp(Yo), coef, F, c.ds_xcd);
-    FGI_LAUNCH_CHECK();
-}
-
 // pseudofermion force of phi^+ (Mhat^+ Mhat)^-1 phi at op64.kappa: Y_e = Mhat X_e
 void fermion_force(Ctx& c, const FermionOp& op64, const d2* Xe, double* F, double coef) {
     const Geom& g = *op64.g;
@@ -940,6 +932,19 @@ void fermion_force_xy_tangent(Ctx& c, const FermionOp& op64, const FermionOp& op
 void spinor_lincomb(Ctx& c, const Geom& g, double a, const d2* x, double b, const d2* y, int g5y, d2* out) {
     lincomb(c, g, a, x, b, y, g5y, out);
 }
+
+// F += coef * TA(U C(X, Y)) for given odd halves X_o, Y_o (operators whose odd
+// reconstruction is not D_oe alone)
+void fermion_force_xyo(Ctx& c, const FermionOp& op64, const d2* Xe, const d2* Xo, const d2* Ye, const d2* Yo,
+                       double* F, double coef) {
+    const Geom& g = *op64.g;
+    hipLaunchKernelGGL(k_fermion_force, dim3(slab_blocks(g.Vh, 2, 256, c.ds_xcd)), dim3(256), 0, c.stream, g,
+                       (const d2*)op64.links, sp(Xe), sp(Xo), sp(Ye), sp(Yo), coef, F, c.ds_xcd);
+    FGI_LAUNCH_CHECK();
+}
+
+// out_o = D_oe g5 in_e (FP64): the first hop of Mhat^+ = g5 Mhat g5
+void hop_oe_g5(Ctx& c, const FermionOp& op64, const d2* in_e, d2* out_o) { hop_g5(c, op64, in_e, out_o, 0); }
 
 // ---------------------------------------------------------------- CG ------
 static double norm2_sync(Ctx& c, const Geom& g, const d2* v) {

@@ -277,6 +277,8 @@ void spinor_lincomb(Ctx&, const Geom&, double a, const d2* x, double b, const d2
 // F += coef * TA(U C(X, Y)) for given even and odd halves of X and Y
 void fermion_force_xyo(Ctx&, const FermionOp& op64, const d2* Xe, const d2* Xo, const d2* Ye, const d2* Yo,
                        double* F, double coef);
+// out_o = D_oe g5 in_e (FP64)
+void hop_oe_g5(Ctx&, const FermionOp& op64, const d2* in_e, d2* out_o);
 //   J += coef * J_V[F_F] given Z = A^-1 rhs (after fermion_tangent_rhs on the same X_e)
 void fermion_force_tangent(Ctx&, const FermionOp& op64, const FermionOp& opW, const double* Vd, const d2* Xe,
                            const d2* Z, double* J, double coef);
