@@ -1869,6 +1869,7 @@ typedef struct {
     double stout_rho;
     int stout_n;         /* stout levels of the links the fermions see */
     int fg_exact;        /* G stages in the exact form */
+    double csw;          /* clover coefficient (no Hasenbusch split with it) */
 } nested_run;
 
 /* the links the fermion terms see at W: a new smeared copy, or NULL for W */
@@ -1904,8 +1905,16 @@ static void terms_force(nested_run *r, const cplx *W, int terms, double *F, int 
     double *Ff = Ws ? calloc(4 * V * 8, sizeof(double)) : F;
     if (terms & TERM_FERM) {
         double k1 = r->kappa2 != 0.0 ? r->kappa2 : r->kappa;
-        count_solve(r, oracle_cg_from(L, k1, Wf, r->phi1, r->X1, r->tol, r->maxiter, NULL, from_last));
-        oracle_fermion_force_add(L, k1, Wf, r->X1, 1.0, Ff);
+        if (r->csw != 0.0) {   /* S_F and -2 log det A_oo */
+            clover_t cl;
+            clover_build(L, k1, r->csw, Wf, &cl, NULL);
+            count_solve(r, cg_cl(L, k1, Wf, &cl, r->phi1, r->X1, r->tol, r->maxiter, NULL, from_last));
+            clover_force_add(L, k1, Wf, &cl, r->X1, 1.0, 1.0, Ff);
+            clover_free(&cl);
+        } else {
+            count_solve(r, oracle_cg_from(L, k1, Wf, r->phi1, r->X1, r->tol, r->maxiter, NULL, from_last));
+            oracle_fermion_force_add(L, k1, Wf, r->X1, 1.0, Ff);
+        }
     }
     if ((terms & TERM_HASEN) && r->kappa2 != 0.0) {
         int it;
@@ -1989,8 +1998,9 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
                              int cg_maxiter, int nlevels, const int *nstages, const int *terms, const int *nsub,
                              const char *kinds, const double *ws, const double *xis, double tau, int nsteps,
                              cplx *U, double *P, const cplx *eta1, const cplx *eta2, double *dH, long *stats3,
-                             int fg_start, double c1, double stout_rho, int stout_n, int fg_exact) {
+                             int fg_start, double c1, double stout_rho, int stout_n, int fg_exact, double csw) {
     if (fg_exact && kappa != 0.0 && stout_n > 0) return -2;
+    if (kappa != 0.0 && csw != 0.0 && (fg_exact || kappa2 != 0.0)) return -2;
     long V = lat_volume(L), Vh = V / 2;
     const char *kp[8];
     const double *wp[8], *xp[8];
@@ -2006,6 +2016,7 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
     r.stout_rho = stout_rho;
     r.stout_n = stout_n;
     r.fg_exact = fg_exact;
+    r.csw = csw;
     cplx *phi1 = NULL, *phi2 = NULL;
     double *h0 = malloc(sizeof(double) * V), *h1 = malloc(sizeof(double) * V), *tmp = malloc(sizeof(double) * V);
     gauge_density(L, beta, c1, U, h0);
@@ -2016,7 +2027,18 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
         cplx *Us = nested_fermion_links(&r, U);
         const cplx *Uf = Us ? Us : U;
         phi1 = malloc(sizeof(cplx) * 12 * Vh);
-        oracle_pf_heatbath(L, kappa2 != 0.0 ? kappa2 : kappa, Uf, eta1, phi1);
+        if (csw != 0.0) {
+            clover_t cl;
+            double *ld = malloc(sizeof(double) * V);
+            clover_build(L, kappa, csw, Uf, &cl, ld);
+            mhat_cl(L, kappa, Uf, &cl, eta1, phi1, 1);
+            for (long i = 0; i < V; i++)
+                if (lat_parity(L, i) == 1) sf0 += -2.0 * ld[i];
+            clover_free(&cl);
+            free(ld);
+        } else {
+            oracle_pf_heatbath(L, kappa2 != 0.0 ? kappa2 : kappa, Uf, eta1, phi1);
+        }
         sf0 += vdot_re(12 * Vh, eta1, eta1);
         if (kappa2 != 0.0) {
             phi2 = malloc(sizeof(cplx) * 12 * Vh);
@@ -2036,7 +2058,24 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
         int it;
         cplx *Us = nested_fermion_links(&r, U);
         const cplx *Uf = Us ? Us : U;
-        double s1 = oracle_pf_action(L, kappa2 != 0.0 ? kappa2 : kappa, Uf, phi1, cg_tol, cg_maxiter, &it);
+        double s1;
+        if (csw != 0.0) {
+            double *ld = malloc(sizeof(double) * V);
+            clover_t cl;
+            clover_build(L, kappa, csw, Uf, &cl, ld);
+            cplx *X = malloc(sizeof(cplx) * 12 * Vh);
+            double *hd = malloc(sizeof(double) * Vh);
+            it = cg_cl(L, kappa, Uf, &cl, phi1, X, cg_tol, cg_maxiter, NULL, 0);
+            pf_density(Vh, phi1, X, hd);
+            s1 = 0.0;
+            for (long k = 0; k < Vh; k++) s1 += hd[k];
+            for (long i = 0; i < V; i++)
+                if (lat_parity(L, i) == 1) s1 += -2.0 * ld[i];
+            clover_free(&cl);
+            free(ld); free(X); free(hd);
+        } else {
+            s1 = oracle_pf_action(L, kappa2 != 0.0 ? kappa2 : kappa, Uf, phi1, cg_tol, cg_maxiter, &it);
+        }
         count_solve(&r, it);
         if (kappa2 != 0.0) {
             s1 += oracle_hasen_action(L, kappa, kappa2, Uf, phi2, cg_tol, cg_maxiter, NULL, &it);
@@ -2057,9 +2096,9 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
  *         difference with step h (needs two force evaluations).         */
 void oracle_brackets(const int L[4], double beta, double kappa, int fermions, double cg_tol,
                      int cg_maxiter, const cplx *U, const double *P, const cplx *phi, double h,
-                     double *SST, double *TST, double c1, double stout_rho, int stout_n) {
+                     double *SST, double *TST, double c1, double stout_rho, int stout_n, double csw) {
     long V = lat_volume(L), n = 4 * V * 8;
-    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 0, c1, stout_rho, stout_n};
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 0, c1, stout_rho, stout_n, csw};
     oracle_stats st = {0, 0, 0};
     double *F = malloc(sizeof(double) * n);
     cplx *Ud = malloc(sizeof(cplx) * 4 * V * 9);

@@ -90,7 +90,7 @@ def _declare(L):
     L.oracle_clover_force_add.argtypes = [_ip, _d, _d, _vp, _vp, _d, _d, _vp]
     L.oracle_clover_cg.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _d, _i]
     L.oracle_trajectory.restype = _i
-    L.oracle_brackets.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _d, _dp, _dp, _d, _d, _i]
+    L.oracle_brackets.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _d, _dp, _dp, _d, _d, _i, _d]
     L.oracle_hasen_heatbath.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _d, _i]
     L.oracle_hasen_heatbath.restype = _i
     L.oracle_hasen_action.argtypes = [_ip, _d, _d, _vp, _vp, _d, _i, _vp, _ip]
@@ -99,7 +99,7 @@ def _declare(L):
     L.oracle_hasen_force_tangent_add.argtypes = [_ip, _d, _d, _vp, _vp, _vp, _vp, _d, _i, _d, _vp]
     L.oracle_hasen_force_tangent_add.restype = _i
     L.oracle_trajectory_nested.argtypes = [_ip, _d, _d, _d, _d, _i, _i, _vp, _vp, _vp, ctypes.c_char_p, _vp, _vp,
-                                           _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i, _d, _d, _i, _i]
+                                           _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i, _d, _d, _i, _i, _d]
     L.oracle_trajectory_nested.restype = _i
     L.oracle_philox.argtypes = [_vp, _vp, _vp]
     L.oracle_refresh.argtypes = [_ip, ctypes.c_uint64, ctypes.c_uint32, _vp, _vp, _vp]
@@ -331,7 +331,7 @@ def trajectory(dims, beta, stages, tau, nsteps, U, P, kappa=0.0, eta=None, tol=1
 
 
 def brackets(dims, beta, U, P, kappa=0.0, phi=None, h=1e-4, tol=1e-14, maxiter=10000, c1=0.0, stout_rho=0.0,
-             stout_n=0):
+             stout_n=0, csw=0.0):
     """(SST, TST) = ({S,{S,T}}, {T,{S,T}}) at (U, P); TST by central difference."""
     U = _c(U, np.complex128)
     P = _c(P, np.float64)
@@ -341,7 +341,7 @@ def brackets(dims, beta, U, P, kappa=0.0, phi=None, h=1e-4, tol=1e-14, maxiter=1
     tst = ctypes.c_double(0)
     lib().oracle_brackets(_dims(dims), beta, kappa, int(ferm), tol, maxiter, _ptr(U), _ptr(P),
                           _ptr(phi_a) if ferm else None, h, ctypes.byref(sst), ctypes.byref(tst), c1, stout_rho,
-                          int(stout_n))
+                          int(stout_n), csw)
     return sst.value, tst.value
 
 
@@ -384,7 +384,8 @@ def hasen_force_tangent(dims, kappa, kappa2, U, phi2, X2, V, tol=1e-14, maxiter=
 
 
 def trajectory_nested(dims, beta, levels, tau, nsteps, U, P, kappa=0.0, kappa2=0.0, eta1=None, eta2=None,
-                      tol=1e-14, maxiter=10000, fg_start=True, c1=0.0, stout_rho=0.0, stout_n=0, fg_exact=False):
+                      tol=1e-14, maxiter=10000, fg_start=True, c1=0.0, stout_rho=0.0, stout_n=0, fg_exact=False,
+                      csw=0.0):
     """levels: list of (stages, terms, nsub), level 0 outermost; terms bit 1 gauge,
     2 S_F (or S_1 with Hasenbusch), 4 S_2.  Returns (U, P, dH, stats, status)."""
     U = np.array(U, dtype=np.complex128, copy=True, order="C")
@@ -404,7 +405,7 @@ def trajectory_nested(dims, beta, levels, tau, nsteps, U, P, kappa=0.0, kappa2=0
                                             _ptr(U), _ptr(P), _ptr(e1) if e1 is not None else None,
                                             _ptr(e2) if e2 is not None else None, ctypes.byref(dH), st,
                                             int(bool(fg_start)), c1, stout_rho, int(stout_n),
-                                            int(bool(fg_exact)))
+                                            int(bool(fg_exact)), csw)
     return U, P, dH.value, dict(solves=st[0], cg_iters=st[1], cg_fail=st[2]), status
 
 

@@ -175,3 +175,19 @@ def test_clover_chain_runs(ctx):
     out = ctx.hmc_run(dims, act, "FG", 1.0, 3, U, 1234, 0, 2, metropolis=False)
     dH = out[0]
     assert len(dH) == 2 and all(np.isfinite(dH)) and all(abs(d) < 5 for d in dH)
+
+
+def test_clover_nested_scales_and_brackets(ctx, orc):
+    dims = (4, 4, 2, 2)
+    U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 711)
+    levels = [(orc.table("FG"), 2, 1), (orc.table("FG"), 1, 2)]
+    act = Action(beta=5.6, kappa=K, csw=CSW, cg_tol=1e-14)
+    U, P = dev(U0), dev(P0)
+    dH, st = ctx.trajectory(dims, act, fgi.integrator_from_levels(levels), 1.0, 3, U, P, dev(eta))
+    Uo, Po, dHo, sto, status = orc.trajectory_nested(dims, 5.6, levels, 1.0, 3, U0, P0, kappa=K, eta1=eta, csw=CSW)
+    assert status == 0 and st["solves"] == sto["solves"]
+    assert relmax(host(U), Uo) < 1e-11 and relmax(host(P), Po) < 1e-11 and abs(dH - dHo) < 1e-9
+    phi = orc.clover_mhat(dims, K, CSW, U0, eta, dagger=True)
+    sst, tst = ctx.poisson_brackets(dims, act, dev(U0), dev(P0), dev(phi), h=1e-4)
+    so, to = orc.brackets(dims, 5.6, U0, P0, kappa=K, phi=phi, h=1e-4, csw=CSW)
+    assert abs(sst - so) < 1e-11 * so and abs(tst - to) < 1e-7 * abs(to)

@@ -302,3 +302,39 @@ def test_exact_form_refused(orc):
     U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 612)
     *_, status = orc.trajectory(dims, 5.6, table("FG"), 1.0, 2, U0, P0, kappa=K, eta=eta, csw=CSW, fg_exact=True)
     assert status == -2
+
+
+def test_nested_driver_with_clover(orc):
+    """the nested driver with the clover term: one level with every term is
+    the single-level trajectory; two scales (S_F + log det outside, S_G
+    inside) are reversible and fourth order in FG"""
+    dims = (4, 4, 2, 2)
+    U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 613)
+    a = orc.trajectory(dims, 5.6, table("FG"), 1.0, 4, U0, P0, kappa=K, eta=eta, csw=CSW)
+    b = orc.trajectory_nested(dims, 5.6, [(table("FG"), 3, 1)], 1.0, 4, U0, P0, kappa=K, eta1=eta, csw=CSW)
+    assert b[4] == 0 and np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert abs(a[2] - b[2]) < 1e-10 and a[3]["solves"] == b[3]["solves"]
+    levels = [(table("FG"), 2, 1), (table("FG"), 1, 2)]
+    dh = []
+    for n in (12, 24):   # (at 6 and 12 the ratio is still pre-asymptotic: slope 5.2)
+        U1, P1, d, _, status = orc.trajectory_nested(dims, 5.6, levels, 1.0, n, U0, P0, kappa=K, eta1=eta, csw=CSW)
+        assert status == 0
+        dh.append(d)
+    assert abs(np.log2(abs(dh[0] / dh[1])) - 4) < 0.5, dh
+    # refused: the Hasenbusch split and the exact form with the clover term
+    assert orc.trajectory_nested(dims, 5.6, levels, 1.0, 2, U0, P0, kappa=K, kappa2=0.14, eta1=eta, eta2=eta,
+                                 csw=CSW)[4] == -2
+    assert orc.trajectory_nested(dims, 5.6, levels, 1.0, 2, U0, P0, kappa=K, eta1=eta, csw=CSW,
+                                 fg_exact=True)[4] == -2
+
+
+def test_brackets_with_clover(orc):
+    """SST is the squared total force, with the clover and log det parts"""
+    dims = (4, 2, 2, 4)
+    U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 614)
+    phi = orc.clover_mhat(dims, K, CSW, U0, eta, dagger=True)
+    F, _ = orc.force(dims, 5.6, U0, kappa=K, phi=phi, csw=CSW)
+    sst, tst = orc.brackets(dims, 5.6, U0, P0, kappa=K, phi=phi, csw=CSW)
+    assert abs(sst - np.sum(F * F)) < 1e-10 * sst
+    sst0, _ = orc.brackets(dims, 5.6, U0, P0, kappa=K, phi=phi)
+    assert abs(sst - sst0) > 1e-3 * sst
