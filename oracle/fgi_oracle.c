@@ -1068,7 +1068,9 @@ static void kt_add(const cplx sg[4][4], const cplx *Bm, cplx c, mat3 *Kt) {
 }
 
 /* Forces of the clover action given the solution X_e = (Mhat^+ Mhat)^-1 phi
- * (pf_scale: S_F; det_scale: the -2 log det A_oo term), ADDED to F.
+ * (pf_scale: S_F; det_scale: the -2 log det A_oo term), ADDED to F.  With
+ * Ye_given the pseudofermion part is the bilinear -2 Re[Y^+ (e_a Mhat) X] for
+ * that Y_e instead (the chi-dependent part of the Hasenbusch ratio term).
  * With Y_e = Mhat X_e, X_o = A_oo^-1 D_oe X_e, Y_o = A_oo^-1 D_eo^+ Y_e:
  *   e_a S_F = -2 Re[Y^+ (e_a Mhat) X]
  *           = 2 kappa^2 Re[Y^+ (e_a D) X]                     (hopping, full X, Y)
@@ -1078,7 +1080,7 @@ static void kt_add(const cplx sg[4][4], const cplx *Bm, cplx c, mat3 *Kt) {
  * Re Tr[e_a Fhat K] = Re Tr[e_a Q (K - K^+)/8] for a colour matrix K per site
  * and plane (kt_add), whose leaf derivatives leaf_force_add takes. */
 static void clover_force_add(const int L[4], double kappa, const cplx *U, const clover_t *cl, const cplx *Xe,
-                             double pf_scale, double det_scale, double *F) {
+                             const cplx *Ye_given, double pf_scale, double det_scale, double *F) {
     long V = lat_volume(L), Vh = V / 2;
     gamma_init();
     cplx sg[6][4][4];
@@ -1091,7 +1093,8 @@ static void clover_force_add(const int L[4], double kappa, const cplx *U, const 
     if (pf_scale != 0.0 && Xe) {
         cplx *ye = malloc(sizeof(cplx) * 12 * Vh);
         cplx *X = malloc(sizeof(cplx) * 12 * V), *Y = malloc(sizeof(cplx) * 12 * V);
-        mhat_cl(L, kappa, U, cl, Xe, ye, 0);
+        if (Ye_given) memcpy(ye, Ye_given, sizeof(cplx) * 12 * Vh);
+        else mhat_cl(L, kappa, U, cl, Xe, ye, 0);
         full_xy(L, U, Xe, ye, X, Y);
         for (long i = 0; i < V; i++)
             if (lat_parity(L, i) == 1) {
@@ -1131,7 +1134,7 @@ void oracle_clover_force_add(const int L[4], double kappa, double csw, const cpl
                              double pf_scale, double det_scale, double *F) {
     clover_t cl;
     clover_build(L, kappa, csw, U, &cl, NULL);
-    clover_force_add(L, kappa, U, &cl, Xe, pf_scale, det_scale, F);
+    clover_force_add(L, kappa, U, &cl, Xe, NULL, pf_scale, det_scale, F);
     clover_free(&cl);
 }
 
@@ -1638,7 +1641,7 @@ static void total_force_from(const int L[4], const oracle_action *act, const cpl
     /* the force on the links the fermions see; with smearing it is carried
      * back to the thin ones */
     double *Ff = Us ? calloc(4 * V * 8, sizeof(double)) : F;
-    if (clp) clover_force_add(L, act->kappa, Uf, clp, X, 1.0, 1.0, Ff);
+    if (clp) clover_force_add(L, act->kappa, Uf, clp, X, NULL, 1.0, 1.0, Ff);
     else oracle_fermion_force_add(L, act->kappa, Uf, X, 1.0, Ff);
     if (Us) {
         double *G = malloc(sizeof(double) * 4 * V * 8);
@@ -1905,18 +1908,37 @@ static void terms_force(nested_run *r, const cplx *W, int terms, double *F, int 
     double *Ff = Ws ? calloc(4 * V * 8, sizeof(double)) : F;
     if (terms & TERM_FERM) {
         double k1 = r->kappa2 != 0.0 ? r->kappa2 : r->kappa;
-        if (r->csw != 0.0) {   /* S_F and -2 log det A_oo */
+        if (r->csw != 0.0) {   /* S_F (S_1 at kappa2) and -2 log det A_oo at kappa */
             clover_t cl;
             clover_build(L, k1, r->csw, Wf, &cl, NULL);
             count_solve(r, cg_cl(L, k1, Wf, &cl, r->phi1, r->X1, r->tol, r->maxiter, NULL, from_last));
-            clover_force_add(L, k1, Wf, &cl, r->X1, 1.0, 1.0, Ff);
+            clover_force_add(L, k1, Wf, &cl, r->X1, NULL, 1.0, k1 == r->kappa ? 1.0 : 0.0, Ff);
             clover_free(&cl);
+            if (k1 != r->kappa) {
+                clover_build(L, r->kappa, r->csw, Wf, &cl, NULL);
+                clover_force_add(L, r->kappa, Wf, &cl, NULL, NULL, 0.0, 1.0, Ff);
+                clover_free(&cl);
+            }
         } else {
             count_solve(r, oracle_cg_from(L, k1, Wf, r->phi1, r->X1, r->tol, r->maxiter, NULL, from_last));
             oracle_fermion_force_add(L, k1, Wf, r->X1, 1.0, Ff);
         }
     }
-    if ((terms & TERM_HASEN) && r->kappa2 != 0.0) {
+    if ((terms & TERM_HASEN) && r->kappa2 != 0.0 && r->csw != 0.0) {
+        /* S_2 = chi^+ (Mhat^+ Mhat)^-1 chi, chi = Mhat2^+ phi2 (clover at kappa2):
+         * the ordinary force of X2 at kappa, plus +2 Re[phi2^+ (e_a Mhat2) X2]
+         * from chi, i.e. the bilinear (X2, phi2) of Mhat2 at scale -1 */
+        clover_t c1l, c2l;
+        clover_build(L, r->kappa, r->csw, Wf, &c1l, NULL);
+        clover_build(L, r->kappa2, r->csw, Wf, &c2l, NULL);
+        cplx *chi = malloc(sizeof(cplx) * 12 * Vh);
+        mhat_cl(L, r->kappa2, Wf, &c2l, r->phi2, chi, 1);
+        count_solve(r, cg_cl(L, r->kappa, Wf, &c1l, chi, r->X2, r->tol, r->maxiter, NULL, from_last));
+        clover_force_add(L, r->kappa, Wf, &c1l, r->X2, NULL, 1.0, 0.0, Ff);
+        clover_force_add(L, r->kappa2, Wf, &c2l, r->X2, r->phi2, -1.0, 0.0, Ff);
+        free(chi);
+        clover_free(&c1l); clover_free(&c2l);
+    } else if ((terms & TERM_HASEN) && r->kappa2 != 0.0) {
         int it;
         hasen_action_from(L, r->kappa, r->kappa2, Wf, r->phi2, r->tol, r->maxiter, r->X2, &it, from_last);
         count_solve(r, it);
@@ -2000,7 +2022,7 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
                              cplx *U, double *P, const cplx *eta1, const cplx *eta2, double *dH, long *stats3,
                              int fg_start, double c1, double stout_rho, int stout_n, int fg_exact, double csw) {
     if (fg_exact && kappa != 0.0 && stout_n > 0) return -2;
-    if (kappa != 0.0 && csw != 0.0 && (fg_exact || kappa2 != 0.0)) return -2;
+    if (kappa != 0.0 && csw != 0.0 && fg_exact) return -2;
     long V = lat_volume(L), Vh = V / 2;
     const char *kp[8];
     const double *wp[8], *xp[8];
@@ -2028,19 +2050,34 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
         const cplx *Uf = Us ? Us : U;
         phi1 = malloc(sizeof(cplx) * 12 * Vh);
         if (csw != 0.0) {
-            clover_t cl;
+            /* phi1 = Mhat^+ eta1 (Mhat2 with Hasenbusch); -2 log det A_oo at kappa */
+            clover_t cl, c2l;
             double *ld = malloc(sizeof(double) * V);
             clover_build(L, kappa, csw, Uf, &cl, ld);
-            mhat_cl(L, kappa, Uf, &cl, eta1, phi1, 1);
             for (long i = 0; i < V; i++)
                 if (lat_parity(L, i) == 1) sf0 += -2.0 * ld[i];
+            if (kappa2 != 0.0) {
+                /* phi2 = Mhat2 (Mhat2^+ Mhat2)^-1 Mhat^+ eta2 */
+                clover_build(L, kappa2, csw, Uf, &c2l, NULL);
+                mhat_cl(L, kappa2, Uf, &c2l, eta1, phi1, 1);
+                phi2 = malloc(sizeof(cplx) * 12 * Vh);
+                cplx *a = malloc(sizeof(cplx) * 12 * Vh), *x = malloc(sizeof(cplx) * 12 * Vh);
+                mhat_cl(L, kappa, Uf, &cl, eta2, a, 1);
+                count_solve(&r, cg_cl(L, kappa2, Uf, &c2l, a, x, cg_tol, cg_maxiter, NULL, 0));
+                mhat_cl(L, kappa2, Uf, &c2l, x, phi2, 0);
+                sf0 += vdot_re(12 * Vh, eta2, eta2);
+                free(a); free(x);
+                clover_free(&c2l);
+            } else {
+                mhat_cl(L, kappa, Uf, &cl, eta1, phi1, 1);
+            }
             clover_free(&cl);
             free(ld);
         } else {
             oracle_pf_heatbath(L, kappa2 != 0.0 ? kappa2 : kappa, Uf, eta1, phi1);
         }
         sf0 += vdot_re(12 * Vh, eta1, eta1);
-        if (kappa2 != 0.0) {
+        if (kappa2 != 0.0 && csw == 0.0) {
             phi2 = malloc(sizeof(cplx) * 12 * Vh);
             count_solve(&r, oracle_hasen_heatbath(L, kappa, kappa2, Uf, eta2, phi2, cg_tol, cg_maxiter));
             sf0 += vdot_re(12 * Vh, eta2, eta2);
@@ -2061,23 +2098,37 @@ int oracle_trajectory_nested(const int L[4], double beta, double kappa, double k
         double s1;
         if (csw != 0.0) {
             double *ld = malloc(sizeof(double) * V);
-            clover_t cl;
+            clover_t cl, c2l;
             clover_build(L, kappa, csw, Uf, &cl, ld);
+            const double k1 = kappa2 != 0.0 ? kappa2 : kappa;
+            if (kappa2 != 0.0) clover_build(L, kappa2, csw, Uf, &c2l, NULL);
+            const clover_t *c1p = kappa2 != 0.0 ? &c2l : &cl;
             cplx *X = malloc(sizeof(cplx) * 12 * Vh);
             double *hd = malloc(sizeof(double) * Vh);
-            it = cg_cl(L, kappa, Uf, &cl, phi1, X, cg_tol, cg_maxiter, NULL, 0);
+            it = cg_cl(L, k1, Uf, c1p, phi1, X, cg_tol, cg_maxiter, NULL, 0);
             pf_density(Vh, phi1, X, hd);
             s1 = 0.0;
             for (long k = 0; k < Vh; k++) s1 += hd[k];
             for (long i = 0; i < V; i++)
                 if (lat_parity(L, i) == 1) s1 += -2.0 * ld[i];
+            if (kappa2 != 0.0) {
+                /* S_2 = chi^+ (Mhat^+ Mhat)^-1 chi, chi = Mhat2^+ phi2 */
+                count_solve(&r, it);
+                cplx *chi = malloc(sizeof(cplx) * 12 * Vh);
+                mhat_cl(L, kappa2, Uf, &c2l, phi2, chi, 1);
+                it = cg_cl(L, kappa, Uf, &cl, chi, X, cg_tol, cg_maxiter, NULL, 0);
+                pf_density(Vh, chi, X, hd);
+                for (long k = 0; k < Vh; k++) s1 += hd[k];
+                free(chi);
+                clover_free(&c2l);
+            }
             clover_free(&cl);
             free(ld); free(X); free(hd);
         } else {
             s1 = oracle_pf_action(L, kappa2 != 0.0 ? kappa2 : kappa, Uf, phi1, cg_tol, cg_maxiter, &it);
         }
         count_solve(&r, it);
-        if (kappa2 != 0.0) {
+        if (kappa2 != 0.0 && csw == 0.0) {
             s1 += oracle_hasen_action(L, kappa, kappa2, Uf, phi2, cg_tol, cg_maxiter, NULL, &it);
             count_solve(&r, it);
         }

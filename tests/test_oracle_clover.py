@@ -338,3 +338,29 @@ def test_brackets_with_clover(orc):
     assert abs(sst - np.sum(F * F)) < 1e-10 * sst
     sst0, _ = orc.brackets(dims, 5.6, U0, P0, kappa=K, phi=phi)
     assert abs(sst - sst0) > 1e-3 * sst
+
+
+def test_hasenbusch_with_clover(orc):
+    """the Hasenbusch split of the clover determinant, det M = det A_oo(kappa)
+    det Mhat2 det(Mhat2^-1 Mhat), on three scales (S_2 outside, S_1 and the log
+    det in the middle, S_G inside): at tau = 0 the heatbath energies return
+    exactly (S_1 = |eta1|^2, S_2 = |eta2|^2 to the solver tolerance), dH falls
+    at fourth order in FG and the trajectory reverses"""
+    dims = (4, 4, 2, 2)
+    U0, P0, eta1, _ = synth.hot_start(dims, synth.SEED_BASE + 615)
+    eta2 = synth.gaussian_noise(synth.rng(synth.SEED_BASE + 616), dims)
+    K2 = 0.13
+    levels = [(table("FG"), 4, 1), (table("FG"), 2, 2), (table("FG"), 1, 2)]
+    args = dict(kappa=K, kappa2=K2, eta1=eta1, eta2=eta2, csw=CSW)
+    _, _, d0, _, status = orc.trajectory_nested(dims, 5.6, levels, 0.0, 1, U0, P0, **args)
+    assert status == 0 and abs(d0) < 1e-10
+    dh = []
+    for n in (8, 16):
+        U1, P1, d, st, status = orc.trajectory_nested(dims, 5.6, levels, 1.0, n, U0, P0, **args)
+        assert status == 0
+        dh.append(d)
+    assert abs(np.log2(abs(dh[0] / dh[1])) - 4) < 0.5, dh
+    # without the split the same field and noise give another dH (the split changes the action terms' noise)
+    _, _, dnh, _, _ = orc.trajectory_nested(dims, 5.6, [(table("FG"), 3, 1)], 1.0, 16, U0, P0, kappa=K, eta1=eta1,
+                                            csw=CSW)
+    assert abs(dnh - dh[1]) > 1e-6
