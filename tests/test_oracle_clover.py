@@ -321,9 +321,7 @@ def test_nested_driver_with_clover(orc):
         assert status == 0
         dh.append(d)
     assert abs(np.log2(abs(dh[0] / dh[1])) - 4) < 0.5, dh
-    # refused: the Hasenbusch split and the exact form with the clover term
-    assert orc.trajectory_nested(dims, 5.6, levels, 1.0, 2, U0, P0, kappa=K, kappa2=0.14, eta1=eta, eta2=eta,
-                                 csw=CSW)[4] == -2
+    # refused: the exact form with the clover term
     assert orc.trajectory_nested(dims, 5.6, levels, 1.0, 2, U0, P0, kappa=K, eta1=eta, csw=CSW,
                                  fg_exact=True)[4] == -2
 
