@@ -116,8 +116,11 @@ typedef struct {
                            kappa^2 D_eo A_oo^-1 D_oe and the action gains
                            -2 sum_{x odd} log det A(x).  0 = Wilson; in [0, 10],
                            else FGI_EINVAL.  With kappa != 0 it needs prec =
-                           FGI_FP64 and no Hasenbusch split (FGI_EINVAL); not
-                           with fg_exact or for batched chains (FGI_EINVAL).
+                           FGI_FP64 (FGI_EINVAL); with the Hasenbusch split
+                           S_1 and S_2 use the clover operators at kappa' and
+                           kappa and the log det is taken at kappa, on the
+                           S_1 scale; not with fg_exact or for batched chains
+                           (FGI_EINVAL).
                            fgi_mhat, fgi_pf_heatbath, fgi_cg_solve,
                            fgi_pf_action (S_F only), fgi_fermion_force (the S_F
                            force only), fgi_force (with the log det force),

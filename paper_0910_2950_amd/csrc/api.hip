@@ -119,7 +119,6 @@ void check_action(const fgi_action* a) {
     if (!(a->csw >= 0.0 && a->csw <= 10.0)) throw Error(FGI_EINVAL, "csw must be in [0, 10]");
     if (a->csw != 0.0 && a->kappa != 0.0) {
         if (a->prec != FGI_FP64) throw Error(FGI_EINVAL, "the clover operator is FP64 only");
-        if (a->kappa_hasen != 0.0) throw Error(FGI_EINVAL, "the clover operator has no Hasenbusch split");
     }
 }
 
@@ -172,8 +171,10 @@ struct Fields {
     // the clover term of the links u is built into c.cl_blk by every clover
     // solve, so the force that follows a solve finds A_ee, A_oo^-1 of its links
     bool clover() const { return act.csw != 0.0 && act.kappa != 0.0; }
-    d2* clover_at(const d2* u, double kappa, double* det = nullptr) {
-        d2* blk = (d2*)c.cl_blk.get(sizeof(d2) * 72 * (size_t)g.V);
+    // slot 0 is the solves' buffer; slot 1 holds a second kappa's blocks
+    // (the Hasenbusch kappa2 operator, or the log det at kappa) meanwhile
+    d2* clover_at(const d2* u, double kappa, double* det = nullptr, int slot = 0) {
+        d2* blk = (d2*)(slot ? c.cl_blk2 : c.cl_blk).get(sizeof(d2) * 72 * (size_t)g.V);
         clover_build(c, g, kappa, act.csw, u, blk, 1, det);
         return blk;
     }
@@ -237,19 +238,31 @@ struct Fields {
         const double k1 = act.kappa_hasen != 0.0 ? act.kappa_hasen : act.kappa;
         if (terms & FGI_TERM_FERMION) {
             solve(fl.u, fl.us, k1, phi[0], X, guess, true);
-            if (clover())   // S_F and the -2 log det A_oo term
+            if (clover()) {   // S_F (S_1 at kappa2) and the -2 log det A_oo term at kappa
+                const bool split = act.kappa_hasen != 0.0;
                 clover_force(c, op64(fl.u, k1), act.csw, (const d2*)c.cl_blk.get(sizeof(d2) * 72 * (size_t)g.V), X,
-                             fo, fc, 1.0, 1.0);
-            else
+                             fo, fc, 1.0, split ? 0.0 : 1.0);
+                if (split)
+                    clover_force(c, op64(fl.u, act.kappa), act.csw, clover_at(fl.u, act.kappa, nullptr, 1), nullptr,
+                                 fo, fc, 0.0, 1.0);
+            } else
                 fermion_force(c, op64(fl.u, k1), X, fo, fc);
         }
         if ((terms & FGI_TERM_HASEN) && act.kappa_hasen != 0.0) {
             // S_2 = chi^+ (Mhat^+ Mhat)^-1 chi, chi = Mhat2^+ phi2: the ordinary force
             // of X2 at kappa plus -kappa2^2 TA(U C(X2, phi2)) from the U dependence of chi
             hasen_solve(fl.u, fl.us, guess, true);
-            fermion_force(c, op64(fl.u, act.kappa), X2, fo, fc);
-            fermion_force_xy(c, op64(fl.u, act.kappa_hasen), X2, phi[1], fo,
-                             -fc * act.kappa_hasen * act.kappa_hasen);
+            if (clover()) {
+                // hasen_solve left A(kappa) in slot 0 and A(kappa2) in slot 1
+                clover_force(c, op64(fl.u, act.kappa), act.csw, (const d2*)c.cl_blk.get(sizeof(d2) * 72 * (size_t)g.V),
+                             X2, fo, fc, 1.0, 0.0);
+                clover_force(c, op64(fl.u, act.kappa_hasen), act.csw,
+                             (const d2*)c.cl_blk2.get(sizeof(d2) * 72 * (size_t)g.V), X2, fo, fc, -1.0, 0.0, phi[1]);
+            } else {
+                fermion_force(c, op64(fl.u, act.kappa), X2, fo, fc);
+                fermion_force_xy(c, op64(fl.u, act.kappa_hasen), X2, phi[1], fo,
+                                 -fc * act.kappa_hasen * act.kappa_hasen);
+            }
         }
         if (smear)
             stout_backprop(c, g, act.stout_rho, act.stout_n, u, (const d2*)c.stout_lev.get(gauge_bytes(g) * act.stout_n),
@@ -300,8 +313,11 @@ struct Fields {
     // chi = Mhat2^+ phi2 at u; X2 = (Mhat^+ Mhat)^-1 chi
     void hasen_solve(const d2* u, const void* us, bool guess = false, bool md = false) {
         d2* t = (d2*)c.tmp_o.get(spinor_bytes(g));
-        mhat(c, op64(u, act.kappa_hasen), P64, SpinorPtr{phi[1], nullptr}, SpinorPtr{t, nullptr},
-             SpinorPtr{chi, nullptr}, 1);
+        if (clover())
+            clover_mhat(c, op64(u, act.kappa_hasen), clover_at(u, act.kappa_hasen, nullptr, 1), phi[1], chi, 1);
+        else
+            mhat(c, op64(u, act.kappa_hasen), P64, SpinorPtr{phi[1], nullptr}, SpinorPtr{t, nullptr},
+                 SpinorPtr{chi, nullptr}, 1);
         solve(u, us, act.kappa, chi, X2, guess, md);
     }
 
@@ -312,6 +328,13 @@ struct Fields {
         const d2* u = fl.u;
         const void* us = fl.us;
         d2* t = (d2*)c.tmp_o.get(spinor_bytes(g));
+        if (clover()) {
+            clover_mhat(c, op64(u, act.kappa), clover_at(u, act.kappa, nullptr, 1), eta2, chi, 1);
+            solve(u, us, act.kappa_hasen, chi, X2);   // leaves A(kappa2) in slot 0
+            clover_mhat(c, op64(u, act.kappa_hasen), (const d2*)c.cl_blk.get(sizeof(d2) * 72 * (size_t)g.V), X2,
+                        phi[1], 0);
+            return;
+        }
         mhat(c, op64(u, act.kappa), P64, SpinorPtr{(void*)eta2, nullptr}, SpinorPtr{t, nullptr},
              SpinorPtr{chi, nullptr}, 1);
         solve(u, us, act.kappa_hasen, chi, X2);
@@ -331,9 +354,9 @@ struct Fields {
         int nb = pf_density_partials(c, g, phi[0], X, eta1, part);
         final_sum(c, part, nb, scal + 4);
         double e = sync_scalar(c, scal + 4, 4);
-        if (clover()) {   // -2 sum_{x odd} log det A(x) is part of H
+        if (clover()) {   // -2 sum_{x odd} log det A(x) at kappa is part of H
             double det = 0.0;
-            clover_at(u, k1, &det);
+            clover_at(u, act.kappa, &det, 1);
             e += det;
         }
         if (act.kappa_hasen != 0.0) {
@@ -387,7 +410,7 @@ int fgi_destroy(fgi_ctx* ctx) {
                           &c.gauge_tan, &c.tg_dmx, &c.tg_rhs, &c.tg_z, &c.tg_dxo, &c.tg_dye, &c.tg_dyo,
                           &c.force3, &c.chain_U, &c.stout_lev, &c.stout_F, &c.stout_ga, &c.stout_gb,
                           &c.stout_part, &c.stout_M, &c.stout_sloppy, &c.hs_dchi, &c.hs_xo, &c.hs_yo,
-                          &c.hs_dxo, &c.hs_dyo, &c.hs_zero, &c.hs_t1, &c.cl_sig, &c.cl_blk, &c.cl_fh,
+                          &c.hs_dxo, &c.hs_dyo, &c.hs_zero, &c.hs_t1, &c.cl_sig, &c.cl_blk, &c.cl_blk2, &c.cl_fh,
                           &c.cl_ld, &c.cl_to, &c.cl_te, &c.cl_ue, &c.cl_r, &c.cl_p, &c.cl_ap, &c.cl_t,
                           &c.cl_ye, &c.cl_xo, &c.cl_yo};
         for (DevBuf* b : bufs) b->release();
@@ -1250,10 +1273,13 @@ double trajectory_packed(Fields& f, const fgi_integrator& integ, double tau, int
         if (phi_given) {
             sf0 = f.pf_energy(f.U, f.Us, nullptr, nullptr, part, scal);
         } else if (f.clover()) {
-            // phi = Mhat^+ eta; the start's -2 log det A_oo enters H
+            // phi = Mhat^+ eta (Mhat2 with the Hasenbusch split); the start's
+            // -2 log det A_oo at kappa enters H
             const d2* fu = f.flinks(f.U, f.Us).u;
-            const d2* blk = f.clover_at(fu, k1, &sf0);
+            f.clover_at(fu, f.act.kappa, &sf0, 1);
+            const d2* blk = f.clover_at(fu, k1);
             clover_mhat(c, f.op64(fu, k1), blk, eta, f.phi[0], 1);
+            if (hasen) f.hasen_heatbath(f.U, f.Us, eta_2);
         } else {
             pf_heatbath(c, f.op64(f.flinks(f.U, f.Us).u, k1), eta, f.phi[0]);
             if (hasen) f.hasen_heatbath(f.U, f.Us, eta_2);

@@ -635,6 +635,8 @@ CGResult clover_cg(Ctx& c, const FermionOp& op, const d2* blk, const d2* phi, d2
 // F += coef * (pf_scale F_pf + det_scale F_det) with F_pf the force of
 // phi^+ (Mhat^+ Mhat)^-1 phi given its solution X_e and F_det that of
 // -2 sum_{x odd} log det A(x); blk must hold A_ee and A_oo^-1 of the links of op.
+// With Ye_given, F_pf is the bilinear 2 Re[Y^+ (e_a Mhat) X] of that Y_e (the
+// chi-dependent part of the Hasenbusch ratio term takes it at scale -1).
 // With Y_e = Mhat X_e, X_o = A_oo^-1 D_oe X_e, Y_o = A_oo^-1 g5 D_oe g5 Y_e the
 // hopping part is the Wilson bilinear of (X, Y) at kappa^2; the clover parts
 // go through Kt (k_clover_kt) and the leaf derivatives (k_clover_force):
@@ -642,7 +644,7 @@ CGResult clover_cg(Ctx& c, const FermionOp& op, const d2* blk, const d2* phi, d2
 //   e_a S_det      = -2 sum_{x odd} Tr[A(x)^-1 e_a A(x)],
 // e_a A = i kappa csw sum sigma (x) e_a Fhat.
 void clover_force(Ctx& c, const FermionOp& op, double csw, const d2* blk, const d2* Xe, double* F, double coef,
-                  double pf_scale, double det_scale) {
+                  double pf_scale, double det_scale, const d2* Ye_given) {
     const Geom& g = *op.g;
     const double k = op.kappa, kc = k * csw;
     const size_t nb = spinor_bytes(g);
@@ -654,7 +656,8 @@ void clover_force(Ctx& c, const FermionOp& op, double csw, const d2* blk, const 
         xo = (d2*)c.cl_xo.get(nb);
         yo = (d2*)c.cl_yo.get(nb);
         d2* te = (d2*)c.cl_t.get(nb);
-        clover_mhat(c, op, blk, Xe, ye, 0);
+        if (Ye_given) ye = (d2*)Ye_given;
+        else clover_mhat(c, op, blk, Xe, ye, 0);
         dslash(c, op, 1, P64, SpinorPtr{(void*)Xe, nullptr}, P64, SpinorPtr{xo, nullptr});
         clover_apply(c, g, blk, 1, xo, nullptr, 0.0, 0, 0, xo);
         spinor_lincomb(c, g, 0.0, ye, 1.0, ye, 1, te);   // te = g5 Y_e

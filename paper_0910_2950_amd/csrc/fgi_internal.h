@@ -104,7 +104,7 @@ struct Ctx {
     DevBuf hs_dchi, hs_xo, hs_yo, hs_dxo, hs_dyo, hs_zero, hs_t1;
     // clover term: blocks (A_ee, A_oo^-1), field strengths / force matrices,
     // log dets, and the vectors of its operator, solver and force
-    DevBuf cl_sig, cl_blk, cl_fh, cl_ld, cl_to, cl_te, cl_ue, cl_r, cl_p, cl_ap, cl_t, cl_ye, cl_xo, cl_yo;
+    DevBuf cl_sig, cl_blk, cl_blk2, cl_fh, cl_ld, cl_to, cl_te, cl_ue, cl_r, cl_p, cl_ap, cl_t, cl_ye, cl_xo, cl_yo;
     DevBuf cdesc, bstate, bscal, bh0, bh1, bres;  // batched chains
     CGState* host_bstates = nullptr;          // pinned [host_b_cap]
     double* host_bscal = nullptr;             // pinned [host_b_cap]
@@ -311,6 +311,6 @@ CGResult clover_cg(Ctx&, const FermionOp& op64, const d2* blk, const d2* phi, d2
                    bool guess);
 // F += coef (pf_scale F_pf(X_e) + det_scale F_det); Xe may be null when pf_scale == 0
 void clover_force(Ctx&, const FermionOp& op64, double csw, const d2* blk, const d2* Xe, double* F, double coef,
-                  double pf_scale, double det_scale);
+                  double pf_scale, double det_scale, const d2* Ye_given = nullptr);
 
 }  // namespace fgi

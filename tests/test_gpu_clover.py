@@ -11,9 +11,11 @@ oracle, through the C ABI (FP64).
     dH to 1e-9 against the oracle, with stout-smeared fermion links and the
     tree-level Symanzik gauge action too; reversibility; an on-device chain
     runs;
-  - csw = 0 leaves the Wilson path bitwise; mixed precision, the Hasenbusch
-    split, the exact G stage and batched chains with the clover term and an
-    out-of-range csw are rejected.
+  - the Hasenbusch split on three scales against the oracle's nested driver,
+    and its heatbath identity at tau = 0;
+  - csw = 0 leaves the Wilson path bitwise; mixed precision, the exact G
+    stage and batched chains with the clover term and an out-of-range csw are
+    rejected.
 """
 import numpy as np
 import pytest
@@ -145,7 +147,6 @@ def test_clover_rejections(ctx):
     dims = (4, 4, 4, 4)
     U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 707)
     bad = [Action(beta=5.6, kappa=K, csw=CSW, prec="mp16", link_recon=12),
-           Action(beta=5.6, kappa=K, kappa_hasen=0.14, csw=CSW),
            Action(beta=5.6, kappa=K, csw=CSW, fg_exact=True),
            Action(beta=5.6, kappa=K, csw=-0.5),
            Action(beta=5.6, kappa=K, csw=float("nan"))]
@@ -191,3 +192,22 @@ def test_clover_nested_scales_and_brackets(ctx, orc):
     sst, tst = ctx.poisson_brackets(dims, act, dev(U0), dev(P0), dev(phi), h=1e-4)
     so, to = orc.brackets(dims, 5.6, U0, P0, kappa=K, phi=phi, h=1e-4, csw=CSW)
     assert abs(sst - so) < 1e-11 * so and abs(tst - to) < 1e-7 * abs(to)
+
+
+def test_clover_hasenbusch_nested(ctx, orc):
+    dims = (4, 4, 2, 2)
+    U0, P0, eta1, _ = synth.hot_start(dims, synth.SEED_BASE + 712)
+    eta2 = synth.gaussian_noise(synth.rng(synth.SEED_BASE + 713), dims)
+    K2 = 0.13
+    levels = [(orc.table("FG"), 4, 1), (orc.table("FG"), 2, 2), (orc.table("FG"), 1, 2)]
+    act = Action(beta=5.6, kappa=K, kappa_hasen=K2, csw=CSW, cg_tol=1e-14)
+    integ = fgi.integrator_from_levels(levels)
+    U, P = dev(U0), dev(P0)
+    d0, _ = ctx.trajectory(dims, act, integ, 0.0, 1, U, P, dev(eta1), dev(eta2))
+    assert abs(d0) < 1e-10
+    U, P = dev(U0), dev(P0)
+    dH, st = ctx.trajectory(dims, act, integ, 1.0, 2, U, P, dev(eta1), dev(eta2))
+    Uo, Po, dHo, sto, status = orc.trajectory_nested(dims, 5.6, levels, 1.0, 2, U0, P0, kappa=K, kappa2=K2,
+                                                     eta1=eta1, eta2=eta2, csw=CSW)
+    assert status == 0 and st["solves"] == sto["solves"]
+    assert relmax(host(U), Uo) < 1e-11 and relmax(host(P), Po) < 1e-11 and abs(dH - dHo) < 1e-9
