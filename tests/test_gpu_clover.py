@@ -211,3 +211,17 @@ def test_clover_hasenbusch_nested(ctx, orc):
                                                      eta1=eta1, eta2=eta2, csw=CSW)
     assert status == 0 and st["solves"] == sto["solves"]
     assert relmax(host(U), Uo) < 1e-11 and relmax(host(P), Po) < 1e-11 and abs(dH - dHo) < 1e-9
+
+
+def test_clover_field_and_log_det_force_at_benchmark_size(ctx, orc):
+    """16^3x32: A(x) on sampled sites, the log det action and its force on
+    every link against the oracle (no solve involved)"""
+    dims = (16, 16, 16, 32)
+    U = links(dims, 714)
+    A, S, F = ctx.clover_field(dims, K, CSW, dev(U))
+    Ao, _, _, So = orc.clover(dims, K, CSW, U)
+    idx = synth.rng(715).choice(synth.volume(dims), 512, replace=False)
+    assert np.max(np.abs(host(A)[idx] - Ao[idx])) < 1e-14
+    assert abs(S - So) < 1e-12 * abs(So)
+    Fo = orc.clover_force(dims, K, CSW, U, None, det_scale=1.0)
+    assert np.max(np.abs(host(F) - Fo)) < 1e-12 * np.max(np.abs(Fo))
