@@ -525,15 +525,16 @@ def clover_leg(R, U_therm, inputs, n, kappa=0.135, csw=1.0, reps=10):
     from the thermalised links with the first timed momenta and noise (FP64
     solves at the timed tolerance), and fgi_mhat with and without the clover
     term (HIP events around reps calls: pack, clover blocks, two hops and the
-    site-local A_ee, A_oo^-1 products)."""
+    site-local A_ee, A_oo^-1 products); the clover trajectory again with the
+    mixed-precision solver (FP32 inner CG, FP64 defect correction)."""
     torch = R.torch
     integ = R.fgi.integrator_builtin("FG", 0.1932)
     U = torch.empty_like(U_therm)
     P = torch.empty_like(inputs[0][0])
     P0, eta = inputs[0]
     out = dict(kappa=kappa, csw=csw, n=n)
-    for key, cc in (("wilson", 0.0), ("clover", csw)):
-        act = R.fgi.Action(beta=R.args.beta, kappa=kappa, csw=cc, cg_tol=R.args.tol, prec="fp64")
+    for key, cc, prec in (("wilson", 0.0, "fp64"), ("clover", csw, "fp64"), ("clover_mp32", csw, "mp32")):
+        act = R.fgi.Action(beta=R.args.beta, kappa=kappa, csw=cc, cg_tol=R.args.tol, prec=prec)
         U.copy_(U_therm)
         P.copy_(P0)
         torch.cuda.synchronize()
@@ -842,6 +843,9 @@ def main():
              clover["clover"]["ms_per_cg_iter"], clover["clover"]["dH"], clover["wilson"]["s_per_traj"],
              clover["wilson"]["cg_iters"], clover["wilson"]["ms_per_cg_iter"], clover["wilson"]["mhat_call_ms"],
              clover["clover"]["mhat_call_ms"]))
+        log("clover FG-mp32 (FP32 inner CG, FP64 defect correction): %.3f s/traj, %d CG iterations (%.3f ms each), "
+            "dH %+.3e" % (clover["clover_mp32"]["s_per_traj"], clover["clover_mp32"]["cg_iters"],
+                          clover["clover_mp32"]["ms_per_cg_iter"], clover["clover_mp32"]["dH"]))
     stout = None
     if args.improved_steps > 0:
         stout = stout_leg(R, U)

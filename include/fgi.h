@@ -115,8 +115,11 @@ typedef struct {
                            the four-leaf clover Q; even-odd Mhat = A_ee -
                            kappa^2 D_eo A_oo^-1 D_oe and the action gains
                            -2 sum_{x odd} log det A(x).  0 = Wilson; in [0, 10],
-                           else FGI_EINVAL.  With kappa != 0 it needs prec =
-                           FGI_FP64 (FGI_EINVAL); with the Hasenbusch split
+                           else FGI_EINVAL.  With kappa != 0 it takes prec =
+                           FGI_FP64, or FGI_MP32 (an FP32 inner CG on the FP32
+                           links with FP64 defect correction; the FP64 true
+                           residual decides, so cg_tol holds as in FP64), not
+                           FGI_MP16 (FGI_EINVAL); with the Hasenbusch split
                            S_1 and S_2 use the clover operators at kappa' and
                            kappa and the log det is taken at kappa, on the
                            S_1 scale; not with fg_exact or for batched chains

@@ -118,7 +118,7 @@ void check_action(const fgi_action* a) {
     if (!(a->stout_rho >= 0.0 && a->stout_rho <= 0.5)) throw Error(FGI_EINVAL, "stout_rho must be in [0, 0.5]");
     if (!(a->csw >= 0.0 && a->csw <= 10.0)) throw Error(FGI_EINVAL, "csw must be in [0, 10]");
     if (a->csw != 0.0 && a->kappa != 0.0) {
-        if (a->prec != FGI_FP64) throw Error(FGI_EINVAL, "the clover operator is FP64 only");
+        if (a->prec == FGI_MP16) throw Error(FGI_EINVAL, "the clover operator takes FGI_FP64 or FGI_MP32");
     }
 }
 
@@ -182,8 +182,14 @@ struct Fields {
     CGResult solve(const d2* u, const void* us, double kappa, const d2* rhs, d2* x, bool guess = false,
                    bool md = false) {
         const double tol = (md && act.cg_tol_md > 0.0) ? act.cg_tol_md : act.cg_tol;
-        CGResult r = clover() ? clover_cg(c, op64(u, kappa), clover_at(u, kappa), rhs, x, tol, act.cg_maxiter, guess)
-                              : cg_solve(c, op64(u, kappa), ops(u, us, kappa), sp, rhs, x, tol, act.cg_maxiter, guess);
+        CGResult r;
+        if (clover() && sp == P32)
+            r = clover_cg_mp(c, op64(u, kappa), ops(u, us, kappa), clover_at(u, kappa), rhs, x, tol, act.cg_maxiter,
+                             guess);
+        else if (clover())
+            r = clover_cg(c, op64(u, kappa), clover_at(u, kappa), rhs, x, tol, act.cg_maxiter, guess);
+        else
+            r = cg_solve(c, op64(u, kappa), ops(u, us, kappa), sp, rhs, x, tol, act.cg_maxiter, guess);
         accumulate_stats(st, r);
         if (!r.converged) nonconv = true;
         return r;
@@ -410,7 +416,8 @@ int fgi_destroy(fgi_ctx* ctx) {
                           &c.gauge_tan, &c.tg_dmx, &c.tg_rhs, &c.tg_z, &c.tg_dxo, &c.tg_dye, &c.tg_dyo,
                           &c.force3, &c.chain_U, &c.stout_lev, &c.stout_F, &c.stout_ga, &c.stout_gb,
                           &c.stout_part, &c.stout_M, &c.stout_sloppy, &c.hs_dchi, &c.hs_xo, &c.hs_yo,
-                          &c.hs_dxo, &c.hs_dyo, &c.hs_zero, &c.hs_t1, &c.cl_sig, &c.cl_blk, &c.cl_blk2, &c.cl_fh,
+                          &c.hs_dxo, &c.hs_dyo, &c.hs_zero, &c.hs_t1, &c.cl_sig, &c.cl_blk, &c.cl_blk2,
+                          &c.cl_blk32, &c.cl_s32, &c.cl_fh,
                           &c.cl_ld, &c.cl_to, &c.cl_te, &c.cl_ue, &c.cl_r, &c.cl_p, &c.cl_ap, &c.cl_t,
                           &c.cl_ye, &c.cl_xo, &c.cl_yo};
         for (DevBuf* b : bufs) b->release();

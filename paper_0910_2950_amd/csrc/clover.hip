@@ -504,6 +504,115 @@ __global__ void __launch_bounds__(CBS) k_cl_p(int Vh, const double* __restrict__
     }
 }
 
+// ---- FP32 inner solver of the mixed-precision clover CG.  FP32 spinors are
+// [6][Vh] float4 (component k in the x,y or z,w half of float4 k / 2), the
+// blocks [72][V] float2 in the FP64 blocks' order.
+__global__ void __launch_bounds__(CBS) k_blk_to_f32(size_t n, const d2* __restrict__ a, f2* __restrict__ b) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) b[t] = f2{(float)a[t].x, (float)a[t].y};
+}
+
+__device__ __forceinline__ cx<float> ld32(const float* __restrict__ v, int Vh, int s, int k) {
+    const size_t o = 4 * ((size_t)(k >> 1) * Vh + s) + 2 * (k & 1);
+    return {v[o], v[o + 1]};
+}
+__device__ __forceinline__ void st32(float* __restrict__ v, int Vh, int s, int k, cx<float> z) {
+    const size_t o = 4 * ((size_t)(k >> 1) * Vh + s) + 2 * (k & 1);
+    v[o] = z.re;
+    v[o + 1] = z.im;
+}
+
+// out = g5^go (A (g5^gi in) - k2 u), FP32 storage and arithmetic
+__global__ void __launch_bounds__(CBS) k_clover_apply32(int Vh, int V, int poff, const f2* __restrict__ blk,
+                                                        const float* in, const float* __restrict__ u, float k2,
+                                                        int gi, int go, float* out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= Vh) return;
+    const size_t site = (size_t)poff + s;
+    cx<float> v[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const cx<float> w = ld32(in, Vh, s, k);
+        v[k] = (gi && k >= 6) ? cx<float>{-w.re, -w.im} : w;
+    }
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+        for (int r = 0; r < 6; r++) {
+            cx<float> acc = {0.0f, 0.0f};
+#pragma unroll
+            for (int c = 0; c < 6; c++) {
+                const f2 e = blk[(size_t)(b * 36 + r * 6 + c) * V + site];
+                acc = acc + cx<float>{e.x, e.y} * v[b * 6 + c];
+            }
+            const int k = b * 6 + r;
+            if (u) acc = acc - k2 * ld32(u, Vh, s, k);
+            if (go && k >= 6) acc = -acc;
+            st32(out, Vh, s, k, acc);
+        }
+}
+
+// partial[b] = sum over the block of Re <a, b> (FP32 vectors, FP64 sums)
+__global__ void __launch_bounds__(CBS) k_dot32(int Vh, const float* __restrict__ a, const float* __restrict__ b,
+                                               double* __restrict__ part) {
+    __shared__ double sh[CBS];
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (s < Vh)
+#pragma unroll
+        for (int k = 0; k < 24; k++) {
+            const size_t o = (size_t)(k >> 2) * Vh * 4 + 4 * (size_t)s + (k & 3);
+            acc += (double)a[o] * (double)b[o];
+        }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = CBS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// x += alpha p, r -= alpha A p (FP32); partial[b] = block sum of |r|^2
+__global__ void __launch_bounds__(CBS) k_cl_xr32(int Vh, const double* __restrict__ st, const float* __restrict__ p,
+                                                 const float* __restrict__ ap, float* __restrict__ x,
+                                                 float* __restrict__ r, double* __restrict__ part) {
+    __shared__ double sh[CBS];
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (s < Vh) {
+        const float a = (float)st[1];
+#pragma unroll
+        for (int k = 0; k < 24; k++) {
+            const size_t o = (size_t)(k >> 2) * Vh * 4 + 4 * (size_t)s + (k & 3);
+            x[o] += a * p[o];
+            const float rv = r[o] - a * ap[o];
+            r[o] = rv;
+            acc += (double)rv * (double)rv;
+        }
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = CBS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// p = r + beta p (FP32)
+__global__ void __launch_bounds__(CBS) k_cl_p32(int Vh, const double* __restrict__ st, const float* __restrict__ r,
+                                                float* __restrict__ p) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= Vh) return;
+    const float b = (float)st[2];
+#pragma unroll
+    for (int k = 0; k < 24; k++) {
+        const size_t o = (size_t)(k >> 2) * Vh * 4 + 4 * (size_t)s + (k & 3);
+        p[o] = r[o] + b * p[o];
+    }
+}
+
 }  // namespace
 
 void clover_build(Ctx& c, const Geom& g, double kappa, double csw, const d2* U, d2* blk, int invert_odd,
@@ -625,6 +734,109 @@ CGResult clover_cg(Ctx& c, const FermionOp& op, const d2* blk, const d2* phi, d2
             FGI_HIP(hipMemcpyAsync(p, r, nb, hipMemcpyDeviceToDevice, c.stream));
             res.reliable_updates++;
         }
+    }
+    res.iters = it;
+    res.converged = conv ? 1 : 0;
+    res.rel_resid = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+    return res;
+}
+
+// Mixed precision: defect correction around an FP32 CG.  Each outer step forms
+// the FP64 true residual r = phi - A x, solves A e = r in FP32 (FP32 links of
+// op32, FP32 blocks, device scalars, |r32|^2 read every CL_BATCH iterations)
+// until its residual has dropped by CL_INNER or below what the outer target
+// needs, and adds e to x in FP64.  The FP64 true residual decides convergence,
+// so the solution meets tol exactly as the FP64 solver's does.
+constexpr double CL_INNER = 1e-5;
+
+CGResult clover_cg_mp(Ctx& c, const FermionOp& op, const FermionOp& op32, const d2* blk, const d2* phi, d2* x,
+                      double tol, int maxiter, bool guess) {
+    const Geom& g = *op.g;
+    const size_t nb = spinor_bytes(g), nb32 = nb / 2;
+    d2* r = (d2*)c.cl_r.get(nb);
+    d2* ap = (d2*)c.cl_ap.get(nb);
+    d2* t = (d2*)c.cl_t.get(nb);
+    f2* blk32 = (f2*)c.cl_blk32.get(sizeof(f2) * 72 * (size_t)g.V);
+    float* s32 = (float*)c.cl_s32.get(nb32 * 7);
+    float *r32 = s32, *p32 = s32 + nb32 / 4, *q32 = s32 + 2 * (nb32 / 4), *e32 = s32 + 3 * (nb32 / 4);
+    float *t32 = s32 + 4 * (nb32 / 4), *to32 = s32 + 5 * (nb32 / 4), *ue32 = s32 + 6 * (nb32 / 4);
+    double* part = partial_buf(c, g);
+    double* part2 = part + nb_of(g.Vh) + 64;
+    double* scal = (double*)c.scal.get(sizeof(double) * 64);
+    double* st = scal + 56;
+    const int nbv = nb_of(g.Vh);
+    {
+        const size_t n = 72 * (size_t)g.V;
+        hipLaunchKernelGGL(k_blk_to_f32, dim3((unsigned)((n + CBS - 1) / CBS)), dim3(CBS), 0, c.stream, n, blk, blk32);
+        FGI_LAUNCH_CHECK();
+    }
+    const float k2 = (float)(op.kappa * op.kappa);
+    auto mhat32 = [&](float* in, float* out, int dagger) {
+        if (dagger) hop_oe_g5_p32(c, op32, in, to32);
+        else dslash(c, op32, 1, P32, SpinorPtr{in, nullptr}, P32, SpinorPtr{to32, nullptr});
+        hipLaunchKernelGGL(k_clover_apply32, dim3(nbv), dim3(CBS), 0, c.stream, g.Vh, g.V, g.Vh,
+                           (const f2*)blk32, (const float*)to32, (const float*)nullptr, 0.0f, 0, 0, to32);
+        dslash(c, op32, 0, P32, SpinorPtr{to32, nullptr}, P32, SpinorPtr{ue32, nullptr});
+        hipLaunchKernelGGL(k_clover_apply32, dim3(nbv), dim3(CBS), 0, c.stream, g.Vh, g.V, 0, (const f2*)blk32,
+                           (const float*)in, (const float*)ue32, k2, dagger, dagger, out);
+        FGI_LAUNCH_CHECK();
+    };
+    auto normal64 = [&](const d2* in, d2* out) {
+        clover_mhat(c, op, blk, in, t, 0);
+        clover_mhat(c, op, blk, t, out, 1);
+    };
+    auto dot32 = [&](const float* a, const float* b, int mode) {
+        hipLaunchKernelGGL(k_dot32, dim3(nbv), dim3(CBS), 0, c.stream, g.Vh, a, b, part);
+        hipLaunchKernelGGL(k_cl_scalar, dim3(1), dim3(CBS), 0, c.stream, (const double*)part, nbv, mode, st);
+        FGI_LAUNCH_CHECK();
+    };
+    CGResult res{};
+    const double bb = dot_re(c, g, phi, phi, 49);
+    const double target = tol * tol * bb;
+    if (!guess) spinor_lincomb(c, g, 0.0, phi, 0.0, phi, 0, x);
+    int it = 0;
+    bool conv = bb == 0.0;
+    double rr = bb;
+    while (!conv) {
+        normal64(x, ap);
+        spinor_lincomb(c, g, 1.0, phi, -1.0, ap, 0, r);
+        rr = dot_re(c, g, r, r, 50);
+        if (rr <= target) {
+            conv = true;
+            break;
+        }
+        if (it >= maxiter) break;
+        if (it > 0) res.reliable_updates++;
+        // inner FP32 solve of A e = r from e = 0
+        convert_spinor(c, g, P64, SpinorPtr{r, nullptr}, P32, SpinorPtr{r32, nullptr});
+        FGI_HIP(hipMemcpyAsync(p32, r32, nb32, hipMemcpyDeviceToDevice, c.stream));
+        FGI_HIP(hipMemsetAsync(e32, 0, nb32, c.stream));
+        dot32(r32, r32, 0);
+        const double rr0 = host_scalar(c, st, 56);
+        const double inner = std::max(CL_INNER * CL_INNER * rr0, 0.25 * target);
+        double rri = rr0;
+        const int before = it;
+        while (rri > inner && it < maxiter) {
+            const int nbatch = std::min(CL_BATCH, maxiter - it);
+            for (int k = 0; k < nbatch; k++) {
+                mhat32(p32, t32, 0);
+                mhat32(t32, q32, 1);
+                dot32(p32, q32, 1);
+                hipLaunchKernelGGL(k_cl_xr32, dim3(nbv), dim3(CBS), 0, c.stream, g.Vh, (const double*)st,
+                                   (const float*)p32, (const float*)q32, e32, r32, part2);
+                hipLaunchKernelGGL(k_cl_scalar, dim3(1), dim3(CBS), 0, c.stream, (const double*)part2, nbv, 2, st);
+                hipLaunchKernelGGL(k_cl_p32, dim3(nbv), dim3(CBS), 0, c.stream, g.Vh, (const double*)st,
+                                   (const float*)r32, p32);
+                FGI_LAUNCH_CHECK();
+            }
+            it += nbatch;
+            rri = host_scalar(c, st, 56);
+            if (!(rri == rri)) break;   // not a number: the outer residual decides
+        }
+        if (it == before) break;   // no FP32 progress possible: report the FP64 residual
+        // x += e
+        convert_spinor(c, g, P32, SpinorPtr{e32, nullptr}, P64, SpinorPtr{ap, nullptr});
+        spinor_lincomb(c, g, 1.0, x, 1.0, ap, 0, x);
     }
     res.iters = it;
     res.converged = conv ? 1 : 0;

@@ -946,6 +946,14 @@ void fermion_force_xyo(Ctx& c, const FermionOp& op64, const d2* Xe, const d2* Xo
 // out_o = D_oe g5 in_e (FP64): the first hop of Mhat^+ = g5 Mhat g5
 void hop_oe_g5(Ctx& c, const FermionOp& op64, const d2* in_e, d2* out_o) { hop_g5(c, op64, in_e, out_o, 0); }
 
+// the same with FP32 spinors on FP32 links
+void hop_oe_g5_p32(Ctx& c, const FermionOp& op32, void* in_e, void* out_o) {
+    DArgs a = base_args(op32, 1);
+    a.in = sp(in_e);
+    a.out = sp(out_o);
+    launch_dslash<M_HOP, P32, P32, P32, P32, 1>(c, op32, a);
+}
+
 // ---------------------------------------------------------------- CG ------
 static double norm2_sync(Ctx& c, const Geom& g, const d2* v) {
     double* part = partial_buf(c, g);

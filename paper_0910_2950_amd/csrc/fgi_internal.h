@@ -104,7 +104,7 @@ struct Ctx {
     DevBuf hs_dchi, hs_xo, hs_yo, hs_dxo, hs_dyo, hs_zero, hs_t1;
     // clover term: blocks (A_ee, A_oo^-1), field strengths / force matrices,
     // log dets, and the vectors of its operator, solver and force
-    DevBuf cl_sig, cl_blk, cl_blk2, cl_fh, cl_ld, cl_to, cl_te, cl_ue, cl_r, cl_p, cl_ap, cl_t, cl_ye, cl_xo, cl_yo;
+    DevBuf cl_sig, cl_blk, cl_blk2, cl_blk32, cl_s32, cl_fh, cl_ld, cl_to, cl_te, cl_ue, cl_r, cl_p, cl_ap, cl_t, cl_ye, cl_xo, cl_yo;
     DevBuf cdesc, bstate, bscal, bh0, bh1, bres;  // batched chains
     CGState* host_bstates = nullptr;          // pinned [host_b_cap]
     double* host_bscal = nullptr;             // pinned [host_b_cap]
@@ -279,6 +279,7 @@ void fermion_force_xyo(Ctx&, const FermionOp& op64, const d2* Xe, const d2* Xo, 
                        double* F, double coef);
 // out_o = D_oe g5 in_e (FP64)
 void hop_oe_g5(Ctx&, const FermionOp& op64, const d2* in_e, d2* out_o);
+void hop_oe_g5_p32(Ctx&, const FermionOp& op32, void* in_e, void* out_o);
 //   J += coef * J_V[F_F] given Z = A^-1 rhs (after fermion_tangent_rhs on the same X_e)
 void fermion_force_tangent(Ctx&, const FermionOp& op64, const FermionOp& opW, const double* Vd, const d2* Xe,
                            const d2* Z, double* J, double coef);
@@ -309,6 +310,10 @@ void clover_unpack(Ctx&, const Geom&, const d2* blk, void* out);
 void clover_mhat(Ctx&, const FermionOp& op64, const d2* blk, const d2* in_e, d2* out_e, int dagger);
 CGResult clover_cg(Ctx&, const FermionOp& op64, const d2* blk, const d2* phi, d2* x, double tol, int maxiter,
                    bool guess);
+// the same solve with an FP32 inner CG on the FP32 links of ops (defect
+// correction: the FP64 true residual decides convergence)
+CGResult clover_cg_mp(Ctx&, const FermionOp& op64, const FermionOp& op32, const d2* blk, const d2* phi, d2* x,
+                      double tol, int maxiter, bool guess);
 // F += coef (pf_scale F_pf(X_e) + det_scale F_det); Xe may be null when pf_scale == 0
 void clover_force(Ctx&, const FermionOp& op64, double csw, const d2* blk, const d2* Xe, double* F, double coef,
                   double pf_scale, double det_scale, const d2* Ye_given = nullptr);

@@ -225,3 +225,22 @@ def test_clover_field_and_log_det_force_at_benchmark_size(ctx, orc):
     assert abs(S - So) < 1e-12 * abs(So)
     Fo = orc.clover_force(dims, K, CSW, U, None, det_scale=1.0)
     assert np.max(np.abs(host(F) - Fo)) < 1e-12 * np.max(np.abs(Fo))
+
+
+def test_clover_mixed_precision(ctx, orc):
+    """FP32 inner CG with FP64 defect correction: the solution meets the FP64
+    tolerance, and trajectories agree with the oracle to the solver tolerance"""
+    dims = (6, 4, 4, 6)
+    U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 716)
+    phi = orc.clover_mhat(dims, K, CSW, U0, eta, dagger=True)
+    for recon in (18, 12):
+        act = Action(beta=5.6, kappa=K, csw=CSW, cg_tol=1e-12, prec="mp32", link_recon=recon)
+        X, st = ctx.cg_solve(dims, act, dev(U0), dev(phi))
+        Xo, _ = orc.clover_cg(dims, K, CSW, U0, phi, tol=1e-14)
+        assert relmax(host(X), Xo) < 1e-9 and st["max_rel_resid"] <= 1e-12
+    act = Action(beta=5.6, kappa=K, csw=CSW, cg_tol=1e-12, prec="mp32", link_recon=12)
+    U, P = dev(U0), dev(P0)
+    dH, st = ctx.trajectory(dims, act, "FG", 1.0, 3, U, P, dev(eta))
+    Uo, Po, dHo, sto, status = orc.trajectory(dims, 5.6, orc.table("FG"), 1.0, 3, U0, P0, kappa=K, eta=eta, csw=CSW)
+    assert status == 0 and st["solves"] == sto["solves"]
+    assert relmax(host(U), Uo) < 1e-8 and relmax(host(P), Po) < 1e-8 and abs(dH - dHo) < 1e-6
