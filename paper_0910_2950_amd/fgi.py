@@ -185,7 +185,7 @@ class Action:
     stout_rho: float = 0.0
     stout_n: int = 0     # stout levels of the links the fermion operator sees (0: thin links)
     cg_tol_md: float = 0.0   # tolerance of the solves inside force evaluations (0: cg_tol)
-    csw: float = 0.0     # clover coefficient of the fermion matrix (0: Wilson; FP64 only)
+    csw: float = 0.0     # clover coefficient of the fermion matrix (0: Wilson; prec fp64 or mp32)
 
     def c(self):
         return fgi_action(self.beta, self.kappa, self.kappa_hasen, self.cg_tol, int(self.cg_maxiter),
