@@ -307,9 +307,12 @@ int fgi_fermion_force(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, co
  *          pairs {0,1} and {2,3});
  *   S_det  host double: -2 sum_{x odd} log det A(x);
  *   F_det  [4][V][8] real: the force -e_a S_det on every link.
- * kappa csw < 1/6 keeps A(x) positive definite for any links (log det is
- * taken of the pivots' moduli).  FGI_EINVAL for a non-finite kappa or csw
- * outside [0, 10].  Synchronises the stream. */
+ * kappa csw < 1/6 keeps A(x) positive definite for any links; above it a
+ * block may be indefinite, and since the Nf = 2 weight is det(A)^2 the term
+ * is -2 sum log |det A(x)|, taken from the moduli of the pivots of a
+ * partially pivoted elimination (a singular block gives NaN, reported as
+ * FGI_ENONFINITE by the calls that sum or solve with it).  FGI_EINVAL for a
+ * non-finite kappa or csw outside [0, 10].  Synchronises the stream. */
 int fgi_clover_field(fgi_ctx* ctx, const fgi_geom* g, double kappa, double csw, const void* U, void* A,
                      double* S_det, void* F_det, void* stream);
 

@@ -133,11 +133,16 @@ __global__ void __launch_bounds__(CBS) k_clover_fhat(Geom g, const d2* __restric
 }
 
 // One 6x6 block of A(x) per thread: b = thread / V, site = thread % V.
-// A = 1 + i kc sum_q sigma_q^b (x) Fhat_q.  log det from Gauss-Jordan
-// elimination without pivoting (A is Hermitian and, for kappa csw < 1/6,
-// positive definite: the pivots are the positive diagonal of its LDL^+
-// factorisation).  Writes A, or A^-1 at odd sites when invert_odd; ld[b V +
-// site] = log det of the block at odd sites, 0 at even ones.
+// A = 1 + i kc sum_q sigma_q^b (x) Fhat_q.  Inverse and log |det| by
+// Gauss-Jordan elimination with partial pivoting: A is Hermitian, positive
+// definite for kappa csw < 1/6 on any field but possibly indefinite above,
+// so the pivot row of column k is the row >= k of largest modulus; the
+// interchanges are undone on the columns of the inverse in reverse order.
+// The Nf = 2 weight is det(A)^2, so log |det| = sum log |pivot| enters the
+// action.  A zero pivot (a singular block) leaves NaN in the block's log det
+// and inverse, which the solver and the energy sum report as non-finite.
+// Writes A, or A^-1 at odd sites when invert_odd; ld[b V + site] = log |det|
+// of the block at odd sites, 0 at even ones.
 __global__ void __launch_bounds__(CBS) k_clover_blocks(Geom g, const double* __restrict__ sig, double kc, const d2* __restrict__ fh,
                                                        d2* __restrict__ blk, double* __restrict__ ld, int invert_odd) {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -177,12 +182,36 @@ __global__ void __launch_bounds__(CBS) k_clover_blocks(Geom g, const double* __r
         for (int r = 0; r < 6; r++)
 #pragma unroll
             for (int c = 0; c < 6; c++) m[r][c] = a[r][c];
-        // in-place Gauss-Jordan inversion
+        // in-place Gauss-Jordan inversion with partial pivoting; row
+        // interchanges are predicated selects over the unrolled rows, so the
+        // block stays in registers
+        int perm[6];
 #pragma unroll
         for (int k = 0; k < 6; k++) {
+            int p = k;
+            double best = m[k][k].re * m[k][k].re + m[k][k].im * m[k][k].im;
+#pragma unroll
+            for (int i = k + 1; i < 6; i++) {
+                const double v = m[i][k].re * m[i][k].re + m[i][k].im * m[i][k].im;
+                if (v > best) {
+                    best = v;
+                    p = i;
+                }
+            }
+            perm[k] = p;
+#pragma unroll
+            for (int i = k + 1; i < 6; i++) {
+                const bool sw = i == p;
+#pragma unroll
+                for (int j = 0; j < 6; j++) {
+                    const cx<double> rk = m[k][j], ri = m[i][j];
+                    m[k][j] = sw ? ri : rk;
+                    m[i][j] = sw ? rk : ri;
+                }
+            }
             const cx<double> piv = m[k][k];
-            logdet += 0.5 * log(piv.re * piv.re + piv.im * piv.im);
             const double den = piv.re * piv.re + piv.im * piv.im;
+            logdet += den > 0.0 ? 0.5 * log(den) : __builtin_nan("");
             const cx<double> inv = {piv.re / den, -piv.im / den};
             m[k][k] = {1.0, 0.0};
 #pragma unroll
@@ -196,6 +225,19 @@ __global__ void __launch_bounds__(CBS) k_clover_blocks(Geom g, const double* __r
                 for (int j = 0; j < 6; j++) m[i][j] = m[i][j] - fct * m[k][j];
             }
         }
+        // undo the interchanges on the columns, last first
+#pragma unroll
+        for (int k = 5; k >= 0; k--)
+#pragma unroll
+            for (int j = k + 1; j < 6; j++) {
+                const bool sw = perm[k] == j;
+#pragma unroll
+                for (int i = 0; i < 6; i++) {
+                    const cx<double> ck = m[i][k], cj = m[i][j];
+                    m[i][k] = sw ? cj : ck;
+                    m[i][j] = sw ? ck : cj;
+                }
+            }
         if (invert_odd) {
 #pragma unroll
             for (int r = 0; r < 6; r++)
@@ -816,7 +858,8 @@ CGResult clover_cg_mp(Ctx& c, const FermionOp& op, const FermionOp& op32, const 
         const double inner = std::max(CL_INNER * CL_INNER * rr0, 0.25 * target);
         double rri = rr0;
         const int before = it;
-        while (rri > inner && it < maxiter) {
+        bool inner_finite = std::isfinite(rr0);
+        while (inner_finite && rri > inner && it < maxiter) {
             const int nbatch = std::min(CL_BATCH, maxiter - it);
             for (int k = 0; k < nbatch; k++) {
                 mhat32(p32, t32, 0);
@@ -831,7 +874,18 @@ CGResult clover_cg_mp(Ctx& c, const FermionOp& op, const FermionOp& op32, const 
             }
             it += nbatch;
             rri = host_scalar(c, st, 56);
-            if (!(rri == rri)) break;   // not a number: the outer residual decides
+            inner_finite = std::isfinite(rri);
+        }
+        if (!inner_finite) {
+            // the FP32 residual is not finite (the recursion broke down, or the
+            // residual does not fit FP32): its correction is discarded and the
+            // FP64 solver continues from the current x
+            const CGResult r64 = clover_cg(c, op, blk, phi, x, tol, std::max(maxiter - it, 0), true);
+            res.iters = it + r64.iters;
+            res.converged = r64.converged;
+            res.rel_resid = r64.rel_resid;
+            res.reliable_updates += r64.reliable_updates + 1;
+            return res;
         }
         if (it == before) break;   // no FP32 progress possible: report the FP64 residual
         // x += e

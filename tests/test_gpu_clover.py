@@ -13,9 +13,13 @@ oracle, through the C ABI (FP64).
     runs;
   - the Hasenbusch split on three scales against the oracle's nested driver,
     and its heatbath identity at tau = 0;
-  - csw = 0 leaves the Wilson path bitwise; mixed precision, the exact G
-    stage and batched chains with the clover term and an out-of-range csw are
-    rejected.
+  - csw = 0 leaves the Wilson path bitwise; MP16, the exact G stage and
+    batched chains with the clover term and an out-of-range csw are rejected;
+  - kappa csw = 0.65, where some blocks of A(x) are indefinite: A, the log
+    det action and force, and Mhat (through A_oo^-1) against the oracle;
+  - the MP32 solver (FP32 inner CG, FP64 defect correction) with smearing
+    and the Hasenbusch split at the solver-tolerance gates, and its FP64
+    fallback when the FP32 residual is not finite.
 """
 import numpy as np
 import pytest
@@ -107,16 +111,22 @@ def test_clover_trajectory(ctx, orc, name):
     assert relmax(host(U), Uo) < 1e-11 and relmax(host(P), Po) < 1e-11 and abs(dH - dHo) < 1e-9
 
 
-def test_clover_with_smearing_and_symanzik(ctx, orc):
+# FP64 solves at 1e-14 hold the 1e-11 / 1e-9 gates; the MP32 solver (FP32
+# inner CG, FP64 defect correction at 1e-12) holds the solver-tolerance gates
+PREC_GATES = [("fp64", 1e-14, 1e-11, 1e-9), ("mp32", 1e-12, 1e-8, 1e-6)]
+
+
+@pytest.mark.parametrize("prec,tol,gate_up,gate_dh", PREC_GATES)
+def test_clover_with_smearing_and_symanzik(ctx, orc, prec, tol, gate_up, gate_dh):
     dims = (4, 2, 2, 4)
     U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 704)
-    act = Action(beta=5.6, kappa=K, csw=CSW, cg_tol=1e-14, stout_rho=0.1, stout_n=2, c1=-1 / 12)
+    act = Action(beta=5.6, kappa=K, csw=CSW, cg_tol=tol, stout_rho=0.1, stout_n=2, c1=-1 / 12, prec=prec)
     U, P = dev(U0), dev(P0)
     dH, _ = ctx.trajectory(dims, act, "FG", 1.0, 2, U, P, dev(eta))
     Uo, Po, dHo, _, status = orc.trajectory(dims, 5.6, orc.table("FG"), 1.0, 2, U0, P0, kappa=K, eta=eta,
                                             csw=CSW, stout_rho=0.1, stout_n=2, c1=-1 / 12)
     assert status == 0
-    assert relmax(host(U), Uo) < 1e-11 and relmax(host(P), Po) < 1e-11 and abs(dH - dHo) < 1e-9
+    assert relmax(host(U), Uo) < gate_up and relmax(host(P), Po) < gate_up and abs(dH - dHo) < gate_dh
 
 
 def test_clover_reversible_from_phi(ctx, orc):
@@ -194,23 +204,24 @@ def test_clover_nested_scales_and_brackets(ctx, orc):
     assert abs(sst - so) < 1e-11 * so and abs(tst - to) < 1e-7 * abs(to)
 
 
-def test_clover_hasenbusch_nested(ctx, orc):
+@pytest.mark.parametrize("prec,tol,gate_up,gate_dh", PREC_GATES)
+def test_clover_hasenbusch_nested(ctx, orc, prec, tol, gate_up, gate_dh):
     dims = (4, 4, 2, 2)
     U0, P0, eta1, _ = synth.hot_start(dims, synth.SEED_BASE + 712)
     eta2 = synth.gaussian_noise(synth.rng(synth.SEED_BASE + 713), dims)
     K2 = 0.13
     levels = [(orc.table("FG"), 4, 1), (orc.table("FG"), 2, 2), (orc.table("FG"), 1, 2)]
-    act = Action(beta=5.6, kappa=K, kappa_hasen=K2, csw=CSW, cg_tol=1e-14)
+    act = Action(beta=5.6, kappa=K, kappa_hasen=K2, csw=CSW, cg_tol=tol, prec=prec)
     integ = fgi.integrator_from_levels(levels)
     U, P = dev(U0), dev(P0)
     d0, _ = ctx.trajectory(dims, act, integ, 0.0, 1, U, P, dev(eta1), dev(eta2))
-    assert abs(d0) < 1e-10
+    assert abs(d0) < 1e-10 if prec == "fp64" else abs(d0) < gate_dh
     U, P = dev(U0), dev(P0)
     dH, st = ctx.trajectory(dims, act, integ, 1.0, 2, U, P, dev(eta1), dev(eta2))
     Uo, Po, dHo, sto, status = orc.trajectory_nested(dims, 5.6, levels, 1.0, 2, U0, P0, kappa=K, kappa2=K2,
                                                      eta1=eta1, eta2=eta2, csw=CSW)
     assert status == 0 and st["solves"] == sto["solves"]
-    assert relmax(host(U), Uo) < 1e-11 and relmax(host(P), Po) < 1e-11 and abs(dH - dHo) < 1e-9
+    assert relmax(host(U), Uo) < gate_up and relmax(host(P), Po) < gate_up and abs(dH - dHo) < gate_dh
 
 
 def test_clover_field_and_log_det_force_at_benchmark_size(ctx, orc):
@@ -244,3 +255,44 @@ def test_clover_mixed_precision(ctx, orc):
     Uo, Po, dHo, sto, status = orc.trajectory(dims, 5.6, orc.table("FG"), 1.0, 3, U0, P0, kappa=K, eta=eta, csw=CSW)
     assert status == 0 and st["solves"] == sto["solves"]
     assert relmax(host(U), Uo) < 1e-8 and relmax(host(P), Po) < 1e-8 and abs(dH - dHo) < 1e-6
+
+
+# kappa csw = 0.65: on a hot start about one site in six has a clover block
+# with a negative determinant (A(x) Hermitian but indefinite), the regime where
+# the block inversion needs its pivoting
+K_IND, CSW_IND = 0.13, 5.0
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 4, 6)])
+def test_clover_indefinite_blocks(ctx, orc, dims):
+    U = links(dims, 720)
+    Ao, _, _, So = orc.clover(dims, K_IND, CSW_IND, U)
+    B = Ao.reshape(-1, 12, 12)
+    neg = (np.linalg.slogdet(B[:, :6, :6])[0].real < 0).sum() + (np.linalg.slogdet(B[:, 6:, 6:])[0].real < 0).sum()
+    assert neg > 0   # the regime is exercised
+    A, S, F = ctx.clover_field(dims, K_IND, CSW_IND, dev(U))
+    assert np.max(np.abs(host(A) - Ao)) < 1e-14
+    assert abs(S - So) < 1e-11 * max(1.0, abs(So))
+    Fo = orc.clover_force(dims, K_IND, CSW_IND, U, None, det_scale=1.0)
+    assert relmax(host(F), Fo) < 1e-11
+    _, _, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 721)
+    act = Action(beta=5.6, kappa=K_IND, csw=CSW_IND)
+    for dag in (False, True):   # Mhat uses A_oo^-1
+        out = host(ctx.mhat(dims, act, dev(U), dev(eta), dagger=dag))
+        assert relmax(out, orc.clover_mhat(dims, K_IND, CSW_IND, U, eta, dagger=dag)) < 1e-11
+
+
+def test_clover_mixed_precision_falls_back_when_fp32_overflows(ctx, orc):
+    """A right-hand side beyond the FP32 range (|phi| ~ 1e39 per component)
+    makes the FP32 inner residual infinite on the first defect-correction step;
+    the MP32 solver then discards the FP32 correction and finishes in FP64
+    from the current solution, meeting cg_tol."""
+    dims = (4, 4, 4, 4)
+    U0, _, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 722)
+    phi = orc.clover_mhat(dims, K, CSW, U0, eta, dagger=True)
+    scale = 1e39
+    act = Action(beta=5.6, kappa=K, csw=CSW, cg_tol=1e-12, prec="mp32", link_recon=18)
+    X, st = ctx.cg_solve(dims, act, dev(U0), dev(phi * scale))
+    Xo, _ = orc.clover_cg(dims, K, CSW, U0, phi, tol=1e-14)
+    assert np.all(np.isfinite(host(X)))
+    assert relmax(host(X) / scale, Xo) < 1e-9 and st["max_rel_resid"] <= 1e-12
