@@ -2170,6 +2170,84 @@ void oracle_brackets(const int L[4], double beta, double kappa, int fermions, do
     free(F); free(Ud);
 }
 
+/* The four dt^4 brackets of Table 1 that are not identically zero, at
+ * (U, P), for the total force (gauge action with rectangle coefficient c1,
+ * plus Wilson pseudofermions when fermions != 0), in the paper's nesting:
+ *   STSST = {{S,T},{S,{S,T}}},   STTST = {{S,T},{T,{S,T}}},
+ *   TTSST = {T,{T,{S,{S,T}}}},   TTTST = {T,{T,{T,{S,T}}}}.
+ * With the flows of the integrator's steps as derivations -- L_T W =
+ * d/dt W(exp(tP) U, P) (the T-hat flow) and L_S W = d/ds W(U, P + s F(U))
+ * (the S-hat flow) -- one has {T, W} = -L_T W, {S, W} = -L_S W, and by the
+ * Jacobi identity {{S,T}, W} = L_S L_T W - L_T L_S W.  With
+ * J_V = J_V[F] = d/dt F(exp(tV) U) (the exact force gradient) and D_b G =
+ * d/dt G(exp(tb) U), every term reduces to force gradients at U and one
+ * derivative of J_P along P or along F:
+ *   STSST = L_S L_T |F|^2             = 2 <F, J_F>
+ *   STTST = [L_S, L_T] <P, J_P>       = <P, D_F J_P> - |J_P|^2 - <P, J_{J_P}>
+ *   TTSST = L_T^2 |F|^2               = 2 |J_P|^2 + 2 <F, D_P J_P>
+ *   TTTST = L_T^3 <P, F>              = d^2/dt^2 <P, J_P(exp(tP) U)>
+ * (<P, F> = -{S,T}; TST = L_T <P, F> = <P, J_P>; in flat space with
+ * J_V = -Hess(S) V these are the familiar -2 g.H.g, K[g,P,P] - 2|HP|^2,
+ * 2 K[P,P,g] + 2|HP|^2 and -L[P,P,P,P]).  D_F J_P, D_P J_P and the second
+ * derivative are central differences with step h (J_P at exp(+-hP) U and
+ * exp(+-hF) U).  Also returns SST = |F|^2 and TST = <P, J_P> (exact here).
+ * out = {SST, TST, STSST, STTST, TTSST, TTTST}; returns 0, or -3 when a
+ * solve hit maxiter. */
+static double dotn(const double *a, const double *b, long n) {
+    double s = 0;
+    for (long k = 0; k < n; k++) s += a[k] * b[k];
+    return s;
+}
+
+int oracle_brackets4(const int L[4], double beta, double kappa, int fermions, double cg_tol, int cg_maxiter,
+                     const cplx *U, const double *P, const cplx *phi, double h, double c1, double *out) {
+    long V = lat_volume(L), Vh = V / 2, n = 4 * V * 8, nu = 4 * V * 9;
+    oracle_action act = {beta, kappa, cg_tol, cg_maxiter, fermions, 1, c1, 0.0, 0, 0.0};
+    oracle_stats st = {0, 0, 0};
+    double *F = malloc(sizeof(double) * n), *Fd = malloc(sizeof(double) * n);
+    double *JP = malloc(sizeof(double) * n), *JF = malloc(sizeof(double) * n);
+    double *JJ = malloc(sizeof(double) * n), *Jd = malloc(sizeof(double) * n);
+    cplx *X = fermions ? malloc(sizeof(cplx) * 12 * Vh) : NULL;
+    cplx *Xd = fermions ? malloc(sizeof(cplx) * 12 * Vh) : NULL;
+    cplx *Ud = malloc(sizeof(cplx) * nu);
+    /* at U: F, J_P, J_F, J_{J_P} */
+    total_force_x(L, &act, U, phi, F, &st, X);
+    total_force_tangent(L, &act, U, X, P, JP, &st);
+    total_force_tangent(L, &act, U, X, F, JF, &st);
+    total_force_tangent(L, &act, U, X, JP, JJ, &st);
+    double sst = dotn(F, F, n), tst = dotn(P, JP, n), jpjp = dotn(JP, JP, n);
+    /* J_P at exp(+-hP) U: D_P J_P and <P, J_P(exp(tP) U)> at t = +-h */
+    double fp_p = 0, fp_m = 0, kp = 0, km = 0;
+    for (int sgn = 1; sgn >= -1; sgn -= 2) {
+        memcpy(Ud, U, sizeof(cplx) * nu);
+        oracle_link_update(L, sgn * h, P, Ud);
+        total_force_x(L, &act, Ud, phi, Fd, &st, Xd);
+        total_force_tangent(L, &act, Ud, Xd, P, Jd, &st);
+        if (sgn > 0) { fp_p = dotn(F, Jd, n); kp = dotn(P, Jd, n); }
+        else { fp_m = dotn(F, Jd, n); km = dotn(P, Jd, n); }
+    }
+    /* J_P at exp(+-hF) U: D_F J_P */
+    double pf_p = 0, pf_m = 0;
+    for (int sgn = 1; sgn >= -1; sgn -= 2) {
+        memcpy(Ud, U, sizeof(cplx) * nu);
+        oracle_link_update(L, sgn * h, F, Ud);
+        total_force_x(L, &act, Ud, phi, Fd, &st, Xd);
+        total_force_tangent(L, &act, Ud, Xd, P, Jd, &st);
+        if (sgn > 0) pf_p = dotn(P, Jd, n);
+        else pf_m = dotn(P, Jd, n);
+    }
+    const double F_DP_JP = (fp_p - fp_m) / (2.0 * h);
+    const double P_DF_JP = (pf_p - pf_m) / (2.0 * h);
+    out[0] = sst;
+    out[1] = tst;
+    out[2] = 2.0 * dotn(F, JF, n);
+    out[3] = P_DF_JP - jpjp - dotn(P, JJ, n);
+    out[4] = 2.0 * jpjp + 2.0 * F_DP_JP;
+    out[5] = (kp - 2.0 * tst + km) / (h * h);
+    free(F); free(Fd); free(JP); free(JF); free(JJ); free(Jd); free(X); free(Xd); free(Ud);
+    return st.cg_fail ? -3 : 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Markov chain: counter-based draws and the HMC accept/reject loop    */
 /* ------------------------------------------------------------------ */

@@ -102,6 +102,8 @@ def _declare(L):
                                            _d, _i, _vp, _vp, _vp, _vp, _dp, _lp, _i, _d, _d, _i, _i, _d]
     L.oracle_trajectory_nested.restype = _i
     L.oracle_philox.argtypes = [_vp, _vp, _vp]
+    L.oracle_brackets4.argtypes = [_ip, _d, _d, _i, _d, _i, _vp, _vp, _vp, _d, _d, _vp]
+    L.oracle_brackets4.restype = _i
     L.oracle_refresh.argtypes = [_ip, ctypes.c_uint64, ctypes.c_uint32, _vp, _vp, _vp]
     L.oracle_metropolis_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
     L.oracle_metropolis_uniform.restype = _d
@@ -343,6 +345,23 @@ def brackets(dims, beta, U, P, kappa=0.0, phi=None, h=1e-4, tol=1e-14, maxiter=1
                           _ptr(phi_a) if ferm else None, h, ctypes.byref(sst), ctypes.byref(tst), c1, stout_rho,
                           int(stout_n), csw)
     return sst.value, tst.value
+
+
+def brackets4(dims, beta, U, P, kappa=0.0, phi=None, h=1e-3, tol=1e-14, maxiter=10000, c1=0.0):
+    """The dt^4 brackets of Table 1 at (U, P) (oracle_brackets4): dict with
+    SST, TST and STSST = {{S,T},{S,{S,T}}}, STTST = {{S,T},{T,{S,T}}},
+    TTSST = {T,{T,{S,{S,T}}}}, TTTST = {T,{T,{T,{S,T}}}}; the derivatives of
+    the force gradient along P and F by central differences with step h."""
+    U = _c(U, np.complex128)
+    P = _c(P, np.float64)
+    ferm = phi is not None
+    phi_a = _c(phi, np.complex128) if ferm else None
+    out = np.zeros(6)
+    rc = lib().oracle_brackets4(_dims(dims), beta, kappa, int(ferm), tol, maxiter, _ptr(U), _ptr(P),
+                                _ptr(phi_a) if ferm else None, h, c1, _ptr(out))
+    if rc != 0:
+        raise RuntimeError("oracle_brackets4: a CG solve did not converge")
+    return dict(zip(("SST", "TST", "STSST", "STTST", "TTSST", "TTTST"), out.tolist()))
 
 
 def hasen_heatbath(dims, kappa, kappa2, U, eta2, tol=1e-14, maxiter=10000):
