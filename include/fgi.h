@@ -394,6 +394,26 @@ int fgi_trajectory_packed(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act
                           double tau, int nsteps, void* U, void* P, const void* eta1, const void* eta2, int pf_is_phi,
                           double* dH, fgi_stats* st, void* stream);
 
+/* ------------------------------------------- allocation-free operator */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * Wilson Schur operator of fgi_mhat on packed fields, out = Mhat in
+ * (dagger = 0) or Mhat^+ in (dagger = 1), Mhat = 1 - kappa^2 D_eo D_oe, with
+ * U in the FGI_FIELD_LINKS layout and in, out in the FGI_FIELD_EVEN layout
+ * (fgi_field_pack; all device memory, caller-owned, 16-byte aligned).
+ * Its odd intermediate D_oe in lives in a fixed library-owned device array
+ * of FGI_NOALLOC_MAX_VH odd sites (25.2 MB per GPU, held until the process
+ * ends); the call allocates and frees nothing.  Asynchronous on the stream
+ * (no synchronisation).  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (other streams, threads or contexts) race and must
+ * be ordered by the caller.  Bitwise the result of fgi_mhat on the same
+ * fields and kappa.  FGI_EINVAL, before any launch, when V/2 exceeds
+ * FGI_NOALLOC_MAX_VH (16^3 x 64 is the largest 16^3 x T lattice), kappa is
+ * not finite, a pointer is null or misaligned, or in and out overlap. */
+#define FGI_NOALLOC_MAX_VH 131072
+int fgi_mhat_packed_noalloc(fgi_ctx* ctx, const fgi_geom* g, double kappa, const void* U, const void* in, void* out,
+                            int dagger, void* stream);
+
 /* ------------------------------------------- Markov chain (HMC, Section 2) */
 /* The heatbath draws of trajectory `traj` of the chain with this seed, from
  * the counter-based generator Philox4x32-10 (Salmon, Moraes, Dror and Shaw,

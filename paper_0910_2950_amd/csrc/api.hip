@@ -5,7 +5,9 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/fgi.h"
 #include "fgi_internal.h"
@@ -58,7 +60,32 @@ Geom make_geom(const int dims[4]) {
 
 using namespace fgi;
 
+// Scratch of the allocation-free entry point (fgi_mhat_packed_noalloc): the
+// odd intermediate D_oe in of one Schur application, FGI_NOALLOC_MAX_VH odd
+// FP64 spinors in the internal layout.  Every GPU the library runs on holds
+// its own copy until the process ends.  In host code this name is only a
+// stand-in: kernels and copies take the per-device address from
+// hipGetSymbolAddress (noalloc_scratch_address), never the name itself.
+static __device__ __align__(256) d2 scratch[12 * (size_t)FGI_NOALLOC_MAX_VH];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::vector<d2*> g_scratch_addr;   // per device index; null until looked up
+
+// The device address of `scratch` on `device`, which must be current: looked
+// up once per device, then served from the table.
+d2* noalloc_scratch_address(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_addr.size() <= device) g_scratch_addr.resize(device + 1, nullptr);
+    if (!g_scratch_addr[device]) {
+        void* ptr = nullptr;
+        FGI_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw Error(FGI_EHIP, "hipGetSymbolAddress returned a null address for the scratch array");
+        g_scratch_addr[device] = (d2*)ptr;
+    }
+    return g_scratch_addr[device];
+}
 
 template <typename F>
 int guarded(F&& f) {
@@ -391,8 +418,10 @@ int fgi_create(fgi_ctx** out, int device) {
         FGI_HIP(hipGetDeviceCount(&n));
         if (device < 0 || device >= n) throw Error(FGI_EINVAL, "bad device index");
         FGI_HIP(hipSetDevice(device));
+        d2* scr = noalloc_scratch_address(device);
         fgi_ctx* c = new fgi_ctx();
         c->c.device = device;
+        c->c.noalloc_scratch = scr;
         FGI_HIP(hipHostMalloc((void**)&c->c.host_scal, 64 * sizeof(double), hipHostMallocDefault));
         FGI_HIP(hipHostMalloc((void**)&c->c.host_state, sizeof(CGState), hipHostMallocDefault));
         void* st = c->c.state.get(sizeof(CGState));
@@ -739,6 +768,30 @@ int fgi_mhat(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void
                  dagger ? 1 : 0);
         }
         unpack_even_spinor(c, g, vout, out);
+    });
+}
+
+int fgi_mhat_packed_noalloc(fgi_ctx* ctx, const fgi_geom* gg, double kappa, const void* U, const void* in, void* out,
+                            int dagger, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg) throw Error(FGI_EINVAL, "null geometry");
+        Geom g = make_geom(gg->dims);
+        if (g.Vh > FGI_NOALLOC_MAX_VH)
+            throw Error(FGI_EINVAL, "fgi_mhat_packed_noalloc: V/2 = " + std::to_string(g.Vh) +
+                                        " odd sites exceed the fixed scratch of FGI_NOALLOC_MAX_VH = " +
+                                        std::to_string(FGI_NOALLOC_MAX_VH));
+        if (!std::isfinite(kappa)) throw Error(FGI_EINVAL, "kappa must be finite");
+        need(U, "U", 16);
+        need(in, "in", 16);
+        need(out, "out", 16);
+        const uintptr_t nb = spinor_bytes(g), a0 = (uintptr_t)in, b0 = (uintptr_t)out;
+        if (a0 < b0 + nb && b0 < a0 + nb) throw Error(FGI_EINVAL, "in and out must not overlap");
+        if (!c.noalloc_scratch) throw Error(FGI_EHIP, "the scratch array has no device address");
+        StreamScope ss(c, stream);
+        FermionOp op{&g, kappa, U, P64, 18};
+        mhat(c, op, P64, SpinorPtr{(void*)in, nullptr}, SpinorPtr{c.noalloc_scratch, nullptr}, SpinorPtr{out, nullptr},
+             dagger ? 1 : 0);
     });
 }
 

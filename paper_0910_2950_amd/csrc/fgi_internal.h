@@ -137,6 +137,9 @@ struct Ctx {
     // undisplaced solutions (a deterministic function of the stage's links, so
     // the stage stays reversible); 0 starts them from zero
     int fg_start = 1;
+    // device address of the fixed scratch array of the allocation-free entry
+    // point on this context's device (looked up once per device at fgi_create)
+    d2* noalloc_scratch = nullptr;
 };
 
 // A batch of independent chains: their descriptors on the device and the

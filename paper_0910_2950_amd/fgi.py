@@ -119,6 +119,7 @@ SIGNATURES = {
     "fgi_total_force_gradient": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _vp, _P(fgi_stats), _vp]),
     "fgi_dslash": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _i, _i, _vp]),
     "fgi_mhat": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _i, _vp]),
+    "fgi_mhat_packed_noalloc": (_i, [_vp, _P(fgi_geom), ctypes.c_double, _vp, _vp, _vp, _i, _vp]),
     "fgi_cg_solve": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _P(fgi_stats), _vp]),
     "fgi_pf_heatbath": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _vp]),
     "fgi_pf_action": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _P(_d), _P(fgi_stats), _vp]),
@@ -426,6 +427,19 @@ class Context:
         _check(lib().fgi_mhat(self.h, _geom(dims), ctypes.byref(act.c()), _ptr(U, torch.complex128, su, "U"),
                               _ptr(inp, torch.complex128, se, "in"), _ptr(out, torch.complex128, se, "out"),
                               int(bool(dagger)), _stream()))
+        return out
+
+    def mhat_packed_noalloc(self, dims, kappa, U, inp, out, dagger=False):
+        """fgi_mhat_packed_noalloc: Mhat (or Mhat^+) on packed fields (uint8
+        device buffers from field_pack), writing the caller's out buffer; the
+        library allocates nothing."""
+        nl, ne = self.field_bytes(dims, "links"), self.field_bytes(dims, "even")
+        for t, n, name in ((U, nl, "U"), (inp, ne, "in"), (out, ne, "out")):
+            if t.dtype != torch.uint8 or t.numel() != n or not t.is_contiguous():
+                raise FgiError(FGI_EINVAL, "%s: packed buffer of the wrong size, dtype or stride" % name)
+        _check(lib().fgi_mhat_packed_noalloc(self.h, _geom(dims), float(kappa), ctypes.c_void_p(U.data_ptr()),
+                                             ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                             int(bool(dagger)), _stream()))
         return out
 
     def cg_solve(self, dims, act, U, phi, X=None, allow_noconv=False):
