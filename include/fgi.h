@@ -359,6 +359,24 @@ int fgi_force_terms(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, cons
  * evaluations).  phi may be NULL for pure gauge. */
 int fgi_poisson_brackets(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* P,
                          const void* phi, double h, double* SST, double* TST, fgi_stats* st, void* stream);
+/* The dt^4 Poisson brackets of Table 1 that enter the fourth-order shadow
+ * Hamiltonians (the paper's nesting): out[6] = {SST, TST, STSST, STTST,
+ * TTSST, TTTST} with STSST = {{S,T},{S,{S,T}}}, STTST = {{S,T},{T,{S,T}}},
+ * TTSST = {T,{T,{S,{S,T}}}}, TTTST = {T,{T,{T,{S,T}}}} ({S,{S,{S,{S,T}}}}
+ * and {T,{S,{S,{S,T}}}} vanish for T quadratic in p).  With the T-hat and
+ * S-hat flows as derivations (L_T W = d/dt W(exp(tP) U, P), L_S W = d/ds
+ * W(U, P + s F)), {T, W} = -L_T W, {S, W} = -L_S W and {{S,T}, W} =
+ * [L_S, L_T] W, so with J_V the exact force gradient of the total force
+ * along V and D_b its derivative along exp(t b) U:
+ *   STSST = 2 <F, J_F>,  STTST = <P, D_F J_P> - |J_P|^2 - <P, J_{J_P}>,
+ *   TTSST = 2 |J_P|^2 + 2 <F, D_P J_P>,  TTTST = d^2/dt^2 <P, J_P(exp(tP) U)>,
+ * SST = |F|^2 and TST = <P, J_P>; the derivatives of J_P by central
+ * differences with step h (eight force gradients and five forces in all,
+ * two solves each with fermions).  The total force as in fgi_force (gauge
+ * action with act->c1, Wilson pseudofermions when kappa != 0 and phi given);
+ * not with Hasenbusch, stout or clover terms (FGI_EINVAL).  Synchronises. */
+int fgi_poisson_brackets4(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* P,
+                          const void* phi, double h, double* out, fgi_stats* st, void* stream);
 
 /* ----------------------------------------------- integrators (Table 1) */
 /* Fill a one-level integrator for a Table 1 scheme (alpha used by PQPQP). */

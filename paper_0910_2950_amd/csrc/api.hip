@@ -448,7 +448,7 @@ int fgi_destroy(fgi_ctx* ctx) {
                           &c.hs_dxo, &c.hs_dyo, &c.hs_zero, &c.hs_t1, &c.cl_sig, &c.cl_blk, &c.cl_blk2,
                           &c.cl_blk32, &c.cl_s32, &c.cl_fh,
                           &c.cl_ld, &c.cl_to, &c.cl_te, &c.cl_ue, &c.cl_r, &c.cl_p, &c.cl_ap, &c.cl_t,
-                          &c.cl_ye, &c.cl_xo, &c.cl_yo};
+                          &c.cl_ye, &c.cl_xo, &c.cl_yo, &c.br_jp, &c.br_jf, &c.br_jj};
         for (DevBuf* b : bufs) b->release();
         for (hipEvent_t e : c.ev_pool) hipEventDestroy(e);
         for (GraphEntry& e : c.graphs) hipGraphExecDestroy(e.exec);
@@ -1151,6 +1151,88 @@ int fgi_poisson_brackets(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act
         }
         *SST = sst;
         *TST = (v[0] - v[1]) / (2.0 * h);
+        if (f.nonconv) throw Error(FGI_ENOCONV, "CG reached cg_maxiter");
+    });
+}
+
+int fgi_poisson_brackets4(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* P,
+                          const void* phi, double h, double* out, fgi_stats* st, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        if (!gg || !out) throw Error(FGI_EINVAL, "null argument");
+        check_action(act);
+        if (!(h > 0)) throw Error(FGI_EINVAL, "h must be positive");
+        if (act->kappa_hasen != 0) throw Error(FGI_EINVAL, "the dt^4 brackets take one pseudofermion");
+        Geom g = make_geom(gg->dims);
+        need(U, "U", 16);
+        need(P, "P", 8);
+        const bool ferm = act->kappa != 0 && phi;
+        if (ferm) need(phi, "phi", 16);
+        StreamScope ss(c, stream);
+        fgi_action a = *act;
+        if (!ferm) a.kappa = 0;
+        Fields f(c, g, a);
+        f.st = st;
+        f.U = (d2*)c.gauge.get(gauge_bytes(g));
+        f.Ud = (d2*)c.gauge_disp.get(gauge_bytes(g));
+        pack_gauge(c, g, U, f.U);
+        double* pm = (double*)c.mom.get(mom_bytes(g));
+        pack_mom(c, g, (const double*)P, pm);
+        if (ferm) {
+            f.phi[0] = (d2*)c.phi.get(spinor_bytes(g));
+            pack_even_spinor(c, g, phi, f.phi[0]);
+            f.X = (d2*)c.X.get(spinor_bytes(g));
+            if (f.sp != P64) {
+                f.Us = c.sloppy.get(sloppy_bytes(g));
+                f.Uds = c.sloppy_disp.get(sloppy_bytes(g));
+                make_sloppy(c, g, f.U, f.Us, f.sp, f.rc);
+            }
+        }
+        const size_t mb = mom_bytes(g);
+        double* fm = (double*)c.force.get(mb);    // F(U)
+        double* fd = (double*)c.force2.get(mb);   // F at a moved U (its solve sets X there)
+        double* jd = (double*)c.force3.get(mb);   // J_P at a moved U
+        double* jp = (double*)c.br_jp.get(mb);
+        double* jf = (double*)c.br_jf.get(mb);
+        double* jj = (double*)c.br_jj.get(mb);
+        double* part = partial_buf(c, g);
+        double* scal = (double*)c.scal.get(sizeof(double) * 64);
+        const long nm = 4L * 2 * 8 * g.Vh;
+        auto dot = [&](const double* x, const double* y) {
+            const int nb = dot_partials(c, nm, x, y, part);
+            final_sum(c, part, nb, scal);
+            return sync_scalar(c, scal, 0);
+        };
+        const int terms = FGI_TERM_GAUGE | FGI_TERM_FERMION;
+        // at U: F, J_P, J_F and J_{J_P} (all with X at U)
+        f.force(f.U, f.Us, terms, fm, 1.0, false);
+        f.force_tangent(f.U, f.Us, terms, pm, jp);
+        f.force_tangent(f.U, f.Us, terms, fm, jf);
+        f.force_tangent(f.U, f.Us, terms, jp, jj);
+        const double sst = dot(fm, fm), tst = dot(pm, jp), fjf = dot(fm, jf), jpjp = dot(jp, jp), pjj = dot(pm, jj);
+        // J_P at exp(+-hP) U (<F, .> and <P, .>) and at exp(+-hF) U (<P, .>)
+        double fjd[2], pjd[2], pjf[2];
+        for (int k = 0; k < 2; k++) {
+            const double hh = k == 0 ? h : -h;
+            link_update(c, g, hh, pm, f.U, f.Ud, f.Uds, f.sp, f.rc);
+            f.force(f.Ud, f.Uds, terms, fd, 1.0, false);
+            f.force_tangent(f.Ud, f.Uds, terms, pm, jd);
+            fjd[k] = dot(fm, jd);
+            pjd[k] = dot(pm, jd);
+        }
+        for (int k = 0; k < 2; k++) {
+            const double hh = k == 0 ? h : -h;
+            link_update(c, g, hh, fm, f.U, f.Ud, f.Uds, f.sp, f.rc);
+            f.force(f.Ud, f.Uds, terms, fd, 1.0, false);
+            f.force_tangent(f.Ud, f.Uds, terms, pm, jd);
+            pjf[k] = dot(pm, jd);
+        }
+        out[0] = sst;
+        out[1] = tst;
+        out[2] = 2.0 * fjf;
+        out[3] = (pjf[0] - pjf[1]) / (2.0 * h) - jpjp - pjj;
+        out[4] = 2.0 * jpjp + 2.0 * (fjd[0] - fjd[1]) / (2.0 * h);
+        out[5] = (pjd[0] - 2.0 * tst + pjd[1]) / (h * h);
         if (f.nonconv) throw Error(FGI_ENOCONV, "CG reached cg_maxiter");
     });
 }

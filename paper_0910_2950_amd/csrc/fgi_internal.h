@@ -106,6 +106,7 @@ struct Ctx {
     // log dets, and the vectors of its operator, solver and force
     DevBuf cl_sig, cl_blk, cl_blk2, cl_blk32, cl_s32, cl_fh, cl_ld, cl_to, cl_te, cl_ue, cl_r, cl_p, cl_ap, cl_t, cl_ye, cl_xo, cl_yo;
     DevBuf cdesc, bstate, bscal, bh0, bh1, bres;  // batched chains
+    DevBuf br_jp, br_jf, br_jj;   // force gradients of the dt^4 brackets
     CGState* host_bstates = nullptr;          // pinned [host_b_cap]
     double* host_bscal = nullptr;             // pinned [host_b_cap]
     size_t host_b_cap = 0;

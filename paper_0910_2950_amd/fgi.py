@@ -125,6 +125,8 @@ SIGNATURES = {
     "fgi_pf_action": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _P(_d), _P(fgi_stats), _vp]),
     "fgi_poisson_brackets": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _d, _P(_d), _P(_d),
                                   _P(fgi_stats), _vp]),
+    "fgi_poisson_brackets4": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _d, _P(_d), _P(fgi_stats),
+                                   _vp]),
     "fgi_integrator_builtin": (_i, [_i, _d, _P(fgi_integrator)]),
     "fgi_trajectory": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _P(fgi_integrator), _d, _i, _vp, _vp, _vp, _vp,
                             _i, _P(_d), _P(fgi_stats), _vp]),
@@ -480,6 +482,19 @@ class Context:
                                           _ptr(phi, torch.complex128, se, "phi"), h, ctypes.byref(a),
                                           ctypes.byref(b), ctypes.byref(st), _stream()))
         return a.value, b.value
+
+    BRACKETS4 = ("SST", "TST", "STSST", "STTST", "TTSST", "TTTST")
+
+    def poisson_brackets4(self, dims, act, U, P, phi=None, h=1e-3):
+        """fgi_poisson_brackets4: dict of SST, TST and the four dt^4 brackets of Table 1."""
+        su, sp, se = self._shapes(dims)
+        out = (ctypes.c_double * 6)()
+        st = fgi_stats()
+        _check(lib().fgi_poisson_brackets4(self.h, _geom(dims), ctypes.byref(act.c()),
+                                           _ptr(U, torch.complex128, su, "U"), _ptr(P, torch.float64, sp, "P"),
+                                           _ptr(phi, torch.complex128, se, "phi"), h, out, ctypes.byref(st),
+                                           _stream()))
+        return dict(zip(self.BRACKETS4, list(out)))
 
     # ---- trajectory
     def trajectory(self, dims, act, integ, tau, nsteps, U, P, eta1=None, eta2=None, pf_is_phi=False,

@@ -88,3 +88,26 @@ def test_batch_rejects_mixed_fermion_content(ctx):
     with pytest.raises(fgi.FgiError) as e:
         run_batch(ctx, chains, Action(beta=0.0), "FG", 2)
     assert e.value.code == fgi.FGI_EINVAL
+
+
+def test_batch_repeats_bitwise_with_reliable_updates(ctx):
+    """Regression for the staging of per-chain solver states: a reliable update
+    uploads the states twice in a row (flags set, then cleared) from one pinned
+    buffer, and an upload still queued when the buffer was rewritten used to
+    pick up the second state, so a restarting chain kept a stale residual and
+    ran to cg_maxiter now and then.  Mixed precision at a tight tolerance (many
+    reliable updates), with a short CG batch (more host round trips), repeated:
+    every run converges and all runs agree bitwise."""
+    chains = make_chains(MIX, 0x09102950 + 404)
+    act = Action(beta=0.0, cg_tol=1e-12, cg_maxiter=20000, prec="mp16", link_recon=12)
+    ctx.set_option("cg_batch", 4)
+    try:
+        runs = [run_batch(ctx, chains, act, "FG", 2) for _ in range(4)]
+    finally:
+        ctx.set_option("cg_batch", 8)   # the context's default
+    ref, st0 = runs[0]
+    assert st0["reliable_updates"] > len(chains)
+    for out, st in runs[1:]:
+        assert st["cg_iters"] == st0["cg_iters"]
+        for (U, P, dH), (U0, P0, dH0) in zip(out, ref):
+            assert np.array_equal(U, U0) and np.array_equal(P, P0) and dH == dH0
