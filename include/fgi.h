@@ -77,7 +77,7 @@ typedef struct {
     double cg_tol;      /* CG stop: |phi - A x| <= cg_tol |phi| (true residual) */
     int cg_maxiter;     /* CG iteration cap */
     int prec;           /* FGI_FP64 | FGI_MP32 | FGI_MP16 (CG inner precision) */
-    int link_recon;     /* 18 or 12: storage of the FP32 sloppy links (FP16 uses 12) */
+    int link_recon;     /* 18 or 12: reals stored per sloppy link (FP32 or FP16); 12 keeps rows 0, 1 and rebuilds row 2 */
     int fg_exact;       /* G stages: 0 = displacement form, 1 = exact force gradient
                            (Section 4; every action term, the Hasenbusch ratio
                            term included; not with stout smearing, not for

@@ -150,7 +150,7 @@ void check_action(const fgi_action* a) {
 }
 
 int sloppy_prec(const fgi_action* a) { return a->prec == FGI_FP64 ? P64 : (a->prec == FGI_MP32 ? P32 : P16); }
-int sloppy_recon(const fgi_action* a) { return a->prec == FGI_MP16 ? 12 : a->link_recon; }
+int sloppy_recon(const fgi_action* a) { return a->link_recon; }
 
 void accumulate_stats(fgi_stats* st, const CGResult& r) {
     if (!st) return;

@@ -274,9 +274,7 @@ template <int P> __device__ __forceinline__ SpinorPtr spin_off(SpinorPtr p, cons
 
 template <int PL, int RECON> __device__ __forceinline__ size_t link_byte_off(const ChainDesc& d) {
     if (PL == P64) return 9 * (size_t)d.link0 * sizeof(d2);
-    if (PL == P32 && RECON == 18) return 9 * (size_t)d.link0 * sizeof(f2);
-    if (PL == P32) return 3 * (size_t)d.link0 * sizeof(f4);
-    return 3 * (size_t)d.link0 * sizeof(h4);
+    return (size_t)d.link0 * sloppy_link_bytes(PL, RECON);
 }
 
 // batched launch: every chain of the batch with its own geometry, kappa,
@@ -699,7 +697,7 @@ static SpinorPtr sp(const void* v, float* norm = nullptr) { return SpinorPtr{(vo
 // normally (batches are many small lattices).
 static const double kL2Bytes = 32.0 * (1 << 20);
 static int links_streamed(const FermionOp& op, long nlinks) {
-    const double per = op.prec == P64 ? 144 : (op.prec == P32 ? (op.recon == 18 ? 72 : 48) : 24);
+    const double per = op.prec == P64 ? 144 : (double)sloppy_link_bytes(op.prec, op.recon);
     return per * (double)nlinks > kL2Bytes ? 1 : 0;
 }
 
@@ -721,6 +719,7 @@ static void launch_dslash(Ctx& c, const FermionOp& op, DArgs& a) {
     } else {
         if (op.prec == P32 && op.recon == 18) launch_dslash_nt<MODE, PIN, PC, POUT, PX, P32, 18, G5IN>(c, nt, nb, a);
         else if (op.prec == P32) launch_dslash_nt<MODE, PIN, PC, POUT, PX, P32, 12, G5IN>(c, nt, nb, a);
+        else if (op.prec == P16 && op.recon == 18) launch_dslash_nt<MODE, PIN, PC, POUT, PX, P16, 18, G5IN>(c, nt, nb, a);
         else if (op.prec == P16) launch_dslash_nt<MODE, PIN, PC, POUT, PX, P16, 12, G5IN>(c, nt, nb, a);
         else throw Error(-1, "sloppy spinors need sloppy links");
     }
@@ -1295,6 +1294,9 @@ static void launch_dslash_b(Ctx& c, const Batch& B, const FermionOp& op, DArgs& 
                                a, B.cd, B.nc, nsb);
         else if (op.prec == P32)
             hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P32, 12, G5IN>), dim3(nb), dim3(c.ds_bs), 0, c.stream,
+                               a, B.cd, B.nc, nsb);
+        else if (op.recon == 18)
+            hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P16, 18, G5IN>), dim3(nb), dim3(c.ds_bs), 0, c.stream,
                                a, B.cd, B.nc, nsb);
         else
             hipLaunchKernelGGL((k_dslash_b<MODE, PIN, PC, POUT, PX, P16, 12, G5IN>), dim3(nb), dim3(c.ds_bs), 0, c.stream,

@@ -450,6 +450,7 @@ enum Prec { P64 = 0, P32 = 1, P16 = 2 };
 template <int P> struct Real { typedef float T; };
 template <> struct Real<P64> { typedef double T; };
 
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -593,6 +594,12 @@ template <> struct RawLink<P64, 18> { d2 v[9]; };
 template <> struct RawLink<P32, 18> { f2 v[9]; };
 template <> struct RawLink<P32, 12> { f4 v[3]; };
 template <> struct RawLink<P16, 12> { h4 v[3]; };
+// FP16 / 18: per (mu, p) a block of 36 Vh bytes holding two half8 arrays
+// (entries 0-3 and 4-7 of the row-major matrix) and one half2 array (entry 8)
+template <> struct RawLink<P16, 18> { h8 v[2]; h2 w; };
+__device__ __forceinline__ const h8* link16x18_block(const void* base, int mu, int p, int Vh) {
+    return (const h8*)((const char*)base + (size_t)((mu * 2 + p) * 36) * Vh);
+}
 
 // nt: non-temporal loads, for link fields larger than the L2 caches together
 // (each link is read once per launch; streaming them keeps the L2 for the
@@ -604,6 +611,20 @@ __device__ __forceinline__ void fetch_link(const void* base, int mu, int p, int 
     constexpr int N = RECON == 18 ? 9 : 3;
     typedef decltype(r.v[0]) T0;
     typedef typename std::remove_reference<T0>::type T;
+    if constexpr (P == P16 && RECON == 18) {
+        const h8* b = link16x18_block(base, mu, p, Vh);
+        const h2* w = (const h2*)(b + 2 * (size_t)Vh);
+        if constexpr (NT) {
+            r.v[0] = __builtin_nontemporal_load(b + s);
+            r.v[1] = __builtin_nontemporal_load(b + Vh + s);
+            r.w = __builtin_nontemporal_load(w + s);
+        } else {
+            r.v[0] = b[s];
+            r.v[1] = b[Vh + s];
+            r.w = w[s];
+        }
+        return;
+    }
     const T* b = (const T*)base + (size_t)((mu * 2 + p) * N) * Vh + s;
     if constexpr (NT) {
 #pragma unroll
@@ -712,6 +733,64 @@ template <typename R> struct LinkIO<P16, 12, R> {
         return u;
     }
 };
+
+template <typename R> struct LinkIO<P16, 18, R> {
+    static __device__ __forceinline__ M3<R> decode(const RawLink<P16, 18>& r) {
+        M3<R> u;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            u.e[k / 3][k % 3] = {R(float(r.v[0][2 * k])), R(float(r.v[0][2 * k + 1]))};
+            u.e[(k + 4) / 3][(k + 4) % 3] = {R(float(r.v[1][2 * k])), R(float(r.v[1][2 * k + 1]))};
+        }
+        u.e[2][2] = {R(float(r.w.x)), R(float(r.w.y))};
+        return u;
+    }
+    static __device__ __forceinline__ M3<R> load(const void* base, int mu, int p, int s, int Vh) {
+        RawLink<P16, 18> r;
+        fetch_link<P16, 18, false>(base, mu, p, s, Vh, r);
+        return decode(r);
+    }
+};
+
+// A link written to a sloppy copy in storage (prec, recon): row-major
+// entries e[0..8] in FP64; r = mu * 2 + p selects the (direction, parity) part.
+__device__ __forceinline__ void store_sloppy_link(void* out, int prec, int recon, int r, int s, int Vh,
+                                                  const cx<double> e[9]) {
+    if (prec == P32 && recon == 18) {
+        f2* o = (f2*)out + (size_t)(r * 9) * Vh + s;
+#pragma unroll
+        for (int k = 0; k < 9; k++) o[(size_t)k * Vh] = f2{(float)e[k].re, (float)e[k].im};
+    } else if (prec == P32) {
+        f4* o = (f4*)out + (size_t)(r * 3) * Vh + s;
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+            o[(size_t)k * Vh] = f4{(float)e[2 * k].re, (float)e[2 * k].im, (float)e[2 * k + 1].re, (float)e[2 * k + 1].im};
+    } else if (recon == 18) {
+        h8* o = (h8*)((char*)out + (size_t)(r * 36) * Vh);
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            h8 v;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                v[2 * k] = (_Float16)e[4 * j + k].re;
+                v[2 * k + 1] = (_Float16)e[4 * j + k].im;
+            }
+            o[(size_t)j * Vh + s] = v;
+        }
+        ((h2*)(o + 2 * (size_t)Vh))[s] = h2{(_Float16)e[8].re, (_Float16)e[8].im};
+    } else {
+        h4* o = (h4*)out + (size_t)(r * 3) * Vh + s;
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+            o[(size_t)k * Vh] = h4{(_Float16)e[2 * k].re, (_Float16)e[2 * k].im, (_Float16)e[2 * k + 1].re,
+                                   (_Float16)e[2 * k + 1].im};
+    }
+}
+
+// bytes of one link in a sloppy copy
+__host__ __device__ __forceinline__ size_t sloppy_link_bytes(int prec, int recon) {
+    return prec == P32 ? (recon == 18 ? 72 : 48) : (recon == 18 ? 36 : 24);
+}
 
 // FP64 master gauge field access (double2 chunks)
 __device__ __forceinline__ M3<double> gauge_load(const d2* U, int mu, int p, int s, int Vh) {

@@ -115,25 +115,13 @@ __device__ __forceinline__ void make_sloppy_body(const Geom& g, const d2* __rest
     if (t >= 4 * g.V) return;
     int s = t % g.Vh, r = t / g.Vh;  // r = mu * 2 + p
     const d2* in = U + (size_t)(r * 9) * g.Vh + s;
-    d2 e[9];
+    cx<double> e[9];
 #pragma unroll
-    for (int k = 0; k < 9; k++) e[k] = in[(size_t)k * g.Vh];
-    if (prec == P32 && recon == 18) {
-        f2* o = (f2*)out + (size_t)(r * 9) * g.Vh + s;
-#pragma unroll
-        for (int k = 0; k < 9; k++) o[(size_t)k * g.Vh] = f2{(float)e[k].x, (float)e[k].y};
-    } else if (prec == P32) {
-        f4* o = (f4*)out + (size_t)(r * 3) * g.Vh + s;
-#pragma unroll
-        for (int k = 0; k < 3; k++)
-            o[(size_t)k * g.Vh] = f4{(float)e[2 * k].x, (float)e[2 * k].y, (float)e[2 * k + 1].x, (float)e[2 * k + 1].y};
-    } else {
-        h4* o = (h4*)out + (size_t)(r * 3) * g.Vh + s;
-#pragma unroll
-        for (int k = 0; k < 3; k++)
-            o[(size_t)k * g.Vh] = h4{(_Float16)e[2 * k].x, (_Float16)e[2 * k].y, (_Float16)e[2 * k + 1].x,
-                                     (_Float16)e[2 * k + 1].y};
+    for (int k = 0; k < 9; k++) {
+        const d2 v = in[(size_t)k * g.Vh];
+        e[k] = {v.x, v.y};
     }
+    store_sloppy_link(out, prec, recon, r, s, g.Vh, e);
 }
 
 __global__ void k_make_sloppy(Geom g, const d2* __restrict__ U, void* __restrict__ out, int prec, int recon) {
@@ -142,9 +130,7 @@ __global__ void k_make_sloppy(Geom g, const d2* __restrict__ U, void* __restrict
 
 // byte offset of a chain's sloppy links in the concatenated sloppy field
 __device__ __forceinline__ size_t sloppy_byte_off(const ChainDesc& d, int prec, int recon) {
-    if (prec == P32 && recon == 18) return 9 * (size_t)d.link0 * sizeof(f2);
-    if (prec == P32) return 3 * (size_t)d.link0 * sizeof(f4);
-    return 3 * (size_t)d.link0 * sizeof(h4);
+    return (size_t)d.link0 * sloppy_link_bytes(prec, recon);
 }
 
 __global__ void k_make_sloppy_b(const ChainDesc* __restrict__ cd, int nc, const d2* __restrict__ U,
@@ -711,25 +697,10 @@ __device__ __forceinline__ void link_update_body(const Geom& g, double h, const 
     M3<double> u = m3_mul(E, gauge_load(src, mu, p, s, g.Vh));
     gauge_store(dst, mu, p, s, g.Vh, u);
     if (sloppy) {
-        if (prec == P32 && recon == 18) {
-            f2* o = (f2*)sloppy + (size_t)(r * 9) * g.Vh + s;
+        cx<double> e[9];
 #pragma unroll
-            for (int k = 0; k < 9; k++) o[(size_t)k * g.Vh] = f2{(float)u.e[k / 3][k % 3].re, (float)u.e[k / 3][k % 3].im};
-        } else if (prec == P32) {
-            f4* o = (f4*)sloppy + (size_t)(r * 3) * g.Vh + s;
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                cx<double> a = u.e[(2 * k) / 3][(2 * k) % 3], b = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3];
-                o[(size_t)k * g.Vh] = f4{(float)a.re, (float)a.im, (float)b.re, (float)b.im};
-            }
-        } else {
-            h4* o = (h4*)sloppy + (size_t)(r * 3) * g.Vh + s;
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                cx<double> a = u.e[(2 * k) / 3][(2 * k) % 3], b = u.e[(2 * k + 1) / 3][(2 * k + 1) % 3];
-                o[(size_t)k * g.Vh] = h4{(_Float16)a.re, (_Float16)a.im, (_Float16)b.re, (_Float16)b.im};
-            }
-        }
+        for (int k = 0; k < 9; k++) e[k] = u.e[k / 3][k % 3];
+        store_sloppy_link(sloppy, prec, recon, r, s, g.Vh, e);
     }
 }
 

@@ -49,10 +49,10 @@ def run_single(ctx, ch, act, name, n):
     return U.cpu().numpy(), P.cpu().numpy(), dH
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mp16"])
-def test_batch_equals_single_chains(ctx, prec):
+@pytest.mark.parametrize("prec,recon", [("fp64", 18), ("mp16", 12), ("mp16", 18)])
+def test_batch_equals_single_chains(ctx, prec, recon):
     chains = make_chains(MIX, 0x09102950 + 400)
-    act = Action(beta=0.0, cg_tol=1e-12 if prec == "fp64" else 1e-10, prec=prec, link_recon=12)
+    act = Action(beta=0.0, cg_tol=1e-12 if prec == "fp64" else 1e-10, prec=prec, link_recon=recon)
     out, st = run_batch(ctx, chains, act, "FG", 3)
     assert st["solves"] == len(chains) * (3 * 3 + 1 + 1)
     for ch, (U, P, dH) in zip(chains, out):

@@ -81,9 +81,10 @@ def test_dslash_full_size(ctx, orc, fields, dims):
     Ud, sd = dev(U), dev(src)
     out = host(ctx.dslash(dims, Action(beta=5.6, kappa=0.1575), Ud, sd, 1))
     assert relmax(out, ref) < 1e-14
-    act16 = Action(beta=5.6, kappa=0.1575, prec="mp16", link_recon=12)
-    out16 = host(ctx.dslash(dims, act16, Ud, sd, 1, prec="mp16"))
-    assert relmax(out16, ref) < 4e-3
+    for recon in (12, 18):
+        act16 = Action(beta=5.6, kappa=0.1575, prec="mp16", link_recon=recon)
+        out16 = host(ctx.dslash(dims, act16, Ud, sd, 1, prec="mp16"))
+        assert relmax(out16, ref) < 4e-3, recon
 
 
 def test_gauge_force_full_size(ctx, orc, fields):
@@ -100,11 +101,12 @@ def test_fermion_force_full_size(ctx, orc, fields):
     assert relmax(F, orc.fermion_force(L16, 0.1575, U, X)) < 1e-13
 
 
-def test_cg_full_size_residual(ctx, orc, fields):
+@pytest.mark.parametrize("recon", [12, 18])
+def test_cg_full_size_residual(ctx, orc, fields, recon):
     U = fields[L16]
     eta = synth.gaussian_noise(synth.rng(912), L16)
     phi = orc.pf_heatbath(L16, 0.1575, U, eta)
-    act = Action(beta=5.6, kappa=0.1575, cg_tol=1e-10, prec="mp16", link_recon=12)
+    act = Action(beta=5.6, kappa=0.1575, cg_tol=1e-10, prec="mp16", link_recon=recon)
     X, st = ctx.cg_solve(L16, act, dev(U), dev(phi))
     X = host(X)
     AX = orc.mhat(L16, 0.1575, U, orc.mhat(L16, 0.1575, U, X, 0), 1)

@@ -119,7 +119,8 @@ def test_dslash_fp64(ctx, orc, dims, out_parity):
     assert relmax(out, ref) < 1e-14
 
 
-@pytest.mark.parametrize("prec,recon,tol", [("mp32", 18, 2e-6), ("mp32", 12, 5e-6), ("mp16", 12, 5e-3)])
+@pytest.mark.parametrize("prec,recon,tol", [("mp32", 18, 2e-6), ("mp32", 12, 5e-6), ("mp16", 12, 5e-3),
+                                             ("mp16", 18, 5e-3)])
 def test_dslash_sloppy(ctx, orc, prec, recon, tol):
     dims = (6, 4, 4, 6)
     U = links(dims, 12)
@@ -156,7 +157,7 @@ def test_cg_fp64(ctx, orc, dims):
     assert abs(st["cg_iters"] - it) <= 3
 
 
-@pytest.mark.parametrize("prec,recon", [("mp32", 18), ("mp32", 12), ("mp16", 12)])
+@pytest.mark.parametrize("prec,recon", [("mp32", 18), ("mp32", 12), ("mp16", 12), ("mp16", 18)])
 def test_cg_mixed_precision(ctx, orc, prec, recon):
     dims = (8, 8, 8, 8)
     U = links(dims, 18)
