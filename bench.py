@@ -34,12 +34,24 @@ METRIC = "s/trajectory at fixed <δH²> (FG vs leapfrog), 16^3x32 Nf=2; Dslash H
 HBM_PEAK_GBS = 8000.0
 # target <dH^2> for 80 % acceptance: <P_acc> = erfc(sqrt(<dH>)/2), <dH^2> ~ 2 <dH>
 DH2_TARGET = 0.257
-# matched step counts from the calibration sweep (bench.py --calibrate)
-N_FG_DEFAULT = 12
-N_LF_DEFAULT = 103
+# The legs of the matched-acceptance comparison: integrator, storage
+# precision of the inner CG, link reconstruction of its sloppy links
+LEGS = {"fg_mp16": ("FG", "mp16", 18), "fg_mp32": ("FG", "mp32", 12), "fg_fp64": ("FG", "fp64", 18),
+        "pqpqp_fp64": ("PQPQP", "fp64", 18), "lf_fp64": ("PQP", "fp64", 18)}
+# calibrated beside the timed legs for reference: FG-MP16 with 12-real links
+CAL_ONLY = {"fg_mp16_r12": ("FG", "mp16", 12)}
+# step counts swept by --calibrate (override with --cal-n)
+CAL_N = {"fg_mp16": [15, 16, 17, 18, 20], "fg_mp16_r12": [15, 16, 17, 18, 19, 20, 22, 24],
+         "fg_mp32": [15, 16, 17, 18, 19, 20, 22],
+         "fg_fp64": [15, 16, 17, 18, 19], "pqpqp_fp64": [20, 22, 24, 28, 32, 36, 40, 44],
+         "lf_fp64": [56, 64, 72, 76, 80]}
+# n* per leg (the smallest swept n with <dH^2> <= DH2_TARGET) is read from
+# this file, written from --calibrate runs; these apply when it is absent
+CALIBRATION_FILE = os.path.join(ROOT, "profiles", "calibration_16x16x16x32.json")
+N_STAR_FALLBACK = {"fg_mp16": 16, "fg_mp32": 16, "fg_fp64": 16, "pqpqp_fp64": 24, "lf_fp64": 80}
 # compulsory bytes per output site of one bare Dslash (8 links + input + output spinor)
-DSLASH_BYTES = {("mp16", 12): 8 * 24 + 2 * (48 + 4), ("mp32", 12): 8 * 48 + 2 * 96,
-                ("mp32", 18): 8 * 72 + 2 * 96, ("fp64", 18): 8 * 144 + 2 * 192}
+DSLASH_BYTES = {("mp16", 12): 8 * 24 + 2 * (48 + 4), ("mp16", 18): 8 * 36 + 2 * (48 + 4),
+                ("mp32", 12): 8 * 48 + 2 * 96, ("mp32", 18): 8 * 72 + 2 * 96, ("fp64", 18): 8 * 144 + 2 * 192}
 PREC_ID = {"fp64": 0, "mp32": 1, "mp16": 2}
 
 
@@ -55,14 +67,19 @@ def parse():
     ap.add_argument("--dims", default="16,16,16,32")
     ap.add_argument("--beta", type=float, default=5.6)
     ap.add_argument("--kappa", type=float, default=0.1575)
-    ap.add_argument("--therm", type=int, default=20, help="FP64 HMC trajectories from the hot start")
-    ap.add_argument("--therm-tau", type=float, default=6.0, help="trajectory length of the thermalisation runs")
-    ap.add_argument("--therm-steps", type=int, default=72)
-    ap.add_argument("--n-fg", type=int, default=N_FG_DEFAULT)
-    ap.add_argument("--n-lf", type=int, default=N_LF_DEFAULT)
-    ap.add_argument("--lf-steps", type=int, default=3, help="timed FP64 leapfrog trajectories (0: skip)")
+    ap.add_argument("--therm-pg", type=int, default=200, help="pure-gauge HMC trajectories from the hot start")
+    ap.add_argument("--beta-pg", type=float, default=5.83, help="beta of the pure-gauge thermalisation phase")
+    ap.add_argument("--therm", type=int, default=20, help="Nf=2 HMC trajectories after the pure-gauge phase")
+    ap.add_argument("--therm-tau", type=float, default=2.0, help="trajectory length of the Nf=2 thermalisation")
+    ap.add_argument("--therm-steps", type=int, default=32, help="FG steps per Nf=2 thermalisation trajectory")
+    ap.add_argument("--therm-md-tol", type=float, default=1e-7, help="MD solve tolerance while thermalising")
+    ap.add_argument("--n-fg", type=int, default=0, help="FG-MP16 step count (0: n* of the calibration)")
+    ap.add_argument("--leg-traj", type=int, default=8,
+                    help="trajectories of each comparison leg (FG-MP32, FG-FP64, PQPQP-FP64) at its n* (0: skip)")
+    ap.add_argument("--lf-traj", type=int, default=12, help="trajectories of the FP64 leapfrog leg at its n*")
     ap.add_argument("--prec", default="mp16", choices=["fp64", "mp32", "mp16"])
-    ap.add_argument("--recon", type=int, default=12)
+    ap.add_argument("--recon", type=int, default=18, choices=[12, 18],
+                    help="reals stored per sloppy link of the headline leg (FP16 or FP32)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--cg-batch", type=int, default=16)
     ap.add_argument("--graphs", type=int, default=1, help="replay CG batches as HIP graphs (0: eager launches)")
@@ -78,16 +95,24 @@ def parse():
     ap.add_argument("--exact-steps", type=int, default=2,
                     help="trajectories of the exact force-gradient form on the first timed inputs (0: skip)")
     ap.add_argument("--chain-steps", type=int, default=3, help="on-device Markov-chain trajectories (0: skip)")
+    ap.add_argument("--dt4-steps", type=int, default=2,
+                    help="exact-FG trajectories with the dt^4 brackets at both ends (0: skip)")
     ap.add_argument("--md-tol", type=float, default=1e-7,
                     help="force-solve tolerance of the looser-MD leg (0: skip; dH solves keep --tol)")
-    ap.add_argument("--tune-alpha", type=int, default=8, metavar="K",
+    ap.add_argument("--tune-alpha", type=int, default=4, metavar="K",
                     help="Omelyan alpha from Poisson brackets measured over K trajectories (0: skip)")
-    ap.add_argument("--n-omelyan", type=int, default=38, help="PQPQP step count of the alpha-tuning leg")
+    ap.add_argument("--asym-factor", type=int, default=2,
+                    help="the bracket legs (alpha tuning, dt^4 row) run at this multiple of their leg's n*: the "
+                         "shadow-Hamiltonian expansion describes dH only inside its asymptotic range, and n* "
+                         "sits at the integrators' stability edge")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default CG schedule (block 256, XCD order, --cg-batch) instead of tuning per leg")
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle CG iterations timed for the CPU baseline")
     ap.add_argument("--calibrate", action="store_true", help="step-size sweep for the matched step counts")
-    ap.add_argument("--cal-traj", type=int, default=6)
+    ap.add_argument("--cal-traj", type=int, default=32, help="trajectories per calibration point")
+    ap.add_argument("--cal-legs", default=",".join(LEGS), help="comma-separated legs to calibrate")
+    ap.add_argument("--cal-n", default="", help="step counts per leg, e.g. 'fg_mp16=18,20;lf_fp64=90'")
+    ap.add_argument("--cal-out", default="", help="also write the calibration JSON to this file")
     ap.add_argument("--seed", type=int, default=0x09102950 + 2)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one device copy of MIB MiB (a known-size kernel that calibrates "
@@ -114,9 +139,10 @@ def source_digest():
 
 
 def read_traffic(kernel_key, lattice="16x16x16x32"):
-    """HBM bytes per launch of the profiled Dslash from the committed rocprofv3
-    counter summary, or None when it is absent or the kernel source changed."""
-    path = os.path.join(ROOT, "profiles", "dslash_hbm_traffic_%s.txt" % lattice)
+    """HBM bytes per launch of the profiled Dslash (kernel_key "prec/recon")
+    from the committed rocprofv3 counter summary, or None when it is absent or
+    the kernel source changed."""
+    path = os.path.join(ROOT, "profiles", "dslash_hbm_traffic_%s_%s.txt" % (lattice, kernel_key.replace("/", "_")))
     if not os.path.exists(path):
         return None
     kv = {}
@@ -154,27 +180,53 @@ class Runner:
         return self.torch.from_numpy(np.ascontiguousarray(a)).to(self.dev)
 
     def thermalise(self):
+        """Seeded hot start, then two phases of on-device HMC chains
+        (fgi_hmc_run: momenta, noise and Metropolis uniforms drawn on the
+        device, links reunitarised after every trajectory):
+          1. --therm-pg pure-gauge trajectories at --beta-pg (FG, tau = 1,
+             n = 10, no accept/reject): cheap, and they carry the plaquette
+             from 0 to about the dynamical value (the Nf = 2 determinant acts
+             at leading order as a shift of beta);
+          2. --therm Nf = 2 trajectories at (beta, kappa) of the workload: FG,
+             tau = --therm-tau, n = --therm-steps, MP16 solves (the MD solves at
+             --therm-md-tol, the heatbath and energy solves at --tol) and the
+             Metropolis test.  A chunk of 4 trajectories with more than two
+             rejections raises n by a quarter before the next chunk (the
+             field's stiffest fermion modes harden as it approaches
+             equilibrium), so the run stays inside the integrator's stability
+             range.
+        Returns the links, the final plaquette and the per-trajectory history."""
         a = self.args
         synth = self.synth
         U0, _, _, _ = synth.hot_start(self.dims, a.seed, fermions=False)
         U = self.to_dev(U0)
-        act = self.action("fp64")
-        integ = self.fgi.integrator_builtin("PQPQP", 0.1932)
-        u = synth.rng(a.seed + 999).random(max(a.therm, 1))
-        plaq = 1.0 - self.ctx.gauge_action(self.dims, 1.0, U) / (6.0 * np.prod(self.dims))
-        for k in range(a.therm):
-            P, eta = synth.refresh(self.dims, a.seed + 1000 * (k + 1))
-            Ut = U.clone()
-            dH, st = self.ctx.trajectory(self.dims, act, integ, a.therm_tau, a.therm_steps, Ut, self.to_dev(P),
-                                         self.to_dev(eta))
-            acc = (k < a.therm // 2) or (u[k] < math.exp(-dH) if dH > -700 else True)
-            if acc:
-                U = Ut
-            self.ctx.reunitarize(self.dims, U)
-            plaq = 1.0 - self.ctx.gauge_action(self.dims, 1.0, U) / (6.0 * np.prod(self.dims))
-            log("therm %2d dH=%+.4e acc=%d plaq=%.5f cg_iters=%d solves=%d %.2fs" %
-                (k, dH, acc, plaq, st["cg_iters"], st["solves"], st["seconds"]))
-        return U, plaq
+        hist = []
+        t0 = time.perf_counter()
+        if a.therm_pg > 0:
+            dH, acc, plaq, st = self.ctx.hmc_run(self.dims, self.fgi.Action(beta=a.beta_pg), "FG", 1.0, 10, U,
+                                                 a.seed + 17, 0, a.therm_pg, metropolis=False)
+            for k in range(a.therm_pg):
+                hist.append(dict(phase="pure_gauge", beta=a.beta_pg, n=10, tau=1.0, dH=dH[k], acc=bool(acc[k]),
+                                 plaq=plaq[k]))
+            log("therm pure gauge beta=%.3f: %d trajectories, plaquette %.5f -> %.5f (%.1fs)" %
+                (a.beta_pg, a.therm_pg, plaq[0], plaq[-1], time.perf_counter() - t0))
+        act = dataclasses.replace(self.action("mp16", 12), cg_tol_md=a.therm_md_tol)
+        n = a.therm_steps
+        k = 0
+        while k < a.therm:
+            m = min(4, a.therm - k)
+            t1 = time.perf_counter()
+            dH, acc, plaq, st = self.ctx.hmc_run(self.dims, act, "FG", a.therm_tau, n, U, a.seed + 29, k, m)
+            for j in range(m):
+                hist.append(dict(phase="nf2", n=n, tau=a.therm_tau, dH=dH[j], acc=bool(acc[j]), plaq=plaq[j]))
+                log("therm %2d n=%d dH=%+.4e acc=%d plaq=%.5f" % (k + j, n, dH[j], acc[j], plaq[j]))
+            log("  chunk: %d CG iterations, %.1fs" % (st["cg_iters"], time.perf_counter() - t1))
+            k += m
+            if m - sum(acc) > m // 2:
+                n = int(math.ceil(1.25 * n))
+        plaq = hist[-1]["plaq"] if hist else float("nan")
+        log("thermalisation %.1fs, plaquette %.5f" % (time.perf_counter() - t0, plaq))
+        return U, plaq, hist
 
     def tune(self, U, prec, recon):
         """Autotune the CG schedule on the thermalised field for one precision
@@ -216,7 +268,14 @@ class Runner:
         for (P0, eta) in inputs:
             U.copy_(U_therm)
             P.copy_(P0)
-            dH, st = self.ctx.trajectory(self.dims, act, integ, 1.0, nsteps, U, P, eta)
+            try:
+                dH, st = self.ctx.trajectory(self.dims, act, integ, 1.0, nsteps, U, P, eta, allow_noconv=True)
+            except self.fgi.FgiError as e:
+                # a trajectory that left the integrator's stability range (a non-finite dH)
+                # counts as rejected, with dH = +inf
+                log("trajectory failed (%s): counted as dH = +inf" % e)
+                dH, st = float("inf"), dict(solves=0, cg_iters=0, cg_iters_max=0, max_rel_resid=0.0,
+                                            reliable_updates=0, force_evals=0, seconds=0.0, status=e.code)
             recs.append(dict(dH=dH, **st))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -267,7 +326,7 @@ def dslash_roofline_large(R, U_therm, prec, recon):
     return dict(lattice=list(dims_b), bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 traffic_GBs=round(traffic / avg_s / 1e9, 1) if traffic else None,
-                avg_launch_us=round(avg_s * 1e6, 3), launches_timed=launches,
+                avg_launch_us=round(avg_s * 1e6, 3), launches_timed=launches, kernel_key="%s/%d" % (prec, recon),
                 algorithmic_bytes_per_launch=sites / launches * bps,
                 kernel="bare even-odd Dslash hop t = D_oe g5 q (%s/%d), %d output sites per launch, on the "
                        "thermalised 16^3x32 field repeated 2x2x2x2" % (prec, recon, V // 2))
@@ -380,7 +439,7 @@ def tune_alpha_leg(R, U_therm, k, n):
     and the same k starts rerun at that alpha."""
     from paper_0910_2950_amd.tuning import predicted_dh2, tune_omelyan_alpha
     torch, ctx, dims = R.torch, R.ctx, R.dims
-    act = R.action(R.args.prec, 12 if R.args.prec == "mp16" else R.args.recon)
+    act = R.action(R.args.prec, R.args.recon)
     inputs = R.fresh_inputs(k, R.args.seed + 300000)
     dS, dT, dh0 = [], [], []
     t0 = time.perf_counter()
@@ -404,6 +463,37 @@ def tune_alpha_leg(R, U_therm, k, n):
                                "tuned": predicted_dh2(alpha, dS, dT, 1.0 / n)},
                 measured_dH2={"0.1932": float(np.mean(np.square(dh0))), "tuned": float(np.mean(np.square(dh1)))},
                 dH={"0.1932": dh0, "tuned": dh1}, seconds=time.perf_counter() - t0)
+
+
+def fg_row(b):
+    """Table 1, last row: H~ = H - dt^4/155520 (36 STSST + 72 STTST + 126 TTSST
+    + 54 TTTST) for the exact force-gradient integrator, so dH = dt^4 times the
+    change of this combination over the trajectory (+ O(dt^6))."""
+    return (36 * b["STSST"] + 72 * b["STTST"] + 126 * b["TTSST"] + 54 * b["TTTST"]) / 155520.0
+
+
+def dt4_leg(R, U_therm, act, n, inputs):
+    """Table 1's dt^4 row on the thermalised field: the four dt^4 brackets
+    (fgi_poisson_brackets4, step 1e-3) at both ends of exact-FG trajectories
+    (n steps, tau = 1) from the given starts, the predicted dH beside the
+    measured one, and the displacement form's dH from the same start."""
+    torch, ctx, dims = R.torch, R.ctx, R.dims
+    act_ex = dataclasses.replace(act, fg_exact=True)
+    out = []
+    t0 = time.perf_counter()
+    for P0, eta in inputs:
+        phi = ctx.pf_heatbath(dims, act, U_therm, eta)
+        b0 = ctx.poisson_brackets4(dims, act, U_therm, P0, phi, h=1e-3)
+        U, P = U_therm.clone(), P0.clone()
+        dH, _ = ctx.trajectory(dims, act_ex, "FG", 1.0, n, U, P, phi, pf_is_phi=True)
+        b1 = ctx.poisson_brackets4(dims, act, U, P, phi, h=1e-3)
+        U, P = U_therm.clone(), P0.clone()
+        dHd, _ = ctx.trajectory(dims, act, "FG", 1.0, n, U, P, phi, pf_is_phi=True)
+        pred = (fg_row(b1) - fg_row(b0)) / n ** 4
+        out.append(dict(dH_exact=dH, dH_predicted=pred, dH_displacement=dHd,
+                        brackets_start=b0, brackets_end=b1))
+    return dict(n=n, trajectories=len(out), records=out, seconds=time.perf_counter() - t0,
+                note="predicted = dt^4 Delta(36 STSST + 72 STTST + 126 TTSST + 54 TTTST)/155520 (Table 1, last row)")
 
 
 def chain_leg(R, U_therm, act, n, ntraj, seed=0x5EED):
@@ -557,16 +647,36 @@ def clover_leg(R, U_therm, inputs, n, kappa=0.135, csw=1.0, reps=10):
 
 
 def summarise(recs):
+    """Per-leg statistics over independent trajectories from the same start
+    field: <dH>, <dH^2>, acceptance <min(1, e^-dH)> and the Creutz mean
+    <e^-dH>, each with its standard error over the trajectories, and the
+    solver counts."""
     dh = np.array([r["dH"] for r in recs])
-    return dict(mean_dH=float(dh.mean()), mean_dH2=float((dh ** 2).mean()),
-                acceptance=float(np.mean(np.minimum(1.0, np.exp(-dh)))),
-                exp_minus_dH=float(np.mean(np.exp(-dh))),
+    n = len(dh)
+    se = (lambda v: float(np.std(v, ddof=1) / math.sqrt(n))) if n > 1 else (lambda v: None)
+    acc = np.minimum(1.0, np.exp(-np.minimum(dh, 700.0)))
+    emd = np.exp(-np.minimum(dh, 700.0))
+    return dict(trajectories=n, mean_dH=float(dh.mean()), mean_dH2=float((dh ** 2).mean()), mean_dH2_err=se(dh ** 2),
+                acceptance=float(acc.mean()), acceptance_err=se(acc),
+                exp_minus_dH=float(emd.mean()), exp_minus_dH_err=se(emd),
                 solves_per_traj=float(np.mean([r["solves"] for r in recs])),
                 cg_iters_per_traj=float(np.mean([r["cg_iters"] for r in recs])),
                 cg_iters_max=int(max(r["cg_iters_max"] for r in recs)),
                 max_rel_resid=float(max(r["max_rel_resid"] for r in recs)),
                 reliable_updates_per_traj=float(np.mean([r["reliable_updates"] for r in recs])),
                 force_evals_per_traj=float(np.mean([r["force_evals"] for r in recs])))
+
+
+def n_star(leg):
+    """n* of a leg from the committed calibration (or the fallback)."""
+    try:
+        with open(CALIBRATION_FILE) as fh:
+            v = json.load(fh)["legs"][leg]["n_star"]
+        if v:
+            return int(v), "calibration"
+    except (OSError, KeyError, ValueError, TypeError):
+        pass
+    return N_STAR_FALLBACK[leg], "fallback"
 
 
 # Compulsory bytes per unit of work (each input read once, each output written
@@ -577,6 +687,11 @@ def summarise(recs):
 # and clear), one force evaluation (fermion force per site plus its four FP64
 # hops per even site, gauge force per link) and one link update per link.
 def cg_iteration_bytes(prec, recon):
+    """Compulsory bytes per even site of one CG iteration: two bare hops (H
+    each); M_CGQ = a hop whose output is q, plus p in (H + vec); M_CGX = a hop
+    that stores nothing (H - vec) plus q, p in and x, r in and out; k_cg_p = r
+    in, p in and out.  4 H + 4 vec + 5 vx: MP16/12 1872 B, MP32/12 3168 B,
+    FP64/18 7872 B."""
     hop = DSLASH_BYTES[(prec, recon)]
     if prec == "fp64":
         vec, vx = 192, 192
@@ -584,8 +699,11 @@ def cg_iteration_bytes(prec, recon):
         vec, vx = 96, 96
     else:
         vec, vx = 52, 96
-    # k_cg_p: r in, p in/out; M_CGQ: p in, q out; M_CGX: q, p in, x and r in/out
-    return 4 * hop + (vx + 2 * vec) + 2 * vec + (2 * vec + 4 * vx)
+    hops = 2 * hop
+    cgq = hop + vec
+    cgx = (hop - vec) + 2 * vec + 4 * vx
+    cgp = vx + 2 * vec
+    return hops + cgq + cgx + cgp
 
 
 RU_BYTES = 4 * DSLASH_BYTES[("fp64", 18)] + 3 * 192 + (96 + 2 * 192) + (192 + 96) + 96
@@ -614,10 +732,72 @@ def trajectory_roofline(summary, dims, prec, recon, link_updates, fermions, seco
                 cg_iteration_bytes_per_even_site=cg_iteration_bytes(prec, recon))
 
 
-def cpu_baseline(args, dims, iters_per_traj, force_evals_per_traj, links_updates_per_traj):
-    """Oracle as it stands, on a bounded sample: time oracle CG iterations, one
-    gauge force, one fermion force and one link update at the full size on a
-    synthetic hot-start field; scale by the trajectory's own counts."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def whole_trajectories(args):
+    """The oracle's whole trajectories on the host for the two small
+    workloads, beside the same trajectories on the GPU:
+      4^4 pure gauge, beta = 6.0: PQP, PQPQP(0.1932) and FG at dtau in
+          {1/4, 1/8, 1/16, 1/32}, tau = 1 (twelve trajectories, one Haar start);
+      8^4 Nf = 2, beta = 5.6, kappa = 0.155: FG at n = 10, tau = 1, CG 1e-10,
+          from a Haar start (FP64 on both sides)."""
+    import torch
+
+    from oracle import oracle as orc
+    from paper_0910_2950_amd import fgi, synth
+    orc.lib()
+    ctx = fgi.Context(0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    out = {}
+    dims = (4, 4, 4, 4)
+    U0, P0, _, _ = synth.hot_start(dims, synth.SEED_BASE, fermions=False)
+    runs = [(nm, n) for nm in ("PQP", "PQPQP", "FG") for n in (4, 8, 16, 32)]
+    t = time.perf_counter()
+    for nm, n in runs:
+        orc.trajectory(dims, 6.0, orc.table(nm), 1.0, n, U0, P0)
+    t_cpu = (time.perf_counter() - t) / len(runs)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for nm, n in runs:
+        ctx.trajectory(dims, fgi.Action(beta=6.0), nm, 1.0, n, dev(U0), dev(P0))
+    torch.cuda.synchronize()
+    t_gpu = (time.perf_counter() - t) / len(runs)
+    out["4x4x4x4_pure_gauge"] = dict(s_per_traj=t_cpu, gpu_s_per_traj=t_gpu, trajectories=len(runs),
+                                     runs="PQP, PQPQP(0.1932), FG x dtau 1/4..1/32, tau=1, beta=6.0")
+    dims = (8, 8, 8, 8)
+    U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 1, fermions=True)
+    t = time.perf_counter()
+    orc.trajectory(dims, 5.6, orc.table("FG"), 1.0, 10, U0, P0, kappa=0.155, eta=eta, tol=1e-10)
+    t_cpu = time.perf_counter() - t
+    act = fgi.Action(beta=5.6, kappa=0.155, cg_tol=1e-10)
+    ctx.trajectory(dims, act, "FG", 1.0, 10, dev(U0), dev(P0), dev(eta))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ctx.trajectory(dims, act, "FG", 1.0, 10, dev(U0), dev(P0), dev(eta))
+    torch.cuda.synchronize()
+    out["8x8x8x8_nf2"] = dict(s_per_traj=t_cpu, gpu_s_per_traj=time.perf_counter() - t, trajectories=1,
+                              runs="FG n=10, tau=1, beta=5.6, kappa=0.155, FP64 CG 1e-10")
+    ctx.close()
+    return out
+
+
+def cpu_baseline(args, dims, lf, fg, n_fg):
+    """The oracle as it stands on the host cores.  For the headline workload
+    a bounded sample -- oracle CG iterations, one gauge force, one fermion
+    force, one link update and one heatbath at 16^3x32 on a synthetic
+    hot-start field -- scaled to one FG trajectory with the GPU run's counts
+    (FP64 CG iterations per solve from the FP64 leapfrog leg, the FG solve
+    and force counts); extrapolated, and labelled so.  For the 4^4 and 8^4
+    workloads the oracle's whole trajectories (whole_trajectories)."""
     from oracle import oracle as orc
     from paper_0910_2950_amd import synth
     U, _, eta, _ = synth.hot_start(dims, args.seed + 77, fermions=True)
@@ -638,47 +818,99 @@ def cpu_baseline(args, dims, iters_per_traj, force_evals_per_traj, links_updates
     t = time.perf_counter()
     orc.link_update(dims, 0.1, P, U)
     t_lu = time.perf_counter() - t
-    est = iters_per_traj * t_it + force_evals_per_traj * (t_gf + t_ff) + links_updates_per_traj * t_lu + t_heat
-    sample = ("oracle at %s: %d CG iterations (%.3f s each), 1 gauge force (%.2f s), 1 fermion force (%.2f s), "
-              "1 link update (%.2f s), 1 heatbath (%.2f s); scaled to one FG trajectory with the GPU run's "
-              "counts (%.0f CG iterations, %.0f force evaluations, %d link updates)"
-              % ("x".join(map(str, dims)), args.cpu_iters, t_it, t_gf, t_ff, t_lu, t_heat, iters_per_traj,
-                 force_evals_per_traj, links_updates_per_traj))
-    return dict(value=est, unit="s/trajectory", cores=orc.threads(), kind="oracle", sample=sample)
+    iters_per_solve = lf["cg_iters_per_traj"] / lf["solves_per_traj"] if lf else \
+        fg["cg_iters_per_traj"] / fg["solves_per_traj"]
+    iters = iters_per_solve * fg["solves_per_traj"]
+    nf, nl = fg["force_evals_per_traj"], 2 * n_fg
+    est = iters * t_it + nf * (t_gf + t_ff) + nl * t_lu + t_heat
+    sample = ("extrapolated: oracle at %s on a hot-start field, %d CG iterations (%.3f s each), 1 gauge force "
+              "(%.2f s), 1 fermion force (%.2f s), 1 link update (%.2f s), 1 heatbath (%.2f s); scaled to one FG "
+              "trajectory at n=%d with the GPU run's counts (%.0f FP64 CG iterations, %.0f force evaluations, %d "
+              "link updates)" % ("x".join(map(str, dims)), args.cpu_iters, t_it, t_gf, t_ff, t_lu, t_heat, n_fg,
+                                 iters, nf, nl))
+    return dict(value=est, unit="s/trajectory", cores=orc.threads(), cpu_model=cpu_model(), kind="oracle",
+                sample=sample, configs=whole_trajectories(args))
 
 
 def calibrate(args):
+    """Step-size sweep on the thermalised field: for every leg and step count,
+    --cal-traj trajectories (tau = 1) from the same field with fresh seeded
+    (P, eta), <dH^2> with its standard error; n* = the smallest swept n whose
+    <dH^2> is at most DH2_TARGET, and the power-law fit of <dH^2> against dtau
+    over the points below 10."""
     R = Runner(args)
-    U, plaq = R.thermalise()
-    legs = [("FG", args.prec, args.recon, [10, 12, 14, 16, 20]), ("FG", "fp64", 18, [12, 16]),
-            ("PQP", "fp64", 18, [64, 96, 128]), ("PQPQP", "fp64", 18, [24, 32, 40])]
+    U, plaq, hist = R.thermalise()
+    ns = dict(CAL_N)
+    for part in filter(None, args.cal_n.split(";")):
+        k, v = part.split("=")
+        ns[k.strip()] = [int(x) for x in v.split(",")]
     out = {}
-    for name, prec, recon, ns in legs:
+    for leg in filter(None, args.cal_legs.split(",")):
+        name, prec, recon = {**LEGS, **CAL_ONLY}[leg]
+        R.apply(None if args.no_autotune else R.tune(U, prec, recon))
         act = R.action(prec, recon)
         pts = []
-        for n in ns:
+        for n in ns[leg]:
             inputs = R.fresh_inputs(args.cal_traj, args.seed + 500000 + 1000 * n)
             recs, sec, _ = R.run_leg(U, act, name, n, inputs)
-            s = summarise(recs)
-            s.update(n=n, s_per_traj=sec / len(recs))
-            pts.append(s)
-            log("cal %-6s %s n=%2d <dH^2>=%.4e acc=%.3f s/traj=%.3f solves=%.0f iters=%.0f" %
-                (name, prec, n, s["mean_dH2"], s["acceptance"], s["s_per_traj"], s["solves_per_traj"],
-                 s["cg_iters_per_traj"]))
-        # fit log <dH^2> = c + q log dt over the points in the asymptotic regime
-        # (<dH^2> < 10); n* = the smallest measured n whose <dH^2> meets the target
+            st = summarise(recs)
+            st.update(n=n, s_per_traj=sec / len(recs), dH=[r["dH"] for r in recs])
+            pts.append(st)
+            log("cal %-10s n=%3d <dH^2>=%.4e +- %.1e acc=%.3f <e^-dH>=%.3f s/traj=%.3f solves=%.0f iters=%.0f" %
+                (leg, n, st["mean_dH2"], st["mean_dH2_err"] or 0, st["acceptance"], st["exp_minus_dH"],
+                 st["s_per_traj"], st["solves_per_traj"], st["cg_iters_per_traj"]))
         fit_pts = [p for p in pts if p["mean_dH2"] < 10.0]
-        q = c = n_fit = None
+        q = n_fit = None
         if len(fit_pts) >= 2:
             x = np.log(1.0 / np.array([p["n"] for p in fit_pts]))
             y = np.log(np.array([max(p["mean_dH2"], 1e-30) for p in fit_pts]))
             q, c = np.polyfit(x, y, 1)
             n_fit = float(math.exp((c - math.log(DH2_TARGET)) / q))
-        ok = [p["n"] for p in pts if p["mean_dH2"] <= DH2_TARGET]
-        n_star = min(ok) if ok else None
-        out[name + "-" + prec] = dict(points=pts, slope=q, n_fit=n_fit, n_star=n_star)
-        log("fit %s-%s: <dH^2> ~ dt^%s  n_fit=%s n*=%s" % (name, prec, q, n_fit, n_star))
-    print(json.dumps(dict(calibration=out, plaquette=plaq, dims=args.dims, target_dH2=DH2_TARGET)))
+        # n*: the smallest swept n from which on every swept point meets the target
+        ok = [p["n"] for p in pts if all(r["mean_dH2"] <= DH2_TARGET for r in pts if r["n"] >= p["n"])]
+        out[leg] = dict(integrator=name, prec=prec, link_recon=recon, points=pts, slope=q, n_fit=n_fit,
+                        n_star=min(ok) if ok else None)
+        log("fit %s: <dH^2> ~ dt^%s  n_fit=%s n*=%s" % (leg, q, n_fit, out[leg]["n_star"]))
+        res = calibration_record(args, R, out, plaq, hist)
+        if args.cal_out:  # after every leg, so a cut-off sweep keeps its finished legs
+            with open(args.cal_out, "w") as fh:
+                json.dump(res, fh)
+    print(json.dumps(calibration_record(args, R, out, plaq, hist)))
+
+
+def calibration_record(args, R, out, plaq, hist):
+    return dict(legs=out, plaquette=plaq, dims=list(R.dims), beta=args.beta, kappa=args.kappa, cg_tol=args.tol,
+               target_dH2=DH2_TARGET, trajectories_per_point=args.cal_traj,
+               thermalisation=dict(pure_gauge=args.therm_pg, beta_pg=args.beta_pg, nf2=args.therm,
+                                   tau=args.therm_tau, steps=args.therm_steps,
+                                   plaquette_history=[round(h["plaq"], 6) for h in hist if h["phase"] == "nf2"]),
+               command="python bench.py " + " ".join(sys.argv[1:]))
+
+
+def leg_record(R, U, leg, n, inputs, schedule):
+    """One comparison leg at its step count n over the given starts: the
+    per-leg statistics, seconds per trajectory and the whole-trajectory
+    roofline."""
+    name, prec, recon = LEGS[leg]
+    R.apply(schedule)
+    recs, sec, _ = R.run_leg(U, R.action(prec, recon), name, n, inputs)
+    st = summarise(recs)
+    st.update(n=n, s_per_traj=sec / len(recs), dH=[r["dH"] for r in recs], schedule=schedule)
+    links = {"FG": 2 * n, "PQPQP": 2 * n, "PQP": n}[name]
+    st["trajectory_roofline"] = trajectory_roofline(st, R.dims, prec, recon, links, True, st["s_per_traj"])
+    log("%-10s n=%3d: %.4f s/traj  <dH^2>=%.4e +- %.1e acc=%.3f <e^-dH>=%.3f +- %.3f solves=%.1f iters=%.0f" %
+        (leg, n, st["s_per_traj"], st["mean_dH2"], st["mean_dH2_err"] or 0, st["acceptance"], st["exp_minus_dH"],
+         st["exp_minus_dH_err"] or 0, st["solves_per_traj"], st["cg_iters_per_traj"]))
+    return st
+
+
+def dslash_sample(R, U, inputs, n, prec, recon):
+    """The Dslash roofline sample, outside the timed region: FG trajectories
+    of the headline leg with the live hop profile on (after every solve, 16
+    back-to-back launches of the CG's bare hop t = D_oe g5 q on the solve's
+    stream, bracketed by HIP events)."""
+    _, _, prof = R.run_leg(U, R.action(prec, recon), "FG", n, inputs, profile=True)
+    return prof
 
 
 def main():
@@ -700,65 +932,85 @@ def main():
         log("copy probe: %d bytes read, %d bytes written" % (4 * n, 4 * n))
         del x, y
     t_setup = time.perf_counter()
-    U, plaq = R.thermalise()
-    act_fg = R.action(args.prec, args.recon)
+    U, plaq, therm_hist = R.thermalise()
+    nstar = {leg: n_star(leg) for leg in LEGS}
+    n_fg = args.n_fg or nstar["fg_mp16"][0]
+    recon_fg = args.recon if args.prec != "fp64" else 18
+    act_fg = R.action(args.prec, recon_fg)
     inputs = R.fresh_inputs(args.warmup + args.steps, args.seed + 100000)
-    log("setup (thermalisation + inputs) %.1fs" % (time.perf_counter() - t_setup))
-
-    tune_fg = tune_lf = None
+    log("setup (thermalisation + inputs) %.1fs; n* %s" % (time.perf_counter() - t_setup,
+                                                          {k: v[0] for k, v in nstar.items()}))
+    sched = {}
     if not args.no_autotune:
-        tune_fg = R.tune(U, args.prec, args.recon if args.prec != "mp16" else 12)
-        if args.lf_steps > 0:
-            tune_lf = R.tune(U, "fp64", 18)
+        for prec, recon in sorted({(args.prec, recon_fg)} | {(LEGS[k][1], LEGS[k][2]) for k in LEGS}):
+            sched[prec, recon] = R.tune(U, prec, recon)
+    tune_fg = sched.get((args.prec, recon_fg))
     R.apply(tune_fg)
-    # warmup (untimed)
+    # warmup (untimed), then the headline: K FG trajectories, profiling off
     if args.warmup:
-        R.run_leg(U, act_fg, "FG", args.n_fg, inputs[:args.warmup])
-    # timed FG leg with live Dslash event timing
-    recs, sec, prof = R.run_leg(U, act_fg, "FG", args.n_fg, inputs[args.warmup:], profile=True)
+        R.run_leg(U, act_fg, "FG", n_fg, inputs[:args.warmup])
+    recs, sec, _ = R.run_leg(U, act_fg, "FG", n_fg, inputs[args.warmup:])
     fg = summarise(recs)
-    fg["schedule"] = tune_fg
+    fg.update(n=n_fg, n_source=nstar["fg_mp16"][1] if not args.n_fg else "--n-fg", schedule=tune_fg,
+              dH=[r["dH"] for r in recs])
     s_per_traj = sec / args.steps
-    fg["trajectory_roofline"] = trajectory_roofline(fg, R.dims, args.prec, 12 if args.prec == "mp16" else args.recon,
-                                                    3 * args.n_fg, True, s_per_traj)
+    fg["s_per_traj"] = s_per_traj
+    fg["trajectory_roofline"] = trajectory_roofline(fg, R.dims, args.prec, recon_fg, 2 * n_fg, True, s_per_traj)
+    log("FG-%s n=%d: %.4f s/traj  <dH^2>=%.4e +- %.1e acc=%.3f <e^-dH>=%.3f solves=%.1f iters=%.0f" %
+        (args.prec, n_fg, s_per_traj, fg["mean_dH2"], fg["mean_dH2_err"] or 0, fg["acceptance"],
+         fg["exp_minus_dH"], fg["solves_per_traj"], fg["cg_iters_per_traj"]))
     log("FG trajectory roofline: %.1f ms of compulsory HBM traffic at 8 TB/s against %.1f ms measured (%.1f%%)" %
         (fg["trajectory_roofline"]["t_roof_ms"], s_per_traj * 1e3, 100 * fg["trajectory_roofline"]["frac"]))
-    log("FG-%s n=%d: %.4f s/traj  <dH^2>=%.4e acc=%.3f solves=%.1f iters=%.0f" %
-        (args.prec, args.n_fg, s_per_traj, fg["mean_dH2"], fg["acceptance"], fg["solves_per_traj"],
-         fg["cg_iters_per_traj"]))
 
-    # exact G stage (Section 4 force gradient, one solve for d_V X in place of
-    # the displaced force's solve) on the same starts as the first timed
-    # trajectories: its cost and dH beside the displacement form's
+    # the other legs at their own n*, on the first timed starts
+    legs = {}
+    k_leg = min(args.leg_traj, args.steps)
+    for leg in ("fg_mp32", "fg_fp64", "pqpqp_fp64"):
+        if k_leg > 0:
+            _, prec, recon = LEGS[leg]
+            legs[leg] = leg_record(R, U, leg, nstar[leg][0], inputs[args.warmup:args.warmup + k_leg],
+                                   sched.get((prec, recon)))
+            legs[leg]["n_source"] = nstar[leg][1]
+    lf = None
+    lf_inputs = []
+    if args.lf_traj > 0:
+        lf_inputs = inputs[args.warmup:args.warmup + min(args.lf_traj, args.steps)]
+        lf_inputs += R.fresh_inputs(args.lf_traj - len(lf_inputs), args.seed + 200000)
+        lf = leg_record(R, U, "lf_fp64", nstar["lf_fp64"][0], lf_inputs, sched.get(("fp64", 18)))
+        lf["n_source"] = nstar["lf_fp64"][1]
+        legs["lf_fp64"] = lf
+
+    # exact G stage (Section 4 force gradient) on the first timed starts
     exact = None
     if args.exact_steps > 0:
+        R.apply(tune_fg)
         k = min(args.exact_steps, args.steps)
         act_ex = dataclasses.replace(act_fg, fg_exact=True)
-        recs_ex, sec_ex, _ = R.run_leg(U, act_ex, "FG", args.n_fg, inputs[args.warmup:args.warmup + k])
+        recs_ex, sec_ex, _ = R.run_leg(U, act_ex, "FG", n_fg, inputs[args.warmup:args.warmup + k])
         exact = summarise(recs_ex)
-        exact.update(n=args.n_fg, s_per_traj=sec_ex / k, trajectories=k,
-                     dH=[r["dH"] for r in recs_ex], dH_displacement_same_start=[r["dH"] for r in recs[:k]])
+        exact.update(n=n_fg, s_per_traj=sec_ex / k, dH=[r["dH"] for r in recs_ex],
+                     dH_displacement_same_start=[r["dH"] for r in recs[:k]])
         log("FG-%s exact form n=%d: %.4f s/traj solves=%.1f iters=%.0f dH=%s (displacement %s)" %
-            (args.prec, args.n_fg, exact["s_per_traj"], exact["solves_per_traj"], exact["cg_iters_per_traj"],
+            (args.prec, n_fg, exact["s_per_traj"], exact["solves_per_traj"], exact["cg_iters_per_traj"],
              ["%+.3e" % d for d in exact["dH"]], ["%+.3e" % d for d in exact["dH_displacement_same_start"]]))
 
-    # FP64 leapfrog leg at its matched step count
-    lf = None
-    if args.lf_steps > 0:
-        R.apply(tune_lf)
-        lf_inputs = R.fresh_inputs(args.lf_steps, args.seed + 200000)
-        recs_lf, sec_lf, _ = R.run_leg(U, R.action("fp64"), "PQP", args.n_lf, lf_inputs)
-        lf = summarise(recs_lf)
-        lf.update(n=args.n_lf, s_per_traj=sec_lf / args.lf_steps, trajectories=args.lf_steps, schedule=tune_lf)
-        lf["trajectory_roofline"] = trajectory_roofline(lf, R.dims, "fp64", 18, args.n_lf, True, lf["s_per_traj"])
-        log("LF-fp64 n=%d: %.4f s/traj  <dH^2>=%.4e acc=%.3f iters=%.0f" %
-            (args.n_lf, lf["s_per_traj"], lf["mean_dH2"], lf["acceptance"], lf["cg_iters_per_traj"]))
+    dt4 = None
+    if args.dt4_steps > 0:
+        R.apply(tune_fg)
+        n4 = args.asym_factor * n_fg
+        dt4 = dt4_leg(R, U, act_fg, n4, inputs[args.warmup:args.warmup + min(args.dt4_steps, args.steps)])
+        for rec in dt4["records"]:
+            log("dt^4 row at n=%d: exact-FG dH %+.4e, Table 1 prediction %+.4e; displacement-form dH %+.4e" %
+                (n4, rec["dH_exact"], rec["dH_predicted"], rec["dH_displacement"]))
 
-    # roofline of the dominant kernel: the bare sloppy Dslash hop inside CG
-    ms, launches, sites = prof
+    # roofline of the dominant kernel, the bare sloppy Dslash hop inside CG,
+    # from a separate profiled pass over the first timed starts
+    R.apply(tune_fg)
+    k_prof = min(2, args.steps)
+    ms, launches, sites = dslash_sample(R, U, inputs[args.warmup:args.warmup + k_prof], n_fg, args.prec, recon_fg)
     V = int(np.prod(R.dims))
-    bps = DSLASH_BYTES[(args.prec, 12 if args.prec == "mp16" else args.recon)]
-    key = "%s/%d" % (args.prec, 12 if args.prec == "mp16" else args.recon)
+    bps = DSLASH_BYTES[(args.prec, recon_fg)]
+    key = "%s/%d" % (args.prec, recon_fg)
     roof = None
     if launches:
         avg_s = ms / 1e3 / launches
@@ -769,17 +1021,23 @@ def main():
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     traffic_GBs=round(traffic / avg_s / 1e9, 1) if traffic else None,
                     kernel="bare even-odd Dslash hop t = D_oe g5 q of the CG (%s storage), %d output sites "
-                           "per launch; HIP events around 16 back-to-back launches after every solve" % (key, V // 2),
+                           "per launch; HIP events around 16 back-to-back launches after every solve of %d "
+                           "untimed FG trajectories" % (key, V // 2, k_prof),
                     algorithmic_bytes_per_launch=bytes_per_launch, avg_launch_us=round(avg_s * 1e6, 3),
                     launches_timed=launches)
 
-    R.apply(tune_fg)
-    large = None
+    large = large_other = None
     if not args.no_large:
-        large = dslash_roofline_large(R, U, args.prec, 12 if args.prec == "mp16" else args.recon)
-        log("Dslash %s on %s: %.1f GB/s (%.1f%% of HBM peak), %.2f us per launch" %
-            (args.prec, "x".join(map(str, large["lattice"])), large["achieved"], 100 * large["frac"],
-             large["avg_launch_us"]))
+        # the 32^3x64 workload keeps 12-real FP16 links (the faster format there,
+        # where the hop streams its links from HBM); the other format beside it
+        recon_l = 12 if args.prec == "mp16" else recon_fg
+        large = dslash_roofline_large(R, U, args.prec, recon_l)
+        if args.prec == "mp16":
+            large_other = dslash_roofline_large(R, U, args.prec, 18)
+        for lg in filter(None, (large, large_other)):
+            log("Dslash %s on %s: %.1f GB/s (%.1f%% of HBM peak), %.2f us per launch" %
+                (lg["kernel_key"], "x".join(map(str, lg["lattice"])), lg["achieved"], 100 * lg["frac"],
+                 lg["avg_launch_us"]))
     hasen = None
     if not args.no_hasenbusch:
         hasen = hasenbusch_leg(R, U, args.prec)
@@ -789,106 +1047,107 @@ def main():
     alpha_leg = None
     if args.tune_alpha > 0:
         R.apply(tune_fg)
-        alpha_leg = tune_alpha_leg(R, U, args.tune_alpha, args.n_omelyan)
+        alpha_leg = tune_alpha_leg(R, U, args.tune_alpha, args.asym_factor * nstar["pqpqp_fp64"][0])
         log("alpha tuning (PQPQP n=%d, %d trajectories): alpha %.4f, predicted <dH^2> %.3e -> %.3e, measured "
-            "%.3e -> %.3e" % (args.n_omelyan, args.tune_alpha, alpha_leg["alpha_tuned"],
+            "%.3e -> %.3e" % (alpha_leg["n"], args.tune_alpha, alpha_leg["alpha_tuned"],
                               alpha_leg["predicted_dH2"]["0.1932"], alpha_leg["predicted_dH2"]["tuned"],
                               alpha_leg["measured_dH2"]["0.1932"], alpha_leg["measured_dH2"]["tuned"]))
     md_leg = None
     if args.md_tol > 0:
-        # the timed starts again, the solves inside force evaluations at --md-tol
+        # the first timed starts again, the solves inside force evaluations at --md-tol
         R.apply(tune_fg)
+        k = min(k_leg or 4, args.steps)
         act_md = dataclasses.replace(act_fg, cg_tol_md=args.md_tol)
-        recs_md, sec_md, _ = R.run_leg(U, act_md, "FG", args.n_fg, inputs[args.warmup:])
+        recs_md, sec_md, _ = R.run_leg(U, act_md, "FG", n_fg, inputs[args.warmup:args.warmup + k])
         md_leg = summarise(recs_md)
-        md_leg.update(cg_tol_md=args.md_tol, n=args.n_fg, s_per_traj=sec_md / args.steps, trajectories=args.steps,
-                      speedup_vs_value=round(s_per_traj / (sec_md / args.steps), 3))
+        same = fg["dH"][:k]
+        md_leg.update(cg_tol_md=args.md_tol, n=n_fg, s_per_traj=sec_md / k,
+                      dH=[r["dH"] for r in recs_md], dH_single_tolerance_same_start=same,
+                      speedup_vs_value=round(s_per_traj / (sec_md / k), 3))
         if lf is not None:
-            # the FP64 leapfrog leg under the same tolerance policy
-            R.apply(tune_lf)
-            recs_lmd, sec_lmd, _ = R.run_leg(U, dataclasses.replace(R.action("fp64"), cg_tol_md=args.md_tol), "PQP",
-                                             args.n_lf, lf_inputs)
+            kl = min(4, len(lf_inputs))
+            R.apply(sched.get(("fp64", 18)))
+            recs_lmd, sec_lmd, _ = R.run_leg(U, dataclasses.replace(R.action("fp64"), cg_tol_md=args.md_tol),
+                                             "PQP", lf["n"], lf_inputs[:kl])
             lmd = summarise(recs_lmd)
-            lmd.update(n=args.n_lf, s_per_traj=sec_lmd / args.lf_steps, trajectories=args.lf_steps)
+            lmd.update(n=lf["n"], s_per_traj=sec_lmd / kl)
             md_leg["lf_fp64"] = lmd
             md_leg["speedup_vs_lf_fp64"] = round(lmd["s_per_traj"] / md_leg["s_per_traj"], 3)
-            log("LF-fp64 n=%d with MD solves at %.0e: %.4f s/traj  <dH^2>=%.4e; FG speedup %.2f" %
-                (args.n_lf, args.md_tol, lmd["s_per_traj"], lmd["mean_dH2"], md_leg["speedup_vs_lf_fp64"]))
-        log("FG-%s n=%d with MD solves at %.0e: %.4f s/traj  <dH^2>=%.4e (timed leg %.4e) iters=%.0f" %
-            (args.prec, args.n_fg, args.md_tol, md_leg["s_per_traj"], md_leg["mean_dH2"], fg["mean_dH2"],
-             md_leg["cg_iters_per_traj"]))
+        log("FG-%s n=%d with MD solves at %.0e: %.4f s/traj on %d starts (single tolerance %.4f), iters=%.0f" %
+            (args.prec, n_fg, args.md_tol, md_leg["s_per_traj"], k, s_per_traj, md_leg["cg_iters_per_traj"]))
     chain = None
     if args.chain_steps > 0:
         R.apply(tune_fg)
-        chain = chain_leg(R, U, act_fg, args.n_fg, args.chain_steps)
+        chain = chain_leg(R, U, act_fg, n_fg, args.chain_steps)
         log("on-device chain (fgi_hmc_run) FG-%s n=%d: %.4f s/traj (timed leg %.4f), accepted %s, dH %s" %
-            (args.prec, args.n_fg, chain["s_per_traj"], s_per_traj, chain["accepted"],
+            (args.prec, n_fg, chain["s_per_traj"], s_per_traj, chain["accepted"],
              ["%+.3e" % d for d in chain["dH"]]))
-    improved = None
+    improved = clover = stout = None
     if args.improved_steps > 0:
         k = min(args.improved_steps, args.steps)
-        improved = improved_gauge_leg(R, U, inputs[args.warmup:args.warmup + k], args.n_fg)
-        log("pure-gauge FG n=%d: Wilson %.4f s/traj, tree-level Symanzik %.4f s/traj (dH %s); gauge force call "
+        improved = improved_gauge_leg(R, U, inputs[args.warmup:args.warmup + k], n_fg)
+        log("pure-gauge FG n=%d: Wilson %.4f s/traj, tree-level Symanzik %.4f s/traj; gauge force call "
             "%.3f ms -> %.3f ms, rectangle kernel %.1f us = %.1f TFLOP/s FP64" %
-            (args.n_fg, improved["wilson"]["s_per_traj"], improved["symanzik"]["s_per_traj"],
-             ["%+.3e" % d for d in improved["symanzik"]["dH"]], improved["gauge_force_call_ms"]["wilson"],
-             improved["gauge_force_call_ms"]["symanzik"], improved["rect_force_kernel"]["us"],
-             improved["rect_force_kernel"]["achieved_TFLOPs"] or 0))
-    clover = None
-    if args.improved_steps > 0:
-        clover = clover_leg(R, U, inputs[args.warmup:args.warmup + 1], args.n_fg)
-        log("clover FG-fp64 n=%d at kappa %.3f, csw %.2f: %.3f s/traj, %d CG iterations (%.3f ms each), dH %+.3e; "
-            "Wilson FG-fp64 at the same kappa %.3f s/traj, %d iterations (%.3f ms each); mhat call %.3f -> %.3f ms" %
-            (args.n_fg, clover["kappa"], clover["csw"], clover["clover"]["s_per_traj"], clover["clover"]["cg_iters"],
-             clover["clover"]["ms_per_cg_iter"], clover["clover"]["dH"], clover["wilson"]["s_per_traj"],
-             clover["wilson"]["cg_iters"], clover["wilson"]["ms_per_cg_iter"], clover["wilson"]["mhat_call_ms"],
-             clover["clover"]["mhat_call_ms"]))
-        log("clover FG-mp32 (FP32 inner CG, FP64 defect correction): %.3f s/traj, %d CG iterations (%.3f ms each), "
-            "dH %+.3e" % (clover["clover_mp32"]["s_per_traj"], clover["clover_mp32"]["cg_iters"],
-                          clover["clover_mp32"]["ms_per_cg_iter"], clover["clover_mp32"]["dH"]))
-    stout = None
-    if args.improved_steps > 0:
+            (n_fg, improved["wilson"]["s_per_traj"], improved["symanzik"]["s_per_traj"],
+             improved["gauge_force_call_ms"]["wilson"], improved["gauge_force_call_ms"]["symanzik"],
+             improved["rect_force_kernel"]["us"], improved["rect_force_kernel"]["achieved_TFLOPs"] or 0))
+        clover = clover_leg(R, U, inputs[args.warmup:args.warmup + 1], n_fg)
+        log("clover FG n=%d at kappa %.3f, csw %.2f: FP64 %.3f s/traj (%d CG iterations), MP32 %.3f s/traj; "
+            "Wilson FP64 at the same kappa %.3f s/traj; mhat call %.3f -> %.3f ms" %
+            (n_fg, clover["kappa"], clover["csw"], clover["clover"]["s_per_traj"], clover["clover"]["cg_iters"],
+             clover["clover_mp32"]["s_per_traj"], clover["wilson"]["s_per_traj"],
+             clover["wilson"]["mhat_call_ms"], clover["clover"]["mhat_call_ms"]))
         stout = stout_leg(R, U)
-        log("stout smearing (rho %.2f, %d levels) at %s: %.1f us per level, adjoint %.1f us per level, %.3f ms per "
-            "force evaluation" % (stout["rho"], stout["n"], "x".join(map(str, R.dims)), stout["smear_us_per_level"],
+        log("stout smearing (rho %.2f, %d levels): %.1f us per level, adjoint %.1f us per level, %.3f ms per "
+            "force evaluation" % (stout["rho"], stout["n"], stout["smear_us_per_level"],
                                   stout["adjoint_us_per_level"], stout["per_force_evaluation_ms"]))
     batched = None
     if not args.no_batched:
         try:
             batched = batched_leg(R, args.prec, 8, args.batched_steps)
+            log("batched 96 chains: %.4f s per trajectory of all chains (%.1f chain-trajectories/s), chain by "
+                "chain %.3f s, speedup %.1fx" % (batched["s_per_batched_trajectory"],
+                                                 batched["chain_trajectories_per_s"], batched["s_chain_by_chain"],
+                                                 batched["speedup_vs_chain_by_chain"]))
         except R.fgi.FgiError as e:
             batched = dict(error=str(e))
             log("batched 96 chains: %s" % e)
-    if batched and "error" not in batched:
-        log("batched 96 chains: %.4f s per trajectory of all chains (%.1f chain-trajectories/s), chain by chain "
-            "%.3f s, speedup %.1fx" % (batched["s_per_batched_trajectory"], batched["chain_trajectories_per_s"],
-                                      batched["s_chain_by_chain"], batched["speedup_vs_chain_by_chain"]))
 
     cpu = None
     if not args.no_cpu_baseline:
-        iters_fp64 = (lf["cg_iters_per_traj"] / lf["solves_per_traj"] * fg["solves_per_traj"]) if lf else \
-            fg["cg_iters_per_traj"]
-        cpu = cpu_baseline(args, R.dims, iters_fp64, fg["solves_per_traj"], 2 * args.n_fg + args.n_fg)
-        log("cpu baseline %.1f s/traj on %d threads" % (cpu["value"], cpu["cores"]))
+        cpu = cpu_baseline(args, R.dims, lf, fg, n_fg)
+        log("cpu baseline %.1f s/traj (extrapolated) on %d threads; whole oracle trajectories: %s" %
+            (cpu["value"], cpu["cores"], {k: round(v["s_per_traj"], 3) for k, v in cpu["configs"].items()}))
 
+    speedup = None
+    if lf is not None:
+        speedup = dict(value=round(lf["s_per_traj"] / s_per_traj, 3),
+                       lf_fp64=dict(n=lf["n"], s_per_traj=lf["s_per_traj"], mean_dH2=lf["mean_dH2"],
+                                    mean_dH2_err=lf["mean_dH2_err"]),
+                       fg=dict(n=n_fg, s_per_traj=s_per_traj, mean_dH2=fg["mean_dH2"],
+                               mean_dH2_err=fg["mean_dH2_err"]),
+                       note="both legs at their own n*: the smallest step count whose <dH^2> in the committed "
+                            "calibration (32 trajectories per point) is at most %.3f (80%% acceptance)" % DH2_TARGET)
+    therm = dict(pure_gauge=args.therm_pg, beta_pg=args.beta_pg, nf2=args.therm, tau=args.therm_tau,
+                 n_final=therm_hist[-1]["n"] if therm_hist else None,
+                 plaquette_history=[round(h["plaq"], 6) for h in therm_hist if h["phase"] == "nf2"],
+                 accepted=[h["acc"] for h in therm_hist if h["phase"] == "nf2"])
     out = dict(metric=METRIC, value=round(s_per_traj, 5), unit="s/trajectory", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(s_per_traj * 1e3, 3), higher_is_better=False,
                scaling="weak", vs_baseline=None, dtype="f32 arithmetic, f16 storage, f64 reliable updates/"
                "Hamiltonian" if args.prec == "mp16" else args.prec, data="synthetic",
-               config=dict(workload="Nf=2 Wilson %s beta=%.2f kappa=%.4f, thermalised by %d FP64 HMC "
-                                    "trajectories from a seeded hot start; FG (%s, displacement form%s) at n=%d, "
-                                    "tau=1, CG tol %.0e" % ("x".join(map(str, R.dims)), args.beta, args.kappa,
-                                                            args.therm, args.prec,
-                                                            ", displaced solve started from the undisplaced "
-                                                            "solution" if args.fg_start else "", args.n_fg,
-                                                            args.tol),
-                           lattice=list(R.dims), integrator="FG", n_steps=args.n_fg, plaquette=round(plaq, 6)),
-               fg=fg, fg_exact=exact, lf_fp64=lf,
-               speedup_vs_lf_fp64=(round(lf["s_per_traj"] / s_per_traj, 3) if lf else None),
-               roofline=roof, roofline_32x32x32x64=large, hasenbusch_32x32x32x64=hasen, batched=batched,
+               config=dict(workload="Nf=2 Wilson %s beta=%.2f kappa=%.4f, thermalised from a seeded hot start "
+                                    "(%d pure-gauge trajectories at beta %.2f, then %d Nf=2 HMC trajectories); FG "
+                                    "(%s, displacement form%s) at its calibrated n*=%d, tau=1, CG tol %.0e" %
+                                    ("x".join(map(str, R.dims)), args.beta, args.kappa, args.therm_pg, args.beta_pg,
+                                     args.therm, args.prec, ", displaced solve started from the undisplaced "
+                                     "solution" if args.fg_start else "", n_fg, args.tol),
+                           lattice=list(R.dims), integrator="FG", n_steps=n_fg, plaquette=round(plaq, 6)),
+               fg=fg, legs=legs, speedup_vs_lf_fp64=speedup, fg_exact=exact, dt4_brackets=dt4, thermalisation=therm,
+               roofline=roof, roofline_32x32x32x64=large, roofline_32x32x32x64_other_links=large_other,
+               hasenbusch_32x32x32x64=hasen, batched=batched,
                alpha_tuning=alpha_leg, md_tolerance=md_leg, chain=chain, improved_gauge=improved, clover=clover,
-               stout=stout,
-               cpu_baseline=cpu)
+               stout=stout, cpu_baseline=cpu)
     print(json.dumps(out), flush=True)
 
 
