@@ -332,6 +332,36 @@ def dslash_roofline_large(R, U_therm, prec, recon):
                        "thermalised 16^3x32 field repeated 2x2x2x2" % (prec, recon, V // 2))
 
 
+def halo_leg(R, U_therm, reps=50, ranks=8):
+    """One GPU's share of the 32^3x64 lattice split over `ranks` GPUs in t: the
+    local 32^3x(64/ranks) slab of the thermalised field repeated 2x2x2x2, its
+    hopping term through face buffers (fgi_halo_time: face pack, interior
+    launch, face launches, one launch over all sites, and the plain local hop),
+    MP16 with FP16/12 and FP16/18 links.  The face transfer itself (xGMI) is not
+    part of a one-GPU run; its time at 153 GB/s per link is given beside."""
+    torch, fgi = R.torch, R.fgi
+    Ub, dims_b = tile_field(torch, U_therm, R.dims, 2)
+    Lt = dims_b[3] // ranks
+    loc = (dims_b[0], dims_b[1], dims_b[2], Lt)
+    V = int(np.prod(loc))
+    U = Ub[:, :V].contiguous()
+    del Ub
+    torch.cuda.empty_cache()
+    g = torch.Generator(device=R.dev)
+    g.manual_seed(R.args.seed + 450000)
+    src = torch.randn((V // 2, 4, 3), dtype=torch.complex128, device=R.dev, generator=g)
+    out = dict(local_lattice=list(loc), ranks=ranks, reps=reps)
+    for recon in (12, 18):
+        act = fgi.Action(beta=R.args.beta, kappa=R.args.kappa, prec="mp16", link_recon=recon)
+        t = R.ctx.halo_time(loc, act, U, src, reps)
+        t["xgmi_us_per_face_at_153GBs"] = round(t["halo_bytes"] / 153e9 * 1e6, 2)
+        t["hop_bytes_algorithmic"] = (V // 2) * DSLASH_BYTES[("mp16", recon)]
+        out["mp16/%d" % recon] = t
+    del U, src
+    torch.cuda.empty_cache()
+    return out
+
+
 def hasenbusch_leg(R, U_therm, prec):
     """The large-lattice workload: Nf=2 at kappa = 0.158 with Hasenbusch mass
     preconditioning (kappa' = 0.150) on three nested FG time scales (S_2
@@ -1038,6 +1068,15 @@ def main():
             log("Dslash %s on %s: %.1f GB/s (%.1f%% of HBM peak), %.2f us per launch" %
                 (lg["kernel_key"], "x".join(map(str, lg["lattice"])), lg["achieved"], 100 * lg["frac"],
                  lg["avg_launch_us"]))
+    halo = None
+    if not args.no_large:
+        halo = halo_leg(R, U)
+        for k in ("mp16/12", "mp16/18"):
+            t = halo[k]
+            log("t-split share %s %s: pack %.2f us, interior %.2f us, faces %.2f us (one launch %.2f us; local hop "
+                "%.2f us); %d-byte faces, %.2f us each over one xGMI link" %
+                ("x".join(map(str, halo["local_lattice"])), k, t["pack_us"], t["interior_us"], t["faces_us"],
+                 t["all_us"], t["local_us"], t["halo_bytes"], t["xgmi_us_per_face_at_153GBs"]))
     hasen = None
     if not args.no_hasenbusch:
         hasen = hasenbusch_leg(R, U, args.prec)
@@ -1145,6 +1184,7 @@ def main():
                            lattice=list(R.dims), integrator="FG", n_steps=n_fg, plaquette=round(plaq, 6)),
                fg=fg, legs=legs, speedup_vs_lf_fp64=speedup, fg_exact=exact, dt4_brackets=dt4, thermalisation=therm,
                roofline=roof, roofline_32x32x32x64=large, roofline_32x32x32x64_other_links=large_other,
+               halo_32x32x32x8=halo,
                hasenbusch_32x32x32x64=hasen, batched=batched,
                alpha_tuning=alpha_leg, md_tolerance=md_leg, chain=chain, improved_gauge=improved, clover=clover,
                stout=stout, cpu_baseline=cpu)

@@ -412,6 +412,51 @@ int fgi_trajectory_packed(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act
                           double tau, int nsteps, void* U, void* P, const void* eta1, const void* eta2, int pf_is_phi,
                           double* dH, fgi_stats* st, void* stream);
 
+/* ------------------------- domain decomposition in t: one GPU's share */
+/* The hopping term of Section 5's even-odd operator on a local sub-lattice of a
+ * lattice split over GPUs in t (g = the local extents, L_t even and >= 2; its
+ * sites in the user layouts of the local lattice).  The hops that cross the two
+ * local t-faces take their operands from halo buffers filled by the
+ * neighbouring ranks' fgi_halo_pack instead of from the local field, so the
+ * caller moves only the faces between GPUs (peer stores or send/recv): two
+ * buffers of fgi_halo_bytes each way per hop, 6 complex numbers per face site in
+ * the working precision (FP64 for FGI_FP64, FP32 for FGI_MP32 and FGI_MP16), in a
+ * layout only these calls read.  The antiperiodic t boundary travels in the
+ * signs: sign_lo = -1 on the rank holding global t = 0, sign_hi = -1 on the rank
+ * holding the last global t slice, +1 otherwise (one rank alone: both -1, which
+ * gives the antiperiodic local lattice).  The decomposed hop is bitwise the
+ * hop of the whole lattice (fgi_dslash in the same precision) on every rank's
+ * sites.  All pointers are device memory; in, out in the even/odd user layout;
+ * prec as fgi_dslash (act->link_recon applies to the sloppy links).
+ * FGI_EINVAL for a null or misaligned pointer, a bad parity, precision or sign,
+ * or L_t < 2.  Asynchronous on the stream. */
+int fgi_halo_bytes(const fgi_geom* g, int prec, size_t* bytes);
+/* to_lo (for the rank below): sign_lo (1 - g_4) psi at the local t = 0 sites;
+ * to_hi (for the rank above): sign_hi U_t(x)^+ (1 + g_4) psi at t = L_t - 1;
+ * psi = in, of parity in_parity. */
+int fgi_halo_pack(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* in,
+                  int in_parity, double sign_lo, double sign_hi, void* to_lo, void* to_hi, int prec, void* stream);
+/* out_{out_parity} = D in_{1 - out_parity} with the forward t hops of the
+ * t = L_t - 1 sites taken from from_hi (the rank above's to_lo) and the
+ * backward t hops of the t = 0 sites from from_lo (the rank below's to_hi).
+ * split = 1 computes the interior slices (1 <= t <= L_t - 2, which need no
+ * halo and can run while the faces travel) and then the two face slices in
+ * one launch; split = 0 one launch over every site.  Both give the same bits. */
+int fgi_dslash_halo(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* in,
+                    void* out, int out_parity, const void* from_lo, const void* from_hi, int split, int prec,
+                    void* stream);
+/* Kernel times of the decomposed hop at act->prec on a rank that is its own
+ * neighbour (HIP events around reps launches each, after one untimed launch):
+ * the face pack, the interior launch, the face launch, one launch over every
+ * site, and the plain local hop (fgi_dslash's kernel) for comparison. */
+typedef struct {
+    double pack_us, interior_us, faces_us, all_us, local_us;
+    long face_sites;  /* F = V/2 / L_t face sites per parity and face */
+    long halo_bytes;  /* bytes of one halo buffer */
+} fgi_halo_timing;
+int fgi_halo_time(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act, const void* U, const void* in, int reps,
+                  fgi_halo_timing* out, void* stream);
+
 /* ------------------------------------------- allocation-free operator */
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64

@@ -448,7 +448,7 @@ int fgi_destroy(fgi_ctx* ctx) {
                           &c.hs_dxo, &c.hs_dyo, &c.hs_zero, &c.hs_t1, &c.cl_sig, &c.cl_blk, &c.cl_blk2,
                           &c.cl_blk32, &c.cl_s32, &c.cl_fh,
                           &c.cl_ld, &c.cl_to, &c.cl_te, &c.cl_ue, &c.cl_r, &c.cl_p, &c.cl_ap, &c.cl_t,
-                          &c.cl_ye, &c.cl_xo, &c.cl_yo, &c.br_jp, &c.br_jf, &c.br_jj};
+                          &c.cl_ye, &c.cl_xo, &c.cl_yo, &c.br_jp, &c.br_jf, &c.br_jj, &c.halo_a, &c.halo_b};
         for (DevBuf* b : bufs) b->release();
         for (hipEvent_t e : c.ev_pool) hipEventDestroy(e);
         for (GraphEntry& e : c.graphs) hipGraphExecDestroy(e.exec);
@@ -738,6 +738,166 @@ int fgi_dslash(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const vo
             convert_spinor(c, g, f.sp, so, P64, SpinorPtr{vout, nullptr});
         }
         unpack_even_spinor(c, g, vout, out);
+    });
+}
+
+// ------------------------------------------ t-decomposed hopping term ---
+namespace {
+Geom halo_geom(const fgi_geom* gg) {
+    if (!gg) throw Error(FGI_EINVAL, "null geometry");
+    Geom g = make_geom(gg->dims);
+    if (g.L[3] < 2) throw Error(FGI_EINVAL, "the local t extent must be at least 2");
+    return g;
+}
+
+// the sloppy (or FP64) operator and the input converted to it, for one halo call
+struct HaloOp {
+    FermionOp op;
+    SpinorPtr in;
+    int prec;
+};
+
+HaloOp halo_setup(Ctx& c, const Geom& g, const fgi_action* act, const void* U, const void* in, int prec) {
+    fgi_action a = *act;
+    a.prec = prec;
+    const int sp = sloppy_prec(&a), rc = sloppy_recon(&a);
+    d2* u = (d2*)c.gauge.get(gauge_bytes(g));
+    pack_gauge(c, g, U, u);
+    d2* vin = (d2*)c.tmp_e.get(spinor_bytes(g));
+    pack_even_spinor(c, g, in, vin);  // same layout for either parity
+    if (sp == P64) return HaloOp{FermionOp{nullptr, a.kappa, u, P64, 18}, SpinorPtr{vin, nullptr}, P64};
+    void* us = c.sloppy.get(sloppy_bytes(g));
+    make_sloppy(c, g, u, us, sp, rc);
+    const size_t nb = sizeof(float) * 24 * (size_t)g.Vh;
+    float* norms = (float*)c.s_norms.get(sizeof(float) * 3 * (size_t)g.Vh);
+    SpinorPtr si{c.s_p.get(nb), norms};
+    convert_spinor(c, g, P64, SpinorPtr{vin, nullptr}, sp, si);
+    return HaloOp{FermionOp{nullptr, a.kappa, us, sp, rc}, si, sp};
+}
+
+void halo_checks(const fgi_action* act, const void* U, const void* in, int prec) {
+    check_action(act);
+    need(U, "U", 16);
+    need(in, "in", 16);
+    if (prec < FGI_FP64 || prec > FGI_MP16) throw Error(FGI_EINVAL, "bad precision");
+}
+}  // namespace
+
+int fgi_halo_bytes(const fgi_geom* gg, int prec, size_t* bytes) {
+    return guarded([&] {
+        Geom g = halo_geom(gg);
+        if (prec < FGI_FP64 || prec > FGI_MP16) throw Error(FGI_EINVAL, "bad precision");
+        if (!bytes) throw Error(FGI_EINVAL, "null bytes");
+        *bytes = halo_bytes(g, prec == FGI_FP64 ? P64 : P32);
+    });
+}
+
+int fgi_halo_pack(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* in,
+                  int in_parity, double sign_lo, double sign_hi, void* to_lo, void* to_hi, int prec, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        Geom g = halo_geom(gg);
+        halo_checks(act, U, in, prec);
+        need(to_lo, "to_lo", 8);
+        need(to_hi, "to_hi", 8);
+        if (in_parity != 0 && in_parity != 1) throw Error(FGI_EINVAL, "parity must be 0 or 1");
+        if (!((sign_lo == 1.0 || sign_lo == -1.0) && (sign_hi == 1.0 || sign_hi == -1.0)))
+            throw Error(FGI_EINVAL, "face signs must be +1 or -1");
+        StreamScope ss(c, stream);
+        HaloOp h = halo_setup(c, g, act, U, in, prec);
+        h.op.g = &g;
+        halo_pack(c, h.op, h.prec, in_parity, h.in, sign_lo, sign_hi, to_lo, to_hi);
+    });
+}
+
+int fgi_dslash_halo(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* in,
+                    void* out, int out_parity, const void* from_lo, const void* from_hi, int split, int prec,
+                    void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        Geom g = halo_geom(gg);
+        halo_checks(act, U, in, prec);
+        need(out, "out", 16);
+        need(from_lo, "from_lo", 8);
+        need(from_hi, "from_hi", 8);
+        if (out_parity != 0 && out_parity != 1) throw Error(FGI_EINVAL, "parity must be 0 or 1");
+        if (split != 0 && split != 1) throw Error(FGI_EINVAL, "split must be 0 or 1");
+        StreamScope ss(c, stream);
+        HaloOp h = halo_setup(c, g, act, U, in, prec);
+        h.op.g = &g;
+        d2* vout = (d2*)c.X.get(spinor_bytes(g));
+        if (h.prec == P64) {
+            SpinorPtr so{vout, nullptr};
+            if (split) {
+                dslash_halo(c, h.op, P64, out_parity, h.in, so, from_lo, from_hi, 1);
+                dslash_halo(c, h.op, P64, out_parity, h.in, so, from_lo, from_hi, 2);
+            } else {
+                dslash_halo(c, h.op, P64, out_parity, h.in, so, from_lo, from_hi, 0);
+            }
+        } else {
+            const size_t nb = sizeof(float) * 24 * (size_t)g.Vh;
+            float* norms = (float*)c.s_norms.get(sizeof(float) * 3 * (size_t)g.Vh);
+            SpinorPtr so{c.s_q.get(nb), norms + g.Vh};
+            if (split) {
+                dslash_halo(c, h.op, h.prec, out_parity, h.in, so, from_lo, from_hi, 1);
+                dslash_halo(c, h.op, h.prec, out_parity, h.in, so, from_lo, from_hi, 2);
+            } else {
+                dslash_halo(c, h.op, h.prec, out_parity, h.in, so, from_lo, from_hi, 0);
+            }
+            convert_spinor(c, g, h.prec, so, P64, SpinorPtr{vout, nullptr});
+        }
+        unpack_even_spinor(c, g, vout, out);
+    });
+}
+
+int fgi_halo_time(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const void* U, const void* in,
+                  int reps, fgi_halo_timing* out, void* stream) {
+    return guarded([&] {
+        Ctx& c = ctx_of(ctx);
+        Geom g = halo_geom(gg);
+        halo_checks(act, U, in, act ? act->prec : FGI_FP64);
+        if (!out) throw Error(FGI_EINVAL, "null output");
+        if (reps < 1 || reps > 100000) throw Error(FGI_EINVAL, "reps must be in [1, 100000]");
+        StreamScope ss(c, stream);
+        HaloOp h = halo_setup(c, g, act, U, in, act->prec);
+        h.op.g = &g;
+        const size_t hb = halo_bytes(g, h.prec == P64 ? P64 : P32);
+        void* ha = c.halo_a.get(hb);
+        void* hb_ = c.halo_b.get(hb);
+        SpinorPtr so;
+        if (h.prec == P64) {
+            so = SpinorPtr{c.X.get(spinor_bytes(g)), nullptr};
+        } else {
+            const size_t nb = sizeof(float) * 24 * (size_t)g.Vh;
+            float* norms = (float*)c.s_norms.get(sizeof(float) * 3 * (size_t)g.Vh);
+            so = SpinorPtr{c.s_q.get(nb), norms + g.Vh};
+        }
+        // one rank holding the whole t ring: its faces are its own neighbours
+        halo_pack(c, h.op, h.prec, 0, h.in, -1.0, -1.0, ha, hb_);
+        hipEvent_t e0, e1;
+        FGI_HIP(hipEventCreate(&e0));
+        FGI_HIP(hipEventCreate(&e1));
+        auto timed = [&](auto body) {
+            body();  // untimed first launch
+            FGI_HIP(hipEventRecord(e0, c.stream));
+            for (int k = 0; k < reps; k++) body();
+            FGI_HIP(hipEventRecord(e1, c.stream));
+            FGI_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            FGI_HIP(hipEventElapsedTime(&ms, e0, e1));
+            return 1e3 * ms / reps;
+        };
+        fgi_halo_timing t{};
+        t.pack_us = timed([&] { halo_pack(c, h.op, h.prec, 0, h.in, -1.0, -1.0, ha, hb_); });
+        t.interior_us = timed([&] { dslash_halo(c, h.op, h.prec, 1, h.in, so, hb_, ha, 1); });
+        t.faces_us = timed([&] { dslash_halo(c, h.op, h.prec, 1, h.in, so, hb_, ha, 2); });
+        t.all_us = timed([&] { dslash_halo(c, h.op, h.prec, 1, h.in, so, hb_, ha, 0); });
+        t.local_us = timed([&] { dslash(c, h.op, 1, h.prec, h.in, h.prec, so); });
+        t.face_sites = g.Vh / g.L[3];
+        t.halo_bytes = (long)hb;
+        FGI_HIP(hipEventDestroy(e0));
+        FGI_HIP(hipEventDestroy(e1));
+        *out = t;
     });
 }
 

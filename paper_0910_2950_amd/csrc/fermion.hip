@@ -1648,4 +1648,220 @@ CGResult cg_solve(Ctx& c, const FermionOp& op64, const FermionOp& ops, int sprec
     return cg_run<P16, P32>(c, op64, ops, phi, X, tol, maxiter, guess);
 }
 
+// ============================================ t-decomposed hopping term ======
+// One GPU's share of a lattice split over GPUs in t: its local sub-lattice is
+// an ordinary (L0, L1, L2, Lt) checkerboard, and the hops across its two
+// t-faces go through halo buffers instead of the local field.  Face sites form
+// one contiguous range of F = Vh / Lt checkerboard indices per t slice (t is
+// the slowest coordinate), and the site (x, y, z) of the t = 0 face and of the
+// t = Lt - 1 face share the face index f = s - t F, also across neighbouring
+// ranks (Lt even keeps the local and global parities equal).
+//
+// The pack kernel forms, for an input field of parity p_in, what each
+// neighbour rank needs from this one:
+//   to_lo[f] = sign_lo (1 - g4) psi(x, t = 0)                (projected half spinor)
+//   to_hi[f] = sign_hi U_t(x)^+ (1 + g4) psi(x, t = Lt - 1)   (already carried by its link)
+// as 2 x 3 complex numbers in the working precision R.  The rank below reads
+// our to_lo as its from_hi, the rank above our to_hi as its from_lo.  The
+// signs carry the antiperiodic boundary: -1 on the lowest rank's to_lo and on
+// the highest rank's to_hi, +1 elsewhere.  The halo hop then applies exactly
+// the arithmetic of the local kernel's t hops (the link product of the forward
+// hop, the spin reconstruction of both), so a decomposed hop is bitwise the
+// hop of the whole lattice.
+struct HaloArgs {
+    Geom g;
+    int p;       // output parity (hop) or input parity (pack)
+    int s0, s1;  // hop: output sites s0 <= s < s1, or with faces the two face slices
+    int faces;
+    const void* links;
+    SpinorPtr in, out;
+    const void* lo;  // hop: from_lo (backward t hops at t = 0);  pack: to_lo
+    const void* hi;  // hop: from_hi (forward t hops at t = Lt-1); pack: to_hi
+    double sign_lo, sign_hi;
+};
+
+template <typename R> struct HaloT;
+template <> struct HaloT<double> { typedef d2 T; };
+template <> struct HaloT<float> { typedef f2 T; };
+
+// component k = 3 j + a of face entry f: SoA over the F face sites
+template <typename R>
+__device__ __forceinline__ void halo_store(void* buf, int F, int f, const cx<R> v[2][3], R sign) {
+    typedef typename HaloT<R>::T T;
+    T* b = (T*)buf;
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) b[(size_t)(3 * j + a) * F + f] = T{sign * v[j][a].re, sign * v[j][a].im};
+}
+
+template <typename R>
+__device__ __forceinline__ void halo_load(const void* buf, int F, int f, cx<R> v[2][3]) {
+    typedef typename HaloT<R>::T T;
+    const T* b = (const T*)buf;
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const T x = b[(size_t)(3 * j + a) * F + f];
+            v[j][a] = {x.x, x.y};
+        }
+}
+
+template <int PIN, int PL, int RECON>
+__global__ void __launch_bounds__(DBS) k_halo_pack(HaloArgs A) {
+    typedef typename Real<PIN == P64 ? P64 : P32>::T R;
+    const Geom& g = A.g;
+    const int F = g.Vh / g.L[3];
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    LoadPlain<PIN, 0, R> ld{A.in};
+    cx<R> psi[4][3], h[2][3];
+    {   // t = 0: the forward hop of the rank below lands here
+        typename LoadPlain<PIN, 0, R>::Raw rs;
+        ld.fetch(f, g.Vh, rs);
+        const R w = ld.get(rs, psi);
+        spin_proj<3, -1>(psi, h);
+        halo_store<R>(const_cast<void*>(A.lo), F, f, h, w * R(A.sign_lo));
+    }
+    {   // t = Lt - 1: the backward hop of the rank above, link product included
+        const int s = (g.L[3] - 1) * F + f;
+        typename LoadPlain<PIN, 0, R>::Raw rs;
+        ld.fetch(s, g.Vh, rs);
+        const R w = ld.get(rs, psi);
+        spin_proj<3, +1>(psi, h);
+        RawLink<PL, RECON> rl;
+        fetch_link<PL, RECON, false>(A.links, 3, A.p, s, g.Vh, rl);
+        const M3<R> u = LinkIO<PL, RECON, R>::decode(rl);
+        cx<R> uh[2][3];
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+                uh[j][a] = cdot3c(u.e[0][a], h[j][0], u.e[1][a], h[j][1], u.e[2][a], h[j][2]);
+        halo_store<R>(const_cast<void*>(A.hi), F, f, uh, w * R(A.sign_hi));
+    }
+}
+
+template <int PIN, int POUT, int PL, int RECON>
+__global__ void __launch_bounds__(DBS) k_dslash_halo(HaloArgs A) {
+    typedef typename Real<PIN == P64 ? P64 : P32>::T R;
+    const Geom& g = A.g;
+    const int F = g.Vh / g.L[3];
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    // faces: threads 0..F-1 take the t = 0 slice, F..2F-1 the t = Lt-1 slice
+    const int s = A.faces ? (i < F ? i : g.Vh - 2 * F + i) : A.s0 + i;
+    if (A.faces ? i >= 2 * F : s >= A.s1) return;
+    const int p = A.p;
+    LoadPlain<PIN, 0, R> ld{A.in};
+    const Coord c = cb_coords(g, p, s);
+    cx<R> acc[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) acc[i][k] = {R(0), R(0)};
+    hop<0, PL, RECON, false>(g, p, s, c, A.links, ld, acc);
+    hop<1, PL, RECON, false>(g, p, s, c, A.links, ld, acc);
+    hop<2, PL, RECON, false>(g, p, s, c, A.links, ld, acc);
+    hop<3, PL, RECON, false>(g, p, s, c, A.links, ld, acc);
+    hop<4, PL, RECON, false>(g, p, s, c, A.links, ld, acc);
+    hop<5, PL, RECON, false>(g, p, s, c, A.links, ld, acc);
+    if (c.c[3] == g.L[3] - 1) {  // forward t hop: the projected spinor of the rank above
+        cx<R> h[2][3];
+        halo_load<R>(A.hi, F, s - (g.L[3] - 1) * F, h);
+        RawLink<PL, RECON> rl;
+        fetch_link<PL, RECON, false>(A.links, 3, p, s, g.Vh, rl);
+        const M3<R> u = LinkIO<PL, RECON, R>::decode(rl);
+        cx<R> uh[2][3];
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+                uh[j][a] = cdot3(u.e[a][0], h[j][0], u.e[a][1], h[j][1], u.e[a][2], h[j][2]);
+        spin_recon_acc<3, -1>(acc, uh, R(1));
+    } else {
+        hop<6, PL, RECON, false>(g, p, s, c, A.links, ld, acc);
+    }
+    if (c.c[3] == 0) {  // backward t hop: the link product of the rank below
+        cx<R> uh[2][3];
+        halo_load<R>(A.lo, F, s, uh);
+        spin_recon_acc<3, +1>(acc, uh, R(1));
+    } else {
+        hop<7, PL, RECON, false>(g, p, s, c, A.links, ld, acc);
+    }
+    SpinorIO<POUT, R>::store(A.out, s, g.Vh, acc);
+}
+
+size_t halo_bytes(const Geom& g, int prec) {
+    return (size_t)6 * (g.Vh / g.L[3]) * (prec == P64 ? sizeof(d2) : sizeof(f2));
+}
+
+template <int PIN, int POUT>
+static void halo_launch(Ctx& c, const FermionOp& op, HaloArgs& a, bool pack) {
+    const int n = pack ? a.g.Vh / a.g.L[3] : (a.faces ? 2 * (a.g.Vh / a.g.L[3]) : a.s1 - a.s0);
+    if (n <= 0) return;
+    const int nb = nblk(n, DBS);
+#define FGI_HALO_K(PL_, RC_)                                                                                   \
+    do {                                                                                                         \
+        if (pack) hipLaunchKernelGGL((k_halo_pack<PIN, PL_, RC_>), dim3(nb), dim3(DBS), 0, c.stream, a);         \
+        else hipLaunchKernelGGL((k_dslash_halo<PIN, POUT, PL_, RC_>), dim3(nb), dim3(DBS), 0, c.stream, a);      \
+    } while (0)
+    if constexpr (PIN == P64) {
+        FGI_HALO_K(P64, 18);
+    } else {
+        if (op.prec == P32 && op.recon == 18) FGI_HALO_K(P32, 18);
+        else if (op.prec == P32) FGI_HALO_K(P32, 12);
+        else if (op.prec == P16 && op.recon == 18) FGI_HALO_K(P16, 18);
+        else if (op.prec == P16) FGI_HALO_K(P16, 12);
+        else throw Error(-1, "sloppy spinors need sloppy links");
+    }
+#undef FGI_HALO_K
+    FGI_LAUNCH_CHECK();
+}
+
+static HaloArgs halo_args(const FermionOp& op) {
+    HaloArgs a{};
+    a.g = *op.g;
+    a.links = op.links;
+    return a;
+}
+
+void halo_pack(Ctx& c, const FermionOp& op, int prec, int in_parity, SpinorPtr in, double sign_lo, double sign_hi,
+               void* to_lo, void* to_hi) {
+    HaloArgs a = halo_args(op);
+    a.p = in_parity;
+    a.in = in;
+    a.lo = to_lo;
+    a.hi = to_hi;
+    a.sign_lo = sign_lo;
+    a.sign_hi = sign_hi;
+    if (prec == P64) halo_launch<P64, P64>(c, op, a, true);
+    else if (prec == P32) halo_launch<P32, P32>(c, op, a, true);
+    else halo_launch<P16, P16>(c, op, a, true);
+}
+
+// part: 0 every site, 1 the interior (1 <= t <= Lt - 2), 2 the two face slices (one launch)
+void dslash_halo(Ctx& c, const FermionOp& op, int prec, int out_parity, SpinorPtr in, SpinorPtr out,
+                 const void* from_lo, const void* from_hi, int part) {
+    HaloArgs a = halo_args(op);
+    a.p = out_parity;
+    a.in = in;
+    a.out = out;
+    a.lo = from_lo;
+    a.hi = from_hi;
+    const int F = a.g.Vh / a.g.L[3];
+    auto run = [&](int s0, int s1, int faces) {
+        a.s0 = s0;
+        a.s1 = s1;
+        a.faces = faces;
+        if (prec == P64) halo_launch<P64, P64>(c, op, a, false);
+        else if (prec == P32) halo_launch<P32, P32>(c, op, a, false);
+        else halo_launch<P16, P16>(c, op, a, false);
+    };
+    if (part == 0) run(0, a.g.Vh, 0);
+    else if (part == 1) run(F, a.g.Vh - F, 0);
+    else if (a.g.L[3] == 2) run(0, a.g.Vh, 0);  // both slices are faces
+    else run(0, 0, 1);
+}
+
 }  // namespace fgi

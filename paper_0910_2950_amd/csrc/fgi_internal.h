@@ -107,6 +107,7 @@ struct Ctx {
     DevBuf cl_sig, cl_blk, cl_blk2, cl_blk32, cl_s32, cl_fh, cl_ld, cl_to, cl_te, cl_ue, cl_r, cl_p, cl_ap, cl_t, cl_ye, cl_xo, cl_yo;
     DevBuf cdesc, bstate, bscal, bh0, bh1, bres;  // batched chains
     DevBuf br_jp, br_jf, br_jj;   // force gradients of the dt^4 brackets
+    DevBuf halo_a, halo_b;        // face buffers of the t-decomposed hop (timing)
     CGState* host_bstates = nullptr;          // pinned [host_b_cap]
     double* host_bscal = nullptr;             // pinned [host_b_cap]
     size_t host_b_cap = 0;
@@ -293,6 +294,12 @@ int pf_density_partials(Ctx&, const Geom&, const d2* phi, const d2* X, const d2*
 void spinor_copy(Ctx&, const Geom&, const d2* src, d2* dst);
 // b = a with storage conversion (P64/P32/P16 -> P64/P32/P16)
 void convert_spinor(Ctx&, const Geom&, int prec_a, SpinorPtr a, int prec_b, SpinorPtr b);
+// t-decomposed hopping term (one GPU's share of a lattice split in t)
+size_t halo_bytes(const Geom&, int prec);
+void halo_pack(Ctx&, const FermionOp&, int prec, int in_parity, SpinorPtr in, double sign_lo, double sign_hi,
+               void* to_lo, void* to_hi);
+void dslash_halo(Ctx&, const FermionOp&, int prec, int out_parity, SpinorPtr in, SpinorPtr out, const void* from_lo,
+                 const void* from_hi, int part);
 
 // batched fermion operations (all chains of B; FP64 fields concatenated chain by chain)
 void pf_heatbath_b(Ctx&, const Batch&, const FermionOp& op64, const d2* eta, d2* phi);

@@ -73,6 +73,15 @@ class fgi_tuning(ctypes.Structure):
                     sched_us_per_iter=list(self.sched_us_per_iter), batch_ms_per_solve=list(self.batch_ms_per_solve))
 
 
+class fgi_halo_timing(ctypes.Structure):
+    _fields_ = [("pack_us", ctypes.c_double), ("interior_us", ctypes.c_double), ("faces_us", ctypes.c_double),
+                ("all_us", ctypes.c_double), ("local_us", ctypes.c_double), ("face_sites", ctypes.c_long),
+                ("halo_bytes", ctypes.c_long)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 def philox4x32_10(ctr, key):
     """The library's Philox4x32-10 of one counter (host)."""
     c = (ctypes.c_uint32 * 4)(*[int(x) & 0xffffffff for x in ctr])
@@ -120,6 +129,10 @@ SIGNATURES = {
     "fgi_dslash": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _i, _i, _vp]),
     "fgi_mhat": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _i, _vp]),
     "fgi_mhat_packed_noalloc": (_i, [_vp, _P(fgi_geom), ctypes.c_double, _vp, _vp, _vp, _i, _vp]),
+    "fgi_halo_bytes": (_i, [_P(fgi_geom), _i, _P(ctypes.c_size_t)]),
+    "fgi_halo_pack": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _i, _d, _d, _vp, _vp, _i, _vp]),
+    "fgi_dslash_halo": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _i, _vp, _vp, _i, _i, _vp]),
+    "fgi_halo_time": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _i, _P(fgi_halo_timing), _vp]),
     "fgi_cg_solve": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _P(fgi_stats), _vp]),
     "fgi_pf_heatbath": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _vp, _vp]),
     "fgi_pf_action": (_i, [_vp, _P(fgi_geom), _P(fgi_action), _vp, _vp, _P(_d), _P(fgi_stats), _vp]),
@@ -422,6 +435,42 @@ class Context:
                                 _ptr(inp, torch.complex128, se, "in"), _ptr(out, torch.complex128, se, "out"),
                                 int(out_parity), PREC[prec], _stream()))
         return out
+
+    # t-decomposed hopping term (one GPU's share of a lattice split in t)
+    def halo_bytes(self, dims, prec="fp64"):
+        n = ctypes.c_size_t()
+        _check(lib().fgi_halo_bytes(_geom(dims), PREC[prec], ctypes.byref(n)))
+        return n.value
+
+    def _halo_buf(self, t, n, name):
+        if t.dtype != torch.uint8 or t.numel() != n or not t.is_contiguous():
+            raise FgiError(FGI_EINVAL, "%s: halo buffer of the wrong size, dtype or stride" % name)
+        return ctypes.c_void_p(t.data_ptr())
+
+    def halo_pack(self, dims, act, U, inp, in_parity, sign_lo, sign_hi, to_lo, to_hi, prec="fp64"):
+        su, _, se = self._shapes(dims)
+        n = self.halo_bytes(dims, prec)
+        _check(lib().fgi_halo_pack(self.h, _geom(dims), ctypes.byref(act.c()), _ptr(U, torch.complex128, su, "U"),
+                                   _ptr(inp, torch.complex128, se, "in"), int(in_parity), float(sign_lo),
+                                   float(sign_hi), self._halo_buf(to_lo, n, "to_lo"), self._halo_buf(to_hi, n, "to_hi"),
+                                   PREC[prec], _stream()))
+
+    def dslash_halo(self, dims, act, U, inp, out_parity, from_lo, from_hi, split=True, prec="fp64", out=None):
+        su, _, se = self._shapes(dims)
+        n = self.halo_bytes(dims, prec)
+        out = torch.empty(se, dtype=torch.complex128, device=U.device) if out is None else out
+        _check(lib().fgi_dslash_halo(self.h, _geom(dims), ctypes.byref(act.c()), _ptr(U, torch.complex128, su, "U"),
+                                     _ptr(inp, torch.complex128, se, "in"), _ptr(out, torch.complex128, se, "out"),
+                                     int(out_parity), self._halo_buf(from_lo, n, "from_lo"),
+                                     self._halo_buf(from_hi, n, "from_hi"), int(bool(split)), PREC[prec], _stream()))
+        return out
+
+    def halo_time(self, dims, act, U, inp, reps=50):
+        su, _, se = self._shapes(dims)
+        t = fgi_halo_timing()
+        _check(lib().fgi_halo_time(self.h, _geom(dims), ctypes.byref(act.c()), _ptr(U, torch.complex128, su, "U"),
+                                   _ptr(inp, torch.complex128, se, "in"), int(reps), ctypes.byref(t), _stream()))
+        return t.as_dict()
 
     def mhat(self, dims, act, U, inp, dagger=False, out=None):
         su, _, se = self._shapes(dims)

@@ -1,0 +1,138 @@
+"""GPU: the hopping term of a lattice split over GPUs in t, one rank's share at
+a time (fgi_halo_pack, fgi_dslash_halo).  The ranks live on one GPU here and
+exchange their face buffers by passing them to each other's call, as peer
+stores over xGMI would; the decomposed hop must be bitwise the whole
+lattice's hop with FP64 and FP32 spinors (with FP16 spinors within one FP16
+step of the per-site scale), and match the oracle's Dslash (FP64).
+
+The global lattices split into 2, 3 and 4 ranks with local t extents of 4, 4
+and 2 (the last has no interior slice), with both output parities, every
+sloppy link format, one launch or the interior/face split; a single rank that
+is its own neighbour reproduces the antiperiodic local lattice.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_0910_2950_amd import synth
+from paper_0910_2950_amd.fgi import Action, Context, FgiError
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+SPLITS = [((4, 4, 4, 8), 2), ((6, 4, 4, 12), 3), ((4, 6, 4, 8), 4)]
+PRECS = [("fp64", 18), ("mp32", 18), ("mp32", 12), ("mp16", 18), ("mp16", 12)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def parity_of(dims):
+    V = synth.volume(dims)
+    c = np.stack(np.unravel_index(np.arange(V), dims[::-1])[::-1], axis=1)
+    return c.sum(axis=1) % 2
+
+
+def decomposed(ctx, dims, R, act, U, src, out_parity, prec, split):
+    """Rank r holds t slices [r Lt, (r+1) Lt): a contiguous slice of the links
+    and of each parity's site list (t is the slowest coordinate, Lt even)."""
+    Lt = dims[3] // R
+    loc = (dims[0], dims[1], dims[2], Lt)
+    V, Vh = synth.volume(loc), synth.volume(loc) // 2
+    n = ctx.halo_bytes(loc, prec)
+    to_lo = [torch.zeros(n, dtype=torch.uint8, device=DEV) for _ in range(R)]
+    to_hi = [torch.zeros(n, dtype=torch.uint8, device=DEV) for _ in range(R)]
+    Ur = [U[:, r * V:(r + 1) * V].contiguous() for r in range(R)]
+    sr = [src[r * Vh:(r + 1) * Vh].contiguous() for r in range(R)]
+    for r in range(R):
+        ctx.halo_pack(loc, act, Ur[r], sr[r], 1 - out_parity, -1.0 if r == 0 else 1.0,
+                      -1.0 if r == R - 1 else 1.0, to_lo[r], to_hi[r], prec)
+    outs = [ctx.dslash_halo(loc, act, Ur[r], sr[r], out_parity, to_hi[(r - 1) % R], to_lo[(r + 1) % R], split,
+                            prec) for r in range(R)]
+    return torch.cat(outs)
+
+
+def fp16_ulp_check(got, whole, dims, R):
+    """FP16 spinors: the decode's scale multiply is a candidate for fusing into
+    the spin projection's adds, and the halo kernels (another kernel, and the
+    pack kernel for the face terms) may fuse it where the whole-lattice kernel
+    does not, one FP32 rounding apart; after the output's rounding to FP16 with
+    its per-site scale that is at most one FP16 step of the site's largest
+    component (a handful of sites in these runs)."""
+    g, w = got.cpu().numpy().reshape(-1, 12), whole.cpu().numpy().reshape(-1, 12)
+    scale = np.max(np.maximum(np.abs(w.real), np.abs(w.imag)), axis=1)
+    d = np.max(np.maximum(np.abs((g - w).real), np.abs((g - w).imag)), axis=1)
+    assert np.all(d <= 2.0 ** -10 * scale + 1e-300), (np.max(d / scale), dims, R)
+    return np.nonzero(d)[0]
+
+
+@pytest.mark.parametrize("dims,R", SPLITS)
+@pytest.mark.parametrize("prec,recon", PRECS)
+def test_decomposed_hop_is_the_whole_hop(ctx, dims, R, prec, recon):
+    U = dev(synth.haar_su3(synth.rng(31), 4 * synth.volume(dims)).reshape(4, -1, 3, 3))
+    src = dev(synth.gaussian_noise(synth.rng(32), dims))
+    act = Action(beta=5.6, kappa=0.155, prec=prec, link_recon=recon)
+    for out_parity in (1, 0):
+        whole = ctx.dslash(dims, act, U, src, out_parity, prec)
+        for split in (True, False):
+            got = decomposed(ctx, dims, R, act, U, src, out_parity, prec, split)
+            if prec != "mp16":  # FP64 and FP32 spinors: the same bits
+                assert torch.equal(got, whole), (dims, R, prec, recon, out_parity, split)
+            else:  # FP16 spinors: every site within one FP16 step
+                fp16_ulp_check(got, whole, dims, R)
+
+
+@pytest.mark.parametrize("dims,R", SPLITS)
+def test_decomposed_hop_matches_oracle(ctx, orc, dims, R):
+    U0 = synth.haar_su3(synth.rng(33), 4 * synth.volume(dims)).reshape(4, -1, 3, 3)
+    src0 = synth.gaussian_noise(synth.rng(34), dims)
+    par = parity_of(dims)
+    full = np.zeros((synth.volume(dims), 4, 3), complex)
+    full[par == 0] = src0
+    ref = orc.dhop(dims, U0, full)[par == 1]
+    got = decomposed(ctx, dims, R, Action(beta=5.6, kappa=0.155), dev(U0), dev(src0), 1, "fp64", True).cpu().numpy()
+    assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-14
+
+
+def test_single_rank_ring_is_the_local_lattice(ctx):
+    dims = (4, 4, 6, 6)
+    U = dev(synth.haar_su3(synth.rng(35), 4 * synth.volume(dims)).reshape(4, -1, 3, 3))
+    src = dev(synth.gaussian_noise(synth.rng(36), dims))
+    for prec, recon in (("fp64", 18), ("mp32", 12)):
+        act = Action(beta=5.6, kappa=0.155, prec=prec, link_recon=recon)
+        assert torch.equal(decomposed(ctx, dims, 1, act, U, src, 1, prec, True), ctx.dslash(dims, act, U, src, 1, prec))
+
+
+def test_halo_timing_runs(ctx):
+    dims = (8, 8, 8, 8)
+    U = dev(synth.haar_su3(synth.rng(37), 4 * synth.volume(dims)).reshape(4, -1, 3, 3))
+    src = dev(synth.gaussian_noise(synth.rng(38), dims))
+    t = ctx.halo_time(dims, Action(beta=5.6, kappa=0.155, prec="mp16", link_recon=18), U, src, reps=5)
+    assert t["face_sites"] == 8 * 8 * 8 // 2 and t["halo_bytes"] == 6 * 8 * t["face_sites"]
+    for k in ("pack_us", "interior_us", "faces_us", "all_us", "local_us"):
+        assert 0.0 < t[k] < 1e5, (k, t)
+
+
+def test_halo_arguments_refused(ctx):
+    dims = (4, 4, 4, 4)
+    U = dev(synth.haar_su3(synth.rng(39), 4 * synth.volume(dims)).reshape(4, -1, 3, 3))
+    src = dev(synth.gaussian_noise(synth.rng(40), dims))
+    act = Action(beta=5.6, kappa=0.155)
+    n = ctx.halo_bytes(dims)
+    a, b = torch.zeros(n, dtype=torch.uint8, device=DEV), torch.zeros(n, dtype=torch.uint8, device=DEV)
+    with pytest.raises(FgiError):
+        ctx.halo_pack(dims, act, U, src, 0, 0.5, 1.0, a, b)
+    with pytest.raises(FgiError):
+        ctx.halo_pack(dims, act, U, src, 2, 1.0, 1.0, a, b)
+    with pytest.raises(FgiError):
+        ctx.dslash_halo(dims, act, U, src, 1, a[:-8], b)
+    with pytest.raises(FgiError):
+        ctx.halo_bytes((4, 4, 4, 1))
