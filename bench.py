@@ -255,7 +255,7 @@ class Runner:
     def run_leg(self, U_therm, act, name, nsteps, inputs, profile=False):
         """Trajectories from U_therm with the given (P, eta) sets; returns per-trajectory records."""
         torch = self.torch
-        integ = self.fgi.integrator_builtin(name, 0.1932)
+        integ = self.fgi.integrator_builtin(name, 0.1932) if isinstance(name, str) else name
         U = torch.empty_like(U_therm)
         P = torch.empty_like(inputs[0][0])
         if profile:
@@ -817,6 +817,25 @@ def whole_trajectories(args):
     out["8x8x8x8_nf2"] = dict(s_per_traj=t_cpu, gpu_s_per_traj=time.perf_counter() - t, trajectories=1,
                               runs="FG n=10, tau=1, beta=5.6, kappa=0.155, FP64 CG 1e-10")
     ctx.close()
+    # the 96-chain batch: the first chain of each size class (the batched leg's own
+    # seeded starts and couplings), one FG n=8 trajectory each, scaled by the class counts
+    rng = synth.rng(args.seed + 500000)
+    dims_list = [d for d, n in BATCH_SPEC for _ in range(n)]
+    betas = rng.uniform(5.5, 6.0, len(dims_list))
+    kappas = rng.uniform(0.150, 0.157, len(dims_list))
+    est, parts, k0 = 0.0, {}, 0
+    for d, n in BATCH_SPEC:
+        U0, P0, eta, _ = synth.hot_start(d, args.seed + 600000 + k0, fermions=True)
+        t = time.perf_counter()
+        orc.trajectory(d, float(betas[k0]), orc.table("FG"), 1.0, 8, U0, P0, kappa=float(kappas[k0]), eta=eta,
+                       tol=args.tol)
+        dt = time.perf_counter() - t
+        parts["x".join(map(str, d))] = round(dt, 4)
+        est += n * dt
+        k0 += n
+    out["96_chain_batch"] = dict(s_per_batched_trajectory=est, extrapolated=True, sample_s_per_class=parts,
+                                 runs="one FG n=8 trajectory (tau=1, FP64 CG %.0e) of the first chain of each size "
+                                      "class, times the class counts (32, 32, 24, 8)" % args.tol)
     return out
 
 
@@ -1155,8 +1174,11 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, R.dims, lf, fg, n_fg)
-        log("cpu baseline %.1f s/traj (extrapolated) on %d threads; whole oracle trajectories: %s" %
-            (cpu["value"], cpu["cores"], {k: round(v["s_per_traj"], 3) for k, v in cpu["configs"].items()}))
+        log("cpu baseline %.1f s/traj (extrapolated) on %d threads; whole oracle trajectories: %s; 96 chains %.1f s "
+            "per batched trajectory (extrapolated)" %
+            (cpu["value"], cpu["cores"], {k: round(v["s_per_traj"], 3) for k, v in cpu["configs"].items()
+                                          if "s_per_traj" in v},
+             cpu["configs"]["96_chain_batch"]["s_per_batched_trajectory"]))
 
     speedup = None
     if lf is not None:
