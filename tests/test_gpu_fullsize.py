@@ -130,3 +130,23 @@ def test_fg_trajectory_full_size(ctx, orc):
     # S_F ~ 8e5 here: a 1e-12 relative solve leaves ~1e-5 in dH on each side
     assert abs(dH - dH_o) < 1e-3, (dH, dH_o)
     assert np.max(np.abs(np.einsum("...ij,...kj->...ik", U1, U1.conj()) - np.eye(3))) < 1e-12
+
+
+@pytest.mark.parametrize("recon", [12, 18])
+def test_mp16_trajectory_tracks_fp64_full_size(ctx, recon):
+    """At the benchmark lattice the mixed-precision FG trajectory (FP16 inner
+    solves, FP64 reliable updates to the same 1e-10 true residual) ends where
+    the FP64 one does: the solves differ only below their tolerance."""
+    dims = L16
+    U0, P0, eta, _ = synth.hot_start(dims, synth.SEED_BASE + 914, fermions=True)
+    res = {}
+    for prec, rc in (("fp64", 18), ("mp16", recon)):
+        act = Action(beta=5.6, kappa=0.1575, cg_tol=1e-10, prec=prec, link_recon=rc)
+        U, P = dev(U0), dev(P0)
+        dH, st = ctx.trajectory(dims, act, "FG", 1.0, 12, U, P, dev(eta))
+        assert st["max_rel_resid"] <= 1e-10
+        res[prec] = (dH, host(U), host(P))
+    (d64, U64, P64), (d16, U16, P16) = res["fp64"], res["mp16"]
+    assert abs(d16 - d64) < 1e-5, (d16, d64)
+    assert np.max(np.abs(U16 - U64)) < 1e-6
+    assert np.max(np.abs(P16 - P64)) < 1e-6 * np.max(np.abs(P64))
