@@ -427,7 +427,9 @@ int fgi_trajectory_packed(fgi_ctx* ctx, const fgi_geom* g, const fgi_action* act
  * gives the antiperiodic local lattice).  The decomposed hop is bitwise the
  * hop of the whole lattice (fgi_dslash in the same precision) on every rank's
  * sites.  All pointers are device memory; in, out in the even/odd user layout;
- * prec as fgi_dslash (act->link_recon applies to the sloppy links).
+ * halo buffers 16-byte aligned for FGI_FP64, 8-byte otherwise, the two of a
+ * pack distinct and neither overlapping in or out; prec as fgi_dslash
+ * (act->link_recon applies to the sloppy links).
  * FGI_EINVAL for a null or misaligned pointer, a bad parity, precision or sign,
  * or L_t < 2.  Asynchronous on the stream. */
 int fgi_halo_bytes(const fgi_geom* g, int prec, size_t* bytes);

@@ -798,8 +798,10 @@ int fgi_halo_pack(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const
         Ctx& c = ctx_of(ctx);
         Geom g = halo_geom(gg);
         halo_checks(act, U, in, prec);
-        need(to_lo, "to_lo", 8);
-        need(to_hi, "to_hi", 8);
+        const size_t hal = prec == FGI_FP64 ? 16 : 8;  // one complex number of the working precision
+        need(to_lo, "to_lo", hal);
+        need(to_hi, "to_hi", hal);
+        if (to_lo == to_hi) throw Error(FGI_EINVAL, "to_lo and to_hi must be different buffers");
         if (in_parity != 0 && in_parity != 1) throw Error(FGI_EINVAL, "parity must be 0 or 1");
         if (!((sign_lo == 1.0 || sign_lo == -1.0) && (sign_hi == 1.0 || sign_hi == -1.0)))
             throw Error(FGI_EINVAL, "face signs must be +1 or -1");
@@ -818,8 +820,9 @@ int fgi_dslash_halo(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, con
         Geom g = halo_geom(gg);
         halo_checks(act, U, in, prec);
         need(out, "out", 16);
-        need(from_lo, "from_lo", 8);
-        need(from_hi, "from_hi", 8);
+        const size_t hal = prec == FGI_FP64 ? 16 : 8;
+        need(from_lo, "from_lo", hal);
+        need(from_hi, "from_hi", hal);
         if (out_parity != 0 && out_parity != 1) throw Error(FGI_EINVAL, "parity must be 0 or 1");
         if (split != 0 && split != 1) throw Error(FGI_EINVAL, "split must be 0 or 1");
         StreamScope ss(c, stream);

@@ -132,6 +132,8 @@ def test_halo_arguments_refused(ctx):
         ctx.halo_pack(dims, act, U, src, 0, 0.5, 1.0, a, b)
     with pytest.raises(FgiError):
         ctx.halo_pack(dims, act, U, src, 2, 1.0, 1.0, a, b)
+    with pytest.raises(FgiError):  # the two faces into one buffer
+        ctx.halo_pack(dims, act, U, src, 0, 1.0, 1.0, a, a)
     with pytest.raises(FgiError):
         ctx.dslash_halo(dims, act, U, src, 1, a[:-8], b)
     with pytest.raises(FgiError):
