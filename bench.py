@@ -407,7 +407,7 @@ def hasenbusch_leg(R, U_therm, prec):
 BATCH_SPEC = [((4, 4, 4, 4), 32), ((6, 6, 6, 6), 32), ((8, 8, 8, 8), 24), ((8, 8, 8, 16), 8)]
 
 
-def batched_leg(R, prec, nsteps, steps):
+def batched_leg(R, prec, nsteps, steps, recon=12):
     """96 independent chains of uneven sizes (32x 4^4, 32x 6^4, 24x 8^4,
     8x 8^3x16), beta ~ U[5.5, 6.0], kappa ~ U[0.150, 0.157], each a seeded Haar
     start with Gaussian momenta and pseudofermion noise: FG trajectories of all
@@ -422,7 +422,7 @@ def batched_leg(R, prec, nsteps, steps):
     for k, dims in enumerate(dims_list):
         U0, P0, eta, _ = synth.hot_start(dims, R.args.seed + 600000 + k, fermions=True)
         host.append((R.to_dev(U0), R.to_dev(P0), R.to_dev(eta)))
-    act = fgi.Action(beta=0.0, cg_tol=R.args.tol, cg_maxiter=50000, prec=prec, link_recon=12 if prec != "fp64" else 18)
+    act = fgi.Action(beta=0.0, cg_tol=R.args.tol, cg_maxiter=50000, prec=prec, link_recon=recon if prec != "fp64" else 18)
 
     def fresh():
         return [dict(dims=d, beta=b, kappa=kp, U=U.clone(), P=P.clone(), eta=e)
@@ -456,7 +456,7 @@ def batched_leg(R, prec, nsteps, steps):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     return dict(workload="96 chains (32x 4^4, 32x 6^4, 24x 8^4, 8x 8^3x16), beta~U[5.5,6.0], kappa~U[0.150,0.157], "
-                         "Haar starts; FG n=%d tau=1, %s CG tol %.0e" % (nsteps, prec, R.args.tol),
+                         "Haar starts; FG n=%d tau=1, %s/%d CG tol %.0e" % (nsteps, prec, act.link_recon, R.args.tol),
                 chains=len(dims_list), s_per_batched_trajectory=round(t_batch, 5),
                 chain_trajectories_per_s=round(len(dims_list) / t_batch, 2),
                 s_chain_by_chain=round(t_seq, 4), speedup_vs_chain_by_chain=round(t_seq / t_batch, 2),
