@@ -100,11 +100,15 @@ def parse():
     ap.add_argument("--md-tol", type=float, default=1e-7,
                     help="force-solve tolerance of the looser-MD leg (0: skip; dH solves keep --tol)")
     ap.add_argument("--tune-alpha", type=int, default=4, metavar="K",
-                    help="Omelyan alpha from Poisson brackets measured over K trajectories (0: skip)")
+                    help="Omelyan alpha from Poisson brackets measured over 2K trajectories, two-fold "
+                         "cross-validated (0: skip)")
+    ap.add_argument("--tune-fg", type=int, default=5, metavar="K",
+                    help="force-gradient family (lam, xi) from dt^2 and dt^4 brackets over 2K exact-FG "
+                         "trajectories, two-fold cross-validated (0: skip)")
     ap.add_argument("--asym-factor", type=int, default=2,
-                    help="the bracket legs (alpha tuning, dt^4 row) run at this multiple of their leg's n*: the "
-                         "shadow-Hamiltonian expansion describes dH only inside its asymptotic range, and n* "
-                         "sits at the integrators' stability edge")
+                    help="the bracket legs (alpha tuning, dt^4 row, FG family tuning) run at this multiple of "
+                         "their leg's n*: the shadow-Hamiltonian expansion describes dH only inside its asymptotic "
+                         "range, and n* sits at the integrators' stability edge")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default CG schedule (block 256, XCD order, --cg-batch) instead of tuning per leg")
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle CG iterations timed for the CPU baseline")
@@ -465,34 +469,53 @@ def batched_leg(R, prec, nsteps, steps, recon=12):
 
 def tune_alpha_leg(R, U_therm, k, n):
     """Section 3 tuning: {S,{S,T}} and {T,{S,T}} measured on the GPU at both ends
-    of k PQPQP(0.1932) trajectories, the alpha minimising the predicted <dH^2>,
-    and the same k starts rerun at that alpha."""
+    of 2k PQPQP(0.1932) trajectories and the alpha minimising the predicted
+    <dH^2> over all of them; checked by two-fold cross-validation: alpha tuned
+    on each half of the starts is run on the other half, so the measured
+    <dH^2> comes from trajectories the tuning never saw.  The starts follow a
+    Metropolis chain from the thermalised links (each measured trajectory is
+    the chain's next proposal), so the brackets sample an ensemble of gauge
+    fields rather than fresh momenta on one field."""
     from paper_0910_2950_amd.tuning import predicted_dh2, tune_omelyan_alpha
-    torch, ctx, dims = R.torch, R.ctx, R.dims
+    ctx, dims = R.ctx, R.dims
     act = R.action(R.args.prec, R.args.recon)
-    inputs = R.fresh_inputs(k, R.args.seed + 300000)
-    dS, dT, dh0 = [], [], []
+    inputs = R.fresh_inputs(2 * k, R.args.seed + 300000)
+    dS, dT, dh0, links, acc = [], [], [], [], []
     t0 = time.perf_counter()
+    metro = np.random.default_rng(R.args.seed + 300000 - 1)
+    U_cur = U_therm.clone()
     for P0, eta in inputs:
-        phi = ctx.pf_heatbath(dims, act, U_therm, eta)
-        s0, q0 = ctx.poisson_brackets(dims, act, U_therm, P0, phi, h=1e-4)
-        U, P = U_therm.clone(), P0.clone()
+        links.append(U_cur)
+        phi = ctx.pf_heatbath(dims, act, U_cur, eta)
+        s0, q0 = ctx.poisson_brackets(dims, act, U_cur, P0, phi, h=1e-4)
+        U, P = U_cur.clone(), P0.clone()
         dH, _ = ctx.trajectory(dims, act, R.fgi.integrator_builtin("PQPQP", 0.1932), 1.0, n, U, P, eta)
         s1, q1 = ctx.poisson_brackets(dims, act, U, P, phi, h=1e-4)
         dS.append(s1 - s0)
         dT.append(q1 - q0)
         dh0.append(dH)
+        acc.append(bool(metro.random() < np.exp(-dH)))
+        if acc[-1]:   # the starts follow a Metropolis chain: an ensemble, not one field
+            ctx.reunitarize(dims, U)
+            U_cur = U
+    dS, dT = np.array(dS), np.array(dT)
     alpha = tune_omelyan_alpha(dS, dT)
-    dh1 = []
-    for P0, eta in inputs:
-        U, P = U_therm.clone(), P0.clone()
-        dH, _ = ctx.trajectory(dims, act, R.fgi.integrator_builtin("PQPQP", alpha), 1.0, n, U, P, eta)
-        dh1.append(dH)
-    return dict(trajectories=k, n=n, alpha_tuned=alpha,
+    folds = (np.arange(k), np.arange(k, 2 * k))
+    alphas, dh_cv, pred_cv = [], [0.0] * (2 * k), 0.0
+    for fit, ev in ((0, 1), (1, 0)):
+        a = tune_omelyan_alpha(dS[folds[fit]], dT[folds[fit]])
+        alphas.append(a)
+        pred_cv += predicted_dh2(a, dS[folds[ev]], dT[folds[ev]], 1.0 / n) / 2
+        for i in folds[ev]:
+            U, P = links[i].clone(), inputs[i][0].clone()
+            dh_cv[i], _ = ctx.trajectory(dims, act, R.fgi.integrator_builtin("PQPQP", a), 1.0, n, U, P,
+                                         inputs[i][1])
+    return dict(trajectories=2 * k, n=n, chain_accepted=acc, alpha_tuned=alpha, alpha_folds=alphas,
                 predicted_dH2={"0.1932": predicted_dh2(0.1932, dS, dT, 1.0 / n),
-                               "tuned": predicted_dh2(alpha, dS, dT, 1.0 / n)},
-                measured_dH2={"0.1932": float(np.mean(np.square(dh0))), "tuned": float(np.mean(np.square(dh1)))},
-                dH={"0.1932": dh0, "tuned": dh1}, seconds=time.perf_counter() - t0)
+                               "tuned": predicted_dh2(alpha, dS, dT, 1.0 / n), "cross_validated": pred_cv},
+                measured_dH2={"0.1932": float(np.mean(np.square(dh0))),
+                              "cross_validated": float(np.mean(np.square(dh_cv)))},
+                dH={"0.1932": dh0, "cross_validated": dh_cv}, seconds=time.perf_counter() - t0)
 
 
 def fg_row(b):
@@ -524,6 +547,77 @@ def dt4_leg(R, U_therm, act, n, inputs):
                         brackets_start=b0, brackets_end=b1))
     return dict(n=n, trajectories=len(out), records=out, seconds=time.perf_counter() - t0,
                 note="predicted = dt^4 Delta(36 STSST + 72 STTST + 126 TTSST + 54 TTTST)/155520 (Table 1, last row)")
+
+
+def fg_family_leg(R, U_therm, act, n, k):
+    """The conclusions' next step for the fourth-order integrators: the family
+    P(lam) Q(1/2) G(1 - 2 lam, xi) Q(1/2) P(lam) with the exact G stage (the FG
+    integrator at (1/6, 1/72)) has a shadow Hamiltonian known to dt^4 in closed
+    form (tuning.fg_family_coeffs), so with the six brackets measured at both
+    ends of 2k exact-FG trajectories (n steps, tau = 1) the member minimising
+    the predicted <dH^2> at dt = 1/n follows.  Checked by two-fold
+    cross-validation: the member tuned on each half of the starts is run on
+    the other half (same cost per step as FG) and compared with FG there.  The
+    starts follow a Metropolis chain from the thermalised links, as in the
+    alpha tuning."""
+    from paper_0910_2950_amd import tuning
+    ctx, dims = R.ctx, R.dims
+    act_ex = dataclasses.replace(act, fg_exact=True)
+    terms = R.fgi.TERM_GAUGE | R.fgi.TERM_FERMION
+
+    def member(lam, xi):
+        return R.fgi.integrator_from_levels([(tuning.fg_family_stages(lam, xi), terms, 1)])
+
+    def run(integ, U0, P0, phi):
+        U, P = U0.clone(), P0.clone()
+        dH, _ = ctx.trajectory(dims, act_ex, integ, 1.0, n, U, P, phi, pf_is_phi=True)
+        return dH, U, P
+
+    t0 = time.perf_counter()
+    fg = member(1.0 / 6.0, 1.0 / 72.0)
+    keys = tuning.FG_KEYS2 + tuning.FG_KEYS4
+    dB = {key: [] for key in keys}
+    starts = R.fresh_inputs(2 * k, R.args.seed + 400000)
+    metro = np.random.default_rng(R.args.seed + 400000 - 1)
+    U_cur = U_therm.clone()
+    links, phis, dh_fg, acc = [], [], [], []
+    for P0, eta in starts:
+        links.append(U_cur)
+        phis.append(ctx.pf_heatbath(dims, act, U_cur, eta))
+        b0 = ctx.poisson_brackets4(dims, act, U_cur, P0, phis[-1], h=1e-3)
+        dH, U, P = run(fg, U_cur, P0, phis[-1])
+        b1 = ctx.poisson_brackets4(dims, act, U, P, phis[-1], h=1e-3)
+        for key in keys:
+            dB[key].append(b1[key] - b0[key])
+        dh_fg.append(dH)
+        acc.append(bool(metro.random() < np.exp(-dH)))
+        if acc[-1]:   # the starts follow a Metropolis chain: an ensemble, not one field
+            ctx.reunitarize(dims, U)
+            U_cur = U
+    dB = {key: np.array(v) for key, v in dB.items()}
+    dt = 1.0 / n
+    lam, xi = tuning.tune_fg_family(dB, dt)
+    folds = (np.arange(k), np.arange(k, 2 * k))
+    fits, dh_cv, pred_cv = [], [0.0] * (2 * k), [0.0] * (2 * k)
+    for fit, ev in ((0, 1), (1, 0)):
+        lf, xf = tuning.tune_fg_family({key: v[folds[fit]] for key, v in dB.items()}, dt)
+        fits.append((lf, xf))
+        pe = tuning.predicted_dh_fg_family(lf, xf, {key: v[folds[ev]] for key, v in dB.items()}, dt)
+        integ = member(lf, xf)
+        for j, i in enumerate(folds[ev]):
+            pred_cv[i] = float(pe[j])
+            dh_cv[i] = run(integ, links[i], starts[i][0], phis[i])[0]
+
+    def ms(v):
+        return float(np.mean(np.square(v)))
+    return dict(trajectories=2 * k, n=n, chain_accepted=acc, lam=lam, xi=xi, fold_fits=fits,
+                predicted_dH2={"FG": ms(tuning.predicted_dh_fg_family(1.0 / 6.0, 1.0 / 72.0, dB, dt)),
+                               "tuned": ms(tuning.predicted_dh_fg_family(lam, xi, dB, dt)),
+                               "cross_validated": ms(pred_cv)},
+                measured_dH2={"FG": ms(dh_fg), "cross_validated": ms(dh_cv)},
+                dH={"FG": dh_fg, "cross_validated": dh_cv, "cross_validated_predicted": pred_cv},
+                bracket_changes={key: [float(x) for x in v] for key, v in dB.items()},
+                seconds=time.perf_counter() - t0)
 
 
 def chain_leg(R, U_therm, act, n, ntraj, seed=0x5EED):
@@ -1106,10 +1200,24 @@ def main():
     if args.tune_alpha > 0:
         R.apply(tune_fg)
         alpha_leg = tune_alpha_leg(R, U, args.tune_alpha, args.asym_factor * nstar["pqpqp_fp64"][0])
-        log("alpha tuning (PQPQP n=%d, %d trajectories): alpha %.4f, predicted <dH^2> %.3e -> %.3e, measured "
-            "%.3e -> %.3e" % (alpha_leg["n"], args.tune_alpha, alpha_leg["alpha_tuned"],
-                              alpha_leg["predicted_dH2"]["0.1932"], alpha_leg["predicted_dH2"]["tuned"],
-                              alpha_leg["measured_dH2"]["0.1932"], alpha_leg["measured_dH2"]["tuned"]))
+        a = alpha_leg
+        log("alpha tuning (PQPQP n=%d, %d trajectories): alpha %.4f (halves %.4f, %.4f), predicted <dH^2> %.3e -> "
+            "%.3e; cross-validated: predicted %.3e, measured %.3e -> %.3e" %
+            (a["n"], a["trajectories"], a["alpha_tuned"], a["alpha_folds"][0], a["alpha_folds"][1],
+             a["predicted_dH2"]["0.1932"], a["predicted_dH2"]["tuned"], a["predicted_dH2"]["cross_validated"],
+             a["measured_dH2"]["0.1932"], a["measured_dH2"]["cross_validated"]))
+    family_leg = None
+    if args.tune_fg > 0:
+        R.apply(tune_fg)
+        n_fam = args.asym_factor * n_fg
+        family_leg = fg_family_leg(R, U, act_fg, n_fam, args.tune_fg)
+        f = family_leg
+        log("FG family tuning (exact G, n=%d, %d trajectories): (lam, xi) = (%.4f, %.5f), halves (%.4f, %.5f) and "
+            "(%.4f, %.5f); predicted <dH^2> FG %.3e -> %.3e; cross-validated: predicted %.3e, measured FG %.3e -> "
+            "%.3e" % (n_fam, f["trajectories"], f["lam"], f["xi"], f["fold_fits"][0][0], f["fold_fits"][0][1],
+                      f["fold_fits"][1][0], f["fold_fits"][1][1], f["predicted_dH2"]["FG"], f["predicted_dH2"]["tuned"],
+                      f["predicted_dH2"]["cross_validated"], f["measured_dH2"]["FG"],
+                      f["measured_dH2"]["cross_validated"]))
     md_leg = None
     if args.md_tol > 0:
         # the first timed starts again, the solves inside force evaluations at --md-tol
@@ -1208,7 +1316,7 @@ def main():
                roofline=roof, roofline_32x32x32x64=large, roofline_32x32x32x64_other_links=large_other,
                halo_32x32x32x8=halo,
                hasenbusch_32x32x32x64=hasen, batched=batched,
-               alpha_tuning=alpha_leg, md_tolerance=md_leg, chain=chain, improved_gauge=improved, clover=clover,
+               alpha_tuning=alpha_leg, fg_family_tuning=family_leg, md_tolerance=md_leg, chain=chain, improved_gauge=improved, clover=clover,
                stout=stout, cpu_baseline=cpu)
     print(json.dumps(out), flush=True)
 
