@@ -82,6 +82,9 @@ def parse():
                     help="reals stored per sloppy link of the headline leg (FP16 or FP32)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--cg-batch", type=int, default=16)
+    ap.add_argument("--cg-form", default="auto", choices=["auto", "0", "1"],
+                    help="CG iteration form of the single-lattice solves: 0 classic (five launches), 1 "
+                         "Chronopoulos-Gear (four), auto: the autotuner's choice per leg on full solves")
     ap.add_argument("--graphs", type=int, default=1, help="replay CG batches as HIP graphs (0: eager launches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 32^3x64 Dslash roofline point")
@@ -175,6 +178,8 @@ class Runner:
         self.ctx.set_option("cg_batch", args.cg_batch)
         self.ctx.set_option("graphs", args.graphs)
         self.ctx.set_option("fg_start", args.fg_start)
+        if args.cg_form != "auto":
+            self.ctx.set_option("cg_form", int(args.cg_form))
 
     def action(self, prec, recon=18):
         return self.fgi.Action(beta=self.args.beta, kappa=self.args.kappa, cg_tol=self.args.tol,
@@ -239,7 +244,11 @@ class Runner:
         act = self.fgi.Action(beta=self.args.beta, kappa=self.args.kappa, cg_tol=self.args.tol, cg_maxiter=50000,
                               prec=prec, link_recon=recon)
         t = self.ctx.autotune_cg(self.dims, act, U, self.to_dev(eta))
-        log("autotune %s: block %d, order %d, cg_batch %d" % (prec, t["dslash_block"], t["xcd_order"], t["cg_batch"]))
+        if self.args.cg_form != "auto":
+            t["cg_form"] = int(self.args.cg_form)
+        log("autotune %s: block %d, order %d, cg_batch %d, CG form %d (full solve %.2f / %.2f ms classic / "
+            "Chronopoulos-Gear)" % (prec, t["dslash_block"], t["xcd_order"], t["cg_batch"], t["cg_form"],
+                                    t["form_ms_per_solve"][0], t["form_ms_per_solve"][1]))
         return t
 
     def apply(self, t):
@@ -248,6 +257,7 @@ class Runner:
         self.ctx.set_option("dslash_block", t["dslash_block"])
         self.ctx.set_option("xcd_order", t["xcd_order"])
         self.ctx.set_option("cg_batch", t["cg_batch"])
+        self.ctx.set_option("cg_form", t.get("cg_form", 0))
 
     def fresh_inputs(self, n, base):
         out = []

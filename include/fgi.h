@@ -175,6 +175,8 @@ typedef struct {
     double max_rel_resid;  /* largest final true relative residual */
     long force_evals;      /* force evaluations (gauge + fermion counted once) */
     double seconds;        /* host wall time of the call */
+    long graph_captures;   /* HIP graphs of CG batches captured during the call: the first call with a
+                              given operator and vectors captures, repeated calls reuse them (0) */
 } fgi_stats;
 
 #define FGI_PQP 0          /* leapfrog, P first (Table 1 row 1) */
@@ -199,7 +201,12 @@ const char* fgi_last_error(void);
  * the undisplaced links, which are a function of the stage's links alone, so
  * the stage stays reversible; 0: from zero), "graphs" (0: launch the batch
  * kernels one by one instead), "ru_delta" (reliable-update residual drop),
- * "profile" (1: after every CG solve, time 16 back-to-back launches of the
+ * "cg_form" (0, the default: the classic CG iteration, five launches; 1: the
+ * Chronopoulos-Gear form, four launches, which applies the operator to the
+ * residual and carries the direction's image by recurrence, with <p, A p>
+ * expanded exactly; single-lattice Wilson solves only, the same tolerance and
+ * true-residual stop; Chronopoulos and Gear, J. Comput. Appl. Math. 25 (1989)
+ * 153), "profile" (1: after every CG solve, time 16 back-to-back launches of the
  * bare Dslash hop on the solve's operator with HIP events), "profile_prec"
  * (profile only solves whose inner precision is 0 FP64 / 1 FP32 / 2 FP16;
  * -1 all), "profile_reset".  An unknown name is FGI_EINVAL. */
@@ -209,14 +216,16 @@ int fgi_set_option(fgi_ctx* ctx, const char* name, double value);
 int fgi_get_profile(fgi_ctx* ctx, double* ms, long* launches, long* sites);
 
 /* Schedule of the CG kernels chosen by fgi_autotune_* (also settable with
- * fgi_set_option: "dslash_block", "xcd_order", "cg_batch"). */
+ * fgi_set_option: "dslash_block", "xcd_order", "cg_batch", "cg_form"). */
 typedef struct {
     int dslash_block;             /* even sites (threads) per block of the Dslash-shaped kernels: 64, 128, 256 */
     int xcd_order;                /* 1: blocks ordered so each XCD owns a contiguous slab of sites; 0: linear */
     int cg_batch;                 /* CG iterations launched between host polls */
-    int pad;
+    int cg_form;                  /* single-lattice CG: 0 classic (five launches per iteration), 1 the
+                                     Chronopoulos-Gear form (four); batched solves use the classic form */
     double sched_us_per_iter[6];  /* measured: candidate (block 64, 128, 256) x (order 0, 1), index 2 k + order */
     double batch_ms_per_solve[5]; /* measured: full solve with cg_batch 4, 8, 16, 32, 64 */
+    double form_ms_per_solve[2];  /* measured: full solve in each CG form (fgi_autotune_cg only; else 0) */
 } fgi_tuning;
 /* Autotuner: times every (block, order) schedule on a 64-iteration solve of
  * the caller's system (U, phi in the user layout, act's precision), then

@@ -440,6 +440,7 @@ int fgi_destroy(fgi_ctx* ctx) {
         DevBuf* bufs[] = {&c.gauge, &c.gauge_disp, &c.sloppy, &c.sloppy_disp, &c.mom, &c.force, &c.force2,
                           &c.scratch_mom, &c.eta, &c.phi, &c.X, &c.Xo, &c.Ye, &c.Yo, &c.tmp_e, &c.tmp_o,
                           &c.cg_r, &c.cg_p, &c.cg_q, &c.s_x, &c.s_r, &c.s_p, &c.s_q, &c.s_t, &c.s_norms,
+                          &c.s_pf, &c.s_sf, &c.s_rt,
                           &c.h0, &c.hf0, &c.partial, &c.scal, &c.state, &c.phi2, &c.eta2, &c.user_tmp,
                           &c.chi, &c.X2, &c.cdesc, &c.bstate, &c.bscal, &c.bh0, &c.bh1, &c.bres,
                           &c.gauge_tan, &c.tg_dmx, &c.tg_rhs, &c.tg_z, &c.tg_dxo, &c.tg_dye, &c.tg_dyo,
@@ -480,6 +481,9 @@ int fgi_set_option(fgi_ctx* ctx, const char* name, double value) {
             c.ds_xcd = value != 0;
         } else if (n == "fg_start") {
             c.fg_start = value != 0;
+        } else if (n == "cg_form") {
+            if (!(value == 0 || value == 1)) throw Error(FGI_EINVAL, "cg_form must be 0 or 1");
+            c.cg_form = (int)value;
         } else if (n == "graphs") {
             c.use_graphs = value != 0;
         } else if (n == "profile") {
@@ -975,6 +979,7 @@ int fgi_cg_solve(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const 
         need(phi, "phi", 16);
         need(X, "X", 16);
         auto t0 = std::chrono::steady_clock::now();
+        const long cap0 = c.graph_captures;
         StreamScope ss(c, stream);
         Fields f(c, g, *act);
         f.st = st;
@@ -990,7 +995,10 @@ int fgi_cg_solve(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, const 
         f.solve(f.U, f.Us, act->kappa, ph, x);
         unpack_even_spinor(c, g, x, X);
         FGI_HIP(hipStreamSynchronize(c.stream));
-        if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (st) {
+            st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            st->graph_captures += c.graph_captures - cap0;
+        }
         if (f.nonconv) throw Error(FGI_ENOCONV, "CG reached cg_maxiter");
     });
     return rc;
@@ -1618,6 +1626,7 @@ extern "C" int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action
         if (ferm) need(eta1, "eta1", 16);
         if (hasen) need(eta2, "eta2", 16);
         auto t0 = std::chrono::steady_clock::now();
+        const long cap0 = c.graph_captures;
         StreamScope ss(c, stream);
         Fields f(c, g, *act);
         f.st = st;
@@ -1642,7 +1651,10 @@ extern "C" int fgi_trajectory(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action
         unpack_mom(c, g, f.P, (double*)P);
         FGI_HIP(hipStreamSynchronize(c.stream));
         *dH = dh;
-        if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (st) {
+            st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            st->graph_captures += c.graph_captures - cap0;
+        }
         if (!std::isfinite(dh)) throw Error(FGI_ENONFINITE, "dH is not finite");
         if (f.nonconv) throw Error(FGI_ENOCONV, "a CG solve reached cg_maxiter");
     });
@@ -1707,6 +1719,7 @@ extern "C" int fgi_trajectory_packed(fgi_ctx* ctx, const fgi_geom* gg, const fgi
         if (ferm) need(eta1, "eta1", 16);
         if (hasen) need(eta2, "eta2", 16);
         auto t0 = std::chrono::steady_clock::now();
+        const long cap0 = c.graph_captures;
         StreamScope ss(c, stream);
         Fields f(c, g, *act);
         f.st = st;
@@ -1721,7 +1734,10 @@ extern "C" int fgi_trajectory_packed(fgi_ctx* ctx, const fgi_geom* gg, const fgi
                                             pf_is_phi ? nullptr : (const d2*)eta2, pf_is_phi != 0);
         FGI_HIP(hipStreamSynchronize(c.stream));
         *dH = dh;
-        if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (st) {
+            st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            st->graph_captures += c.graph_captures - cap0;
+        }
         if (!std::isfinite(dh)) throw Error(FGI_ENONFINITE, "dH is not finite");
         if (f.nonconv) throw Error(FGI_ENOCONV, "a CG solve reached cg_maxiter");
     });
@@ -1774,6 +1790,7 @@ extern "C" int fgi_hmc_run(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* a
         if (ntraj == 0) return;
         const bool ferm = act->kappa != 0.0, hasen = act->kappa_hasen != 0.0;
         auto t0 = std::chrono::steady_clock::now();
+        const long cap0 = c.graph_captures;
         StreamScope ss(c, stream);
         Fields f(c, g, *act);
         f.st = st;
@@ -1810,7 +1827,10 @@ extern "C" int fgi_hmc_run(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* a
         }
         unpack_gauge(c, g, Ucur, U);
         FGI_HIP(hipStreamSynchronize(c.stream));
-        if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (st) {
+            st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            st->graph_captures += c.graph_captures - cap0;
+        }
         if (nonconv) throw Error(FGI_ENOCONV, "a CG solve reached cg_maxiter");
     });
 }
@@ -1985,6 +2005,7 @@ extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain
         Batch B;
         describe_batch(c, nchains, chains, cd, B);
         auto t0 = std::chrono::steady_clock::now();
+        const long cap0 = c.graph_captures;
         StreamScope ss(c, stream);
         upload_batch(c, cd, B);
         BFields f(c, *act);
@@ -2039,7 +2060,10 @@ extern "C" int fgi_trajectory_batched(fgi_ctx* ctx, int nchains, const fgi_chain
             dH[i] = out[i] + (ferm ? out[nchains + i] : 0.0);
             finite = finite && std::isfinite(dH[i]);
         }
-        if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (st) {
+            st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            st->graph_captures += c.graph_captures - cap0;
+        }
         if (!finite) throw Error(FGI_ENONFINITE, "dH is not finite");
         if (f.nonconv) throw Error(FGI_ENOCONV, "a CG solve reached cg_maxiter");
     });
@@ -2069,7 +2093,7 @@ double time_solve(Ctx& c, Solve solve) {
 
 // phase 1 with `solve64` (returns iterations), phase 2 with `solve_full`
 template <typename S64, typename SFull, typename Rebuild>
-void tune(Ctx& c, S64 solve64, SFull solve_full, Rebuild rebuild, fgi_tuning* out) {
+void tune(Ctx& c, S64 solve64, SFull solve_full, Rebuild rebuild, fgi_tuning* out, bool forms) {
     fgi_tuning t{};
     const int saved_batch = c.cg_batch;
     double best = 1e300;
@@ -2091,6 +2115,23 @@ void tune(Ctx& c, S64 solve64, SFull solve_full, Rebuild rebuild, fgi_tuning* ou
     c.ds_bs = bb;
     c.ds_xcd = bx;
     rebuild();
+    // the CG form (single-lattice solves only), on full solves: the
+    // Chronopoulos-Gear form saves a launch per iteration but may take a few
+    // more iterations
+    int bf = c.cg_form;
+    if (forms) {
+        best = 1e300;
+        for (int f = 0; f < 2; f++) {
+            c.cg_form = f;
+            const double ms = 1e3 * time_solve(c, [&] { solve_full(); return 1; });
+            t.form_ms_per_solve[f] = ms;
+            if (ms < best) {
+                best = ms;
+                bf = f;
+            }
+        }
+    }
+    c.cg_form = bf;   // unchanged unless timed
     best = 1e300;
     int bn = saved_batch;
     for (int k = 0; k < 5; k++) {
@@ -2106,6 +2147,7 @@ void tune(Ctx& c, S64 solve64, SFull solve_full, Rebuild rebuild, fgi_tuning* ou
     t.dslash_block = bb;
     t.xcd_order = bx;
     t.cg_batch = bn;
+    t.cg_form = bf;
     if (out) *out = t;
 }
 }  // namespace
@@ -2137,7 +2179,7 @@ int fgi_autotune_cg(fgi_ctx* ctx, const fgi_geom* gg, const fgi_action* act, con
         pack_even_spinor(c, g, phi, ph);
         tune(
             c, [&] { return f64.solve(f.U, f.Us, act->kappa, ph, x).iters; },
-            [&] { f.solve(f.U, f.Us, act->kappa, ph, x); }, [] {}, out);
+            [&] { f.solve(f.U, f.Us, act->kappa, ph, x); }, [] {}, out, true);
     });
 }
 
@@ -2188,6 +2230,6 @@ int fgi_autotune_batched(fgi_ctx* ctx, int nchains, const fgi_chain* chains, con
                 f64.solve(f.U, f.Us, f.phi, f.X);
                 return 64;
             },
-            [&] { f.solve(f.U, f.Us, f.phi, f.X); }, rebuild, out);
+            [&] { f.solve(f.U, f.Us, f.phi, f.X); }, rebuild, out, false);
     });
 }

@@ -145,10 +145,14 @@ enum Mode {
     M_SCHUR = 1,  // out = center - kappa^2 [g5] acc          [|out|^2 partials]
     M_CGQ = 2,    // CG: q = p - kappa^2 acc (center p), |q|^2 partials (pAp)
     M_CGX = 3,    // CG: Ap = q - kappa^2 g5 acc; x += alpha p; r -= alpha Ap; |r|^2 partials
-    M_RESID = 4   // r = aux - (center - kappa^2 g5 acc), |r|^2 partials
+    M_RESID = 4,  // r = aux - (center - kappa^2 g5 acc), |r|^2 partials
+    M_CGS = 5     // CG, Chronopoulos-Gear form: w = q - kappa^2 g5 acc; p = rt + beta p;
+                  // s = w + beta s; x += alpha p; r -= alpha s; the hops' copy rt of r;
+                  // |r|^2, Re<rt, s>, Re<p, s> partials
 };
 // With a CG state and partials, an M_HOP launch carries one extra block per
-// chain (logical index nb) that sums the M_CGQ partials into st->pAp.
+// chain (logical index nb) that sums the M_CGQ partials into st->pAp, or with
+// cgs set the three M_CGS partials into the state (cgs_state_update).
 
 struct DArgs {
     Geom g;
@@ -162,7 +166,41 @@ struct DArgs {
     int g5out;
     int gate;   // with st: 0 skip once st->stop_at <= iteration, 1 skip unless st->act
     int xcd;    // XCD-aware block order
+    int cgs;    // M_HOP reduction block of the Chronopoulos-Gear form
+    SpinorPtr dir, adir;   // M_CGS: p and s = A p, in the precision of x and r
 };
+
+// Chronopoulos-Gear form (Chronopoulos and Gear, J. Comput. Appl. Math. 25
+// (1989) 153): the operator is applied to the residual, w = A rt with rt the
+// residual as the hops read it, and the direction and its image follow by
+// recurrence, p_k = rt_k + beta_k p_{k-1}, s_k = w_k + beta_k s_{k-1}, so one
+// kernel updates p, s, x and r and the direction update needs no launch of its
+// own.  <p_k, A p_k> is not taken from the usual recurrence (it assumes
+// rt = r and exact conjugacy, which FP16 storage and reliable updates break)
+// but expanded exactly: |Mhat rt_k|^2 + 2 beta Re<rt_k, s_{k-1}> + beta^2
+// Re<p_{k-1}, s_{k-1}>, the last two summed by the update kernel before.
+// First kernel of iteration k (the reduction block of its hop): the previous
+// update's partials |r_k|^2, Re<rt_k, s_{k-1}>, Re<p_{k-1}, s_{k-1}> give
+// rr_k, beta_k = rr_k / rr_{k-1} and the correction; the stop test on rr_k.
+__device__ __forceinline__ void cgs_state_update(CGState* st, const StateView& S, int iter, const double* part,
+                                                 int nb, double* lds) {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        v[0] += part[k];
+        v[1] += part[nb + k];
+        v[2] += part[2 * nb + k];
+    }
+    block_sum<3>(v, lds);
+    if (threadIdx.x == 0) {
+        // a select, not S.rr[(iter - 1) & 1]: a run-time index into the state
+        // copy makes the compiler place it in LDS, one copy per thread
+        const double beta = v[0] / ((iter & 1) ? S.rr[0] : S.rr[1]);
+        st->rr[iter & 1] = v[0];
+        st->beta = beta;
+        st->corr = 2.0 * beta * v[1] + beta * beta * v[2];
+        if (v[0] <= S.rr_stop) st->stop_at = iter;
+    }
+}
 
 // NT: the links are streamed with non-temporal loads (see links_streamed)
 template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN, bool NT>
@@ -178,8 +216,10 @@ __device__ __forceinline__ void dslash_body(const DArgs& A, int b, int nb, doubl
     if (A.st) {  // uniform over the chain's blocks: converged / masked chains no-op
         if (A.gate ? !S.act : S.stop_at <= iter) return;
         if constexpr (MODE == M_HOP) {
-            if (b >= nb) {  // the reduction block: pAp of this iteration
-                if (A.partial) {
+            if (b >= nb) {  // the reduction block: pAp of this iteration, or the CG-form state
+                if (A.cgs) {
+                    cgs_state_update(A.st, S, iter, A.partial, nb, lds);
+                } else if (A.partial) {
                     const double pAp = sum_partials(A.partial, nb, lds);
                     if (threadIdx.x == 0) A.st->pAp = pAp;
                 }
@@ -188,7 +228,7 @@ __device__ __forceinline__ void dslash_body(const DArgs& A, int b, int nb, doubl
         }
     }
     int s = b * blockDim.x + threadIdx.x;
-    double nrm = 0.0;
+    double nrm = 0.0, rs = 0.0, ps = 0.0;
     if (s < g.Vh) {
         cx<R> acc[4][3];
         LoadPlain<PIN, G5IN, R> ld{A.in};
@@ -240,10 +280,58 @@ __device__ __forceinline__ void dslash_body(const DArgs& A, int b, int nb, doubl
                     }
                 SpinorIO<PX, RX>::store(A.x, s, g.Vh, xv);
                 SpinorIO<PX, RX>::store(A.r, s, g.Vh, rv);
+            } else if (MODE == M_CGS) {
+                typedef typename Real<PX>::T RX;
+                const RX be = RX(S.beta);
+                const RX al = RX(((iter & 1) ? S.rr[1] : S.rr[0]) / (S.pAp + S.corr));
+                cx<RX> tv[4][3], pv[4][3], sv[4][3], xv[4][3], rv[4][3];
+                SpinorIO<PC, RX>::load(A.aux, s, g.Vh, tv);  // rt_k, as the hops read it
+                SpinorIO<PX, RX>::load(A.dir, s, g.Vh, pv);
+                SpinorIO<PX, RX>::load(A.adir, s, g.Vh, sv);
+                SpinorIO<PX, RX>::load(A.x, s, g.Vh, xv);
+                SpinorIO<PX, RX>::load(A.r, s, g.Vh, rv);
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        const cx<RX> w = {RX(acc[i][k].re), RX(acc[i][k].im)};
+                        pv[i][k].re = fma(be, pv[i][k].re, tv[i][k].re);
+                        pv[i][k].im = fma(be, pv[i][k].im, tv[i][k].im);
+                        sv[i][k].re = fma(be, sv[i][k].re, w.re);
+                        sv[i][k].im = fma(be, sv[i][k].im, w.im);
+                        xv[i][k] = xv[i][k] + al * pv[i][k];
+                        rv[i][k] = rv[i][k] - al * sv[i][k];
+                        nrm += double(rv[i][k].re) * double(rv[i][k].re) + double(rv[i][k].im) * double(rv[i][k].im);
+                        ps += double(pv[i][k].re) * double(sv[i][k].re) + double(pv[i][k].im) * double(sv[i][k].im);
+                    }
+                SpinorIO<PX, RX>::store(A.dir, s, g.Vh, pv);
+                SpinorIO<PX, RX>::store(A.adir, s, g.Vh, sv);
+                SpinorIO<PX, RX>::store(A.x, s, g.Vh, xv);
+                SpinorIO<PX, RX>::store(A.r, s, g.Vh, rv);
+                if constexpr (PC != PX) {  // the hops' copy of r, and Re<rt, s> with the stored values
+                    static_assert(PC == P16, "a separate copy of r is kept for FP16 hops only");
+                    SpinorIO<PC, RX>::store(A.aux, s, g.Vh, rv);
+                    quantize16(rv);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+#pragma unroll
+                    for (int k = 0; k < 3; k++)
+                        rs += double(rv[i][k].re) * double(sv[i][k].re) + double(rv[i][k].im) * double(sv[i][k].im);
             }
         }
     }
     if (MODE == M_HOP || !A.partial) return;
+    if constexpr (MODE == M_CGS) {
+        double v[3] = {nrm, rs, ps};
+        block_sum<3>(v, lds);
+        if (threadIdx.x == 0) {
+            A.partial[b] = v[0];
+            A.partial[nb + b] = v[1];
+            A.partial[2 * nb + b] = v[2];
+        }
+        return;
+    }
     double v[1] = {nrm};
     block_sum<1>(v, lds);
     if (threadIdx.x == 0) A.partial[b] = v[0];
@@ -251,7 +339,7 @@ __device__ __forceinline__ void dslash_body(const DArgs& A, int b, int nb, doubl
 
 template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN, bool NT>
 __global__ void __launch_bounds__(DBS) k_dslash(DArgs A) {
-    __shared__ double lds[DBS / 64];
+    __shared__ double lds[3 * DBS / 64];
     // site blocks in XCD-aware order (the same order in every kernel of the
     // solver, so a site stays on one XCD); a reduction block comes last
     const int nb = (A.g.Vh + blockDim.x - 1) / blockDim.x;
@@ -282,7 +370,7 @@ template <int PL, int RECON> __device__ __forceinline__ size_t link_byte_off(con
 // blocks past them (an M_HOP with partials) are the chains' reduction blocks
 template <int MODE, int PIN, int PC, int POUT, int PX, int PL, int RECON, int G5IN>
 __global__ void __launch_bounds__(DBS) k_dslash_b(DArgs base, const ChainDesc* __restrict__ cd, int nc, int nsb) {
-    __shared__ double lds[DBS / 64];
+    __shared__ double lds[3 * DBS / 64];
     const int gb = (int)blockIdx.x < nsb ? (base.xcd ? xcd_block(blockIdx.x, nsb) : (int)blockIdx.x) : blockIdx.x;
     const int c = gb < nsb ? find_chain(cd, nc, gb, GRID_DS) : gb - nsb;
     const ChainDesc& d = cd[c];
@@ -415,6 +503,41 @@ __global__ void k_add_to64(int Vh, SpinorPtr x, SpinorPtr y) {
 #pragma unroll
         for (int k = 0; k < 3; k++) b[i][k] = b[i][k] + a[i][k];
     SpinorIO<P64, double>::store(y, s, Vh, b);
+}
+
+// The three partials an M_CGS launch leaves (|r|^2, Re<rt, s>, Re<p, s>) for
+// the vectors as they stand: the start of a Chronopoulos-Gear run and each
+// reliable update, so the next iteration's first kernel finds them as after
+// any other iteration.  Blocks of the solver's block size, indexed linearly.
+template <int PP, int PX>
+__global__ void __launch_bounds__(DBS) k_cgs_partials(int Vh, SpinorPtr r, SpinorPtr rt, SpinorPtr p, SpinorPtr sv,
+                                                      double* partial) {
+    __shared__ double lds[3 * DBS / 64];
+    typedef typename Real<PX>::T RX;
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int s = b * blockDim.x + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (s < Vh) {
+        cx<RX> rv[4][3], tv[4][3], pv[4][3], w[4][3];
+        SpinorIO<PX, RX>::load(r, s, Vh, rv);
+        SpinorIO<PP, RX>::load(rt, s, Vh, tv);
+        SpinorIO<PX, RX>::load(p, s, Vh, pv);
+        SpinorIO<PX, RX>::load(sv, s, Vh, w);
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                v[0] += double(rv[i][k].re) * double(rv[i][k].re) + double(rv[i][k].im) * double(rv[i][k].im);
+                v[1] += double(tv[i][k].re) * double(w[i][k].re) + double(tv[i][k].im) * double(w[i][k].im);
+                v[2] += double(pv[i][k].re) * double(w[i][k].re) + double(pv[i][k].im) * double(w[i][k].im);
+            }
+    }
+    block_sum<3>(v, lds);
+    if (threadIdx.x == 0) {
+        partial[b] = v[0];
+        partial[nb + b] = v[1];
+        partial[2 * nb + b] = v[2];
+    }
 }
 
 __global__ void k_set_state(CGState* st, CGState v) {
@@ -994,6 +1117,7 @@ static double true_residual(Ctx& c, const FermionOp& op64, const d2* phi, const 
 
 struct CGVecs {
     SpinorPtr x, r, p, q, t;  // x, r in PX; p, q, t in PP
+    SpinorPtr pf, sf, rt;     // Chronopoulos-Gear form: p, s = A p in PX; rt, the hops' r, in PP (r itself if PP = PX)
 };
 
 // One CG iteration on A = Mhat^+ Mhat: a direction update and four
@@ -1056,10 +1180,77 @@ static void cg_iteration(Ctx& c, const FermionOp& ops, const CGVecs& v, int j) {
     }
 }
 
+// One iteration in the Chronopoulos-Gear form: four Dslash-shaped kernels.
+//   t = D_oe rt; rr, beta and the <p, A p> correction from the partials  [one extra block]
+//   q = rt - k^2 D_eo t; |q|^2 partials
+//   t = D_oe g5 q; |q|^2 summed into pAp  [one extra block]
+//   w = q - k^2 g5 D_eo t; p = rt + beta p; s = w + beta s; x += alpha p; r -= alpha s;
+//   rt; |r|^2, Re<rt, s>, Re<p, s> partials
+template <int PP, int PX>
+static void cg_iteration_cgs(Ctx& c, const FermionOp& ops, const CGVecs& v, int j) {
+    CGState* st = dev_state(c);
+    double* part = partial_buf(c, *ops.g);
+    {
+        DArgs a = base_args(ops, 1);
+        a.in = v.rt;
+        a.out = v.t;
+        a.partial = part;
+        a.cgs = 1;
+        a.st = st;
+        a.iter = j;
+        launch_dslash<M_HOP, PP, PP, PP, PX, 0>(c, ops, a);
+    }
+    {
+        DArgs a = base_args(ops, 0);
+        a.in = v.t;
+        a.center = v.rt;
+        a.out = v.q;
+        a.partial = part;
+        a.st = st;
+        a.iter = j;
+        launch_dslash<M_CGQ, PP, PP, PP, PX, 0>(c, ops, a);
+    }
+    {
+        DArgs a = base_args(ops, 1);
+        a.in = v.q;
+        a.out = v.t;
+        a.partial = part;
+        a.st = st;
+        a.iter = j;
+        launch_dslash<M_HOP, PP, PP, PP, PX, 1>(c, ops, a);
+    }
+    {
+        DArgs a = base_args(ops, 0);
+        a.in = v.t;
+        a.center = v.q;
+        a.aux = v.rt;
+        a.x = v.x;
+        a.r = v.r;
+        a.dir = v.pf;
+        a.adir = v.sf;
+        a.g5out = 1;
+        a.partial = part;
+        a.st = st;
+        a.iter = j;
+        launch_dslash<M_CGS, PP, PP, PP, PX, 0>(c, ops, a);
+    }
+}
+
+// the M_CGS partials of the vectors as they stand (start of a run, reliable update)
+template <int PP, int PX>
+static void cgs_partials(Ctx& c, const Geom& g, const CGVecs& v) {
+    hipLaunchKernelGGL((k_cgs_partials<PP, PX>), dim3(nblk(g.Vh, c.ds_bs)), dim3(c.ds_bs), 0, c.stream, g.Vh, v.r,
+                       v.rt, v.pf, v.sf, partial_buf(c, g));
+    FGI_LAUNCH_CHECK();
+}
+
 // B iterations then the batch's closing reduction and base += B, on c.stream
 template <int PP, int PX>
 static void cg_batch_eager(Ctx& c, const FermionOp& ops, const CGVecs& v, int B) {
-    for (int j = 0; j < B; j++) cg_iteration<PP, PX>(c, ops, v, j);
+    for (int j = 0; j < B; j++) {
+        if (c.cg_form) cg_iteration_cgs<PP, PX>(c, ops, v, j);
+        else cg_iteration<PP, PX>(c, ops, v, j);
+    }
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(DBS), 0, c.stream, dev_state(c), (const double*)partial_buf(c, *ops.g),
                        nblk(ops.g->Vh, c.ds_bs), B);
     FGI_LAUNCH_CHECK();
@@ -1107,16 +1298,18 @@ static GraphEntry& cached_graph(Ctx& c, const std::string& key, Body body) {
     }
     c.stream = saved;
     c.graphs.push_back(e);
+    c.graph_captures++;
     return c.graphs.back();
 }
 
 template <int PP, int PX>
 static std::string graph_key(const char* what, Ctx& c, const FermionOp& ops, const CGVecs& v, int n) {
     char key[512];
-    snprintf(key, sizeof key, "%s/%d/%d/%p/%.17g/%d/%d/%d/%d/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%d/%d/%d", what, PP,
-             PX, ops.links, ops.kappa, ops.prec, ops.recon, ops.g->L[0], ops.g->L[1], ops.g->L[2], ops.g->L[3],
-             ops.g->Vh, v.x.v, v.r.v, v.p.v, v.q.v, v.t.v, (void*)v.p.norm, (void*)dev_state(c),
-             (void*)partial_buf(c, *ops.g), n, c.ds_bs, c.ds_xcd);
+    snprintf(key, sizeof key, "%s/%d/%d/%p/%.17g/%d/%d/%d/%d/%d/%d/%d/%p/%p/%p/%p/%p/%p/%p/%p/%d/%d/%d/%d/%p/%p/%p/%p",
+             what, PP, PX, ops.links, ops.kappa, ops.prec, ops.recon, ops.g->L[0], ops.g->L[1], ops.g->L[2],
+             ops.g->L[3], ops.g->Vh, v.x.v, v.r.v, v.p.v, v.q.v, v.t.v, (void*)v.p.norm, (void*)dev_state(c),
+             (void*)partial_buf(c, *ops.g), n, c.ds_bs, c.ds_xcd, c.cg_form, v.pf.v, v.sf.v, v.rt.v,
+             (void*)v.rt.norm);
     return key;
 }
 
@@ -1140,6 +1333,47 @@ static void zero_spinor(Ctx& c, const Geom& g, void* v, int prec) {
     if (prec == P16) throw Error(-1, "zero_spinor: FP16");
     hipLaunchKernelGGL(k_zero, dim3(nblk((long)n, 256)), dim3(256), 0, c.stream, n, (double*)v);
     FGI_LAUNCH_CHECK();
+}
+
+// s = A p at a reliable update of the Chronopoulos-Gear form, from p as the
+// hops read it: with FP16 hops p is first rounded to FP16 storage (in q) and
+// kept that way, so s stays the image of the p that x is moved along.
+template <int PP, int PX>
+static void cgs_refresh_s(Ctx& c, const FermionOp& ops, const CGVecs& v) {
+    const Geom& g = *ops.g;
+    SpinorPtr pin = v.pf;
+    if constexpr (PP != PX) {
+        convert<PX, PP>(c, g, v.pf, v.q);
+        convert<PP, PX>(c, g, v.q, v.pf);
+        pin = v.q;
+    }
+    {
+        DArgs a = base_args(ops, 1);
+        a.in = pin;
+        a.out = v.t;
+        launch_dslash<M_HOP, PP, PP, PP, PX, 0>(c, ops, a);
+    }
+    {
+        DArgs a = base_args(ops, 0);
+        a.in = v.t;
+        a.center = pin;
+        a.out = v.q;   // M pin, in place when pin is q (each site reads only its own centre)
+        launch_dslash<M_SCHUR, PP, PP, PP, PX, 0>(c, ops, a);
+    }
+    {
+        DArgs a = base_args(ops, 1);
+        a.in = v.q;
+        a.out = v.t;
+        launch_dslash<M_HOP, PP, PP, PP, PX, 1>(c, ops, a);
+    }
+    {
+        DArgs a = base_args(ops, 0);
+        a.in = v.t;
+        a.center = v.q;
+        a.out = v.sf;
+        a.g5out = 1;
+        launch_dslash<M_SCHUR, PP, PP, PX, PX, 0>(c, ops, a);
+    }
 }
 
 // guess: X holds the starting point on entry (else CG starts from zero); the
@@ -1170,8 +1404,8 @@ static CGResult cg_run(Ctx& c, const FermionOp& op64, const FermionOp& ops, cons
         }
     }
     const d2* r_start = guess ? r64 : phi;
-    CGVecs v;
-    float* norms = (float*)c.s_norms.get(sizeof(float) * 3 * (size_t)g.Vh);
+    CGVecs v{};   // every field null until set: the graph key reads them all
+    float* norms = (float*)c.s_norms.get(sizeof(float) * 4 * (size_t)g.Vh);
     if (PX == P64) {
         if (!guess) spinor_copy(c, g, phi, r64);
         v.x = sp(X);
@@ -1193,9 +1427,25 @@ static CGResult cg_run(Ctx& c, const FermionOp& op64, const FermionOp& ops, cons
         convert<P64, PP>(c, g, sp(r_start), v.p);
     }
     partial_buf(c, g);  // allocate before any capture
+    const bool cgs = c.cg_form != 0;
+    if (cgs) {  // Chronopoulos-Gear form: p = s = 0, rt = r, and the partials its first iteration sums
+        const size_t nx = PX == P64 ? n64 : sizeof(float) * 24 * (size_t)g.Vh;
+        v.pf = sp(c.s_pf.get(nx));
+        v.sf = sp(c.s_sf.get(nx));
+        zero_spinor(c, g, v.pf.v, PX);
+        zero_spinor(c, g, v.sf.v, PX);
+        if constexpr (PP == PX) {
+            v.rt = v.r;
+        } else {
+            v.rt = sp(c.s_rt.get(sizeof(_Float16) * 24 * (size_t)g.Vh), norms + 3 * (size_t)g.Vh);
+            convert<PX, PP>(c, g, v.r, v.rt);
+        }
+        cgs_partials<PP, PX>(c, g, v);
+    }
     CGState* st = dev_state(c);
     CGState h{};
     h.rr[0] = rr0;
+    h.rr[1] = rr0;   // the CG form's first beta divides by it (p = s = 0 there, so its value does not matter)
     h.rr_stop = (PX == P64) ? target : std::max(c.ru_delta * c.ru_delta * rr0, target);
     h.beta = 0.0;
     h.stop_at = INT_MAX;
@@ -1236,6 +1486,11 @@ static CGResult cg_run(Ctx& c, const FermionOp& op64, const FermionOp& ops, cons
             if (PX != P64) {
                 convert<P64, PX>(c, g, sp(r64), v.r);
                 zero_spinor(c, g, v.x.v, P32);
+            }
+            if (cgs) {  // the hops' copy of the new r, s = A p afresh, and the partials
+                if constexpr (PP != PX) convert<PX, PP>(c, g, v.r, v.rt);
+                cgs_refresh_s<PP, PX>(c, ops, v);
+                cgs_partials<PP, PX>(c, g, v);
             }
             CGState u = hs;
             u.beta = rr / hs.rr[(kend - 1) & 1];
@@ -1517,7 +1772,7 @@ static std::vector<CGResult> cg_run_b(Ctx& c, const Batch& B, const FermionOp& o
             FGI_LAUNCH_CHECK();
         }
     }
-    CGVecs v;
+    CGVecs v{};
     float* norms = (float*)c.s_norms.get(sizeof(float) * 3 * (size_t)B.sites);
     const d2* r_start = guess ? r64 : phi;
     if (PX == P64) {

@@ -53,7 +53,7 @@ struct alignas(64) CGState {
     double pAp;        // <p, A p> of the current iteration
     double rr_stop;    // inner stopping target
     double beta;       // p_k = r_k + beta p_{k-1} of the current iteration
-    double pad;
+    double corr;       // Chronopoulos-Gear form: <p_k, A p_k> = pAp + corr
 };
 static_assert(sizeof(CGState) == 64, "CGState is read as 16-byte vectors");
 
@@ -61,7 +61,7 @@ static_assert(sizeof(CGState) == 64, "CGState is read as 16-byte vectors");
 // the state once, up front, instead of one memory round trip per use).
 struct StateView {
     int stop_at, base, base0, act;
-    double rr[2], pAp, rr_stop, beta;
+    double rr[2], pAp, rr_stop, beta, corr;
 };
 __device__ __forceinline__ StateView load_state(const CGState* st) {
     typedef int i4 __attribute__((ext_vector_type(4)));
@@ -70,7 +70,7 @@ __device__ __forceinline__ StateView load_state(const CGState* st) {
     const dd2 r = *(const dd2*)&st->rr[0];
     const dd2 q = *(const dd2*)&st->pAp;
     const dd2 t = *(const dd2*)&st->beta;
-    return StateView{a.x, a.y, a.z, a.w, {r.x, r.y}, q.x, q.y, t.x};
+    return StateView{a.x, a.y, a.z, a.w, {r.x, r.y}, q.x, q.y, t.x, t.y};
 }
 
 // one instantiated CG batch graph, keyed by everything its kernels capture
@@ -92,6 +92,7 @@ struct Ctx {
     DevBuf gauge, gauge_disp, sloppy, sloppy_disp, mom, force, force2, scratch_mom;
     DevBuf eta, phi, X, Xo, Ye, Yo, tmp_e, tmp_o, cg_r, cg_p, cg_q;
     DevBuf s_x, s_r, s_p, s_q, s_t, s_norms;
+    DevBuf s_pf, s_sf, s_rt;   // Chronopoulos-Gear form: p and s = A p (FP32 or FP64), the hops' copy of r
     DevBuf h0, hf0, partial, scal, state;
     DevBuf phi2, eta2, user_tmp, chi, X2;
     // force gradient of the pseudofermion force: tangent links and vectors
@@ -128,6 +129,7 @@ struct Ctx {
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
     std::vector<GraphEntry> graphs;
+    long graph_captures = 0;   // graphs captured and instantiated so far (a steady state adds none)
     // solver tuning
     int cg_batch = 8;          // iterations launched between host polls
     // schedule of the Dslash-shaped kernels (set by hand or by fgi_autotune_cg):
@@ -135,6 +137,9 @@ struct Ctx {
     int ds_bs = 256;
     int ds_xcd = 1;
     double ru_delta = 0.1;     // reliable-update trigger |r| drop
+    // single-lattice CG iteration: 0 the classic form (five launches), 1 the
+    // Chronopoulos-Gear form with exact <p, A p> (four launches; fermion.hip)
+    int cg_form = 0;
     // FG displacement form: the solves of the displaced force start from the
     // undisplaced solutions (a deterministic function of the stage's links, so
     // the stage stays reversible); 0 starts them from zero

@@ -65,12 +65,13 @@ class fgi_chain(ctypes.Structure):
 
 class fgi_tuning(ctypes.Structure):
     _fields_ = [("dslash_block", ctypes.c_int), ("xcd_order", ctypes.c_int), ("cg_batch", ctypes.c_int),
-                ("pad", ctypes.c_int), ("sched_us_per_iter", ctypes.c_double * 6),
-                ("batch_ms_per_solve", ctypes.c_double * 5)]
+                ("cg_form", ctypes.c_int), ("sched_us_per_iter", ctypes.c_double * 6),
+                ("batch_ms_per_solve", ctypes.c_double * 5), ("form_ms_per_solve", ctypes.c_double * 2)]
 
     def as_dict(self):
         return dict(dslash_block=self.dslash_block, xcd_order=self.xcd_order, cg_batch=self.cg_batch,
-                    sched_us_per_iter=list(self.sched_us_per_iter), batch_ms_per_solve=list(self.batch_ms_per_solve))
+                    cg_form=self.cg_form, sched_us_per_iter=list(self.sched_us_per_iter),
+                    batch_ms_per_solve=list(self.batch_ms_per_solve), form_ms_per_solve=list(self.form_ms_per_solve))
 
 
 class fgi_halo_timing(ctypes.Structure):
@@ -94,7 +95,7 @@ def philox4x32_10(ctr, key):
 class fgi_stats(ctypes.Structure):
     _fields_ = [("solves", ctypes.c_long), ("cg_iters", ctypes.c_long), ("cg_iters_max", ctypes.c_int),
                 ("reliable_updates", ctypes.c_int), ("max_rel_resid", ctypes.c_double),
-                ("force_evals", ctypes.c_long), ("seconds", ctypes.c_double)]
+                ("force_evals", ctypes.c_long), ("seconds", ctypes.c_double), ("graph_captures", ctypes.c_long)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -44,8 +44,9 @@ def test_struct_layouts_match_c_sizes():
     assert ctypes.sizeof(fgi.fgi_action) == 88
     # fgi_chain: int dims[4], int pad, double beta, double kappa, 3 pointers
     assert ctypes.sizeof(fgi.fgi_chain) == 64 and fgi.fgi_chain.beta.offset == 24
-    # fgi_tuning: 4 ints, 6 + 5 doubles
-    assert ctypes.sizeof(fgi.fgi_tuning) == 16 + 11 * 8 and fgi.fgi_tuning.sched_us_per_iter.offset == 16
+    # fgi_tuning: 4 ints, 6 + 5 + 2 doubles
+    assert ctypes.sizeof(fgi.fgi_tuning) == 16 + 13 * 8 and fgi.fgi_tuning.sched_us_per_iter.offset == 16
+    assert fgi.fgi_tuning.cg_form.offset == 12 and fgi.fgi_tuning.form_ms_per_solve.offset == 16 + 11 * 8
 
 
 def test_struct_layouts_match_the_c_compiler(tmp_path):

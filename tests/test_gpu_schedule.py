@@ -30,6 +30,7 @@ def default_schedule(ctx):
     ctx.set_option("dslash_block", 256)
     ctx.set_option("xcd_order", 1)
     ctx.set_option("cg_batch", 8)
+    ctx.set_option("cg_form", 0)
 
 
 def set_schedule(ctx, bs, x):
@@ -115,6 +116,9 @@ def test_autotune_single(ctx, orc):
     assert all(v > 0 for v in t["sched_us_per_iter"]) and all(v > 0 for v in t["batch_ms_per_solve"])
     k = [64, 128, 256].index(t["dslash_block"])
     assert t["sched_us_per_iter"][2 * k + t["xcd_order"]] == min(t["sched_us_per_iter"])
+    # both CG forms timed on full solves, the faster kept
+    assert t["cg_form"] in (0, 1) and all(v > 0 for v in t["form_ms_per_solve"])
+    assert t["form_ms_per_solve"][t["cg_form"]] == min(t["form_ms_per_solve"])
     # the context now runs the chosen schedule, and still solves correctly
     X, st = ctx.cg_solve(dims, act, dev(U0), dev(phi0))
     assert st["max_rel_resid"] <= 1e-10
