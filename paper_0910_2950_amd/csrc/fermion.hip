@@ -593,17 +593,27 @@ __global__ void k_pf_density(int Vh, const d2* __restrict__ phi, const d2* __res
 // bc = -1 on the time boundary link.
 // C(A, B) of the link (mu, x) for full-lattice vectors A, B (parity p site s,
 // its forward neighbour sn of the other parity)
+// A full-lattice field as its two parity halves seen from one site: `here`
+// the half of the site's parity, `there` the other (its neighbours').  Chosen
+// by selects once per thread: an array of the two indexed by the run-time
+// parity would make the compiler keep a copy per thread in LDS.
+struct PairAt {
+    SpinorPtr here, there;
+};
+__device__ __forceinline__ PairAt pair_at(SpinorPtr even, SpinorPtr odd, int p) {
+    return PairAt{p ? odd : even, p ? even : odd};
+}
+
 template <int MU>
-__device__ __forceinline__ M3<double> outer_c(const Geom& g, int p, int s, int sn, const SpinorPtr A[2],
-                                              const SpinorPtr B[2]) {
+__device__ __forceinline__ M3<double> outer_c(const Geom& g, int s, int sn, const PairAt& A, const PairAt& B) {
     cx<double> a[4][3], h1[2][3], h2[2][3], h3[2][3], h4[2][3];
-    SpinorIO<P64, double>::load(A[1 - p], sn, g.Vh, a);
+    SpinorIO<P64, double>::load(A.there, sn, g.Vh, a);
     spin_proj<MU, -1>(a, h1);
-    SpinorIO<P64, double>::load(B[p], s, g.Vh, a);
+    SpinorIO<P64, double>::load(B.here, s, g.Vh, a);
     spin_proj<MU, -1>(a, h2);
-    SpinorIO<P64, double>::load(B[1 - p], sn, g.Vh, a);
+    SpinorIO<P64, double>::load(B.there, sn, g.Vh, a);
     spin_proj<MU, +1>(a, h3);
-    SpinorIO<P64, double>::load(A[p], s, g.Vh, a);
+    SpinorIO<P64, double>::load(A.here, s, g.Vh, a);
     spin_proj<MU, +1>(a, h4);
     M3<double> C;
 #pragma unroll
@@ -628,9 +638,9 @@ __device__ __forceinline__ void ff_add(const Geom& g, int p, int s, const Coord&
 
 template <int MU>
 __device__ __forceinline__ void ff_link(const Geom& g, int p, int s, const Coord& c, const d2* U,
-                                        const SpinorPtr X[2], const SpinorPtr Y[2], double coef, double* F) {
+                                        const PairAt& X, const PairAt& Y, double coef, double* F) {
     int sn = cb_neighbour(g, c, MU, +1);
-    M3<double> C = outer_c<MU>(g, p, s, sn, X, Y);
+    M3<double> C = outer_c<MU>(g, s, sn, X, Y);
     ff_add<MU>(g, p, s, c, m3_mul(gauge_load(U, MU, p, s, g.Vh), C), coef, F);
 }
 
@@ -641,7 +651,7 @@ __global__ void __launch_bounds__(256) k_fermion_force(Geom g, const d2* __restr
     if (t >= g.V) return;
     int p = t / g.Vh, s = t % g.Vh;
     Coord c = cb_coords(g, p, s);
-    SpinorPtr X[2] = {Xe, Xo}, Y[2] = {Ye, Yo};
+    const PairAt X = pair_at(Xe, Xo, p), Y = pair_at(Ye, Yo, p);
     ff_link<0>(g, p, s, c, U, X, Y, coef, F);
     ff_link<1>(g, p, s, c, U, X, Y, coef, F);
     ff_link<2>(g, p, s, c, U, X, Y, coef, F);
@@ -654,12 +664,12 @@ __global__ void __launch_bounds__(256) k_fermion_force(Geom g, const d2* __restr
 //   J += coef bc TA( U [C(dX, Y) + C(X, dY)] + V U C(X, Y) ).
 template <int MU>
 __device__ __forceinline__ void ff_tangent_link(const Geom& g, int p, int s, const Coord& c, const d2* U,
-                                                const double* Vd, const SpinorPtr X[2], const SpinorPtr Y[2],
-                                                const SpinorPtr dX[2], const SpinorPtr dY[2], double coef,
+                                                const double* Vd, const PairAt& X, const PairAt& Y,
+                                                const PairAt& dX, const PairAt& dY, double coef,
                                                 double* J) {
     int sn = cb_neighbour(g, c, MU, +1);
-    M3<double> C1 = outer_c<MU>(g, p, s, sn, dX, Y);
-    M3<double> C2 = outer_c<MU>(g, p, s, sn, X, dY);
+    M3<double> C1 = outer_c<MU>(g, s, sn, dX, Y);
+    M3<double> C2 = outer_c<MU>(g, s, sn, X, dY);
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
@@ -667,7 +677,7 @@ __device__ __forceinline__ void ff_tangent_link(const Geom& g, int p, int s, con
     M3<double> u = gauge_load(U, MU, p, s, g.Vh);
     double v[8];
     mom_load(Vd, MU, p, s, g.Vh, v);
-    M3<double> W0 = m3_mul(alg_matrix(v), m3_mul(u, outer_c<MU>(g, p, s, sn, X, Y)));
+    M3<double> W0 = m3_mul(alg_matrix(v), m3_mul(u, outer_c<MU>(g, s, sn, X, Y)));
     M3<double> W = m3_mul(u, C1);
 #pragma unroll
     for (int i = 0; i < 3; i++)
@@ -685,7 +695,7 @@ __global__ void __launch_bounds__(256) k_fermion_force_tangent(Geom g, const d2*
     if (t >= g.V) return;
     int p = t / g.Vh, s = t % g.Vh;
     Coord c = cb_coords(g, p, s);
-    SpinorPtr X[2] = {Xe, Xo}, Y[2] = {Ye, Yo}, dX[2] = {dXe, dXo}, dY[2] = {dYe, dYo};
+    const PairAt X = pair_at(Xe, Xo, p), Y = pair_at(Ye, Yo, p), dX = pair_at(dXe, dXo, p), dY = pair_at(dYe, dYo, p);
     ff_tangent_link<0>(g, p, s, c, U, Vd, X, Y, dX, dY, coef, J);
     ff_tangent_link<1>(g, p, s, c, U, Vd, X, Y, dX, dY, coef, J);
     ff_tangent_link<2>(g, p, s, c, U, Vd, X, Y, dX, dY, coef, J);
@@ -799,7 +809,8 @@ __global__ void __launch_bounds__(256) k_fermion_force_b(const ChainDesc* __rest
     if (t >= g.V) return;
     int p = t / g.Vh, s = t % g.Vh;
     Coord c = cb_coords(g, p, s);
-    SpinorPtr X[2] = {spin_off<P64>(Xe, d), spin_off<P64>(Xo, d)}, Y[2] = {spin_off<P64>(Ye, d), spin_off<P64>(Yo, d)};
+    const PairAt X = pair_at(spin_off<P64>(Xe, d), spin_off<P64>(Xo, d), p);
+    const PairAt Y = pair_at(spin_off<P64>(Ye, d), spin_off<P64>(Yo, d), p);
     const d2* u = U + 9 * d.link0;
     double* f = F + 8 * d.link0;
     const double cf = coef * d.kappa * d.kappa;

@@ -52,11 +52,30 @@ __device__ __forceinline__ int cb_index(const Geom& g, const Coord& c) {
 }
 
 // checkerboard index of the neighbour x +/- mu (it has the other parity)
+// a[d] read and written by selects: indexing a small array with a run-time d
+// makes the compiler keep a per-thread copy of it in LDS (or scratch); with d
+// known at compile time the selects fold to the plain access.
+__device__ __forceinline__ int sel4(const int a[4], int d) {
+    return d == 0 ? a[0] : (d == 1 ? a[1] : (d == 2 ? a[2] : a[3]));
+}
+__device__ __forceinline__ void put4(int a[4], int d, int v) {
+    a[0] = d == 0 ? v : a[0];
+    a[1] = d == 1 ? v : a[1];
+    a[2] = d == 2 ? v : a[2];
+    a[3] = d == 3 ? v : a[3];
+}
+
+// c moved by dir (+1 or -1) along mu, periodically
+__device__ __forceinline__ Coord cb_shift(const Geom& g, Coord c, int mu, int dir) {
+    const int L = sel4(g.L, mu);
+    int v = sel4(c.c, mu) + dir;
+    v = v < 0 ? v + L : (v >= L ? v - L : v);
+    put4(c.c, mu, v);
+    return c;
+}
+
 __device__ __forceinline__ int cb_neighbour(const Geom& g, Coord c, int mu, int dir) {
-    int v = c.c[mu] + dir;
-    v = v < 0 ? v + g.L[mu] : (v >= g.L[mu] ? v - g.L[mu] : v);
-    c.c[mu] = v;
-    return cb_index(g, c);
+    return cb_index(g, cb_shift(g, c, mu, dir));
 }
 
 // XCD-aware block order: the hardware hands consecutive workgroups to the 8

@@ -270,8 +270,7 @@ __device__ __forceinline__ void gauge_force_body(const Geom& g, double beta, con
     int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
     Coord c = cb_coords(g, p, s);
     int s_pmu = cb_neighbour(g, c, mu, +1);
-    Coord cpm = c;
-    cpm.c[mu] = (c.c[mu] + 1) % g.L[mu];
+    const Coord cpm = cb_shift(g, c, mu, +1);
     M3<double> A = m3_zero<double>();
 #pragma unroll 1
     for (int nu = 0; nu < 4; nu++) {
@@ -342,8 +341,7 @@ __global__ void __launch_bounds__(256) k_gauge_tangent(Geom g, double beta, cons
     int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
     Coord c = cb_coords(g, p, s);
     int s_pmu = cb_neighbour(g, c, mu, +1);
-    Coord cpm = c;
-    cpm.c[mu] = (c.c[mu] + 1) % g.L[mu];
+    const Coord cpm = cb_shift(g, c, mu, +1);
     M3<double> A = m3_zero<double>(), dA = m3_zero<double>();
 #pragma unroll 1
     for (int nu = 0; nu < 4; nu++) {

@@ -27,6 +27,8 @@ namespace {
 
 __device__ __forceinline__ int cparity(const Coord& y) { return (y.c[0] + y.c[1] + y.c[2] + y.c[3]) & 1; }
 
+// (an indexed store: here the compiler's per-thread LDS copy of y is the
+// cheaper home; with selects these kernels spill hundreds of bytes a lane)
 __device__ __forceinline__ Coord shifted(const Geom& g, Coord y, int d, int k) {
     int v = y.c[d] + k;
     v = v < 0 ? v + g.L[d] : (v >= g.L[d] ? v - g.L[d] : v);
