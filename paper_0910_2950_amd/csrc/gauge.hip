@@ -186,13 +186,13 @@ __device__ __forceinline__ void ham_density_body(const Geom& g, double beta, con
     h[t] = acc;
 }
 
-__global__ void k_ham_density(Geom g, double beta, const d2* __restrict__ U, const double* __restrict__ P,
+__global__ void __launch_bounds__(256) k_ham_density(Geom g, double beta, const d2* __restrict__ U, const double* __restrict__ P,
                               double* __restrict__ h) {
     ham_density_body(g, beta, U, P, h, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // bscale multiplies each chain's beta (1 - 8 c1 for the plaquettes of the improved action)
-__global__ void k_ham_density_b(const ChainDesc* __restrict__ cd, int nc, const d2* __restrict__ U,
+__global__ void __launch_bounds__(256) k_ham_density_b(const ChainDesc* __restrict__ cd, int nc, const d2* __restrict__ U,
                                 const double* __restrict__ P, double* __restrict__ h, double bscale) {
     const int c = find_chain(cd, nc, blockIdx.x, GRID_V);
     const ChainDesc& d = cd[c];
@@ -702,12 +702,12 @@ __device__ __forceinline__ void link_update_body(const Geom& g, double h, const 
     }
 }
 
-__global__ void k_link_update(Geom g, double h, const double* __restrict__ X, const d2* __restrict__ src,
+__global__ void __launch_bounds__(256) k_link_update(Geom g, double h, const double* __restrict__ X, const d2* __restrict__ src,
                               d2* __restrict__ dst, void* __restrict__ sloppy, int prec, int recon) {
     link_update_body(g, h, X, src, dst, sloppy, prec, recon, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-__global__ void k_link_update_b(const ChainDesc* __restrict__ cd, int nc, double h, const double* __restrict__ X,
+__global__ void __launch_bounds__(256) k_link_update_b(const ChainDesc* __restrict__ cd, int nc, double h, const double* __restrict__ X,
                                 const d2* __restrict__ src, d2* __restrict__ dst, void* __restrict__ sloppy, int prec,
                                 int recon) {
     const int c = find_chain(cd, nc, blockIdx.x, GRID_4V);
@@ -809,7 +809,7 @@ void reunitarize(Ctx& c, const Geom& g, d2* U) {
     FGI_LAUNCH_CHECK();
 }
 
-__global__ void k_exp_batch(int n, const double* __restrict__ p, double h, d2* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_exp_batch(int n, const double* __restrict__ p, double h, d2* __restrict__ out) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     double x[8];
