@@ -1313,8 +1313,10 @@ def main():
                  accepted=[h["acc"] for h in therm_hist if h["phase"] == "nf2"])
     out = dict(metric=METRIC, value=round(s_per_traj, 5), unit="s/trajectory", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(s_per_traj * 1e3, 3), higher_is_better=False,
-               scaling="weak", vs_baseline=None, dtype="f32 arithmetic, f16 storage, f64 reliable updates/"
-               "Hamiltonian" if args.prec == "mp16" else args.prec, data="synthetic",
+               scaling="weak", vs_baseline=None, dtype={"fp64": "f64"}.get(args.prec, "f32"),
+               precision={"mp16": "f32 arithmetic on f16 storage (per-site scale), f64 reliable updates, "
+                                  "Hamiltonian and dH", "mp32": "f32 arithmetic and storage, f64 reliable updates, "
+                                  "Hamiltonian and dH", "fp64": "f64 throughout"}[args.prec], data="synthetic",
                config=dict(workload="Nf=2 Wilson %s beta=%.2f kappa=%.4f, thermalised from a seeded hot start "
                                     "(%d pure-gauge trajectories at beta %.2f, then %d Nf=2 HMC trajectories); FG "
                                     "(%s, displacement form%s) at its calibrated n*=%d, tau=1, CG tol %.0e" %
