@@ -504,6 +504,7 @@ def tune_alpha_leg(R, U_therm, k, n):
         dS.append(s1 - s0)
         dT.append(q1 - q0)
         dh0.append(dH)
+        log("  alpha tuning: start %d/%d, PQPQP(0.1932) dH %+.3e" % (len(dh0), 2 * k, dH))
         acc.append(bool(metro.random() < np.exp(-dH)))
         if acc[-1]:   # the starts follow a Metropolis chain: an ensemble, not one field
             ctx.reunitarize(dims, U)
@@ -520,6 +521,7 @@ def tune_alpha_leg(R, U_therm, k, n):
             U, P = links[i].clone(), inputs[i][0].clone()
             dh_cv[i], _ = ctx.trajectory(dims, act, R.fgi.integrator_builtin("PQPQP", a), 1.0, n, U, P,
                                          inputs[i][1])
+            log("  alpha tuning: start %d held out, alpha %.4f dH %+.3e" % (i + 1, a, dh_cv[i]))
     return dict(trajectories=2 * k, n=n, chain_accepted=acc, alpha_tuned=alpha, alpha_folds=alphas,
                 predicted_dH2={"0.1932": predicted_dh2(0.1932, dS, dT, 1.0 / n),
                                "tuned": predicted_dh2(alpha, dS, dT, 1.0 / n), "cross_validated": pred_cv},
@@ -600,6 +602,7 @@ def fg_family_leg(R, U_therm, act, n, k):
         for key in keys:
             dB[key].append(b1[key] - b0[key])
         dh_fg.append(dH)
+        log("  FG family tuning: start %d/%d, FG dH %+.3e" % (len(dh_fg), 2 * k, dH))
         acc.append(bool(metro.random() < np.exp(-dH)))
         if acc[-1]:   # the starts follow a Metropolis chain: an ensemble, not one field
             ctx.reunitarize(dims, U)
@@ -617,6 +620,7 @@ def fg_family_leg(R, U_therm, act, n, k):
         for j, i in enumerate(folds[ev]):
             pred_cv[i] = float(pe[j])
             dh_cv[i] = run(integ, links[i], starts[i][0], phis[i])[0]
+            log("  FG family tuning: start %d held out, dH %+.3e (predicted %+.3e)" % (i + 1, dh_cv[i], pred_cv[i]))
 
     def ms(v):
         return float(np.mean(np.square(v)))
