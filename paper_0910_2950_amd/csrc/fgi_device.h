@@ -78,6 +78,15 @@ __device__ __forceinline__ int cb_neighbour(const Geom& g, Coord c, int mu, int 
     return cb_index(g, cb_shift(g, c, mu, dir));
 }
 
+// the same with indexed accesses, for the few kernels where the compiler's
+// per-thread LDS copy of c costs less than the registers the selects need
+__device__ __forceinline__ int cb_neighbour_ix(const Geom& g, Coord c, int mu, int dir) {
+    int v = c.c[mu] + dir;
+    v = v < 0 ? v + g.L[mu] : (v >= g.L[mu] ? v - g.L[mu] : v);
+    c.c[mu] = v;
+    return cb_index(g, c);
+}
+
 // XCD-aware block order: the hardware hands consecutive workgroups to the 8
 // XCDs round-robin; remap so each XCD walks one contiguous slab of sites and
 // neighbour reads stay in its own L2.
