@@ -264,29 +264,31 @@ void final_sum(Ctx& c, const double* partial, int n, double* out) {
 //                                     + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)];
 // the part of S_G holding U_mu(x) is -beta/3 ReTr(U_mu(x) A_mu(x)), so
 // F_mu(x) = -e S = -(beta/6) TA(U_mu(x) A_mu(x)).
-__device__ __forceinline__ void gauge_force_body(const Geom& g, double beta, const d2* __restrict__ U,
-                                                 double* __restrict__ F, double coef, int accumulate, int t) {
-    if (t >= 4 * g.V) return;
-    int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
-    Coord c = cb_coords(g, p, s);
-    int s_pmu = cb_neighbour(g, c, mu, +1);
-    const Coord cpm = cb_shift(g, c, mu, +1);
+// one link U_mu(x); MU known at compile time (every block of the force
+// launch holds links of one direction, so the switch below does not diverge)
+template <int MU>
+__device__ __forceinline__ void gauge_force_link(const Geom& g, double beta, const d2* __restrict__ U,
+                                                 double* __restrict__ F, double coef, int accumulate, int s, int p,
+                                                 int r) {
+    const Coord c = cb_coords(g, p, s);
+    const int s_pmu = cb_neighbour(g, c, MU, +1);
+    const Coord cpm = cb_shift(g, c, MU, +1);
     M3<double> A = m3_zero<double>();
 #pragma unroll 1
     for (int nu = 0; nu < 4; nu++) {
-        if (nu == mu) continue;
+        if (nu == MU) continue;
         int s_pnu = cb_neighbour(g, c, nu, +1);
         int s_mnu = cb_neighbour(g, c, nu, -1);
         int s_pmu_mnu = cb_neighbour(g, cpm, nu, -1);
         // upper: U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
-        M3<double> up = m3_mul_nd(m3_mul_nd(gauge_load(U, nu, 1 - p, s_pmu, g.Vh), gauge_load(U, mu, 1 - p, s_pnu, g.Vh)),
+        M3<double> up = m3_mul_nd(m3_mul_nd(gauge_load(U, nu, 1 - p, s_pmu, g.Vh), gauge_load(U, MU, 1 - p, s_pnu, g.Vh)),
                                   gauge_load(U, nu, p, s, g.Vh));
         m3_acc(A, up);
         // lower: (U_mu(x-nu) U_nu(x+mu-nu))^+ U_nu(x-nu)
-        M3<double> ed = m3_mul(gauge_load(U, mu, 1 - p, s_mnu, g.Vh), gauge_load(U, nu, p, s_pmu_mnu, g.Vh));
+        M3<double> ed = m3_mul(gauge_load(U, MU, 1 - p, s_mnu, g.Vh), gauge_load(U, nu, p, s_pmu_mnu, g.Vh));
         m3_acc(A, m3_mul_dn(ed, gauge_load(U, nu, 1 - p, s_mnu, g.Vh)));
     }
-    M3<double> W = m3_mul(gauge_load(U, mu, p, s, g.Vh), A);
+    M3<double> W = m3_mul(gauge_load(U, MU, p, s, g.Vh), A);
     double x[8];
     ta_components(W, x);
     double* o = F + (size_t)(r * 8) * g.Vh + s;
@@ -295,6 +297,18 @@ __device__ __forceinline__ void gauge_force_body(const Geom& g, double beta, con
     for (int a = 0; a < 8; a++) {
         double v = f * x[a];
         o[(size_t)a * g.Vh] = accumulate ? o[(size_t)a * g.Vh] + v : v;
+    }
+}
+
+__device__ __forceinline__ void gauge_force_body(const Geom& g, double beta, const d2* __restrict__ U,
+                                                 double* __restrict__ F, double coef, int accumulate, int t) {
+    if (t >= 4 * g.V) return;
+    int s = t % g.Vh, r = t / g.Vh, p = r & 1, mu = r >> 1;
+    switch (mu) {
+    case 0: gauge_force_link<0>(g, beta, U, F, coef, accumulate, s, p, r); break;
+    case 1: gauge_force_link<1>(g, beta, U, F, coef, accumulate, s, p, r); break;
+    case 2: gauge_force_link<2>(g, beta, U, F, coef, accumulate, s, p, r); break;
+    default: gauge_force_link<3>(g, beta, U, F, coef, accumulate, s, p, r); break;
     }
 }
 
