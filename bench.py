@@ -62,7 +62,7 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6, help="timed FG trajectories")
+    ap.add_argument("--steps", type=int, default=12, help="timed FG trajectories")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dims", default="16,16,16,32")
     ap.add_argument("--beta", type=float, default=5.6)
