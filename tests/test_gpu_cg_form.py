@@ -15,7 +15,8 @@ Against the oracle's CG and against the classic form, through the C ABI:
   - at 16^3x32 (MP16) the oracle's FP64 residual of the GPU's solution meets
     1e-10;
   - an MP16 FG trajectory in either form ends at the same fields and dH to
-    the solvers' accuracy.
+    the solvers' accuracy; a nested Hasenbusch FG trajectory in this form
+    matches the oracle's nested driver.
 """
 import contextlib
 
@@ -207,3 +208,29 @@ def test_repeat_calls_reuse_graphs(ctx, f, prec):
             Ut, Pt = U.clone(), dev(P0)
             dH, st = ctx.trajectory(dims, act, "FG", 1.0, 4, Ut, Pt, dev(eta))
         assert st["graph_captures"] == 0, st
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mp16"])
+def test_nested_hasenbusch_either_form(ctx, orc, prec):
+    """Nested Hasenbusch FG trajectory (S_2 outer, S_1 middle, gauge inner)
+    with every solve in the Chronopoulos-Gear form: the oracle's nested driver
+    to the same gates as the classic form (FP64 1e-12 / 1e-9 with solves at
+    1e-14; MP16 to the solver tolerance)."""
+    from paper_0910_2950_amd import fgi as F
+    dims = (6, 4, 4, 6) if prec == "fp64" else (8, 8, 8, 8)
+    U0, P0, eta1, _ = synth.hot_start(dims, synth.SEED_BASE + 370, fermions=True)
+    eta2 = synth.gaussian_noise(synth.rng(371), dims)
+    fg = [("P", 1 / 6, 0.0), ("Q", 0.5, 0.0), ("G", 2 / 3, 1 / 72), ("Q", 0.5, 0.0), ("P", 1 / 6, 0.0)]
+    levels = [(fg, F.TERM_HASEN, 1), (fg, F.TERM_FERMION, 2), (fg, F.TERM_GAUGE, 2)]
+    tol = 1e-14 if prec == "fp64" else 1e-10
+    act = Action(beta=5.6, kappa=0.155, kappa_hasen=0.140, cg_tol=tol, prec=prec,
+                 link_recon=12 if prec != "fp64" else 18)
+    U, P = dev(U0), dev(P0)
+    with form(ctx, 1):
+        dH, st = ctx.trajectory(dims, act, F.integrator_from_levels(levels), 1.0, 2, U, P, dev(eta1), dev(eta2))
+    Uo, Po, dHo, sto, _ = orc.trajectory_nested(dims, 5.6, levels, 1.0, 2, U0, P0, kappa=0.155, kappa2=0.140,
+                                                eta1=eta1, eta2=eta2, tol=1e-14 if prec == "fp64" else 1e-12)
+    gate_u, gate_h = (1e-12, 1e-9) if prec == "fp64" else (1e-7, 1e-6)
+    assert st["solves"] == sto["solves"]
+    assert relmax(host(U), Uo) < gate_u and relmax(host(P), Po) < gate_u
+    assert abs(dH - dHo) < gate_h, (dH, dHo)
