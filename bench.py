@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--no-large", action="store_true", help="skip the 32^3x64 Dslash roofline point")
     ap.add_argument("--no-batched", action="store_true", help="skip the 96-chain batched workload")
     ap.add_argument("--batched-steps", type=int, default=2, help="timed batched trajectories")
+    ap.add_argument("--ensemble", default="2,8", metavar="K,...",
+                    help="chain counts of the headline workload run together by the batched path ('' to skip)")
     ap.add_argument("--no-hasenbusch", action="store_true", help="skip the 32^3x64 Hasenbusch MD-step leg")
     ap.add_argument("--improved-steps", type=int, default=2,
                     help="pure-gauge FG trajectories per gauge action, Wilson and tree-level Symanzik (0: skip)")
@@ -475,6 +477,44 @@ def batched_leg(R, prec, nsteps, steps, recon=12):
                 chain_trajectories_per_s=round(len(dims_list) / t_batch, 2),
                 s_chain_by_chain=round(t_seq, 4), speedup_vs_chain_by_chain=round(t_seq / t_batch, 2),
                 cg_iters_per_batched_trajectory=float(np.mean(iters)), timed=steps, schedule=tuning)
+
+
+def ensemble_leg(R, U_therm, act, nsteps, counts, ref_dH, steps=1):
+    """K independent chains of the headline workload advanced together by the
+    batched path (one set of launches per MD sub-step covers all K lattices):
+    the FG trajectories of the headline leg's first K timed starts (its
+    momenta and noise on the thermalised field), K chains at a time.  At
+    16^3x32 every CG kernel of one chain fills the GPU with one wave per SIMD;
+    K chains give each SIMD K waves, so this measures how much throughput a
+    single chain leaves unused.  dH of each chain is compared with the single
+    chain run of the same start: the batched path gives each chain the bits
+    of its single run, so the difference is zero."""
+    torch, fgi = R.torch, R.fgi
+    out = {}
+    for K in counts:
+        inputs = R.fresh_inputs(K, R.args.seed + 100000 + R.args.warmup)
+
+        def fresh():
+            return [dict(dims=R.dims, beta=R.args.beta, kappa=R.args.kappa, U=U_therm.clone(), P=P.clone(), eta=e)
+                    for P, e in inputs]
+        R.ctx.trajectory_batched(fresh(), act, "FG", 1.0, nsteps)  # warmup (graph capture)
+        times, dHs = [], None
+        for _ in range(steps):
+            chains = fresh()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            dHs, st = R.ctx.trajectory_batched(chains, act, "FG", 1.0, nsteps)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        t = float(np.mean(times))
+        m = min(K, len(ref_dH))
+        out[str(K)] = dict(s_per_batched_trajectory=round(t, 4), trajectories_per_s=round(K / t, 3),
+                           dH=dHs, max_abs_dH_diff_vs_single=float(np.max(np.abs(np.array(dHs[:m]) -
+                                                                                  np.array(ref_dH[:m])))))
+    return dict(workload="K chains of %s beta=%.2f kappa=%.4f from the thermalised field with the headline's first "
+                         "K timed (momenta, noise); FG n=%d tau=1, %s/%d CG tol %.0e, batched path" %
+                         ("x".join(map(str, R.dims)), R.args.beta, R.args.kappa, nsteps, act.prec, act.link_recon,
+                          R.args.tol), timed=steps, chains=out)
 
 
 def tune_alpha_leg(R, U_therm, k, n):
@@ -1292,6 +1332,22 @@ def main():
         except R.fgi.FgiError as e:
             batched = dict(error=str(e))
             log("batched 96 chains: %s" % e)
+    ensemble = None
+    if args.ensemble:
+        R.apply(tune_fg)
+        counts = [int(k) for k in args.ensemble.split(",")]
+        try:
+            ensemble = ensemble_leg(R, U, act_fg, n_fg, counts, fg["dH"])
+            ensemble["single_chain_s_per_traj"] = round(s_per_traj, 4)
+            for K, e in ensemble["chains"].items():
+                e["throughput_vs_single_chain"] = round(e["trajectories_per_s"] * s_per_traj, 3)
+                log("%s chains of %s batched: %.4f s per trajectory of all chains, %.3f trajectories/s (%.2fx one "
+                    "chain), max |dH - dH single| %.1e" % (K, "x".join(map(str, R.dims)), e["s_per_batched_trajectory"],
+                                                           e["trajectories_per_s"], e["throughput_vs_single_chain"],
+                                                           e["max_abs_dH_diff_vs_single"]))
+        except R.fgi.FgiError as e:
+            ensemble = dict(error=str(e))
+            log("ensemble: %s" % e)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -1331,7 +1387,7 @@ def main():
                fg=fg, legs=legs, speedup_vs_lf_fp64=speedup, fg_exact=exact, dt4_brackets=dt4, thermalisation=therm,
                roofline=roof, roofline_32x32x32x64=large, roofline_32x32x32x64_other_links=large_other,
                halo_32x32x32x8=halo,
-               hasenbusch_32x32x32x64=hasen, batched=batched,
+               hasenbusch_32x32x32x64=hasen, batched=batched, ensemble=ensemble,
                alpha_tuning=alpha_leg, fg_family_tuning=family_leg, md_tolerance=md_leg, chain=chain, improved_gauge=improved, clover=clover,
                stout=stout, cpu_baseline=cpu)
     print(json.dumps(out), flush=True)

@@ -147,3 +147,36 @@ def test_family_leg_cross_validates(monkeypatch):
     assert [integ for _, integ in cv] == [("member", 1)] * k + [("member", 2)] * k
     assert [tag for tag, _ in cv] == [measure[i][0] for i in list(range(k, 2 * k)) + list(range(k))]
     assert len(out["dH"]["cross_validated_predicted"]) == 2 * k
+
+
+def test_ensemble_leg_batches_the_headline_starts(monkeypatch):
+    """K chains built from the headline's first K timed starts on clones of the
+    thermalised links, one untimed batched call before the timed ones, and
+    each chain's dH compared with the single run of its start."""
+    monkeypatch.setattr(bench, "log", lambda *a: None)
+    calls = []
+
+    class Ctx:
+        def trajectory_batched(self, chains, act, integ, tau, n):
+            calls.append([(c["dims"], c["beta"], c["kappa"], c["U"].tag, c["P"].tag, c["eta"].tag) for c in chains])
+            return [0.01 * i for i in range(len(chains))], {}
+
+    requested = []
+
+    def fresh_inputs(n, base):
+        requested.append((n, base))
+        return [(Field(("P", base + i)), Field(("eta", base + i))) for i in range(n)]
+    R = types.SimpleNamespace(ctx=Ctx(), dims=(4, 4, 4, 8), fgi=fgi, fresh_inputs=fresh_inputs,
+                              torch=types.SimpleNamespace(cuda=types.SimpleNamespace(synchronize=lambda: None)),
+                              args=types.SimpleNamespace(seed=10, warmup=1, beta=5.6, kappa=0.1575, tol=1e-10))
+    act = fgi.Action(beta=5.6, kappa=0.1575, prec="mp16", link_recon=18)
+    out = bench.ensemble_leg(R, Field("Utherm"), act, 16, [2, 3], [0.0, 0.01, 0.5], steps=2)
+    assert requested == [(2, 100011), (3, 100011)]        # the headline's timed starts begin at seed + 100000 + warmup
+    assert [len(c) for c in calls] == [2, 2, 2, 3, 3, 3]   # per K: one untimed call, then two timed
+    for chains in calls:
+        assert [c[3] for c in chains] == ["Utherm"] * len(chains)
+        assert [(c[4], c[5]) for c in chains] == [(("P", 100011 + i), ("eta", 100011 + i)) for i in range(len(chains))]
+        assert all(c[:3] == ((4, 4, 4, 8), 5.6, 0.1575) for c in chains)
+    assert out["chains"]["2"]["max_abs_dH_diff_vs_single"] == 0.0
+    assert out["chains"]["3"]["max_abs_dH_diff_vs_single"] == pytest.approx(0.48)
+    assert out["timed"] == 2
