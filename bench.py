@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--lf-traj", type=int, default=12, help="trajectories of the FP64 leapfrog leg at its n*")
     ap.add_argument("--prec", default="mp16", choices=["fp64", "mp32", "mp16"])
     ap.add_argument("--recon", type=int, default=18, choices=[12, 18],
-                    help="reals stored per sloppy link of the headline leg (FP16 or FP32)")
+                    help="reals stored per sloppy link of the headline leg (16-bit or FP32)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--cg-batch", type=int, default=16)
     ap.add_argument("--cg-form", default="auto", choices=["auto", "0", "1"],
@@ -353,7 +353,7 @@ def halo_leg(R, U_therm, reps=50, ranks=8):
     local 32^3x(64/ranks) slab of the thermalised field repeated 2x2x2x2, its
     hopping term through face buffers (fgi_halo_time: face pack, interior
     launch, face launches, one launch over all sites, and the plain local hop),
-    MP16 with FP16/12 and FP16/18 links.  The face transfer itself (xGMI) is not
+    MP16 with FP16/12 and fixed-point 16-bit/18 links.  The face transfer itself (xGMI) is not
     part of a one-GPU run; its time at 153 GB/s per link is given beside."""
     torch, fgi = R.torch, R.fgi
     Ub, dims_b = tile_field(torch, U_therm, R.dims, 2)

@@ -61,8 +61,10 @@ extern "C" {
 
 #define FGI_FP64 0 /* everything FP64 */
 #define FGI_MP32 1 /* CG inner iterations FP32 (links and vectors), FP64 reliable updates */
-#define FGI_MP16 2 /* CG inner iterations with FP16 12-real links and FP16 vectors
-                      (per-site scale), FP32 accumulation, FP64 reliable updates */
+#define FGI_MP16 2 /* CG inner iterations with 16-bit links (12 reals in FP16, or
+                      18 reals in 16-bit fixed point, round(32767 r)) and FP16
+                      vectors (per-site scale), FP32 accumulation, FP64
+                      reliable updates */
 
 typedef struct fgi_ctx fgi_ctx;
 
@@ -77,7 +79,7 @@ typedef struct {
     double cg_tol;      /* CG stop: |phi - A x| <= cg_tol |phi| (true residual) */
     int cg_maxiter;     /* CG iteration cap */
     int prec;           /* FGI_FP64 | FGI_MP32 | FGI_MP16 (CG inner precision) */
-    int link_recon;     /* 18 or 12: reals stored per sloppy link (FP32 or FP16); 12 keeps rows 0, 1 and rebuilds row 2 */
+    int link_recon;     /* 18 or 12: reals stored per sloppy link (FP32, or 16-bit: FP16 for 12, fixed point for 18); 12 keeps rows 0, 1 and rebuilds row 2 */
     int fg_exact;       /* G stages: 0 = displacement form, 1 = exact force gradient
                            (Section 4; every action term, the Hasenbusch ratio
                            term included; not with stout smearing, not for

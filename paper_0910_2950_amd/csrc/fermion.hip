@@ -77,7 +77,8 @@ template <int PIN, int G5IN, typename R> struct LoadPlain {
 // The eight hops of D, k = 2 mu + d: d = 0 the forward hop (1 - g_mu) U_mu(x)
 // psi(x + mu), d = 1 the backward hop (1 + g_mu) U_mu(x - mu)^+ psi(x - mu).
 // Each hop projects to a half spinor, multiplies by the link and accumulates
-// the rebuilt spinor times w = (storage scale) x (antiperiodic sign in t).
+// the rebuilt spinor times w = (storage scale) x (link unit) x (antiperiodic
+// sign in t).
 template <int K, int PL, int RECON, bool NT, typename R, typename L>
 __device__ __forceinline__ void hop(const Geom& g, int p, int s, const Coord& c, const void* links, const L& load,
                                     cx<R> acc[4][3]) {
@@ -87,7 +88,7 @@ __device__ __forceinline__ void hop(const Geom& g, int p, int s, const Coord& c,
     cx<R> psi[4][3], h[2][3], uh[2][3];
     typename L::Raw rs;
     load.fetch(sn, g.Vh, rs);
-    R w = load.get(rs, psi);
+    R w = load.get(rs, psi) * R(link_unit<PL, RECON>());
     spin_proj<MU, FWD ? -1 : +1>(psi, h);
     // the link is loaded after the projection: loads issued any earlier only
     // raise the register count (and lower occupancy on large lattices)
@@ -2005,7 +2006,7 @@ __global__ void __launch_bounds__(DBS) k_halo_pack(HaloArgs A) {
 #pragma unroll
             for (int a = 0; a < 3; a++)
                 uh[j][a] = cdot3c(u.e[0][a], h[j][0], u.e[1][a], h[j][1], u.e[2][a], h[j][2]);
-        halo_store<R>(const_cast<void*>(A.hi), F, f, uh, w * R(A.sign_hi));
+        halo_store<R>(const_cast<void*>(A.hi), F, f, uh, w * R(A.sign_hi) * R(link_unit<PL, RECON>()));
     }
 }
 
@@ -2044,7 +2045,7 @@ __global__ void __launch_bounds__(DBS) k_dslash_halo(HaloArgs A) {
 #pragma unroll
             for (int a = 0; a < 3; a++)
                 uh[j][a] = cdot3(u.e[a][0], h[j][0], u.e[a][1], h[j][1], u.e[a][2], h[j][2]);
-        spin_recon_acc<3, -1>(acc, uh, R(1));
+        spin_recon_acc<3, -1>(acc, uh, R(link_unit<PL, RECON>()));
     } else {
         hop<6, PL, RECON, false>(g, p, s, c, A.links, ld, acc);
     }

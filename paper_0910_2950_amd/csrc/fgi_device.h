@@ -481,6 +481,8 @@ template <> struct Real<P64> { typedef double T; };
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef short s2 __attribute__((ext_vector_type(2)));
+typedef short s8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f2 __attribute__((ext_vector_type(2)));
 typedef double d2 __attribute__((ext_vector_type(2)));
@@ -622,11 +624,22 @@ template <> struct RawLink<P64, 18> { d2 v[9]; };
 template <> struct RawLink<P32, 18> { f2 v[9]; };
 template <> struct RawLink<P32, 12> { f4 v[3]; };
 template <> struct RawLink<P16, 12> { h4 v[3]; };
-// FP16 / 18: per (mu, p) a block of 36 Vh bytes holding two half8 arrays
-// (entries 0-3 and 4-7 of the row-major matrix) and one half2 array (entry 8)
-template <> struct RawLink<P16, 18> { h8 v[2]; h2 w; };
-__device__ __forceinline__ const h8* link16x18_block(const void* base, int mu, int p, int Vh) {
-    return (const h8*)((const char*)base + (size_t)((mu * 2 + p) * 36) * Vh);
+// 16-bit / 18: per (mu, p) a block of 36 Vh bytes holding two short8 arrays
+// (entries 0-3 and 4-7 of the row-major matrix) and one short2 array (entry
+// 8); every real r of the link is kept as the 16-bit fixed-point value
+// q = round(32767 r) (an entry of a unitary matrix has |r| <= 1), an absolute
+// error of 1.5e-5 against FP16's relative 4.9e-4 near 1: a link error is a
+// fixed change of the operator the inner solver inverts, and costs CG
+// iterations where rounding of the vectors does not
+template <> struct RawLink<P16, 18> { s8 v[2]; s2 w; };
+__device__ __forceinline__ const s8* link16x18_block(const void* base, int mu, int p, int Vh) {
+    return (const s8*)((const char*)base + (size_t)((mu * 2 + p) * 36) * Vh);
+}
+// the factor that turns a decoded sloppy link into the link: the 16-bit /18
+// format decodes to 32767 times the entries (the hop applies the factor once,
+// with the spinor's weight), the other formats to the entries themselves
+template <int P, int RECON> __host__ __device__ constexpr float link_unit() {
+    return (P == P16 && RECON == 18) ? 1.0f / 32767.0f : 1.0f;
 }
 
 // nt: non-temporal loads, for link fields larger than the L2 caches together
@@ -640,8 +653,8 @@ __device__ __forceinline__ void fetch_link(const void* base, int mu, int p, int 
     typedef decltype(r.v[0]) T0;
     typedef typename std::remove_reference<T0>::type T;
     if constexpr (P == P16 && RECON == 18) {
-        const h8* b = link16x18_block(base, mu, p, Vh);
-        const h2* w = (const h2*)(b + 2 * (size_t)Vh);
+        const s8* b = link16x18_block(base, mu, p, Vh);
+        const s2* w = (const s2*)(b + 2 * (size_t)Vh);
         if constexpr (NT) {
             r.v[0] = __builtin_nontemporal_load(b + s);
             r.v[1] = __builtin_nontemporal_load(b + Vh + s);
@@ -763,6 +776,7 @@ template <typename R> struct LinkIO<P16, 12, R> {
 };
 
 template <typename R> struct LinkIO<P16, 18, R> {
+    // 32767 times the link (see link_unit)
     static __device__ __forceinline__ M3<R> decode(const RawLink<P16, 18>& r) {
         M3<R> u;
 #pragma unroll
@@ -776,9 +790,16 @@ template <typename R> struct LinkIO<P16, 18, R> {
     static __device__ __forceinline__ M3<R> load(const void* base, int mu, int p, int s, int Vh) {
         RawLink<P16, 18> r;
         fetch_link<P16, 18, false>(base, mu, p, s, Vh, r);
-        return decode(r);
+        M3<R> u = decode(r);
+        m3_scale(u, R(link_unit<P16, 18>()));
+        return u;
     }
 };
+
+// a real in [-1, 1] as 16-bit fixed point, rounded to nearest (ties to even)
+__device__ __forceinline__ short fixed16(double x) {
+    return (short)rint(fmin(fmax(x, -1.0), 1.0) * 32767.0);
+}
 
 // A link written to a sloppy copy in storage (prec, recon): row-major
 // entries e[0..8] in FP64; r = mu * 2 + p selects the (direction, parity) part.
@@ -794,18 +815,18 @@ __device__ __forceinline__ void store_sloppy_link(void* out, int prec, int recon
         for (int k = 0; k < 3; k++)
             o[(size_t)k * Vh] = f4{(float)e[2 * k].re, (float)e[2 * k].im, (float)e[2 * k + 1].re, (float)e[2 * k + 1].im};
     } else if (recon == 18) {
-        h8* o = (h8*)((char*)out + (size_t)(r * 36) * Vh);
+        s8* o = (s8*)((char*)out + (size_t)(r * 36) * Vh);
 #pragma unroll
         for (int j = 0; j < 2; j++) {
-            h8 v;
+            s8 v;
 #pragma unroll
             for (int k = 0; k < 4; k++) {
-                v[2 * k] = (_Float16)e[4 * j + k].re;
-                v[2 * k + 1] = (_Float16)e[4 * j + k].im;
+                v[2 * k] = fixed16(e[4 * j + k].re);
+                v[2 * k + 1] = fixed16(e[4 * j + k].im);
             }
             o[(size_t)j * Vh + s] = v;
         }
-        ((h2*)(o + 2 * (size_t)Vh))[s] = h2{(_Float16)e[8].re, (_Float16)e[8].im};
+        ((s2*)(o + 2 * (size_t)Vh))[s] = s2{fixed16(e[8].re), fixed16(e[8].im)};
     } else {
         h4* o = (h4*)out + (size_t)(r * 3) * Vh + s;
 #pragma unroll
