@@ -79,7 +79,11 @@ typedef struct {
     double cg_tol;      /* CG stop: |phi - A x| <= cg_tol |phi| (true residual) */
     int cg_maxiter;     /* CG iteration cap */
     int prec;           /* FGI_FP64 | FGI_MP32 | FGI_MP16 (CG inner precision) */
-    int link_recon;     /* 18 or 12: reals stored per sloppy link (FP32, or 16-bit: FP16 for 12, fixed point for 18); 12 keeps rows 0, 1 and rebuilds row 2 */
+    int link_recon;     /* 18 or 12: reals stored per sloppy link (FP32, or 16-bit: FP16 for 12, fixed point for 18); 12 keeps rows 0, 1 and rebuilds row 2.
+                           Both compressions assume unitary links: 12 rebuilds row 2 from
+                           unitarity, and the 16-bit fixed point of 18 holds reals in
+                           [-1, 1] (larger ones are clamped; the FP64 reliable updates
+                           still decide convergence) */
     int fg_exact;       /* G stages: 0 = displacement form, 1 = exact force gradient
                            (Section 4; every action term, the Hasenbusch ratio
                            term included; not with stout smearing, not for
