@@ -485,8 +485,9 @@ def ensemble_leg(R, U_therm, act, nsteps, counts, ref_dH, steps=1):
     the FG trajectories of the headline leg's first K timed starts (its
     momenta and noise on the thermalised field), K chains at a time.  At
     16^3x32 every CG kernel of one chain fills the GPU with one wave per SIMD;
-    K chains give each SIMD K waves, so this measures how much throughput a
-    single chain leaves unused.  dH of each chain is compared with the single
+    K chains give each SIMD up to K waves (as many as the kernels' registers
+    allow) and share each launch's fixed cost, so this measures how much
+    throughput a single chain leaves unused.  dH of each chain is compared with the single
     chain run of the same start: the batched path gives each chain the bits
     of its single run, so the difference is zero."""
     torch, fgi = R.torch, R.fgi
